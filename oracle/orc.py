@@ -1,0 +1,213 @@
+"""ctypes wrapper of the scalable C oracle (oracle/orc.c).
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the benchmark's
+CPU-baseline leg use it; the product library never does.  See orc.c for the
+passages of the paper each step follows.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liborc.so")
+SRC_PATH = os.path.join(HERE, "orc.c")
+
+SINK = -1
+KEY_TOP = 2**31 - 1
+OK, EINVAL, EINADMISSIBLE, EITERLIMIT, ENOMEM = 0, 1, 2, 3, 4
+RANK_KRUSKAL, RANK_PATHSORT = 0, 1
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n_major", ctypes.c_int64), ("n_valuations", ctypes.c_int64),
+                ("n_even_switches", ctypes.c_int64),
+                ("n_odd_switches", ctypes.c_int64)]
+
+
+def build(force: bool = False) -> str:
+    """Compile orc.c with gcc into liborc.so next to it."""
+    if force or not os.path.exists(LIB_PATH) or \
+            os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH):
+        tmp = LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-shared", "-fPIC",
+                               "-o", tmp, SRC_PATH])
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(LIB_PATH)
+        L.orc_x_sets.restype = _I64
+        L.orc_x_sets.argtypes = [_I64, _P, _P, _P, _P, _P]
+        L.orc_preprocess.restype = _I64
+        L.orc_preprocess.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _P, _P]
+        L.orc_valuation.restype = ctypes.c_int
+        L.orc_valuation.argtypes = [_I64, _P, _P, _P, ctypes.c_int, _P, _P]
+        L.orc_odd_switch.restype = _I64
+        L.orc_odd_switch.argtypes = [_I64, _P, _P, _P, _P, _P]
+        L.orc_even_switch.restype = _I64
+        L.orc_even_switch.argtypes = [_I64, _P, _P, _P, _P, _P]
+        L.orc_hash.restype = ctypes.c_uint64
+        L.orc_hash.argtypes = [_I64, _P]
+        L.orc_order_by_pri.restype = None
+        L.orc_order_by_pri.argtypes = [_I64, _P, _P]
+        L.orc_solve.restype = ctypes.c_int
+        L.orc_solve.argtypes = [_I64, _P, _P, _P, _P, ctypes.c_int, _I64, _I64,
+                                _P, _P, _P, ctypes.POINTER(Stats), _P, _I64]
+        _lib = L
+    return _lib
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def preprocess(game: dict) -> dict:
+    """The modified game with dummy Even vertices (see orc_preprocess)."""
+    n = int(game["n"])
+    off = _c(game["offsets"], np.int64)
+    tgt = _c(game["targets"], np.int32)
+    own = _c(game["owner"], np.uint8)
+    pri = _c(game["pri"], np.int32)
+    m = int(off[-1])
+    off2 = np.zeros(2 * n + 1, np.int64)
+    tgt2 = np.zeros(m + n, np.int32)
+    own2 = np.zeros(2 * n, np.uint8)
+    pri2 = np.zeros(2 * n, np.int32)
+    dum = np.zeros(max(n, 1), np.int32)
+    n_aug = lib().orc_preprocess(n, _ptr(off), _ptr(tgt), _ptr(own), _ptr(pri),
+                                 _ptr(off2), _ptr(tgt2), _ptr(own2),
+                                 _ptr(pri2), _ptr(dum))
+    if n_aug < 0:
+        raise ValueError("preprocessing failed (priority overflow)")
+    k = n_aug - n
+    m_aug = m + k
+    return {"n": n_aug, "m": m_aug, "offsets": off2[:n_aug + 1].copy(),
+            "targets": tgt2[:m_aug].copy(), "owner": own2[:n_aug].copy(),
+            "pri": pri2[:n_aug].copy(), "dummy_of": dum[:k].copy(),
+            "n_orig": n}
+
+
+def identity(game: dict) -> dict:
+    n = int(game["n"])
+    return {"n": n, "m": int(game["m"]),
+            "offsets": _c(game["offsets"], np.int64),
+            "targets": _c(game["targets"], np.int32),
+            "owner": _c(game["owner"], np.uint8),
+            "pri": _c(game["pri"], np.int32),
+            "dummy_of": np.zeros(0, np.int32), "n_orig": n}
+
+
+def x_sets(game: dict):
+    n = int(game["n"])
+    inx = np.zeros(n, np.uint8)
+    inxp = np.zeros(n, np.uint8)
+    lib().orc_x_sets(n, _ptr(_c(game["offsets"], np.int64)),
+                     _ptr(_c(game["targets"], np.int32)),
+                     _ptr(_c(game["owner"], np.uint8)), _ptr(inx), _ptr(inxp))
+    return inx.astype(bool), inxp.astype(bool)
+
+
+def order_by_pri(pri) -> np.ndarray:
+    pri = _c(pri, np.int32)
+    out = np.zeros(pri.size, np.int32)
+    lib().orc_order_by_pri(pri.size, _ptr(pri), _ptr(out))
+    return out
+
+
+def valuation(succ, pri, method: int = RANK_KRUSKAL, by_pri=None):
+    """Ranks of Val^{sigma,tau}; succ uses SINK for the sink.
+    Returns (key[n+1], n_finite, status)."""
+    succ = _c(succ, np.int32)
+    pri = _c(pri, np.int32)
+    n = succ.size
+    if by_pri is None and method == RANK_KRUSKAL:
+        by_pri = order_by_pri(pri)
+    bp = _c(by_pri, np.int32) if by_pri is not None else None
+    key = np.zeros(n + 1, np.int32)
+    nf = ctypes.c_int64(0)
+    rc = lib().orc_valuation(n, _ptr(succ), _ptr(pri),
+                             _ptr(bp) if bp is not None else None, method,
+                             _ptr(key), ctypes.byref(nf))
+    return key, int(nf.value), int(rc)
+
+
+def odd_switch(g: dict, key, tau) -> tuple:
+    tau = _c(tau, np.int32).copy()
+    c = lib().orc_odd_switch(int(g["n"]), _ptr(_c(g["offsets"], np.int64)),
+                             _ptr(_c(g["targets"], np.int32)),
+                             _ptr(_c(g["owner"], np.uint8)),
+                             _ptr(_c(key, np.int32)), _ptr(tau))
+    return tau, int(c)
+
+
+def even_switch(g: dict, key, sigma) -> tuple:
+    sigma = _c(sigma, np.int32).copy()
+    c = lib().orc_even_switch(int(g["n"]), _ptr(_c(g["offsets"], np.int64)),
+                              _ptr(_c(g["targets"], np.int32)),
+                              _ptr(_c(g["owner"], np.uint8)),
+                              _ptr(_c(key, np.int32)), _ptr(sigma))
+    return sigma, int(c)
+
+
+def key_hash(key) -> int:
+    key = _c(key, np.int32)
+    return int(lib().orc_hash(key.size, _ptr(key)))
+
+
+def initial_strategies(g: dict):
+    """sigma_init = the sink for every Even vertex; tau = first row entry."""
+    n = int(g["n"])
+    off = _c(g["offsets"], np.int64)
+    tgt = _c(g["targets"], np.int32)
+    own = _c(g["owner"], np.uint8)
+    sigma = np.full(n, SINK, np.int32)
+    tau = np.where(own == 1, tgt[off[:-1]], SINK).astype(np.int32)
+    return sigma, tau
+
+
+def solve(game: dict, preprocess_game: bool = True,
+          method: int = RANK_KRUSKAL, trace: bool = False,
+          max_major: int = 0, max_inner: int = 0, aug: dict = None) -> dict:
+    """Algorithm 1; returns winners, strategies, counts, the last key array
+    and (with trace) the hash of every valuation."""
+    g = aug if aug is not None else (
+        preprocess(game) if preprocess_game else identity(game))
+    n = int(g["n"])
+    sigma, tau = initial_strategies(g)
+    key = np.zeros(n + 1, np.int32)
+    st = Stats()
+    cap = 100000 if trace else 0
+    tr = np.zeros(max(cap, 1), np.uint64)
+    rc = lib().orc_solve(n, _ptr(_c(g["offsets"], np.int64)),
+                         _ptr(_c(g["targets"], np.int32)),
+                         _ptr(_c(g["owner"], np.uint8)),
+                         _ptr(_c(g["pri"], np.int32)), method, max_major,
+                         max_inner, _ptr(sigma), _ptr(tau), _ptr(key),
+                         ctypes.byref(st), _ptr(tr) if trace else None, cap)
+    n0 = int(g["n_orig"])
+    winner = (key[:n0] != KEY_TOP).astype(np.uint8)
+    return {"aug": g, "status": int(rc), "winner": winner, "sigma": sigma,
+            "tau": tau, "key": key, "n_major": int(st.n_major),
+            "n_valuations": int(st.n_valuations),
+            "n_even_switches": int(st.n_even_switches),
+            "n_odd_switches": int(st.n_odd_switches),
+            "trace": tr[:min(int(st.n_valuations), cap)].copy()
+            if trace else None}

@@ -1,0 +1,54 @@
+"""Shared test helpers: stepwise oracle runs and array hashing."""
+from __future__ import annotations
+
+import numpy as np
+
+from oracle import orc
+
+KEY_TOP = 2**31 - 1
+_HASH_MUL = np.uint64(1099511628211)
+
+
+def np_hash(a) -> int:
+    """The same polynomial hash as orc_hash: h = h*M + (uint32)a[i] + 1."""
+    x = np.ascontiguousarray(a).astype(np.int64).astype(np.uint32)
+    x = x.astype(np.uint64) + np.uint64(1)
+    n = x.size
+    if n == 0:
+        return 0
+    with np.errstate(over="ignore"):
+        pw = np.ones(n, dtype=np.uint64)
+        if n > 1:
+            pw[1:] = _HASH_MUL
+            pw = np.cumprod(pw)[::-1].copy()
+        return int((x * pw).sum(dtype=np.uint64))
+
+
+def oracle_trajectory(aug: dict, max_vals: int = 10**9):
+    """Runs Algorithm 1 stepwise on the modified game with the C oracle and
+    yields (sigma, tau, key) for every valuation, in order."""
+    sigma, tau = orc.initial_strategies(aug)
+    by_pri = orc.order_by_pri(aug["pri"])
+    own = np.asarray(aug["owner"])
+    count = 0
+    while True:
+        while True:
+            succ = np.where(own == 1, tau, sigma).astype(np.int32)
+            key, nf, rc = orc.valuation(succ, aug["pri"], by_pri=by_pri)
+            assert rc == 0
+            yield sigma.copy(), tau.copy(), key
+            count += 1
+            if count >= max_vals:
+                return
+            tau, c = orc.odd_switch(aug, key, tau)
+            if c == 0:
+                break
+        sigma, c = orc.even_switch(aug, key, sigma)
+        if c == 0:
+            return
+
+
+def to_np(x):
+    if hasattr(x, "detach"):
+        return x.detach().cpu().numpy()
+    return np.asarray(x)

@@ -1,0 +1,471 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Nothing here touches the GPU.  Each test names the passage it pins:
+  * the Euler-tour list of Figure 1 and its start/end pointer walk-through
+    (section 5, "Constructing the list ranking instance in parallel");
+  * the formal reduction: exclusive prefix sums of the up/down edge weights
+    along the list equal the valuations (section 5, "Formal reduction");
+  * the Maxdiff order on small hand-made valuations (section 3);
+  * winners: Zielonka's algorithm and brute force over positional
+    strategies (section 2, positional determinacy; Theorem 1);
+  * best responses: Bellman-Ford (section 4) and brute force over tau;
+  * preprocessing: no Odd-only cycle is left (section 3, "The algorithm");
+  * the scalable C oracle against the literal one, valuation by valuation.
+"""
+from __future__ import annotations
+
+import itertools
+
+import numpy as np
+import pytest
+
+from oracle import literal as L
+from oracle import orc
+from oracle.zielonka import zielonka
+from paper_1705_02313_amd import synth
+from tests.helpers import np_hash
+
+
+# ---------------------------------------------------------------------------
+# Figure 1 and the sequential list construction
+# ---------------------------------------------------------------------------
+FIG1_PARENT = {"b": "a", "c": "a", "d": "b", "e": "b"}
+
+
+def test_fig1_list_d_before_e():
+    succ, head = L.euler_list_sequential(FIG1_PARENT, ["b", "c", "d", "e"])
+    tour = L.walk_list(succ, head)
+    assert tour[0] == ("head", "a") and tour[-1] == ("tail", "a")
+    assert tour[1:-1] == [("a", "b"), ("b", "d"), ("d", "b"), ("b", "e"),
+                          ("e", "b"), ("b", "a"), ("a", "c"), ("c", "a")]
+
+
+def test_fig1_pointer_walkthrough():
+    """The walk-through of b's pointers: start(b) = (a,b) at first; after d
+    it is (d,b); after e it is (e,b); then (b,d)->(d,b), (e,b)->(b,a)."""
+    parent = FIG1_PARENT
+    start = {"b": ("a", "b"), "d": ("b", "d"), "e": ("b", "e")}
+    end = {"b": ("b", "a"), "d": ("d", "b"), "e": ("e", "b")}
+    links = {}
+    seen = []
+    for v in ["d", "e"]:
+        u = parent[v]
+        links[start[u]] = start[v]
+        start[u] = end[v]
+        seen.append(start["b"])
+    assert seen == [("d", "b"), ("e", "b")]
+    for v in ["b", "d", "e"]:
+        links[start[v]] = end[v]
+    assert links[("a", "b")] == ("b", "d")
+    assert links[("d", "b")] == ("b", "e")
+    assert links[("b", "d")] == ("d", "b")
+    assert links[("e", "b")] == ("b", "a")
+    # the library routine makes exactly these links
+    succ, _ = L.euler_list_sequential(parent, ["b", "c", "d", "e"])
+    for k, v in links.items():
+        assert succ[k] == v
+
+
+def test_fig1_e_before_d_is_another_tour():
+    succ, head = L.euler_list_sequential(FIG1_PARENT, ["e", "d", "c", "b"])
+    tour = L.walk_list(succ, head)[1:-1]
+    assert tour == [("a", "c"), ("c", "a"), ("a", "b"), ("b", "e"),
+                    ("e", "b"), ("b", "d"), ("d", "b"), ("b", "a")]
+
+
+def _dfs_tour(parent, order):
+    kids = {}
+    for v in order:
+        kids.setdefault(parent[v], []).append(v)
+    root = [v for v in set(parent.values()) if v not in parent][0]
+    out = []
+
+    def rec(u):
+        for c in kids.get(u, []):
+            out.append((u, c))
+            rec(c)
+            out.append((c, u))
+    rec(root)
+    return out
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_sequential_list_is_dfs_tour(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(2, 60))
+    parent = {v: int(rng.integers(0, v)) for v in range(1, n)}
+    order = list(rng.permutation(np.arange(1, n)))
+    order = [int(v) for v in order]
+    succ, head = L.euler_list_sequential(parent, order)
+    tour = L.walk_list(succ, head)[1:-1]
+    assert tour == _dfs_tour(parent, order)
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_formal_reduction_prefix_sums_are_valuations(seed):
+    """Weights A_{pri(v)} on the down edge (u,v) and A_{-pri(u)} on the up
+    edge (u,v); the exclusive prefix at the up edge of v is Val(v)."""
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(2, 40))
+    # vertex 0 plays the sink (the root); its priority does not count
+    parent = {v: int(rng.integers(0, v)) for v in range(1, n)}
+    pri = rng.integers(0, 6, size=n)         # repeated priorities allowed
+    vals = L.Vals(pri)
+    order = [int(v) for v in rng.permutation(np.arange(1, n))]
+    succ, head = L.euler_list_sequential(parent, order)
+    tour = L.walk_list(succ, head)[1:-1]
+    acc = vals.zero()
+    for (x, y) in tour:
+        if parent.get(y) == x:               # down edge into y
+            w = vals.unit(pri[y], +1)
+        else:                                # up edge out of x
+            w = vals.unit(pri[x], -1)
+            # exclusive prefix at the up edge of x: the path x .. root
+            expect = vals.zero()
+            u = x
+            while u != 0:
+                expect = expect + vals.unit(pri[u])
+                u = parent[u]
+            np.testing.assert_array_equal(acc, expect)
+        acc = acc + w
+    np.testing.assert_array_equal(acc, vals.zero())
+
+
+# ---------------------------------------------------------------------------
+# the order on valuations (section 3)
+# ---------------------------------------------------------------------------
+def test_maxdiff_order_cases():
+    dom = np.array([0, 1, 2, 3])
+    z = np.zeros(4, np.int64)
+    a = np.array([0, 0, 1, 0])   # one visit to priority 2 (even)
+    b = np.array([0, 0, 0, 1])   # one visit to priority 3 (odd)
+    c = np.array([5, 0, 1, 0])   # 2 once, 0 five times
+    assert L.val_lt(z, a, dom)            # even Maxdiff: more is better
+    assert L.val_lt(b, z, dom)            # odd Maxdiff: more is worse
+    assert L.val_lt(a, c, dom)            # Maxdiff 0 (even), 1 < 5
+    assert L.val_lt(b, a, dom)            # Maxdiff 3 (odd): b has more
+    assert L.val_le(a, a, dom) and not L.val_lt(a, a, dom)
+    assert L.val_lt(c, L.TOP, dom) and not L.val_le(L.TOP, c, dom)
+    assert L.val_le(L.TOP, L.TOP, dom)    # top equals top
+    assert L.maxdiff(a, c, dom) == 0 and L.maxdiff(a, b, dom) == 3
+
+
+def test_distinct_priorities_rank_matches_signed_powers():
+    """With distinct priorities a finite valuation is a set, and the order is
+    that of sum over the set of (-1)^p 2^p (a closed form checked here
+    against the literal comparator on random sets)."""
+    rng = np.random.default_rng(3)
+    dom = np.arange(12)
+    for _ in range(300):
+        s1 = rng.integers(0, 2, 12)
+        s2 = rng.integers(0, 2, 12)
+        v1 = sum(((-1) ** p) * (1 << p) for p in range(12) if s1[p])
+        v2 = sum(((-1) ** p) * (1 << p) for p in range(12) if s2[p])
+        assert L.val_lt(s1, s2, dom) == (v1 < v2)
+
+
+# ---------------------------------------------------------------------------
+# winners
+# ---------------------------------------------------------------------------
+def _tiny(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(2, 8))
+    if seed % 4 == 3 and n >= 3:
+        return synth.chain_game(n, seed)
+    return synth.random_game(n, 1 if seed % 3 == 0 else 2, 3, seed)
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_winners_si_zielonka_bruteforce(seed):
+    g = _tiny(seed)
+    z = zielonka(g)
+    r = L.solve(g)
+    np.testing.assert_array_equal(r["winner"], z)
+    try:
+        b = L.brute_force_winners(g, limit=200000)
+    except ValueError:
+        return
+    np.testing.assert_array_equal(b, z)
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_winners_zielonka_midsize(seed):
+    g = synth.random_game(300 + 17 * seed, 1 + seed % 3, 5, seed)
+    np.testing.assert_array_equal(L.solve(g)["winner"], zielonka(g))
+
+
+def test_winners_c_oracle_vs_zielonka_larger():
+    for seed, n in [(0, 2000), (1, 2500)]:
+        g = synth.random_game(n, 2, 5, seed)
+        np.testing.assert_array_equal(orc.solve(g)["winner"], zielonka(g))
+    g = synth.chain_game(2000, 4)
+    np.testing.assert_array_equal(orc.solve(g)["winner"], zielonka(g))
+
+
+def test_self_loops_and_single_vertices():
+    # a single Odd vertex with an odd self-loop: Odd wins
+    for owner, pri, win in [(1, 1, 1), (1, 2, 0), (0, 1, 1), (0, 0, 0)]:
+        g = {"n": 1, "m": 1, "offsets": np.array([0, 1]),
+             "targets": np.array([0], np.int32),
+             "owner": np.array([owner], np.uint8),
+             "pri": np.array([pri], np.int32)}
+        assert L.solve(g)["winner"][0] == win
+        assert orc.solve(g)["winner"][0] == win
+        assert zielonka(g)[0] == win
+
+
+# ---------------------------------------------------------------------------
+# best responses (section 4)
+# ---------------------------------------------------------------------------
+def _same(v1, v2):
+    if v1 is L.TOP or v2 is L.TOP:
+        return v1 is v2
+    return np.array_equal(v1, v2)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_si_best_response_equals_bellman_ford(seed):
+    g = synth.random_game(10 + 7 * seed, 2, 4, 50 + seed) if seed % 3 else \
+        synth.chain_game(10 + 7 * seed, 50 + seed)
+    r = L.solve(g)
+    aug = r["aug"]
+    rows = L.rows_of(aug)
+    for sigma, tau, val in r["majors"]:
+        lab, _ = L.bellman_ford(aug, r["vals"], rows, sigma)
+        assert all(_same(a, b) for a, b in zip(lab, val))
+
+
+@pytest.mark.parametrize("seed", range(15))
+def test_si_best_response_is_pointwise_minimum(seed):
+    """Brute force over every positional tau (modified games of at most 12
+    vertices): SI's Val^sigma is the pointwise minimum (section 3, "Best
+    responses")."""
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(3, 7))
+    g = synth.random_game(n, 1, 3, 900 + seed)
+    r = L.solve(g)
+    aug = r["aug"]
+    if aug["n"] > 12:
+        pytest.skip("modified game too large for brute force")
+    rows = L.rows_of(aug)
+    dom = r["vals"].dom
+    for sigma, tau, val in r["majors"]:
+        best = L.brute_force_tau_min(aug, r["vals"], rows, sigma)
+        for v in range(aug["n"]):
+            assert L.val_le(val[v], best[v], dom) and \
+                L.val_le(best[v], val[v], dom)
+
+
+# ---------------------------------------------------------------------------
+# preprocessing (section 3)
+# ---------------------------------------------------------------------------
+def _odd_subgraph_acyclic(aug) -> bool:
+    n = aug["n"]
+    rows = L.rows_of(aug)
+    odd = [v for v in range(n) if aug["owner"][v] == 1]
+    state = {}
+
+    def dfs(u):
+        state[u] = 1
+        for w in rows[u]:
+            if aug["owner"][w] != 1:
+                continue
+            if state.get(w) == 1:
+                return False
+            if w not in state and not dfs(w):
+                return False
+        state[u] = 2
+        return True
+    return all(dfs(v) for v in odd if v not in state)
+
+
+@pytest.mark.parametrize("seed", range(25))
+def test_preprocessing_breaks_odd_cycles_and_keeps_winners(seed):
+    g = synth.random_game(20 + 9 * seed, 1 + seed % 3, 5, 300 + seed) \
+        if seed % 5 else synth.chain_game(20 + 9 * seed, 300 + seed)
+    aug = L.preprocess(g)
+    assert _odd_subgraph_acyclic(aug)      # sigma_init is admissible
+    caug = orc.preprocess(g)
+    for k in ("offsets", "targets", "owner", "pri"):
+        np.testing.assert_array_equal(np.asarray(aug[k]), caug[k])
+    # winners of the modified game (without the sink) on original vertices
+    z_aug = zielonka(aug)[: g["n"]]
+    np.testing.assert_array_equal(z_aug, zielonka(g))
+
+
+def test_without_preprocessing_si_can_fail():
+    """Uniform owners create Odd-only cycles: without the preprocessing the
+    initial strategy is not admissible on some games (why it is always on)."""
+    bad = 0
+    for seed in range(60):
+        g = synth.random_game(12, 1, 3, 4000 + seed)
+        try:
+            r = L.solve(g, preprocess_game=False)
+            if not np.array_equal(r["winner"], zielonka(g)):
+                bad += 1
+        except L.Inadmissible:
+            bad += 1
+    assert bad > 0
+
+
+# ---------------------------------------------------------------------------
+# the C oracle against the literal oracle
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", range(30))
+def test_c_oracle_matches_literal(seed):
+    n = [3, 4, 6, 8, 12, 25, 60, 150][seed % 8]
+    g = synth.random_game(n, 2, 5, seed) if seed % 3 else \
+        synth.chain_game(max(n, 3), seed)
+    r = L.solve(g, trace=True)
+    lhash = [np_hash(k) for k in r["keys"]]
+    for method in (orc.RANK_KRUSKAL, orc.RANK_PATHSORT):
+        c = orc.solve(g, method=method, trace=True)
+        assert c["status"] == 0
+        assert c["n_major"] == r["n_major"]
+        assert c["n_valuations"] == r["n_valuations"]
+        assert [int(x) for x in c["trace"]] == lhash
+        np.testing.assert_array_equal(c["winner"], r["winner"])
+        np.testing.assert_array_equal(c["sigma"], r["sigma"])
+        np.testing.assert_array_equal(c["tau"], r["tau"])
+
+
+@pytest.mark.parametrize("kind", ["rnd", "chain"])
+def test_rank_constructions_agree(kind):
+    g = synth.random_game(5000, 2, 6, 12) if kind == "rnd" else \
+        synth.chain_game(4000, 12)
+    a = orc.solve(g, method=orc.RANK_KRUSKAL, trace=True)
+    b = orc.solve(g, method=orc.RANK_PATHSORT, trace=True)
+    assert list(a["trace"]) == list(b["trace"])
+
+
+def test_rank_constructions_agree_on_a_deep_list():
+    """One path through every vertex (depth = n): the Kruskal construction
+    against the comparator sort."""
+    rng = np.random.default_rng(5)
+    n = 3000
+    order = rng.permutation(n)
+    succ = np.full(n, -1, np.int32)
+    succ[order[:-1]] = order[1:]
+    pri = rng.permutation(n).astype(np.int32)
+    k1, nf1, _ = orc.valuation(succ, pri, orc.RANK_KRUSKAL)
+    k2, nf2, _ = orc.valuation(succ, pri, orc.RANK_PATHSORT)
+    np.testing.assert_array_equal(k1, k2)
+    assert nf1 == nf2 == n + 1
+
+
+def test_hash_implementations_agree():
+    rng = np.random.default_rng(0)
+    for n in (0, 1, 2, 7, 1000):
+        a = rng.integers(-5, 2**31 - 1, size=n).astype(np.int32)
+        assert orc.key_hash(a) == np_hash(a)
+
+
+def test_final_strategy_invariants():
+    """At the end no edge is switchable, and the winning sets are closed
+    under the winners' strategies and the losers' moves (Theorem 1)."""
+    for g in [synth.random_game(20000, 2, 5, 8), synth.chain_game(20000, 8)]:
+        r = orc.solve(g)
+        aug = r["aug"]
+        key = r["key"]
+        n = aug["n"]
+        off, tgt, own = aug["offsets"], aug["targets"], aug["owner"]
+        _, c_odd = orc.odd_switch(aug, key, r["tau"])
+        _, c_even = orc.even_switch(aug, key, r["sigma"])
+        assert c_odd == 0 and c_even == 0
+        win = key[:n] != orc.KEY_TOP            # True = Odd wins (modified)
+        for v in range(n):
+            row = tgt[off[v]:off[v + 1]]
+            if own[v] == 0:
+                if not win[v]:
+                    assert r["sigma"][v] >= 0 and not win[r["sigma"][v]]
+                else:
+                    assert win[row].all()
+            else:
+                if win[v]:
+                    assert win[r["tau"][v]]
+                else:
+                    assert (~win[row]).all()
+
+
+# ---------------------------------------------------------------------------
+# planted mistakes: the pins above catch them
+# ---------------------------------------------------------------------------
+def test_planted_parity_flip_is_caught(monkeypatch):
+    orig = L.val_le
+
+    def flipped(l1, l2, dom):
+        if l1 is L.TOP or l2 is L.TOP:
+            return orig(l1, l2, dom)
+        i = L.maxdiff(l1, l2, dom)
+        if i is None:
+            return True
+        return l1[i] > l2[i]          # wrong: ignores the parity
+    monkeypatch.setattr(L, "val_le", flipped)
+    caught = False
+    for seed in range(40):
+        g = _tiny(seed)
+        try:
+            if not np.array_equal(L.solve(g)["winner"], zielonka(g)):
+                caught = True
+                break
+        except (L.Inadmissible, RuntimeError):
+            caught = True
+            break
+    assert caught
+
+
+def test_planted_dropped_term_is_caught(monkeypatch):
+    """A valuation that forgets the starting vertex's own priority."""
+    orig = L.valuation
+
+    def dropped(g, vals, sigma, tau):
+        val, cyc = orig(g, vals, sigma, tau)
+        out = []
+        for v, x in enumerate(val):
+            out.append(x if x is L.TOP else x - vals.unit(g["pri"][v]))
+        return out, cyc
+    monkeypatch.setattr(L, "valuation", dropped)
+    caught = False
+    for seed in range(12):
+        g = synth.random_game(10 + 7 * seed, 2, 4, 50 + seed)
+        try:
+            r = L.solve(g)
+        except (L.Inadmissible, RuntimeError):
+            caught = True          # the wrong order led SI astray
+            break
+        aug = r["aug"]
+        rows = L.rows_of(aug)
+        for sigma, tau, val in r["majors"]:
+            lab, _ = L.bellman_ford(aug, r["vals"], rows, sigma)
+            if not all(_same(a, b) for a, b in zip(lab, val)):
+                caught = True
+        if caught:
+            break
+    assert caught
+
+
+# ---------------------------------------------------------------------------
+# input generators
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("kind", ["rnd", "chain"])
+def test_generators_deterministic_and_well_formed(kind):
+    for n in (3, 12, 100, 5000):
+        make = (lambda s: synth.random_game(n, 2, 5, s)) if kind == "rnd" \
+            else (lambda s: synth.chain_game(n, s))
+        a, b = make(9), make(9)
+        for k in ("offsets", "targets", "owner", "pri"):
+            np.testing.assert_array_equal(a[k], b[k])
+        off, tgt = a["offsets"], a["targets"]
+        assert off[0] == 0 and off[-1] == a["m"] == tgt.size
+        deg = np.diff(off)
+        assert (deg >= 1).all()
+        if kind == "rnd":
+            assert (deg >= min(2, n - 1)).all() and (deg <= min(5, n - 1)).all()
+        np.testing.assert_array_equal(np.sort(a["pri"]), np.arange(n))
+        for v in range(n):
+            row = tgt[off[v]:off[v + 1]]
+            assert (np.diff(row) > 0).all()          # sorted, no repeats
+            if kind == "rnd":
+                assert v not in row
+            else:
+                assert (v + 1) % n in row
