@@ -1,0 +1,211 @@
+/*
+ * pg.h -- C ABI of the MI355X parity-game strategy-improvement library.
+ *
+ * The library solves parity games by greedy all-switches strategy
+ * improvement with one-player strategy improvement for best responses
+ * (Fearnley, "Efficient Parallel Strategy Improvement for Parity Games",
+ * Algorithm 1 in section 4).  Every step of that loop -- preprocessing,
+ * valuation (cycle marking, nearest-greater-ancestor tree, Euler-tour list
+ * construction, list ranking) and the switching rules -- runs in HIP kernels
+ * on the GPU the caller's stream belongs to.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Every call returns a pg_status.  Nothing throws or aborts across the
+ *    ABI.  On failure pg_last_error() returns a description; it is per
+ *    thread and stays valid until that thread's next call.
+ *  - Vertex ids are int32.  A game may have at most 2^30 - 2 vertices after
+ *    preprocessing; offsets are int64 (or int32 with PG_OFFSETS_I32).
+ *  - Buffers belong to the caller.  Without PG_PTR_DEVICE in `flags` they are
+ *    host pointers; with it they are device pointers on the current device
+ *    (for example torch tensors' data_ptr()).  Calls that write outputs
+ *    return after the outputs are written (the stream is synchronised).
+ *  - `hip_stream` is a hipStream_t (NULL = the default stream).  The game's
+ *    device memory is allocated by pg_load_csr and released by pg_free.
+ *  - Calls on one game must not overlap; different games are independent.
+ *
+ * Game model (section 2, "Parity games"): vertices 0..n-1, each owned by Even
+ * (0) or Odd (1), each with a priority and at least one outgoing edge.  The
+ * library needs pairwise distinct priorities: it represents a valuation by
+ * its rank, which is exact only when no priority repeats.
+ *
+ * The modified game (section 3, "A modified game" and "The algorithm"): a
+ * sink s gets an implicit edge from every Even vertex; preprocessing then
+ * appends dummy Even vertices d_w (ids n, n+1, ...) so that Odd cannot close
+ * a cycle of Odd vertices against the initial strategy.  n_aug and m_aug
+ * count the modified game without the sink.  Strategies and keys below are
+ * indexed in the modified game; PG_SINK names the sink as a successor.
+ */
+#ifndef PG_H
+#define PG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pg_game pg_game;
+
+typedef enum pg_status {
+    PG_OK = 0,
+    PG_EINVAL = 1,          /* invalid argument or game                      */
+    PG_ENOMEM = 2,          /* device or host allocation failed              */
+    PG_EDEVICE = 3,         /* a HIP runtime call failed                     */
+    PG_EITERLIMIT = 4,      /* an iteration cap was reached                  */
+    PG_EINADMISSIBLE = 5,   /* a cycle with odd largest priority was found   */
+    PG_EINTERNAL = 6        /* an internal consistency check failed          */
+} pg_status;
+
+/* Successor id meaning "the sink" in an Even entry of sigma. */
+#define PG_SINK (-1)
+/* Valuation key of a vertex whose play is infinite (the valuation top). */
+#define PG_KEY_TOP 2147483647
+
+enum {
+    PG_PTR_DEVICE = 1u,     /* buffer arguments are device pointers          */
+    PG_NO_PREPROCESS = 2u,  /* pg_load_csr: do not insert dummy vertices     */
+    PG_OFFSETS_I32 = 4u     /* pg_load_csr: offsets are int32, not int64     */
+};
+
+/*
+ * pg_load_csr -- validate a game and copy it to the device.
+ *
+ *   n, m      vertex and edge counts (n >= 1, m >= n)
+ *   offsets   n+1 entries: row v is targets[offsets[v] .. offsets[v+1]);
+ *             offsets[0] = 0, offsets[n] = m, every row non-empty (the paper
+ *             assumes no terminal vertices, section 2)
+ *   targets   m int32 successor ids in [0, n); self-loops and repeated
+ *             edges are allowed
+ *   owner     n bytes: 0 = Even, 1 = Odd
+ *   priority  n int32 priorities, >= 0 and pairwise distinct
+ *   flags     PG_PTR_DEVICE, PG_NO_PREPROCESS, PG_OFFSETS_I32
+ *
+ * Unless PG_NO_PREPROCESS is given, the admissibility preprocessing of
+ * section 3 ("The algorithm") runs on the device: X is the largest set of
+ * Odd vertices that each have a successor in X; for every w in X with a
+ * predecessor in X a dummy Even vertex d_w is appended (in increasing w),
+ * with the single row [w]; every edge (u, w) with u, w in X is redirected to
+ * d_w in place.  Dummies get priorities 0, 1, ... (the index of w); the
+ * original priorities are raised by that count rounded up to even, which
+ * keeps their order and parity.
+ *
+ * The inputs may be freed when the call returns.  Errors: PG_EINVAL for a
+ * malformed game (bad offsets, a terminal vertex, a target out of range, an
+ * owner not in {0,1}, a negative or repeated priority, a shifted priority
+ * above INT32_MAX, too many vertices), PG_ENOMEM, PG_EDEVICE.
+ */
+pg_status pg_load_csr(int64_t n, int64_t m, const void *offsets,
+                      const int32_t *targets, const uint8_t *owner,
+                      const int32_t *priority, uint32_t flags,
+                      void *hip_stream, pg_game **out_game);
+
+/* Sizes of the original and the modified game (any pointer may be NULL). */
+pg_status pg_game_info(const pg_game *game, int64_t *n, int64_t *m,
+                       int64_t *n_aug, int64_t *m_aug);
+
+/*
+ * pg_export_game -- copy the modified game out (for inspection and tests).
+ *   offsets  n_aug+1 int64;  targets  m_aug int32;  owner  n_aug bytes;
+ *   priority n_aug int32.   Any pointer may be NULL.
+ */
+pg_status pg_export_game(const pg_game *game, int64_t *offsets,
+                         int32_t *targets, uint8_t *owner, int32_t *priority,
+                         uint32_t flags, void *hip_stream);
+
+/*
+ * pg_initial_strategies -- the strategies Algorithm 1 starts from:
+ * sigma_init(v) = PG_SINK for every Even vertex (section 3, "The
+ * algorithm"), and for every Odd vertex the first entry of its row (the
+ * "arbitrary" initial Odd strategy of Algorithm 1).  sigma and tau have
+ * n_aug entries; entries of the other player are PG_SINK.
+ */
+pg_status pg_initial_strategies(pg_game *game, int32_t *sigma, int32_t *tau,
+                                uint32_t flags, void *hip_stream);
+
+/*
+ * pg_valuation -- one valuation Val^{sigma,tau} (section 3, "Valuations";
+ * computed as in section 5).
+ *
+ *   sigma   n_aug entries; for Even vertices a successor id or PG_SINK
+ *   tau     n_aug entries; for Odd vertices a successor id
+ *           (entries of the other player are ignored; every chosen successor
+ *           must be an edge of the modified game -- this is not checked)
+ *   key     n_aug+1 outputs: for a vertex whose play reaches the sink, the
+ *           rank of its valuation among all such vertices and the sink
+ *           (0 = smallest in the paper's order); PG_KEY_TOP for an infinite
+ *           play.  key[n_aug] is the sink's own rank.
+ *   n_finite (nullable) number of finite entries of key (the sink included)
+ *
+ * Returns PG_EINADMISSIBLE if the play graph has a cycle whose largest
+ * priority is odd (sigma is not admissible, section 3); key is then
+ * unspecified.
+ */
+pg_status pg_valuation(pg_game *game, const int32_t *sigma,
+                       const int32_t *tau, int32_t *key, int64_t *n_finite,
+                       uint32_t flags, void *hip_stream);
+
+/*
+ * pg_best_response -- the inner loop of Algorithm 1: one-player strategy
+ * improvement for Odd against a fixed admissible sigma (section 4).  Starting
+ * from tau, it repeats valuation and All_Odd -- every Odd vertex whose row
+ * has a successor of strictly smaller key moves to the first such successor
+ * of least key -- until no Odd vertex switches.
+ *
+ *   sigma         n_aug entries (as in pg_valuation), admissible
+ *   tau           n_aug entries; in: the start strategy; out: br(sigma)
+ *   key           n_aug+1 outputs (nullable): Val^{sigma, br(sigma)}
+ *   n_valuations  (nullable) number of valuations computed
+ *   max_inner     cap on valuations (0 = none); PG_EITERLIMIT when reached
+ */
+pg_status pg_best_response(pg_game *game, const int32_t *sigma, int32_t *tau,
+                           int32_t *key, int32_t *n_valuations,
+                           int32_t max_inner, uint32_t flags,
+                           void *hip_stream);
+
+typedef struct pg_solve_opts {
+    int32_t max_major;      /* cap on outer iterations (0 = none)            */
+    int32_t max_inner;      /* cap on valuations per best response (0=none)  */
+    uint32_t flags;         /* PG_PTR_DEVICE for the output buffers          */
+    int32_t reserved;
+} pg_solve_opts;
+
+typedef struct pg_stats {
+    int64_t n, m, n_aug, m_aug;
+    int64_t n_major;        /* outer iterations, the final one included      */
+    int64_t n_valuations;   /* valuations over the whole solve               */
+    int64_t n_odd_switches; /* vertices switched by All_Odd, summed          */
+    int64_t n_even_switches;/* vertices switched by All_Even, summed         */
+    double seconds;         /* wall time of the solve on the host clock      */
+} pg_stats;
+
+/*
+ * pg_solve -- Algorithm 1 from the initial strategies to the end.  The outer
+ * loop switches Even by greedy all-switches (section 3, "Switching rules"):
+ * among the sink (option 0) and the row, the first option of greatest key
+ * replaces sigma(v) if its key is strictly greater.  It stops when no Even
+ * vertex switches; by Theorem 1 the vertices of key PG_KEY_TOP are then
+ * exactly Even's winning set.
+ *
+ *   opts     nullable (no caps; host outputs)
+ *   winner   n outputs (original vertices): 0 = W_Even, 1 = W_Odd
+ *   sigma    n_aug outputs (nullable): the final sigma* (PG_SINK for the
+ *            sink); vertices Even wins never map to the sink
+ *   tau      n_aug outputs (nullable): the final tau* = br(sigma*)
+ *   stats    nullable
+ */
+pg_status pg_solve(pg_game *game, const pg_solve_opts *opts, uint8_t *winner,
+                   int32_t *sigma, int32_t *tau, pg_stats *stats,
+                   void *hip_stream);
+
+/* Release the game's device memory.  NULL is accepted. */
+pg_status pg_free(pg_game *game);
+
+/* Description of the calling thread's last error ("" if none). */
+const char *pg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PG_H */

@@ -1,0 +1,740 @@
+// The C ABI (include/pg.h): game loading and validation, the admissibility
+// preprocessing, strategy import/export and the loops of Algorithm 1.
+#include <chrono>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pg_common.h"
+
+static thread_local std::string g_last_error;
+
+pg_status pg_fail(pg_status st, const std::string &msg) {
+  g_last_error = msg;
+  return st;
+}
+
+namespace pgk {
+
+// ---------------------------------------------------------------------------
+// validation (section 2: every vertex owned by one player, has an outgoing
+// edge and a priority; distinct priorities are required by the rank keys)
+// ---------------------------------------------------------------------------
+__global__ void k_off32_to_64(const int32_t *in, int64_t *out, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = in[i];
+}
+
+__global__ void k_check_offsets(const int64_t *off, int64_t n, int64_t m,
+                                int32_t *ctr) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int64_t a = off[v], b = off[v + 1];
+  bool bad = (b <= a) || (b > m) || (a < 0);
+  if (v == 0 && a != 0) bad = true;
+  if (v == n - 1 && b != m) bad = true;
+  if (bad) atomicOr(&ctr[C_ERR], ERR_INVAL);
+}
+
+__global__ void k_check_targets(const int32_t *tgt, int64_t m, int64_t n,
+                                int32_t *ctr) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m) return;
+  const int32_t t = tgt[e];
+  if (t < 0 || (int64_t)t >= n) atomicOr(&ctr[C_ERR], ERR_INVAL);
+}
+
+__global__ void k_check_vertices(const uint8_t *owner, const int32_t *pri,
+                                 int64_t n, int32_t *ctr) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  if (owner[v] > 1 || pri[v] < 0) atomicOr(&ctr[C_ERR], ERR_INVAL);
+}
+
+// ---------------------------------------------------------------------------
+// preprocessing (section 3, "The algorithm")
+// ---------------------------------------------------------------------------
+// X: the largest set of Odd vertices each with a successor in X, found by
+// removing Odd vertices without a successor in X until nothing changes.
+// Updates are made in place; any interleaving of them converges to the same
+// largest fixpoint.
+__global__ void k_x_init(const uint8_t *owner, uint8_t *inx, int64_t n) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) inx[v] = owner[v] == 1;
+}
+
+__global__ void k_x_round(const int64_t *__restrict__ off,
+                          const int32_t *__restrict__ tgt, uint8_t *inx,
+                          int64_t n, int32_t *ctr) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool drop = false;
+  if (v < n && __hip_atomic_load(&inx[v], __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT)) {
+    bool any = false;
+    for (int64_t e = off[v], end = off[v + 1]; e < end && !any; ++e)
+      any = __hip_atomic_load(&inx[tgt[e]], __ATOMIC_RELAXED,
+                              __HIP_MEMORY_SCOPE_AGENT) != 0;
+    if (!any) {
+      __hip_atomic_store(&inx[v], (uint8_t)0, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+      drop = true;
+    }
+  }
+  if (__ballot(drop) && (threadIdx.x & (kWave - 1)) == 0)
+    atomicAdd(&ctr[C_MISC], 1);
+}
+
+// X': members of X with a predecessor in X
+__global__ void k_xp_mark(const int64_t *__restrict__ off,
+                          const int32_t *__restrict__ tgt,
+                          const uint8_t *__restrict__ inx, uint32_t *xp,
+                          int64_t n) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n || !inx[v]) return;
+  for (int64_t e = off[v], end = off[v + 1]; e < end; ++e) {
+    const int32_t w = tgt[e];
+    if (inx[w]) xp[w] = 1u;
+  }
+}
+
+// The modified game: rows of original vertices keep their length, edges
+// between members of X go through the dummy of their target; the dummy of the
+// i-th member w of X' is vertex n + i, Even, priority i, row [w].  Original
+// priorities rise by K (|X'| rounded up to even).
+__global__ void k_aug_build(int64_t n, int64_t m, int64_t K,
+                            const int64_t *__restrict__ off,
+                            const int32_t *__restrict__ tgt,
+                            const uint8_t *__restrict__ owner,
+                            const int32_t *__restrict__ pri,
+                            const uint8_t *__restrict__ inx,
+                            const uint32_t *__restrict__ xp,
+                            const uint32_t *__restrict__ did, int64_t *off2,
+                            int32_t *tgt2, uint8_t *owner2, int32_t *pri2,
+                            int32_t *ctr) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  off2[v] = off[v];
+  if (v == n - 1) off2[n] = off[n];
+  const bool vx = inx[v] != 0;
+  for (int64_t e = off[v], end = off[v + 1]; e < end; ++e) {
+    const int32_t w = tgt[e];
+    tgt2[e] = (vx && inx[w]) ? (int32_t)(n + did[w]) : w;
+  }
+  owner2[v] = owner[v];
+  const int64_t p = (int64_t)pri[v] + K;
+  if (p > 2147483647LL) atomicOr(&ctr[C_ERR], ERR_INVAL);
+  pri2[v] = (int32_t)p;
+  if (xp[v]) {
+    const int64_t i = did[v];
+    owner2[n + i] = 0;
+    pri2[n + i] = (int32_t)i;
+    tgt2[m + i] = (int32_t)v;
+    off2[n + i + 1] = m + i + 1;
+  }
+}
+
+// signed-priority order: odd priorities descending, then even ascending
+__global__ void k_rv_keys(const int32_t *pri, uint32_t *sk, uint32_t *sv,
+                          int64_t n) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const uint32_t p = (uint32_t)pri[v];
+  sk[v] = (p & 1u) ? (0x7fffffffu - p) : (0x80000000u + p);
+  sv[v] = (uint32_t)v;
+}
+
+__global__ void k_rv_finish(const uint32_t *skS, const uint32_t *svS,
+                            int32_t *perm, int64_t n, int32_t *ctr) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool odd = false;
+  if (i < n) {
+    perm[i] = (int32_t)svS[i];
+    odd = skS[i] < 0x80000000u;
+    if (i > 0 && skS[i] == skS[i - 1]) atomicOr(&ctr[C_ERR], ERR_DUPPRI);
+  }
+  uint64_t b = __ballot(odd);
+  if (b && (threadIdx.x & (kWave - 1)) == 0)
+    atomicAdd(&ctr[C_MISC], (int)__popcll(b));
+}
+
+// ---------------------------------------------------------------------------
+// strategies <-> play graph
+// ---------------------------------------------------------------------------
+__global__ void k_sp_init(const int64_t *off, const int32_t *tgt,
+                          const uint8_t *owner, const int32_t *pri, int2 *sp,
+                          int32_t N) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v == 0) sp[N] = make_int2(N, 2147483647);
+  if (v >= N) return;
+  const int32_t s = owner[v] ? tgt[off[v]] : N;
+  sp[v] = make_int2(s, pri[v]);
+}
+
+__global__ void k_sp_import(const uint8_t *owner, const int32_t *sigma,
+                            const int32_t *tau, int2 *sp, int32_t N,
+                            int32_t *ctr) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= N) return;
+  int32_t s;
+  if (owner[v] == 0) {
+    s = sigma[v];
+    if (s == PG_SINK) s = N;
+  } else {
+    s = tau[v];
+  }
+  if (s < 0 || s > N || (s == N && owner[v] != 0)) {
+    atomicOr(&ctr[C_ERR], ERR_INVAL);
+    s = N;
+  }
+  sp[v].x = s;
+}
+
+__global__ void k_sp_export(const uint8_t *owner, const int2 *sp,
+                            int32_t *sigma, int32_t *tau, int32_t N) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= N) return;
+  const int32_t s = sp[v].x;
+  const bool even = owner[v] == 0;
+  if (sigma) sigma[v] = even ? (s == N ? PG_SINK : s) : PG_SINK;
+  if (tau) tau[v] = even ? PG_SINK : s;
+}
+
+__global__ void k_initial(const int64_t *off, const int32_t *tgt,
+                          const uint8_t *owner, int32_t *sigma, int32_t *tau,
+                          int32_t N) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= N) return;
+  if (sigma) sigma[v] = PG_SINK;
+  if (tau) tau[v] = owner[v] ? tgt[off[v]] : PG_SINK;
+}
+
+// Theorem 1: W_Even is the set of vertices whose final valuation is top
+__global__ void k_winner(const int32_t *key, uint8_t *winner, int64_t n) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) winner[v] = key[v] == PG_KEY_TOP ? 0 : 1;
+}
+
+}  // namespace pgk
+
+using namespace pgk;
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+namespace {
+
+struct DevGuard {
+  int prev = -1;
+  explicit DevGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DevGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev)
+      (void)hipSetDevice(prev);
+  }
+};
+
+template <typename T>
+pg_status dev_alloc(T **p, int64_t count) {
+  size_t bytes = sizeof(T) * (size_t)(count > 0 ? count : 1);
+  hipError_t e = hipMalloc((void **)p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return pg_fail(PG_ENOMEM, "hipMalloc of " + std::to_string(bytes) +
+                                  " bytes failed: " + hipGetErrorString(e));
+  }
+  return PG_OK;
+}
+
+#define PG_TRY(expr)                   \
+  do {                                 \
+    pg_status st_ = (expr);            \
+    if (st_ != PG_OK) return st_;      \
+  } while (0)
+
+// Copies count elements to or from the caller's buffer, which is on the
+// device when `device` is true.
+pg_status copy_in(void *dst, const void *src, size_t bytes, bool device,
+                  hipStream_t s) {
+  if (bytes == 0) return PG_OK;
+  PG_HIP(hipMemcpyAsync(dst, src, bytes,
+                        device ? hipMemcpyDeviceToDevice
+                               : hipMemcpyHostToDevice,
+                        s));
+  return PG_OK;
+}
+
+pg_status copy_out(void *dst, const void *src, size_t bytes, bool device,
+                   hipStream_t s) {
+  if (bytes == 0) return PG_OK;
+  PG_HIP(hipMemcpyAsync(dst, src, bytes,
+                        device ? hipMemcpyDeviceToDevice
+                               : hipMemcpyDeviceToHost,
+                        s));
+  return PG_OK;
+}
+
+pg_status sync_ctr(pg_game *g, hipStream_t s) {
+  PG_HIP(hipMemcpyAsync(g->hctr, g->ctr, sizeof(int32_t) * C_COUNT,
+                        hipMemcpyDeviceToHost, s));
+  PG_HIP(hipStreamSynchronize(s));
+  return PG_OK;
+}
+
+void free_game(pg_game *g) {
+  if (!g) return;
+  void *ptrs[] = {g->off,  g->tgt,   g->owner, g->pri,     g->perm,
+                  g->sp,   g->key,   g->ng,    g->cand,    g->wl0,
+                  g->wl1,  g->rs,    g->sk0,   g->sv0,     g->sk1,
+                  g->sv1,  g->tile_cnt, g->scan_tmp, g->kids, g->first,
+                  g->pos,  g->haseven, g->elem, g->ctr};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  for (int k = 0; k < 8; ++k) {
+    if (g->lv[k].sum) (void)hipFree(g->lv[k].sum);
+    if (g->lv[k].next) (void)hipFree(g->lv[k].next);
+    if (g->lv[k].base) (void)hipFree(g->lv[k].base);
+  }
+  if (g->hctr) (void)hipHostFree(g->hctr);
+  delete g;
+}
+
+// Allocates the per-solve state once the modified game's size is known.
+pg_status alloc_state(pg_game *g) {
+  const int64_t N = g->n_aug;
+  PG_TRY(dev_alloc(&g->perm, N));
+  PG_TRY(dev_alloc(&g->sp, N + 1));
+  PG_TRY(dev_alloc(&g->key, N + 1));
+  PG_TRY(dev_alloc(&g->ng, N + 1));
+  PG_TRY(dev_alloc(&g->cand, N));
+  PG_TRY(dev_alloc(&g->wl0, N));
+  PG_TRY(dev_alloc(&g->wl1, N));
+  PG_TRY(dev_alloc(&g->rs, N + 1));
+  PG_TRY(dev_alloc(&g->sk0, N));
+  PG_TRY(dev_alloc(&g->sv0, N));
+  PG_TRY(dev_alloc(&g->sk1, N));
+  PG_TRY(dev_alloc(&g->sv1, N));
+  g->tiles = radix_tiles(N);
+  PG_TRY(dev_alloc(&g->tile_cnt, 256 * g->tiles));
+  g->scan_tmp_bytes = radix_scan_tmp_bytes(N);
+  size_t s2 = scan_excl_u32(nullptr, nullptr, N, nullptr, 0);
+  if (s2 > g->scan_tmp_bytes) g->scan_tmp_bytes = s2;
+  PG_TRY(dev_alloc((uint8_t **)&g->scan_tmp, (int64_t)g->scan_tmp_bytes + 16));
+  PG_TRY(dev_alloc(&g->kids, N));
+  PG_TRY(dev_alloc(&g->first, N + 1));
+  PG_TRY(dev_alloc(&g->pos, N + 1));
+  PG_TRY(dev_alloc(&g->haseven, N + 1));
+  PG_TRY(dev_alloc(&g->elem, 2 * N + 2));
+  // sublist levels for the longest possible Euler list
+  int64_t size = 2 * N + 2;
+  for (int k = 0; k < 7; ++k) {
+    const int stride = 32;
+    const int64_t ns = (size + stride - 1) / stride;
+    PG_TRY(dev_alloc(&g->lv[k].sum, ns));
+    PG_TRY(dev_alloc(&g->lv[k].next, ns));
+    PG_TRY(dev_alloc(&g->lv[k].base, ns));
+    size = ns;
+    if (size <= 1) break;
+  }
+  int bits = 1;
+  while ((int64_t(1) << bits) <= N + 1) ++bits;
+  g->sort_bits = bits;
+  return PG_OK;
+}
+
+pg_status check_err(pg_game *g, const char *what) {
+  const int e = g->hctr[C_ERR];
+  if (e & ERR_INVAL) return pg_fail(PG_EINVAL, std::string(what));
+  if (e & ERR_DUPPRI)
+    return pg_fail(PG_EINVAL, "priorities must be pairwise distinct");
+  if (e & ERR_INADMISSIBLE)
+    return pg_fail(PG_EINADMISSIBLE,
+                   "the play graph has a cycle whose largest priority is odd");
+  if (e & (ERR_LISTWALK | ERR_RANKCOUNT))
+    return pg_fail(PG_EINTERNAL, "list ranking failed a consistency check");
+  return PG_OK;
+}
+
+pg_status load_impl(int64_t n, int64_t m, const void *offsets,
+                    const int32_t *targets, const uint8_t *owner,
+                    const int32_t *priority, uint32_t flags, hipStream_t s,
+                    pg_game *g) {
+  const bool dev = flags & PG_PTR_DEVICE;
+  g->n = n;
+  g->m = m;
+  PG_HIP(hipHostMalloc((void **)&g->hctr, sizeof(int32_t) * C_COUNT,
+                       hipHostMallocDefault));
+  PG_TRY(dev_alloc(&g->ctr, C_COUNT));
+  fill_i32(g->ctr, 0, C_COUNT, s);
+
+  // input copies
+  int64_t *off_in = nullptr;
+  int32_t *tgt_in = nullptr, *pri_in = nullptr;
+  uint8_t *own_in = nullptr;
+  struct Tmp {
+    std::vector<void *> p;
+    ~Tmp() { for (void *x : p) if (x) (void)hipFree(x); }
+  } tmp;
+  PG_TRY(dev_alloc(&off_in, n + 1));
+  tmp.p.push_back(off_in);
+  PG_TRY(dev_alloc(&tgt_in, m));
+  tmp.p.push_back(tgt_in);
+  PG_TRY(dev_alloc(&own_in, n));
+  tmp.p.push_back(own_in);
+  PG_TRY(dev_alloc(&pri_in, n));
+  tmp.p.push_back(pri_in);
+  if (flags & PG_OFFSETS_I32) {
+    int32_t *o32 = nullptr;
+    PG_TRY(dev_alloc(&o32, n + 1));
+    tmp.p.push_back(o32);
+    PG_TRY(copy_in(o32, offsets, sizeof(int32_t) * (n + 1), dev, s));
+    hipLaunchKernelGGL(k_off32_to_64, dim3(grid_for(n + 1)), dim3(kBlock), 0,
+                       s, o32, off_in, n + 1);
+  } else {
+    PG_TRY(copy_in(off_in, offsets, sizeof(int64_t) * (n + 1), dev, s));
+  }
+  PG_TRY(copy_in(tgt_in, targets, sizeof(int32_t) * m, dev, s));
+  PG_TRY(copy_in(own_in, owner, n, dev, s));
+  PG_TRY(copy_in(pri_in, priority, sizeof(int32_t) * n, dev, s));
+
+  hipLaunchKernelGGL(k_check_offsets, dim3(grid_for(n)), dim3(kBlock), 0, s,
+                     off_in, n, m, g->ctr);
+  PG_TRY(sync_ctr(g, s));
+  if (g->hctr[C_ERR])
+    return pg_fail(PG_EINVAL,
+                   "offsets must start at 0, end at m and give every vertex "
+                   "a non-empty row");
+  hipLaunchKernelGGL(k_check_targets, dim3(grid_for(m)), dim3(kBlock), 0, s,
+                     tgt_in, m, n, g->ctr);
+  hipLaunchKernelGGL(k_check_vertices, dim3(grid_for(n)), dim3(kBlock), 0, s,
+                     own_in, pri_in, n, g->ctr);
+  PG_TRY(sync_ctr(g, s));
+  if (g->hctr[C_ERR])
+    return pg_fail(PG_EINVAL,
+                   "targets must lie in [0, n), owners in {0, 1} and "
+                   "priorities be >= 0");
+
+  int64_t nxp = 0;
+  uint8_t *inx = nullptr;
+  uint32_t *xp = nullptr, *did = nullptr;
+  if (!(flags & PG_NO_PREPROCESS)) {
+    PG_TRY(dev_alloc(&inx, n));
+    tmp.p.push_back(inx);
+    PG_TRY(dev_alloc(&xp, n));
+    tmp.p.push_back(xp);
+    PG_TRY(dev_alloc(&did, n));
+    tmp.p.push_back(did);
+    hipLaunchKernelGGL(k_x_init, dim3(grid_for(n)), dim3(kBlock), 0, s, own_in,
+                       inx, n);
+    for (int64_t round = 0;; round += 4) {
+      if (round > 4 * n + 64)
+        return pg_fail(PG_EINTERNAL, "preprocessing did not converge");
+      fill_i32(g->ctr + C_MISC, 0, 1, s);
+      for (int k = 0; k < 4; ++k)
+        hipLaunchKernelGGL(k_x_round, dim3(grid_for(n)), dim3(kBlock), 0, s,
+                           off_in, tgt_in, inx, n, g->ctr);
+      PG_TRY(sync_ctr(g, s));
+      if (g->hctr[C_MISC] == 0) break;
+    }
+    fill_i32((int32_t *)xp, 0, n, s);
+    hipLaunchKernelGGL(k_xp_mark, dim3(grid_for(n)), dim3(kBlock), 0, s,
+                       off_in, tgt_in, inx, xp, n);
+    size_t need = scan_excl_u32(nullptr, nullptr, n, nullptr, s);
+    void *stmp = nullptr;
+    PG_TRY(dev_alloc((uint8_t **)&stmp, (int64_t)need + 16));
+    tmp.p.push_back(stmp);
+    scan_excl_u32(xp, did, n, stmp, s);
+    uint32_t last[2] = {0, 0};
+    PG_HIP(hipMemcpyAsync(&last[0], did + (n - 1), 4, hipMemcpyDeviceToHost,
+                          s));
+    PG_HIP(hipMemcpyAsync(&last[1], xp + (n - 1), 4, hipMemcpyDeviceToHost, s));
+    PG_HIP(hipStreamSynchronize(s));
+    nxp = (int64_t)last[0] + last[1];
+  }
+  g->n_aug = n + nxp;
+  g->m_aug = m + nxp;
+  if (g->n_aug > kMaxVertices)
+    return pg_fail(PG_EINVAL, "too many vertices after preprocessing");
+
+  PG_TRY(dev_alloc(&g->off, g->n_aug + 1));
+  PG_TRY(dev_alloc(&g->tgt, g->m_aug));
+  PG_TRY(dev_alloc(&g->owner, g->n_aug));
+  PG_TRY(dev_alloc(&g->pri, g->n_aug));
+  if (flags & PG_NO_PREPROCESS) {
+    PG_HIP(hipMemcpyAsync(g->off, off_in, sizeof(int64_t) * (n + 1),
+                          hipMemcpyDeviceToDevice, s));
+    PG_HIP(hipMemcpyAsync(g->tgt, tgt_in, sizeof(int32_t) * m,
+                          hipMemcpyDeviceToDevice, s));
+    PG_HIP(hipMemcpyAsync(g->owner, own_in, n, hipMemcpyDeviceToDevice, s));
+    PG_HIP(hipMemcpyAsync(g->pri, pri_in, sizeof(int32_t) * n,
+                          hipMemcpyDeviceToDevice, s));
+  } else {
+    const int64_t K = nxp + (nxp & 1);
+    hipLaunchKernelGGL(k_aug_build, dim3(grid_for(n)), dim3(kBlock), 0, s, n,
+                       m, K, off_in, tgt_in, own_in, pri_in, inx, xp, did,
+                       g->off, g->tgt, g->owner, g->pri, g->ctr);
+  }
+  PG_TRY(alloc_state(g));
+
+  // signed-priority order, distinctness check, count of odd priorities
+  const int64_t N = g->n_aug;
+  fill_i32(g->ctr + C_MISC, 0, 1, s);
+  hipLaunchKernelGGL(k_rv_keys, dim3(grid_for(N)), dim3(kBlock), 0, s, g->pri,
+                     g->sk0, g->sv0, N);
+  int which = radix_sort(g->sk0, g->sv0, g->sk1, g->sv1, N, 32, g->tile_cnt,
+                         g->scan_tmp, s);
+  hipLaunchKernelGGL(k_rv_finish, dim3(grid_for(N)), dim3(kBlock), 0, s,
+                     which ? g->sk1 : g->sk0, which ? g->sv1 : g->sv0, g->perm,
+                     N, g->ctr);
+  hipLaunchKernelGGL(k_sp_init, dim3(grid_for(N)), dim3(kBlock), 0, s, g->off,
+                     g->tgt, g->owner, g->pri, g->sp, (int32_t)N);
+  PG_TRY(sync_ctr(g, s));
+  PG_TRY(check_err(g, "a priority exceeds INT32_MAX after preprocessing"));
+  g->n_oddpri = g->hctr[C_MISC];
+  return PG_OK;
+}
+
+// Stages caller strategy arrays (host or device) into the play graph.
+pg_status import_strats(pg_game *g, const int32_t *sigma, const int32_t *tau,
+                        bool dev, hipStream_t s) {
+  const int64_t N = g->n_aug;
+  const int32_t *ds = sigma, *dt = tau;
+  if (!dev) {
+    PG_TRY(copy_in(g->wl0, sigma, sizeof(int32_t) * N, false, s));
+    PG_TRY(copy_in(g->wl1, tau, sizeof(int32_t) * N, false, s));
+    ds = g->wl0;
+    dt = g->wl1;
+  }
+  fill_i32(g->ctr, 0, C_COUNT, s);
+  hipLaunchKernelGGL(k_sp_import, dim3(grid_for(N)), dim3(kBlock), 0, s,
+                     g->owner, ds, dt, g->sp, (int32_t)N, g->ctr);
+  PG_TRY(sync_ctr(g, s));
+  if (g->hctr[C_ERR] & ERR_INVAL)
+    return pg_fail(PG_EINVAL,
+                   "a strategy entry is out of range (Even: a vertex id or "
+                   "PG_SINK, Odd: a vertex id)");
+  return PG_OK;
+}
+
+pg_status export_strats(pg_game *g, int32_t *sigma, int32_t *tau, bool dev,
+                        hipStream_t s) {
+  const int64_t N = g->n_aug;
+  if (!sigma && !tau) return PG_OK;
+  int32_t *ds = dev ? sigma : (sigma ? g->wl0 : nullptr);
+  int32_t *dt = dev ? tau : (tau ? g->wl1 : nullptr);
+  hipLaunchKernelGGL(k_sp_export, dim3(grid_for(N)), dim3(kBlock), 0, s,
+                     g->owner, g->sp, ds, dt, (int32_t)N);
+  if (!dev) {
+    if (sigma) PG_TRY(copy_out(sigma, g->wl0, sizeof(int32_t) * N, false, s));
+    if (tau) PG_TRY(copy_out(tau, g->wl1, sizeof(int32_t) * N, false, s));
+  }
+  PG_HIP(hipStreamSynchronize(s));
+  return PG_OK;
+}
+
+// The inner loop of Algorithm 1 on the play graph in g->sp.
+pg_status inner_loop(pg_game *g, int32_t max_inner, hipStream_t s,
+                     int64_t *n_val, int64_t *n_sw) {
+  int32_t inner = 0;
+  for (;;) {
+    if (max_inner > 0 && inner >= max_inner)
+      return pg_fail(PG_EITERLIMIT, "best response: valuation cap reached");
+    PG_TRY(valuation_device(g, s, nullptr));
+    ++inner;
+    ++*n_val;
+    int32_t c = 0;
+    PG_TRY(switch_device(g, true, s, &c));
+    *n_sw += c;
+    if (c == 0) return PG_OK;
+  }
+}
+
+}  // namespace
+
+// ===========================================================================
+// the C ABI
+// ===========================================================================
+extern "C" {
+
+const char *pg_last_error(void) { return g_last_error.c_str(); }
+
+pg_status pg_load_csr(int64_t n, int64_t m, const void *offsets,
+                      const int32_t *targets, const uint8_t *owner,
+                      const int32_t *priority, uint32_t flags,
+                      void *hip_stream, pg_game **out_game) {
+  g_last_error.clear();
+  if (!out_game) return pg_fail(PG_EINVAL, "out_game is NULL");
+  *out_game = nullptr;
+  if (n < 1 || m < n) return pg_fail(PG_EINVAL, "need n >= 1 and m >= n");
+  if (n > kMaxVertices || m > 0x7fffffffLL * 4)
+    return pg_fail(PG_EINVAL, "game too large");
+  if (!offsets || !targets || !owner || !priority)
+    return pg_fail(PG_EINVAL, "a game array is NULL");
+  if ((flags & PG_OFFSETS_I32) && m > 0x7fffffffLL)
+    return pg_fail(PG_EINVAL, "int32 offsets cannot address m edges");
+  pg_game *g = new (std::nothrow) pg_game();
+  if (!g) return pg_fail(PG_ENOMEM, "host allocation failed");
+  if (hipGetDevice(&g->device) != hipSuccess) {
+    delete g;
+    return pg_fail(PG_EDEVICE, "no HIP device");
+  }
+  hipStream_t s = (hipStream_t)hip_stream;
+  pg_status st = load_impl(n, m, offsets, targets, owner, priority, flags, s, g);
+  if (st != PG_OK) {
+    (void)hipStreamSynchronize(s);
+    free_game(g);
+    return st;
+  }
+  *out_game = g;
+  return PG_OK;
+}
+
+pg_status pg_game_info(const pg_game *g, int64_t *n, int64_t *m,
+                       int64_t *n_aug, int64_t *m_aug) {
+  if (!g) return pg_fail(PG_EINVAL, "game is NULL");
+  if (n) *n = g->n;
+  if (m) *m = g->m;
+  if (n_aug) *n_aug = g->n_aug;
+  if (m_aug) *m_aug = g->m_aug;
+  return PG_OK;
+}
+
+pg_status pg_export_game(const pg_game *gc, int64_t *offsets, int32_t *targets,
+                         uint8_t *owner, int32_t *priority, uint32_t flags,
+                         void *hip_stream) {
+  if (!gc) return pg_fail(PG_EINVAL, "game is NULL");
+  pg_game *g = const_cast<pg_game *>(gc);
+  DevGuard guard(g->device);
+  hipStream_t s = (hipStream_t)hip_stream;
+  const bool dev = flags & PG_PTR_DEVICE;
+  if (offsets)
+    PG_TRY(copy_out(offsets, g->off, sizeof(int64_t) * (g->n_aug + 1), dev, s));
+  if (targets)
+    PG_TRY(copy_out(targets, g->tgt, sizeof(int32_t) * g->m_aug, dev, s));
+  if (owner) PG_TRY(copy_out(owner, g->owner, g->n_aug, dev, s));
+  if (priority)
+    PG_TRY(copy_out(priority, g->pri, sizeof(int32_t) * g->n_aug, dev, s));
+  PG_HIP(hipStreamSynchronize(s));
+  return PG_OK;
+}
+
+pg_status pg_initial_strategies(pg_game *g, int32_t *sigma, int32_t *tau,
+                                uint32_t flags, void *hip_stream) {
+  if (!g) return pg_fail(PG_EINVAL, "game is NULL");
+  DevGuard guard(g->device);
+  hipStream_t s = (hipStream_t)hip_stream;
+  const bool dev = flags & PG_PTR_DEVICE;
+  const int64_t N = g->n_aug;
+  int32_t *ds = dev ? sigma : (sigma ? g->wl0 : nullptr);
+  int32_t *dt = dev ? tau : (tau ? g->wl1 : nullptr);
+  hipLaunchKernelGGL(k_initial, dim3(grid_for(N)), dim3(kBlock), 0, s, g->off,
+                     g->tgt, g->owner, ds, dt, (int32_t)N);
+  if (!dev) {
+    if (sigma) PG_TRY(copy_out(sigma, g->wl0, sizeof(int32_t) * N, false, s));
+    if (tau) PG_TRY(copy_out(tau, g->wl1, sizeof(int32_t) * N, false, s));
+  }
+  PG_HIP(hipStreamSynchronize(s));
+  return PG_OK;
+}
+
+pg_status pg_valuation(pg_game *g, const int32_t *sigma, const int32_t *tau,
+                       int32_t *key, int64_t *n_finite, uint32_t flags,
+                       void *hip_stream) {
+  if (!g) return pg_fail(PG_EINVAL, "game is NULL");
+  if (!sigma || !tau || !key) return pg_fail(PG_EINVAL, "NULL argument");
+  DevGuard guard(g->device);
+  hipStream_t s = (hipStream_t)hip_stream;
+  const bool dev = flags & PG_PTR_DEVICE;
+  PG_TRY(import_strats(g, sigma, tau, dev, s));
+  PG_TRY(valuation_device(g, s, n_finite));
+  PG_TRY(copy_out(key, g->key, sizeof(int32_t) * (g->n_aug + 1), dev, s));
+  PG_TRY(sync_ctr(g, s));
+  PG_TRY(check_err(g, "invalid strategy"));
+  return PG_OK;
+}
+
+pg_status pg_best_response(pg_game *g, const int32_t *sigma, int32_t *tau,
+                           int32_t *key, int32_t *n_valuations,
+                           int32_t max_inner, uint32_t flags,
+                           void *hip_stream) {
+  if (!g) return pg_fail(PG_EINVAL, "game is NULL");
+  if (!sigma || !tau) return pg_fail(PG_EINVAL, "NULL argument");
+  DevGuard guard(g->device);
+  hipStream_t s = (hipStream_t)hip_stream;
+  const bool dev = flags & PG_PTR_DEVICE;
+  PG_TRY(import_strats(g, sigma, tau, dev, s));
+  int64_t nv = 0, nsw = 0;
+  pg_status st = inner_loop(g, max_inner, s, &nv, &nsw);
+  if (n_valuations) *n_valuations = (int32_t)nv;
+  if (st != PG_OK) return st;
+  PG_TRY(export_strats(g, nullptr, tau, dev, s));
+  if (key)
+    PG_TRY(copy_out(key, g->key, sizeof(int32_t) * (g->n_aug + 1), dev, s));
+  PG_HIP(hipStreamSynchronize(s));
+  return PG_OK;
+}
+
+pg_status pg_solve(pg_game *g, const pg_solve_opts *opts, uint8_t *winner,
+                   int32_t *sigma, int32_t *tau, pg_stats *stats,
+                   void *hip_stream) {
+  if (!g) return pg_fail(PG_EINVAL, "game is NULL");
+  if (!winner) return pg_fail(PG_EINVAL, "winner is NULL");
+  DevGuard guard(g->device);
+  hipStream_t s = (hipStream_t)hip_stream;
+  pg_solve_opts o{};
+  if (opts) o = *opts;
+  const bool dev = o.flags & PG_PTR_DEVICE;
+  const auto t0 = std::chrono::steady_clock::now();
+  const int64_t N = g->n_aug;
+  hipLaunchKernelGGL(k_sp_init, dim3(grid_for(N)), dim3(kBlock), 0, s, g->off,
+                     g->tgt, g->owner, g->pri, g->sp, (int32_t)N);
+  int64_t n_major = 0, n_val = 0, n_odd = 0, n_even = 0;
+  pg_status st = PG_OK;
+  for (;;) {
+    if (o.max_major > 0 && n_major >= o.max_major) {
+      st = pg_fail(PG_EITERLIMIT, "solve: outer iteration cap reached");
+      break;
+    }
+    ++n_major;
+    st = inner_loop(g, o.max_inner, s, &n_val, &n_odd);
+    if (st != PG_OK) break;
+    int32_t c = 0;
+    st = switch_device(g, false, s, &c);
+    if (st != PG_OK) break;
+    n_even += c;
+    if (c == 0) break;
+  }
+  if (stats) {
+    stats->n = g->n;
+    stats->m = g->m;
+    stats->n_aug = g->n_aug;
+    stats->m_aug = g->m_aug;
+    stats->n_major = n_major;
+    stats->n_valuations = n_val;
+    stats->n_odd_switches = n_odd;
+    stats->n_even_switches = n_even;
+  }
+  if (st != PG_OK) return st;
+  uint8_t *dw = winner;
+  if (!dev) dw = (uint8_t *)g->wl0;
+  hipLaunchKernelGGL(k_winner, dim3(grid_for(g->n)), dim3(kBlock), 0, s,
+                     g->key, dw, g->n);
+  if (!dev) PG_TRY(copy_out(winner, dw, g->n, false, s));
+  PG_HIP(hipStreamSynchronize(s));
+  PG_TRY(export_strats(g, sigma, tau, dev, s));
+  const auto t1 = std::chrono::steady_clock::now();
+  if (stats) stats->seconds = std::chrono::duration<double>(t1 - t0).count();
+  return PG_OK;
+}
+
+pg_status pg_free(pg_game *g) {
+  if (!g) return PG_OK;
+  DevGuard guard(g->device);
+  (void)hipDeviceSynchronize();
+  free_game(g);
+  return PG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,141 @@
+// Internal definitions shared by the library's HIP translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/pg.h"
+
+namespace pgk {
+
+constexpr int kBlock = 256;            // threads per block for flat kernels
+constexpr int kWave = 64;              // CDNA wavefront width
+constexpr int kMaxVertices = (1 << 30) - 2;
+
+// Counters and flags kept in one small device array so that a single
+// device-to-host copy returns all of them.
+enum Counter : int {
+  C_ERR = 0,          // error bits (ERR_*)
+  C_WL_NG = 1,        // ng worklist length (unresolved after the walk)
+  C_WL_ROOT = 2,      // root worklist length
+  C_NFIN = 3,         // finite vertices excluding the sink
+  C_SWITCH = 4,       // switches made by the last switch kernel
+  C_WL_NG2 = 5,       // next-round ng worklist length
+  C_WL_ROOT2 = 6,     // next-round root worklist length
+  C_MISC = 7,         // scratch counter (preprocessing changes, X' size)
+  C_COUNT = 16
+};
+
+enum ErrBit : int {
+  ERR_INADMISSIBLE = 1,  // a cycle whose largest priority is odd
+  ERR_LISTWALK = 2,      // a list walk exceeded its bound (broken list)
+  ERR_INVAL = 4,         // input validation failed
+  ERR_DUPPRI = 8,        // repeated priority
+  ERR_RANKCOUNT = 16,    // list ranking did not emit every finite vertex
+};
+
+// Per-level arrays of the recursive sublist list ranking.
+struct RankLevel {
+  int64_t size = 0;      // elements of this level
+  int stride = 0;        // splitter stride (elements e with e % stride == 0)
+  int64_t nsplit = 0;    // splitters = elements of the next level
+  int32_t *sum = nullptr;   // per splitter: weight of its sublist
+  int32_t *next = nullptr;  // per splitter: index of the next splitter or -1
+  int32_t *base = nullptr;  // per splitter: exclusive rank of its sublist
+};
+
+}  // namespace pgk
+
+struct pg_game {
+  int device = 0;
+  int64_t n = 0, m = 0;          // original game
+  int64_t n_aug = 0, m_aug = 0;  // modified game (sink not counted)
+  int32_t n_oddpri = 0;          // vertices with an odd priority
+  int sort_bits = 0;             // bits of a parent id key (ids 0..n_aug+1)
+
+  // modified game, device resident
+  int64_t *off = nullptr;   // [n_aug+1]
+  int32_t *tgt = nullptr;   // [m_aug]
+  uint8_t *owner = nullptr; // [n_aug]
+  int32_t *pri = nullptr;   // [n_aug]
+  int32_t *perm = nullptr;  // [n_aug] vertices in signed-priority order
+
+  // play graph and valuation state
+  int2 *sp = nullptr;       // [n_aug+1] {successor (sink = n_aug), priority}
+  int32_t *key = nullptr;   // [n_aug+1]
+  int32_t *ng = nullptr;    // [n_aug+1] nearest greater successor-ancestor
+  int32_t *cand = nullptr;  // [n_aug]   walk candidates of unresolved vertices
+  int32_t *wl0 = nullptr;   // [n_aug]   worklists
+  int32_t *wl1 = nullptr;   // [n_aug]
+  uint8_t *rs = nullptr;    // [n_aug+1] 0 unknown, 1 finite, 2 top
+
+  // sorting
+  uint32_t *sk0 = nullptr, *sv0 = nullptr, *sk1 = nullptr, *sv1 = nullptr;
+  uint32_t *tile_cnt = nullptr;  // [256 * tiles]
+  int64_t tiles = 0;
+  void *scan_tmp = nullptr;      // device-wide scan partials
+  size_t scan_tmp_bytes = 0;
+
+  // Euler list of the nearest-greater-ancestor tree
+  int32_t *kids = nullptr;   // [n_aug]   vertices in (parent, signed-priority) order
+  int32_t *first = nullptr;  // [n_aug+1] sorted position of the first child, or -1
+  int32_t *pos = nullptr;    // [n_aug+1] sorted position of each finite vertex
+  uint8_t *haseven = nullptr;// [n_aug+1] 1 if the last child has even priority
+  int2 *elem = nullptr;      // [2*n_aug+2] {next element or -1, node | weight bit}
+
+  pgk::RankLevel lv[8];
+  int nlevels = 0;
+
+  int32_t *ctr = nullptr;    // [C_COUNT] device counters
+  int32_t *hctr = nullptr;   // pinned host mirror
+};
+
+// ---- error reporting (pg_api.hip) -----------------------------------------
+pg_status pg_fail(pg_status st, const std::string &msg);
+
+#define PG_HIP(call)                                                        \
+  do {                                                                      \
+    hipError_t e_ = (call);                                                 \
+    if (e_ != hipSuccess)                                                   \
+      return pg_fail(e_ == hipErrorOutOfMemory ? PG_ENOMEM : PG_EDEVICE,    \
+                     std::string(#call) + ": " + hipGetErrorString(e_));   \
+  } while (0)
+
+// ---- primitives (pg_prims.hip) --------------------------------------------
+namespace pgk {
+
+inline unsigned grid_for(int64_t n, int block = kBlock) {
+  int64_t g = (n + block - 1) / block;
+  return (unsigned)(g < 1 ? 1 : g);
+}
+
+void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+void fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s);
+
+// Exclusive prefix sum of int64 values (in and out may alias).  Returns the
+// number of temporary bytes needed when tmp == nullptr.
+size_t scan_excl_i64(const int64_t *in, int64_t *out, int64_t n, void *tmp,
+                     hipStream_t s);
+size_t scan_excl_u32(const uint32_t *in, uint32_t *out, int64_t n, void *tmp,
+                     hipStream_t s);
+
+// Stable LSD radix sort of (key, value) pairs on the low `bits` bits of the
+// key.  Ping-pongs between (k0, v0) and (k1, v1); returns 0 if the result is
+// in (k0, v0), 1 if in (k1, v1).  tile_cnt must hold 256 * radix_tiles(n).
+int64_t radix_tiles(int64_t n);
+int radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
+               int64_t n, int bits, uint32_t *tile_cnt, void *scan_tmp,
+               hipStream_t s);
+size_t radix_scan_tmp_bytes(int64_t n);
+
+}  // namespace pgk
+
+// ---- valuation and switching (pg_val.hip) ---------------------------------
+namespace pgk {
+// One valuation of the play graph held in g->sp; writes g->key.
+pg_status valuation_device(pg_game *g, hipStream_t s, int64_t *n_finite_out);
+// One All_Odd (odd = true) or All_Even step on g->sp from g->key.
+pg_status switch_device(pg_game *g, bool odd, hipStream_t s, int32_t *count);
+}  // namespace pgk

@@ -1,0 +1,257 @@
+// Data-parallel primitives: fills, device-wide exclusive scans and a stable
+// LSD radix sort.  Written for wave64: wave-level scans use lane shuffles and
+// the radix sort ranks digits inside a wave with ballots (a match of the
+// eight digit bits), so no LDS atomics decide an order.
+#include "pg_common.h"
+
+namespace pgk {
+
+// ---------------------------------------------------------------------------
+// fills (kernels rather than hipMemsetAsync, so the calls can live in a
+// captured graph)
+// ---------------------------------------------------------------------------
+__global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+
+__global__ void k_fill_u8(uint8_t *p, uint8_t v, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+
+static unsigned capped_grid(int64_t n) {
+  unsigned g = grid_for(n);
+  return g > 65536u ? 65536u : g;
+}
+
+void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_i32, dim3(capped_grid(n)), dim3(kBlock), 0, s, p,
+                     v, n);
+}
+
+void fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_u8, dim3(capped_grid(n)), dim3(kBlock), 0, s, p,
+                     v, n);
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scan: reduce tiles, scan the tile sums (recursively), then scan
+// each tile with its offset
+// ---------------------------------------------------------------------------
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kBlock * kScanItems;  // 2048
+
+template <typename T>
+__device__ T wave_incl_scan(T x) {
+  const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    T y = __shfl_up(x, off, kWave);
+    if (lane >= off) x += y;
+  }
+  return x;
+}
+
+// Exclusive scan of one value per thread across the block; returns the
+// thread's exclusive prefix and writes the block total to *total.
+template <typename T>
+__device__ T block_excl_scan(T x, T *total) {
+  __shared__ T wsum[kBlock / kWave];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+  T inc = wave_incl_scan(x);
+  if (lane == kWave - 1) wsum[w] = inc;
+  __syncthreads();
+  T before = 0, all = 0;
+#pragma unroll
+  for (int i = 0; i < kBlock / kWave; ++i) {
+    T s = wsum[i];
+    if (i < w) before += s;
+    all += s;
+  }
+  __syncthreads();
+  *total = all;
+  return before + inc - x;
+}
+
+template <typename T>
+__global__ void k_scan_reduce(const T *in, T *part, int64_t n) {
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  T acc = 0;
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    int64_t i = base + (int64_t)j * kBlock + threadIdx.x;
+    if (i < n) acc += in[i];
+  }
+  T tot;
+  block_excl_scan(acc, &tot);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+template <typename T>
+__global__ void k_scan_down(const T *in, T *out, const T *part, int64_t n) {
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  // blocked arrangement: thread t owns items [base + t*8, base + t*8 + 8)
+  T v[kScanItems];
+  T acc = 0;
+  const int64_t my = base + (int64_t)threadIdx.x * kScanItems;
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    int64_t i = my + j;
+    v[j] = (i < n) ? in[i] : (T)0;
+    acc += v[j];
+  }
+  T tot;
+  T run = block_excl_scan(acc, &tot) + (part ? part[blockIdx.x] : (T)0);
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    int64_t i = my + j;
+    if (i < n) out[i] = run;
+    run += v[j];
+  }
+}
+
+template <typename T>
+static size_t scan_tmp_need(int64_t n) {
+  size_t bytes = 0;
+  while (n > kScanTile) {
+    int64_t t = (n + kScanTile - 1) / kScanTile;
+    bytes += (size_t)t * sizeof(T);
+    n = t;
+  }
+  return bytes;
+}
+
+template <typename T>
+static void scan_rec(const T *in, T *out, int64_t n, T *tmp, hipStream_t s) {
+  if (n <= 0) return;
+  if (n <= kScanTile) {
+    hipLaunchKernelGGL(k_scan_down<T>, dim3(1), dim3(kBlock), 0, s, in, out,
+                       (const T *)nullptr, n);
+    return;
+  }
+  int64_t t = (n + kScanTile - 1) / kScanTile;
+  hipLaunchKernelGGL(k_scan_reduce<T>, dim3((unsigned)t), dim3(kBlock), 0, s,
+                     in, tmp, n);
+  scan_rec<T>(tmp, tmp, t, tmp + t, s);
+  hipLaunchKernelGGL(k_scan_down<T>, dim3((unsigned)t), dim3(kBlock), 0, s, in,
+                     out, (const T *)tmp, n);
+}
+
+size_t scan_excl_i64(const int64_t *in, int64_t *out, int64_t n, void *tmp,
+                     hipStream_t s) {
+  if (!tmp) return scan_tmp_need<int64_t>(n);
+  scan_rec<int64_t>(in, out, n, (int64_t *)tmp, s);
+  return 0;
+}
+
+size_t scan_excl_u32(const uint32_t *in, uint32_t *out, int64_t n, void *tmp,
+                     hipStream_t s) {
+  if (!tmp) return scan_tmp_need<uint32_t>(n);
+  scan_rec<uint32_t>(in, out, n, (uint32_t *)tmp, s);
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// stable LSD radix sort, 8-bit digits
+// ---------------------------------------------------------------------------
+constexpr int kRsItems = 16;
+constexpr int kRsTile = kBlock * kRsItems;  // 4096 keys per tile
+constexpr int kRsWaves = kBlock / kWave;    // 4
+
+int64_t radix_tiles(int64_t n) { return (n + kRsTile - 1) / kRsTile; }
+
+size_t radix_scan_tmp_bytes(int64_t n) {
+  return scan_tmp_need<uint32_t>(256 * radix_tiles(n));
+}
+
+__global__ __launch_bounds__(kBlock) void k_rs_upsweep(const uint32_t *keys,
+                                                       int64_t n, int shift,
+                                                       uint32_t *tile_cnt,
+                                                       int64_t tiles) {
+  __shared__ uint32_t hist[256];
+  hist[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kRsTile;
+#pragma unroll 4
+  for (int r = 0; r < kRsItems; ++r) {
+    int64_t i = base + (int64_t)r * kBlock + threadIdx.x;
+    if (i < n) atomicAdd(&hist[(keys[i] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  tile_cnt[(int64_t)threadIdx.x * tiles + blockIdx.x] = hist[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kBlock) void k_rs_downsweep(
+    const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout,
+    int64_t n, int shift, const uint32_t *tile_off, int64_t tiles) {
+  __shared__ uint32_t run[256];
+  __shared__ uint32_t wcnt[kRsWaves][256];
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int w = tid / kWave;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+  run[tid] = tile_off[(int64_t)tid * tiles + blockIdx.x];
+#pragma unroll
+  for (int j = 0; j < kRsWaves; ++j) wcnt[j][tid] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kRsTile;
+  for (int r = 0; r < kRsItems; ++r) {
+    const int64_t i = base + (int64_t)r * kBlock + tid;
+    const bool valid = i < n;
+    uint32_t k = valid ? kin[i] : 0u;
+    uint32_t v = valid ? vin[i] : 0u;
+    const uint32_t d = (k >> shift) & 255u;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t bb = __ballot(bit);
+      peers &= bit ? bb : ~bb;
+    }
+    const uint32_t before = (uint32_t)__popcll(peers & lt);
+    if (valid && before == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t p = run[d] + before;
+      for (int j = 0; j < w; ++j) p += wcnt[j][d];
+      kout[p] = k;
+      vout[p] = v;
+    }
+    __syncthreads();
+    uint32_t add = 0;
+#pragma unroll
+    for (int j = 0; j < kRsWaves; ++j) {
+      add += wcnt[j][tid];
+      wcnt[j][tid] = 0;
+    }
+    run[tid] += add;
+    __syncthreads();
+  }
+}
+
+int radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
+               int64_t n, int bits, uint32_t *tile_cnt, void *scan_tmp,
+               hipStream_t s) {
+  if (n <= 0 || bits <= 0) return 0;
+  const int64_t tiles = radix_tiles(n);
+  int cur = 0;
+  for (int shift = 0; shift < bits; shift += 8) {
+    uint32_t *ki = cur ? k1 : k0, *vi = cur ? v1 : v0;
+    uint32_t *ko = cur ? k0 : k1, *vo = cur ? v0 : v1;
+    hipLaunchKernelGGL(k_rs_upsweep, dim3((unsigned)tiles), dim3(kBlock), 0, s,
+                       ki, n, shift, tile_cnt, tiles);
+    scan_excl_u32(tile_cnt, tile_cnt, 256 * tiles, scan_tmp, s);
+    hipLaunchKernelGGL(k_rs_downsweep, dim3((unsigned)tiles), dim3(kBlock), 0,
+                       s, ki, vi, ko, vo, n, shift, tile_cnt, tiles);
+    cur ^= 1;
+  }
+  return cur;
+}
+
+}  // namespace pgk

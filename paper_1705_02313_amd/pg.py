@@ -1,0 +1,258 @@
+"""Python binding of the C ABI in include/pg.h (ctypes; argument marshalling
+only -- every step of the solver runs in the HIP library).
+
+Arrays may be numpy arrays (host memory) or torch tensors on the GPU (device
+memory, passed with PG_PTR_DEVICE on torch's current stream).  The library
+must have been built (``python -m paper_1705_02313_amd.build_lib``); without
+it every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpgsi.so")
+
+PG_OK, PG_EINVAL, PG_ENOMEM, PG_EDEVICE = 0, 1, 2, 3
+PG_EITERLIMIT, PG_EINADMISSIBLE, PG_EINTERNAL = 4, 5, 6
+PG_SINK = -1
+PG_KEY_TOP = 2**31 - 1
+PG_PTR_DEVICE, PG_NO_PREPROCESS, PG_OFFSETS_I32 = 1, 2, 4
+
+STATUS_NAMES = {0: "PG_OK", 1: "PG_EINVAL", 2: "PG_ENOMEM", 3: "PG_EDEVICE",
+                4: "PG_EITERLIMIT", 5: "PG_EINADMISSIBLE", 6: "PG_EINTERNAL"}
+
+EXPORTS = ["pg_load_csr", "pg_game_info", "pg_export_game",
+           "pg_initial_strategies", "pg_valuation", "pg_best_response",
+           "pg_solve", "pg_free", "pg_last_error"]
+
+
+class PgError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+        self.message = message
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("max_major", ctypes.c_int32), ("max_inner", ctypes.c_int32),
+                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64),
+                ("n_aug", ctypes.c_int64), ("m_aug", ctypes.c_int64),
+                ("n_major", ctypes.c_int64), ("n_valuations", ctypes.c_int64),
+                ("n_odd_switches", ctypes.c_int64),
+                ("n_even_switches", ctypes.c_int64),
+                ("seconds", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing: build it with "
+                "`python -m paper_1705_02313_amd.build_lib`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I64, I32, U32 = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                            ctypes.c_uint32)
+        L.pg_load_csr.argtypes = [I64, I64, P, P, P, P, U32, P,
+                                  ctypes.POINTER(P)]
+        L.pg_game_info.argtypes = [P] + [ctypes.POINTER(I64)] * 4
+        L.pg_export_game.argtypes = [P, P, P, P, P, U32, P]
+        L.pg_initial_strategies.argtypes = [P, P, P, U32, P]
+        L.pg_valuation.argtypes = [P, P, P, P, ctypes.POINTER(I64), U32, P]
+        L.pg_best_response.argtypes = [P, P, P, P, ctypes.POINTER(I32), I32,
+                                       U32, P]
+        L.pg_solve.argtypes = [P, ctypes.POINTER(SolveOpts), P, P, P,
+                               ctypes.POINTER(Stats), P]
+        L.pg_free.argtypes = [P]
+        L.pg_last_error.argtypes = []
+        L.pg_last_error.restype = ctypes.c_char_p
+        for name in EXPORTS[:-1]:
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != PG_OK:
+        raise PgError(status, lib().pg_last_error().decode())
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if _is_torch(x):
+        return ctypes.c_void_p(x.data_ptr())
+    return x.ctypes.data_as(ctypes.c_void_p)
+
+
+def _stream(device: bool):
+    if not device:
+        return None
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Game:
+    """A game loaded on the device (modified by preprocessing unless
+    ``preprocess=False``)."""
+
+    def __init__(self, offsets, targets, owner, priority, n: int = None,
+                 preprocess: bool = True):
+        device = _is_torch(targets)
+        if device:
+            import torch
+            offsets = offsets.contiguous()
+            targets = targets.to(torch.int32).contiguous()
+            owner = owner.to(torch.uint8).contiguous()
+            priority = priority.to(torch.int32).contiguous()
+            off_i32 = offsets.dtype == torch.int32
+            if not off_i32:
+                offsets = offsets.to(torch.int64)
+            m = int(targets.numel())
+        else:
+            offsets = np.ascontiguousarray(offsets)
+            off_i32 = offsets.dtype == np.int32
+            if not off_i32:
+                offsets = offsets.astype(np.int64, copy=False)
+            targets = np.ascontiguousarray(targets, dtype=np.int32)
+            owner = np.ascontiguousarray(owner, dtype=np.uint8)
+            priority = np.ascontiguousarray(priority, dtype=np.int32)
+            m = int(targets.size)
+        if n is None:
+            n = int(offsets.numel() if device else offsets.size) - 1
+        flags = (PG_PTR_DEVICE if device else 0) | \
+            (0 if preprocess else PG_NO_PREPROCESS) | \
+            (PG_OFFSETS_I32 if off_i32 else 0)
+        h = ctypes.c_void_p()
+        _check(lib().pg_load_csr(n, m, _ptr(offsets), _ptr(targets),
+                                 _ptr(owner), _ptr(priority), flags,
+                                 _stream(device), ctypes.byref(h)))
+        self._h = h
+        self.device = device
+        vals = [ctypes.c_int64() for _ in range(4)]
+        _check(lib().pg_game_info(self._h, *[ctypes.byref(v) for v in vals]))
+        self.n, self.m, self.n_aug, self.m_aug = [int(v.value) for v in vals]
+
+    @classmethod
+    def from_dict(cls, g: dict, device: bool = False, preprocess: bool = True):
+        if device:
+            import torch
+            t = {k: torch.from_numpy(np.ascontiguousarray(g[k])).cuda()
+                 for k in ("offsets", "targets", "owner", "pri")}
+            return cls(t["offsets"], t["targets"], t["owner"], t["pri"],
+                       n=int(g["n"]), preprocess=preprocess)
+        return cls(g["offsets"], g["targets"], g["owner"], g["pri"],
+                   n=int(g["n"]), preprocess=preprocess)
+
+    # -- helpers -------------------------------------------------------------
+    def _out(self, count: int, dtype):
+        if self.device:
+            import torch
+            tdt = {np.int32: torch.int32, np.int64: torch.int64,
+                   np.uint8: torch.uint8}[dtype]
+            return torch.empty(count, dtype=tdt, device="cuda")
+        return np.empty(count, dtype=dtype)
+
+    def _in(self, x, dtype=np.int32):
+        if self.device:
+            import torch
+            if not _is_torch(x):
+                x = torch.from_numpy(np.ascontiguousarray(x, dtype=dtype))
+            return x.to(device="cuda", dtype=torch.int32).contiguous()
+        if _is_torch(x):
+            x = x.cpu().numpy()
+        return np.ascontiguousarray(x, dtype=dtype)
+
+    @property
+    def _flags(self) -> int:
+        return PG_PTR_DEVICE if self.device else 0
+
+    # -- calls ---------------------------------------------------------------
+    def export(self) -> dict:
+        off = np.empty(self.n_aug + 1, np.int64)
+        tgt = np.empty(self.m_aug, np.int32)
+        own = np.empty(self.n_aug, np.uint8)
+        pri = np.empty(self.n_aug, np.int32)
+        _check(lib().pg_export_game(self._h, _ptr(off), _ptr(tgt), _ptr(own),
+                                    _ptr(pri), 0, _stream(self.device)))
+        return {"n": self.n_aug, "m": self.m_aug, "offsets": off,
+                "targets": tgt, "owner": own, "pri": pri}
+
+    def initial_strategies(self):
+        sigma = self._out(self.n_aug, np.int32)
+        tau = self._out(self.n_aug, np.int32)
+        _check(lib().pg_initial_strategies(self._h, _ptr(sigma), _ptr(tau),
+                                           self._flags,
+                                           _stream(self.device)))
+        return sigma, tau
+
+    def valuation(self, sigma, tau):
+        """Returns (key[n_aug+1], n_finite)."""
+        sigma = self._in(sigma)
+        tau = self._in(tau)
+        key = self._out(self.n_aug + 1, np.int32)
+        nf = ctypes.c_int64()
+        _check(lib().pg_valuation(self._h, _ptr(sigma), _ptr(tau), _ptr(key),
+                                  ctypes.byref(nf), self._flags,
+                                  _stream(self.device)))
+        return key, int(nf.value)
+
+    def best_response(self, sigma, tau, max_inner: int = 0):
+        """Returns (tau, key, n_valuations)."""
+        sigma = self._in(sigma)
+        tau = self._in(tau)
+        tau = tau.clone() if self.device else tau.copy()
+        key = self._out(self.n_aug + 1, np.int32)
+        nv = ctypes.c_int32()
+        _check(lib().pg_best_response(self._h, _ptr(sigma), _ptr(tau),
+                                      _ptr(key), ctypes.byref(nv), max_inner,
+                                      self._flags, _stream(self.device)))
+        return tau, key, int(nv.value)
+
+    def solve(self, max_major: int = 0, max_inner: int = 0) -> dict:
+        opts = SolveOpts(max_major, max_inner, self._flags, 0)
+        winner = self._out(self.n, np.uint8)
+        sigma = self._out(self.n_aug, np.int32)
+        tau = self._out(self.n_aug, np.int32)
+        st = Stats()
+        _check(lib().pg_solve(self._h, ctypes.byref(opts), _ptr(winner),
+                              _ptr(sigma), _ptr(tau), ctypes.byref(st),
+                              _stream(self.device)))
+        return {"winner": winner, "sigma": sigma, "tau": tau,
+                "stats": st.as_dict()}
+
+    def free(self):
+        if getattr(self, "_h", None):
+            lib().pg_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.free()

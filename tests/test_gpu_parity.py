@@ -1,0 +1,148 @@
+"""Device path vs the CPU oracle, element by element (bit-exact: all outputs
+are integers).  Every call goes through the C ABI of the HIP library."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import orc
+from paper_1705_02313_amd import synth
+from paper_1705_02313_amd.pg import Game
+from tests.helpers import oracle_trajectory, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _tiny_games():
+    out = []
+    for n in range(3, 13):
+        for seed in range(6):
+            out.append(("rnd", n, seed, synth.random_game(n, 2, 5, 100 * n + seed)))
+    for n in (3, 5, 9, 12):
+        out.append(("chain", n, 0, synth.chain_game(n, 7 + n)))
+    return out
+
+
+def _compare_aug(dev: Game, aug: dict):
+    ex = dev.export()
+    assert ex["n"] == aug["n"] and ex["m"] == aug["m"]
+    np.testing.assert_array_equal(ex["offsets"], aug["offsets"])
+    np.testing.assert_array_equal(ex["targets"], aug["targets"])
+    np.testing.assert_array_equal(ex["owner"], aug["owner"])
+    np.testing.assert_array_equal(ex["pri"], aug["pri"])
+
+
+def test_preprocess_matches_oracle(pglib):
+    cases = [("c0", 1000, s, synth.random_game(1000, 2, 5, s)) for s in range(4)]
+    cases += [("chain", 3000, 1, synth.chain_game(3000, 11))]
+    cases += _tiny_games()[::7]
+    for name, n, seed, g in cases:
+        _say("preprocess", name, n, seed)
+        with Game.from_dict(g) as dev:
+            _compare_aug(dev, orc.preprocess(g))
+
+
+def test_valuations_along_trajectory(pglib):
+    """Every valuation of the oracle's Algorithm 1 run, recomputed on the
+    device from the same (sigma, tau)."""
+    for n, seed, kind in [(1000, 0, "rnd"), (1000, 1, "rnd"), (2000, 2, "chain"),
+                          (20000, 3, "rnd")]:
+        g = synth.random_game(n, 2, 5, seed) if kind == "rnd" else \
+            synth.chain_game(n, seed)
+        aug = orc.preprocess(g)
+        _say("trajectory", kind, n, seed)
+        with Game.from_dict(g) as dev:
+            for k, (sigma, tau, key) in enumerate(oracle_trajectory(aug)):
+                dkey, nf = dev.valuation(sigma, tau)
+                np.testing.assert_array_equal(to_np(dkey), key,
+                                              err_msg=f"valuation {k}")
+                assert nf == int((key != orc.KEY_TOP).sum())
+
+
+def test_best_response_matches_oracle(pglib):
+    g = synth.random_game(3000, 2, 5, 5)
+    aug = orc.preprocess(g)
+    sigma, tau = orc.initial_strategies(aug)
+    with Game.from_dict(g) as dev:
+        for major in range(4):
+            # oracle inner loop
+            t = tau.copy()
+            nval = 0
+            by_pri = orc.order_by_pri(aug["pri"])
+            while True:
+                succ = np.where(aug["owner"] == 1, t, sigma).astype(np.int32)
+                key, _, rc = orc.valuation(succ, aug["pri"], by_pri=by_pri)
+                nval += 1
+                t, c = orc.odd_switch(aug, key, t)
+                if c == 0:
+                    break
+            dtau, dkey, dn = dev.best_response(sigma, tau)
+            np.testing.assert_array_equal(to_np(dtau), t)
+            np.testing.assert_array_equal(to_np(dkey), key)
+            assert dn == nval
+            tau = t
+            sigma, c = orc.even_switch(aug, key, sigma)
+            if c == 0:
+                break
+
+
+def _solve_both(g, **kw):
+    ref = orc.solve(g)
+    assert ref["status"] == 0
+    with Game.from_dict(g, **kw) as dev:
+        out = dev.solve()
+    return ref, out
+
+
+def _assert_solve_equal(ref, out):
+    np.testing.assert_array_equal(to_np(out["winner"]), ref["winner"])
+    np.testing.assert_array_equal(to_np(out["sigma"]), ref["sigma"])
+    np.testing.assert_array_equal(to_np(out["tau"]), ref["tau"])
+    assert out["stats"]["n_major"] == ref["n_major"]
+    assert out["stats"]["n_valuations"] == ref["n_valuations"]
+
+
+def test_solve_tiny_games(pglib):
+    for name, n, seed, g in _tiny_games():
+        _say("solve tiny", name, n, seed)
+        ref, out = _solve_both(g)
+        _assert_solve_equal(ref, out)
+
+
+def test_solve_config0_seeds(pglib):
+    for seed in range(12):
+        g = synth.random_game(1000, 2, 5, seed)
+        _say("solve c0 seed", seed)
+        ref, out = _solve_both(g)
+        _assert_solve_equal(ref, out)
+
+
+def test_solve_midsize_ragged(pglib):
+    """Sizes spanning many tiles with ragged tails."""
+    for n, kind in [(4099, "rnd"), (50_001, "rnd"), (30_007, "chain")]:
+        g = synth.random_game(n, 2, 10, n) if kind == "rnd" else \
+            synth.chain_game(n, n)
+        _say("solve midsize", kind, n)
+        ref, out = _solve_both(g)
+        _assert_solve_equal(ref, out)
+
+
+def test_device_pointers_same_as_host(pglib):
+    import torch
+    g = synth.random_game(5000, 2, 8, 77)
+    with Game.from_dict(g) as h:
+        a = h.solve()
+    with Game.from_dict(g, device=True) as d:
+        b = d.solve()
+        assert isinstance(b["winner"], torch.Tensor) and b["winner"].is_cuda
+    np.testing.assert_array_equal(to_np(a["winner"]), to_np(b["winner"]))
+    np.testing.assert_array_equal(to_np(a["sigma"]), to_np(b["sigma"]))
+    np.testing.assert_array_equal(to_np(a["tau"]), to_np(b["tau"]))
+    assert a["stats"]["n_valuations"] == b["stats"]["n_valuations"]
