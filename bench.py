@@ -1,0 +1,235 @@
+"""Benchmark: greedy all-switches strategy improvement on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
+
+A step is one whole job on the workload's game, whose arrays already sit in
+HBM when the timed region starts: pg_load_csr (validation, the admissibility
+preprocessing, the signed-priority order) + pg_solve (every best-response
+iteration and every Even switch until no switch) + pg_free.  The headline
+value is edges per second per best-response iteration,
+    m * n_valuations / (seconds per step),
+m being the original game's edge count.
+
+Workloads (seeded, synthetic; see paper_1705_02313_amd/synth.py):
+  c2  random game, n = 10,000,000, out-degree U[2,5], int64 offsets (default)
+  c1  random game, n = 1,000,000, out-degree U[2,10]
+  c3  long-chain game, n = 8,000,000
+  c0  random game, n = 1,000, out-degree U[2,5]
+
+Printed: one JSON line with the driver's fields plus "roofline" (the kernel
+that takes the most time, its algorithmic bytes over its event-timed
+duration against 8 TB/s) and "cpu_baseline" (the CPU oracle timed on this
+host on a bounded sample of the same workload).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "c0": ("random parity game n=1000 deg U[2,5]", 0),
+    "c1": ("random parity game n=1000000 deg U[2,10]", 1),
+    "c2": ("random parity game n=10000000 deg U[2,5] int64 offsets", 2),
+    "c3": ("long-chain parity game n=8000000", 3),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(game: dict, iters: int = 3) -> dict:
+    """The CPU oracle on this host: its preprocessing, then the first `iters`
+    best-response iterations (valuation + All_Odd) of Algorithm 1."""
+    from oracle import orc
+    t0 = time.perf_counter()
+    aug = orc.preprocess(game)
+    t_pre = time.perf_counter() - t0
+    sigma, tau = orc.initial_strategies(aug)
+    by_pri = orc.order_by_pri(aug["pri"])
+    times = []
+    for _ in range(iters):
+        t1 = time.perf_counter()
+        succ = np.where(aug["owner"] == 1, tau, sigma).astype(np.int32)
+        key, _, rc = orc.valuation(succ, aug["pri"], by_pri=by_pri)
+        tau, c = orc.odd_switch(aug, key, tau)
+        times.append(time.perf_counter() - t1)
+        if c == 0:
+            break
+    t_iter = statistics.median(times)
+    return {"value": game["m"] / t_iter, "unit": "edges/s per best-response "
+            "iteration", "cores": 1, "kind": "oracle",
+            "sample": f"oracle preprocessing ({t_pre:.2f} s, not in value) "
+                      f"then {len(times)} best-response iterations "
+                      "(valuation + All_Odd) from the initial strategies, "
+                      f"median {t_iter:.3f} s each, single thread",
+            "host_cpu": _host_cpu()}
+
+
+def _host_cpu() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true",
+                    help="skip the per-kernel event profiler")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not "
+              "supported (the solver keeps a whole game on one device)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1705_02313_amd import synth
+    from paper_1705_02313_amd.pg import Game
+
+    desc, cfg = WORKLOADS[args.workload]
+    log(f"generating {args.workload}: {desc}")
+    t0 = time.perf_counter()
+    game = synth.config_game(cfg)
+    log(f"generated n={game['n']} m={game['m']} in "
+        f"{time.perf_counter() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    arrs = {k: torch.from_numpy(np.ascontiguousarray(game[k])).to(dev)
+            for k in ("offsets", "targets", "owner", "pri")}
+    torch.cuda.synchronize()
+
+    def step(profile: bool):
+        t_a = time.perf_counter()
+        g = Game(arrs["offsets"], arrs["targets"], arrs["owner"], arrs["pri"],
+                 n=game["n"])
+        torch.cuda.synchronize()
+        t_b = time.perf_counter()
+        if profile:
+            g.profile(True)
+        out = g.solve()
+        torch.cuda.synchronize()
+        t_c = time.perf_counter()
+        prof = g.profile_read() if profile else {}
+        info = (g.n_aug, g.m_aug)
+        g.free()
+        torch.cuda.synchronize()
+        t_d = time.perf_counter()
+        return {"load": t_b - t_a, "solve": t_c - t_b, "free": t_d - t_c,
+                "total": t_d - t_a, "stats": out["stats"], "prof": prof,
+                "aug": info, "winner": out["winner"]}
+
+    for i in range(args.warmup):
+        r = step(False)
+        log(f"warmup {i}: {r['total'] * 1e3:.1f} ms "
+            f"(solve {r['solve'] * 1e3:.1f} ms)")
+
+    torch.cuda.synchronize()
+    runs = []
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t_start = time.perf_counter()
+    ev0.record()
+    for i in range(args.steps):
+        r = step(not args.no_profile)
+        runs.append(r)
+        log(f"step {i}: {r['total'] * 1e3:.1f} ms (load {r['load'] * 1e3:.1f}, "
+            f"solve {r['solve'] * 1e3:.1f}, valuations "
+            f"{r['stats']['n_valuations']})")
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    ms_per_step = wall * 1e3 / args.steps
+
+    nval = runs[0]["stats"]["n_valuations"]
+    assert all(r["stats"]["n_valuations"] == nval for r in runs)
+    win = runs[0]["winner"].cpu().numpy()
+    m = game["m"]
+    value = m * nval / (ms_per_step / 1e3)
+    solve_s = [r["solve"] for r in runs]
+    load_s = [r["load"] for r in runs]
+
+    # roofline of the dominant kernel (summed over the timed steps)
+    roof = None
+    kernels = {}
+    if not args.no_profile:
+        agg = {}
+        for r in runs:
+            for k, d in r["prof"].items():
+                a = agg.setdefault(k, {"ms": 0.0, "calls": 0, "bytes": 0.0})
+                a["ms"] += d["ms"]
+                a["calls"] += d["calls"]
+                a["bytes"] += d["bytes"]
+        for k, a in agg.items():
+            kernels[k] = {"ms_total": round(a["ms"], 3), "calls": a["calls"],
+                          "avg_us": round(1e3 * a["ms"] / a["calls"], 2),
+                          "alg_GBps": round(a["bytes"] / (a["ms"] / 1e3) / 1e9,
+                                            1) if a["ms"] > 0 else None}
+        dom = max(agg, key=lambda k: agg[k]["ms"])
+        a = agg[dom]
+        achieved = a["bytes"] / (a["ms"] / 1e3) / 1e9
+        roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "avg_launch_us": round(1e3 * a["ms"] / a["calls"], 2),
+                "bytes_per_launch": round(a["bytes"] / a["calls"]),
+                "traffic": None}
+
+    line = {
+        "metric": "edges/s per best-response iteration",
+        "value": value,
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": desc, "n": game["n"], "m": m,
+                   "n_aug": runs[0]["aug"][0], "m_aug": runs[0]["aug"][1],
+                   "step": "pg_load_csr + pg_solve + pg_free, inputs resident "
+                           "in HBM"},
+        "solve_seconds_median": statistics.median(solve_s),
+        "load_seconds_median": statistics.median(load_s),
+        "n_major": runs[0]["stats"]["n_major"],
+        "n_valuations": nval,
+        "ms_per_iteration": 1e3 * statistics.median(solve_s) / nval,
+        "w_even": int((win == 0).sum()),
+        "event_ms_total": ev0.elapsed_time(ev1),
+        "roofline": roof,
+        "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a sample of the same workload")
+        line["cpu_baseline"] = cpu_baseline(game)
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -198,6 +198,23 @@ pg_status pg_solve(pg_game *game, const pg_solve_opts *opts, uint8_t *winner,
                    int32_t *sigma, int32_t *tau, pg_stats *stats,
                    void *hip_stream);
 
+/*
+ * Kernel profiling.  When enabled, every kernel the library launches for this
+ * game is bracketed by two HIP events on the call's stream, and after each
+ * synchronisation the elapsed times are added up per kernel kind together
+ * with the kernel's algorithmic bytes (the bytes the step must move, as
+ * computed from its sizes; not measured traffic).
+ *
+ * pg_profile_enable: on != 0 enables and clears the counters; 0 disables.
+ * pg_profile_kinds:  number of kernel kinds.
+ * pg_profile_read:   totals for one kind: name (static string), summed
+ *                    milliseconds, launches, summed algorithmic bytes.
+ */
+pg_status pg_profile_enable(pg_game *game, int32_t on);
+int32_t pg_profile_kinds(void);
+pg_status pg_profile_read(const pg_game *game, int32_t kind, const char **name,
+                          double *ms, int64_t *calls, double *bytes);
+
 /* Release the game's device memory.  NULL is accepted. */
 pg_status pg_free(pg_game *game);
 

@@ -175,14 +175,11 @@ __global__ void k_sp_import(const uint8_t *owner, const int32_t *sigma,
                             int32_t *ctr) {
   int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= N) return;
-  int32_t s;
-  if (owner[v] == 0) {
-    s = sigma[v];
-    if (s == PG_SINK) s = N;
-  } else {
-    s = tau[v];
-  }
-  if (s < 0 || s > N || (s == N && owner[v] != 0)) {
+  const bool even = owner[v] == 0;
+  int32_t s = even ? sigma[v] : tau[v];
+  if (even && s == PG_SINK) {
+    s = N;
+  } else if (s < 0 || s >= N) {
     atomicOr(&ctr[C_ERR], ERR_INVAL);
     s = N;
   }
@@ -206,6 +203,25 @@ __global__ void k_initial(const int64_t *off, const int32_t *tgt,
   if (v >= N) return;
   if (sigma) sigma[v] = PG_SINK;
   if (tau) tau[v] = owner[v] ? tgt[off[v]] : PG_SINK;
+}
+
+// Odd vertices and the edges of their rows (for the switch kernels' bytes)
+__global__ void k_count_odd(const int64_t *off, const uint8_t *owner,
+                            int64_t n, unsigned long long *out) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long e = 0, c = 0;
+  if (v < n && owner[v] == 1) {
+    e = (unsigned long long)(off[v + 1] - off[v]);
+    c = 1;
+  }
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    e += __shfl_down(e, o, kWave);
+    c += __shfl_down(c, o, kWave);
+  }
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    if (c) atomicAdd(&out[0], c);
+    if (e) atomicAdd(&out[1], e);
+  }
 }
 
 // Theorem 1: W_Even is the set of vertices whose final valuation is top
@@ -280,6 +296,7 @@ pg_status sync_ctr(pg_game *g, hipStream_t s) {
   PG_HIP(hipMemcpyAsync(g->hctr, g->ctr, sizeof(int32_t) * C_COUNT,
                         hipMemcpyDeviceToHost, s));
   PG_HIP(hipStreamSynchronize(s));
+  if (g->prof.on) g->prof.flush();
   return PG_OK;
 }
 
@@ -298,6 +315,7 @@ void free_game(pg_game *g) {
     if (g->lv[k].base) (void)hipFree(g->lv[k].base);
   }
   if (g->hctr) (void)hipHostFree(g->hctr);
+  g->prof.release();
   delete g;
 }
 
@@ -493,6 +511,19 @@ pg_status load_impl(int64_t n, int64_t m, const void *offsets,
   PG_TRY(sync_ctr(g, s));
   PG_TRY(check_err(g, "a priority exceeds INT32_MAX after preprocessing"));
   g->n_oddpri = g->hctr[C_MISC];
+  {
+    unsigned long long *cnt = nullptr;
+    PG_TRY(dev_alloc(&cnt, 2));
+    tmp.p.push_back(cnt);
+    fill_i32((int32_t *)cnt, 0, 4, s);
+    hipLaunchKernelGGL(k_count_odd, dim3(grid_for(N)), dim3(kBlock), 0, s,
+                       g->off, g->owner, N, cnt);
+    unsigned long long h[2] = {0, 0};
+    PG_HIP(hipMemcpyAsync(h, cnt, sizeof(h), hipMemcpyDeviceToHost, s));
+    PG_HIP(hipStreamSynchronize(s));
+    g->n_odd = (int64_t)h[0];
+    g->m_odd = (int64_t)h[1];
+  }
   return PG_OK;
 }
 
@@ -726,6 +757,26 @@ pg_status pg_solve(pg_game *g, const pg_solve_opts *opts, uint8_t *winner,
   PG_TRY(export_strats(g, sigma, tau, dev, s));
   const auto t1 = std::chrono::steady_clock::now();
   if (stats) stats->seconds = std::chrono::duration<double>(t1 - t0).count();
+  return PG_OK;
+}
+
+pg_status pg_profile_enable(pg_game *g, int32_t on) {
+  if (!g) return pg_fail(PG_EINVAL, "game is NULL");
+  g->prof.on = on != 0;
+  g->prof.reset();
+  return PG_OK;
+}
+
+int32_t pg_profile_kinds(void) { return (int32_t)K_COUNT; }
+
+pg_status pg_profile_read(const pg_game *g, int32_t kind, const char **name,
+                          double *ms, int64_t *calls, double *bytes) {
+  if (!g) return pg_fail(PG_EINVAL, "game is NULL");
+  if (kind < 0 || kind >= K_COUNT) return pg_fail(PG_EINVAL, "bad kind");
+  if (name) *name = kKernelNames[kind];
+  if (ms) *ms = g->prof.ms[kind];
+  if (calls) *calls = g->prof.calls[kind];
+  if (bytes) *bytes = g->prof.bytes[kind];
   return PG_OK;
 }
 

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/pg.h"
 
@@ -36,6 +37,62 @@ enum ErrBit : int {
   ERR_RANKCOUNT = 16,    // list ranking did not emit every finite vertex
 };
 
+// Kernel kinds for the optional event profiler (pg_profile_* in pg.h).
+enum KId : int {
+  K_FILL = 0, K_NG_WALK, K_NG_ROUND, K_ROOT_WALK, K_ROOT_ROUND, K_SORT_KEYS,
+  K_RS_UPSWEEP, K_RS_SCAN, K_RS_DOWNSWEEP, K_LINK_INFO, K_LINK_BUILD,
+  K_LR_SUM1, K_LR_SUMK, K_LR_TOP, K_LR_DISTK, K_LR_EMIT1, K_ODD_SWITCH,
+  K_EVEN_SWITCH, K_PREP, K_OTHER, K_COUNT
+};
+extern const char *const kKernelNames[K_COUNT];
+
+// Records a pair of HIP events around each profiled launch on the launch's
+// stream; elapsed times are collected after the stream has been synchronised.
+struct Prof {
+  bool on = false;
+  double ms[K_COUNT] = {};
+  int64_t calls[K_COUNT] = {};
+  double bytes[K_COUNT] = {};
+  struct Pend {
+    int kid;
+    double bytes;
+    hipEvent_t a, b;
+  };
+  std::vector<hipEvent_t> pool;
+  std::vector<Pend> pend;
+  hipEvent_t get();
+  void flush();     // call only after the stream has been synchronised
+  void reset();
+  void release();
+};
+
+struct ProfScope {
+  Prof *p;
+  hipStream_t s;
+  Prof::Pend e{};
+  ProfScope(Prof *prof, int kid, double bytes, hipStream_t st)
+      : p(prof && prof->on ? prof : nullptr), s(st) {
+    if (!p) return;
+    e.kid = kid;
+    e.bytes = bytes;
+    e.a = p->get();
+    e.b = p->get();
+    (void)hipEventRecord(e.a, s);
+  }
+  ~ProfScope() {
+    if (!p) return;
+    (void)hipEventRecord(e.b, s);
+    p->pend.push_back(e);
+  }
+};
+
+// Launch with profiling: `bytes` are the kernel's algorithmic bytes.
+#define PG_LAUNCH(prof, kid, bytes, kern, grid, block, smem, stream, ...) \
+  do {                                                                    \
+    ::pgk::ProfScope ps_((prof), (kid), (double)(bytes), (stream));       \
+    hipLaunchKernelGGL(kern, grid, block, smem, stream, __VA_ARGS__);     \
+  } while (0)
+
 // Per-level arrays of the recursive sublist list ranking.
 struct RankLevel {
   int64_t size = 0;      // elements of this level
@@ -53,6 +110,7 @@ struct pg_game {
   int64_t n = 0, m = 0;          // original game
   int64_t n_aug = 0, m_aug = 0;  // modified game (sink not counted)
   int32_t n_oddpri = 0;          // vertices with an odd priority
+  int64_t n_odd = 0, m_odd = 0;  // Odd vertices and the edges of their rows
   int sort_bits = 0;             // bits of a parent id key (ids 0..n_aug+1)
 
   // modified game, device resident
@@ -90,6 +148,8 @@ struct pg_game {
 
   int32_t *ctr = nullptr;    // [C_COUNT] device counters
   int32_t *hctr = nullptr;   // pinned host mirror
+
+  pgk::Prof prof;
 };
 
 // ---- error reporting (pg_api.hip) -----------------------------------------
@@ -111,15 +171,17 @@ inline unsigned grid_for(int64_t n, int block = kBlock) {
   return (unsigned)(g < 1 ? 1 : g);
 }
 
-void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
-void fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s);
+void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s,
+              Prof *prof = nullptr);
+void fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s,
+             Prof *prof = nullptr);
 
 // Exclusive prefix sum of int64 values (in and out may alias).  Returns the
 // number of temporary bytes needed when tmp == nullptr.
 size_t scan_excl_i64(const int64_t *in, int64_t *out, int64_t n, void *tmp,
                      hipStream_t s);
 size_t scan_excl_u32(const uint32_t *in, uint32_t *out, int64_t n, void *tmp,
-                     hipStream_t s);
+                     hipStream_t s, Prof *prof = nullptr);
 
 // Stable LSD radix sort of (key, value) pairs on the low `bits` bits of the
 // key.  Ping-pongs between (k0, v0) and (k1, v1); returns 0 if the result is
@@ -127,7 +189,7 @@ size_t scan_excl_u32(const uint32_t *in, uint32_t *out, int64_t n, void *tmp,
 int64_t radix_tiles(int64_t n);
 int radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
                int64_t n, int bits, uint32_t *tile_cnt, void *scan_tmp,
-               hipStream_t s);
+               hipStream_t s, Prof *prof = nullptr);
 size_t radix_scan_tmp_bytes(int64_t n);
 
 }  // namespace pgk

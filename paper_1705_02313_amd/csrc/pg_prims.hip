@@ -6,6 +6,56 @@
 
 namespace pgk {
 
+const char *const kKernelNames[K_COUNT] = {
+    "fill",        "ng_walk",     "ng_round",      "root_walk",
+    "root_round",  "sort_keys",   "radix_upsweep", "radix_scan",
+    "radix_downsweep", "link_info", "link_build",  "lr_sum1",
+    "lr_sumk",     "lr_top",      "lr_distk",      "lr_emit1",
+    "odd_switch",  "even_switch", "preprocess",    "other"};
+
+hipEvent_t Prof::get() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+void Prof::flush() {
+  for (Pend &p : pend) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, p.a, p.b) == hipSuccess) {
+      ms[p.kid] += t;
+      calls[p.kid] += 1;
+      bytes[p.kid] += p.bytes;
+    }
+    pool.push_back(p.a);
+    pool.push_back(p.b);
+  }
+  pend.clear();
+}
+
+void Prof::reset() {
+  for (int k = 0; k < K_COUNT; ++k) {
+    ms[k] = 0.0;
+    calls[k] = 0;
+    bytes[k] = 0.0;
+  }
+}
+
+void Prof::release() {
+  for (Pend &p : pend) {
+    pool.push_back(p.a);
+    pool.push_back(p.b);
+  }
+  pend.clear();
+  for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  pool.clear();
+}
+
 // ---------------------------------------------------------------------------
 // fills (kernels rather than hipMemsetAsync, so the calls can live in a
 // captured graph)
@@ -27,16 +77,16 @@ static unsigned capped_grid(int64_t n) {
   return g > 65536u ? 65536u : g;
 }
 
-void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s) {
+void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s, Prof *prof) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_fill_i32, dim3(capped_grid(n)), dim3(kBlock), 0, s, p,
-                     v, n);
+  PG_LAUNCH(prof, K_FILL, 4.0 * n, k_fill_i32, dim3(capped_grid(n)),
+            dim3(kBlock), 0, s, p, v, n);
 }
 
-void fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s) {
+void fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s, Prof *prof) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_fill_u8, dim3(capped_grid(n)), dim3(kBlock), 0, s, p,
-                     v, n);
+  PG_LAUNCH(prof, K_FILL, 1.0 * n, k_fill_u8, dim3(capped_grid(n)),
+            dim3(kBlock), 0, s, p, v, n);
 }
 
 // ---------------------------------------------------------------------------
@@ -128,32 +178,33 @@ static size_t scan_tmp_need(int64_t n) {
 }
 
 template <typename T>
-static void scan_rec(const T *in, T *out, int64_t n, T *tmp, hipStream_t s) {
+static void scan_rec(const T *in, T *out, int64_t n, T *tmp, hipStream_t s,
+                     Prof *prof) {
   if (n <= 0) return;
   if (n <= kScanTile) {
-    hipLaunchKernelGGL(k_scan_down<T>, dim3(1), dim3(kBlock), 0, s, in, out,
-                       (const T *)nullptr, n);
+    PG_LAUNCH(prof, K_RS_SCAN, 2.0 * sizeof(T) * n, k_scan_down<T>, dim3(1),
+              dim3(kBlock), 0, s, in, out, (const T *)nullptr, n);
     return;
   }
   int64_t t = (n + kScanTile - 1) / kScanTile;
-  hipLaunchKernelGGL(k_scan_reduce<T>, dim3((unsigned)t), dim3(kBlock), 0, s,
-                     in, tmp, n);
-  scan_rec<T>(tmp, tmp, t, tmp + t, s);
-  hipLaunchKernelGGL(k_scan_down<T>, dim3((unsigned)t), dim3(kBlock), 0, s, in,
-                     out, (const T *)tmp, n);
+  PG_LAUNCH(prof, K_RS_SCAN, 1.0 * sizeof(T) * n, k_scan_reduce<T>,
+            dim3((unsigned)t), dim3(kBlock), 0, s, in, tmp, n);
+  scan_rec<T>(tmp, tmp, t, tmp + t, s, prof);
+  PG_LAUNCH(prof, K_RS_SCAN, 2.0 * sizeof(T) * n, k_scan_down<T>,
+            dim3((unsigned)t), dim3(kBlock), 0, s, in, out, (const T *)tmp, n);
 }
 
 size_t scan_excl_i64(const int64_t *in, int64_t *out, int64_t n, void *tmp,
                      hipStream_t s) {
   if (!tmp) return scan_tmp_need<int64_t>(n);
-  scan_rec<int64_t>(in, out, n, (int64_t *)tmp, s);
+  scan_rec<int64_t>(in, out, n, (int64_t *)tmp, s, nullptr);
   return 0;
 }
 
 size_t scan_excl_u32(const uint32_t *in, uint32_t *out, int64_t n, void *tmp,
-                     hipStream_t s) {
+                     hipStream_t s, Prof *prof) {
   if (!tmp) return scan_tmp_need<uint32_t>(n);
-  scan_rec<uint32_t>(in, out, n, (uint32_t *)tmp, s);
+  scan_rec<uint32_t>(in, out, n, (uint32_t *)tmp, s, prof);
   return 0;
 }
 
@@ -237,18 +288,22 @@ __global__ __launch_bounds__(kBlock) void k_rs_downsweep(
 
 int radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
                int64_t n, int bits, uint32_t *tile_cnt, void *scan_tmp,
-               hipStream_t s) {
+               hipStream_t s, Prof *prof) {
   if (n <= 0 || bits <= 0) return 0;
   const int64_t tiles = radix_tiles(n);
   int cur = 0;
   for (int shift = 0; shift < bits; shift += 8) {
     uint32_t *ki = cur ? k1 : k0, *vi = cur ? v1 : v0;
     uint32_t *ko = cur ? k0 : k1, *vo = cur ? v0 : v1;
-    hipLaunchKernelGGL(k_rs_upsweep, dim3((unsigned)tiles), dim3(kBlock), 0, s,
-                       ki, n, shift, tile_cnt, tiles);
-    scan_excl_u32(tile_cnt, tile_cnt, 256 * tiles, scan_tmp, s);
-    hipLaunchKernelGGL(k_rs_downsweep, dim3((unsigned)tiles), dim3(kBlock), 0,
-                       s, ki, vi, ko, vo, n, shift, tile_cnt, tiles);
+    // algorithmic bytes: keys read (4 B) and 1 KiB of counts per tile;
+    // then keys and values read and written (16 B)
+    PG_LAUNCH(prof, K_RS_UPSWEEP, 4.0 * n + 1024.0 * tiles, k_rs_upsweep,
+              dim3((unsigned)tiles), dim3(kBlock), 0, s, ki, n, shift,
+              tile_cnt, tiles);
+    scan_excl_u32(tile_cnt, tile_cnt, 256 * tiles, scan_tmp, s, prof);
+    PG_LAUNCH(prof, K_RS_DOWNSWEEP, 16.0 * n + 1024.0 * tiles, k_rs_downsweep,
+              dim3((unsigned)tiles), dim3(kBlock), 0, s, ki, vi, ko, vo, n,
+              shift, tile_cnt, tiles);
     cur ^= 1;
   }
   return cur;

@@ -417,11 +417,12 @@ static pg_status read_ctr(pg_game *g, hipStream_t s) {
   PG_HIP(hipMemcpyAsync(g->hctr, g->ctr, sizeof(int32_t) * C_COUNT,
                         hipMemcpyDeviceToHost, s));
   PG_HIP(hipStreamSynchronize(s));
+  if (g->prof.on) g->prof.flush();
   return PG_OK;
 }
 
 static void zero_ctr(pg_game *g, hipStream_t s, int which) {
-  fill_i32(g->ctr + which, 0, 1, s);
+  fill_i32(g->ctr + which, 0, 1, s, &g->prof);
 }
 
 // Plans the sublist levels for a level-1 list of L elements.
@@ -448,12 +449,14 @@ static void plan_levels(pg_game *g, int64_t L) {
 pg_status valuation_device(pg_game *g, hipStream_t s, int64_t *n_finite_out) {
   const int32_t N = (int32_t)g->n_aug;
   // --- ng ---------------------------------------------------------------
-  fill_i32(g->ng, -1, N, s);
-  fill_i32(g->cand, -1, N, s);
-  fill_i32(g->ctr, 0, C_COUNT, s);
-  hipLaunchKernelGGL(k_ng_walk, dim3(grid_for(N)), dim3(kBlock), 0, s, N,
-                     g->sp, g->ng, g->cand, (const int32_t *)nullptr, 0,
-                     g->wl0, g->ctr, (int)C_WL_NG, kWalkSteps);
+  Prof *pf = &g->prof;
+  fill_i32(g->ng, -1, N, s, pf);
+  fill_i32(g->cand, -1, N, s, pf);
+  fill_i32(g->ctr, 0, C_COUNT, s, pf);
+  PG_LAUNCH(pf, K_NG_WALK, 20.0 * N, k_ng_walk, dim3(grid_for(N)),
+            dim3(kBlock), 0, s, N, g->sp, g->ng, g->cand,
+            (const int32_t *)nullptr, 0, g->wl0, g->ctr, (int)C_WL_NG,
+            kWalkSteps);
   pg_status st = read_ctr(g, s);
   if (st != PG_OK) return st;
   int32_t pending = g->hctr[C_WL_NG];
@@ -462,9 +465,10 @@ pg_status valuation_device(pg_game *g, hipStream_t s, int64_t *n_finite_out) {
     if (round >= kMaxRounds)
       return pg_fail(PG_EINTERNAL, "ng resolution did not converge");
     zero_ctr(g, s, C_WL_NG);
-    hipLaunchKernelGGL(k_ng_walk, dim3(grid_for(pending)), dim3(kBlock), 0, s,
-                       N, g->sp, g->ng, g->cand, (const int32_t *)wa, pending,
-                       wb, g->ctr, (int)C_WL_NG, kWalkSteps);
+    PG_LAUNCH(pf, K_NG_ROUND, 24.0 * pending, k_ng_walk,
+              dim3(grid_for(pending)), dim3(kBlock), 0, s, N, g->sp, g->ng,
+              g->cand, (const int32_t *)wa, pending, wb, g->ctr, (int)C_WL_NG,
+              kWalkSteps);
     st = read_ctr(g, s);
     if (st != PG_OK) return st;
     pending = g->hctr[C_WL_NG];
@@ -474,12 +478,12 @@ pg_status valuation_device(pg_game *g, hipStream_t s, int64_t *n_finite_out) {
     return pg_fail(PG_EINADMISSIBLE,
                    "the play graph has a cycle whose largest priority is odd");
   // --- root: finite or top ---------------------------------------------
-  fill_u8(g->rs, 0, (int64_t)N + 1, s);
-  fill_i32(g->cand, -1, N, s);
-  hipLaunchKernelGGL(k_root_walk, dim3(grid_for(N)), dim3(kBlock), 0, s, N,
-                     g->ng, g->rs, g->cand, g->key,
-                     (const int32_t *)nullptr, 0, g->wl0, g->ctr,
-                     (int)C_WL_ROOT, kWalkSteps);
+  fill_u8(g->rs, 0, (int64_t)N + 1, s, pf);
+  fill_i32(g->cand, -1, N, s, pf);
+  PG_LAUNCH(pf, K_ROOT_WALK, 10.0 * N, k_root_walk, dim3(grid_for(N)),
+            dim3(kBlock), 0, s, N, g->ng, g->rs, g->cand, g->key,
+            (const int32_t *)nullptr, 0, g->wl0, g->ctr, (int)C_WL_ROOT,
+            kWalkSteps);
   st = read_ctr(g, s);
   if (st != PG_OK) return st;
   pending = g->hctr[C_WL_ROOT];
@@ -488,10 +492,10 @@ pg_status valuation_device(pg_game *g, hipStream_t s, int64_t *n_finite_out) {
     if (round >= kMaxRounds)
       return pg_fail(PG_EINTERNAL, "root resolution did not converge");
     zero_ctr(g, s, C_WL_ROOT);
-    hipLaunchKernelGGL(k_root_walk, dim3(grid_for(pending)), dim3(kBlock), 0,
-                       s, N, g->ng, g->rs, g->cand, g->key,
-                       (const int32_t *)wa, pending, wb, g->ctr,
-                       (int)C_WL_ROOT, kWalkSteps);
+    PG_LAUNCH(pf, K_ROOT_ROUND, 14.0 * pending, k_root_walk,
+              dim3(grid_for(pending)), dim3(kBlock), 0, s, N, g->ng, g->rs,
+              g->cand, g->key, (const int32_t *)wa, pending, wb, g->ctr,
+              (int)C_WL_ROOT, kWalkSteps);
     st = read_ctr(g, s);
     if (st != PG_OK) return st;
     pending = g->hctr[C_WL_ROOT];
@@ -499,22 +503,23 @@ pg_status valuation_device(pg_game *g, hipStream_t s, int64_t *n_finite_out) {
   }
   const int32_t nF = g->hctr[C_NFIN];
   // --- sort finite vertices by (parent, signed priority) -------------------
-  hipLaunchKernelGGL(k_sort_keys, dim3(grid_for(N)), dim3(kBlock), 0, s, N,
-                     g->perm, g->ng, g->rs, g->sk0, g->sv0);
+  PG_LAUNCH(pf, K_SORT_KEYS, 17.0 * N, k_sort_keys, dim3(grid_for(N)),
+            dim3(kBlock), 0, s, N, g->perm, g->ng, g->rs, g->sk0, g->sv0);
   int which = radix_sort(g->sk0, g->sv0, g->sk1, g->sv1, N, g->sort_bits,
-                         g->tile_cnt, g->scan_tmp, s);
+                         g->tile_cnt, g->scan_tmp, s, pf);
   const uint32_t *skS = which ? g->sk1 : g->sk0;
   const uint32_t *svS = which ? g->sv1 : g->sv0;
   // --- Euler list ----------------------------------------------------------
-  fill_i32(g->first, -1, (int64_t)N + 1, s);
-  fill_u8(g->haseven, 0, (int64_t)N + 1, s);
+  fill_i32(g->first, -1, (int64_t)N + 1, s, pf);
+  fill_u8(g->haseven, 0, (int64_t)N + 1, s, pf);
   if (nF > 0)
-    hipLaunchKernelGGL(k_link_info, dim3(grid_for(nF)), dim3(kBlock), 0, s, N,
-                       nF, g->n_oddpri, skS, svS, g->perm, g->kids, g->pos,
-                       g->first, g->haseven);
-  hipLaunchKernelGGL(k_link_build, dim3(grid_for(nF > 0 ? nF : 1)),
-                     dim3(kBlock), 0, s, N, nF, g->n_oddpri, skS, svS,
-                     g->kids, g->pos, g->first, g->haseven, g->elem);
+    PG_LAUNCH(pf, K_LINK_INFO, 24.0 * nF, k_link_info, dim3(grid_for(nF)),
+              dim3(kBlock), 0, s, N, nF, g->n_oddpri, skS, svS, g->perm,
+              g->kids, g->pos, g->first, g->haseven);
+  PG_LAUNCH(pf, K_LINK_BUILD, 41.0 * nF, k_link_build,
+            dim3(grid_for(nF > 0 ? nF : 1)), dim3(kBlock), 0, s, N, nF,
+            g->n_oddpri, skS, svS, g->kids, g->pos, g->first, g->haseven,
+            g->elem);
   // --- list ranking -----------------------------------------------------
   const int64_t L = 2 * (int64_t)nF + 2;
   plan_levels(g, L);
@@ -524,35 +529,36 @@ pg_status valuation_device(pg_game *g, hipStream_t s, int64_t *n_finite_out) {
   {
     RankLevel &l0 = g->lv[0];
     const int64_t threads = (l0.nsplit + kPerThread1 - 1) / kPerThread1;
-    hipLaunchKernelGGL(k_lr_sum1, dim3(grid_for(threads)), dim3(kBlock), 0, s,
-                       g->elem, L, l0.stride, l0.nsplit, kPerThread1, l0.sum,
-                       l0.next, g->ctr);
+    PG_LAUNCH(pf, K_LR_SUM1, 8.0 * L + 8.0 * l0.nsplit, k_lr_sum1,
+              dim3(grid_for(threads)), dim3(kBlock), 0, s, g->elem, L,
+              l0.stride, l0.nsplit, kPerThread1, l0.sum, l0.next, g->ctr);
   }
   for (int k = 1; k < nl; ++k) {
     RankLevel &lp = g->lv[k - 1];
     RankLevel &lk = g->lv[k];
-    hipLaunchKernelGGL(k_lr_sumk, dim3(grid_for(lk.nsplit)), dim3(kBlock), 0,
-                       s, lp.next, lp.sum, lk.size, lk.stride, lk.nsplit,
-                       lk.sum, lk.next, g->ctr);
+    PG_LAUNCH(pf, K_LR_SUMK, 8.0 * lk.size + 8.0 * lk.nsplit, k_lr_sumk,
+              dim3(grid_for(lk.nsplit)), dim3(kBlock), 0, s, lp.next, lp.sum,
+              lk.size, lk.stride, lk.nsplit, lk.sum, lk.next, g->ctr);
   }
   {
     RankLevel &lt = g->lv[nl - 1];
-    hipLaunchKernelGGL(k_lr_top, dim3(1), dim3(kTopThreads), 0, s, lt.next,
-                       lt.sum, (int32_t)lt.nsplit, lt.base, expect, g->ctr);
+    PG_LAUNCH(pf, K_LR_TOP, 12.0 * lt.nsplit, k_lr_top, dim3(1),
+              dim3(kTopThreads), 0, s, lt.next, lt.sum, (int32_t)lt.nsplit,
+              lt.base, expect, g->ctr);
   }
   for (int k = nl - 1; k >= 1; --k) {
     RankLevel &lp = g->lv[k - 1];
     RankLevel &lk = g->lv[k];
-    hipLaunchKernelGGL(k_lr_distk, dim3(grid_for(lk.nsplit)), dim3(kBlock), 0,
-                       s, lp.next, lp.sum, lk.stride, lk.nsplit, lk.base,
-                       lp.base);
+    PG_LAUNCH(pf, K_LR_DISTK, 12.0 * lk.size + 4.0 * lk.nsplit, k_lr_distk,
+              dim3(grid_for(lk.nsplit)), dim3(kBlock), 0, s, lp.next, lp.sum,
+              lk.stride, lk.nsplit, lk.base, lp.base);
   }
   {
     RankLevel &l0 = g->lv[0];
     const int64_t threads = (l0.nsplit + kPerThread1 - 1) / kPerThread1;
-    hipLaunchKernelGGL(k_lr_emit1, dim3(grid_for(threads)), dim3(kBlock), 0, s,
-                       g->elem, l0.stride, l0.nsplit, kPerThread1, l0.base,
-                       g->key);
+    PG_LAUNCH(pf, K_LR_EMIT1, 8.0 * L + 4.0 * l0.nsplit + 4.0 * (nF + 1),
+              k_lr_emit1, dim3(grid_for(threads)), dim3(kBlock), 0, s,
+              g->elem, l0.stride, l0.nsplit, kPerThread1, l0.base, g->key);
   }
   if (n_finite_out) *n_finite_out = (int64_t)nF + 1;
   return PG_OK;
@@ -561,12 +567,21 @@ pg_status valuation_device(pg_game *g, hipStream_t s, int64_t *n_finite_out) {
 pg_status switch_device(pg_game *g, bool odd, hipStream_t s, int32_t *count) {
   const int32_t N = (int32_t)g->n_aug;
   zero_ctr(g, s, C_SWITCH);
+  Prof *pf = &g->prof;
+  // offsets (8 B per row) and owners for every vertex; for the player's own
+  // rows the targets and the key of each target (8 B per edge), the current
+  // choice and its key (12 B per vertex)
   if (odd)
-    hipLaunchKernelGGL(k_odd_switch, dim3(grid_for(N)), dim3(kBlock), 0, s, N,
-                       g->off, g->tgt, g->owner, g->key, g->sp, g->ctr);
+    PG_LAUNCH(pf, K_ODD_SWITCH,
+              9.0 * N + 8.0 + 8.0 * g->m_odd + 12.0 * g->n_odd, k_odd_switch,
+              dim3(grid_for(N)), dim3(kBlock), 0, s, N, g->off, g->tgt,
+              g->owner, g->key, g->sp, g->ctr);
   else
-    hipLaunchKernelGGL(k_even_switch, dim3(grid_for(N)), dim3(kBlock), 0, s, N,
-                       g->off, g->tgt, g->owner, g->key, g->sp, g->ctr);
+    PG_LAUNCH(pf, K_EVEN_SWITCH,
+              9.0 * N + 8.0 + 8.0 * (g->m_aug - g->m_odd) +
+                  12.0 * (N - g->n_odd),
+              k_even_switch, dim3(grid_for(N)), dim3(kBlock), 0, s, N, g->off,
+              g->tgt, g->owner, g->key, g->sp, g->ctr);
   pg_status st = read_ctr(g, s);
   if (st != PG_OK) return st;
   if (g->hctr[C_ERR] & ERR_LISTWALK)

@@ -27,7 +27,8 @@ STATUS_NAMES = {0: "PG_OK", 1: "PG_EINVAL", 2: "PG_ENOMEM", 3: "PG_EDEVICE",
 
 EXPORTS = ["pg_load_csr", "pg_game_info", "pg_export_game",
            "pg_initial_strategies", "pg_valuation", "pg_best_response",
-           "pg_solve", "pg_free", "pg_last_error"]
+           "pg_solve", "pg_profile_enable", "pg_profile_kinds",
+           "pg_profile_read", "pg_free", "pg_last_error"]
 
 
 class PgError(RuntimeError):
@@ -78,6 +79,12 @@ def lib() -> ctypes.CDLL:
                                        U32, P]
         L.pg_solve.argtypes = [P, ctypes.POINTER(SolveOpts), P, P, P,
                                ctypes.POINTER(Stats), P]
+        L.pg_profile_enable.argtypes = [P, I32]
+        L.pg_profile_kinds.argtypes = []
+        L.pg_profile_read.argtypes = [P, I32, ctypes.POINTER(ctypes.c_char_p),
+                                      ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(I64),
+                                      ctypes.POINTER(ctypes.c_double)]
         L.pg_free.argtypes = [P]
         L.pg_last_error.argtypes = []
         L.pg_last_error.restype = ctypes.c_char_p
@@ -239,6 +246,27 @@ class Game:
                               _stream(self.device)))
         return {"winner": winner, "sigma": sigma, "tau": tau,
                 "stats": st.as_dict()}
+
+    def profile(self, on: bool = True):
+        """Enables (and clears) or disables the per-kernel event profiler."""
+        _check(lib().pg_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self) -> dict:
+        """{kernel kind: {"ms", "calls", "bytes"}} for kinds that ran."""
+        out = {}
+        for k in range(lib().pg_profile_kinds()):
+            name = ctypes.c_char_p()
+            ms = ctypes.c_double()
+            calls = ctypes.c_int64()
+            by = ctypes.c_double()
+            _check(lib().pg_profile_read(self._h, k, ctypes.byref(name),
+                                         ctypes.byref(ms), ctypes.byref(calls),
+                                         ctypes.byref(by)))
+            if calls.value:
+                out[name.value.decode()] = {"ms": ms.value,
+                                            "calls": int(calls.value),
+                                            "bytes": by.value}
+        return out
 
     def free(self):
         if getattr(self, "_h", None):
