@@ -302,11 +302,13 @@ pg_status sync_ctr(pg_game *g, hipStream_t s) {
 
 void free_game(pg_game *g) {
   if (!g) return;
-  void *ptrs[] = {g->off,  g->tgt,   g->owner, g->pri,     g->perm,
-                  g->sp,   g->key,   g->ng,    g->cand,    g->wl0,
-                  g->wl1,  g->rs,    g->sk0,   g->sv0,     g->sk1,
-                  g->sv1,  g->tile_cnt, g->scan_tmp, g->kids, g->first,
-                  g->pos,  g->haseven, g->elem, g->ctr};
+  void *ptrs[] = {g->off,      g->tgt,      g->owner,    g->pri,
+                  g->perm,     g->sp,       g->key,      g->ngp[0],
+                  g->ngp[1],   g->candp[0], g->candp[1], g->rcand,
+                  g->wl0,      g->wl1,      g->rs,       g->sk0,
+                  g->sv0,      g->sk1,      g->sv1,      g->tile_cnt,
+                  g->scan_tmp, g->kids,     g->first,    g->pos,
+                  g->haseven,  g->elem,     g->ctr};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (int k = 0; k < 8; ++k) {
@@ -325,8 +327,11 @@ pg_status alloc_state(pg_game *g) {
   PG_TRY(dev_alloc(&g->perm, N));
   PG_TRY(dev_alloc(&g->sp, N + 1));
   PG_TRY(dev_alloc(&g->key, N + 1));
-  PG_TRY(dev_alloc(&g->ng, N + 1));
-  PG_TRY(dev_alloc(&g->cand, N));
+  for (int k = 0; k < 2; ++k) {
+    PG_TRY(dev_alloc(&g->ngp[k], N));
+    PG_TRY(dev_alloc(&g->candp[k], N));
+  }
+  PG_TRY(dev_alloc(&g->rcand, N));
   PG_TRY(dev_alloc(&g->wl0, N));
   PG_TRY(dev_alloc(&g->wl1, N));
   PG_TRY(dev_alloc(&g->rs, N + 1));
@@ -343,6 +348,7 @@ pg_status alloc_state(pg_game *g) {
   PG_TRY(dev_alloc(&g->kids, N));
   PG_TRY(dev_alloc(&g->first, N + 1));
   PG_TRY(dev_alloc(&g->pos, N + 1));
+  fill_i32(g->pos, 0, N + 1, 0);
   PG_TRY(dev_alloc(&g->haseven, N + 1));
   PG_TRY(dev_alloc(&g->elem, 2 * N + 2));
   // sublist levels for the longest possible Euler list
@@ -572,11 +578,10 @@ pg_status inner_loop(pg_game *g, int32_t max_inner, hipStream_t s,
   for (;;) {
     if (max_inner > 0 && inner >= max_inner)
       return pg_fail(PG_EITERLIMIT, "best response: valuation cap reached");
-    PG_TRY(valuation_device(g, s, nullptr));
+    int32_t c = 0;
+    PG_TRY(iteration_device(g, s, &c));
     ++inner;
     ++*n_val;
-    int32_t c = 0;
-    PG_TRY(switch_device(g, true, s, &c));
     *n_sw += c;
     if (c == 0) return PG_OK;
   }
@@ -679,6 +684,7 @@ pg_status pg_valuation(pg_game *g, const int32_t *sigma, const int32_t *tau,
   hipStream_t s = (hipStream_t)hip_stream;
   const bool dev = flags & PG_PTR_DEVICE;
   PG_TRY(import_strats(g, sigma, tau, dev, s));
+  valuation_reset(g, s);
   PG_TRY(valuation_device(g, s, n_finite));
   PG_TRY(copy_out(key, g->key, sizeof(int32_t) * (g->n_aug + 1), dev, s));
   PG_TRY(sync_ctr(g, s));
@@ -696,6 +702,7 @@ pg_status pg_best_response(pg_game *g, const int32_t *sigma, int32_t *tau,
   hipStream_t s = (hipStream_t)hip_stream;
   const bool dev = flags & PG_PTR_DEVICE;
   PG_TRY(import_strats(g, sigma, tau, dev, s));
+  valuation_reset(g, s);
   int64_t nv = 0, nsw = 0;
   pg_status st = inner_loop(g, max_inner, s, &nv, &nsw);
   if (n_valuations) *n_valuations = (int32_t)nv;
@@ -721,6 +728,7 @@ pg_status pg_solve(pg_game *g, const pg_solve_opts *opts, uint8_t *winner,
   const int64_t N = g->n_aug;
   hipLaunchKernelGGL(k_sp_init, dim3(grid_for(N)), dim3(kBlock), 0, s, g->off,
                      g->tgt, g->owner, g->pri, g->sp, (int32_t)N);
+  valuation_reset(g, s);
   int64_t n_major = 0, n_val = 0, n_odd = 0, n_even = 0;
   pg_status st = PG_OK;
   for (;;) {

@@ -19,14 +19,15 @@ constexpr int kMaxVertices = (1 << 30) - 2;
 // device-to-host copy returns all of them.
 enum Counter : int {
   C_ERR = 0,          // error bits (ERR_*)
-  C_WL_NG = 1,        // ng worklist length (unresolved after the walk)
-  C_WL_ROOT = 2,      // root worklist length
-  C_NFIN = 3,         // finite vertices excluding the sink
-  C_SWITCH = 4,       // switches made by the last switch kernel
-  C_WL_NG2 = 5,       // next-round ng worklist length
-  C_WL_ROOT2 = 6,     // next-round root worklist length
-  C_MISC = 7,         // scratch counter (preprocessing changes, X' size)
-  C_COUNT = 16
+  C_NFIN = 1,         // finite vertices excluding the sink
+  C_SWITCH = 2,       // switches made by the last switch kernel
+  C_ABORT = 3,        // nonzero: bounded rounds left work; later kernels skip
+  C_MISC = 4,         // scratch counter (preprocessing changes, odd count)
+  C_HA = 5,           // worklist lengths of host-driven rounds
+  C_HB = 6,
+  C_NGW = 8,          // C_NGW + r: ng worklist length after round r
+  C_RTW = 16,         // C_RTW + r: root worklist length after round r
+  C_COUNT = 32
 };
 
 enum ErrBit : int {
@@ -55,9 +56,11 @@ struct Prof {
   double bytes[K_COUNT] = {};
   struct Pend {
     int kid;
-    double bytes;
+    double bytes;     // fixed part
+    double per_nf;    // plus this many bytes per finite vertex
     hipEvent_t a, b;
   };
+  double nf = 0.0;    // finite count of the valuation being flushed
   std::vector<hipEvent_t> pool;
   std::vector<Pend> pend;
   hipEvent_t get();
@@ -70,11 +73,13 @@ struct ProfScope {
   Prof *p;
   hipStream_t s;
   Prof::Pend e{};
-  ProfScope(Prof *prof, int kid, double bytes, hipStream_t st)
+  ProfScope(Prof *prof, int kid, double bytes, hipStream_t st,
+            double per_nf = 0.0)
       : p(prof && prof->on ? prof : nullptr), s(st) {
     if (!p) return;
     e.kid = kid;
     e.bytes = bytes;
+    e.per_nf = per_nf;
     e.a = p->get();
     e.b = p->get();
     (void)hipEventRecord(e.a, s);
@@ -91,6 +96,14 @@ struct ProfScope {
   do {                                                                    \
     ::pgk::ProfScope ps_((prof), (kid), (double)(bytes), (stream));       \
     hipLaunchKernelGGL(kern, grid, block, smem, stream, __VA_ARGS__);     \
+  } while (0)
+
+// Same, for kernels whose bytes are `per_nf` per finite vertex (the count
+// is read back with the valuation's counters).
+#define PG_LAUNCH_NF(prof, kid, per_nf, kern, grid, block, smem, stream, ...) \
+  do {                                                                        \
+    ::pgk::ProfScope ps_((prof), (kid), 0.0, (stream), (double)(per_nf));    \
+    hipLaunchKernelGGL(kern, grid, block, smem, stream, __VA_ARGS__);         \
   } while (0)
 
 // Per-level arrays of the recursive sublist list ranking.
@@ -123,8 +136,10 @@ struct pg_game {
   // play graph and valuation state
   int2 *sp = nullptr;       // [n_aug+1] {successor (sink = n_aug), priority}
   int32_t *key = nullptr;   // [n_aug+1]
-  int32_t *ng = nullptr;    // [n_aug+1] nearest greater successor-ancestor
-  int32_t *cand = nullptr;  // [n_aug]   walk candidates of unresolved vertices
+  int32_t *ngp[2] = {nullptr, nullptr};    // [n_aug] nearest greater vertex
+  int32_t *candp[2] = {nullptr, nullptr};  // [n_aug] walk candidates
+  int par = 0;              // which ng/cand pair the next valuation uses
+  int32_t *rcand = nullptr; // [n_aug]   root-walk candidates
   int32_t *wl0 = nullptr;   // [n_aug]   worklists
   int32_t *wl1 = nullptr;   // [n_aug]
   uint8_t *rs = nullptr;    // [n_aug+1] 0 unknown, 1 finite, 2 top
@@ -181,23 +196,32 @@ void fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s,
 size_t scan_excl_i64(const int64_t *in, int64_t *out, int64_t n, void *tmp,
                      hipStream_t s);
 size_t scan_excl_u32(const uint32_t *in, uint32_t *out, int64_t n, void *tmp,
-                     hipStream_t s, Prof *prof = nullptr);
+                     hipStream_t s, Prof *prof = nullptr,
+                     const int32_t *gate = nullptr);
 
 // Stable LSD radix sort of (key, value) pairs on the low `bits` bits of the
 // key.  Ping-pongs between (k0, v0) and (k1, v1); returns 0 if the result is
 // in (k0, v0), 1 if in (k1, v1).  tile_cnt must hold 256 * radix_tiles(n).
 int64_t radix_tiles(int64_t n);
+// `gate` (nullable) points at a device word; when it is nonzero the sort's
+// kernels return at once.
 int radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
                int64_t n, int bits, uint32_t *tile_cnt, void *scan_tmp,
-               hipStream_t s, Prof *prof = nullptr);
+               hipStream_t s, Prof *prof = nullptr,
+               const int32_t *gate = nullptr);
 size_t radix_scan_tmp_bytes(int64_t n);
 
 }  // namespace pgk
 
 // ---- valuation and switching (pg_val.hip) ---------------------------------
 namespace pgk {
+// Clears the walk state; call once before a sequence of valuations.
+void valuation_reset(pg_game *g, hipStream_t s);
 // One valuation of the play graph held in g->sp; writes g->key.
 pg_status valuation_device(pg_game *g, hipStream_t s, int64_t *n_finite_out);
 // One All_Odd (odd = true) or All_Even step on g->sp from g->key.
 pg_status switch_device(pg_game *g, bool odd, hipStream_t s, int32_t *count);
+// One best-response iteration (valuation, then All_Odd) with a single
+// host synchronisation; returns the number of Odd switches.
+pg_status iteration_device(pg_game *g, hipStream_t s, int32_t *count);
 }  // namespace pgk

@@ -30,7 +30,7 @@ void Prof::flush() {
     if (hipEventElapsedTime(&t, p.a, p.b) == hipSuccess) {
       ms[p.kid] += t;
       calls[p.kid] += 1;
-      bytes[p.kid] += p.bytes;
+      bytes[p.kid] += p.bytes + p.per_nf * nf;
     }
     pool.push_back(p.a);
     pool.push_back(p.b);
@@ -130,7 +130,9 @@ __device__ T block_excl_scan(T x, T *total) {
 }
 
 template <typename T>
-__global__ void k_scan_reduce(const T *in, T *part, int64_t n) {
+__global__ void k_scan_reduce(const T *in, T *part, int64_t n,
+                              const int32_t *gate) {
+  if (gate && *gate) return;
   const int64_t base = (int64_t)blockIdx.x * kScanTile;
   T acc = 0;
 #pragma unroll
@@ -144,7 +146,9 @@ __global__ void k_scan_reduce(const T *in, T *part, int64_t n) {
 }
 
 template <typename T>
-__global__ void k_scan_down(const T *in, T *out, const T *part, int64_t n) {
+__global__ void k_scan_down(const T *in, T *out, const T *part, int64_t n,
+                            const int32_t *gate) {
+  if (gate && *gate) return;
   const int64_t base = (int64_t)blockIdx.x * kScanTile;
   // blocked arrangement: thread t owns items [base + t*8, base + t*8 + 8)
   T v[kScanItems];
@@ -179,32 +183,33 @@ static size_t scan_tmp_need(int64_t n) {
 
 template <typename T>
 static void scan_rec(const T *in, T *out, int64_t n, T *tmp, hipStream_t s,
-                     Prof *prof) {
+                     Prof *prof, const int32_t *gate) {
   if (n <= 0) return;
   if (n <= kScanTile) {
     PG_LAUNCH(prof, K_RS_SCAN, 2.0 * sizeof(T) * n, k_scan_down<T>, dim3(1),
-              dim3(kBlock), 0, s, in, out, (const T *)nullptr, n);
+              dim3(kBlock), 0, s, in, out, (const T *)nullptr, n, gate);
     return;
   }
   int64_t t = (n + kScanTile - 1) / kScanTile;
   PG_LAUNCH(prof, K_RS_SCAN, 1.0 * sizeof(T) * n, k_scan_reduce<T>,
-            dim3((unsigned)t), dim3(kBlock), 0, s, in, tmp, n);
-  scan_rec<T>(tmp, tmp, t, tmp + t, s, prof);
+            dim3((unsigned)t), dim3(kBlock), 0, s, in, tmp, n, gate);
+  scan_rec<T>(tmp, tmp, t, tmp + t, s, prof, gate);
   PG_LAUNCH(prof, K_RS_SCAN, 2.0 * sizeof(T) * n, k_scan_down<T>,
-            dim3((unsigned)t), dim3(kBlock), 0, s, in, out, (const T *)tmp, n);
+            dim3((unsigned)t), dim3(kBlock), 0, s, in, out, (const T *)tmp, n,
+            gate);
 }
 
 size_t scan_excl_i64(const int64_t *in, int64_t *out, int64_t n, void *tmp,
                      hipStream_t s) {
   if (!tmp) return scan_tmp_need<int64_t>(n);
-  scan_rec<int64_t>(in, out, n, (int64_t *)tmp, s, nullptr);
+  scan_rec<int64_t>(in, out, n, (int64_t *)tmp, s, nullptr, nullptr);
   return 0;
 }
 
 size_t scan_excl_u32(const uint32_t *in, uint32_t *out, int64_t n, void *tmp,
-                     hipStream_t s, Prof *prof) {
+                     hipStream_t s, Prof *prof, const int32_t *gate) {
   if (!tmp) return scan_tmp_need<uint32_t>(n);
-  scan_rec<uint32_t>(in, out, n, (uint32_t *)tmp, s, prof);
+  scan_rec<uint32_t>(in, out, n, (uint32_t *)tmp, s, prof, gate);
   return 0;
 }
 
@@ -224,7 +229,9 @@ size_t radix_scan_tmp_bytes(int64_t n) {
 __global__ __launch_bounds__(kBlock) void k_rs_upsweep(const uint32_t *keys,
                                                        int64_t n, int shift,
                                                        uint32_t *tile_cnt,
-                                                       int64_t tiles) {
+                                                       int64_t tiles,
+                                                       const int32_t *gate) {
+  if (gate && *gate) return;
   __shared__ uint32_t hist[256];
   hist[threadIdx.x] = 0;
   __syncthreads();
@@ -240,7 +247,9 @@ __global__ __launch_bounds__(kBlock) void k_rs_upsweep(const uint32_t *keys,
 
 __global__ __launch_bounds__(kBlock) void k_rs_downsweep(
     const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout,
-    int64_t n, int shift, const uint32_t *tile_off, int64_t tiles) {
+    int64_t n, int shift, const uint32_t *tile_off, int64_t tiles,
+    const int32_t *gate) {
+  if (gate && *gate) return;
   __shared__ uint32_t run[256];
   __shared__ uint32_t wcnt[kRsWaves][256];
   const int tid = threadIdx.x;
@@ -288,7 +297,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_downsweep(
 
 int radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
                int64_t n, int bits, uint32_t *tile_cnt, void *scan_tmp,
-               hipStream_t s, Prof *prof) {
+               hipStream_t s, Prof *prof, const int32_t *gate) {
   if (n <= 0 || bits <= 0) return 0;
   const int64_t tiles = radix_tiles(n);
   int cur = 0;
@@ -299,11 +308,11 @@ int radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
     // then keys and values read and written (16 B)
     PG_LAUNCH(prof, K_RS_UPSWEEP, 4.0 * n + 1024.0 * tiles, k_rs_upsweep,
               dim3((unsigned)tiles), dim3(kBlock), 0, s, ki, n, shift,
-              tile_cnt, tiles);
-    scan_excl_u32(tile_cnt, tile_cnt, 256 * tiles, scan_tmp, s, prof);
+              tile_cnt, tiles, gate);
+    scan_excl_u32(tile_cnt, tile_cnt, 256 * tiles, scan_tmp, s, prof, gate);
     PG_LAUNCH(prof, K_RS_DOWNSWEEP, 16.0 * n + 1024.0 * tiles, k_rs_downsweep,
               dim3((unsigned)tiles), dim3(kBlock), 0, s, ki, vi, ko, vo, n,
-              shift, tile_cnt, tiles);
+              shift, tile_cnt, tiles, gate);
     cur ^= 1;
   }
   return cur;

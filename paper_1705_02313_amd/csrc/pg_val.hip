@@ -38,6 +38,10 @@ __device__ __forceinline__ int ld_relaxed(const int32_t *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+__device__ __forceinline__ void st_relaxed(int32_t *p, int32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // wave-aggregated counter increment: one atomic per wave
 __device__ __forceinline__ void count_wave(int32_t *ctr, bool pred) {
   uint64_t b = __ballot(pred);
@@ -45,116 +49,196 @@ __device__ __forceinline__ void count_wave(int32_t *ctr, bool pred) {
     atomicAdd(ctr, (int)__popcll(b));
 }
 
+constexpr int kStride = 32;        // splitter stride at every level
+
+// size of level k of the sublist ranking for an Euler list of L elements
+__device__ __host__ __forceinline__ int64_t level_size(int64_t L, int k) {
+  for (int j = 0; j < k; ++j) L = (L + kStride - 1) / kStride;
+  return L;
+}
+
 // ---------------------------------------------------------------------------
 // ng: nearest greater vertex along the play
 // ---------------------------------------------------------------------------
 // N = n_aug (the sink's id), TOP id = N + 1.  cand[v] of an unresolved v is
 // the next vertex of v's play not yet compared with v; every vertex strictly
-// between v and cand[v] has a smaller priority than v.
-__global__ __launch_bounds__(kBlock) void k_ng_walk(
+// between v and cand[v] has a smaller priority than v.  Returns ng(v), or -1
+// with *u holding the candidate when the step budget runs out.
+__device__ __forceinline__ int32_t ng_walk(int32_t N, const int2 *sp,
+                                           const int32_t *ng,
+                                           const int32_t *cand, int32_t v,
+                                           int32_t *u_io, int steps,
+                                           int32_t *ctr) {
+  const int pv = sp[v].y;
+  int32_t u = *u_io;
+  for (int s = 0; s < steps; ++s) {
+    if (u == N) return N;
+    if (u == v) {
+      // v came back to itself: it has the largest priority of its cycle,
+      // which must be even for an admissible sigma (section 3)
+      if (pv & 1) atomicOr(&ctr[C_ERR], ERR_INADMISSIBLE);
+      return N + 1;
+    }
+    const int2 su = sp[u];
+    if (su.y > pv) return u;
+    const int32_t r = ld_relaxed(&ng[u]);
+    if (r >= 0) {
+      if (r >= N) return r;  // nothing larger than u (hence v) after u
+      u = r;
+      continue;
+    }
+    const int32_t c = ld_relaxed(&cand[u]);
+    u = (c >= 0) ? c : su.x;
+  }
+  *u_io = u;
+  return -1;
+}
+
+// Full pass.  Also clears this valuation's root-walk state.
+__global__ __launch_bounds__(kBlock) void k_ng_full(
     int32_t N, const int2 *__restrict__ sp, int32_t *ng, int32_t *cand,
-    const int32_t *wl_in, int32_t wl_len, int32_t *wl_out, int32_t *ctr,
-    int wl_ctr, int steps) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int32_t v;
-  int32_t u;
-  bool live;
-  if (wl_in) {
-    live = i < wl_len;
-    v = live ? wl_in[i] : 0;
-    u = live ? cand[v] : 0;
+    int32_t *wl_out, int32_t *ctr, int slot_out, int steps, uint8_t *rs,
+    int32_t *rcand) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int32_t v = (int32_t)i;
+  rs[v] = 0;
+  rcand[v] = -1;
+  int32_t u = sp[v].x;
+  const int32_t res = ng_walk(N, sp, ng, cand, v, &u, steps, ctr);
+  if (res >= 0) {
+    st_relaxed(&ng[v], res);
   } else {
-    live = i < N;
-    v = live ? (int32_t)i : 0;
-    u = live ? sp[v].x : 0;
+    st_relaxed(&cand[v], u);
+    wl_out[atomicAdd(&ctr[slot_out], 1)] = v;
   }
-  bool pending = false;
-  if (live) {
-    const int pv = sp[v].y;
-    int32_t res = -1;
-    for (int s = 0; s < steps; ++s) {
-      if (u == N) { res = N; break; }
-      if (u == v) {
-        // v returned to itself: it has the largest priority of its cycle
-        res = N + 1;
-        if (pv & 1) atomicOr(&ctr[C_ERR], ERR_INADMISSIBLE);
-        break;
-      }
-      const int2 su = sp[u];
-      if (su.y > pv) { res = u; break; }
-      const int32_t r = ld_relaxed(&ng[u]);
-      if (r >= 0) {
-        if (r >= N) { res = r; break; }  // nothing larger after u
-        u = r;
-        continue;
-      }
-      const int32_t c = ld_relaxed(&cand[u]);
-      u = (c >= 0) ? c : su.x;
-    }
+}
+
+// A round over the worklist left by the previous pass: the candidates of
+// unresolved vertices jump over other candidates (pointer jumping).  A fixed
+// grid strides over the list, whose length is read on the device.
+__global__ __launch_bounds__(kBlock) void k_ng_round(
+    int32_t N, const int2 *__restrict__ sp, int32_t *ng, int32_t *cand,
+    const int32_t *wl_in, int32_t *wl_out, int32_t *ctr, int slot_in,
+    int slot_out, int last, int steps) {
+  const int32_t cnt = ctr[slot_in];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
+       i += stride) {
+    const int32_t v = wl_in[i];
+    int32_t u = ld_relaxed(&cand[v]);
+    const int32_t res = ng_walk(N, sp, ng, cand, v, &u, steps, ctr);
     if (res >= 0) {
-      __hip_atomic_store(&ng[v], res, __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
+      st_relaxed(&ng[v], res);
     } else {
-      __hip_atomic_store(&cand[v], u, __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
-      pending = true;
+      st_relaxed(&cand[v], u);
+      wl_out[atomicAdd(&ctr[slot_out], 1)] = v;
+      if (last) atomicOr(&ctr[C_ABORT], 1);
     }
   }
-  if (pending) wl_out[atomicAdd(&ctr[wl_ctr], 1)] = v;
 }
 
 // ---------------------------------------------------------------------------
 // root: does the ng chain end at the sink (finite) or at TOP?
-// rs[v]: 0 unknown, 1 finite, 2 top.  Top vertices get key TOP and ng TOP.
+// rs[v]: 0 unknown, 1 finite, 2 top.  Top vertices get key TOP.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_root_walk(
-    int32_t N, int32_t *ng, uint8_t *rs, int32_t *cand, int32_t *key,
-    const int32_t *wl_in, int32_t wl_len, int32_t *wl_out, int32_t *ctr,
-    int wl_ctr, int steps) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int32_t v = 0, r = 0;
-  bool live;
-  if (wl_in) {
-    live = i < wl_len;
-    if (live) { v = wl_in[i]; r = cand[v]; }
-  } else {
-    live = i < N;
-    if (live) { v = (int32_t)i; r = ng[v]; }
+// Follows the chain from *r_io; returns the fate, or 0 with *r_io at the
+// first vertex not yet decided (-2 when ng of v itself is unresolved).
+__device__ __forceinline__ int root_walk(int32_t N, const int32_t *ng,
+                                         const uint8_t *rs,
+                                         const int32_t *rcand, int32_t v,
+                                         int32_t *r_io, int steps) {
+  int32_t r = *r_io;
+  if (r == -2) r = ld_relaxed(&ng[v]);
+  if (r < 0) {
+    *r_io = -2;
+    return 0;
+  }
+  for (int s = 0; s < steps; ++s) {
+    if (r == N) return 1;
+    if (r == N + 1) return 2;
+    const int known = __hip_atomic_load(&rs[r], __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
+    if (known) return known;
+    int32_t nx = ld_relaxed(&rcand[r]);
+    if (nx < 0) nx = ld_relaxed(&ng[r]);
+    if (nx < 0) break;  // ng of r not resolved yet
+    r = nx;
+  }
+  *r_io = r;
+  return 0;
+}
+
+// Full pass.  Also clears the other ng/cand pair (used by the next
+// valuation) and this valuation's Euler-list per-vertex state.
+__global__ __launch_bounds__(kBlock) void k_root_full(
+    int32_t N, const int32_t *ng, uint8_t *rs, int32_t *rcand, int32_t *key,
+    int32_t *wl_out, int32_t *ctr, int slot_out, int steps, int32_t *ng_next,
+    int32_t *cand_next, int32_t *first, uint8_t *haseven) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    first[N] = -1;
+    haseven[N] = 0;
   }
   int fate = 0;
-  bool pending = false;
-  if (live) {
-    for (int s = 0; s < steps; ++s) {
-      if (r == N) { fate = 1; break; }
-      if (r == N + 1) { fate = 2; break; }
-      const int known = __hip_atomic_load(&rs[r], __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT);
-      if (known) { fate = known; break; }
-      const int32_t c = wl_in ? ld_relaxed(&cand[r]) : -1;
-      // in the first pass follow ng; in later rounds jump over the
-      // candidates published by other unresolved vertices
-      r = (c >= 0 && wl_in) ? c : ld_relaxed(&ng[r]);
-    }
+  if (i < N) {
+    const int32_t v = (int32_t)i;
+    ng_next[v] = -1;
+    cand_next[v] = -1;
+    first[v] = -1;
+    haseven[v] = 0;
+    int32_t r = ld_relaxed(&ng[v]);
+    if (r < 0) r = -2;
+    fate = root_walk(N, ng, rs, rcand, v, &r, steps);
     if (fate) {
       __hip_atomic_store(&rs[v], (uint8_t)fate, __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
       if (fate == 2) key[v] = PG_KEY_TOP;
     } else {
-      __hip_atomic_store(&cand[v], r, __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
-      pending = true;
+      st_relaxed(&rcand[v], r);
+      wl_out[atomicAdd(&ctr[slot_out], 1)] = v;
     }
   }
   count_wave(&ctr[C_NFIN], fate == 1);
-  if (pending) wl_out[atomicAdd(&ctr[wl_ctr], 1)] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_root_round(
+    int32_t N, const int32_t *ng, uint8_t *rs, int32_t *rcand, int32_t *key,
+    const int32_t *wl_in, int32_t *wl_out, int32_t *ctr, int slot_in,
+    int slot_out, int last, int steps) {
+  const int32_t cnt = ctr[slot_in];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  // uniform trip count so every lane reaches the wave-wide count
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < cnt;
+       base += stride) {
+    const int64_t i = base + threadIdx.x;
+    int fate = 0;
+    if (i < cnt) {
+      const int32_t v = wl_in[i];
+      int32_t r = ld_relaxed(&rcand[v]);
+      fate = root_walk(N, ng, rs, rcand, v, &r, steps);
+      if (fate) {
+        __hip_atomic_store(&rs[v], (uint8_t)fate, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        if (fate == 2) key[v] = PG_KEY_TOP;
+      } else {
+        st_relaxed(&rcand[v], r);
+        wl_out[atomicAdd(&ctr[slot_out], 1)] = v;
+        if (last) atomicOr(&ctr[C_ABORT], 1);
+      }
+    }
+    count_wave(&ctr[C_NFIN], fate == 1);
+  }
 }
 
 // sort keys in signed-priority order: the parent for finite vertices, N + 1
 // (after every parent) for top vertices
 __global__ __launch_bounds__(kBlock) void k_sort_keys(
     int32_t N, const int32_t *__restrict__ perm, const int32_t *__restrict__ ng,
-    const uint8_t *__restrict__ rs, uint32_t *sk, uint32_t *sv) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint8_t *__restrict__ rs, uint32_t *sk, uint32_t *sv,
+    const int32_t *ctr) {
+  if (ctr[C_ABORT]) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
   const int32_t v = perm[i];
   sk[i] = (rs[v] == 1) ? (uint32_t)ng[v] : (uint32_t)(N + 1);
@@ -168,12 +252,19 @@ __global__ __launch_bounds__(kBlock) void k_sort_keys(
 // Elements: 0 enters the root (the sink), 1 leaves it; 2i+2 enters kids[i],
 // 2i+3 leaves it.
 __global__ __launch_bounds__(kBlock) void k_link_info(
-    int32_t N, int32_t nF, int32_t n_oddpri, const uint32_t *__restrict__ skS,
+    int32_t N, int32_t n_oddpri, const uint32_t *__restrict__ skS,
     const uint32_t *__restrict__ svS, const int32_t *__restrict__ perm,
-    int32_t *kids, int32_t *pos, int32_t *first, uint8_t *haseven) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t *kids, int32_t *pos, int32_t *first, uint8_t *haseven,
+    int32_t *ctr) {
+  if (ctr[C_ABORT]) return;
+  const int32_t nF = ctr[C_NFIN];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nF) return;
   const uint32_t p = skS[i];
+  if (p > (uint32_t)N) {  // finite count and sort keys disagree
+    atomicOr(&ctr[C_ERR], ERR_RANKCOUNT);
+    return;
+  }
   const uint32_t r = svS[i];
   const int32_t c = perm[r];
   kids[i] = c;
@@ -183,11 +274,13 @@ __global__ __launch_bounds__(kBlock) void k_link_info(
 }
 
 __global__ __launch_bounds__(kBlock) void k_link_build(
-    int32_t N, int32_t nF, int32_t n_oddpri, const uint32_t *__restrict__ skS,
+    int32_t N, int32_t n_oddpri, const uint32_t *__restrict__ skS,
     const uint32_t *__restrict__ svS, const int32_t *__restrict__ kids,
     const int32_t *__restrict__ pos, const int32_t *__restrict__ first,
-    const uint8_t *__restrict__ haseven, int2 *elem) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint8_t *__restrict__ haseven, int2 *elem, const int32_t *ctr) {
+  if (ctr[C_ABORT] || (ctr[C_ERR] & ERR_RANKCOUNT)) return;
+  const int32_t nF = ctr[C_NFIN];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) {
     const int32_t f = first[N];
     elem[0] = make_int2(f >= 0 ? 2 * f + 2 : 1, N);
@@ -219,62 +312,81 @@ __global__ __launch_bounds__(kBlock) void k_link_build(
 // ---------------------------------------------------------------------------
 // list ranking by sublists
 // ---------------------------------------------------------------------------
-// Level 1 walks the Euler list (weights are the top bits of elem[].y); higher
-// levels walk the reduced lists (int weights).  Splitters are the elements
-// whose index is a multiple of the stride; element 0 (the list head) is one.
+// Level 0 walks the Euler list (weights are the top bits of elem[].y); level k
+// walks the list of level-(k-1) splitters (int weights).  Splitters are the
+// elements whose index is a multiple of the stride; element 0 (the list head)
+// is one.  Every size comes from the finite count on the device.
 __global__ __launch_bounds__(kBlock) void k_lr_sum1(
-    const int2 *__restrict__ elem, int64_t L, int stride, int64_t nsplit,
-    int per_thread, int32_t *sum, int32_t *next, int32_t *ctr) {
+    const int2 *__restrict__ elem, int per_thread, int32_t *sum,
+    int32_t *next, int32_t *ctr) {
+  if (ctr[C_ABORT]) return;
+  const int64_t L = 2 * (int64_t)ctr[C_NFIN] + 2;
+  const int64_t nsplit = level_size(L, 1);
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
   for (int k = 0; k < per_thread; ++k) {
     const int64_t j = t + (int64_t)k * nthreads;
     if (j >= nsplit) break;
-    int64_t e = j * stride;
+    int64_t e = j * kStride;
     int32_t acc = 0;
     int64_t steps = 0;
     for (;;) {
       const int2 el = elem[e];
       acc += (int32_t)((uint32_t)el.y >> 31);
       e = el.x;
-      if (e < 0 || e % stride == 0) break;
+      if (e < 0 || e % kStride == 0) break;
       if (++steps > L) { atomicOr(&ctr[C_ERR], ERR_LISTWALK); e = -1; break; }
     }
     sum[j] = acc;
-    next[j] = e < 0 ? -1 : (int32_t)(e / stride);
+    next[j] = e < 0 ? -1 : (int32_t)(e / kStride);
   }
 }
 
 __global__ __launch_bounds__(kBlock) void k_lr_sumk(
     const int32_t *__restrict__ lnext, const int32_t *__restrict__ lw,
-    int64_t L, int stride, int64_t nsplit, int32_t *sum, int32_t *next,
-    int32_t *ctr) {
+    int level, int32_t *sum, int32_t *next, int32_t *ctr) {
+  if (ctr[C_ABORT]) return;
+  const int64_t L = 2 * (int64_t)ctr[C_NFIN] + 2;
+  const int64_t size = level_size(L, level);
+  const int64_t nsplit = level_size(L, level + 1);
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= nsplit) return;
-  int64_t e = j * stride;
+  int64_t e = j * kStride;
   int32_t acc = 0;
   int64_t steps = 0;
   for (;;) {
     acc += lw[e];
     e = lnext[e];
-    if (e < 0 || e % stride == 0) break;
-    if (++steps > L) { atomicOr(&ctr[C_ERR], ERR_LISTWALK); e = -1; break; }
+    if (e < 0 || e % kStride == 0) break;
+    if (++steps > size) {
+      atomicOr(&ctr[C_ERR], ERR_LISTWALK);
+      e = -1;
+      break;
+    }
   }
   sum[j] = acc;
-  next[j] = e < 0 ? -1 : (int32_t)(e / stride);
+  next[j] = e < 0 ? -1 : (int32_t)(e / kStride);
 }
 
-// Ranks a list of at most kTopMax elements (head = 0) inside one block by
-// pointer jumping: suffix sums, then base = total - suffix.
+// Ranks the top list (at most kTopMax elements, head = 0) inside one block
+// by pointer jumping: suffix sums, then base = total - suffix.
 constexpr int kTopMax = 4096;
 constexpr int kTopThreads = 1024;
 
 __global__ __launch_bounds__(kTopThreads) void k_lr_top(
     const int32_t *__restrict__ lnext, const int32_t *__restrict__ lw,
-    int32_t L, int32_t *base, int32_t expect_total, int32_t *ctr) {
+    int level, int32_t *base, int32_t *ctr) {
+  if (ctr[C_ABORT]) return;
+  const int32_t nF = ctr[C_NFIN];
+  const int64_t L0 = 2 * (int64_t)nF + 2;
+  const int32_t L = (int32_t)level_size(L0, level);
   __shared__ int32_t nx[kTopMax];
   __shared__ int32_t sm[kTopMax];
   constexpr int per = kTopMax / kTopThreads;
+  if (L > kTopMax) {
+    if (threadIdx.x == 0) atomicOr(&ctr[C_ERR], ERR_LISTWALK);
+    return;
+  }
   for (int k = 0; k < per; ++k) {
     const int i = threadIdx.x + k * kTopThreads;
     nx[i] = (i < L) ? lnext[i] : -1;
@@ -302,44 +414,51 @@ __global__ __launch_bounds__(kTopThreads) void k_lr_top(
     const int i = threadIdx.x + k * kTopThreads;
     if (i < L) base[i] = total - sm[i];
   }
-  if (threadIdx.x == 0 && expect_total >= 0 && total != expect_total)
+  if (threadIdx.x == 0 && total != nF + 1)
     atomicOr(&ctr[C_ERR], ERR_RANKCOUNT);
 }
 
 // Hands each element of a level-k sublist its exclusive rank.
 __global__ __launch_bounds__(kBlock) void k_lr_distk(
     const int32_t *__restrict__ lnext, const int32_t *__restrict__ lw,
-    int stride, int64_t nsplit, const int32_t *__restrict__ sbase,
-    int32_t *lbase) {
+    int level, const int32_t *__restrict__ sbase, int32_t *lbase,
+    const int32_t *ctr) {
+  if (ctr[C_ABORT]) return;
+  const int64_t L = 2 * (int64_t)ctr[C_NFIN] + 2;
+  const int64_t size = level_size(L, level);
+  const int64_t nsplit = level_size(L, level + 1);
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= nsplit) return;
-  int64_t e = j * stride;
+  int64_t e = j * kStride;
   int32_t b = sbase[j];
-  for (;;) {
+  for (int64_t steps = 0; steps <= size; ++steps) {
     lbase[e] = b;
     b += lw[e];
     e = lnext[e];
-    if (e < 0 || e % stride == 0) break;
+    if (e < 0 || e % kStride == 0) break;
   }
 }
 
 // Final pass over the Euler list: every weighted element emits the key of
 // its node.
 __global__ __launch_bounds__(kBlock) void k_lr_emit1(
-    const int2 *__restrict__ elem, int stride, int64_t nsplit, int per_thread,
-    const int32_t *__restrict__ sbase, int32_t *key) {
+    const int2 *__restrict__ elem, int per_thread,
+    const int32_t *__restrict__ sbase, int32_t *key, const int32_t *ctr) {
+  if (ctr[C_ABORT]) return;
+  const int64_t L = 2 * (int64_t)ctr[C_NFIN] + 2;
+  const int64_t nsplit = level_size(L, 1);
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
   for (int k = 0; k < per_thread; ++k) {
     const int64_t j = t + (int64_t)k * nthreads;
     if (j >= nsplit) break;
-    int64_t e = j * stride;
+    int64_t e = j * kStride;
     int32_t b = sbase[j];
-    for (;;) {
+    for (int64_t steps = 0; steps <= L; ++steps) {
       const int2 el = elem[e];
       if (el.y < 0) key[el.y & 0x7fffffff] = b++;
       e = el.x;
-      if (e < 0 || e % stride == 0) break;
+      if (e < 0 || e % kStride == 0) break;
     }
   }
 }
@@ -353,6 +472,7 @@ __global__ __launch_bounds__(kBlock) void k_odd_switch(
     int32_t N, const int64_t *__restrict__ off, const int32_t *__restrict__ tgt,
     const uint8_t *__restrict__ owner, const int32_t *__restrict__ key,
     int2 *sp, int32_t *ctr) {
+  if (ctr[C_ABORT]) return;
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool sw = false;
   if (v < N && owner[v] == 1) {
@@ -403,170 +523,180 @@ __global__ __launch_bounds__(kBlock) void k_even_switch(
 }  // namespace pgk
 
 // ===========================================================================
-// host side of the valuation
+// host side
 // ===========================================================================
 namespace pgk {
 
-constexpr int kWalkSteps = 256;     // bounded walks before the jump rounds
-constexpr int kMaxRounds = 64;      // jump rounds before giving up
-constexpr int kStride1 = 32;        // level-1 splitter stride
-constexpr int kStrideK = 32;        // higher-level splitter stride
-constexpr int kPerThread1 = 4;      // level-1 sublists per thread
+constexpr int kWalkSteps = 256;   // walk budget of one pass or round
+constexpr int kFastRounds = 2;    // rounds enqueued without looking back
+constexpr int kMaxRounds = 64;    // rounds of the careful path before failing
+constexpr int kRoundBlocks = 1024;
+constexpr int kPerThread1 = 4;    // level-1 sublists per thread
 
 static pg_status read_ctr(pg_game *g, hipStream_t s) {
   PG_HIP(hipMemcpyAsync(g->hctr, g->ctr, sizeof(int32_t) * C_COUNT,
                         hipMemcpyDeviceToHost, s));
   PG_HIP(hipStreamSynchronize(s));
-  if (g->prof.on) g->prof.flush();
+  if (g->prof.on) {
+    g->prof.nf = (double)g->hctr[C_NFIN];
+    g->prof.flush();
+  }
   return PG_OK;
 }
 
-static void zero_ctr(pg_game *g, hipStream_t s, int which) {
-  fill_i32(g->ctr + which, 0, 1, s, &g->prof);
+// number of walking levels of the sublist ranking for the longest list
+static int plan_levels(int64_t N) {
+  const int64_t Lmax = 2 * N + 2;
+  int k = 1;
+  while (level_size(Lmax, k) > kTopMax) ++k;
+  return k;
 }
 
-// Plans the sublist levels for a level-1 list of L elements.
-static void plan_levels(pg_game *g, int64_t L) {
-  int k = 0;
-  int64_t size = L;
-  int stride = kStride1;
-  // level 0 always walks the Euler list; further levels until the reduced
-  // list fits the LDS ranking
-  while ((k == 0 || size > kTopMax) && k < 7) {
-    g->lv[k].size = size;
-    g->lv[k].stride = stride;
-    g->lv[k].nsplit = (size + stride - 1) / stride;
-    size = g->lv[k].nsplit;
-    stride = kStrideK;
-    ++k;
-  }
-  g->lv[k].size = size;
-  g->lv[k].stride = 0;
-  g->lv[k].nsplit = 0;
-  g->nlevels = k;  // levels that walk; level k is ranked in LDS
+void valuation_reset(pg_game *g, hipStream_t s) {
+  const int64_t N = g->n_aug;
+  fill_i32(g->ngp[g->par], -1, N, s, &g->prof);
+  fill_i32(g->candp[g->par], -1, N, s, &g->prof);
 }
 
-pg_status valuation_device(pg_game *g, hipStream_t s, int64_t *n_finite_out) {
+// ng and root phases with a fixed number of rounds; nothing is read back.
+static void enqueue_walks(pg_game *g, hipStream_t s) {
   const int32_t N = (int32_t)g->n_aug;
-  // --- ng ---------------------------------------------------------------
   Prof *pf = &g->prof;
-  fill_i32(g->ng, -1, N, s, pf);
-  fill_i32(g->cand, -1, N, s, pf);
+  int32_t *ng = g->ngp[g->par], *cand = g->candp[g->par];
+  int32_t *ngn = g->ngp[g->par ^ 1], *candn = g->candp[g->par ^ 1];
   fill_i32(g->ctr, 0, C_COUNT, s, pf);
-  PG_LAUNCH(pf, K_NG_WALK, 20.0 * N, k_ng_walk, dim3(grid_for(N)),
-            dim3(kBlock), 0, s, N, g->sp, g->ng, g->cand,
-            (const int32_t *)nullptr, 0, g->wl0, g->ctr, (int)C_WL_NG,
-            kWalkSteps);
+  PG_LAUNCH(pf, K_NG_WALK, 22.0 * N, k_ng_full, dim3(grid_for(N)),
+            dim3(kBlock), 0, s, N, g->sp, ng, cand, g->wl0, g->ctr,
+            (int)C_NGW, kWalkSteps, g->rs, g->rcand);
+  int32_t *wa = g->wl0, *wb = g->wl1;
+  for (int r = 1; r <= kFastRounds; ++r) {
+    PG_LAUNCH(pf, K_NG_ROUND, 0.0, k_ng_round, dim3(kRoundBlocks),
+              dim3(kBlock), 0, s, N, g->sp, ng, cand, (const int32_t *)wa, wb,
+              g->ctr, (int)(C_NGW + r - 1), (int)(C_NGW + r),
+              (int)(r == kFastRounds), kWalkSteps);
+    int32_t *t = wa; wa = wb; wb = t;
+  }
+  PG_LAUNCH(pf, K_ROOT_WALK, 22.0 * N, k_root_full, dim3(grid_for(N)),
+            dim3(kBlock), 0, s, N, ng, g->rs, g->rcand, g->key, g->wl0,
+            g->ctr, (int)C_RTW, kWalkSteps, ngn, candn, g->first, g->haseven);
+  wa = g->wl0; wb = g->wl1;
+  for (int r = 1; r <= kFastRounds; ++r) {
+    PG_LAUNCH(pf, K_ROOT_ROUND, 0.0, k_root_round, dim3(kRoundBlocks),
+              dim3(kBlock), 0, s, N, ng, g->rs, g->rcand, g->key,
+              (const int32_t *)wa, wb, g->ctr, (int)(C_RTW + r - 1),
+              (int)(C_RTW + r), (int)(r == kFastRounds), kWalkSteps);
+    int32_t *t = wa; wa = wb; wb = t;
+  }
+}
+
+// ng and root phases looping on the host until every vertex is resolved.
+static pg_status careful_walks(pg_game *g, hipStream_t s) {
+  const int32_t N = (int32_t)g->n_aug;
+  Prof *pf = &g->prof;
+  int32_t *ng = g->ngp[g->par], *cand = g->candp[g->par];
+  int32_t *ngn = g->ngp[g->par ^ 1], *candn = g->candp[g->par ^ 1];
+  fill_i32(ng, -1, N, s, pf);
+  fill_i32(cand, -1, N, s, pf);
+  fill_i32(g->ctr, 0, C_COUNT, s, pf);
+  PG_LAUNCH(pf, K_NG_WALK, 22.0 * N, k_ng_full, dim3(grid_for(N)),
+            dim3(kBlock), 0, s, N, g->sp, ng, cand, g->wl0, g->ctr, (int)C_HA,
+            kWalkSteps, g->rs, g->rcand);
   pg_status st = read_ctr(g, s);
   if (st != PG_OK) return st;
-  int32_t pending = g->hctr[C_WL_NG];
   int32_t *wa = g->wl0, *wb = g->wl1;
-  for (int round = 0; pending > 0; ++round) {
-    if (round >= kMaxRounds)
+  int in = C_HA, out = C_HB;
+  for (int r = 0; g->hctr[in] > 0; ++r) {
+    if (r >= kMaxRounds)
       return pg_fail(PG_EINTERNAL, "ng resolution did not converge");
-    zero_ctr(g, s, C_WL_NG);
-    PG_LAUNCH(pf, K_NG_ROUND, 24.0 * pending, k_ng_walk,
-              dim3(grid_for(pending)), dim3(kBlock), 0, s, N, g->sp, g->ng,
-              g->cand, (const int32_t *)wa, pending, wb, g->ctr, (int)C_WL_NG,
-              kWalkSteps);
+    fill_i32(g->ctr + out, 0, 1, s, pf);
+    PG_LAUNCH(pf, K_NG_ROUND, 0.0, k_ng_round, dim3(kRoundBlocks),
+              dim3(kBlock), 0, s, N, g->sp, ng, cand, (const int32_t *)wa, wb,
+              g->ctr, in, out, 0, kWalkSteps);
     st = read_ctr(g, s);
     if (st != PG_OK) return st;
-    pending = g->hctr[C_WL_NG];
     int32_t *t = wa; wa = wb; wb = t;
+    int ti = in; in = out; out = ti;
   }
-  if (g->hctr[C_ERR] & ERR_INADMISSIBLE)
-    return pg_fail(PG_EINADMISSIBLE,
-                   "the play graph has a cycle whose largest priority is odd");
-  // --- root: finite or top ---------------------------------------------
-  fill_u8(g->rs, 0, (int64_t)N + 1, s, pf);
-  fill_i32(g->cand, -1, N, s, pf);
-  PG_LAUNCH(pf, K_ROOT_WALK, 10.0 * N, k_root_walk, dim3(grid_for(N)),
-            dim3(kBlock), 0, s, N, g->ng, g->rs, g->cand, g->key,
-            (const int32_t *)nullptr, 0, g->wl0, g->ctr, (int)C_WL_ROOT,
-            kWalkSteps);
+  fill_i32(g->ctr + C_HA, 0, 2, s, pf);
+  fill_i32(g->ctr + C_NFIN, 0, 1, s, pf);
+  PG_LAUNCH(pf, K_ROOT_WALK, 22.0 * N, k_root_full, dim3(grid_for(N)),
+            dim3(kBlock), 0, s, N, ng, g->rs, g->rcand, g->key, g->wl0,
+            g->ctr, (int)C_HA, kWalkSteps, ngn, candn, g->first, g->haseven);
   st = read_ctr(g, s);
   if (st != PG_OK) return st;
-  pending = g->hctr[C_WL_ROOT];
   wa = g->wl0; wb = g->wl1;
-  for (int round = 0; pending > 0; ++round) {
-    if (round >= kMaxRounds)
+  in = C_HA; out = C_HB;
+  for (int r = 0; g->hctr[in] > 0; ++r) {
+    if (r >= kMaxRounds)
       return pg_fail(PG_EINTERNAL, "root resolution did not converge");
-    zero_ctr(g, s, C_WL_ROOT);
-    PG_LAUNCH(pf, K_ROOT_ROUND, 14.0 * pending, k_root_walk,
-              dim3(grid_for(pending)), dim3(kBlock), 0, s, N, g->ng, g->rs,
-              g->cand, g->key, (const int32_t *)wa, pending, wb, g->ctr,
-              (int)C_WL_ROOT, kWalkSteps);
+    fill_i32(g->ctr + out, 0, 1, s, pf);
+    PG_LAUNCH(pf, K_ROOT_ROUND, 0.0, k_root_round, dim3(kRoundBlocks),
+              dim3(kBlock), 0, s, N, ng, g->rs, g->rcand, g->key,
+              (const int32_t *)wa, wb, g->ctr, in, out, 0, kWalkSteps);
     st = read_ctr(g, s);
     if (st != PG_OK) return st;
-    pending = g->hctr[C_WL_ROOT];
     int32_t *t = wa; wa = wb; wb = t;
+    int ti = in; in = out; out = ti;
   }
-  const int32_t nF = g->hctr[C_NFIN];
-  // --- sort finite vertices by (parent, signed priority) -------------------
-  PG_LAUNCH(pf, K_SORT_KEYS, 17.0 * N, k_sort_keys, dim3(grid_for(N)),
-            dim3(kBlock), 0, s, N, g->perm, g->ng, g->rs, g->sk0, g->sv0);
-  int which = radix_sort(g->sk0, g->sv0, g->sk1, g->sv1, N, g->sort_bits,
-                         g->tile_cnt, g->scan_tmp, s, pf);
-  const uint32_t *skS = which ? g->sk1 : g->sk0;
-  const uint32_t *svS = which ? g->sv1 : g->sv0;
-  // --- Euler list ----------------------------------------------------------
-  fill_i32(g->first, -1, (int64_t)N + 1, s, pf);
-  fill_u8(g->haseven, 0, (int64_t)N + 1, s, pf);
-  if (nF > 0)
-    PG_LAUNCH(pf, K_LINK_INFO, 24.0 * nF, k_link_info, dim3(grid_for(nF)),
-              dim3(kBlock), 0, s, N, nF, g->n_oddpri, skS, svS, g->perm,
-              g->kids, g->pos, g->first, g->haseven);
-  PG_LAUNCH(pf, K_LINK_BUILD, 41.0 * nF, k_link_build,
-            dim3(grid_for(nF > 0 ? nF : 1)), dim3(kBlock), 0, s, N, nF,
-            g->n_oddpri, skS, svS, g->kids, g->pos, g->first, g->haseven,
-            g->elem);
-  // --- list ranking -----------------------------------------------------
-  const int64_t L = 2 * (int64_t)nF + 2;
-  plan_levels(g, L);
-  const int nl = g->nlevels;
-  const int32_t expect = nF + 1;
-  // level 0 is the Euler list itself
-  {
-    RankLevel &l0 = g->lv[0];
-    const int64_t threads = (l0.nsplit + kPerThread1 - 1) / kPerThread1;
-    PG_LAUNCH(pf, K_LR_SUM1, 8.0 * L + 8.0 * l0.nsplit, k_lr_sum1,
-              dim3(grid_for(threads)), dim3(kBlock), 0, s, g->elem, L,
-              l0.stride, l0.nsplit, kPerThread1, l0.sum, l0.next, g->ctr);
-  }
-  for (int k = 1; k < nl; ++k) {
-    RankLevel &lp = g->lv[k - 1];
-    RankLevel &lk = g->lv[k];
-    PG_LAUNCH(pf, K_LR_SUMK, 8.0 * lk.size + 8.0 * lk.nsplit, k_lr_sumk,
-              dim3(grid_for(lk.nsplit)), dim3(kBlock), 0, s, lp.next, lp.sum,
-              lk.size, lk.stride, lk.nsplit, lk.sum, lk.next, g->ctr);
-  }
-  {
-    RankLevel &lt = g->lv[nl - 1];
-    PG_LAUNCH(pf, K_LR_TOP, 12.0 * lt.nsplit, k_lr_top, dim3(1),
-              dim3(kTopThreads), 0, s, lt.next, lt.sum, (int32_t)lt.nsplit,
-              lt.base, expect, g->ctr);
-  }
-  for (int k = nl - 1; k >= 1; --k) {
-    RankLevel &lp = g->lv[k - 1];
-    RankLevel &lk = g->lv[k];
-    PG_LAUNCH(pf, K_LR_DISTK, 12.0 * lk.size + 4.0 * lk.nsplit, k_lr_distk,
-              dim3(grid_for(lk.nsplit)), dim3(kBlock), 0, s, lp.next, lp.sum,
-              lk.stride, lk.nsplit, lk.base, lp.base);
-  }
-  {
-    RankLevel &l0 = g->lv[0];
-    const int64_t threads = (l0.nsplit + kPerThread1 - 1) / kPerThread1;
-    PG_LAUNCH(pf, K_LR_EMIT1, 8.0 * L + 4.0 * l0.nsplit + 4.0 * (nF + 1),
-              k_lr_emit1, dim3(grid_for(threads)), dim3(kBlock), 0, s,
-              g->elem, l0.stride, l0.nsplit, kPerThread1, l0.base, g->key);
-  }
-  if (n_finite_out) *n_finite_out = (int64_t)nF + 1;
+  fill_i32(g->ctr + C_ABORT, 0, 1, s, pf);
   return PG_OK;
 }
 
-pg_status switch_device(pg_game *g, bool odd, hipStream_t s, int32_t *count) {
+// sort, Euler list and list ranking; every kernel skips when C_ABORT is set.
+static void enqueue_rank(pg_game *g, hipStream_t s) {
   const int32_t N = (int32_t)g->n_aug;
-  zero_ctr(g, s, C_SWITCH);
+  Prof *pf = &g->prof;
+  const int32_t *ng = g->ngp[g->par];
+  const int32_t *gate = g->ctr + C_ABORT;
+  PG_LAUNCH(pf, K_SORT_KEYS, 17.0 * N, k_sort_keys, dim3(grid_for(N)),
+            dim3(kBlock), 0, s, N, g->perm, ng, g->rs, g->sk0, g->sv0,
+            g->ctr);
+  const int which = radix_sort(g->sk0, g->sv0, g->sk1, g->sv1, N,
+                               g->sort_bits, g->tile_cnt, g->scan_tmp, s, pf,
+                               gate);
+  const uint32_t *skS = which ? g->sk1 : g->sk0;
+  const uint32_t *svS = which ? g->sv1 : g->sv0;
+  // the finite count is only known on the device: size grids for N
+  PG_LAUNCH_NF(pf, K_LINK_INFO, 24.0, k_link_info, dim3(grid_for(N)),
+            dim3(kBlock), 0, s, N, g->n_oddpri, skS, svS, g->perm, g->kids,
+            g->pos, g->first, g->haseven, g->ctr);
+  PG_LAUNCH_NF(pf, K_LINK_BUILD, 41.0, k_link_build, dim3(grid_for(N)),
+            dim3(kBlock), 0, s, N, g->n_oddpri, skS, svS, g->kids, g->pos,
+            g->first, g->haseven, g->elem, g->ctr);
+  const int nl = g->nlevels;
+  const int64_t Lmax = 2 * (int64_t)N + 2;
+  const int64_t ns1 = level_size(Lmax, 1);
+  const int64_t thr1 = (ns1 + kPerThread1 - 1) / kPerThread1;
+  // 8 B per list element (2 per finite vertex) and 8 B per splitter
+  PG_LAUNCH_NF(pf, K_LR_SUM1, 16.5, k_lr_sum1, dim3(grid_for(thr1)),
+            dim3(kBlock), 0, s, g->elem, kPerThread1, g->lv[0].sum,
+            g->lv[0].next, g->ctr);
+  for (int k = 1; k < nl; ++k) {
+    const int64_t nsk = level_size(Lmax, k + 1);
+    // 8 B per element of the level-k list (about 2 nF / 32^k elements)
+    PG_LAUNCH_NF(pf, K_LR_SUMK,
+                 16.0 * (double)level_size(Lmax, k) / (double)Lmax, k_lr_sumk,
+              dim3(grid_for(nsk)), dim3(kBlock), 0, s, g->lv[k - 1].next,
+              g->lv[k - 1].sum, k, g->lv[k].sum, g->lv[k].next, g->ctr);
+  }
+  PG_LAUNCH(pf, K_LR_TOP, 12.0 * level_size(Lmax, nl), k_lr_top, dim3(1),
+            dim3(kTopThreads), 0, s, g->lv[nl - 1].next, g->lv[nl - 1].sum, nl,
+            g->lv[nl - 1].base, g->ctr);
+  for (int k = nl - 1; k >= 1; --k) {
+    const int64_t nsk = level_size(Lmax, k + 1);
+    PG_LAUNCH_NF(pf, K_LR_DISTK,
+                 24.0 * (double)level_size(Lmax, k) / (double)Lmax, k_lr_distk,
+              dim3(grid_for(nsk)), dim3(kBlock), 0, s, g->lv[k - 1].next,
+              g->lv[k - 1].sum, k, g->lv[k].base, g->lv[k - 1].base, g->ctr);
+  }
+  // 8 B per list element, 4 B per splitter, one 4 B key per finite vertex
+  PG_LAUNCH_NF(pf, K_LR_EMIT1, 20.25, k_lr_emit1, dim3(grid_for(thr1)),
+            dim3(kBlock), 0, s, g->elem, kPerThread1, g->lv[0].base, g->key,
+            g->ctr);
+}
+
+static void enqueue_switch(pg_game *g, bool odd, hipStream_t s) {
+  const int32_t N = (int32_t)g->n_aug;
   Prof *pf = &g->prof;
   // offsets (8 B per row) and owners for every vertex; for the player's own
   // rows the targets and the key of each target (8 B per edge), the current
@@ -582,12 +712,68 @@ pg_status switch_device(pg_game *g, bool odd, hipStream_t s, int32_t *count) {
                   12.0 * (N - g->n_odd),
               k_even_switch, dim3(grid_for(N)), dim3(kBlock), 0, s, N, g->off,
               g->tgt, g->owner, g->key, g->sp, g->ctr);
+}
+
+static pg_status check_ctr(pg_game *g) {
+  const int e = g->hctr[C_ERR];
+  if (e & ERR_INADMISSIBLE)
+    return pg_fail(PG_EINADMISSIBLE,
+                   "the play graph has a cycle whose largest priority is odd");
+  if (e & ERR_LISTWALK)
+    return pg_fail(PG_EINTERNAL, "list ranking walk exceeded its bound");
+  if (e & ERR_RANKCOUNT)
+    return pg_fail(PG_EINTERNAL, "list ranking lost elements");
+  return PG_OK;
+}
+
+// One valuation (and, with odd_switch, the All_Odd step after it) with one
+// host synchronisation on the common path.
+static pg_status run_valuation(pg_game *g, hipStream_t s, bool odd_switch,
+                               int32_t *count, int64_t *n_finite) {
+  g->nlevels = plan_levels(g->n_aug);
+  enqueue_walks(g, s);
+  enqueue_rank(g, s);
+  if (odd_switch) {
+    fill_i32(g->ctr + C_SWITCH, 0, 1, s, &g->prof);
+    enqueue_switch(g, true, s);
+  }
   pg_status st = read_ctr(g, s);
   if (st != PG_OK) return st;
-  if (g->hctr[C_ERR] & ERR_LISTWALK)
-    return pg_fail(PG_EINTERNAL, "list ranking walk exceeded its bound");
-  if (g->hctr[C_ERR] & ERR_RANKCOUNT)
-    return pg_fail(PG_EINTERNAL, "list ranking lost elements");
+  if (g->hctr[C_ABORT]) {
+    // a walk outlasted the fixed rounds: finish on the host-driven path and
+    // redo everything after the walks (the gated kernels did nothing)
+    st = careful_walks(g, s);
+    if (st != PG_OK) return st;
+    enqueue_rank(g, s);
+    if (odd_switch) {
+      fill_i32(g->ctr + C_SWITCH, 0, 1, s, &g->prof);
+      enqueue_switch(g, true, s);
+    }
+    st = read_ctr(g, s);
+    if (st != PG_OK) return st;
+  }
+  g->par ^= 1;
+  st = check_ctr(g);
+  if (st != PG_OK) return st;
+  if (count) *count = g->hctr[C_SWITCH];
+  if (n_finite) *n_finite = (int64_t)g->hctr[C_NFIN] + 1;
+  return PG_OK;
+}
+
+pg_status valuation_device(pg_game *g, hipStream_t s, int64_t *n_finite_out) {
+  return run_valuation(g, s, false, nullptr, n_finite_out);
+}
+
+pg_status iteration_device(pg_game *g, hipStream_t s, int32_t *count) {
+  return run_valuation(g, s, true, count, nullptr);
+}
+
+pg_status switch_device(pg_game *g, bool odd, hipStream_t s, int32_t *count) {
+  fill_i32(g->ctr + C_SWITCH, 0, 1, s, &g->prof);
+  fill_i32(g->ctr + C_ABORT, 0, 1, s, &g->prof);
+  enqueue_switch(g, odd, s);
+  pg_status st = read_ctr(g, s);
+  if (st != PG_OK) return st;
   *count = g->hctr[C_SWITCH];
   return PG_OK;
 }

@@ -66,6 +66,11 @@ def lib() -> ctypes.CDLL:
             raise ImportError(
                 f"{LIB_PATH} is missing: build it with "
                 "`python -m paper_1705_02313_amd.build_lib`")
+        # torch ships its own HIP runtime (same soname as the system one).
+        # Loading torch first makes the library bind to that runtime, so one
+        # process never holds two HIP runtimes (a second one leaves torch
+        # without devices).
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         P, I64, I32, U32 = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
                             ctypes.c_uint32)
