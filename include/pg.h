@@ -215,6 +215,52 @@ int32_t pg_profile_kinds(void);
 pg_status pg_profile_read(const pg_game *game, int32_t kind, const char **name,
                           double *ms, int64_t *calls, double *bytes);
 
+/*
+ * Batched and continuously served solving.  A batch is an arena on the
+ * device that holds many games at once; one pg_batch_step advances every game
+ * in it by one best-response iteration of Algorithm 1 (a valuation, All_Odd,
+ * and All_Even for the games whose All_Odd switched nothing), all games in
+ * the same kernel launches.  Each game follows its own copy of Algorithm 1,
+ * so its strategies, winners and counts are those pg_solve gives it alone.
+ *
+ * pg_batch_create  an arena for up to max_vertices / max_edges of modified
+ *                  games (the HBM footprint budget) and max_games games.
+ * pg_batch_submit  validates and preprocesses one game (arguments as
+ *                  pg_load_csr) and queues it; returns a ticket.  PG_ENOMEM
+ *                  if the game alone exceeds the arena.  Queued games join
+ *                  the arena, first come first served, at a step where they
+ *                  fit beside the games already in it.
+ * pg_batch_step    admits queued games that fit (and drops finished ones
+ *                  when they hold a quarter of the arena), then advances
+ *                  every live game once.  Outputs (nullable): games running,
+ *                  games queued, games finished by this step.
+ * pg_batch_poll    done = 1 once the game has finished; then writes its
+ *                  winner (n), sigma and tau (n_aug, as pg_solve) and
+ *                  stats, and releases the ticket.  flags: PG_PTR_DEVICE for
+ *                  device output buffers.
+ * pg_batch_info    games running and queued, current arena size.
+ * pg_batch_free    releases everything, including unpolled games.
+ *
+ * Calls on one batch must not overlap.
+ */
+typedef struct pg_batch pg_batch;
+pg_status pg_batch_create(int64_t max_vertices, int64_t max_edges,
+                          int32_t max_games, void *hip_stream,
+                          pg_batch **out);
+pg_status pg_batch_submit(pg_batch *batch, int64_t n, int64_t m,
+                          const void *offsets, const int32_t *targets,
+                          const uint8_t *owner, const int32_t *priority,
+                          uint32_t flags, int64_t *ticket);
+pg_status pg_batch_step(pg_batch *batch, int32_t *n_live, int32_t *n_queued,
+                        int32_t *n_finished);
+pg_status pg_batch_poll(pg_batch *batch, int64_t ticket, int32_t *done,
+                        uint8_t *winner, int32_t *sigma, int32_t *tau,
+                        pg_stats *stats, uint32_t flags);
+pg_status pg_batch_info(const pg_batch *batch, int32_t *n_live,
+                        int32_t *n_queued, int64_t *arena_vertices,
+                        int64_t *arena_edges);
+pg_status pg_batch_free(pg_batch *batch);
+
 /* Release the game's device memory.  NULL is accepted. */
 pg_status pg_free(pg_game *game);
 

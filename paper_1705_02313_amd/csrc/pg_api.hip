@@ -58,6 +58,10 @@ __global__ void k_check_vertices(const uint8_t *owner, const int32_t *pri,
 // removing Odd vertices without a successor in X until nothing changes.
 // Updates are made in place; any interleaving of them converges to the same
 // largest fixpoint.
+__device__ __forceinline__ int32_t ld_flag(const int32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __global__ void k_x_init(const uint8_t *owner, uint8_t *inx, int64_t n) {
   int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v < n) inx[v] = owner[v] == 1;
@@ -80,8 +84,10 @@ __global__ void k_x_round(const int64_t *__restrict__ off,
       drop = true;
     }
   }
-  if (__ballot(drop) && (threadIdx.x & (kWave - 1)) == 0)
-    atomicAdd(&ctr[C_MISC], 1);
+  // a change flag: most waves find it already set and only read it
+  if (__ballot(drop) && (threadIdx.x & (kWave - 1)) == 0 &&
+      ld_flag(&ctr[C_MISC]) == 0)
+    atomicOr(&ctr[C_MISC], 1);
 }
 
 // X': members of X with a predecessor in X
@@ -144,22 +150,39 @@ __global__ void k_rv_keys(const int32_t *pri, uint32_t *sk, uint32_t *sv,
 }
 
 __global__ void k_rv_finish(const uint32_t *skS, const uint32_t *svS,
-                            int32_t *perm, int64_t n, int32_t *ctr) {
+                            int32_t *perm, int32_t *rvpos, int64_t n,
+                            int32_t *ctr) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool odd = false;
   if (i < n) {
     perm[i] = (int32_t)svS[i];
+    rvpos[svS[i]] = (int32_t)i;
     odd = skS[i] < 0x80000000u;
     if (i > 0 && skS[i] == skS[i - 1]) atomicOr(&ctr[C_ERR], ERR_DUPPRI);
   }
-  uint64_t b = __ballot(odd);
-  if (b && (threadIdx.x & (kWave - 1)) == 0)
-    atomicAdd(&ctr[C_MISC], (int)__popcll(b));
+  count_block(&ctr[C_DIST_MISC], odd);
+}
+
+// Odd vertices and Even vertices as two increasing lists (for the switch
+// kernels), from the exclusive scan `oscan` of the Odd flags.
+__global__ void k_split_players(const uint8_t *owner, const uint32_t *oscan,
+                                int32_t *odd_ids, int32_t *even_ids,
+                                int64_t n) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  if (owner[v] == 1) odd_ids[oscan[v]] = (int32_t)v;
+  else even_ids[v - oscan[v]] = (int32_t)v;
+}
+
+__global__ void k_odd_flags(const uint8_t *owner, uint32_t *f, int64_t n) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) f[v] = owner[v] == 1;
 }
 
 // ---------------------------------------------------------------------------
 // strategies <-> play graph
 // ---------------------------------------------------------------------------
+// sp[v] = {successor, priority of the successor}; the sink's is INT32_MAX
 __global__ void k_sp_init(const int64_t *off, const int32_t *tgt,
                           const uint8_t *owner, const int32_t *pri, int2 *sp,
                           int32_t N) {
@@ -167,12 +190,14 @@ __global__ void k_sp_init(const int64_t *off, const int32_t *tgt,
   if (v == 0) sp[N] = make_int2(N, 2147483647);
   if (v >= N) return;
   const int32_t s = owner[v] ? tgt[off[v]] : N;
-  sp[v] = make_int2(s, pri[v]);
+  sp[v] = make_int2(s, s == N ? 2147483647 : pri[s]);
 }
 
-__global__ void k_sp_import(const uint8_t *owner, const int32_t *sigma,
-                            const int32_t *tau, int2 *sp, int32_t N,
-                            int32_t *ctr) {
+
+
+__global__ void k_sp_import(const uint8_t *owner, const int32_t *pri,
+                            const int32_t *sigma, const int32_t *tau, int2 *sp,
+                            int32_t N, int32_t *ctr) {
   int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= N) return;
   const bool even = owner[v] == 0;
@@ -183,7 +208,7 @@ __global__ void k_sp_import(const uint8_t *owner, const int32_t *sigma,
     atomicOr(&ctr[C_ERR], ERR_INVAL);
     s = N;
   }
-  sp[v].x = s;
+  sp[v] = make_int2(s, s == N ? 2147483647 : pri[s]);
 }
 
 __global__ void k_sp_export(const uint8_t *owner, const int2 *sp,
@@ -205,22 +230,22 @@ __global__ void k_initial(const int64_t *off, const int32_t *tgt,
   if (tau) tau[v] = owner[v] ? tgt[off[v]] : PG_SINK;
 }
 
-// Odd vertices and the edges of their rows (for the switch kernels' bytes)
-__global__ void k_count_odd(const int64_t *off, const uint8_t *owner,
-                            int64_t n, unsigned long long *out) {
-  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  unsigned long long e = 0, c = 0;
-  if (v < n && owner[v] == 1) {
-    e = (unsigned long long)(off[v + 1] - off[v]);
-    c = 1;
-  }
-  for (int o = kWave / 2; o > 0; o >>= 1) {
-    e += __shfl_down(e, o, kWave);
-    c += __shfl_down(c, o, kWave);
-  }
-  if ((threadIdx.x & (kWave - 1)) == 0) {
-    if (c) atomicAdd(&out[0], c);
-    if (e) atomicAdd(&out[1], e);
+// Edges of the Odd rows (for the switch kernels' byte counts): a grid-stride
+// sum with one atomic per block.
+__global__ void k_count_odd_edges(const int64_t *off, const uint8_t *owner,
+                                  int64_t n, unsigned long long *out) {
+  __shared__ unsigned long long part[kBlock / kWave];
+  unsigned long long e = 0;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x)
+    if (owner[v] == 1) e += (unsigned long long)(off[v + 1] - off[v]);
+  for (int o = kWave / 2; o > 0; o >>= 1) e += __shfl_down(e, o, kWave);
+  if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x / kWave] = e;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int w = 0; w < kBlock / kWave; ++w) t += part[w];
+    atomicAdd(out, t);
   }
 }
 
@@ -237,7 +262,7 @@ using namespace pgk;
 // ---------------------------------------------------------------------------
 // helpers
 // ---------------------------------------------------------------------------
-namespace {
+namespace pgk {
 
 struct DevGuard {
   int prev = -1;
@@ -252,23 +277,7 @@ struct DevGuard {
   }
 };
 
-template <typename T>
-pg_status dev_alloc(T **p, int64_t count) {
-  size_t bytes = sizeof(T) * (size_t)(count > 0 ? count : 1);
-  hipError_t e = hipMalloc((void **)p, bytes);
-  if (e != hipSuccess) {
-    *p = nullptr;
-    return pg_fail(PG_ENOMEM, "hipMalloc of " + std::to_string(bytes) +
-                                  " bytes failed: " + hipGetErrorString(e));
-  }
-  return PG_OK;
-}
 
-#define PG_TRY(expr)                   \
-  do {                                 \
-    pg_status st_ = (expr);            \
-    if (st_ != PG_OK) return st_;      \
-  } while (0)
 
 // Copies count elements to or from the caller's buffer, which is on the
 // device when `device` is true.
@@ -303,12 +312,13 @@ pg_status sync_ctr(pg_game *g, hipStream_t s) {
 void free_game(pg_game *g) {
   if (!g) return;
   void *ptrs[] = {g->off,      g->tgt,      g->owner,    g->pri,
-                  g->perm,     g->sp,       g->key,      g->ngp[0],
-                  g->ngp[1],   g->candp[0], g->candp[1], g->rcand,
-                  g->wl0,      g->wl1,      g->rs,       g->sk0,
-                  g->sv0,      g->sk1,      g->sv1,      g->tile_cnt,
-                  g->scan_tmp, g->kids,     g->first,    g->pos,
-                  g->haseven,  g->elem,     g->ctr};
+                  g->perm,     g->rvpos,    g->odd_ids,  g->even_ids,
+                  g->sp,       g->key,      g->ngp[0],   g->ngp[1],
+                  g->candp[0], g->candp[1], g->rcand,    g->wl0,
+                  g->wl1,      g->rs,       g->sk0,      g->sv0,
+                  g->sk1,      g->sv1,      g->tile_cnt, g->scan_tmp,
+                  g->kids,     g->fh,       g->pos,      g->elem,
+                  g->ctr,      g->u64tmp};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (int k = 0; k < 8; ++k) {
@@ -321,10 +331,15 @@ void free_game(pg_game *g) {
   delete g;
 }
 
-// Allocates the per-solve state once the modified game's size is known.
-pg_status alloc_state(pg_game *g) {
-  const int64_t N = g->n_aug;
+// Allocates the per-solve state for games of up to `cap` vertices (the
+// modified game's own size for a single game, the arena size for a batch).
+pg_status alloc_state(pg_game *g, int64_t cap) {
+  const int64_t N = cap;
+  PG_TRY(dev_alloc(&g->odd_ids, N));
+  PG_TRY(dev_alloc(&g->even_ids, N));
+  PG_TRY(dev_alloc(&g->u64tmp, 2));
   PG_TRY(dev_alloc(&g->perm, N));
+  PG_TRY(dev_alloc(&g->rvpos, N));
   PG_TRY(dev_alloc(&g->sp, N + 1));
   PG_TRY(dev_alloc(&g->key, N + 1));
   for (int k = 0; k < 2; ++k) {
@@ -346,10 +361,9 @@ pg_status alloc_state(pg_game *g) {
   if (s2 > g->scan_tmp_bytes) g->scan_tmp_bytes = s2;
   PG_TRY(dev_alloc((uint8_t **)&g->scan_tmp, (int64_t)g->scan_tmp_bytes + 16));
   PG_TRY(dev_alloc(&g->kids, N));
-  PG_TRY(dev_alloc(&g->first, N + 1));
+  PG_TRY(dev_alloc(&g->fh, N + 1));
   PG_TRY(dev_alloc(&g->pos, N + 1));
   fill_i32(g->pos, 0, N + 1, 0);
-  PG_TRY(dev_alloc(&g->haseven, N + 1));
   PG_TRY(dev_alloc(&g->elem, 2 * N + 2));
   // sublist levels for the longest possible Euler list
   int64_t size = 2 * N + 2;
@@ -362,9 +376,6 @@ pg_status alloc_state(pg_game *g) {
     size = ns;
     if (size <= 1) break;
   }
-  int bits = 1;
-  while ((int64_t(1) << bits) <= N + 1) ++bits;
-  g->sort_bits = bits;
   return PG_OK;
 }
 
@@ -381,17 +392,19 @@ pg_status check_err(pg_game *g, const char *what) {
   return PG_OK;
 }
 
-pg_status load_impl(int64_t n, int64_t m, const void *offsets,
-                    const int32_t *targets, const uint8_t *owner,
-                    const int32_t *priority, uint32_t flags, hipStream_t s,
-                    pg_game *g) {
+// Validates a game and builds its modified game in g->off, g->tgt,
+// g->owner, g->pri (section 3 preprocessing unless PG_NO_PREPROCESS).
+pg_status load_modified(int64_t n, int64_t m, const void *offsets,
+                        const int32_t *targets, const uint8_t *owner,
+                        const int32_t *priority, uint32_t flags, hipStream_t s,
+                        pg_game *g) {
   const bool dev = flags & PG_PTR_DEVICE;
   g->n = n;
   g->m = m;
   PG_HIP(hipHostMalloc((void **)&g->hctr, sizeof(int32_t) * C_COUNT,
                        hipHostMallocDefault));
-  PG_TRY(dev_alloc(&g->ctr, C_COUNT));
-  fill_i32(g->ctr, 0, C_COUNT, s);
+  PG_TRY(dev_alloc(&g->ctr, C_TOTAL));
+  fill_i32(g->ctr, 0, C_TOTAL, s);
 
   // input copies
   int64_t *off_in = nullptr;
@@ -500,36 +513,54 @@ pg_status load_impl(int64_t n, int64_t m, const void *offsets,
                        m, K, off_in, tgt_in, own_in, pri_in, inx, xp, did,
                        g->off, g->tgt, g->owner, g->pri, g->ctr);
   }
-  PG_TRY(alloc_state(g));
+  PG_TRY(sync_ctr(g, s));
+  PG_TRY(check_err(g, "a priority exceeds INT32_MAX after preprocessing"));
+  return PG_OK;
+}
 
-  // signed-priority order, distinctness check, count of odd priorities
+// The signed-priority order (and the distinctness check), the initial play
+// graph and the two players' vertex lists of the modified game in g->off,
+// g->tgt, g->owner, g->pri (state allocated by alloc_state).
+pg_status finalize_state(pg_game *g, hipStream_t s, bool init_sp) {
   const int64_t N = g->n_aug;
-  fill_i32(g->ctr + C_MISC, 0, 1, s);
+  int bits = 1;
+  while ((int64_t(1) << bits) <= N + 1) ++bits;
+  g->sort_bits = bits;
+  fill_i32(g->ctr, 0, C_TOTAL, s);
   hipLaunchKernelGGL(k_rv_keys, dim3(grid_for(N)), dim3(kBlock), 0, s, g->pri,
                      g->sk0, g->sv0, N);
   int which = radix_sort(g->sk0, g->sv0, g->sk1, g->sv1, N, 32, g->tile_cnt,
                          g->scan_tmp, s);
   hipLaunchKernelGGL(k_rv_finish, dim3(grid_for(N)), dim3(kBlock), 0, s,
                      which ? g->sk1 : g->sk0, which ? g->sv1 : g->sv0, g->perm,
-                     N, g->ctr);
-  hipLaunchKernelGGL(k_sp_init, dim3(grid_for(N)), dim3(kBlock), 0, s, g->off,
-                     g->tgt, g->owner, g->pri, g->sp, (int32_t)N);
+                     g->rvpos, N, g->ctr);
+  sum_dist(g->ctr, C_DIST_MISC, C_MISC, s);
+  if (init_sp)
+    hipLaunchKernelGGL(k_sp_init, dim3(grid_for(N)), dim3(kBlock), 0, s,
+                       g->off, g->tgt, g->owner, g->pri, g->sp, (int32_t)N);
   PG_TRY(sync_ctr(g, s));
-  PG_TRY(check_err(g, "a priority exceeds INT32_MAX after preprocessing"));
+  PG_TRY(check_err(g, "invalid game"));
   g->n_oddpri = g->hctr[C_MISC];
-  {
-    unsigned long long *cnt = nullptr;
-    PG_TRY(dev_alloc(&cnt, 2));
-    tmp.p.push_back(cnt);
-    fill_i32((int32_t *)cnt, 0, 4, s);
-    hipLaunchKernelGGL(k_count_odd, dim3(grid_for(N)), dim3(kBlock), 0, s,
-                       g->off, g->owner, N, cnt);
-    unsigned long long h[2] = {0, 0};
-    PG_HIP(hipMemcpyAsync(h, cnt, sizeof(h), hipMemcpyDeviceToHost, s));
-    PG_HIP(hipStreamSynchronize(s));
-    g->n_odd = (int64_t)h[0];
-    g->m_odd = (int64_t)h[1];
-  }
+  // the two players' vertex lists and the Odd rows' edge count
+  uint32_t *flags = g->sk0, *oscan = g->sk1;
+  hipLaunchKernelGGL(k_odd_flags, dim3(grid_for(N)), dim3(kBlock), 0, s,
+                     g->owner, flags, N);
+  scan_excl_u32(flags, oscan, N, g->scan_tmp, s);
+  uint32_t last[2] = {0, 0};
+  PG_HIP(hipMemcpyAsync(&last[0], oscan + (N - 1), 4, hipMemcpyDeviceToHost,
+                        s));
+  PG_HIP(hipMemcpyAsync(&last[1], flags + (N - 1), 4, hipMemcpyDeviceToHost,
+                        s));
+  fill_i32((int32_t *)g->u64tmp, 0, 2, s);
+  hipLaunchKernelGGL(k_count_odd_edges, dim3(1024), dim3(kBlock), 0, s,
+                     g->off, g->owner, N, g->u64tmp);
+  unsigned long long me = 0;
+  PG_HIP(hipMemcpyAsync(&me, g->u64tmp, sizeof(me), hipMemcpyDeviceToHost, s));
+  hipLaunchKernelGGL(k_split_players, dim3(grid_for(N)), dim3(kBlock), 0, s,
+                     g->owner, oscan, g->odd_ids, g->even_ids, N);
+  PG_HIP(hipStreamSynchronize(s));
+  g->n_odd = (int64_t)last[0] + last[1];
+  g->m_odd = (int64_t)me;
   return PG_OK;
 }
 
@@ -546,7 +577,7 @@ pg_status import_strats(pg_game *g, const int32_t *sigma, const int32_t *tau,
   }
   fill_i32(g->ctr, 0, C_COUNT, s);
   hipLaunchKernelGGL(k_sp_import, dim3(grid_for(N)), dim3(kBlock), 0, s,
-                     g->owner, ds, dt, g->sp, (int32_t)N, g->ctr);
+                     g->owner, g->pri, ds, dt, g->sp, (int32_t)N, g->ctr);
   PG_TRY(sync_ctr(g, s));
   if (g->hctr[C_ERR] & ERR_INVAL)
     return pg_fail(PG_EINVAL,
@@ -570,6 +601,14 @@ pg_status export_strats(pg_game *g, int32_t *sigma, int32_t *tau, bool dev,
   PG_HIP(hipStreamSynchronize(s));
   return PG_OK;
 }
+
+pg_status export_keys(pg_game *g, int32_t *key, bool dev, hipStream_t s) {
+  return copy_out(key, g->key, sizeof(int32_t) * (g->n_aug + 1), dev, s);
+}
+
+}  // namespace pgk
+
+namespace {
 
 // The inner loop of Algorithm 1 on the play graph in g->sp.
 pg_status inner_loop(pg_game *g, int32_t max_inner, hipStream_t s,
@@ -617,7 +656,10 @@ pg_status pg_load_csr(int64_t n, int64_t m, const void *offsets,
     return pg_fail(PG_EDEVICE, "no HIP device");
   }
   hipStream_t s = (hipStream_t)hip_stream;
-  pg_status st = load_impl(n, m, offsets, targets, owner, priority, flags, s, g);
+  pg_status st =
+      load_modified(n, m, offsets, targets, owner, priority, flags, s, g);
+  if (st == PG_OK) st = alloc_state(g, g->n_aug);
+  if (st == PG_OK) st = finalize_state(g, s, true);
   if (st != PG_OK) {
     (void)hipStreamSynchronize(s);
     free_game(g);
@@ -686,7 +728,7 @@ pg_status pg_valuation(pg_game *g, const int32_t *sigma, const int32_t *tau,
   PG_TRY(import_strats(g, sigma, tau, dev, s));
   valuation_reset(g, s);
   PG_TRY(valuation_device(g, s, n_finite));
-  PG_TRY(copy_out(key, g->key, sizeof(int32_t) * (g->n_aug + 1), dev, s));
+  PG_TRY(export_keys(g, key, dev, s));
   PG_TRY(sync_ctr(g, s));
   PG_TRY(check_err(g, "invalid strategy"));
   return PG_OK;
@@ -708,8 +750,7 @@ pg_status pg_best_response(pg_game *g, const int32_t *sigma, int32_t *tau,
   if (n_valuations) *n_valuations = (int32_t)nv;
   if (st != PG_OK) return st;
   PG_TRY(export_strats(g, nullptr, tau, dev, s));
-  if (key)
-    PG_TRY(copy_out(key, g->key, sizeof(int32_t) * (g->n_aug + 1), dev, s));
+  if (key) PG_TRY(export_keys(g, key, dev, s));
   PG_HIP(hipStreamSynchronize(s));
   return PG_OK;
 }

@@ -1,0 +1,739 @@
+// Many games solved together: an arena holding the disjoint union of the live
+// games, each game running its own copy of Algorithm 1 (section 4).
+//
+// Every submitted game is validated and preprocessed on its own, exactly as
+// pg_load_csr would (its modified game is therefore the solo one).  The arena
+// concatenates the live modified games: vertex v of game s becomes vb_s + v,
+// all games share one sink, and game s's priorities are raised by an even
+// offset so that the priority ranges of different games are disjoint.  Within
+// a game, order and parity of priorities are unchanged and its plays never
+// leave it, so every valuation of the arena orders a game's vertices (and the
+// sink) exactly as the solo valuation does; the switching rules compare keys
+// within one row only.  Hence each game takes the same switches, valuation
+// counts and winners as when solved alone.
+//
+// A step advances every live game by one best-response iteration: one
+// valuation of the arena, All_Odd on the games' Odd vertices, and, for games
+// whose All_Odd switched nothing, All_Even.  A game whose All_Even switched
+// nothing is finished: its results are copied out and it leaves the arena at
+// the next rebuild.  Rebuilds happen when queued games fit (admission by the
+// arena's vertex and edge capacity, first come first served) or when finished
+// games hold a quarter of the arena.
+#include <chrono>
+#include <deque>
+#include <map>
+#include <vector>
+
+#include "pg_common.h"
+
+namespace pgk {
+
+struct GameDesc {
+  const int64_t *off;
+  const int32_t *tgt;
+  const uint8_t *owner;
+  const int32_t *pri;
+  int2 *saved;        // [n_aug] strategies in the game's own ids
+  uint8_t *res_winner;
+  int32_t *res_sigma, *res_tau;
+  int64_t vb, eb;     // first arena vertex / edge
+  int32_t n_aug, n_orig;
+  int64_t m_aug;
+  int32_t poff;       // priority offset (even)
+  int32_t init;       // 1: start from the initial strategies
+};
+
+// index of the game whose range [start[s], start[s+1]) holds x
+__device__ __forceinline__ int find_game(const int64_t *start, int G,
+                                         int64_t x) {
+  int lo = 0, hi = G - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= x) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void k_arena_vertices(const GameDesc *__restrict__ d,
+                                  const int64_t *__restrict__ vstart, int G,
+                                  int32_t N, int64_t M, int64_t *off,
+                                  uint8_t *owner, int32_t *pri, int32_t *gid,
+                                  int2 *sp) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v == 0) off[N] = M;
+  if (v >= N) return;
+  const int s = find_game(vstart, G, v);
+  const GameDesc &g = d[s];
+  const int64_t lv = v - g.vb;
+  off[v] = g.eb + g.off[lv];
+  owner[v] = g.owner[lv];
+  pri[v] = g.pri[lv] + g.poff;
+  gid[v] = s;
+  int32_t x;
+  if (g.init) {
+    x = g.owner[lv] ? (int32_t)(g.vb + g.tgt[g.off[lv]]) : N;
+  } else {
+    const int32_t l = g.saved[lv].x;
+    x = (l == g.n_aug) ? N : (int32_t)(g.vb + l);
+  }
+  sp[v].x = x;
+}
+
+__global__ void k_arena_edges(const GameDesc *__restrict__ d,
+                              const int64_t *__restrict__ estart, int G,
+                              int64_t M, int32_t *tgt) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= M) return;
+  const int s = find_game(estart, G, e);
+  tgt[e] = (int32_t)(d[s].vb + d[s].tgt[e - d[s].eb]);
+}
+
+// the priority of each vertex's successor (second half of sp)
+__global__ void k_arena_sp_pri(const int32_t *pri, int2 *sp, int32_t N) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v == 0) sp[N] = make_int2(N, 2147483647);
+  if (v >= N) return;
+  const int32_t x = sp[v].x;
+  sp[v].y = (x == N) ? 2147483647 : pri[x];
+}
+
+// strategies of the arena back into each live game's own ids
+__global__ void k_arena_save(const GameDesc *__restrict__ d,
+                             const int32_t *__restrict__ gid, const int2 *sp,
+                             int32_t N) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= N) return;
+  const GameDesc &g = d[gid[v]];
+  const int32_t x = sp[v].x;
+  g.saved[v - g.vb].x = (x == N) ? g.n_aug : (int32_t)(x - g.vb);
+}
+
+// results of the games that finished in this step (Theorem 1: W_Even is the
+// set of top keys)
+__global__ void k_arena_export(const GameDesc *__restrict__ d,
+                               const int32_t *__restrict__ gid,
+                               const uint8_t *__restrict__ newly_done,
+                               const int2 *sp, const int32_t *key,
+                               const uint8_t *owner, int32_t N) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= N) return;
+  const int s = gid[v];
+  if (!newly_done[s]) return;
+  const GameDesc &g = d[s];
+  const int64_t lv = v - g.vb;
+  const int32_t x = sp[v].x;
+  const int32_t lx = (x == N) ? PG_SINK : (int32_t)(x - g.vb);
+  const bool even = owner[v] == 0;
+  g.res_sigma[lv] = even ? lx : PG_SINK;
+  g.res_tau[lv] = even ? PG_SINK : lx;
+  if (lv < g.n_orig) g.res_winner[lv] = key[v] == PG_KEY_TOP ? 0 : 1;
+}
+
+// counts one per switching lane into cnt[game]; one atomic per wave when the
+// wave's lanes all belong to the same game
+__device__ __forceinline__ void count_game(int32_t *cnt, int s, bool sw) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int s0 = __shfl(s, 0, kWave);
+  const bool same = __all(s == s0);
+  const uint64_t b = __ballot(sw);
+  if (same) {
+    if (lane == 0 && b) atomicAdd(&cnt[s0], (int)__popcll(b));
+  } else if (sw) {
+    atomicAdd(&cnt[s], 1);
+  }
+}
+
+constexpr int kRowBatchB = 4;
+
+__global__ __launch_bounds__(kBlock) void k_batch_odd(
+    int64_t count, const int32_t *__restrict__ ids,
+    const int64_t *__restrict__ off, const int32_t *__restrict__ tgt,
+    const int32_t *__restrict__ key, const int32_t *__restrict__ pri, int2 *sp,
+    const int32_t *__restrict__ gid, const uint8_t *__restrict__ run,
+    int32_t *cnt, const int32_t *ctr) {
+  if (ctr[C_ABORT]) return;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool sw = false;
+  int s = 0;
+  if (t < count) {
+    const int32_t v = ids[t];
+    s = gid[v];
+    if (run[s]) {
+      const int64_t e0 = off[v], e1 = off[v + 1];
+      const int32_t cur = sp[v].x;
+      const int32_t kc = key[cur];
+      int32_t best = -1, kb = 0;
+      for (int64_t b = e0; b < e1; b += kRowBatchB) {
+        int32_t u[kRowBatchB], k[kRowBatchB];
+#pragma unroll
+        for (int j = 0; j < kRowBatchB; ++j)
+          u[j] = (b + j < e1) ? tgt[b + j] : -1;
+#pragma unroll
+        for (int j = 0; j < kRowBatchB; ++j) k[j] = (u[j] >= 0) ? key[u[j]] : 0;
+#pragma unroll
+        for (int j = 0; j < kRowBatchB; ++j)
+          if (u[j] >= 0 && (best < 0 || k[j] < kb)) { kb = k[j]; best = u[j]; }
+      }
+      if (kb < kc) {
+        sp[v] = make_int2(best, pri[best]);
+        sw = true;
+      }
+    }
+  }
+  count_game(cnt, s, sw);
+}
+
+__global__ __launch_bounds__(kBlock) void k_batch_even(
+    int32_t N, int64_t count, const int32_t *__restrict__ ids,
+    const int64_t *__restrict__ off, const int32_t *__restrict__ tgt,
+    const int32_t *__restrict__ key, const int32_t *__restrict__ pri, int2 *sp,
+    const int32_t *__restrict__ gid, const uint8_t *__restrict__ pending,
+    int32_t *cnt) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool sw = false;
+  int s = 0;
+  if (t < count) {
+    const int32_t v = ids[t];
+    s = gid[v];
+    if (pending[s]) {
+      const int64_t e0 = off[v], e1 = off[v + 1];
+      const int32_t cur = sp[v].x;
+      const int32_t kc = key[cur];
+      int32_t best = N, kb = key[N];
+      for (int64_t b = e0; b < e1; b += kRowBatchB) {
+        int32_t u[kRowBatchB], k[kRowBatchB];
+#pragma unroll
+        for (int j = 0; j < kRowBatchB; ++j)
+          u[j] = (b + j < e1) ? tgt[b + j] : -1;
+#pragma unroll
+        for (int j = 0; j < kRowBatchB; ++j) k[j] = (u[j] >= 0) ? key[u[j]] : 0;
+#pragma unroll
+        for (int j = 0; j < kRowBatchB; ++j)
+          if (u[j] >= 0 && k[j] > kb) { kb = k[j]; best = u[j]; }
+      }
+      if (kb > kc) {
+        sp[v] = make_int2(best, best == N ? 2147483647 : pri[best]);
+        sw = true;
+      }
+    }
+  }
+  count_game(cnt, s, sw);
+}
+
+// Per game, after All_Odd: one more valuation; no Odd switch ends the inner
+// loop and starts an All_Even step (one more outer iteration).
+__global__ void k_batch_ctl1(int G, const uint8_t *run, const int32_t *cnt_odd,
+                             uint8_t *pending, int32_t *n_val,
+                             int32_t *n_major) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= G) return;
+  pending[s] = 0;
+  if (!run[s]) return;
+  n_val[s] += 1;
+  if (cnt_odd[s] == 0) {
+    pending[s] = 1;
+    n_major[s] += 1;
+  }
+}
+
+// Per game, after All_Even: no Even switch finishes the game.
+__global__ void k_batch_ctl2(int G, uint8_t *run, uint8_t *pending,
+                             int32_t *cnt_odd, int32_t *cnt_even,
+                             int64_t *sw_odd, int64_t *sw_even,
+                             uint8_t *newly_done) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= G) return;
+  newly_done[s] = 0;
+  if (run[s]) {
+    sw_odd[s] += cnt_odd[s];
+    if (pending[s]) {
+      sw_even[s] += cnt_even[s];
+      if (cnt_even[s] == 0) {
+        newly_done[s] = 1;
+        run[s] = 0;
+      }
+    }
+  }
+  cnt_odd[s] = 0;
+  cnt_even[s] = 0;
+}
+
+// flag when two neighbours of a sorted key array are equal
+__global__ void k_dup_check(const uint32_t *sk, int64_t n, int32_t *flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > 0 && i < n && sk[i] == sk[i - 1]) *flag = 1;
+}
+
+__global__ void k_max_i32(const int32_t *a, int64_t n, int32_t *out) {
+  int32_t mx = -1;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    mx = a[i] > mx ? a[i] : mx;
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    const int32_t y = __shfl_down(mx, o, kWave);
+    mx = y > mx ? y : mx;
+  }
+  if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(out, mx);
+}
+
+}  // namespace pgk
+
+using namespace pgk;
+
+namespace {
+
+enum BState { B_QUEUED = 0, B_LIVE = 1, B_DONE = 2 };
+
+struct BGame {
+  int64_t ticket = 0;
+  pg_game *g = nullptr;     // the modified game (no valuation state)
+  int state = B_QUEUED;
+  int slot = -1;            // index in the current arena build
+  bool started = false;     // has been in an arena before
+  int32_t maxpri = 0;
+  int2 *saved = nullptr;
+  uint8_t *res_winner = nullptr;
+  int32_t *res_sigma = nullptr, *res_tau = nullptr;
+  pg_stats st{};
+  bool in_arena = false;    // still occupies arena vertices
+  bool polled = false;      // results handed out; free once out of the arena
+};
+
+void free_bgame(BGame *b) {
+  if (!b) return;
+  if (b->saved) (void)hipFree(b->saved);
+  if (b->res_winner) (void)hipFree(b->res_winner);
+  if (b->res_sigma) (void)hipFree(b->res_sigma);
+  if (b->res_tau) (void)hipFree(b->res_tau);
+  free_game(b->g);
+  delete b;
+}
+
+}  // namespace
+
+struct pg_batch {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int64_t cap_v = 0, cap_e = 0;
+  int max_games = 0;
+  pg_game *arena = nullptr;
+  int64_t next_ticket = 1;
+  std::map<int64_t, BGame *> games;
+  std::deque<BGame *> queue;
+  std::vector<BGame *> built;      // games of the current arena, by slot
+  int64_t done_vertices = 0;       // arena vertices of finished games
+  // per-slot device state
+  GameDesc *d_desc = nullptr;
+  int64_t *d_vstart = nullptr, *d_estart = nullptr;
+  int32_t *d_gid = nullptr;
+  uint8_t *d_run = nullptr, *d_pending = nullptr, *d_newly = nullptr;
+  int32_t *d_cnt_odd = nullptr, *d_cnt_even = nullptr;
+  int32_t *d_nval = nullptr, *d_nmaj = nullptr;
+  int64_t *d_sw_odd = nullptr, *d_sw_even = nullptr;
+  int32_t *d_i32 = nullptr;        // scratch
+  // host mirrors
+  std::vector<uint8_t> h_newly;
+  std::vector<int32_t> h_nval, h_nmaj;
+  std::vector<int64_t> h_sw_odd, h_sw_even;
+};
+
+namespace {
+
+pg_status batch_alloc(pg_batch *b) {
+  pg_game *a = new (std::nothrow) pg_game();
+  if (!a) return pg_fail(PG_ENOMEM, "host allocation failed");
+  b->arena = a;
+  a->device = b->device;
+  PG_HIP(hipHostMalloc((void **)&a->hctr, sizeof(int32_t) * C_COUNT,
+                       hipHostMallocDefault));
+  PG_TRY(dev_alloc(&a->ctr, C_TOTAL));
+  PG_TRY(dev_alloc(&a->off, b->cap_v + 1));
+  PG_TRY(dev_alloc(&a->tgt, b->cap_e));
+  PG_TRY(dev_alloc(&a->owner, b->cap_v));
+  PG_TRY(dev_alloc(&a->pri, b->cap_v));
+  PG_TRY(alloc_state(a, b->cap_v));
+  const int G = b->max_games;
+  PG_TRY(dev_alloc(&b->d_desc, G));
+  PG_TRY(dev_alloc(&b->d_vstart, G));
+  PG_TRY(dev_alloc(&b->d_estart, G));
+  PG_TRY(dev_alloc(&b->d_gid, b->cap_v));
+  PG_TRY(dev_alloc(&b->d_run, G));
+  PG_TRY(dev_alloc(&b->d_pending, G));
+  PG_TRY(dev_alloc(&b->d_newly, G));
+  PG_TRY(dev_alloc(&b->d_cnt_odd, G));
+  PG_TRY(dev_alloc(&b->d_cnt_even, G));
+  PG_TRY(dev_alloc(&b->d_nval, G));
+  PG_TRY(dev_alloc(&b->d_nmaj, G));
+  PG_TRY(dev_alloc(&b->d_sw_odd, G));
+  PG_TRY(dev_alloc(&b->d_sw_even, G));
+  PG_TRY(dev_alloc(&b->d_i32, 4));
+  b->h_newly.resize(G);
+  b->h_nval.resize(G);
+  b->h_nmaj.resize(G);
+  b->h_sw_odd.resize(G);
+  b->h_sw_even.resize(G);
+  return PG_OK;
+}
+
+void batch_release(pg_batch *b) {
+  if (!b) return;
+  for (auto &kv : b->games) free_bgame(kv.second);
+  free_game(b->arena);
+  void *ptrs[] = {b->d_desc,    b->d_vstart,  b->d_estart,  b->d_gid,
+                  b->d_run,     b->d_pending, b->d_newly,   b->d_cnt_odd,
+                  b->d_cnt_even, b->d_nval,   b->d_nmaj,    b->d_sw_odd,
+                  b->d_sw_even, b->d_i32};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  delete b;
+}
+
+// Copies the live games' strategies out of the arena, then lays out the
+// arena again with the live games plus queued games that fit.
+pg_status rebuild(pg_batch *b, bool *built_any) {
+  hipStream_t s = b->stream;
+  pg_game *a = b->arena;
+  // save strategies of games still running
+  if (!b->built.empty() && a->n_aug > 0) {
+    hipLaunchKernelGGL(k_arena_save, dim3(grid_for(a->n_aug)), dim3(kBlock), 0,
+                       s, b->d_desc, b->d_gid, a->sp, (int32_t)a->n_aug);
+    // the copies must be done before games leaving the arena are freed
+    PG_HIP(hipStreamSynchronize(s));
+  }
+  std::vector<BGame *> next;
+  int64_t nv = 0, ne = 0;
+  for (BGame *g : b->built)
+    if (g->state == B_LIVE) {
+      next.push_back(g);
+      nv += g->g->n_aug;
+      ne += g->g->m_aug;
+    } else {
+      g->in_arena = false;
+      if (g->polled) {
+        b->games.erase(g->ticket);
+        free_bgame(g);
+      }
+    }
+  while (!b->queue.empty()) {
+    BGame *g = b->queue.front();
+    if (nv + g->g->n_aug > b->cap_v || ne + g->g->m_aug > b->cap_e ||
+        (int)next.size() >= b->max_games)
+      break;  // first come, first served
+    b->queue.pop_front();
+    g->state = B_LIVE;
+    next.push_back(g);
+    nv += g->g->n_aug;
+    ne += g->g->m_aug;
+  }
+  std::vector<GameDesc> desc(next.size());
+  std::vector<int64_t> vstart(next.size()), estart(next.size());
+  // iteration counters continue across rebuilds
+  std::vector<int32_t> nval(next.size()), nmaj(next.size());
+  std::vector<int64_t> swo(next.size()), swe(next.size());
+  int64_t vb = 0, eb = 0, poff = 0;
+  for (size_t i = 0; i < next.size(); ++i) {
+    BGame *g = next[i];
+    GameDesc &d = desc[i];
+    d.off = g->g->off;
+    d.tgt = g->g->tgt;
+    d.owner = g->g->owner;
+    d.pri = g->g->pri;
+    d.saved = g->saved;
+    d.res_winner = g->res_winner;
+    d.res_sigma = g->res_sigma;
+    d.res_tau = g->res_tau;
+    d.vb = vb;
+    d.eb = eb;
+    d.n_aug = (int32_t)g->g->n_aug;
+    d.n_orig = (int32_t)g->g->n;
+    d.m_aug = g->g->m_aug;
+    d.poff = (int32_t)poff;
+    d.init = g->started ? 0 : 1;
+    vstart[i] = vb;
+    estart[i] = eb;
+    nval[i] = (int32_t)g->st.n_valuations;
+    nmaj[i] = (int32_t)g->st.n_major;
+    swo[i] = g->st.n_odd_switches;
+    swe[i] = g->st.n_even_switches;
+    vb += g->g->n_aug;
+    eb += g->g->m_aug;
+    poff += (int64_t)g->maxpri + 1;
+    poff += poff & 1;
+    if (poff > 2000000000LL)
+      return pg_fail(PG_ENOMEM, "batch: priority space of the arena exhausted");
+    g->slot = (int)i;
+    g->started = true;
+    g->in_arena = true;
+  }
+  b->built = next;
+  b->done_vertices = 0;
+  *built_any = !next.empty();
+  const int G = (int)next.size();
+  a->n = a->n_aug = vb;
+  a->m = a->m_aug = eb;
+  if (G == 0) return PG_OK;
+  PG_HIP(hipMemcpyAsync(b->d_desc, desc.data(), sizeof(GameDesc) * G,
+                        hipMemcpyHostToDevice, s));
+  PG_HIP(hipMemcpyAsync(b->d_vstart, vstart.data(), sizeof(int64_t) * G,
+                        hipMemcpyHostToDevice, s));
+  PG_HIP(hipMemcpyAsync(b->d_estart, estart.data(), sizeof(int64_t) * G,
+                        hipMemcpyHostToDevice, s));
+  const int32_t N = (int32_t)vb;
+  hipLaunchKernelGGL(k_arena_vertices, dim3(grid_for(N)), dim3(kBlock), 0, s,
+                     b->d_desc, b->d_vstart, G, N, eb, a->off, a->owner, a->pri,
+                     b->d_gid, a->sp);
+  hipLaunchKernelGGL(k_arena_edges, dim3(grid_for(eb)), dim3(kBlock), 0, s,
+                     b->d_desc, b->d_estart, G, eb, a->tgt);
+  hipLaunchKernelGGL(k_arena_sp_pri, dim3(grid_for(N)), dim3(kBlock), 0, s,
+                     a->pri, a->sp, N);
+  fill_u8(b->d_run, 1, G, s);
+  fill_u8(b->d_pending, 0, G, s);
+  fill_u8(b->d_newly, 0, G, s);
+  fill_i32(b->d_cnt_odd, 0, G, s);
+  fill_i32(b->d_cnt_even, 0, G, s);
+  PG_HIP(hipMemcpyAsync(b->d_nval, nval.data(), 4 * (size_t)G,
+                        hipMemcpyHostToDevice, s));
+  PG_HIP(hipMemcpyAsync(b->d_nmaj, nmaj.data(), 4 * (size_t)G,
+                        hipMemcpyHostToDevice, s));
+  PG_HIP(hipMemcpyAsync(b->d_sw_odd, swo.data(), 8 * (size_t)G,
+                        hipMemcpyHostToDevice, s));
+  PG_HIP(hipMemcpyAsync(b->d_sw_even, swe.data(), 8 * (size_t)G,
+                        hipMemcpyHostToDevice, s));
+  PG_TRY(finalize_state(a, s, false));
+  valuation_reset(a, s);
+  return PG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pg_status pg_batch_create(int64_t max_vertices, int64_t max_edges,
+                          int32_t max_games, void *hip_stream,
+                          pg_batch **out) {
+  if (!out) return pg_fail(PG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (max_vertices < 1 || max_edges < 1 || max_vertices > kMaxVertices ||
+      max_games < 1)
+    return pg_fail(PG_EINVAL, "bad batch capacity");
+  pg_batch *b = new (std::nothrow) pg_batch();
+  if (!b) return pg_fail(PG_ENOMEM, "host allocation failed");
+  if (hipGetDevice(&b->device) != hipSuccess) {
+    delete b;
+    return pg_fail(PG_EDEVICE, "no HIP device");
+  }
+  b->stream = (hipStream_t)hip_stream;
+  b->cap_v = max_vertices;
+  b->cap_e = max_edges;
+  b->max_games = max_games;
+  pg_status st = batch_alloc(b);
+  if (st != PG_OK) {
+    batch_release(b);
+    return st;
+  }
+  *out = b;
+  return PG_OK;
+}
+
+pg_status pg_batch_submit(pg_batch *b, int64_t n, int64_t m,
+                          const void *offsets, const int32_t *targets,
+                          const uint8_t *owner, const int32_t *priority,
+                          uint32_t flags, int64_t *ticket) {
+  if (!b || !ticket) return pg_fail(PG_EINVAL, "NULL argument");
+  if (n < 1 || m < n) return pg_fail(PG_EINVAL, "need n >= 1 and m >= n");
+  hipStream_t s = b->stream;
+  BGame *bg = new (std::nothrow) BGame();
+  if (!bg) return pg_fail(PG_ENOMEM, "host allocation failed");
+  bg->g = new (std::nothrow) pg_game();
+  if (!bg->g) {
+    delete bg;
+    return pg_fail(PG_ENOMEM, "host allocation failed");
+  }
+  bg->g->device = b->device;
+  pg_status st = load_modified(n, m, offsets, targets, owner, priority, flags,
+                               s, bg->g);
+  if (st == PG_OK && (bg->g->n_aug > b->cap_v || bg->g->m_aug > b->cap_e))
+    st = pg_fail(PG_ENOMEM, "game larger than the batch capacity");
+  if (st == PG_OK) st = dev_alloc(&bg->saved, bg->g->n_aug);
+  if (st == PG_OK) st = dev_alloc(&bg->res_winner, n);
+  if (st == PG_OK) st = dev_alloc(&bg->res_sigma, bg->g->n_aug);
+  if (st == PG_OK) st = dev_alloc(&bg->res_tau, bg->g->n_aug);
+  if (st == PG_OK) {
+    // largest priority of the modified game (for the arena offsets)
+    fill_i32(b->d_i32, -1, 1, s);
+    hipLaunchKernelGGL(k_max_i32, dim3(256), dim3(kBlock), 0, s, bg->g->pri,
+                       bg->g->n_aug, b->d_i32);
+    int32_t mx = 0;
+    hipError_t e = hipMemcpyAsync(&mx, b->d_i32, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) st = pg_fail(PG_EDEVICE, hipGetErrorString(e));
+    bg->maxpri = mx;
+  }
+  if (st == PG_OK) {
+    // distinct priorities: sort them in the arena's sort buffers (calls on
+    // one batch do not overlap, so no step is using them now)
+    pg_game *a = b->arena;
+    const int64_t N = bg->g->n_aug;
+    hipLaunchKernelGGL(k_rv_keys, dim3(grid_for(N)), dim3(kBlock), 0, s,
+                       bg->g->pri, a->sk0, a->sv0, N);
+    const int w = radix_sort(a->sk0, a->sv0, a->sk1, a->sv1, N, 32,
+                             a->tile_cnt, a->scan_tmp, s);
+    fill_i32(b->d_i32, 0, 1, s);
+    hipLaunchKernelGGL(k_dup_check, dim3(grid_for(N)), dim3(kBlock), 0, s,
+                       w ? a->sk1 : a->sk0, N, b->d_i32);
+    int32_t dup = 0;
+    hipError_t e = hipMemcpyAsync(&dup, b->d_i32, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) st = pg_fail(PG_EDEVICE, hipGetErrorString(e));
+    else if (dup) st = pg_fail(PG_EINVAL, "priorities must be pairwise distinct");
+  }
+  if (st != PG_OK) {
+    (void)hipStreamSynchronize(s);
+    free_bgame(bg);
+    return st;
+  }
+  bg->ticket = b->next_ticket++;
+  bg->st.n = n;
+  bg->st.m = m;
+  bg->st.n_aug = bg->g->n_aug;
+  bg->st.m_aug = bg->g->m_aug;
+  b->games[bg->ticket] = bg;
+  b->queue.push_back(bg);
+  *ticket = bg->ticket;
+  return PG_OK;
+}
+
+pg_status pg_batch_step(pg_batch *b, int32_t *n_live, int32_t *n_queued,
+                        int32_t *n_finished) {
+  if (!b) return pg_fail(PG_EINVAL, "batch is NULL");
+  hipStream_t s = b->stream;
+  pg_game *a = b->arena;
+  // rebuild when queued games can come in or finished games hold a quarter
+  // of the arena
+  int64_t live_v = 0, live_e = 0;
+  for (BGame *g : b->built)
+    if (g->state == B_LIVE) {
+      live_v += g->g->n_aug;
+      live_e += g->g->m_aug;
+    }
+  bool admit = false;
+  if (!b->queue.empty()) {
+    BGame *q = b->queue.front();
+    admit = live_v + q->g->n_aug <= b->cap_v &&
+            live_e + q->g->m_aug <= b->cap_e;
+  }
+  const bool shrink = a->n_aug > 0 && 4 * b->done_vertices >= a->n_aug;
+  const bool empty = live_v == 0;
+  if (admit || shrink || (empty && !b->built.empty())) {
+    bool any = false;
+    PG_TRY(rebuild(b, &any));
+  }
+  int32_t finished = 0;
+  const int G = (int)b->built.size();
+  bool live = false;
+  for (BGame *g : b->built) live |= g->state == B_LIVE;
+  if (live) {
+    PG_TRY(valuation_device(a, s, nullptr));
+    const int32_t N = (int32_t)a->n_aug;
+    if (a->n_odd > 0)
+      hipLaunchKernelGGL(k_batch_odd, dim3(grid_for(a->n_odd)), dim3(kBlock), 0,
+                         s, a->n_odd, a->odd_ids, a->off, a->tgt, a->key,
+                         a->pri, a->sp, b->d_gid, b->d_run, b->d_cnt_odd,
+                         a->ctr);
+    hipLaunchKernelGGL(k_batch_ctl1, dim3(grid_for(G)), dim3(kBlock), 0, s, G,
+                       b->d_run, b->d_cnt_odd, b->d_pending, b->d_nval,
+                       b->d_nmaj);
+    const int64_t ne = N - a->n_odd;
+    if (ne > 0)
+      hipLaunchKernelGGL(k_batch_even, dim3(grid_for(ne)), dim3(kBlock), 0, s,
+                         N, ne, a->even_ids, a->off, a->tgt, a->key, a->pri,
+                         a->sp, b->d_gid, b->d_pending, b->d_cnt_even);
+    hipLaunchKernelGGL(k_batch_ctl2, dim3(grid_for(G)), dim3(kBlock), 0, s, G,
+                       b->d_run, b->d_pending, b->d_cnt_odd, b->d_cnt_even,
+                       b->d_sw_odd, b->d_sw_even, b->d_newly);
+    hipLaunchKernelGGL(k_arena_export, dim3(grid_for(N)), dim3(kBlock), 0, s,
+                       b->d_desc, b->d_gid, b->d_newly, a->sp, a->key,
+                       a->owner, N);
+    PG_HIP(hipMemcpyAsync(b->h_newly.data(), b->d_newly, G,
+                          hipMemcpyDeviceToHost, s));
+    PG_HIP(hipMemcpyAsync(b->h_nval.data(), b->d_nval, 4 * (size_t)G,
+                          hipMemcpyDeviceToHost, s));
+    PG_HIP(hipMemcpyAsync(b->h_nmaj.data(), b->d_nmaj, 4 * (size_t)G,
+                          hipMemcpyDeviceToHost, s));
+    PG_HIP(hipMemcpyAsync(b->h_sw_odd.data(), b->d_sw_odd, 8 * (size_t)G,
+                          hipMemcpyDeviceToHost, s));
+    PG_HIP(hipMemcpyAsync(b->h_sw_even.data(), b->d_sw_even, 8 * (size_t)G,
+                          hipMemcpyDeviceToHost, s));
+    PG_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < G; ++i) {
+      BGame *g = b->built[i];
+      if (g->state != B_LIVE) continue;
+      g->st.n_valuations = b->h_nval[i];
+      g->st.n_major = b->h_nmaj[i];
+      g->st.n_odd_switches = b->h_sw_odd[i];
+      g->st.n_even_switches = b->h_sw_even[i];
+      if (b->h_newly[i]) {
+        g->state = B_DONE;
+        b->done_vertices += g->g->n_aug;
+        ++finished;
+      }
+    }
+  }
+  if (n_live) {
+    int32_t c = 0;
+    for (BGame *g : b->built) c += g->state == B_LIVE;
+    *n_live = c;
+  }
+  if (n_queued) *n_queued = (int32_t)b->queue.size();
+  if (n_finished) *n_finished = finished;
+  return PG_OK;
+}
+
+pg_status pg_batch_poll(pg_batch *b, int64_t ticket, int32_t *done,
+                        uint8_t *winner, int32_t *sigma, int32_t *tau,
+                        pg_stats *stats, uint32_t flags) {
+  if (!b || !done) return pg_fail(PG_EINVAL, "NULL argument");
+  auto it = b->games.find(ticket);
+  if (it == b->games.end()) return pg_fail(PG_EINVAL, "unknown ticket");
+  BGame *g = it->second;
+  *done = g->state == B_DONE;
+  if (stats) *stats = g->st;
+  if (!*done) return PG_OK;
+  hipStream_t s = b->stream;
+  const bool dev = flags & PG_PTR_DEVICE;
+  if (winner) PG_TRY(copy_out(winner, g->res_winner, g->g->n, dev, s));
+  if (sigma)
+    PG_TRY(copy_out(sigma, g->res_sigma, sizeof(int32_t) * g->g->n_aug, dev, s));
+  if (tau)
+    PG_TRY(copy_out(tau, g->res_tau, sizeof(int32_t) * g->g->n_aug, dev, s));
+  PG_HIP(hipStreamSynchronize(s));
+  g->polled = true;
+  if (!g->in_arena) {
+    b->games.erase(it);
+    free_bgame(g);
+  }  // else: still laid out in the arena; released at the next rebuild
+  return PG_OK;
+}
+
+pg_status pg_batch_info(const pg_batch *b, int32_t *n_live,
+                        int32_t *n_queued, int64_t *arena_vertices,
+                        int64_t *arena_edges) {
+  if (!b) return pg_fail(PG_EINVAL, "batch is NULL");
+  int32_t c = 0;
+  for (BGame *g : b->built) c += g->state == B_LIVE;
+  if (n_live) *n_live = c;
+  if (n_queued) *n_queued = (int32_t)b->queue.size();
+  if (arena_vertices) *arena_vertices = b->arena->n_aug;
+  if (arena_edges) *arena_edges = b->arena->m_aug;
+  return PG_OK;
+}
+
+pg_status pg_batch_free(pg_batch *b) {
+  if (!b) return PG_OK;
+  (void)hipStreamSynchronize(b->stream);
+  batch_release(b);
+  return PG_OK;
+}
+
+}  // extern "C"

@@ -27,8 +27,17 @@ enum Counter : int {
   C_HB = 6,
   C_NGW = 8,          // C_NGW + r: ng worklist length after round r
   C_RTW = 16,         // C_RTW + r: root worklist length after round r
-  C_COUNT = 32
+  C_COUNT = 32,       // the part copied back to the host
+  // Hot counts are spread over kDistSlots slots kDistStride ints apart (one
+  // atomic per block into slot blockIdx % kDistSlots) and summed by one
+  // small kernel: a single address hit by every block serialises.
+  C_DIST_NF = 32,
+  C_DIST_SW = 32 + 1024,
+  C_DIST_MISC = 32 + 2048,
+  C_TOTAL = 32 + 3072
 };
+constexpr int kDistSlots = 64;
+constexpr int kDistStride = 16;
 
 enum ErrBit : int {
   ERR_INADMISSIBLE = 1,  // a cycle whose largest priority is odd
@@ -134,8 +143,9 @@ struct pg_game {
   int32_t *perm = nullptr;  // [n_aug] vertices in signed-priority order
 
   // play graph and valuation state
-  int2 *sp = nullptr;       // [n_aug+1] {successor (sink = n_aug), priority}
-  int32_t *key = nullptr;   // [n_aug+1]
+  // [n_aug+1] {successor (the sink is n_aug), priority of that successor}
+  int2 *sp = nullptr;
+  int32_t *key = nullptr;   // [n_aug+1] valuation keys; n_aug is the sink
   int32_t *ngp[2] = {nullptr, nullptr};    // [n_aug] nearest greater vertex
   int32_t *candp[2] = {nullptr, nullptr};  // [n_aug] walk candidates
   int par = 0;              // which ng/cand pair the next valuation uses
@@ -153,15 +163,20 @@ struct pg_game {
 
   // Euler list of the nearest-greater-ancestor tree
   int32_t *kids = nullptr;   // [n_aug]   vertices in (parent, signed-priority) order
-  int32_t *first = nullptr;  // [n_aug+1] sorted position of the first child, or -1
+  // [n_aug+1] 0 for a leaf, else (sorted position of the first child + 1),
+  // with bit 31 set when the last child has an even priority
+  uint32_t *fh = nullptr;
   int32_t *pos = nullptr;    // [n_aug+1] sorted position of each finite vertex
-  uint8_t *haseven = nullptr;// [n_aug+1] 1 if the last child has even priority
+  int32_t *rvpos = nullptr;  // [n_aug] position of each vertex in perm
+  int32_t *odd_ids = nullptr;   // [n_odd]  Odd vertices, increasing
+  int32_t *even_ids = nullptr;  // [n_aug - n_odd] Even vertices, increasing
   int2 *elem = nullptr;      // [2*n_aug+2] {next element or -1, node | weight bit}
 
   pgk::RankLevel lv[8];
   int nlevels = 0;
 
-  int32_t *ctr = nullptr;    // [C_COUNT] device counters
+  unsigned long long *u64tmp = nullptr;  // [2] scratch for 64-bit sums
+  int32_t *ctr = nullptr;    // [C_TOTAL] device counters
   int32_t *hctr = nullptr;   // pinned host mirror
 
   pgk::Prof prof;
@@ -178,8 +193,32 @@ pg_status pg_fail(pg_status st, const std::string &msg);
                      std::string(#call) + ": " + hipGetErrorString(e_));   \
   } while (0)
 
+#define PG_TRY(expr)                   \
+  do {                                 \
+    pg_status st_ = (expr);            \
+    if (st_ != PG_OK) return st_;      \
+  } while (0)
+
 // ---- primitives (pg_prims.hip) --------------------------------------------
 namespace pgk {
+
+// Adds the number of threads of the block with `pred` to the distributed
+// counter starting at `dist` (see C_DIST_*).  Every thread of the block must
+// call it.
+__device__ __forceinline__ void count_block(int32_t *dist, bool pred) {
+  __shared__ int32_t blk;
+  if (threadIdx.x == 0) blk = 0;
+  __syncthreads();
+  const uint64_t b = __ballot(pred);
+  if ((threadIdx.x & (kWave - 1)) == 0 && b) atomicAdd(&blk, (int)__popcll(b));
+  __syncthreads();
+  if (threadIdx.x == 0 && blk)
+    atomicAdd(&dist[(blockIdx.x % kDistSlots) * kDistStride], blk);
+}
+
+// ctr[dst] += sum of the distributed counter at ctr + dist (one block).
+void sum_dist(int32_t *ctr, int dist, int dst, hipStream_t s,
+              Prof *prof = nullptr);
 
 inline unsigned grid_for(int64_t n, int block = kBlock) {
   int64_t g = (n + block - 1) / block;
@@ -208,7 +247,7 @@ int64_t radix_tiles(int64_t n);
 int radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
                int64_t n, int bits, uint32_t *tile_cnt, void *scan_tmp,
                hipStream_t s, Prof *prof = nullptr,
-               const int32_t *gate = nullptr);
+               const int32_t *gate = nullptr, bool index_values = false);
 size_t radix_scan_tmp_bytes(int64_t n);
 
 }  // namespace pgk
@@ -224,4 +263,34 @@ pg_status switch_device(pg_game *g, bool odd, hipStream_t s, int32_t *count);
 // One best-response iteration (valuation, then All_Odd) with a single
 // host synchronisation; returns the number of Odd switches.
 pg_status iteration_device(pg_game *g, hipStream_t s, int32_t *count);
+}  // namespace pgk
+
+// ---- loading helpers shared by single games and batches (pg_api.hip) ------
+namespace pgk {
+__global__ void k_rv_keys(const int32_t *pri, uint32_t *sk, uint32_t *sv,
+                          int64_t n);
+template <typename T>
+pg_status dev_alloc(T **p, int64_t count) {
+  size_t bytes = sizeof(T) * (size_t)(count > 0 ? count : 1);
+  hipError_t e = hipMalloc((void **)p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return pg_fail(PG_ENOMEM, "hipMalloc of " + std::to_string(bytes) +
+                                  " bytes failed: " + hipGetErrorString(e));
+  }
+  return PG_OK;
+}
+pg_status copy_in(void *dst, const void *src, size_t bytes, bool device,
+                  hipStream_t s);
+pg_status copy_out(void *dst, const void *src, size_t bytes, bool device,
+                   hipStream_t s);
+pg_status sync_ctr(pg_game *g, hipStream_t s);
+void free_game(pg_game *g);
+pg_status alloc_state(pg_game *g, int64_t cap);
+pg_status check_err(pg_game *g, const char *what);
+pg_status load_modified(int64_t n, int64_t m, const void *offsets,
+                        const int32_t *targets, const uint8_t *owner,
+                        const int32_t *priority, uint32_t flags, hipStream_t s,
+                        pg_game *g);
+pg_status finalize_state(pg_game *g, hipStream_t s, bool init_sp);
 }  // namespace pgk

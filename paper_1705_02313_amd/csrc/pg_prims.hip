@@ -89,6 +89,18 @@ void fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s, Prof *prof) {
             dim3(kBlock), 0, s, p, v, n);
 }
 
+__global__ void k_sum_dist(int32_t *ctr, int dist, int dst) {
+  int32_t v = ctr[dist + threadIdx.x * kDistStride];
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_down(v, o, kWave);
+  if (threadIdx.x == 0) ctr[dst] += v;
+}
+
+void sum_dist(int32_t *ctr, int dist, int dst, hipStream_t s, Prof *prof) {
+  static_assert(kDistSlots == kWave, "one lane per slot");
+  PG_LAUNCH(prof, K_OTHER, 0.0, k_sum_dist, dim3(1), dim3(kDistSlots), 0, s,
+            ctr, dist, dst);
+}
+
 // ---------------------------------------------------------------------------
 // exclusive scan: reduce tiles, scan the tile sums (recursively), then scan
 // each tile with its offset
@@ -246,7 +258,8 @@ __global__ __launch_bounds__(kBlock) void k_rs_upsweep(const uint32_t *keys,
 }
 
 __global__ __launch_bounds__(kBlock) void k_rs_downsweep(
-    const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout,
+    const uint32_t *kin, const uint32_t *__restrict__ vin, uint32_t *kout,
+    uint32_t *vout,
     int64_t n, int shift, const uint32_t *tile_off, int64_t tiles,
     const int32_t *gate) {
   if (gate && *gate) return;
@@ -265,7 +278,8 @@ __global__ __launch_bounds__(kBlock) void k_rs_downsweep(
     const int64_t i = base + (int64_t)r * kBlock + tid;
     const bool valid = i < n;
     uint32_t k = valid ? kin[i] : 0u;
-    uint32_t v = valid ? vin[i] : 0u;
+    // without an input value array the value is the input position
+    uint32_t v = valid ? (vin ? vin[i] : (uint32_t)i) : 0u;
     const uint32_t d = (k >> shift) & 255u;
     uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -297,12 +311,17 @@ __global__ __launch_bounds__(kBlock) void k_rs_downsweep(
 
 int radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
                int64_t n, int bits, uint32_t *tile_cnt, void *scan_tmp,
-               hipStream_t s, Prof *prof, const int32_t *gate) {
+               hipStream_t s, Prof *prof, const int32_t *gate,
+               bool index_values) {
   if (n <= 0 || bits <= 0) return 0;
   const int64_t tiles = radix_tiles(n);
   int cur = 0;
   for (int shift = 0; shift < bits; shift += 8) {
-    uint32_t *ki = cur ? k1 : k0, *vi = cur ? v1 : v0;
+    uint32_t *ki = cur ? k1 : k0;
+    // with index_values the first pass takes each key's input position as
+    // its value instead of reading v0
+    const uint32_t *vi =
+        cur ? v1 : ((index_values && shift == 0) ? nullptr : v0);
     uint32_t *ko = cur ? k0 : k1, *vo = cur ? v0 : v1;
     // algorithmic bytes: keys read (4 B) and 1 KiB of counts per tile;
     // then keys and values read and written (16 B)

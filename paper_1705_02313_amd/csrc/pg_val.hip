@@ -42,13 +42,6 @@ __device__ __forceinline__ void st_relaxed(int32_t *p, int32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// wave-aggregated counter increment: one atomic per wave
-__device__ __forceinline__ void count_wave(int32_t *ctr, bool pred) {
-  uint64_t b = __ballot(pred);
-  if (b && (threadIdx.x & (kWave - 1)) == (unsigned)(__ffsll((long long)b) - 1))
-    atomicAdd(ctr, (int)__popcll(b));
-}
-
 constexpr int kStride = 32;        // splitter stride at every level
 
 // size of level k of the sublist ranking for an Euler list of L elements
@@ -65,11 +58,12 @@ __device__ __host__ __forceinline__ int64_t level_size(int64_t L, int k) {
 // between v and cand[v] has a smaller priority than v.  Returns ng(v), or -1
 // with *u holding the candidate when the step budget runs out.
 __device__ __forceinline__ int32_t ng_walk(int32_t N, const int2 *sp,
+                                           const int32_t *pri,
                                            const int32_t *ng,
                                            const int32_t *cand, int32_t v,
                                            int32_t *u_io, int steps,
                                            int32_t *ctr) {
-  const int pv = sp[v].y;
+  const int pv = pri[v];
   int32_t u = *u_io;
   for (int s = 0; s < steps; ++s) {
     if (u == N) return N;
@@ -79,8 +73,7 @@ __device__ __forceinline__ int32_t ng_walk(int32_t N, const int2 *sp,
       if (pv & 1) atomicOr(&ctr[C_ERR], ERR_INADMISSIBLE);
       return N + 1;
     }
-    const int2 su = sp[u];
-    if (su.y > pv) return u;
+    if (pri[u] > pv) return u;
     const int32_t r = ld_relaxed(&ng[u]);
     if (r >= 0) {
       if (r >= N) return r;  // nothing larger than u (hence v) after u
@@ -88,28 +81,61 @@ __device__ __forceinline__ int32_t ng_walk(int32_t N, const int2 *sp,
       continue;
     }
     const int32_t c = ld_relaxed(&cand[u]);
-    u = (c >= 0) ? c : su.x;
+    u = (c >= 0) ? c : sp[u].x;
   }
   *u_io = u;
   return -1;
 }
 
-// Full pass.  Also clears this valuation's root-walk state.
+// Full pass: a plain walk along the play (one 8-byte load per step, no
+// reads of other threads' results); vertices that run out of steps go to the
+// worklist.  Also clears this valuation's root-walk state.
 __global__ __launch_bounds__(kBlock) void k_ng_full(
-    int32_t N, const int2 *__restrict__ sp, int32_t *ng, int32_t *cand,
-    int32_t *wl_out, int32_t *ctr, int slot_out, int steps, uint8_t *rs,
-    int32_t *rcand) {
+    int32_t N, const int2 *__restrict__ sp, const int32_t *__restrict__ pri,
+    int32_t *ng, int32_t *cand, int32_t *wl_out, int32_t *ctr, int slot_out,
+    int steps, uint8_t *rs, int32_t *rcand) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
   const int32_t v = (int32_t)i;
   rs[v] = 0;
   rcand[v] = -1;
-  int32_t u = sp[v].x;
-  const int32_t res = ng_walk(N, sp, ng, cand, v, &u, steps, ctr);
+  // sp[x] = {successor of x, priority of that successor}: the first
+  // comparison needs no gather, each further step one
+  const int pv = pri[v];
+  const int2 me = sp[v];
+  int32_t u = me.x;
+  int pu = me.y;
+  int32_t res = -1;
+  // Brent's cycle detection: a walk that meets its checkpoint again circles
+  // a cycle without v whose priorities are all below v's, so nothing after
+  // v is larger (ng = TOP)
+  int32_t mark = v;
+  int lam = 1, power = 1;
+  for (int s = 0; s < steps; ++s) {
+    if (u == N) { res = N; break; }
+    if (u == v) {
+      // back at v: v has the largest priority of its cycle, which must be
+      // even for an admissible sigma (section 3)
+      if (pv & 1) atomicOr(&ctr[C_ERR], ERR_INADMISSIBLE);
+      res = N + 1;
+      break;
+    }
+    if (pu > pv) { res = u; break; }
+    if (u == mark) { res = N + 1; break; }
+    if (lam == power) {
+      mark = u;
+      power <<= 1;
+      lam = 0;
+    }
+    ++lam;
+    const int2 su = sp[u];
+    u = su.x;
+    pu = su.y;
+  }
   if (res >= 0) {
-    st_relaxed(&ng[v], res);
+    ng[v] = res;
   } else {
-    st_relaxed(&cand[v], u);
+    cand[v] = u;
     wl_out[atomicAdd(&ctr[slot_out], 1)] = v;
   }
 }
@@ -118,16 +144,16 @@ __global__ __launch_bounds__(kBlock) void k_ng_full(
 // unresolved vertices jump over other candidates (pointer jumping).  A fixed
 // grid strides over the list, whose length is read on the device.
 __global__ __launch_bounds__(kBlock) void k_ng_round(
-    int32_t N, const int2 *__restrict__ sp, int32_t *ng, int32_t *cand,
-    const int32_t *wl_in, int32_t *wl_out, int32_t *ctr, int slot_in,
-    int slot_out, int last, int steps) {
+    int32_t N, const int2 *__restrict__ sp, const int32_t *__restrict__ pri,
+    int32_t *ng, int32_t *cand, const int32_t *wl_in, int32_t *wl_out,
+    int32_t *ctr, int slot_in, int slot_out, int last, int steps) {
   const int32_t cnt = ctr[slot_in];
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
        i += stride) {
     const int32_t v = wl_in[i];
     int32_t u = ld_relaxed(&cand[v]);
-    const int32_t res = ng_walk(N, sp, ng, cand, v, &u, steps, ctr);
+    const int32_t res = ng_walk(N, sp, pri, ng, cand, v, &u, steps, ctr);
     if (res >= 0) {
       st_relaxed(&ng[v], res);
     } else {
@@ -169,46 +195,57 @@ __device__ __forceinline__ int root_walk(int32_t N, const int32_t *ng,
   return 0;
 }
 
-// Full pass.  Also clears the other ng/cand pair (used by the next
-// valuation) and this valuation's Euler-list per-vertex state.
+// Full pass: a plain walk along the ng chain (one load per step).  Writes
+// the vertex's sort key at its signed-priority position (its parent when
+// finite, N + 1 when top).  Also clears the other ng/cand pair (used by the
+// next valuation) and this valuation's Euler-list per-vertex state.
 __global__ __launch_bounds__(kBlock) void k_root_full(
     int32_t N, const int32_t *ng, uint8_t *rs, int32_t *rcand, int32_t *key,
     int32_t *wl_out, int32_t *ctr, int slot_out, int steps, int32_t *ng_next,
-    int32_t *cand_next, int32_t *first, uint8_t *haseven) {
+    int32_t *cand_next, uint32_t *fh, const int32_t *__restrict__ rvpos,
+    uint32_t *sk) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0) {
-    first[N] = -1;
-    haseven[N] = 0;
-  }
+  if (i == 0) fh[N] = 0u;
   int fate = 0;
   if (i < N) {
     const int32_t v = (int32_t)i;
     ng_next[v] = -1;
     cand_next[v] = -1;
-    first[v] = -1;
-    haseven[v] = 0;
-    int32_t r = ld_relaxed(&ng[v]);
-    if (r < 0) r = -2;
-    fate = root_walk(N, ng, rs, rcand, v, &r, steps);
+    fh[v] = 0u;
+    const int32_t p = ng[v];
+    int32_t r = p;
+    if (r < 0) {
+      r = -2;                       // ng(v) itself is not resolved yet
+    } else {
+      for (int s = 0; s < steps; ++s) {
+        if (r >= N) break;
+        const int32_t nx = ng[r];
+        if (nx < 0) break;          // ng of r not resolved yet
+        r = nx;
+      }
+    }
+    if (r == N) fate = 1;
+    else if (r == N + 1) fate = 2;
     if (fate) {
-      __hip_atomic_store(&rs[v], (uint8_t)fate, __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
+      rs[v] = (uint8_t)fate;
+      sk[rvpos[v]] = fate == 1 ? (uint32_t)p : (uint32_t)(N + 1);
       if (fate == 2) key[v] = PG_KEY_TOP;
     } else {
-      st_relaxed(&rcand[v], r);
+      rcand[v] = r;
       wl_out[atomicAdd(&ctr[slot_out], 1)] = v;
     }
   }
-  count_wave(&ctr[C_NFIN], fate == 1);
+  count_block(&ctr[C_DIST_NF], fate == 1);
 }
 
 __global__ __launch_bounds__(kBlock) void k_root_round(
     int32_t N, const int32_t *ng, uint8_t *rs, int32_t *rcand, int32_t *key,
     const int32_t *wl_in, int32_t *wl_out, int32_t *ctr, int slot_in,
-    int slot_out, int last, int steps) {
+    int slot_out, int last, int steps, const int32_t *__restrict__ rvpos,
+    uint32_t *sk) {
   const int32_t cnt = ctr[slot_in];
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  // uniform trip count so every lane reaches the wave-wide count
+  // uniform trip count so that every thread reaches the block-wide count
   for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < cnt;
        base += stride) {
     const int64_t i = base + threadIdx.x;
@@ -220,6 +257,7 @@ __global__ __launch_bounds__(kBlock) void k_root_round(
       if (fate) {
         __hip_atomic_store(&rs[v], (uint8_t)fate, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
+        sk[rvpos[v]] = fate == 1 ? (uint32_t)ng[v] : (uint32_t)(N + 1);
         if (fate == 2) key[v] = PG_KEY_TOP;
       } else {
         st_relaxed(&rcand[v], r);
@@ -227,22 +265,8 @@ __global__ __launch_bounds__(kBlock) void k_root_round(
         if (last) atomicOr(&ctr[C_ABORT], 1);
       }
     }
-    count_wave(&ctr[C_NFIN], fate == 1);
+    count_block(&ctr[C_DIST_NF], fate == 1);
   }
-}
-
-// sort keys in signed-priority order: the parent for finite vertices, N + 1
-// (after every parent) for top vertices
-__global__ __launch_bounds__(kBlock) void k_sort_keys(
-    int32_t N, const int32_t *__restrict__ perm, const int32_t *__restrict__ ng,
-    const uint8_t *__restrict__ rs, uint32_t *sk, uint32_t *sv,
-    const int32_t *ctr) {
-  if (ctr[C_ABORT]) return;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  const int32_t v = perm[i];
-  sk[i] = (rs[v] == 1) ? (uint32_t)ng[v] : (uint32_t)(N + 1);
-  sv[i] = (uint32_t)i;
 }
 
 // ---------------------------------------------------------------------------
@@ -254,8 +278,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_keys(
 __global__ __launch_bounds__(kBlock) void k_link_info(
     int32_t N, int32_t n_oddpri, const uint32_t *__restrict__ skS,
     const uint32_t *__restrict__ svS, const int32_t *__restrict__ perm,
-    int32_t *kids, int32_t *pos, int32_t *first, uint8_t *haseven,
-    int32_t *ctr) {
+    int32_t *kids, int32_t *pos, uint32_t *fh, int32_t *ctr) {
   if (ctr[C_ABORT]) return;
   const int32_t nF = ctr[C_NFIN];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -269,22 +292,26 @@ __global__ __launch_bounds__(kBlock) void k_link_info(
   const int32_t c = perm[r];
   kids[i] = c;
   pos[c] = (int32_t)i;
-  if (i == 0 || skS[i - 1] != p) first[p] = (int32_t)i;
-  if (i == nF - 1 || skS[i + 1] != p) haseven[p] = (r >= (uint32_t)n_oddpri);
+  // fh[p]: first child position + 1 and, in bit 31, whether the last child
+  // has an even priority; the two parts come from different threads
+  if (i == 0 || skS[i - 1] != p) atomicOr(&fh[p], (uint32_t)(i + 1));
+  if ((i == nF - 1 || skS[i + 1] != p) && r >= (uint32_t)n_oddpri)
+    atomicOr(&fh[p], 0x80000000u);
 }
 
 __global__ __launch_bounds__(kBlock) void k_link_build(
     int32_t N, int32_t n_oddpri, const uint32_t *__restrict__ skS,
     const uint32_t *__restrict__ svS, const int32_t *__restrict__ kids,
-    const int32_t *__restrict__ pos, const int32_t *__restrict__ first,
-    const uint8_t *__restrict__ haseven, int2 *elem, const int32_t *ctr) {
+    const int32_t *__restrict__ pos, const uint32_t *__restrict__ fh,
+    int2 *elem, const int32_t *ctr) {
   if (ctr[C_ABORT] || (ctr[C_ERR] & ERR_RANKCOUNT)) return;
   const int32_t nF = ctr[C_NFIN];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) {
-    const int32_t f = first[N];
-    elem[0] = make_int2(f >= 0 ? 2 * f + 2 : 1, N);
-    const int w = (f < 0 || !haseven[N]) ? 1 : 0;
+    const uint32_t f = fh[N];
+    const int32_t first = (int32_t)(f & 0x7fffffffu) - 1;
+    elem[0] = make_int2(first >= 0 ? 2 * first + 2 : 1, N);
+    const int w = (first < 0 || !(f >> 31)) ? 1 : 0;
     elem[1] = make_int2(-1, N | (w << 31));
   }
   if (i >= nF) return;
@@ -293,7 +320,8 @@ __global__ __launch_bounds__(kBlock) void k_link_build(
   const bool ev = svS[i] >= (uint32_t)n_oddpri;
   const bool seg_start = (i == 0) || (skS[i - 1] != p);
   const bool seg_end = (i == nF - 1) || (skS[i + 1] != p);
-  const int32_t fc = first[c];
+  const uint32_t f = fh[c];
+  const int32_t fc = (int32_t)(f & 0x7fffffffu) - 1;
   // enter c: first child of c, or straight to leaving c.  It carries the
   // parent's in-order point when c is the parent's first even child.
   const bool wd = ev && (seg_start || svS[i - 1] < (uint32_t)n_oddpri);
@@ -302,7 +330,7 @@ __global__ __launch_bounds__(kBlock) void k_link_build(
                 (int32_t)p | ((int32_t)wd << 31));
   // leave c: next sibling, else leave the parent.  It carries c's own
   // in-order point when c has no even child.
-  const bool wu = (fc < 0) || !haseven[c];
+  const bool wu = (fc < 0) || !(f >> 31);
   int32_t nx;
   if (!seg_end) nx = (int32_t)(2 * i + 4);
   else nx = (p == (uint32_t)N) ? 1 : 2 * pos[p] + 3;
@@ -466,58 +494,79 @@ __global__ __launch_bounds__(kBlock) void k_lr_emit1(
 // ---------------------------------------------------------------------------
 // switching rules
 // ---------------------------------------------------------------------------
+// Each thread takes one vertex of the player from a compacted list and reads
+// its row four targets at a time, so that four key gathers are in flight.
+constexpr int kRowBatch = 4;
+
 // All_Odd (section 4): the first successor of least key, if strictly below
-// the current choice.  All decisions read the same valuation.
+// the current choice.  All decisions read the same valuation.  A vertex that
+// switches also records its new successor's priority in the play graph.
 __global__ __launch_bounds__(kBlock) void k_odd_switch(
-    int32_t N, const int64_t *__restrict__ off, const int32_t *__restrict__ tgt,
-    const uint8_t *__restrict__ owner, const int32_t *__restrict__ key,
-    int2 *sp, int32_t *ctr) {
+    int32_t N, int64_t count, const int32_t *__restrict__ ids,
+    const int64_t *__restrict__ off, const int32_t *__restrict__ tgt,
+    const int32_t *__restrict__ key, const int32_t *__restrict__ pri, int2 *sp,
+    int32_t *ctr) {
   if (ctr[C_ABORT]) return;
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool sw = false;
-  if (v < N && owner[v] == 1) {
-    int64_t e = off[v];
-    const int64_t end = off[v + 1];
-    int32_t best = tgt[e];
-    int32_t kb = key[best];
-    for (++e; e < end; ++e) {
-      const int32_t u = tgt[e];
-      const int32_t ku = key[u];
-      if (ku < kb) { kb = ku; best = u; }
-    }
+  if (t < count) {
+    const int32_t v = ids[t];
+    const int64_t e0 = off[v], e1 = off[v + 1];
     const int32_t cur = sp[v].x;
-    if (kb < key[cur]) {
-      sp[v].x = best;
+    const int32_t kc = key[cur];
+    int32_t best = -1;
+    int32_t kb = 0;
+    for (int64_t b = e0; b < e1; b += kRowBatch) {
+      int32_t u[kRowBatch], k[kRowBatch];
+#pragma unroll
+      for (int j = 0; j < kRowBatch; ++j) u[j] = (b + j < e1) ? tgt[b + j] : -1;
+#pragma unroll
+      for (int j = 0; j < kRowBatch; ++j) k[j] = (u[j] >= 0) ? key[u[j]] : 0;
+#pragma unroll
+      for (int j = 0; j < kRowBatch; ++j)
+        if (u[j] >= 0 && (best < 0 || k[j] < kb)) { kb = k[j]; best = u[j]; }
+    }
+    if (kb < kc) {
+      sp[v] = make_int2(best, pri[best]);
       sw = true;
     }
   }
-  count_wave(&ctr[C_SWITCH], sw);
+  count_block(&ctr[C_DIST_SW], sw);
 }
 
 // All_Even, greedy all-switches (section 3): options are the sink (first),
 // then the row; the first option of greatest key, if strictly above the
 // current choice.
 __global__ __launch_bounds__(kBlock) void k_even_switch(
-    int32_t N, const int64_t *__restrict__ off, const int32_t *__restrict__ tgt,
-    const uint8_t *__restrict__ owner, const int32_t *__restrict__ key,
-    int2 *sp, int32_t *ctr) {
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t N, int64_t count, const int32_t *__restrict__ ids,
+    const int64_t *__restrict__ off, const int32_t *__restrict__ tgt,
+    const int32_t *__restrict__ key, const int32_t *__restrict__ pri, int2 *sp,
+    int32_t *ctr) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool sw = false;
-  if (v < N && owner[v] == 0) {
+  if (t < count) {
+    const int32_t v = ids[t];
+    const int64_t e0 = off[v], e1 = off[v + 1];
+    const int32_t cur = sp[v].x;
+    const int32_t kc = key[cur];
     int32_t best = N;
     int32_t kb = key[N];
-    for (int64_t e = off[v], end = off[v + 1]; e < end; ++e) {
-      const int32_t u = tgt[e];
-      const int32_t ku = key[u];
-      if (ku > kb) { kb = ku; best = u; }
+    for (int64_t b = e0; b < e1; b += kRowBatch) {
+      int32_t u[kRowBatch], k[kRowBatch];
+#pragma unroll
+      for (int j = 0; j < kRowBatch; ++j) u[j] = (b + j < e1) ? tgt[b + j] : -1;
+#pragma unroll
+      for (int j = 0; j < kRowBatch; ++j) k[j] = (u[j] >= 0) ? key[u[j]] : 0;
+#pragma unroll
+      for (int j = 0; j < kRowBatch; ++j)
+        if (u[j] >= 0 && k[j] > kb) { kb = k[j]; best = u[j]; }
     }
-    const int32_t cur = sp[v].x;
-    if (kb > key[cur]) {
-      sp[v].x = best;
+    if (kb > kc) {
+      sp[v] = make_int2(best, best == N ? 2147483647 : pri[best]);
       sw = true;
     }
   }
-  count_wave(&ctr[C_SWITCH], sw);
+  count_block(&ctr[C_DIST_SW], sw);
 }
 
 }  // namespace pgk
@@ -527,11 +576,14 @@ __global__ __launch_bounds__(kBlock) void k_even_switch(
 // ===========================================================================
 namespace pgk {
 
-constexpr int kWalkSteps = 256;   // walk budget of one pass or round
-constexpr int kFastRounds = 2;    // rounds enqueued without looking back
+// A wave lasts as long as its longest walk, so the full passes stop early and
+// leave long walks to compact worklist rounds (which also take shortcuts).
+constexpr int kFullSteps = 8;     // plain-walk budget of the full passes
+constexpr int kWalkSteps = 64;    // shortcut-walk budget of one round
+constexpr int kFastRounds = 3;    // rounds enqueued without looking back
 constexpr int kMaxRounds = 64;    // rounds of the careful path before failing
 constexpr int kRoundBlocks = 1024;
-constexpr int kPerThread1 = 4;    // level-1 sublists per thread
+constexpr int kPerThread1 = 1;    // level-1 sublists per thread
 
 static pg_status read_ctr(pg_game *g, hipStream_t s) {
   PG_HIP(hipMemcpyAsync(g->hctr, g->ctr, sizeof(int32_t) * C_COUNT,
@@ -564,29 +616,35 @@ static void enqueue_walks(pg_game *g, hipStream_t s) {
   Prof *pf = &g->prof;
   int32_t *ng = g->ngp[g->par], *cand = g->candp[g->par];
   int32_t *ngn = g->ngp[g->par ^ 1], *candn = g->candp[g->par ^ 1];
-  fill_i32(g->ctr, 0, C_COUNT, s, pf);
-  PG_LAUNCH(pf, K_NG_WALK, 22.0 * N, k_ng_full, dim3(grid_for(N)),
-            dim3(kBlock), 0, s, N, g->sp, ng, cand, g->wl0, g->ctr,
-            (int)C_NGW, kWalkSteps, g->rs, g->rcand);
+  fill_i32(g->ctr, 0, C_TOTAL, s, pf);
+  // own record 8, first successor record 8, result 4; state resets 5
+  PG_LAUNCH(pf, K_NG_WALK, 25.0 * N, k_ng_full, dim3(grid_for(N)),
+            dim3(kBlock), 0, s, N, g->sp, g->pri, ng, cand, g->wl0, g->ctr,
+            (int)C_NGW, kFullSteps, g->rs, g->rcand);
   int32_t *wa = g->wl0, *wb = g->wl1;
   for (int r = 1; r <= kFastRounds; ++r) {
     PG_LAUNCH(pf, K_NG_ROUND, 0.0, k_ng_round, dim3(kRoundBlocks),
-              dim3(kBlock), 0, s, N, g->sp, ng, cand, (const int32_t *)wa, wb,
-              g->ctr, (int)(C_NGW + r - 1), (int)(C_NGW + r),
+              dim3(kBlock), 0, s, N, g->sp, g->pri, ng, cand,
+              (const int32_t *)wa, wb, g->ctr, (int)(C_NGW + r - 1),
+              (int)(C_NGW + r),
               (int)(r == kFastRounds), kWalkSteps);
     int32_t *t = wa; wa = wb; wb = t;
   }
-  PG_LAUNCH(pf, K_ROOT_WALK, 22.0 * N, k_root_full, dim3(grid_for(N)),
+  // own ng 4, parent's ng 4, rvpos 4, sort key 4, rs 1; resets 12
+  PG_LAUNCH(pf, K_ROOT_WALK, 29.0 * N, k_root_full, dim3(grid_for(N)),
             dim3(kBlock), 0, s, N, ng, g->rs, g->rcand, g->key, g->wl0,
-            g->ctr, (int)C_RTW, kWalkSteps, ngn, candn, g->first, g->haseven);
+            g->ctr, (int)C_RTW, kFullSteps, ngn, candn, g->fh, g->rvpos,
+            g->sk0);
   wa = g->wl0; wb = g->wl1;
   for (int r = 1; r <= kFastRounds; ++r) {
     PG_LAUNCH(pf, K_ROOT_ROUND, 0.0, k_root_round, dim3(kRoundBlocks),
               dim3(kBlock), 0, s, N, ng, g->rs, g->rcand, g->key,
               (const int32_t *)wa, wb, g->ctr, (int)(C_RTW + r - 1),
-              (int)(C_RTW + r), (int)(r == kFastRounds), kWalkSteps);
+              (int)(C_RTW + r), (int)(r == kFastRounds), kWalkSteps,
+              g->rvpos, g->sk0);
     int32_t *t = wa; wa = wb; wb = t;
   }
+  sum_dist(g->ctr, C_DIST_NF, C_NFIN, s, pf);
 }
 
 // ng and root phases looping on the host until every vertex is resolved.
@@ -597,10 +655,10 @@ static pg_status careful_walks(pg_game *g, hipStream_t s) {
   int32_t *ngn = g->ngp[g->par ^ 1], *candn = g->candp[g->par ^ 1];
   fill_i32(ng, -1, N, s, pf);
   fill_i32(cand, -1, N, s, pf);
-  fill_i32(g->ctr, 0, C_COUNT, s, pf);
-  PG_LAUNCH(pf, K_NG_WALK, 22.0 * N, k_ng_full, dim3(grid_for(N)),
-            dim3(kBlock), 0, s, N, g->sp, ng, cand, g->wl0, g->ctr, (int)C_HA,
-            kWalkSteps, g->rs, g->rcand);
+  fill_i32(g->ctr, 0, C_TOTAL, s, pf);
+  PG_LAUNCH(pf, K_NG_WALK, 25.0 * N, k_ng_full, dim3(grid_for(N)),
+            dim3(kBlock), 0, s, N, g->sp, g->pri, ng, cand, g->wl0, g->ctr,
+            (int)C_HA, kFullSteps, g->rs, g->rcand);
   pg_status st = read_ctr(g, s);
   if (st != PG_OK) return st;
   int32_t *wa = g->wl0, *wb = g->wl1;
@@ -610,8 +668,8 @@ static pg_status careful_walks(pg_game *g, hipStream_t s) {
       return pg_fail(PG_EINTERNAL, "ng resolution did not converge");
     fill_i32(g->ctr + out, 0, 1, s, pf);
     PG_LAUNCH(pf, K_NG_ROUND, 0.0, k_ng_round, dim3(kRoundBlocks),
-              dim3(kBlock), 0, s, N, g->sp, ng, cand, (const int32_t *)wa, wb,
-              g->ctr, in, out, 0, kWalkSteps);
+              dim3(kBlock), 0, s, N, g->sp, g->pri, ng, cand,
+              (const int32_t *)wa, wb, g->ctr, in, out, 0, kWalkSteps);
     st = read_ctr(g, s);
     if (st != PG_OK) return st;
     int32_t *t = wa; wa = wb; wb = t;
@@ -619,9 +677,11 @@ static pg_status careful_walks(pg_game *g, hipStream_t s) {
   }
   fill_i32(g->ctr + C_HA, 0, 2, s, pf);
   fill_i32(g->ctr + C_NFIN, 0, 1, s, pf);
-  PG_LAUNCH(pf, K_ROOT_WALK, 22.0 * N, k_root_full, dim3(grid_for(N)),
+  fill_i32(g->ctr + C_DIST_NF, 0, kDistSlots * kDistStride, s, pf);
+  PG_LAUNCH(pf, K_ROOT_WALK, 29.0 * N, k_root_full, dim3(grid_for(N)),
             dim3(kBlock), 0, s, N, ng, g->rs, g->rcand, g->key, g->wl0,
-            g->ctr, (int)C_HA, kWalkSteps, ngn, candn, g->first, g->haseven);
+            g->ctr, (int)C_HA, kFullSteps, ngn, candn, g->fh, g->rvpos,
+            g->sk0);
   st = read_ctr(g, s);
   if (st != PG_OK) return st;
   wa = g->wl0; wb = g->wl1;
@@ -632,12 +692,14 @@ static pg_status careful_walks(pg_game *g, hipStream_t s) {
     fill_i32(g->ctr + out, 0, 1, s, pf);
     PG_LAUNCH(pf, K_ROOT_ROUND, 0.0, k_root_round, dim3(kRoundBlocks),
               dim3(kBlock), 0, s, N, ng, g->rs, g->rcand, g->key,
-              (const int32_t *)wa, wb, g->ctr, in, out, 0, kWalkSteps);
+              (const int32_t *)wa, wb, g->ctr, in, out, 0, kWalkSteps,
+              g->rvpos, g->sk0);
     st = read_ctr(g, s);
     if (st != PG_OK) return st;
     int32_t *t = wa; wa = wb; wb = t;
     int ti = in; in = out; out = ti;
   }
+  sum_dist(g->ctr, C_DIST_NF, C_NFIN, s, pf);
   fill_i32(g->ctr + C_ABORT, 0, 1, s, pf);
   return PG_OK;
 }
@@ -646,23 +708,23 @@ static pg_status careful_walks(pg_game *g, hipStream_t s) {
 static void enqueue_rank(pg_game *g, hipStream_t s) {
   const int32_t N = (int32_t)g->n_aug;
   Prof *pf = &g->prof;
-  const int32_t *ng = g->ngp[g->par];
   const int32_t *gate = g->ctr + C_ABORT;
-  PG_LAUNCH(pf, K_SORT_KEYS, 17.0 * N, k_sort_keys, dim3(grid_for(N)),
-            dim3(kBlock), 0, s, N, g->perm, ng, g->rs, g->sk0, g->sv0,
-            g->ctr);
+  // the root walks wrote the keys in signed-priority order; the values are
+  // the positions in that order
   const int which = radix_sort(g->sk0, g->sv0, g->sk1, g->sv1, N,
                                g->sort_bits, g->tile_cnt, g->scan_tmp, s, pf,
-                               gate);
+                               gate, true);
   const uint32_t *skS = which ? g->sk1 : g->sk0;
   const uint32_t *svS = which ? g->sv1 : g->sv0;
   // the finite count is only known on the device: size grids for N
-  PG_LAUNCH_NF(pf, K_LINK_INFO, 24.0, k_link_info, dim3(grid_for(N)),
-            dim3(kBlock), 0, s, N, g->n_oddpri, skS, svS, g->perm, g->kids,
-            g->pos, g->first, g->haseven, g->ctr);
-  PG_LAUNCH_NF(pf, K_LINK_BUILD, 41.0, k_link_build, dim3(grid_for(N)),
-            dim3(kBlock), 0, s, N, g->n_oddpri, skS, svS, g->kids, g->pos,
-            g->first, g->haseven, g->elem, g->ctr);
+  // keys, values, perm 12; kids, pos 8; fh at segment ends
+  PG_LAUNCH_NF(pf, K_LINK_INFO, 22.0, k_link_info, dim3(grid_for(N)),
+               dim3(kBlock), 0, s, N, g->n_oddpri, skS, svS, g->perm,
+               g->kids, g->pos, g->fh, g->ctr);
+  // keys, values, kids 12; fh 4; two elements 16; pos at segment ends
+  PG_LAUNCH_NF(pf, K_LINK_BUILD, 34.0, k_link_build, dim3(grid_for(N)),
+               dim3(kBlock), 0, s, N, g->n_oddpri, skS, svS, g->kids,
+               g->pos, g->fh, g->elem, g->ctr);
   const int nl = g->nlevels;
   const int64_t Lmax = 2 * (int64_t)N + 2;
   const int64_t ns1 = level_size(Lmax, 1);
@@ -701,17 +763,23 @@ static void enqueue_switch(pg_game *g, bool odd, hipStream_t s) {
   // offsets (8 B per row) and owners for every vertex; for the player's own
   // rows the targets and the key of each target (8 B per edge), the current
   // choice and its key (12 B per vertex)
-  if (odd)
-    PG_LAUNCH(pf, K_ODD_SWITCH,
-              9.0 * N + 8.0 + 8.0 * g->m_odd + 12.0 * g->n_odd, k_odd_switch,
-              dim3(grid_for(N)), dim3(kBlock), 0, s, N, g->off, g->tgt,
-              g->owner, g->key, g->sp, g->ctr);
-  else
-    PG_LAUNCH(pf, K_EVEN_SWITCH,
-              9.0 * N + 8.0 + 8.0 * (g->m_aug - g->m_odd) +
-                  12.0 * (N - g->n_odd),
-              k_even_switch, dim3(grid_for(N)), dim3(kBlock), 0, s, N, g->off,
-              g->tgt, g->owner, g->key, g->sp, g->ctr);
+  fill_i32(g->ctr + C_DIST_SW, 0, kDistSlots * kDistStride, s, pf);
+  // per vertex: id 4, two offsets 16, current choice 8 (read and write
+  // counted once) and its key 4 -> 28; per edge: target 4 and its key 4
+  if (odd) {
+    const int64_t cnt = g->n_odd;
+    if (cnt > 0)
+      PG_LAUNCH(pf, K_ODD_SWITCH, 28.0 * cnt + 8.0 * g->m_odd, k_odd_switch,
+                dim3(grid_for(cnt)), dim3(kBlock), 0, s, N, cnt, g->odd_ids,
+                g->off, g->tgt, g->key, g->pri, g->sp, g->ctr);
+  } else {
+    const int64_t cnt = N - g->n_odd;
+    if (cnt > 0)
+      PG_LAUNCH(pf, K_EVEN_SWITCH, 28.0 * cnt + 8.0 * (g->m_aug - g->m_odd),
+                k_even_switch, dim3(grid_for(cnt)), dim3(kBlock), 0, s, N, cnt,
+                g->even_ids, g->off, g->tgt, g->key, g->pri, g->sp, g->ctr);
+  }
+  sum_dist(g->ctr, C_DIST_SW, C_SWITCH, s, pf);
 }
 
 static pg_status check_ctr(pg_game *g) {

@@ -28,7 +28,9 @@ STATUS_NAMES = {0: "PG_OK", 1: "PG_EINVAL", 2: "PG_ENOMEM", 3: "PG_EDEVICE",
 EXPORTS = ["pg_load_csr", "pg_game_info", "pg_export_game",
            "pg_initial_strategies", "pg_valuation", "pg_best_response",
            "pg_solve", "pg_profile_enable", "pg_profile_kinds",
-           "pg_profile_read", "pg_free", "pg_last_error"]
+           "pg_profile_read", "pg_batch_create", "pg_batch_submit",
+           "pg_batch_step", "pg_batch_poll", "pg_batch_info", "pg_batch_free",
+           "pg_free", "pg_last_error"]
 
 
 class PgError(RuntimeError):
@@ -90,6 +92,16 @@ def lib() -> ctypes.CDLL:
                                       ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(I64),
                                       ctypes.POINTER(ctypes.c_double)]
+        L.pg_batch_create.argtypes = [I64, I64, I32, P, ctypes.POINTER(P)]
+        L.pg_batch_submit.argtypes = [P, I64, I64, P, P, P, P, U32,
+                                      ctypes.POINTER(I64)]
+        L.pg_batch_step.argtypes = [P] + [ctypes.POINTER(I32)] * 3
+        L.pg_batch_poll.argtypes = [P, I64, ctypes.POINTER(I32), P, P, P,
+                                    ctypes.POINTER(Stats), U32]
+        L.pg_batch_info.argtypes = [P, ctypes.POINTER(I32),
+                                    ctypes.POINTER(I32), ctypes.POINTER(I64),
+                                    ctypes.POINTER(I64)]
+        L.pg_batch_free.argtypes = [P]
         L.pg_free.argtypes = [P]
         L.pg_last_error.argtypes = []
         L.pg_last_error.restype = ctypes.c_char_p
@@ -276,6 +288,101 @@ class Game:
     def free(self):
         if getattr(self, "_h", None):
             lib().pg_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.free()
+
+
+class Batch:
+    """Many games solved together on the device (see pg_batch_* in pg.h)."""
+
+    def __init__(self, max_vertices: int, max_edges: int,
+                 max_games: int = 65536, stream=None):
+        h = ctypes.c_void_p()
+        _check(lib().pg_batch_create(max_vertices, max_edges, max_games,
+                                     stream, ctypes.byref(h)))
+        self._h = h
+        self._sizes = {}
+
+    def submit(self, g: dict, device: bool = False) -> int:
+        """Queues a game (dict as produced by synth); returns its ticket."""
+        if device:
+            import torch
+            arr = {k: torch.from_numpy(np.ascontiguousarray(g[k])).cuda()
+                   for k in ("offsets", "targets", "owner", "pri")}
+            off = arr["offsets"]
+            flags = PG_PTR_DEVICE | (PG_OFFSETS_I32 if off.dtype ==
+                                     torch.int32 else 0)
+            arr["offsets"] = off if off.dtype == torch.int32 else \
+                off.to(torch.int64)
+            arr["targets"] = arr["targets"].to(torch.int32)
+            arr["owner"] = arr["owner"].to(torch.uint8)
+            arr["pri"] = arr["pri"].to(torch.int32)
+        else:
+            off = np.ascontiguousarray(g["offsets"])
+            flags = PG_OFFSETS_I32 if off.dtype == np.int32 else 0
+            arr = {"offsets": off if off.dtype == np.int32 else
+                   off.astype(np.int64),
+                   "targets": np.ascontiguousarray(g["targets"], np.int32),
+                   "owner": np.ascontiguousarray(g["owner"], np.uint8),
+                   "pri": np.ascontiguousarray(g["pri"], np.int32)}
+        t = ctypes.c_int64()
+        _check(lib().pg_batch_submit(self._h, int(g["n"]), int(g["m"]),
+                                     _ptr(arr["offsets"]),
+                                     _ptr(arr["targets"]), _ptr(arr["owner"]),
+                                     _ptr(arr["pri"]), flags,
+                                     ctypes.byref(t)))
+        self._sizes[int(t.value)] = int(g["n"])
+        return int(t.value)
+
+    def step(self):
+        """One step; returns (live, queued, finished by this step)."""
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().pg_batch_step(self._h, ctypes.byref(a), ctypes.byref(b),
+                                   ctypes.byref(c)))
+        return int(a.value), int(b.value), int(c.value)
+
+    def poll(self, ticket: int):
+        """None while running; else a dict like Game.solve() (host arrays)."""
+        st = Stats()
+        done = ctypes.c_int32()
+        _check(lib().pg_batch_poll(self._h, ticket, ctypes.byref(done), None,
+                                   None, None, ctypes.byref(st), 0))
+        if not done.value:
+            return None
+        n = self._sizes[ticket]
+        n_aug = int(st.n_aug)
+        winner = np.empty(n, np.uint8)
+        sigma = np.empty(n_aug, np.int32)
+        tau = np.empty(n_aug, np.int32)
+        _check(lib().pg_batch_poll(self._h, ticket, ctypes.byref(done),
+                                   _ptr(winner), _ptr(sigma), _ptr(tau),
+                                   ctypes.byref(st), 0))
+        del self._sizes[ticket]
+        return {"winner": winner, "sigma": sigma, "tau": tau,
+                "stats": st.as_dict()}
+
+    def info(self):
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        c, d = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().pg_batch_info(self._h, ctypes.byref(a), ctypes.byref(b),
+                                   ctypes.byref(c), ctypes.byref(d)))
+        return {"live": int(a.value), "queued": int(b.value),
+                "arena_vertices": int(c.value), "arena_edges": int(d.value)}
+
+    def free(self):
+        if getattr(self, "_h", None):
+            lib().pg_batch_free(self._h)
             self._h = None
 
     def __del__(self):
