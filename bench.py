@@ -15,6 +15,11 @@ Workloads (seeded, synthetic; see paper_1705_02313_amd/synth.py):
   c1  random game, n = 1,000,000, out-degree U[2,10]
   c3  long-chain game, n = 8,000,000
   c0  random game, n = 1,000, out-degree U[2,5]
+  c4  batched/served mix: 1,024 random games, n log-uniform in [1e3, 2e5],
+      out-degree U[2,8]; games/s one at a time (pg_load_csr + pg_solve each),
+      batched with every game present at the start (the calibration rate mu),
+      and served as a Poisson stream at 1.5 mu under an arena budget of a
+      quarter of the mix's modified vertices (latency p50/p99)
 
 Printed: one JSON line with the driver's fields plus "roofline" (the kernel
 that takes the most time, its algorithmic bytes over its event-timed
@@ -42,6 +47,8 @@ WORKLOADS = {
     "c1": ("random parity game n=1000000 deg U[2,10]", 1),
     "c2": ("random parity game n=10000000 deg U[2,5] int64 offsets", 2),
     "c3": ("long-chain parity game n=8000000", 3),
+    "c4": ("1024 random parity games, n log-uniform [1e3, 2e5], deg U[2,8]",
+           4),
 }
 
 
@@ -88,6 +95,91 @@ def _host_cpu() -> str:
     return "unknown"
 
 
+def bench_mix(args) -> dict:
+    """The batched/served workload; see the module docstring."""
+    import torch
+    from paper_1705_02313_amd import synth
+    from paper_1705_02313_amd.pg import Game
+    from paper_1705_02313_amd.serve import poisson_arrivals, serve
+
+    t0 = time.perf_counter()
+    games = synth.mixed_batch(args.mix_games, 4000)
+    log(f"generated {len(games)} games in {time.perf_counter() - t0:.1f}s, "
+        f"sum n = {sum(g['n'] for g in games)}")
+    torch.cuda.set_device(0)
+    # one game at a time
+    solo = []
+    t0 = time.perf_counter()
+    n_aug_total = m_aug_total = 0
+    for g in games:
+        with Game.from_dict(g) as d:
+            r = d.solve()
+            n_aug_total += d.n_aug
+            m_aug_total += d.m_aug
+        solo.append(r)
+    t_solo = time.perf_counter() - t0
+    log(f"one at a time: {t_solo:.2f}s, {len(games) / t_solo:.1f} games/s")
+
+    def same(res) -> bool:
+        for i, r in res["results"].items():
+            a = solo[i]
+            if not (np.array_equal(a["winner"], r["winner"]) and
+                    np.array_equal(a["sigma"], r["sigma"]) and
+                    np.array_equal(a["tau"], r["tau"]) and
+                    a["stats"]["n_valuations"] == r["stats"]["n_valuations"]
+                    and a["stats"]["n_major"] == r["stats"]["n_major"]):
+                return False
+        return len(res["results"]) == len(games)
+
+    cap_v, cap_e = n_aug_total + 1, m_aug_total + 1
+    # calibration: every game present at t = 0
+    zeros = np.zeros(len(games))
+    rb = serve(games, zeros, cap_v, cap_e)
+    mu = len(games) / rb["makespan"]
+    log(f"batched (all at t=0): {rb['makespan']:.2f}s, {mu:.1f} games/s, "
+        f"{rb['steps']} steps")
+    # served: Poisson stream at 1.5 mu, arena budget a quarter of the mix
+    arr = poisson_arrivals(len(games), 1.5 * mu, 4242)
+    budget_v = max(cap_v // 4, max(int(r["stats"]["n_aug"]) for r in solo) + 1)
+    budget_e = max(cap_e // 4, max(int(r["stats"]["m_aug"]) for r in solo) + 1)
+    rs = serve(games, arr, budget_v, budget_e)
+    lat = rs["latency"]
+    served = len(games) / rs["makespan"]
+    log(f"served (Poisson 1.5 mu, quarter arena): {rs['makespan']:.2f}s, "
+        f"{served:.1f} games/s, p50 {np.percentile(lat, 50) * 1e3:.1f} ms, "
+        f"p99 {np.percentile(lat, 99) * 1e3:.1f} ms")
+    ident = same(rb) and same(rs)
+    return {
+        "metric": "batched games/s",
+        "value": served,
+        "unit": "games/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 0,
+        "ms_per_step": rs["makespan"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS["c4"][0], "games": len(games),
+                   "sum_n": int(sum(g["n"] for g in games)),
+                   "sum_n_aug": int(n_aug_total),
+                   "arena_budget_vertices": int(budget_v),
+                   "arrivals": "Poisson, rate 1.5 x batched calibration rate"},
+        "served_games_per_s": served,
+        "latency_p50_ms": float(np.percentile(lat, 50) * 1e3),
+        "latency_p99_ms": float(np.percentile(lat, 99) * 1e3),
+        "batched_all_at_once_games_per_s": mu,
+        "one_at_a_time_games_per_s": len(games) / t_solo,
+        "speedup_served_vs_one_at_a_time": served * t_solo / len(games),
+        "identical_to_one_at_a_time": bool(ident),
+        "served_steps": rs["steps"],
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +189,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the per-kernel event profiler")
+    ap.add_argument("--mix-games", type=int, default=1024,
+                    help="games in the batched/served workload")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device 3 times (a plain "
                          "copy kernel of known size, to scale HBM counters)")
@@ -116,6 +210,10 @@ def main():
               "supported (the solver keeps a whole game on one device)",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "c4":
+        print(json.dumps(bench_mix(args)), flush=True)
+        return
 
     import torch
     from paper_1705_02313_amd import synth

@@ -65,7 +65,8 @@ typedef enum pg_status {
 enum {
     PG_PTR_DEVICE = 1u,     /* buffer arguments are device pointers          */
     PG_NO_PREPROCESS = 2u,  /* pg_load_csr: do not insert dummy vertices     */
-    PG_OFFSETS_I32 = 4u     /* pg_load_csr: offsets are int32, not int64     */
+    PG_OFFSETS_I32 = 4u,    /* pg_load_csr: offsets are int32, not int64     */
+    PG_CAREFUL_WALKS = 8u   /* pg_load_csr: host-driven walk rounds (below)  */
 };
 
 /*
@@ -79,7 +80,8 @@ enum {
  *             edges are allowed
  *   owner     n bytes: 0 = Even, 1 = Odd
  *   priority  n int32 priorities, >= 0 and pairwise distinct
- *   flags     PG_PTR_DEVICE, PG_NO_PREPROCESS, PG_OFFSETS_I32
+ *   flags     PG_PTR_DEVICE, PG_NO_PREPROCESS, PG_OFFSETS_I32,
+ *             PG_CAREFUL_WALKS
  *
  * Unless PG_NO_PREPROCESS is given, the admissibility preprocessing of
  * section 3 ("The algorithm") runs on the device: X is the largest set of
@@ -89,6 +91,12 @@ enum {
  * d_w in place.  Dummies get priorities 0, 1, ... (the index of w); the
  * original priorities are raised by that count rounded up to even, which
  * keeps their order and parity.
+ *
+ * Every valuation first walks the play graph with a fixed number of device
+ * rounds and falls back by itself to rounds driven from the host (each one
+ * followed by a read-back of the count of open walks) when those leave work.
+ * PG_CAREFUL_WALKS makes every valuation of this game take the host-driven
+ * rounds directly: slower, same results; it exists to test that path.
  *
  * The inputs may be freed when the call returns.  Errors: PG_EINVAL for a
  * malformed game (bad offsets, a terminal vertex, a target out of range, an
@@ -238,6 +246,8 @@ pg_status pg_profile_read(const pg_game *game, int32_t kind, const char **name,
  *                  winner (n), sigma and tau (n_aug, as pg_solve) and
  *                  stats, and releases the ticket.  flags: PG_PTR_DEVICE for
  *                  device output buffers.
+ * pg_batch_finished  tickets of finished games not yet polled (up to
+ *                  capacity of them; *count = how many there are).
  * pg_batch_info    games running and queued, current arena size.
  * pg_batch_free    releases everything, including unpolled games.
  *
@@ -256,6 +266,8 @@ pg_status pg_batch_step(pg_batch *batch, int32_t *n_live, int32_t *n_queued,
 pg_status pg_batch_poll(pg_batch *batch, int64_t ticket, int32_t *done,
                         uint8_t *winner, int32_t *sigma, int32_t *tau,
                         pg_stats *stats, uint32_t flags);
+pg_status pg_batch_finished(const pg_batch *batch, int64_t *tickets,
+                            int32_t capacity, int32_t *count);
 pg_status pg_batch_info(const pg_batch *batch, int32_t *n_live,
                         int32_t *n_queued, int64_t *arena_vertices,
                         int64_t *arena_edges);

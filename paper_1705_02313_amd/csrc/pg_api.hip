@@ -660,6 +660,7 @@ pg_status pg_load_csr(int64_t n, int64_t m, const void *offsets,
       load_modified(n, m, offsets, targets, owner, priority, flags, s, g);
   if (st == PG_OK) st = alloc_state(g, g->n_aug);
   if (st == PG_OK) st = finalize_state(g, s, true);
+  g->careful = flags & PG_CAREFUL_WALKS;
   if (st != PG_OK) {
     (void)hipStreamSynchronize(s);
     free_game(g);

@@ -716,6 +716,21 @@ pg_status pg_batch_poll(pg_batch *b, int64_t ticket, int32_t *done,
   return PG_OK;
 }
 
+pg_status pg_batch_finished(const pg_batch *b, int64_t *tickets,
+                            int32_t capacity, int32_t *count) {
+  if (!b || !count) return pg_fail(PG_EINVAL, "NULL argument");
+  int32_t c = 0;
+  for (const auto &kv : b->games) {
+    const BGame *g = kv.second;
+    if (g->state == B_DONE && !g->polled) {
+      if (tickets && c < capacity) tickets[c] = g->ticket;
+      ++c;
+    }
+  }
+  *count = c;
+  return PG_OK;
+}
+
 pg_status pg_batch_info(const pg_batch *b, int32_t *n_live,
                         int32_t *n_queued, int64_t *arena_vertices,
                         int64_t *arena_edges) {

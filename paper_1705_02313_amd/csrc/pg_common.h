@@ -22,11 +22,8 @@ enum Counter : int {
   C_NFIN = 1,         // finite vertices excluding the sink
   C_SWITCH = 2,       // switches made by the last switch kernel
   C_ABORT = 3,        // nonzero: bounded rounds left work; later kernels skip
-  C_MISC = 4,         // scratch counter (preprocessing changes, odd count)
-  C_HA = 5,           // worklist lengths of host-driven rounds
-  C_HB = 6,
-  C_NGW = 8,          // C_NGW + r: ng worklist length after round r
-  C_RTW = 16,         // C_RTW + r: root worklist length after round r
+  C_MISC = 4,         // scratch counter (preprocessing changes, odd count,
+                      // open vertices of host-driven walk rounds)
   C_COUNT = 32,       // the part copied back to the host
   // Hot counts are spread over kDistSlots slots kDistStride ints apart (one
   // atomic per block into slot blockIdx % kDistSlots) and summed by one
@@ -134,6 +131,7 @@ struct pg_game {
   int32_t n_oddpri = 0;          // vertices with an odd priority
   int64_t n_odd = 0, m_odd = 0;  // Odd vertices and the edges of their rows
   int sort_bits = 0;             // bits of a parent id key (ids 0..n_aug+1)
+  bool careful = false;          // PG_CAREFUL_WALKS: host-driven walk rounds
 
   // modified game, device resident
   int64_t *off = nullptr;   // [n_aug+1]
@@ -150,7 +148,7 @@ struct pg_game {
   int32_t *candp[2] = {nullptr, nullptr};  // [n_aug] walk candidates
   int par = 0;              // which ng/cand pair the next valuation uses
   int32_t *rcand = nullptr; // [n_aug]   root-walk candidates
-  int32_t *wl0 = nullptr;   // [n_aug]   worklists
+  int32_t *wl0 = nullptr;   // [n_aug]   staging of host strategies
   int32_t *wl1 = nullptr;   // [n_aug]
   uint8_t *rs = nullptr;    // [n_aug+1] 0 unknown, 1 finite, 2 top
 

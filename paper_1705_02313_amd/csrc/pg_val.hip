@@ -88,80 +88,84 @@ __device__ __forceinline__ int32_t ng_walk(int32_t N, const int2 *sp,
 }
 
 // Full pass: a plain walk along the play (one 8-byte load per step, no
-// reads of other threads' results); vertices that run out of steps go to the
-// worklist.  Also clears this valuation's root-walk state.
+// reads of other threads' results).  A vertex that runs out of steps keeps
+// ng = -1 and records where its walk stopped in cand; the rounds pick it up.
+// Also clears this valuation's root-walk state.  With `dist`, the unresolved
+// vertices are counted there (every thread of the block takes part).
 __global__ __launch_bounds__(kBlock) void k_ng_full(
     int32_t N, const int2 *__restrict__ sp, const int32_t *__restrict__ pri,
-    int32_t *ng, int32_t *cand, int32_t *wl_out, int32_t *ctr, int slot_out,
-    int steps, uint8_t *rs, int32_t *rcand) {
+    int32_t *ng, int32_t *cand, int32_t *ctr, int steps, uint8_t *rs,
+    int32_t *rcand, int32_t *dist) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  const int32_t v = (int32_t)i;
-  rs[v] = 0;
-  rcand[v] = -1;
-  // sp[x] = {successor of x, priority of that successor}: the first
-  // comparison needs no gather, each further step one
-  const int pv = pri[v];
-  const int2 me = sp[v];
-  int32_t u = me.x;
-  int pu = me.y;
-  int32_t res = -1;
-  // Brent's cycle detection: a walk that meets its checkpoint again circles
-  // a cycle without v whose priorities are all below v's, so nothing after
-  // v is larger (ng = TOP)
-  int32_t mark = v;
-  int lam = 1, power = 1;
-  for (int s = 0; s < steps; ++s) {
-    if (u == N) { res = N; break; }
-    if (u == v) {
-      // back at v: v has the largest priority of its cycle, which must be
-      // even for an admissible sigma (section 3)
-      if (pv & 1) atomicOr(&ctr[C_ERR], ERR_INADMISSIBLE);
-      res = N + 1;
-      break;
+  bool pending = false;
+  if (i < N) {
+    const int32_t v = (int32_t)i;
+    rs[v] = 0;
+    rcand[v] = -1;
+    // sp[x] = {successor of x, priority of that successor}: the first
+    // comparison needs no gather, each further step one
+    const int pv = pri[v];
+    const int2 me = sp[v];
+    int32_t u = me.x;
+    int pu = me.y;
+    int32_t res = -1;
+    // Brent's cycle detection: a walk that meets its checkpoint again
+    // circles a cycle without v whose priorities are all below v's, so
+    // nothing after v is larger (ng = TOP)
+    int32_t mark = v;
+    int lam = 1, power = 1;
+    for (int st = 0; st < steps; ++st) {
+      if (u == N) { res = N; break; }
+      if (u == v) {
+        // back at v: v has the largest priority of its cycle, which must be
+        // even for an admissible sigma (section 3)
+        if (pv & 1) atomicOr(&ctr[C_ERR], ERR_INADMISSIBLE);
+        res = N + 1;
+        break;
+      }
+      if (pu > pv) { res = u; break; }
+      if (u == mark) { res = N + 1; break; }
+      if (lam == power) {
+        mark = u;
+        power <<= 1;
+        lam = 0;
+      }
+      ++lam;
+      const int2 su = sp[u];
+      u = su.x;
+      pu = su.y;
     }
-    if (pu > pv) { res = u; break; }
-    if (u == mark) { res = N + 1; break; }
-    if (lam == power) {
-      mark = u;
-      power <<= 1;
-      lam = 0;
-    }
-    ++lam;
-    const int2 su = sp[u];
-    u = su.x;
-    pu = su.y;
+    if (res >= 0) ng[v] = res;
+    else cand[v] = u;
+    pending = res < 0;
   }
-  if (res >= 0) {
-    ng[v] = res;
-  } else {
-    cand[v] = u;
-    wl_out[atomicAdd(&ctr[slot_out], 1)] = v;
-  }
+  if (dist) count_block(dist, pending);
 }
 
-// A round over the worklist left by the previous pass: the candidates of
-// unresolved vertices jump over other candidates (pointer jumping).  A fixed
-// grid strides over the list, whose length is read on the device.
+// A round over every vertex whose ng is still open: its walk continues from
+// its candidate and jumps over other vertices' results and candidates
+// (pointer jumping).  A dense pass (one coalesced read of ng per vertex)
+// instead of a compacted worklist: appending to a shared list serialises on
+// its length counter.  `last`: a vertex still open raises C_ABORT.
 __global__ __launch_bounds__(kBlock) void k_ng_round(
     int32_t N, const int2 *__restrict__ sp, const int32_t *__restrict__ pri,
-    int32_t *ng, int32_t *cand, const int32_t *wl_in, int32_t *wl_out,
-    int32_t *ctr, int slot_in, int slot_out, int last, int steps) {
-  const int32_t cnt = ctr[slot_in];
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
-       i += stride) {
-    const int32_t v = wl_in[i];
-    int32_t u = ld_relaxed(&cand[v]);
-    const int32_t res = ng_walk(N, sp, pri, ng, cand, v, &u, steps, ctr);
-    if (res >= 0) {
-      st_relaxed(&ng[v], res);
-    } else {
-      st_relaxed(&cand[v], u);
-      wl_out[atomicAdd(&ctr[slot_out], 1)] = v;
-      if (last) atomicOr(&ctr[C_ABORT], 1);
+    int32_t *ng, int32_t *cand, int32_t *ctr, int last, int steps,
+    int32_t *dist) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool pending = false;
+  if (i < N) {
+    const int32_t v = (int32_t)i;
+    if (ld_relaxed(&ng[v]) < 0) {
+      int32_t u = ld_relaxed(&cand[v]);
+      const int32_t res = ng_walk(N, sp, pri, ng, cand, v, &u, steps, ctr);
+      if (res >= 0) st_relaxed(&ng[v], res);
+      else st_relaxed(&cand[v], u);
+      pending = res < 0;
     }
   }
+  if (last && __ballot(pending) && (threadIdx.x & (kWave - 1)) == 0)
+    atomicOr(&ctr[C_ABORT], 1);
+  if (dist) count_block(dist, pending);
 }
 
 // ---------------------------------------------------------------------------
@@ -198,12 +202,15 @@ __device__ __forceinline__ int root_walk(int32_t N, const int32_t *ng,
 // Full pass: a plain walk along the ng chain (one load per step).  Writes
 // the vertex's sort key at its signed-priority position (its parent when
 // finite, N + 1 when top).  Also clears the other ng/cand pair (used by the
-// next valuation) and this valuation's Euler-list per-vertex state.
+// next valuation) and this valuation's Euler-list per-vertex state.  An
+// undecided vertex keeps rs = 0 and records where its walk stopped in rcand
+// (-2: its own ng is still open).  With `dist`, undecided vertices are
+// counted there.
 __global__ __launch_bounds__(kBlock) void k_root_full(
     int32_t N, const int32_t *ng, uint8_t *rs, int32_t *rcand, int32_t *key,
-    int32_t *wl_out, int32_t *ctr, int slot_out, int steps, int32_t *ng_next,
-    int32_t *cand_next, uint32_t *fh, const int32_t *__restrict__ rvpos,
-    uint32_t *sk) {
+    int32_t *ctr, int steps, int32_t *ng_next, int32_t *cand_next,
+    uint32_t *fh, const int32_t *__restrict__ rvpos, uint32_t *sk,
+    int32_t *dist) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) fh[N] = 0u;
   int fate = 0;
@@ -217,7 +224,7 @@ __global__ __launch_bounds__(kBlock) void k_root_full(
     if (r < 0) {
       r = -2;                       // ng(v) itself is not resolved yet
     } else {
-      for (int s = 0; s < steps; ++s) {
+      for (int st = 0; st < steps; ++st) {
         if (r >= N) break;
         const int32_t nx = ng[r];
         if (nx < 0) break;          // ng of r not resolved yet
@@ -232,26 +239,23 @@ __global__ __launch_bounds__(kBlock) void k_root_full(
       if (fate == 2) key[v] = PG_KEY_TOP;
     } else {
       rcand[v] = r;
-      wl_out[atomicAdd(&ctr[slot_out], 1)] = v;
     }
   }
   count_block(&ctr[C_DIST_NF], fate == 1);
+  if (dist) count_block(dist, i < N && fate == 0);
 }
 
+// A round over every undecided vertex (dense, like k_ng_round).
 __global__ __launch_bounds__(kBlock) void k_root_round(
     int32_t N, const int32_t *ng, uint8_t *rs, int32_t *rcand, int32_t *key,
-    const int32_t *wl_in, int32_t *wl_out, int32_t *ctr, int slot_in,
-    int slot_out, int last, int steps, const int32_t *__restrict__ rvpos,
-    uint32_t *sk) {
-  const int32_t cnt = ctr[slot_in];
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  // uniform trip count so that every thread reaches the block-wide count
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < cnt;
-       base += stride) {
-    const int64_t i = base + threadIdx.x;
-    int fate = 0;
-    if (i < cnt) {
-      const int32_t v = wl_in[i];
+    int32_t *ctr, int last, int steps, const int32_t *__restrict__ rvpos,
+    uint32_t *sk, int32_t *dist) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int fate = 0;
+  bool pending = false;
+  if (i < N) {
+    const int32_t v = (int32_t)i;
+    if (rs[v] == 0) {
       int32_t r = ld_relaxed(&rcand[v]);
       fate = root_walk(N, ng, rs, rcand, v, &r, steps);
       if (fate) {
@@ -261,12 +265,14 @@ __global__ __launch_bounds__(kBlock) void k_root_round(
         if (fate == 2) key[v] = PG_KEY_TOP;
       } else {
         st_relaxed(&rcand[v], r);
-        wl_out[atomicAdd(&ctr[slot_out], 1)] = v;
-        if (last) atomicOr(&ctr[C_ABORT], 1);
+        pending = true;
       }
     }
-    count_block(&ctr[C_DIST_NF], fate == 1);
   }
+  if (last && __ballot(pending) && (threadIdx.x & (kWave - 1)) == 0)
+    atomicOr(&ctr[C_ABORT], 1);
+  count_block(&ctr[C_DIST_NF], fate == 1);
+  if (dist) count_block(dist, pending);
 }
 
 // ---------------------------------------------------------------------------
@@ -582,8 +588,7 @@ constexpr int kFullSteps = 8;     // plain-walk budget of the full passes
 constexpr int kWalkSteps = 64;    // shortcut-walk budget of one round
 constexpr int kFastRounds = 3;    // rounds enqueued without looking back
 constexpr int kMaxRounds = 64;    // rounds of the careful path before failing
-constexpr int kRoundBlocks = 1024;
-constexpr int kPerThread1 = 1;    // level-1 sublists per thread
+constexpr int kPerThread1 = 4;    // level-1 sublists per thread
 
 static pg_status read_ctr(pg_game *g, hipStream_t s) {
   PG_HIP(hipMemcpyAsync(g->hctr, g->ctr, sizeof(int32_t) * C_COUNT,
@@ -619,32 +624,37 @@ static void enqueue_walks(pg_game *g, hipStream_t s) {
   fill_i32(g->ctr, 0, C_TOTAL, s, pf);
   // own record 8, first successor record 8, result 4; state resets 5
   PG_LAUNCH(pf, K_NG_WALK, 25.0 * N, k_ng_full, dim3(grid_for(N)),
-            dim3(kBlock), 0, s, N, g->sp, g->pri, ng, cand, g->wl0, g->ctr,
-            (int)C_NGW, kFullSteps, g->rs, g->rcand);
-  int32_t *wa = g->wl0, *wb = g->wl1;
-  for (int r = 1; r <= kFastRounds; ++r) {
-    PG_LAUNCH(pf, K_NG_ROUND, 0.0, k_ng_round, dim3(kRoundBlocks),
-              dim3(kBlock), 0, s, N, g->sp, g->pri, ng, cand,
-              (const int32_t *)wa, wb, g->ctr, (int)(C_NGW + r - 1),
-              (int)(C_NGW + r),
-              (int)(r == kFastRounds), kWalkSteps);
-    int32_t *t = wa; wa = wb; wb = t;
-  }
+            dim3(kBlock), 0, s, N, g->sp, g->pri, ng, cand, g->ctr,
+            kFullSteps, g->rs, g->rcand, (int32_t *)nullptr);
+  for (int r = 1; r <= kFastRounds; ++r)
+    PG_LAUNCH(pf, K_NG_ROUND, 4.0 * N, k_ng_round, dim3(grid_for(N)),
+              dim3(kBlock), 0, s, N, g->sp, g->pri, ng, cand, g->ctr,
+              (int)(r == kFastRounds), kWalkSteps, (int32_t *)nullptr);
   // own ng 4, parent's ng 4, rvpos 4, sort key 4, rs 1; resets 12
   PG_LAUNCH(pf, K_ROOT_WALK, 29.0 * N, k_root_full, dim3(grid_for(N)),
-            dim3(kBlock), 0, s, N, ng, g->rs, g->rcand, g->key, g->wl0,
-            g->ctr, (int)C_RTW, kFullSteps, ngn, candn, g->fh, g->rvpos,
-            g->sk0);
-  wa = g->wl0; wb = g->wl1;
-  for (int r = 1; r <= kFastRounds; ++r) {
-    PG_LAUNCH(pf, K_ROOT_ROUND, 0.0, k_root_round, dim3(kRoundBlocks),
-              dim3(kBlock), 0, s, N, ng, g->rs, g->rcand, g->key,
-              (const int32_t *)wa, wb, g->ctr, (int)(C_RTW + r - 1),
-              (int)(C_RTW + r), (int)(r == kFastRounds), kWalkSteps,
-              g->rvpos, g->sk0);
-    int32_t *t = wa; wa = wb; wb = t;
-  }
+            dim3(kBlock), 0, s, N, ng, g->rs, g->rcand, g->key, g->ctr,
+            kFullSteps, ngn, candn, g->fh, g->rvpos, g->sk0,
+            (int32_t *)nullptr);
+  for (int r = 1; r <= kFastRounds; ++r)
+    PG_LAUNCH(pf, K_ROOT_ROUND, 1.0 * N, k_root_round, dim3(grid_for(N)),
+              dim3(kBlock), 0, s, N, ng, g->rs, g->rcand, g->key, g->ctr,
+              (int)(r == kFastRounds), kWalkSteps, g->rvpos, g->sk0,
+              (int32_t *)nullptr);
   sum_dist(g->ctr, C_DIST_NF, C_NFIN, s, pf);
+}
+
+// Clears the distributed counter at C_DIST_MISC and C_MISC, runs `launch`
+// (which counts its open vertices there) and reads the count back.
+template <class F>
+static pg_status counted(pg_game *g, hipStream_t s, F launch, int32_t *open) {
+  Prof *pf = &g->prof;
+  fill_i32(g->ctr + C_MISC, 0, 1, s, pf);
+  fill_i32(g->ctr + C_DIST_MISC, 0, kDistSlots * kDistStride, s, pf);
+  launch(g->ctr + C_DIST_MISC);
+  sum_dist(g->ctr, C_DIST_MISC, C_MISC, s, pf);
+  PG_TRY(read_ctr(g, s));
+  *open = g->hctr[C_MISC];
+  return PG_OK;
 }
 
 // ng and root phases looping on the host until every vertex is resolved.
@@ -656,48 +666,36 @@ static pg_status careful_walks(pg_game *g, hipStream_t s) {
   fill_i32(ng, -1, N, s, pf);
   fill_i32(cand, -1, N, s, pf);
   fill_i32(g->ctr, 0, C_TOTAL, s, pf);
-  PG_LAUNCH(pf, K_NG_WALK, 25.0 * N, k_ng_full, dim3(grid_for(N)),
-            dim3(kBlock), 0, s, N, g->sp, g->pri, ng, cand, g->wl0, g->ctr,
-            (int)C_HA, kFullSteps, g->rs, g->rcand);
-  pg_status st = read_ctr(g, s);
-  if (st != PG_OK) return st;
-  int32_t *wa = g->wl0, *wb = g->wl1;
-  int in = C_HA, out = C_HB;
-  for (int r = 0; g->hctr[in] > 0; ++r) {
+  int32_t open = 0;
+  PG_TRY(counted(g, s, [&](int32_t *dist) {
+    PG_LAUNCH(pf, K_NG_WALK, 25.0 * N, k_ng_full, dim3(grid_for(N)),
+              dim3(kBlock), 0, s, N, g->sp, g->pri, ng, cand, g->ctr,
+              kFullSteps, g->rs, g->rcand, dist);
+  }, &open));
+  for (int r = 0; open > 0; ++r) {
     if (r >= kMaxRounds)
       return pg_fail(PG_EINTERNAL, "ng resolution did not converge");
-    fill_i32(g->ctr + out, 0, 1, s, pf);
-    PG_LAUNCH(pf, K_NG_ROUND, 0.0, k_ng_round, dim3(kRoundBlocks),
-              dim3(kBlock), 0, s, N, g->sp, g->pri, ng, cand,
-              (const int32_t *)wa, wb, g->ctr, in, out, 0, kWalkSteps);
-    st = read_ctr(g, s);
-    if (st != PG_OK) return st;
-    int32_t *t = wa; wa = wb; wb = t;
-    int ti = in; in = out; out = ti;
+    PG_TRY(counted(g, s, [&](int32_t *dist) {
+      PG_LAUNCH(pf, K_NG_ROUND, 4.0 * N, k_ng_round, dim3(grid_for(N)),
+                dim3(kBlock), 0, s, N, g->sp, g->pri, ng, cand, g->ctr, 0,
+                kWalkSteps, dist);
+    }, &open));
   }
-  fill_i32(g->ctr + C_HA, 0, 2, s, pf);
   fill_i32(g->ctr + C_NFIN, 0, 1, s, pf);
   fill_i32(g->ctr + C_DIST_NF, 0, kDistSlots * kDistStride, s, pf);
-  PG_LAUNCH(pf, K_ROOT_WALK, 29.0 * N, k_root_full, dim3(grid_for(N)),
-            dim3(kBlock), 0, s, N, ng, g->rs, g->rcand, g->key, g->wl0,
-            g->ctr, (int)C_HA, kFullSteps, ngn, candn, g->fh, g->rvpos,
-            g->sk0);
-  st = read_ctr(g, s);
-  if (st != PG_OK) return st;
-  wa = g->wl0; wb = g->wl1;
-  in = C_HA; out = C_HB;
-  for (int r = 0; g->hctr[in] > 0; ++r) {
+  PG_TRY(counted(g, s, [&](int32_t *dist) {
+    PG_LAUNCH(pf, K_ROOT_WALK, 29.0 * N, k_root_full, dim3(grid_for(N)),
+              dim3(kBlock), 0, s, N, ng, g->rs, g->rcand, g->key, g->ctr,
+              kFullSteps, ngn, candn, g->fh, g->rvpos, g->sk0, dist);
+  }, &open));
+  for (int r = 0; open > 0; ++r) {
     if (r >= kMaxRounds)
       return pg_fail(PG_EINTERNAL, "root resolution did not converge");
-    fill_i32(g->ctr + out, 0, 1, s, pf);
-    PG_LAUNCH(pf, K_ROOT_ROUND, 0.0, k_root_round, dim3(kRoundBlocks),
-              dim3(kBlock), 0, s, N, ng, g->rs, g->rcand, g->key,
-              (const int32_t *)wa, wb, g->ctr, in, out, 0, kWalkSteps,
-              g->rvpos, g->sk0);
-    st = read_ctr(g, s);
-    if (st != PG_OK) return st;
-    int32_t *t = wa; wa = wb; wb = t;
-    int ti = in; in = out; out = ti;
+    PG_TRY(counted(g, s, [&](int32_t *dist) {
+      PG_LAUNCH(pf, K_ROOT_ROUND, 1.0 * N, k_root_round, dim3(grid_for(N)),
+                dim3(kBlock), 0, s, N, ng, g->rs, g->rcand, g->key, g->ctr,
+                0, kWalkSteps, g->rvpos, g->sk0, dist);
+    }, &open));
   }
   sum_dist(g->ctr, C_DIST_NF, C_NFIN, s, pf);
   fill_i32(g->ctr + C_ABORT, 0, 1, s, pf);
@@ -799,7 +797,8 @@ static pg_status check_ctr(pg_game *g) {
 static pg_status run_valuation(pg_game *g, hipStream_t s, bool odd_switch,
                                int32_t *count, int64_t *n_finite) {
   g->nlevels = plan_levels(g->n_aug);
-  enqueue_walks(g, s);
+  if (g->careful) PG_TRY(careful_walks(g, s));
+  else enqueue_walks(g, s);
   enqueue_rank(g, s);
   if (odd_switch) {
     fill_i32(g->ctr + C_SWITCH, 0, 1, s, &g->prof);

@@ -20,7 +20,7 @@ PG_OK, PG_EINVAL, PG_ENOMEM, PG_EDEVICE = 0, 1, 2, 3
 PG_EITERLIMIT, PG_EINADMISSIBLE, PG_EINTERNAL = 4, 5, 6
 PG_SINK = -1
 PG_KEY_TOP = 2**31 - 1
-PG_PTR_DEVICE, PG_NO_PREPROCESS, PG_OFFSETS_I32 = 1, 2, 4
+PG_PTR_DEVICE, PG_NO_PREPROCESS, PG_OFFSETS_I32, PG_CAREFUL_WALKS = 1, 2, 4, 8
 
 STATUS_NAMES = {0: "PG_OK", 1: "PG_EINVAL", 2: "PG_ENOMEM", 3: "PG_EDEVICE",
                 4: "PG_EITERLIMIT", 5: "PG_EINADMISSIBLE", 6: "PG_EINTERNAL"}
@@ -29,7 +29,8 @@ EXPORTS = ["pg_load_csr", "pg_game_info", "pg_export_game",
            "pg_initial_strategies", "pg_valuation", "pg_best_response",
            "pg_solve", "pg_profile_enable", "pg_profile_kinds",
            "pg_profile_read", "pg_batch_create", "pg_batch_submit",
-           "pg_batch_step", "pg_batch_poll", "pg_batch_info", "pg_batch_free",
+           "pg_batch_step", "pg_batch_poll", "pg_batch_finished",
+           "pg_batch_info", "pg_batch_free",
            "pg_free", "pg_last_error"]
 
 
@@ -101,6 +102,7 @@ def lib() -> ctypes.CDLL:
         L.pg_batch_info.argtypes = [P, ctypes.POINTER(I32),
                                     ctypes.POINTER(I32), ctypes.POINTER(I64),
                                     ctypes.POINTER(I64)]
+        L.pg_batch_finished.argtypes = [P, P, I32, ctypes.POINTER(I32)]
         L.pg_batch_free.argtypes = [P]
         L.pg_free.argtypes = [P]
         L.pg_last_error.argtypes = []
@@ -137,10 +139,10 @@ def _stream(device: bool):
 
 class Game:
     """A game loaded on the device (modified by preprocessing unless
-    ``preprocess=False``)."""
+    ``preprocess=False``; ``careful_walks=True`` sets PG_CAREFUL_WALKS)."""
 
     def __init__(self, offsets, targets, owner, priority, n: int = None,
-                 preprocess: bool = True):
+                 preprocess: bool = True, careful_walks: bool = False):
         device = _is_torch(targets)
         if device:
             import torch
@@ -165,7 +167,8 @@ class Game:
             n = int(offsets.numel() if device else offsets.size) - 1
         flags = (PG_PTR_DEVICE if device else 0) | \
             (0 if preprocess else PG_NO_PREPROCESS) | \
-            (PG_OFFSETS_I32 if off_i32 else 0)
+            (PG_OFFSETS_I32 if off_i32 else 0) | \
+            (PG_CAREFUL_WALKS if careful_walks else 0)
         h = ctypes.c_void_p()
         _check(lib().pg_load_csr(n, m, _ptr(offsets), _ptr(targets),
                                  _ptr(owner), _ptr(priority), flags,
@@ -177,15 +180,18 @@ class Game:
         self.n, self.m, self.n_aug, self.m_aug = [int(v.value) for v in vals]
 
     @classmethod
-    def from_dict(cls, g: dict, device: bool = False, preprocess: bool = True):
+    def from_dict(cls, g: dict, device: bool = False, preprocess: bool = True,
+                  careful_walks: bool = False):
         if device:
             import torch
             t = {k: torch.from_numpy(np.ascontiguousarray(g[k])).cuda()
                  for k in ("offsets", "targets", "owner", "pri")}
             return cls(t["offsets"], t["targets"], t["owner"], t["pri"],
-                       n=int(g["n"]), preprocess=preprocess)
+                       n=int(g["n"]), preprocess=preprocess,
+                       careful_walks=careful_walks)
         return cls(g["offsets"], g["targets"], g["owner"], g["pri"],
-                   n=int(g["n"]), preprocess=preprocess)
+                   n=int(g["n"]), preprocess=preprocess,
+                   careful_walks=careful_walks)
 
     # -- helpers -------------------------------------------------------------
     def _out(self, count: int, dtype):
@@ -371,6 +377,17 @@ class Batch:
         del self._sizes[ticket]
         return {"winner": winner, "sigma": sigma, "tau": tau,
                 "stats": st.as_dict()}
+
+    def finished(self) -> list:
+        """Tickets of finished games not yet polled."""
+        c = ctypes.c_int32()
+        _check(lib().pg_batch_finished(self._h, None, 0, ctypes.byref(c)))
+        if c.value == 0:
+            return []
+        buf = np.empty(c.value, np.int64)
+        _check(lib().pg_batch_finished(self._h, _ptr(buf), c.value,
+                                       ctypes.byref(c)))
+        return [int(x) for x in buf[:c.value]]
 
     def info(self):
         a, b = ctypes.c_int32(), ctypes.c_int32()

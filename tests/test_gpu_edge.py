@@ -170,8 +170,9 @@ def test_deterministic_repeats():
         np.testing.assert_array_equal(a[k], b[k])
 
 
-@pytest.mark.parametrize("n", [1000, 200_000, 2_000_000])
-def test_deep_list_valuation(n):
+@pytest.mark.parametrize("n,careful", [(1000, False), (200_000, False),
+                                       (2_000_000, False), (200_000, True)])
+def test_deep_list_valuation(n, careful):
     """One play through every vertex (the chain i -> i+1, each dummy to its
     w, one Even vertex to the sink): an Euler list as long as the game."""
     g = synth.chain_game(n, 77)
@@ -200,7 +201,23 @@ def test_deep_list_valuation(n):
     succ = np.where(own == 1, tau, sigma).astype(np.int32)
     key, nf, rc = orc.valuation(succ, aug["pri"])
     assert rc == 0
-    with Game.from_dict(g) as d:
+    with Game.from_dict(g, careful_walks=careful) as d:
         dkey, dnf = d.valuation(sigma, tau)
     assert dnf == nf
     np.testing.assert_array_equal(to_np(dkey), key)
+
+
+@pytest.mark.parametrize("g", [synth.random_game(20000, 2, 6, 41),
+                               synth.chain_game(30000, 42)],
+                         ids=["random", "chain"])
+def test_careful_walks_same_results(g):
+    """The host-driven walk rounds (the fallback of the fixed device rounds)
+    give the oracle's results on whole solves."""
+    ref = orc.solve(g)
+    assert ref["status"] == 0
+    with Game.from_dict(g, careful_walks=True) as d:
+        out = d.solve()
+    np.testing.assert_array_equal(to_np(out["winner"]), ref["winner"])
+    np.testing.assert_array_equal(to_np(out["sigma"]), ref["sigma"])
+    np.testing.assert_array_equal(to_np(out["tau"]), ref["tau"])
+    assert out["stats"]["n_valuations"] == ref["n_valuations"]
