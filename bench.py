@@ -52,6 +52,43 @@ WORKLOADS = {
 }
 
 
+TRAFFIC_FILES = {"c2": "traffic_random10M.json"}
+
+
+def sources_sha256() -> str:
+    """Hash of the library's kernel sources and header (file names and
+    contents), to tie stored counter readings to the code they measured."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1705_02313_amd", "csrc")
+    files = sorted(glob.glob(os.path.join(csrc, "*.hip")) +
+                   glob.glob(os.path.join(csrc, "*.h")))
+    files.append(os.path.join(ROOT, "include", "pg.h"))
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def counter_traffic(workload: str, kind: str):
+    """HBM bytes per launch of `kind` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, each scaled by its reading on a plain
+    copy), or None when there is none or the kernels changed since."""
+    name = TRAFFIC_FILES.get(workload)
+    if not name:
+        return None
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("sources_sha256") != sources_sha256():
+        return None
+    return t["bytes_per_launch"].get(kind)
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -305,7 +342,7 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "avg_launch_us": round(1e3 * a["ms"] / a["calls"], 2),
                 "bytes_per_launch": round(a["bytes"] / a["calls"]),
-                "traffic": None}
+                "traffic": counter_traffic(args.workload, dom)}
 
     line = {
         "metric": "edges/s per best-response iteration",
