@@ -1,8 +1,10 @@
-"""ctypes wrapper of the scalable C oracle (oracle/orc.c).
+"""ctypes wrapper of the scalable C oracle (oracle/orc.c for distinct
+priorities with rank valuations, oracle/orc_dense.c for repeated priorities
+with the paper's count valuations).
 
 TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the benchmark's
-CPU-baseline leg use it; the product library never does.  See orc.c for the
-passages of the paper each step follows.
+CPU-baseline leg use it; the product library never does.  See the C files for
+the passages of the paper each step follows.
 """
 from __future__ import annotations
 
@@ -14,7 +16,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liborc.so")
-SRC_PATH = os.path.join(HERE, "orc.c")
+SRC_PATHS = [os.path.join(HERE, "orc.c"), os.path.join(HERE, "orc_dense.c")]
 
 SINK = -1
 KEY_TOP = 2**31 - 1
@@ -32,12 +34,13 @@ class Stats(ctypes.Structure):
 
 
 def build(force: bool = False) -> str:
-    """Compile orc.c with gcc into liborc.so next to it."""
+    """Compile the C files with gcc into liborc.so next to them."""
     if force or not os.path.exists(LIB_PATH) or \
-            os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH):
+            os.path.getmtime(LIB_PATH) < max(os.path.getmtime(p)
+                                             for p in SRC_PATHS):
         tmp = LIB_PATH + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-shared", "-fPIC",
-                               "-o", tmp, SRC_PATH])
+                               "-o", tmp, *SRC_PATHS])
         os.replace(tmp, LIB_PATH)
     return LIB_PATH
 
@@ -67,6 +70,23 @@ def lib():
         L.orc_solve.restype = ctypes.c_int
         L.orc_solve.argtypes = [_I64, _P, _P, _P, _P, ctypes.c_int, _I64, _I64,
                                 _P, _P, _P, ctypes.POINTER(Stats), _P, _I64]
+        L.orc_dense_preprocess.restype = _I64
+        L.orc_dense_preprocess.argtypes = [_I64] + [_P] * 9
+        L.orc_dense_priorities.restype = _I64
+        L.orc_dense_priorities.argtypes = [_I64, _P, _P, _P]
+        L.orc_dense_valuation.restype = ctypes.c_int
+        L.orc_dense_valuation.argtypes = [_I64, _P, _P, _I64, _P, _P, _P]
+        L.orc_dense_compare.restype = ctypes.c_int
+        L.orc_dense_compare.argtypes = [_I64, _I64, _P, _P, _P, _I64, _I64]
+        L.orc_dense_odd_switch.restype = _I64
+        L.orc_dense_odd_switch.argtypes = [_I64, _P, _P, _P, _I64, _P, _P, _P,
+                                           _P]
+        L.orc_dense_even_switch.restype = _I64
+        L.orc_dense_even_switch.argtypes = [_I64, _P, _P, _P, _I64, _P, _P,
+                                            _P, _P]
+        L.orc_dense_solve.restype = ctypes.c_int
+        L.orc_dense_solve.argtypes = [_I64, _P, _P, _P, _P, _I64, _I64, _P, _P,
+                                      _P, _P, ctypes.POINTER(Stats), _P, _I64]
         _lib = L
     return _lib
 
@@ -210,4 +230,126 @@ def solve(game: dict, preprocess_game: bool = True,
             "n_even_switches": int(st.n_even_switches),
             "n_odd_switches": int(st.n_odd_switches),
             "trace": tr[:min(int(st.n_valuations), cap)].copy()
+            if trace else None}
+
+
+# --------------------------------------------------------------------------
+# count valuations (oracle/orc_dense.c): priorities may repeat
+# --------------------------------------------------------------------------
+def dense_preprocess(game: dict) -> dict:
+    """The modified game of the count-valuation path: dummies get priority
+    0 and, when there is a dummy, the original priorities are raised by 2."""
+    n = int(game["n"])
+    off = _c(game["offsets"], np.int64)
+    tgt = _c(game["targets"], np.int32)
+    own = _c(game["owner"], np.uint8)
+    pri = _c(game["pri"], np.int32)
+    m = int(off[-1])
+    off2 = np.zeros(2 * n + 1, np.int64)
+    tgt2 = np.zeros(m + n, np.int32)
+    own2 = np.zeros(2 * n, np.uint8)
+    pri2 = np.zeros(2 * n, np.int32)
+    dum = np.zeros(max(n, 1), np.int32)
+    n_aug = lib().orc_dense_preprocess(n, _ptr(off), _ptr(tgt), _ptr(own),
+                                       _ptr(pri), _ptr(off2), _ptr(tgt2),
+                                       _ptr(own2), _ptr(pri2), _ptr(dum))
+    if n_aug < 0:
+        raise ValueError("preprocessing failed (priority overflow)")
+    k = n_aug - n
+    m_aug = m + k
+    return {"n": n_aug, "m": m_aug, "offsets": off2[:n_aug + 1].copy(),
+            "targets": tgt2[:m_aug].copy(), "owner": own2[:n_aug].copy(),
+            "pri": pri2[:n_aug].copy(), "dummy_of": dum[:k].copy(),
+            "n_orig": n}
+
+
+def dense_priorities(pri):
+    """(values, idx): the distinct priorities in increasing order and each
+    vertex's position among them."""
+    pri = _c(pri, np.int32)
+    values = np.zeros(max(pri.size, 1), np.int32)
+    idx = np.zeros(pri.size, np.int32)
+    d = lib().orc_dense_priorities(pri.size, _ptr(pri), _ptr(values),
+                                   _ptr(idx))
+    return values[:d].copy(), idx
+
+
+def dense_valuation(succ, pri):
+    """Count valuations of the play graph succ (SINK for the sink).
+    Returns (counts[n+1, d], top[n], values[d], status); row n is the sink
+    and column j counts priority values[j]."""
+    succ = _c(succ, np.int32)
+    values, idx = dense_priorities(pri)
+    n, d = succ.size, values.size
+    counts = np.zeros((n + 1, d), np.int32)
+    top = np.zeros(max(n, 1), np.uint8)
+    rc = lib().orc_dense_valuation(n, _ptr(succ), _ptr(idx), d,
+                                   _ptr(values), _ptr(counts), _ptr(top))
+    return counts, top[:n].copy(), values, int(rc)
+
+
+def dense_compare(counts, top, values, a: int, b: int) -> int:
+    """-1, 0 or 1: Val(a) below, equal to or above Val(b) (n = the sink)."""
+    counts = _c(counts, np.int32)
+    top = _c(top, np.uint8)
+    values = _c(values, np.int32)
+    n = top.size
+    return int(lib().orc_dense_compare(n, values.size, _ptr(values),
+                                       _ptr(counts), _ptr(top), a, b))
+
+
+def dense_odd_switch(g: dict, counts, top, values, tau) -> tuple:
+    tau = _c(tau, np.int32).copy()
+    c = lib().orc_dense_odd_switch(
+        int(g["n"]), _ptr(_c(g["offsets"], np.int64)),
+        _ptr(_c(g["targets"], np.int32)), _ptr(_c(g["owner"], np.uint8)),
+        int(np.size(values)), _ptr(_c(values, np.int32)),
+        _ptr(_c(counts, np.int32)), _ptr(_c(top, np.uint8)), _ptr(tau))
+    return tau, int(c)
+
+
+def dense_even_switch(g: dict, counts, top, values, sigma) -> tuple:
+    sigma = _c(sigma, np.int32).copy()
+    c = lib().orc_dense_even_switch(
+        int(g["n"]), _ptr(_c(g["offsets"], np.int64)),
+        _ptr(_c(g["targets"], np.int32)), _ptr(_c(g["owner"], np.uint8)),
+        int(np.size(values)), _ptr(_c(values, np.int32)),
+        _ptr(_c(counts, np.int32)), _ptr(_c(top, np.uint8)), _ptr(sigma))
+    return sigma, int(c)
+
+
+def dense_solve(game: dict, preprocess_game: bool = True, trace: bool = False,
+                max_major: int = 0, max_inner: int = 0,
+                aug: dict = None) -> dict:
+    """Algorithm 1 with count valuations; returns winners, strategies,
+    counts, the last valuation (counts, top, values) and with trace the two
+    hashes (counts, top flags) of every valuation."""
+    g = aug if aug is not None else (
+        dense_preprocess(game) if preprocess_game else identity(game))
+    n = int(g["n"])
+    sigma, tau = initial_strategies(g)
+    values, _ = dense_priorities(g["pri"])
+    d = values.size
+    counts = np.zeros((n + 1, d), np.int32)
+    top = np.zeros(max(n, 1), np.uint8)
+    st = Stats()
+    cap = 200000 if trace else 0
+    tr = np.zeros(max(cap, 1), np.uint64)
+    rc = lib().orc_dense_solve(n, _ptr(_c(g["offsets"], np.int64)),
+                               _ptr(_c(g["targets"], np.int32)),
+                               _ptr(_c(g["owner"], np.uint8)),
+                               _ptr(_c(g["pri"], np.int32)), max_major,
+                               max_inner, _ptr(sigma), _ptr(tau),
+                               _ptr(counts), _ptr(top), ctypes.byref(st),
+                               _ptr(tr) if trace else None, cap)
+    n0 = int(g["n_orig"])
+    top = top[:n].copy()
+    winner = (top[:n0] == 0).astype(np.uint8)
+    nv = int(st.n_valuations)
+    return {"aug": g, "status": int(rc), "winner": winner, "sigma": sigma,
+            "tau": tau, "counts": counts, "top": top, "values": values,
+            "n_major": int(st.n_major), "n_valuations": nv,
+            "n_even_switches": int(st.n_even_switches),
+            "n_odd_switches": int(st.n_odd_switches),
+            "trace": tr[:min(2 * nv, cap)].reshape(-1, 2).copy()
             if trace else None}

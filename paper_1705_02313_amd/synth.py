@@ -10,7 +10,8 @@ A game is returned as a dict of numpy arrays in CSR form::
     offsets    int64[n+1] (or int32 with ``offsets_dtype=np.int32``)
     targets    int32[m]   successor ids, each row sorted ascending
     owner      uint8[n]   0 = Even, 1 = Odd
-    pri        int32[n]   pairwise distinct priorities
+    pri        int32[n]   priorities (pairwise distinct except in
+                          ``few_priorities_game``)
 
 The game model is the tuple (V, V_Even, V_Odd, E, pri) of the paper's
 preliminaries (section 2): every vertex has at least one outgoing edge.
@@ -27,6 +28,10 @@ Recipes (all draws from ``numpy.random.Generator(PCG64(seed))``):
   edge); it draws j from [1, n-1) instead.  Owners alternate in runs whose
   lengths are uniform in [1, 64], starting with a random owner; pri is a
   random permutation.
+* ``few_priorities_game`` -- the graph and owners of ``random_game`` with the
+  same seed; priorities drawn uniformly from [0, d) by a second, independent
+  stream (``PCG64([seed, 1])``), so they repeat: the regime of the paper's
+  experiments, whose games have 2 to 4 distinct priorities.
 * ``mixed_batch`` -- the batched workload: game g uses seed base+g,
   n_g = round(exp(U(ln nmin, ln nmax))) and a random game with out-degree
   uniform in [2, 8].
@@ -35,8 +40,8 @@ from __future__ import annotations
 
 import numpy as np
 
-__all__ = ["random_game", "chain_game", "mixed_batch", "config_game",
-           "CONFIG_SEED_BASE"]
+__all__ = ["random_game", "chain_game", "few_priorities_game", "mixed_batch",
+           "config_game", "CONFIG_SEED_BASE"]
 
 CONFIG_SEED_BASE = 1000
 
@@ -132,6 +137,15 @@ def chain_game(n: int, seed: int, offsets_dtype=np.int64) -> dict:
     offsets, targets = _rows_to_csr(deg, flat, offsets_dtype)
     return {"n": n, "m": int(deg.sum()), "offsets": offsets,
             "targets": targets, "owner": owner, "pri": pri}
+
+
+def few_priorities_game(n: int, dmin: int, dmax: int, d: int, seed: int,
+                        offsets_dtype=np.int64) -> dict:
+    """Random game whose priorities take only d values (they repeat)."""
+    g = random_game(n, dmin, dmax, seed, offsets_dtype)
+    rng = np.random.Generator(np.random.PCG64([seed, 1]))
+    g["pri"] = rng.integers(0, d, size=n).astype(np.int32)
+    return g
 
 
 def mixed_batch(count: int, seed_base: int, nmin: int = 1000,
