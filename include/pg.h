@@ -66,7 +66,8 @@ enum {
     PG_PTR_DEVICE = 1u,     /* buffer arguments are device pointers          */
     PG_NO_PREPROCESS = 2u,  /* pg_load_csr: do not insert dummy vertices     */
     PG_OFFSETS_I32 = 4u,    /* pg_load_csr: offsets are int32, not int64     */
-    PG_CAREFUL_WALKS = 8u   /* pg_load_csr: host-driven walk rounds (below)  */
+    PG_CAREFUL_WALKS = 8u,  /* pg_load_csr: host-driven walk rounds (below)  */
+    PG_COUNT_VALUATION = 16u /* pg_load_csr: count valuations (below)        */
 };
 
 /*
@@ -79,18 +80,31 @@ enum {
  *   targets   m int32 successor ids in [0, n); self-loops and repeated
  *             edges are allowed
  *   owner     n bytes: 0 = Even, 1 = Odd
- *   priority  n int32 priorities, >= 0 and pairwise distinct
+ *   priority  n int32 priorities, >= 0 (they may repeat; see below)
  *   flags     PG_PTR_DEVICE, PG_NO_PREPROCESS, PG_OFFSETS_I32,
- *             PG_CAREFUL_WALKS
+ *             PG_CAREFUL_WALKS, PG_COUNT_VALUATION
+ *
+ * Two representations of valuations (section 3, "Valuations").  With
+ * pairwise distinct priorities a finite valuation is the set of priorities
+ * on a path and the library ranks the vertices by it (rank valuations,
+ * pg_valuation).  When priorities repeat -- the paper's own setting, with a
+ * handful of priorities -- or PG_COUNT_VALUATION is given, the library keeps
+ * the paper's count vectors (one count per priority in use) and ranks the
+ * Euler tour of the play graph's tree with vector addition (section 5,
+ * "Formal reduction to list ranking"); at most 32 distinct priorities after
+ * preprocessing (pg_count_info, pg_valuation_counts).
  *
  * Unless PG_NO_PREPROCESS is given, the admissibility preprocessing of
  * section 3 ("The algorithm") runs on the device: X is the largest set of
  * Odd vertices that each have a successor in X; for every w in X with a
  * predecessor in X a dummy Even vertex d_w is appended (in increasing w),
  * with the single row [w]; every edge (u, w) with u, w in X is redirected to
- * d_w in place.  Dummies get priorities 0, 1, ... (the index of w); the
- * original priorities are raised by that count rounded up to even, which
- * keeps their order and parity.
+ * d_w in place.  With rank valuations the dummies get priorities 0, 1, ...
+ * (the index of w) and the original priorities are raised by that count
+ * rounded up to even; with count valuations every dummy gets priority 0 and
+ * the original priorities are raised by 2 when there is a dummy.  Both keep
+ * the order and parity of the original priorities below which the dummies
+ * lie, so every winner is kept.
  *
  * Every valuation first walks the play graph with a fixed number of device
  * rounds and falls back by itself to rounds driven from the host (each one
@@ -100,13 +114,22 @@ enum {
  *
  * The inputs may be freed when the call returns.  Errors: PG_EINVAL for a
  * malformed game (bad offsets, a terminal vertex, a target out of range, an
- * owner not in {0,1}, a negative or repeated priority, a shifted priority
- * above INT32_MAX, too many vertices), PG_ENOMEM, PG_EDEVICE.
+ * owner not in {0,1}, a negative priority, a shifted priority above
+ * INT32_MAX, too many vertices, more than 32 distinct priorities with count
+ * valuations), PG_ENOMEM, PG_EDEVICE.
  */
 pg_status pg_load_csr(int64_t n, int64_t m, const void *offsets,
                       const int32_t *targets, const uint8_t *owner,
                       const int32_t *priority, uint32_t flags,
                       void *hip_stream, pg_game **out_game);
+
+/*
+ * pg_count_info -- *d = the number of distinct priorities of the modified
+ * game when it uses count valuations, else 0; values (nullable, room for 32)
+ * receives them in increasing order: column j of a count row counts
+ * values[j].
+ */
+pg_status pg_count_info(const pg_game *game, int32_t *d, int32_t *values);
 
 /* Sizes of the original and the modified game (any pointer may be NULL). */
 pg_status pg_game_info(const pg_game *game, int64_t *n, int64_t *m,
@@ -147,11 +170,34 @@ pg_status pg_initial_strategies(pg_game *game, int32_t *sigma, int32_t *tau,
  *
  * Returns PG_EINADMISSIBLE if the play graph has a cycle whose largest
  * priority is odd (sigma is not admissible, section 3); key is then
- * unspecified.
+ * unspecified.  PG_EINVAL for a game with count valuations.
  */
 pg_status pg_valuation(pg_game *game, const int32_t *sigma,
                        const int32_t *tau, int32_t *key, int64_t *n_finite,
                        uint32_t flags, void *hip_stream);
+
+/*
+ * pg_valuation_counts -- one valuation of a count-valuation game as the
+ * paper defines it (section 3, "Valuations"), computed by list ranking the
+ * Euler tour of the tree of finite vertices with vector addition (section 5,
+ * "Formal reduction to list ranking"; the list is built with the atomic
+ * exchange of "Constructing the list ranking instance in parallel").
+ *
+ *   sigma, tau  as in pg_valuation
+ *   counts      (n_aug+1) * d int32, row-major: row v holds, for each
+ *               column j, how many vertices of priority values[j]
+ *               (pg_count_info) the play from v visits before the sink; row
+ *               n_aug is the sink's (zero); rows of top vertices are zero
+ *   top         (nullable) n_aug bytes: 1 where the play is infinite (top)
+ *   n_finite    (nullable) vertices with a finite play, the sink included
+ *
+ * PG_EINVAL for a game with rank valuations; PG_EINADMISSIBLE as in
+ * pg_valuation.
+ */
+pg_status pg_valuation_counts(pg_game *game, const int32_t *sigma,
+                              const int32_t *tau, int32_t *counts,
+                              uint8_t *top, int64_t *n_finite, uint32_t flags,
+                              void *hip_stream);
 
 /*
  * pg_best_response -- the inner loop of Algorithm 1: one-player strategy
@@ -162,7 +208,9 @@ pg_status pg_valuation(pg_game *game, const int32_t *sigma,
  *
  *   sigma         n_aug entries (as in pg_valuation), admissible
  *   tau           n_aug entries; in: the start strategy; out: br(sigma)
- *   key           n_aug+1 outputs (nullable): Val^{sigma, br(sigma)}
+ *   key           n_aug+1 outputs (nullable): Val^{sigma, br(sigma)} as
+ *                 ranks; must be NULL for a count-valuation game (whose
+ *                 valuations compare count rows by Maxdiff instead of keys)
  *   n_valuations  (nullable) number of valuations computed
  *   max_inner     cap on valuations (0 = none); PG_EITERLIMIT when reached
  */

@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpgsi.so")
-SOURCES = ["pg_prims.hip", "pg_val.hip", "pg_api.hip", "pg_batch.hip"]
+SOURCES = ["pg_prims.hip", "pg_val.hip", "pg_count.hip", "pg_api.hip",
+           "pg_batch.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("PG_OFFLOAD_ARCH", "gfx950")

@@ -107,7 +107,7 @@ __global__ void k_xp_mark(const int64_t *__restrict__ off,
 // between members of X go through the dummy of their target; the dummy of the
 // i-th member w of X' is vertex n + i, Even, priority i, row [w].  Original
 // priorities rise by K (|X'| rounded up to even).
-__global__ void k_aug_build(int64_t n, int64_t m, int64_t K,
+__global__ void k_aug_build(int64_t n, int64_t m, int64_t K, int dense,
                             const int64_t *__restrict__ off,
                             const int32_t *__restrict__ tgt,
                             const uint8_t *__restrict__ owner,
@@ -133,7 +133,7 @@ __global__ void k_aug_build(int64_t n, int64_t m, int64_t K,
   if (xp[v]) {
     const int64_t i = did[v];
     owner2[n + i] = 0;
-    pri2[n + i] = (int32_t)i;
+    pri2[n + i] = dense ? 0 : (int32_t)i;
     tgt2[m + i] = (int32_t)v;
     off2[n + i + 1] = m + i + 1;
   }
@@ -151,14 +151,15 @@ __global__ void k_rv_keys(const int32_t *pri, uint32_t *sk, uint32_t *sv,
 
 __global__ void k_rv_finish(const uint32_t *skS, const uint32_t *svS,
                             int32_t *perm, int32_t *rvpos, int64_t n,
-                            int32_t *ctr) {
+                            int check_dup, int32_t *ctr) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool odd = false;
   if (i < n) {
     perm[i] = (int32_t)svS[i];
     rvpos[svS[i]] = (int32_t)i;
     odd = skS[i] < 0x80000000u;
-    if (i > 0 && skS[i] == skS[i - 1]) atomicOr(&ctr[C_ERR], ERR_DUPPRI);
+    if (check_dup && i > 0 && skS[i] == skS[i - 1])
+      atomicOr(&ctr[C_ERR], ERR_DUPPRI);
   }
   count_block(&ctr[C_DIST_MISC], odd);
 }
@@ -250,9 +251,11 @@ __global__ void k_count_odd_edges(const int64_t *off, const uint8_t *owner,
 }
 
 // Theorem 1: W_Even is the set of vertices whose final valuation is top
-__global__ void k_winner(const int32_t *key, uint8_t *winner, int64_t n) {
+// Theorem 1: Even wins exactly where the final valuation is top (the walks
+// of the last valuation marked those vertices with rs = 2).
+__global__ void k_winner(const uint8_t *rs, uint8_t *winner, int64_t n) {
   int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < n) winner[v] = key[v] == PG_KEY_TOP ? 0 : 1;
+  if (v < n) winner[v] = rs[v] == 2 ? 0 : 1;
 }
 
 }  // namespace pgk
@@ -318,13 +321,16 @@ void free_game(pg_game *g) {
                   g->wl1,      g->rs,       g->sk0,      g->sv0,
                   g->sk1,      g->sv1,      g->tile_cnt, g->scan_tmp,
                   g->kids,     g->fh,       g->pos,      g->elem,
-                  g->ctr,      g->u64tmp};
+                  g->ctr,      g->u64tmp,   g->cvals,    g->pidx,
+                  g->cnt};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (int k = 0; k < 8; ++k) {
     if (g->lv[k].sum) (void)hipFree(g->lv[k].sum);
     if (g->lv[k].next) (void)hipFree(g->lv[k].next);
     if (g->lv[k].base) (void)hipFree(g->lv[k].base);
+    if (g->vsum[k]) (void)hipFree(g->vsum[k]);
+    if (g->vbase[k]) (void)hipFree(g->vbase[k]);
   }
   if (g->hctr) (void)hipHostFree(g->hctr);
   g->prof.release();
@@ -393,11 +399,15 @@ pg_status check_err(pg_game *g, const char *what) {
 }
 
 // Validates a game and builds its modified game in g->off, g->tgt,
-// g->owner, g->pri (section 3 preprocessing unless PG_NO_PREPROCESS).
+// g->owner, g->pri (section 3 preprocessing unless PG_NO_PREPROCESS).  For
+// rank valuations the dummies get the distinct priorities 0, 1, ... and the
+// original ones are raised by |X'| rounded up to even; for count valuations
+// (dense) every dummy gets priority 0 and the original ones are raised by 2
+// when there is a dummy, so that few distinct priorities stay few.
 pg_status load_modified(int64_t n, int64_t m, const void *offsets,
                         const int32_t *targets, const uint8_t *owner,
                         const int32_t *priority, uint32_t flags, hipStream_t s,
-                        pg_game *g) {
+                        pg_game *g, bool dense) {
   const bool dev = flags & PG_PTR_DEVICE;
   g->n = n;
   g->m = m;
@@ -508,10 +518,10 @@ pg_status load_modified(int64_t n, int64_t m, const void *offsets,
     PG_HIP(hipMemcpyAsync(g->pri, pri_in, sizeof(int32_t) * n,
                           hipMemcpyDeviceToDevice, s));
   } else {
-    const int64_t K = nxp + (nxp & 1);
+    const int64_t K = dense ? (nxp > 0 ? 2 : 0) : nxp + (nxp & 1);
     hipLaunchKernelGGL(k_aug_build, dim3(grid_for(n)), dim3(kBlock), 0, s, n,
-                       m, K, off_in, tgt_in, own_in, pri_in, inx, xp, did,
-                       g->off, g->tgt, g->owner, g->pri, g->ctr);
+                       m, K, (int)dense, off_in, tgt_in, own_in, pri_in, inx,
+                       xp, did, g->off, g->tgt, g->owner, g->pri, g->ctr);
   }
   PG_TRY(sync_ctr(g, s));
   PG_TRY(check_err(g, "a priority exceeds INT32_MAX after preprocessing"));
@@ -521,7 +531,8 @@ pg_status load_modified(int64_t n, int64_t m, const void *offsets,
 // The signed-priority order (and the distinctness check), the initial play
 // graph and the two players' vertex lists of the modified game in g->off,
 // g->tgt, g->owner, g->pri (state allocated by alloc_state).
-pg_status finalize_state(pg_game *g, hipStream_t s, bool init_sp) {
+pg_status finalize_state(pg_game *g, hipStream_t s, bool init_sp,
+                         bool distinct) {
   const int64_t N = g->n_aug;
   int bits = 1;
   while ((int64_t(1) << bits) <= N + 1) ++bits;
@@ -533,7 +544,7 @@ pg_status finalize_state(pg_game *g, hipStream_t s, bool init_sp) {
                          g->scan_tmp, s);
   hipLaunchKernelGGL(k_rv_finish, dim3(grid_for(N)), dim3(kBlock), 0, s,
                      which ? g->sk1 : g->sk0, which ? g->sv1 : g->sv0, g->perm,
-                     g->rvpos, N, g->ctr);
+                     g->rvpos, N, (int)distinct, g->ctr);
   sum_dist(g->ctr, C_DIST_MISC, C_MISC, s);
   if (init_sp)
     hipLaunchKernelGGL(k_sp_init, dim3(grid_for(N)), dim3(kBlock), 0, s,
@@ -656,10 +667,28 @@ pg_status pg_load_csr(int64_t n, int64_t m, const void *offsets,
     return pg_fail(PG_EDEVICE, "no HIP device");
   }
   hipStream_t s = (hipStream_t)hip_stream;
-  pg_status st =
-      load_modified(n, m, offsets, targets, owner, priority, flags, s, g);
-  if (st == PG_OK) st = alloc_state(g, g->n_aug);
-  if (st == PG_OK) st = finalize_state(g, s, true);
+  // rank valuations unless asked for counts; repeated priorities switch to
+  // counts (the modified game is then built again with the dummies at 0)
+  bool dense = flags & PG_COUNT_VALUATION;
+  pg_status st;
+  for (;;) {
+    st = load_modified(n, m, offsets, targets, owner, priority, flags, s, g,
+                       dense);
+    if (st == PG_OK) st = alloc_state(g, g->n_aug);
+    if (st == PG_OK) st = finalize_state(g, s, true, !dense);
+    if (st == PG_OK || dense || !(g->hctr && (g->hctr[C_ERR] & ERR_DUPPRI)))
+      break;
+    (void)hipStreamSynchronize(s);
+    const int dev = g->device;
+    free_game(g);
+    g = new (std::nothrow) pg_game();
+    if (!g) return pg_fail(PG_ENOMEM, "host allocation failed");
+    g->device = dev;
+    g_last_error.clear();
+    dense = true;
+  }
+  if (st == PG_OK && dense) st = count_setup(g, s);
+  g->dense = dense;
   g->careful = flags & PG_CAREFUL_WALKS;
   if (st != PG_OK) {
     (void)hipStreamSynchronize(s);
@@ -667,6 +696,14 @@ pg_status pg_load_csr(int64_t n, int64_t m, const void *offsets,
     return st;
   }
   *out_game = g;
+  return PG_OK;
+}
+
+pg_status pg_count_info(const pg_game *g, int32_t *d, int32_t *values) {
+  if (!g || !d) return pg_fail(PG_EINVAL, "NULL argument");
+  *d = g->dense ? g->d : 0;
+  if (values && g->dense)
+    for (int j = 0; j < g->d; ++j) values[j] = g->values[j];
   return PG_OK;
 }
 
@@ -723,6 +760,9 @@ pg_status pg_valuation(pg_game *g, const int32_t *sigma, const int32_t *tau,
                        void *hip_stream) {
   if (!g) return pg_fail(PG_EINVAL, "game is NULL");
   if (!sigma || !tau || !key) return pg_fail(PG_EINVAL, "NULL argument");
+  if (g->dense)
+    return pg_fail(PG_EINVAL, "a count-valuation game has no rank keys: use "
+                              "pg_valuation_counts");
   DevGuard guard(g->device);
   hipStream_t s = (hipStream_t)hip_stream;
   const bool dev = flags & PG_PTR_DEVICE;
@@ -735,12 +775,33 @@ pg_status pg_valuation(pg_game *g, const int32_t *sigma, const int32_t *tau,
   return PG_OK;
 }
 
+pg_status pg_valuation_counts(pg_game *g, const int32_t *sigma,
+                              const int32_t *tau, int32_t *counts,
+                              uint8_t *top, int64_t *n_finite, uint32_t flags,
+                              void *hip_stream) {
+  if (!g) return pg_fail(PG_EINVAL, "game is NULL");
+  if (!sigma || !tau || !counts) return pg_fail(PG_EINVAL, "NULL argument");
+  if (!g->dense)
+    return pg_fail(PG_EINVAL, "not a count-valuation game: use pg_valuation");
+  DevGuard guard(g->device);
+  hipStream_t s = (hipStream_t)hip_stream;
+  const bool dev = flags & PG_PTR_DEVICE;
+  PG_TRY(import_strats(g, sigma, tau, dev, s));
+  valuation_reset(g, s);
+  PG_TRY(valuation_device(g, s, n_finite));
+  PG_TRY(export_counts(g, counts, top, dev, s));
+  return PG_OK;
+}
+
 pg_status pg_best_response(pg_game *g, const int32_t *sigma, int32_t *tau,
                            int32_t *key, int32_t *n_valuations,
                            int32_t max_inner, uint32_t flags,
                            void *hip_stream) {
   if (!g) return pg_fail(PG_EINVAL, "game is NULL");
   if (!sigma || !tau) return pg_fail(PG_EINVAL, "NULL argument");
+  if (key && g->dense)
+    return pg_fail(PG_EINVAL, "a count-valuation game has no rank keys: "
+                              "pass key = NULL");
   DevGuard guard(g->device);
   hipStream_t s = (hipStream_t)hip_stream;
   const bool dev = flags & PG_PTR_DEVICE;
@@ -801,7 +862,7 @@ pg_status pg_solve(pg_game *g, const pg_solve_opts *opts, uint8_t *winner,
   uint8_t *dw = winner;
   if (!dev) dw = (uint8_t *)g->wl0;
   hipLaunchKernelGGL(k_winner, dim3(grid_for(g->n)), dim3(kBlock), 0, s,
-                     g->key, dw, g->n);
+                     g->rs, dw, g->n);
   if (!dev) PG_TRY(copy_out(winner, dw, g->n, false, s));
   PG_HIP(hipStreamSynchronize(s));
   PG_TRY(export_strats(g, sigma, tau, dev, s));

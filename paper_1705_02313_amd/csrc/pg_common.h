@@ -173,6 +173,18 @@ struct pg_game {
   pgk::RankLevel lv[8];
   int nlevels = 0;
 
+  // count valuations (repeated priorities; see pg_count.hip)
+  bool dense = false;
+  int32_t d = 0;              // distinct priorities in use
+  int32_t dw = 0;             // ints per count row: d rounded up to 4/8/16/32
+  uint32_t odd_cols = 0;      // bit j: the j-th smallest priority is odd
+  int32_t values[32] = {};    // the distinct priorities, increasing
+  int32_t *cvals = nullptr;   // [32] the same on the device
+  uint8_t *pidx = nullptr;    // [n_aug] column of each vertex's priority
+  int32_t *cnt = nullptr;     // [(n_aug+1) * dw] counts; row n_aug: the sink
+  int32_t *vsum[8] = {};      // per level: dw ints per splitter
+  int32_t *vbase[8] = {};
+
   unsigned long long *u64tmp = nullptr;  // [2] scratch for 64-bit sums
   int32_t *ctr = nullptr;    // [C_TOTAL] device counters
   int32_t *hctr = nullptr;   // pinned host mirror
@@ -212,6 +224,22 @@ __device__ __forceinline__ void count_block(int32_t *dist, bool pred) {
   __syncthreads();
   if (threadIdx.x == 0 && blk)
     atomicAdd(&dist[(blockIdx.x % kDistSlots) * kDistStride], blk);
+}
+
+__device__ __forceinline__ int ld_relaxed(const int32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void st_relaxed(int32_t *p, int32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+constexpr int kStride = 32;        // splitter stride at every level
+
+// size of level k of the sublist ranking for an Euler list of L elements
+__device__ __host__ __forceinline__ int64_t level_size(int64_t L, int k) {
+  for (int j = 0; j < k; ++j) L = (L + kStride - 1) / kStride;
+  return L;
 }
 
 // ctr[dst] += sum of the distributed counter at ctr + dist (one block).
@@ -263,6 +291,23 @@ pg_status switch_device(pg_game *g, bool odd, hipStream_t s, int32_t *count);
 pg_status iteration_device(pg_game *g, hipStream_t s, int32_t *count);
 }  // namespace pgk
 
+// ---- count valuations (pg_count.hip) ---------------------------------------
+namespace pgk {
+constexpr int kCountMax = 32;   // most distinct priorities of a count game
+// After finalize_state: the distinct priorities, each vertex's column and
+// the count buffers.  PG_EINVAL when more than kCountMax priorities are used.
+pg_status count_setup(pg_game *g, hipStream_t s);
+// walking levels of the vector list ranking for games of n_aug vertices
+int count_levels(int64_t n_aug, int dw);
+// Euler list and vector list ranking after the walks; gated by C_ABORT.
+void enqueue_count(pg_game *g, hipStream_t s);
+// All_Odd (odd) or All_Even on count valuations; counts into C_DIST_SW.
+void enqueue_count_switch(pg_game *g, bool odd, hipStream_t s);
+// counts[(n_aug+1) * d] row-major (top rows zero) and top[n_aug]
+pg_status export_counts(pg_game *g, int32_t *counts, uint8_t *top, bool dev,
+                        hipStream_t s);
+}  // namespace pgk
+
 // ---- loading helpers shared by single games and batches (pg_api.hip) ------
 namespace pgk {
 __global__ void k_rv_keys(const int32_t *pri, uint32_t *sk, uint32_t *sv,
@@ -289,6 +334,8 @@ pg_status check_err(pg_game *g, const char *what);
 pg_status load_modified(int64_t n, int64_t m, const void *offsets,
                         const int32_t *targets, const uint8_t *owner,
                         const int32_t *priority, uint32_t flags, hipStream_t s,
-                        pg_game *g);
-pg_status finalize_state(pg_game *g, hipStream_t s, bool init_sp);
+                        pg_game *g, bool dense = false);
+// distinct: reject repeated priorities (rank valuations)
+pg_status finalize_state(pg_game *g, hipStream_t s, bool init_sp,
+                         bool distinct = true);
 }  // namespace pgk

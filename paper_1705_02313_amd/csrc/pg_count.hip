@@ -1,0 +1,691 @@
+// Count valuations for games whose priorities repeat: the paper's own
+// representation (section 3, "Valuations": a finite valuation counts how
+// often each priority occurs on the play to the sink) computed the paper's
+// way (section 5, "Formal reduction to list ranking"): one list ranking over
+// the Euler tour of the tree of finite vertices rooted at the sink, with the
+// weight +1 at pri(v) on the edge entering v and -1 on the edge leaving it,
+// and vector addition as the operator.  The exclusive prefix at the edge
+// leaving v is Val(v).
+//
+// Steps per valuation (after the walks of pg_val.hip have classified every
+// vertex as finite or top):
+//   1. compaction: finite vertex v gets position f; element 0 is the sink's
+//      list head, 2f+1 the edge entering v, 2f+2 the edge leaving it;
+//   2. the list by the atomic-exchange construction (section 5,
+//      "Constructing the list ranking instance in parallel"): start(x) is
+//      the end of x's list so far; every finite v swaps the edge leaving v
+//      into start(parent) and links the previous end to the edge entering v;
+//      a last pass links the end of every list to the edge leaving its
+//      vertex (the sink's list ends the tour);
+//   3. list ranking by sublists (section 5, "List ranking") with count
+//      vectors of dw ints as weights: level-1 sums, recursive levels, the top
+//      level by pointer jumping in LDS, bases handed back down, and a last
+//      walk that writes every finite vertex's counts.
+// Switching compares count rows by Maxdiff (the largest column that differs
+// decides by the parity of its priority); top is above every count vector.
+#include <algorithm>
+
+#include "pg_common.h"
+
+namespace pgk {
+
+constexpr int kVTopThreads = 1024;
+constexpr int kVTopInts = 8192;   // LDS ints holding the top level's sums
+
+__host__ __device__ constexpr int vtop_max(int D) { return kVTopInts / D; }
+
+// ---------------------------------------------------------------------------
+// set-up: distinct priorities and each vertex's column
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int32_t decode_signed(uint32_t k) {
+  // inverse of the signed-priority key (odd descending, then even ascending)
+  return k < 0x80000000u ? (int32_t)(0x7fffffffu - k)
+                         : (int32_t)(k - 0x80000000u);
+}
+
+__global__ void k_cnt_count_distinct(const uint32_t *skS, int64_t n,
+                                     int32_t *ctr) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool first = i < n && (i == 0 || skS[i] != skS[i - 1]);
+  count_block(&ctr[C_DIST_MISC], first);
+}
+
+// only launched once at most kCountMax distinct keys are known to exist
+__global__ void k_cnt_write_distinct(const uint32_t *skS, int64_t n,
+                                     int32_t *vals, int32_t *ctr) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || (i > 0 && skS[i] == skS[i - 1])) return;
+  const int slot = atomicAdd(&ctr[C_MISC], 1);
+  if (slot < kCountMax) vals[slot] = decode_signed(skS[i]);
+}
+
+__global__ void k_cnt_pidx(const int32_t *pri, int64_t n,
+                           const int32_t *__restrict__ vals, int d,
+                           uint8_t *pidx) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int32_t p = pri[v];
+  int lo = 0, hi = d - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (vals[mid] < p) lo = mid + 1;
+    else hi = mid;
+  }
+  pidx[v] = (uint8_t)lo;
+}
+
+// ---------------------------------------------------------------------------
+// the Euler list of the tree of finite vertices
+// ---------------------------------------------------------------------------
+__global__ void k_cnt_flags(int32_t N, const uint8_t *rs, uint32_t *f,
+                            const int32_t *ctr) {
+  if (ctr[C_ABORT]) return;
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < N) f[v] = rs[v] == 1;
+}
+
+// Positions of the finite vertices, the payloads of their two elements
+// (vertex id, bit 31 on the edge leaving it) and the initial list ends.
+__global__ void k_cnt_compact(int32_t N, const uint8_t *__restrict__ rs,
+                              const uint32_t *__restrict__ fscan,
+                              int32_t *fpos, int32_t *fvert, int32_t *start,
+                              int2 *elem, int32_t *ctr) {
+  if (ctr[C_ABORT]) return;
+  const int32_t nF = ctr[C_NFIN];
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v == 0) {
+    start[nF] = 0;       // the sink's list starts at the head element
+    elem[0].y = N;       // the head carries no weight
+    fpos[N] = nF;
+  }
+  if (v >= N || rs[v] != 1) return;
+  const int32_t f = (int32_t)fscan[v];
+  if (f >= nF) {  // the finite count and the compaction disagree
+    atomicOr(&ctr[C_ERR], ERR_RANKCOUNT);
+    return;
+  }
+  fpos[v] = f;
+  fvert[f] = (int32_t)v;
+  start[f] = 2 * f + 1;
+  elem[2 * f + 1].y = (int32_t)v;
+  elem[2 * f + 2].y = (int32_t)v | (int32_t)0x80000000;
+}
+
+// Every finite v appends the tour of its subtree to its parent's list.
+__global__ void k_cnt_link(int32_t N, const int32_t *__restrict__ fvert,
+                           const int2 *__restrict__ sp,
+                           const int32_t *__restrict__ fpos, int32_t *start,
+                           int2 *elem, const int32_t *ctr) {
+  if (ctr[C_ABORT] || (ctr[C_ERR] & ERR_RANKCOUNT)) return;
+  const int32_t nF = ctr[C_NFIN];
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nF) return;
+  const int32_t v = fvert[f];
+  const int32_t u = sp[v].x;                 // finite or the sink
+  const int32_t pu = (u == N) ? nF : fpos[u];
+  const int32_t old = atomicExch(&start[pu], (int32_t)(2 * f + 2));
+  elem[old].x = (int32_t)(2 * f + 1);
+}
+
+// The end of every finite vertex's list leads to the edge leaving it; the
+// sink's list ends the tour.
+__global__ void k_cnt_close(const int32_t *__restrict__ start, int2 *elem,
+                            const int32_t *ctr) {
+  if (ctr[C_ABORT] || (ctr[C_ERR] & ERR_RANKCOUNT)) return;
+  const int32_t nF = ctr[C_NFIN];
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f > nF) return;
+  elem[start[f]].x = (f == nF) ? -1 : (int32_t)(2 * f + 2);
+}
+
+// ---------------------------------------------------------------------------
+// vector list ranking
+// ---------------------------------------------------------------------------
+// adds s at column col without indexing a register array at run time
+template <int D>
+__device__ __forceinline__ void add_unit(int32_t (&a)[D], int col,
+                                         int32_t s) {
+#pragma unroll
+  for (int i = 0; i < D; ++i) a[i] += (i == col) ? s : 0;
+}
+
+template <int D>
+__device__ __forceinline__ void load_vec(const int32_t *p, int32_t (&a)[D]) {
+  const int4 *q = reinterpret_cast<const int4 *>(p);
+#pragma unroll
+  for (int i = 0; i < D / 4; ++i) {
+    const int4 x = q[i];
+    a[4 * i] = x.x;
+    a[4 * i + 1] = x.y;
+    a[4 * i + 2] = x.z;
+    a[4 * i + 3] = x.w;
+  }
+}
+
+template <int D>
+__device__ __forceinline__ void store_vec(int32_t *p, const int32_t (&a)[D]) {
+  int4 *q = reinterpret_cast<int4 *>(p);
+#pragma unroll
+  for (int i = 0; i < D / 4; ++i)
+    q[i] = make_int4(a[4 * i], a[4 * i + 1], a[4 * i + 2], a[4 * i + 3]);
+}
+
+// Level 1: each splitter (element index a multiple of kStride; element 0,
+// the head, is one) sums the weights of its sublist.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_vlr_sum1(
+    int32_t N, const int2 *__restrict__ elem,
+    const uint8_t *__restrict__ pidx, int per_thread, int32_t *vsum,
+    int32_t *next, int32_t *ctr) {
+  if (ctr[C_ABORT]) return;
+  const int64_t L = 2 * (int64_t)ctr[C_NFIN] + 1;
+  const int64_t nsplit = level_size(L, 1);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
+  for (int k = 0; k < per_thread; ++k) {
+    const int64_t j = t + (int64_t)k * nthreads;
+    if (j >= nsplit) break;
+    int64_t e = j * kStride;
+    int32_t acc[D] = {};
+    int64_t steps = 0;
+    for (;;) {
+      const int2 el = elem[e];
+      const int32_t x = el.y & 0x7fffffff;
+      if (x < N) add_unit<D>(acc, pidx[x], el.y < 0 ? -1 : 1);
+      e = el.x;
+      if (e < 0 || e % kStride == 0) break;
+      if (++steps > L) {
+        atomicOr(&ctr[C_ERR], ERR_LISTWALK);
+        e = -1;
+        break;
+      }
+    }
+    store_vec<D>(vsum + j * D, acc);
+    next[j] = e < 0 ? -1 : (int32_t)(e / kStride);
+  }
+}
+
+// Level k >= 2: the same over the list of level-(k-1) splitters.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_vlr_sumk(
+    const int32_t *__restrict__ lnext, const int32_t *__restrict__ lw,
+    int level, int32_t *vsum, int32_t *next, int32_t *ctr) {
+  if (ctr[C_ABORT]) return;
+  const int64_t L = 2 * (int64_t)ctr[C_NFIN] + 1;
+  const int64_t size = level_size(L, level);
+  const int64_t nsplit = level_size(L, level + 1);
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nsplit) return;
+  int64_t e = j * kStride;
+  int32_t acc[D] = {};
+  int64_t steps = 0;
+  for (;;) {
+    int32_t w[D];
+    load_vec<D>(lw + e * D, w);
+#pragma unroll
+    for (int i = 0; i < D; ++i) acc[i] += w[i];
+    e = lnext[e];
+    if (e < 0 || e % kStride == 0) break;
+    if (++steps > size) {
+      atomicOr(&ctr[C_ERR], ERR_LISTWALK);
+      e = -1;
+      break;
+    }
+  }
+  store_vec<D>(vsum + j * D, acc);
+  next[j] = e < 0 ? -1 : (int32_t)(e / kStride);
+}
+
+// The top level (at most vtop_max(D) nodes, head = 0) in one block: suffix
+// sums by pointer jumping in LDS, then base = total - suffix.  The whole tour
+// sums to the zero vector (every vertex is entered and left once).
+template <int D>
+__global__ __launch_bounds__(kVTopThreads) void k_vlr_top(
+    const int32_t *__restrict__ lnext, const int32_t *__restrict__ lw,
+    int level, int32_t *base, int32_t *ctr) {
+  if (ctr[C_ABORT]) return;
+  constexpr int TM = vtop_max(D);
+  constexpr int per = (TM + kVTopThreads - 1) / kVTopThreads;
+  __shared__ int32_t nx[TM];
+  __shared__ int32_t sm[TM * D];
+  const int64_t L0 = 2 * (int64_t)ctr[C_NFIN] + 1;
+  const int32_t T = (int32_t)level_size(L0, level);
+  if (T > TM) {
+    if (threadIdx.x == 0) atomicOr(&ctr[C_ERR], ERR_LISTWALK);
+    return;
+  }
+  for (int k = 0; k < per; ++k) {
+    const int i = threadIdx.x + k * kVTopThreads;
+    if (i >= TM) break;
+    nx[i] = (i < T) ? lnext[i] : -1;
+#pragma unroll
+    for (int c = 0; c < D; ++c) sm[i * D + c] = (i < T) ? lw[i * D + c] : 0;
+  }
+  __syncthreads();
+  for (int round = 0; (1 << round) < T; ++round) {
+    int32_t nn[per], ss[per][D];
+    for (int k = 0; k < per; ++k) {
+      const int i = threadIdx.x + k * kVTopThreads;
+      if (i >= TM) break;
+      const int p = nx[i];
+      nn[k] = (p >= 0) ? nx[p] : -1;
+#pragma unroll
+      for (int c = 0; c < D; ++c)
+        ss[k][c] = sm[i * D + c] + ((p >= 0) ? sm[p * D + c] : 0);
+    }
+    __syncthreads();
+    for (int k = 0; k < per; ++k) {
+      const int i = threadIdx.x + k * kVTopThreads;
+      if (i >= TM) break;
+      nx[i] = nn[k];
+#pragma unroll
+      for (int c = 0; c < D; ++c) sm[i * D + c] = ss[k][c];
+    }
+    __syncthreads();
+  }
+  for (int k = 0; k < per; ++k) {
+    const int i = threadIdx.x + k * kVTopThreads;
+    if (i >= T) break;
+#pragma unroll
+    for (int c = 0; c < D; ++c) base[i * D + c] = sm[c] - sm[i * D + c];
+  }
+  if (threadIdx.x < D && sm[threadIdx.x] != 0)
+    atomicOr(&ctr[C_ERR], ERR_RANKCOUNT);
+}
+
+// Hands each node of a level-k sublist its exclusive prefix vector.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_vlr_distk(
+    const int32_t *__restrict__ lnext, const int32_t *__restrict__ lw,
+    int level, const int32_t *__restrict__ sbase, int32_t *lbase,
+    const int32_t *ctr) {
+  if (ctr[C_ABORT]) return;
+  const int64_t L = 2 * (int64_t)ctr[C_NFIN] + 1;
+  const int64_t size = level_size(L, level);
+  const int64_t nsplit = level_size(L, level + 1);
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nsplit) return;
+  int64_t e = j * kStride;
+  int32_t b[D];
+  load_vec<D>(sbase + j * D, b);
+  for (int64_t steps = 0; steps <= size; ++steps) {
+    store_vec<D>(lbase + e * D, b);
+    int32_t w[D];
+    load_vec<D>(lw + e * D, w);
+#pragma unroll
+    for (int i = 0; i < D; ++i) b[i] += w[i];
+    e = lnext[e];
+    if (e < 0 || e % kStride == 0) break;
+  }
+}
+
+// Last walk of every level-1 sublist: the edge leaving v emits Val(v), the
+// exclusive prefix at that element.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_vlr_emit1(
+    int32_t N, const int2 *__restrict__ elem,
+    const uint8_t *__restrict__ pidx, int per_thread,
+    const int32_t *__restrict__ sbase, int32_t *cnt, const int32_t *ctr) {
+  if (ctr[C_ABORT]) return;
+  const int64_t L = 2 * (int64_t)ctr[C_NFIN] + 1;
+  const int64_t nsplit = level_size(L, 1);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
+  for (int k = 0; k < per_thread; ++k) {
+    const int64_t j = t + (int64_t)k * nthreads;
+    if (j >= nsplit) break;
+    int64_t e = j * kStride;
+    int32_t b[D];
+    load_vec<D>(sbase + j * D, b);
+    for (int64_t steps = 0; steps <= L; ++steps) {
+      const int2 el = elem[e];
+      const int32_t x = el.y & 0x7fffffff;
+      if (x < N) {
+        const int col = pidx[x];
+        if (el.y < 0) {
+          store_vec<D>(cnt + (int64_t)x * D, b);
+          add_unit<D>(b, col, -1);
+        } else {
+          add_unit<D>(b, col, 1);
+        }
+      }
+      e = el.x;
+      if (e < 0 || e % kStride == 0) break;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// switching on count valuations
+// ---------------------------------------------------------------------------
+// -1: a below b, 0: equal, 1: above.  Top equals top and is above every
+// count vector; otherwise the largest differing column decides: a larger
+// count is better at an even priority, worse at an odd one.
+template <int D>
+__device__ __forceinline__ int vcmp(bool ta, const int32_t (&a)[D], bool tb,
+                                    const int32_t (&b)[D], uint32_t odd_cols) {
+  if (ta || tb) return ta == tb ? 0 : (ta ? 1 : -1);
+  int r = 0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    if (a[i] != b[i]) {
+      const bool even = !((odd_cols >> i) & 1u);
+      r = ((a[i] < b[i]) == even) ? -1 : 1;
+    }
+  }
+  return r;
+}
+
+// the valuation of vertex u (u == N: the sink, the zero vector)
+template <int D>
+__device__ __forceinline__ bool load_val(int32_t N, const uint8_t *rs,
+                                         const int32_t *cnt, int32_t u,
+                                         int32_t (&a)[D]) {
+  load_vec<D>(cnt + (int64_t)u * D, a);
+  return u < N && rs[u] == 2;
+}
+
+// All_Odd (section 4): the first successor of least valuation, if strictly
+// below the current choice.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_cnt_odd_switch(
+    int32_t N, int64_t count, const int32_t *__restrict__ ids,
+    const int64_t *__restrict__ off, const int32_t *__restrict__ tgt,
+    const uint8_t *__restrict__ rs, const int32_t *__restrict__ cnt,
+    uint32_t odd_cols, const int32_t *__restrict__ pri, int2 *sp,
+    int32_t *ctr) {
+  if (ctr[C_ABORT]) return;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool sw = false;
+  if (t < count) {
+    const int32_t v = ids[t];
+    const int64_t e0 = off[v], e1 = off[v + 1];
+    int32_t best = tgt[e0];
+    int32_t bv[D];
+    bool bt = load_val<D>(N, rs, cnt, best, bv);
+    for (int64_t e = e0 + 1; e < e1; ++e) {
+      const int32_t u = tgt[e];
+      int32_t uv[D];
+      const bool ut = load_val<D>(N, rs, cnt, u, uv);
+      if (vcmp<D>(ut, uv, bt, bv, odd_cols) < 0) {
+        best = u;
+        bt = ut;
+#pragma unroll
+        for (int i = 0; i < D; ++i) bv[i] = uv[i];
+      }
+    }
+    const int32_t cur = sp[v].x;
+    int32_t cv[D];
+    const bool ct = load_val<D>(N, rs, cnt, cur, cv);
+    if (vcmp<D>(bt, bv, ct, cv, odd_cols) < 0) {
+      sp[v] = make_int2(best, pri[best]);
+      sw = true;
+    }
+  }
+  count_block(&ctr[C_DIST_SW], sw);
+}
+
+// All_Even, greedy all-switches (section 3): the sink first, then the row;
+// the first option of greatest valuation, if strictly above the current one.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_cnt_even_switch(
+    int32_t N, int64_t count, const int32_t *__restrict__ ids,
+    const int64_t *__restrict__ off, const int32_t *__restrict__ tgt,
+    const uint8_t *__restrict__ rs, const int32_t *__restrict__ cnt,
+    uint32_t odd_cols, const int32_t *__restrict__ pri, int2 *sp,
+    int32_t *ctr) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool sw = false;
+  if (t < count) {
+    const int32_t v = ids[t];
+    const int64_t e0 = off[v], e1 = off[v + 1];
+    int32_t best = N;
+    int32_t bv[D] = {};
+    bool bt = false;
+    for (int64_t e = e0; e < e1; ++e) {
+      const int32_t u = tgt[e];
+      int32_t uv[D];
+      const bool ut = load_val<D>(N, rs, cnt, u, uv);
+      if (vcmp<D>(ut, uv, bt, bv, odd_cols) > 0) {
+        best = u;
+        bt = ut;
+#pragma unroll
+        for (int i = 0; i < D; ++i) bv[i] = uv[i];
+      }
+    }
+    const int32_t cur = sp[v].x;
+    int32_t cv[D];
+    const bool ct = load_val<D>(N, rs, cnt, cur, cv);
+    if (vcmp<D>(bt, bv, ct, cv, odd_cols) > 0) {
+      sp[v] = make_int2(best, best == N ? 2147483647 : pri[best]);
+      sw = true;
+    }
+  }
+  count_block(&ctr[C_DIST_SW], sw);
+}
+
+// counts out[(N+1) * d] (rows of top vertices zero) and top[N]
+template <int D>
+__global__ void k_cnt_export(int32_t N, int d, const uint8_t *rs,
+                             const int32_t *cnt, int32_t *out, uint8_t *top) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v > N) return;
+  const bool tp = v < N && rs[v] == 2;
+  if (v < N && top) top[v] = tp;
+  for (int j = 0; j < d; ++j) out[v * d + j] = tp ? 0 : cnt[v * D + j];
+}
+
+}  // namespace pgk
+
+// ===========================================================================
+// host side
+// ===========================================================================
+namespace pgk {
+
+constexpr int kVPerThread1 = 4;   // level-1 sublists per thread
+
+int count_levels(int64_t n_aug, int dw) {
+  const int64_t Lmax = 2 * n_aug + 1;
+  int k = 1;
+  while (level_size(Lmax, k) > vtop_max(dw)) ++k;
+  return k;
+}
+
+pg_status count_setup(pg_game *g, hipStream_t s) {
+  const int64_t N = g->n_aug;
+  // the distinct priorities, from the signed-priority order
+  hipLaunchKernelGGL(k_rv_keys, dim3(grid_for(N)), dim3(kBlock), 0, s, g->pri,
+                     g->sk0, g->sv0, N);
+  const int w = radix_sort(g->sk0, g->sv0, g->sk1, g->sv1, N, 32, g->tile_cnt,
+                           g->scan_tmp, s);
+  const uint32_t *skS = w ? g->sk1 : g->sk0;
+  fill_i32(g->ctr, 0, C_TOTAL, s);
+  hipLaunchKernelGGL(k_cnt_count_distinct, dim3(grid_for(N)), dim3(kBlock), 0,
+                     s, skS, N, g->ctr);
+  sum_dist(g->ctr, C_DIST_MISC, C_MISC, s);
+  PG_TRY(sync_ctr(g, s));
+  const int d = g->hctr[C_MISC];
+  if (d < 1 || d > kCountMax)
+    return pg_fail(PG_EINVAL,
+                   "count valuations support at most 32 distinct priorities "
+                   "(after preprocessing); this game uses " +
+                       std::to_string(d));
+  PG_TRY(dev_alloc(&g->cvals, kCountMax));
+  fill_i32(g->ctr + C_MISC, 0, 1, s);
+  hipLaunchKernelGGL(k_cnt_write_distinct, dim3(grid_for(N)), dim3(kBlock), 0,
+                     s, skS, N, g->cvals, g->ctr);
+  PG_HIP(hipMemcpyAsync(g->values, g->cvals, sizeof(int32_t) * d,
+                        hipMemcpyDeviceToHost, s));
+  PG_HIP(hipStreamSynchronize(s));
+  std::sort(g->values, g->values + d);
+  PG_HIP(hipMemcpyAsync(g->cvals, g->values, sizeof(int32_t) * d,
+                        hipMemcpyHostToDevice, s));
+  g->d = d;
+  g->dw = d <= 4 ? 4 : d <= 8 ? 8 : d <= 16 ? 16 : 32;
+  g->odd_cols = 0;
+  for (int j = 0; j < d; ++j)
+    if (g->values[j] & 1) g->odd_cols |= 1u << j;
+  PG_TRY(dev_alloc(&g->pidx, N));
+  hipLaunchKernelGGL(k_cnt_pidx, dim3(grid_for(N)), dim3(kBlock), 0, s, g->pri,
+                     N, g->cvals, d, g->pidx);
+  // count rows; the sink's row stays zero
+  PG_TRY(dev_alloc(&g->cnt, (N + 1) * g->dw));
+  fill_i32(g->cnt, 0, (N + 1) * g->dw, s);
+  int64_t size = 2 * N + 1;
+  for (int k = 0; k < 8; ++k) {
+    const int64_t ns = (size + kStride - 1) / kStride;
+    PG_TRY(dev_alloc(&g->vsum[k], ns * g->dw));
+    PG_TRY(dev_alloc(&g->vbase[k], ns * g->dw));
+    size = ns;
+    if (size <= 1) break;
+  }
+  PG_HIP(hipStreamSynchronize(s));
+  return PG_OK;
+}
+
+template <int D>
+static void enqueue_count_t(pg_game *g, hipStream_t s) {
+  const int32_t N = (int32_t)g->n_aug;
+  Prof *pf = &g->prof;
+  const int32_t *gate = g->ctr + C_ABORT;
+  uint32_t *flags = g->sk0, *fscan = g->sk1;
+  int32_t *start = reinterpret_cast<int32_t *>(g->fh);
+  // rs 1, flag 4; then the scan
+  PG_LAUNCH(pf, K_LINK_INFO, 5.0 * N, k_cnt_flags, dim3(grid_for(N)),
+            dim3(kBlock), 0, s, N, g->rs, flags, g->ctr);
+  scan_excl_u32(flags, fscan, N, g->scan_tmp, s, pf, gate);
+  // rs 1, scan 4 per vertex; fpos, fvert, start, two payloads 20 per finite
+  PG_LAUNCH(pf, K_LINK_INFO, 5.0 * N, k_cnt_compact, dim3(grid_for(N)),
+            dim3(kBlock), 0, s, N, g->rs, fscan, g->pos, g->kids, start,
+            g->elem, g->ctr);
+  // fvert 4, play-graph record 8, fpos 4, exchange 8, link 4; close 8
+  PG_LAUNCH_NF(pf, K_LINK_BUILD, 28.0, k_cnt_link, dim3(grid_for(N)),
+               dim3(kBlock), 0, s, N, g->kids, g->sp, g->pos, start, g->elem,
+               g->ctr);
+  PG_LAUNCH_NF(pf, K_LINK_BUILD, 8.0, k_cnt_close, dim3(grid_for(N + 1)),
+               dim3(kBlock), 0, s, start, g->elem, g->ctr);
+  const int nl = g->nlevels;
+  const int64_t Lmax = 2 * (int64_t)N + 1;
+  const int64_t ns1 = level_size(Lmax, 1);
+  const int64_t thr1 = (ns1 + kVPerThread1 - 1) / kVPerThread1;
+  // two elements (8 B each) and two column reads per finite vertex
+  PG_LAUNCH_NF(pf, K_LR_SUM1, 18.0, k_vlr_sum1<D>, dim3(grid_for(thr1)),
+               dim3(kBlock), 0, s, N, g->elem, g->pidx, kVPerThread1,
+               g->vsum[0], g->lv[0].next, g->ctr);
+  for (int k = 1; k < nl; ++k) {
+    const int64_t nsk = level_size(Lmax, k + 1);
+    PG_LAUNCH_NF(pf, K_LR_SUMK,
+                 (4.0 * D + 4.0) * 2.0 * (double)level_size(Lmax, k) /
+                     (double)Lmax,
+                 k_vlr_sumk<D>, dim3(grid_for(nsk)), dim3(kBlock), 0, s,
+                 g->lv[k - 1].next, g->vsum[k - 1], k, g->vsum[k],
+                 g->lv[k].next, g->ctr);
+  }
+  PG_LAUNCH(pf, K_LR_TOP, (8.0 * D + 4.0) * level_size(Lmax, nl),
+            k_vlr_top<D>, dim3(1), dim3(kVTopThreads), 0, s,
+            g->lv[nl - 1].next, g->vsum[nl - 1], nl, g->vbase[nl - 1],
+            g->ctr);
+  for (int k = nl - 1; k >= 1; --k) {
+    const int64_t nsk = level_size(Lmax, k + 1);
+    PG_LAUNCH_NF(pf, K_LR_DISTK,
+                 (8.0 * D + 4.0) * 2.0 * (double)level_size(Lmax, k) /
+                     (double)Lmax,
+                 k_vlr_distk<D>, dim3(grid_for(nsk)), dim3(kBlock), 0, s,
+                 g->lv[k - 1].next, g->vsum[k - 1], k, g->vbase[k],
+                 g->vbase[k - 1], g->ctr);
+  }
+  // two elements and two column reads per finite vertex, one count row
+  PG_LAUNCH_NF(pf, K_LR_EMIT1, 18.0 + 4.0 * D, k_vlr_emit1<D>,
+               dim3(grid_for(thr1)), dim3(kBlock), 0, s, N, g->elem, g->pidx,
+               kVPerThread1, g->vbase[0], g->cnt, g->ctr);
+}
+
+void enqueue_count(pg_game *g, hipStream_t s) {
+  switch (g->dw) {
+    case 4: enqueue_count_t<4>(g, s); break;
+    case 8: enqueue_count_t<8>(g, s); break;
+    case 16: enqueue_count_t<16>(g, s); break;
+    default: enqueue_count_t<32>(g, s); break;
+  }
+}
+
+template <int D>
+static void enqueue_count_switch_t(pg_game *g, bool odd, hipStream_t s) {
+  const int32_t N = (int32_t)g->n_aug;
+  Prof *pf = &g->prof;
+  fill_i32(g->ctr + C_DIST_SW, 0, kDistSlots * kDistStride, s, pf);
+  // per vertex: id 4, two offsets 16, current choice 8 and its row; per
+  // edge: target 4, its top flag 1 and its count row 4 D
+  if (odd) {
+    const int64_t cnt = g->n_odd;
+    if (cnt > 0)
+      PG_LAUNCH(pf, K_ODD_SWITCH,
+                (28.0 + 4.0 * D) * cnt + (5.0 + 4.0 * D) * g->m_odd,
+                k_cnt_odd_switch<D>, dim3(grid_for(cnt)), dim3(kBlock), 0, s,
+                N, cnt, g->odd_ids, g->off, g->tgt, g->rs, g->cnt,
+                g->odd_cols, g->pri, g->sp, g->ctr);
+  } else {
+    const int64_t cnt = N - g->n_odd;
+    if (cnt > 0)
+      PG_LAUNCH(pf, K_EVEN_SWITCH,
+                (28.0 + 4.0 * D) * cnt +
+                    (5.0 + 4.0 * D) * (g->m_aug - g->m_odd),
+                k_cnt_even_switch<D>, dim3(grid_for(cnt)), dim3(kBlock), 0, s,
+                N, cnt, g->even_ids, g->off, g->tgt, g->rs, g->cnt,
+                g->odd_cols, g->pri, g->sp, g->ctr);
+  }
+  sum_dist(g->ctr, C_DIST_SW, C_SWITCH, s, pf);
+}
+
+void enqueue_count_switch(pg_game *g, bool odd, hipStream_t s) {
+  switch (g->dw) {
+    case 4: enqueue_count_switch_t<4>(g, odd, s); break;
+    case 8: enqueue_count_switch_t<8>(g, odd, s); break;
+    case 16: enqueue_count_switch_t<16>(g, odd, s); break;
+    default: enqueue_count_switch_t<32>(g, odd, s); break;
+  }
+}
+
+pg_status export_counts(pg_game *g, int32_t *counts, uint8_t *top, bool dev,
+                        hipStream_t s) {
+  const int64_t N = g->n_aug;
+  const int64_t nc = (N + 1) * g->d;
+  int32_t *dc = counts;
+  uint8_t *dt = top;
+  struct Tmp {
+    void *p[2] = {nullptr, nullptr};
+    ~Tmp() {
+      for (void *x : p)
+        if (x) (void)hipFree(x);
+    }
+  } tmp;
+  if (!dev) {
+    PG_TRY(dev_alloc(&dc, nc));
+    tmp.p[0] = dc;
+    if (top) {
+      PG_TRY(dev_alloc(&dt, N));
+      tmp.p[1] = dt;
+    }
+  }
+  const unsigned grid = grid_for(N + 1);
+  switch (g->dw) {
+    case 4: hipLaunchKernelGGL(k_cnt_export<4>, dim3(grid), dim3(kBlock), 0, s,
+                               (int32_t)N, g->d, g->rs, g->cnt, dc, dt); break;
+    case 8: hipLaunchKernelGGL(k_cnt_export<8>, dim3(grid), dim3(kBlock), 0, s,
+                               (int32_t)N, g->d, g->rs, g->cnt, dc, dt); break;
+    case 16: hipLaunchKernelGGL(k_cnt_export<16>, dim3(grid), dim3(kBlock), 0,
+                                s, (int32_t)N, g->d, g->rs, g->cnt, dc, dt);
+      break;
+    default: hipLaunchKernelGGL(k_cnt_export<32>, dim3(grid), dim3(kBlock), 0,
+                                s, (int32_t)N, g->d, g->rs, g->cnt, dc, dt);
+      break;
+  }
+  if (!dev) {
+    PG_TRY(copy_out(counts, dc, sizeof(int32_t) * nc, false, s));
+    if (top) PG_TRY(copy_out(top, dt, N, false, s));
+  }
+  PG_HIP(hipStreamSynchronize(s));
+  return PG_OK;
+}
+
+}  // namespace pgk

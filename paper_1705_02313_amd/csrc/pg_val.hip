@@ -34,21 +34,6 @@
 
 namespace pgk {
 
-__device__ __forceinline__ int ld_relaxed(const int32_t *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ void st_relaxed(int32_t *p, int32_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-constexpr int kStride = 32;        // splitter stride at every level
-
-// size of level k of the sublist ranking for an Euler list of L elements
-__device__ __host__ __forceinline__ int64_t level_size(int64_t L, int k) {
-  for (int j = 0; j < k; ++j) L = (L + kStride - 1) / kStride;
-  return L;
-}
 
 // ---------------------------------------------------------------------------
 // ng: nearest greater vertex along the play
@@ -780,6 +765,18 @@ static void enqueue_switch(pg_game *g, bool odd, hipStream_t s) {
   sum_dist(g->ctr, C_DIST_SW, C_SWITCH, s, pf);
 }
 
+// The valuation after the walks: rank keys (distinct priorities) or count
+// vectors (pg_count.hip).
+static void enqueue_values(pg_game *g, hipStream_t s) {
+  if (g->dense) enqueue_count(g, s);
+  else enqueue_rank(g, s);
+}
+
+static void enqueue_any_switch(pg_game *g, bool odd, hipStream_t s) {
+  if (g->dense) enqueue_count_switch(g, odd, s);
+  else enqueue_switch(g, odd, s);
+}
+
 static pg_status check_ctr(pg_game *g) {
   const int e = g->hctr[C_ERR];
   if (e & ERR_INADMISSIBLE)
@@ -796,13 +793,14 @@ static pg_status check_ctr(pg_game *g) {
 // host synchronisation on the common path.
 static pg_status run_valuation(pg_game *g, hipStream_t s, bool odd_switch,
                                int32_t *count, int64_t *n_finite) {
-  g->nlevels = plan_levels(g->n_aug);
+  g->nlevels = g->dense ? count_levels(g->n_aug, g->dw)
+                        : plan_levels(g->n_aug);
   if (g->careful) PG_TRY(careful_walks(g, s));
   else enqueue_walks(g, s);
-  enqueue_rank(g, s);
+  enqueue_values(g, s);
   if (odd_switch) {
     fill_i32(g->ctr + C_SWITCH, 0, 1, s, &g->prof);
-    enqueue_switch(g, true, s);
+    enqueue_any_switch(g, true, s);
   }
   pg_status st = read_ctr(g, s);
   if (st != PG_OK) return st;
@@ -811,10 +809,10 @@ static pg_status run_valuation(pg_game *g, hipStream_t s, bool odd_switch,
     // redo everything after the walks (the gated kernels did nothing)
     st = careful_walks(g, s);
     if (st != PG_OK) return st;
-    enqueue_rank(g, s);
+    enqueue_values(g, s);
     if (odd_switch) {
       fill_i32(g->ctr + C_SWITCH, 0, 1, s, &g->prof);
-      enqueue_switch(g, true, s);
+      enqueue_any_switch(g, true, s);
     }
     st = read_ctr(g, s);
     if (st != PG_OK) return st;
@@ -838,7 +836,7 @@ pg_status iteration_device(pg_game *g, hipStream_t s, int32_t *count) {
 pg_status switch_device(pg_game *g, bool odd, hipStream_t s, int32_t *count) {
   fill_i32(g->ctr + C_SWITCH, 0, 1, s, &g->prof);
   fill_i32(g->ctr + C_ABORT, 0, 1, s, &g->prof);
-  enqueue_switch(g, odd, s);
+  enqueue_any_switch(g, odd, s);
   pg_status st = read_ctr(g, s);
   if (st != PG_OK) return st;
   *count = g->hctr[C_SWITCH];

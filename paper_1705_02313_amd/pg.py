@@ -20,13 +20,15 @@ PG_OK, PG_EINVAL, PG_ENOMEM, PG_EDEVICE = 0, 1, 2, 3
 PG_EITERLIMIT, PG_EINADMISSIBLE, PG_EINTERNAL = 4, 5, 6
 PG_SINK = -1
 PG_KEY_TOP = 2**31 - 1
-PG_PTR_DEVICE, PG_NO_PREPROCESS, PG_OFFSETS_I32, PG_CAREFUL_WALKS = 1, 2, 4, 8
+PG_PTR_DEVICE, PG_NO_PREPROCESS, PG_OFFSETS_I32 = 1, 2, 4
+PG_CAREFUL_WALKS, PG_COUNT_VALUATION = 8, 16
 
 STATUS_NAMES = {0: "PG_OK", 1: "PG_EINVAL", 2: "PG_ENOMEM", 3: "PG_EDEVICE",
                 4: "PG_EITERLIMIT", 5: "PG_EINADMISSIBLE", 6: "PG_EINTERNAL"}
 
-EXPORTS = ["pg_load_csr", "pg_game_info", "pg_export_game",
-           "pg_initial_strategies", "pg_valuation", "pg_best_response",
+EXPORTS = ["pg_load_csr", "pg_game_info", "pg_count_info", "pg_export_game",
+           "pg_initial_strategies", "pg_valuation", "pg_valuation_counts",
+           "pg_best_response",
            "pg_solve", "pg_profile_enable", "pg_profile_kinds",
            "pg_profile_read", "pg_batch_create", "pg_batch_submit",
            "pg_batch_step", "pg_batch_poll", "pg_batch_finished",
@@ -80,6 +82,9 @@ def lib() -> ctypes.CDLL:
         L.pg_load_csr.argtypes = [I64, I64, P, P, P, P, U32, P,
                                   ctypes.POINTER(P)]
         L.pg_game_info.argtypes = [P] + [ctypes.POINTER(I64)] * 4
+        L.pg_count_info.argtypes = [P, ctypes.POINTER(I32), P]
+        L.pg_valuation_counts.argtypes = [P, P, P, P, P, ctypes.POINTER(I64),
+                                          U32, P]
         L.pg_export_game.argtypes = [P, P, P, P, P, U32, P]
         L.pg_initial_strategies.argtypes = [P, P, P, U32, P]
         L.pg_valuation.argtypes = [P, P, P, P, ctypes.POINTER(I64), U32, P]
@@ -139,10 +144,13 @@ def _stream(device: bool):
 
 class Game:
     """A game loaded on the device (modified by preprocessing unless
-    ``preprocess=False``; ``careful_walks=True`` sets PG_CAREFUL_WALKS)."""
+    ``preprocess=False``; ``careful_walks=True`` sets PG_CAREFUL_WALKS,
+    ``count_valuation=True`` PG_COUNT_VALUATION).  Games whose priorities
+    repeat use count valuations by themselves (``self.d > 0``)."""
 
     def __init__(self, offsets, targets, owner, priority, n: int = None,
-                 preprocess: bool = True, careful_walks: bool = False):
+                 preprocess: bool = True, careful_walks: bool = False,
+                 count_valuation: bool = False):
         device = _is_torch(targets)
         if device:
             import torch
@@ -168,7 +176,8 @@ class Game:
         flags = (PG_PTR_DEVICE if device else 0) | \
             (0 if preprocess else PG_NO_PREPROCESS) | \
             (PG_OFFSETS_I32 if off_i32 else 0) | \
-            (PG_CAREFUL_WALKS if careful_walks else 0)
+            (PG_CAREFUL_WALKS if careful_walks else 0) | \
+            (PG_COUNT_VALUATION if count_valuation else 0)
         h = ctypes.c_void_p()
         _check(lib().pg_load_csr(n, m, _ptr(offsets), _ptr(targets),
                                  _ptr(owner), _ptr(priority), flags,
@@ -178,20 +187,24 @@ class Game:
         vals = [ctypes.c_int64() for _ in range(4)]
         _check(lib().pg_game_info(self._h, *[ctypes.byref(v) for v in vals]))
         self.n, self.m, self.n_aug, self.m_aug = [int(v.value) for v in vals]
+        d = ctypes.c_int32()
+        values = np.zeros(32, np.int32)
+        _check(lib().pg_count_info(self._h, ctypes.byref(d), _ptr(values)))
+        self.d = int(d.value)
+        self.values = values[:self.d].copy()
 
     @classmethod
     def from_dict(cls, g: dict, device: bool = False, preprocess: bool = True,
-                  careful_walks: bool = False):
+                  careful_walks: bool = False, count_valuation: bool = False):
+        kw = {"n": int(g["n"]), "preprocess": preprocess,
+              "careful_walks": careful_walks,
+              "count_valuation": count_valuation}
         if device:
             import torch
             t = {k: torch.from_numpy(np.ascontiguousarray(g[k])).cuda()
                  for k in ("offsets", "targets", "owner", "pri")}
-            return cls(t["offsets"], t["targets"], t["owner"], t["pri"],
-                       n=int(g["n"]), preprocess=preprocess,
-                       careful_walks=careful_walks)
-        return cls(g["offsets"], g["targets"], g["owner"], g["pri"],
-                   n=int(g["n"]), preprocess=preprocess,
-                   careful_walks=careful_walks)
+            return cls(t["offsets"], t["targets"], t["owner"], t["pri"], **kw)
+        return cls(g["offsets"], g["targets"], g["owner"], g["pri"], **kw)
 
     # -- helpers -------------------------------------------------------------
     def _out(self, count: int, dtype):
@@ -246,12 +259,27 @@ class Game:
                                   _stream(self.device)))
         return key, int(nf.value)
 
+    def valuation_counts(self, sigma, tau):
+        """Count valuations: returns (counts[n_aug+1, d], top[n_aug],
+        n_finite); column j counts priority self.values[j]."""
+        sigma = self._in(sigma)
+        tau = self._in(tau)
+        counts = self._out((self.n_aug + 1) * self.d, np.int32)
+        top = self._out(self.n_aug, np.uint8)
+        nf = ctypes.c_int64()
+        _check(lib().pg_valuation_counts(self._h, _ptr(sigma), _ptr(tau),
+                                         _ptr(counts), _ptr(top),
+                                         ctypes.byref(nf), self._flags,
+                                         _stream(self.device)))
+        return counts.reshape(self.n_aug + 1, self.d), top, int(nf.value)
+
     def best_response(self, sigma, tau, max_inner: int = 0):
-        """Returns (tau, key, n_valuations)."""
+        """Returns (tau, key, n_valuations); key is None for a game with
+        count valuations."""
         sigma = self._in(sigma)
         tau = self._in(tau)
         tau = tau.clone() if self.device else tau.copy()
-        key = self._out(self.n_aug + 1, np.int32)
+        key = None if self.d else self._out(self.n_aug + 1, np.int32)
         nv = ctypes.c_int32()
         _check(lib().pg_best_response(self._h, _ptr(sigma), _ptr(tau),
                                       _ptr(key), ctypes.byref(nv), max_inner,

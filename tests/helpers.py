@@ -52,3 +52,26 @@ def to_np(x):
     if hasattr(x, "detach"):
         return x.detach().cpu().numpy()
     return np.asarray(x)
+
+
+def dense_oracle_trajectory(aug: dict, max_vals: int = 10**9):
+    """As oracle_trajectory, with the count-valuation oracle; yields
+    (sigma, tau, counts, top) for every valuation, in order."""
+    sigma, tau = orc.initial_strategies(aug)
+    own = np.asarray(aug["owner"])
+    count = 0
+    while True:
+        while True:
+            succ = np.where(own == 1, tau, sigma).astype(np.int32)
+            counts, top, values, rc = orc.dense_valuation(succ, aug["pri"])
+            assert rc == 0
+            yield sigma.copy(), tau.copy(), counts, top
+            count += 1
+            if count >= max_vals:
+                return
+            tau, c = orc.dense_odd_switch(aug, counts, top, values, tau)
+            if c == 0:
+                break
+        sigma, c = orc.dense_even_switch(aug, counts, top, values, sigma)
+        if c == 0:
+            return

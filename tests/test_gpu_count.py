@@ -1,0 +1,138 @@
+"""Count valuations on the device (games whose priorities repeat) against
+the count-valuation oracle, through the C ABI: valuations along the
+oracle's trajectory (counts and top flags, element by element), whole
+solves (strategies, winners, iteration and switch counts) for every count
+row width, the forced mode on distinct priorities, the host-driven walk
+path, deep lists and the error paths."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from oracle import orc
+from paper_1705_02313_amd import synth
+from paper_1705_02313_amd.pg import PG_EINVAL, Game, PgError
+from tests.helpers import dense_oracle_trajectory, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def _check_solve(g, **kw):
+    ref = orc.dense_solve(g)
+    assert ref["status"] == orc.OK
+    with Game.from_dict(g, **kw) as d:
+        assert d.d == ref["values"].size
+        np.testing.assert_array_equal(d.values, ref["values"])
+        out = d.solve()
+    np.testing.assert_array_equal(to_np(out["winner"]), ref["winner"])
+    np.testing.assert_array_equal(to_np(out["sigma"]), ref["sigma"])
+    np.testing.assert_array_equal(to_np(out["tau"]), ref["tau"])
+    st = out["stats"]
+    assert st["n_major"] == ref["n_major"]
+    assert st["n_valuations"] == ref["n_valuations"]
+    assert st["n_odd_switches"] == ref["n_odd_switches"]
+    assert st["n_even_switches"] == ref["n_even_switches"]
+    return out
+
+
+@pytest.mark.parametrize("n,d,seed", [(300, 2, 1), (5000, 3, 2),
+                                      (20000, 4, 3), (3000, 7, 4)])
+def test_count_valuations_along_trajectory(n, d, seed):
+    g = synth.few_priorities_game(n, 2, 5, d, seed)
+    aug = orc.dense_preprocess(g)
+    with Game.from_dict(g) as dev:
+        assert dev.n_aug == aug["n"]
+        for i, (sigma, tau, counts, top) in enumerate(
+                dense_oracle_trajectory(aug, max_vals=12)):
+            c, t, nf = dev.valuation_counts(sigma, tau)
+            np.testing.assert_array_equal(to_np(t), top, err_msg=f"val {i}")
+            np.testing.assert_array_equal(to_np(c), counts,
+                                          err_msg=f"val {i}")
+            assert nf == int((top == 0).sum()) + 1
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 4, 5, 8, 9, 16, 17, 31])
+def test_count_solve_every_row_width(d):
+    g = synth.few_priorities_game(4000, 1, 6, d, 100 + d)
+    _check_solve(g)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_count_solve_small_ragged(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(2, 400))
+    g = synth.few_priorities_game(n, 1, 4, int(rng.integers(2, 5)),
+                                  200 + seed)
+    _check_solve(g)
+
+
+def test_count_solve_midsize():
+    g = synth.few_priorities_game(300_000, 2, 8, 4, 77)
+    _check_solve(g)
+
+
+def test_count_solve_deep_chain():
+    """A chain game with few priorities: Euler lists as deep as the game."""
+    g = synth.chain_game(200_000, 91)
+    g["pri"] = np.random.default_rng(91).integers(0, 3, g["n"]).astype(
+        np.int32)
+    _check_solve(g)
+
+
+def test_count_forced_on_distinct_priorities():
+    g = synth.random_game(24, 1, 3, 5)
+    _check_solve(g, count_valuation=True)
+
+
+def test_count_careful_walks():
+    g = synth.few_priorities_game(30000, 2, 6, 4, 8)
+    _check_solve(g, careful_walks=True)
+
+
+def test_count_device_pointers():
+    g = synth.few_priorities_game(10000, 2, 5, 3, 9)
+    ref = orc.dense_solve(g)
+    with Game.from_dict(g, device=True) as d:
+        out = d.solve()
+    np.testing.assert_array_equal(to_np(out["winner"]), ref["winner"])
+    np.testing.assert_array_equal(to_np(out["sigma"]), ref["sigma"])
+    np.testing.assert_array_equal(to_np(out["tau"]), ref["tau"])
+
+
+def test_count_errors():
+    g = synth.few_priorities_game(2000, 2, 4, 40, 10)
+    with pytest.raises(PgError) as e:
+        Game.from_dict(g)
+    assert e.value.status == PG_EINVAL
+    h = synth.few_priorities_game(500, 2, 4, 3, 11)
+    with Game.from_dict(h) as d:
+        sigma, tau = d.initial_strategies()
+        with pytest.raises(PgError) as e:
+            d.valuation(sigma, tau)
+        assert e.value.status == PG_EINVAL
+        t2, key, nv = d.best_response(sigma, tau)
+        assert key is None and nv >= 1
+    # rank games reject the count entry point
+    r = synth.random_game(500, 2, 4, 12)
+    with Game.from_dict(r) as d:
+        assert d.d == 0
+        sigma, tau = d.initial_strategies()
+        with pytest.raises(PgError) as e:
+            d.valuation_counts(sigma, tau)
+        assert e.value.status == PG_EINVAL
+
+
+def test_count_all_top_and_single_vertices():
+    # every play infinite: Even vertices on even self-loops
+    g = {"n": 3, "m": 3, "offsets": np.array([0, 1, 2, 3]),
+         "targets": np.array([0, 1, 2], np.int32),
+         "owner": np.array([0, 0, 1], np.uint8),
+         "pri": np.array([2, 2, 2], np.int32)}
+    out = _check_solve(g)
+    np.testing.assert_array_equal(to_np(out["winner"]), [0, 0, 0])
+    for owner, pri in [(0, 0), (0, 1), (1, 2), (1, 3)]:
+        one = {"n": 1, "m": 1, "offsets": np.array([0, 1]),
+               "targets": np.array([0], np.int32),
+               "owner": np.array([owner], np.uint8),
+               "pri": np.array([pri], np.int32)}
+        _check_solve(one, count_valuation=True)
