@@ -15,6 +15,9 @@ Workloads (seeded, synthetic; see paper_1705_02313_amd/synth.py):
   c1  random game, n = 1,000,000, out-degree U[2,10]
   c3  long-chain game, n = 8,000,000
   c0  random game, n = 1,000, out-degree U[2,5]
+  d4  random game, n = 10,000,000, out-degree U[2,5], priorities drawn from
+      4 values: count valuations, the paper's regime (2 to 4 priorities)
+  d4s the same with n = 1,000,000, out-degree U[2,10]
   c4  batched/served mix: 1,024 random games, n log-uniform in [1e3, 2e5],
       out-degree U[2,8]; games/s one at a time (pg_load_csr + pg_solve each),
       batched with every game present at the start (the calibration rate mu),
@@ -49,6 +52,10 @@ WORKLOADS = {
     "c3": ("long-chain parity game n=8000000", 3),
     "c4": ("1024 random parity games, n log-uniform [1e3, 2e5], deg U[2,8]",
            4),
+    "d4": ("random parity game n=10000000 deg U[2,5], 4 repeated priorities "
+           "(count valuations)", 5),
+    "d4s": ("random parity game n=1000000 deg U[2,10], 4 repeated priorities "
+            "(count valuations)", 6),
 }
 
 
@@ -93,21 +100,26 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(game: dict, iters: int = 3) -> dict:
+def cpu_baseline(game: dict, iters: int = 3, counts: bool = False) -> dict:
     """The CPU oracle on this host: its preprocessing, then the first `iters`
-    best-response iterations (valuation + All_Odd) of Algorithm 1."""
+    best-response iterations (valuation + All_Odd) of Algorithm 1 (with the
+    count-valuation oracle when `counts`)."""
     from oracle import orc
     t0 = time.perf_counter()
-    aug = orc.preprocess(game)
+    aug = orc.dense_preprocess(game) if counts else orc.preprocess(game)
     t_pre = time.perf_counter() - t0
     sigma, tau = orc.initial_strategies(aug)
-    by_pri = orc.order_by_pri(aug["pri"])
+    by_pri = None if counts else orc.order_by_pri(aug["pri"])
     times = []
     for _ in range(iters):
         t1 = time.perf_counter()
         succ = np.where(aug["owner"] == 1, tau, sigma).astype(np.int32)
-        key, _, rc = orc.valuation(succ, aug["pri"], by_pri=by_pri)
-        tau, c = orc.odd_switch(aug, key, tau)
+        if counts:
+            cnt, top, values, rc = orc.dense_valuation(succ, aug["pri"])
+            tau, c = orc.dense_odd_switch(aug, cnt, top, values, tau)
+        else:
+            key, _, rc = orc.valuation(succ, aug["pri"], by_pri=by_pri)
+            tau, c = orc.odd_switch(aug, key, tau)
         times.append(time.perf_counter() - t1)
         if c == 0:
             break
@@ -280,7 +292,7 @@ def main():
         torch.cuda.synchronize()
         t_c = time.perf_counter()
         prof = g.profile_read() if profile else {}
-        info = (g.n_aug, g.m_aug)
+        info = (g.n_aug, g.m_aug, g.d)
         g.free()
         torch.cuda.synchronize()
         t_d = time.perf_counter()
@@ -359,6 +371,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "n": game["n"], "m": m,
                    "n_aug": runs[0]["aug"][0], "m_aug": runs[0]["aug"][1],
+                   "valuation": (f"counts, d={runs[0]['aug'][2]}"
+                                 if runs[0]["aug"][2] else "ranks"),
                    "step": "pg_load_csr + pg_solve + pg_free, inputs resident "
                            "in HBM"},
         "solve_seconds_median": statistics.median(solve_s),
@@ -373,7 +387,8 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample of the same workload")
-        line["cpu_baseline"] = cpu_baseline(game)
+        line["cpu_baseline"] = cpu_baseline(game,
+                                            counts=runs[0]["aug"][2] > 0)
     else:
         line["cpu_baseline"] = None
     print(json.dumps(line), flush=True)

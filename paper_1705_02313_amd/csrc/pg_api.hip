@@ -322,7 +322,7 @@ void free_game(pg_game *g) {
                   g->sk1,      g->sv1,      g->tile_cnt, g->scan_tmp,
                   g->kids,     g->fh,       g->pos,      g->elem,
                   g->ctr,      g->u64tmp,   g->cvals,    g->pidx,
-                  g->cnt};
+                  g->cnt,      g->elem4};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (int k = 0; k < 8; ++k) {

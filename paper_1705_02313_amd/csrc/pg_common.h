@@ -182,6 +182,7 @@ struct pg_game {
   int32_t *cvals = nullptr;   // [32] the same on the device
   uint8_t *pidx = nullptr;    // [n_aug] column of each vertex's priority
   int32_t *cnt = nullptr;     // [(n_aug+1) * dw] counts; row n_aug: the sink
+  int4 *elem4 = nullptr;      // [2*n_aug+2] {next, vertex | up bit, column}
   int32_t *vsum[8] = {};      // per level: dw ints per splitter
   int32_t *vbase[8] = {};
 

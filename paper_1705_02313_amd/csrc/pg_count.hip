@@ -10,13 +10,22 @@
 // Steps per valuation (after the walks of pg_val.hip have classified every
 // vertex as finite or top):
 //   1. compaction: finite vertex v gets position f; element 0 is the sink's
-//      list head, 2f+1 the edge entering v, 2f+2 the edge leaving it;
+//      list head, 2f+1 the edge entering v, 2f+2 the edge leaving it.  An
+//      element is {next, v | bit 31 on the edge leaving v, column of
+//      pri(v)}: 16 bytes, so one load per list step brings its weight (a
+//      random access costs a whole cache line either way); top vertices get
+//      -1 in the first count column, so a comparison reads one row;
 //   2. the list by the atomic-exchange construction (section 5,
 //      "Constructing the list ranking instance in parallel"): start(x) is
 //      the end of x's list so far; every finite v swaps the edge leaving v
 //      into start(parent) and links the previous end to the edge entering v;
 //      a last pass links the end of every list to the edge leaving its
-//      vertex (the sink's list ends the tour);
+//      vertex.  The sink's children are the exception: early on most Even
+//      vertices choose the sink, and millions of exchanges on its one
+//      pointer serialise.  They are chained instead in position order from a
+//      scan of "my parent is the sink" flags (any order of the children
+//      gives an Euler tour, and this one keeps the sink's part of the tour
+//      in increasing memory order); the last of them ends the tour;
 //   3. list ranking by sublists (section 5, "List ranking") with count
 //      vectors of dw ints as weights: level-1 sums, recursive levels, the top
 //      level by pointer jumping in LDS, bases handed back down, and a last
@@ -84,21 +93,25 @@ __global__ void k_cnt_flags(int32_t N, const uint8_t *rs, uint32_t *f,
   if (v < N) f[v] = rs[v] == 1;
 }
 
-// Positions of the finite vertices, the payloads of their two elements
-// (vertex id, bit 31 on the edge leaving it) and the initial list ends.
+// Positions of the finite vertices, the payloads of their two elements and
+// the initial list ends; the top marker in the count rows of top vertices.
+template <int D>
 __global__ void k_cnt_compact(int32_t N, const uint8_t *__restrict__ rs,
                               const uint32_t *__restrict__ fscan,
-                              int32_t *fpos, int32_t *fvert, int32_t *start,
-                              int2 *elem, int32_t *ctr) {
+                              const uint8_t *__restrict__ pidx, int32_t *fpos,
+                              int32_t *fvert, int32_t *start, int4 *elem,
+                              int32_t *cnt, int32_t *ctr) {
   if (ctr[C_ABORT]) return;
   const int32_t nF = ctr[C_NFIN];
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v == 0) {
-    start[nF] = 0;       // the sink's list starts at the head element
-    elem[0].y = N;       // the head carries no weight
-    fpos[N] = nF;
+  if (v == 0) {  // the head carries no weight
+    elem[0].y = N;
+    elem[0].z = 0;
   }
-  if (v >= N || rs[v] != 1) return;
+  if (v >= N) return;
+  const uint8_t st = rs[v];
+  if (st == 2) cnt[v * D] = -1;
+  if (st != 1) return;
   const int32_t f = (int32_t)fscan[v];
   if (f >= nF) {  // the finite count and the compaction disagree
     atomicOr(&ctr[C_ERR], ERR_RANKCOUNT);
@@ -107,35 +120,61 @@ __global__ void k_cnt_compact(int32_t N, const uint8_t *__restrict__ rs,
   fpos[v] = f;
   fvert[f] = (int32_t)v;
   start[f] = 2 * f + 1;
+  const int32_t col = pidx[v];
   elem[2 * f + 1].y = (int32_t)v;
+  elem[2 * f + 1].z = col;
   elem[2 * f + 2].y = (int32_t)v | (int32_t)0x80000000;
+  elem[2 * f + 2].z = col;
 }
 
-// Every finite v appends the tour of its subtree to its parent's list.
+// Every finite v whose parent is not the sink appends the tour of its
+// subtree to its parent's list; the others raise their flag for the scan.
 __global__ void k_cnt_link(int32_t N, const int32_t *__restrict__ fvert,
                            const int2 *__restrict__ sp,
                            const int32_t *__restrict__ fpos, int32_t *start,
-                           int2 *elem, const int32_t *ctr) {
+                           int4 *elem, uint32_t *sink_flag,
+                           const int32_t *ctr) {
   if (ctr[C_ABORT] || (ctr[C_ERR] & ERR_RANKCOUNT)) return;
   const int32_t nF = ctr[C_NFIN];
   const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= nF) return;
   const int32_t v = fvert[f];
   const int32_t u = sp[v].x;                 // finite or the sink
-  const int32_t pu = (u == N) ? nF : fpos[u];
-  const int32_t old = atomicExch(&start[pu], (int32_t)(2 * f + 2));
+  sink_flag[f] = u == N;
+  if (u == N) return;
+  const int32_t old = atomicExch(&start[fpos[u]], (int32_t)(2 * f + 2));
   elem[old].x = (int32_t)(2 * f + 1);
 }
 
 // The end of every finite vertex's list leads to the edge leaving it; the
-// sink's list ends the tour.
-__global__ void k_cnt_close(const int32_t *__restrict__ start, int2 *elem,
+// sink's children are listed by their rank among them.
+__global__ void k_cnt_close(const int32_t *__restrict__ start,
+                            const uint32_t *__restrict__ sink_flag,
+                            const uint32_t *__restrict__ sink_rank,
+                            int32_t *sink_kids, int4 *elem,
                             const int32_t *ctr) {
   if (ctr[C_ABORT] || (ctr[C_ERR] & ERR_RANKCOUNT)) return;
   const int32_t nF = ctr[C_NFIN];
   const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (f > nF) return;
-  elem[start[f]].x = (f == nF) ? -1 : (int32_t)(2 * f + 2);
+  if (f >= nF) return;
+  elem[start[f]].x = (int32_t)(2 * f + 2);
+  if (sink_flag[f]) sink_kids[sink_rank[f]] = (int32_t)f;
+}
+
+// The sink's list: head -> tour(c0) -> tour(c1) -> ... -> end, c_r being
+// its r-th child in position order.
+__global__ void k_cnt_sink_chain(const uint32_t *__restrict__ sink_flag,
+                                 const uint32_t *__restrict__ sink_rank,
+                                 const int32_t *__restrict__ sink_kids,
+                                 int4 *elem, const int32_t *ctr) {
+  if (ctr[C_ABORT] || (ctr[C_ERR] & ERR_RANKCOUNT)) return;
+  const int32_t nF = ctr[C_NFIN];
+  const int64_t S =
+      nF > 0 ? (int64_t)sink_rank[nF - 1] + sink_flag[nF - 1] : 0;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r == 0) elem[0].x = S > 0 ? 2 * sink_kids[0] + 1 : -1;
+  if (r >= S) return;
+  elem[2 * sink_kids[r] + 2].x = (r + 1 < S) ? 2 * sink_kids[r + 1] + 1 : -1;
 }
 
 // ---------------------------------------------------------------------------
@@ -174,8 +213,7 @@ __device__ __forceinline__ void store_vec(int32_t *p, const int32_t (&a)[D]) {
 // the head, is one) sums the weights of its sublist.
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_vlr_sum1(
-    int32_t N, const int2 *__restrict__ elem,
-    const uint8_t *__restrict__ pidx, int per_thread, int32_t *vsum,
+    int32_t N, const int4 *__restrict__ elem, int per_thread, int32_t *vsum,
     int32_t *next, int32_t *ctr) {
   if (ctr[C_ABORT]) return;
   const int64_t L = 2 * (int64_t)ctr[C_NFIN] + 1;
@@ -189,9 +227,9 @@ __global__ __launch_bounds__(kBlock) void k_vlr_sum1(
     int32_t acc[D] = {};
     int64_t steps = 0;
     for (;;) {
-      const int2 el = elem[e];
+      const int4 el = elem[e];
       const int32_t x = el.y & 0x7fffffff;
-      if (x < N) add_unit<D>(acc, pidx[x], el.y < 0 ? -1 : 1);
+      if (x < N) add_unit<D>(acc, el.z, el.y < 0 ? -1 : 1);
       e = el.x;
       if (e < 0 || e % kStride == 0) break;
       if (++steps > L) {
@@ -323,8 +361,7 @@ __global__ __launch_bounds__(kBlock) void k_vlr_distk(
 // exclusive prefix at that element.
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_vlr_emit1(
-    int32_t N, const int2 *__restrict__ elem,
-    const uint8_t *__restrict__ pidx, int per_thread,
+    int32_t N, const int4 *__restrict__ elem, int per_thread,
     const int32_t *__restrict__ sbase, int32_t *cnt, const int32_t *ctr) {
   if (ctr[C_ABORT]) return;
   const int64_t L = 2 * (int64_t)ctr[C_NFIN] + 1;
@@ -338,10 +375,10 @@ __global__ __launch_bounds__(kBlock) void k_vlr_emit1(
     int32_t b[D];
     load_vec<D>(sbase + j * D, b);
     for (int64_t steps = 0; steps <= L; ++steps) {
-      const int2 el = elem[e];
+      const int4 el = elem[e];
       const int32_t x = el.y & 0x7fffffff;
       if (x < N) {
-        const int col = pidx[x];
+        const int col = el.z;
         if (el.y < 0) {
           store_vec<D>(cnt + (int64_t)x * D, b);
           add_unit<D>(b, col, -1);
@@ -376,13 +413,13 @@ __device__ __forceinline__ int vcmp(bool ta, const int32_t (&a)[D], bool tb,
   return r;
 }
 
-// the valuation of vertex u (u == N: the sink, the zero vector)
+// the valuation of vertex u (u == N: the sink, the zero vector); returns
+// whether it is top (the marker -1 in the first column)
 template <int D>
-__device__ __forceinline__ bool load_val(int32_t N, const uint8_t *rs,
-                                         const int32_t *cnt, int32_t u,
+__device__ __forceinline__ bool load_val(const int32_t *cnt, int32_t u,
                                          int32_t (&a)[D]) {
   load_vec<D>(cnt + (int64_t)u * D, a);
-  return u < N && rs[u] == 2;
+  return a[0] < 0;
 }
 
 // All_Odd (section 4): the first successor of least valuation, if strictly
@@ -391,8 +428,8 @@ template <int D>
 __global__ __launch_bounds__(kBlock) void k_cnt_odd_switch(
     int32_t N, int64_t count, const int32_t *__restrict__ ids,
     const int64_t *__restrict__ off, const int32_t *__restrict__ tgt,
-    const uint8_t *__restrict__ rs, const int32_t *__restrict__ cnt,
-    uint32_t odd_cols, const int32_t *__restrict__ pri, int2 *sp,
+    const int32_t *__restrict__ cnt, uint32_t odd_cols,
+    const int32_t *__restrict__ pri, int2 *sp,
     int32_t *ctr) {
   if (ctr[C_ABORT]) return;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -402,11 +439,11 @@ __global__ __launch_bounds__(kBlock) void k_cnt_odd_switch(
     const int64_t e0 = off[v], e1 = off[v + 1];
     int32_t best = tgt[e0];
     int32_t bv[D];
-    bool bt = load_val<D>(N, rs, cnt, best, bv);
+    bool bt = load_val<D>(cnt, best, bv);
     for (int64_t e = e0 + 1; e < e1; ++e) {
       const int32_t u = tgt[e];
       int32_t uv[D];
-      const bool ut = load_val<D>(N, rs, cnt, u, uv);
+      const bool ut = load_val<D>(cnt, u, uv);
       if (vcmp<D>(ut, uv, bt, bv, odd_cols) < 0) {
         best = u;
         bt = ut;
@@ -416,7 +453,7 @@ __global__ __launch_bounds__(kBlock) void k_cnt_odd_switch(
     }
     const int32_t cur = sp[v].x;
     int32_t cv[D];
-    const bool ct = load_val<D>(N, rs, cnt, cur, cv);
+    const bool ct = load_val<D>(cnt, cur, cv);
     if (vcmp<D>(bt, bv, ct, cv, odd_cols) < 0) {
       sp[v] = make_int2(best, pri[best]);
       sw = true;
@@ -431,8 +468,8 @@ template <int D>
 __global__ __launch_bounds__(kBlock) void k_cnt_even_switch(
     int32_t N, int64_t count, const int32_t *__restrict__ ids,
     const int64_t *__restrict__ off, const int32_t *__restrict__ tgt,
-    const uint8_t *__restrict__ rs, const int32_t *__restrict__ cnt,
-    uint32_t odd_cols, const int32_t *__restrict__ pri, int2 *sp,
+    const int32_t *__restrict__ cnt, uint32_t odd_cols,
+    const int32_t *__restrict__ pri, int2 *sp,
     int32_t *ctr) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool sw = false;
@@ -445,7 +482,7 @@ __global__ __launch_bounds__(kBlock) void k_cnt_even_switch(
     for (int64_t e = e0; e < e1; ++e) {
       const int32_t u = tgt[e];
       int32_t uv[D];
-      const bool ut = load_val<D>(N, rs, cnt, u, uv);
+      const bool ut = load_val<D>(cnt, u, uv);
       if (vcmp<D>(ut, uv, bt, bv, odd_cols) > 0) {
         best = u;
         bt = ut;
@@ -455,7 +492,7 @@ __global__ __launch_bounds__(kBlock) void k_cnt_even_switch(
     }
     const int32_t cur = sp[v].x;
     int32_t cv[D];
-    const bool ct = load_val<D>(N, rs, cnt, cur, cv);
+    const bool ct = load_val<D>(cnt, cur, cv);
     if (vcmp<D>(bt, bv, ct, cv, odd_cols) > 0) {
       sp[v] = make_int2(best, best == N ? 2147483647 : pri[best]);
       sw = true;
@@ -482,7 +519,7 @@ __global__ void k_cnt_export(int32_t N, int d, const uint8_t *rs,
 // ===========================================================================
 namespace pgk {
 
-constexpr int kVPerThread1 = 4;   // level-1 sublists per thread
+constexpr int kVPerThread1 = 1;   // level-1 sublists per thread (1 measured best)
 
 int count_levels(int64_t n_aug, int dw) {
   const int64_t Lmax = 2 * n_aug + 1;
@@ -526,6 +563,7 @@ pg_status count_setup(pg_game *g, hipStream_t s) {
   for (int j = 0; j < d; ++j)
     if (g->values[j] & 1) g->odd_cols |= 1u << j;
   PG_TRY(dev_alloc(&g->pidx, N));
+  PG_TRY(dev_alloc(&g->elem4, 2 * N + 2));
   hipLaunchKernelGGL(k_cnt_pidx, dim3(grid_for(N)), dim3(kBlock), 0, s, g->pri,
                      N, g->cvals, d, g->pidx);
   // count rows; the sink's row stays zero
@@ -554,23 +592,33 @@ static void enqueue_count_t(pg_game *g, hipStream_t s) {
   PG_LAUNCH(pf, K_LINK_INFO, 5.0 * N, k_cnt_flags, dim3(grid_for(N)),
             dim3(kBlock), 0, s, N, g->rs, flags, g->ctr);
   scan_excl_u32(flags, fscan, N, g->scan_tmp, s, pf, gate);
-  // rs 1, scan 4 per vertex; fpos, fvert, start, two payloads 20 per finite
-  PG_LAUNCH(pf, K_LINK_INFO, 5.0 * N, k_cnt_compact, dim3(grid_for(N)),
-            dim3(kBlock), 0, s, N, g->rs, fscan, g->pos, g->kids, start,
-            g->elem, g->ctr);
-  // fvert 4, play-graph record 8, fpos 4, exchange 8, link 4; close 8
-  PG_LAUNCH_NF(pf, K_LINK_BUILD, 28.0, k_cnt_link, dim3(grid_for(N)),
-               dim3(kBlock), 0, s, N, g->kids, g->sp, g->pos, start, g->elem,
-               g->ctr);
-  PG_LAUNCH_NF(pf, K_LINK_BUILD, 8.0, k_cnt_close, dim3(grid_for(N + 1)),
-               dim3(kBlock), 0, s, start, g->elem, g->ctr);
+  // rs 1, scan 4 per vertex; column 1, fpos, fvert, start 12 and two
+  // payloads 16 per finite vertex
+  PG_LAUNCH(pf, K_LINK_INFO, 5.0 * N, k_cnt_compact<D>, dim3(grid_for(N)),
+            dim3(kBlock), 0, s, N, g->rs, fscan, g->pidx, g->pos, g->kids,
+            start, g->elem4, g->cnt, g->ctr);
+  // fvert 4, play-graph record 8, flag 4, fpos 4, exchange 8, link 4
+  uint32_t *sink_flag = g->sk0, *sink_rank = g->sk1;
+  int32_t *sink_kids = reinterpret_cast<int32_t *>(g->sv0);
+  PG_LAUNCH_NF(pf, K_LINK_BUILD, 32.0, k_cnt_link, dim3(grid_for(N)),
+               dim3(kBlock), 0, s, N, g->kids, g->sp, g->pos, start,
+               g->elem4, sink_flag, g->ctr);
+  scan_excl_u32(sink_flag, sink_rank, N, g->scan_tmp, s, pf, gate);
+  // start 4, link 4, flag and rank 8, then the sink's chain (about 12 per
+  // child of the sink)
+  PG_LAUNCH_NF(pf, K_LINK_BUILD, 16.0, k_cnt_close, dim3(grid_for(N)),
+               dim3(kBlock), 0, s, start, sink_flag, sink_rank, sink_kids,
+               g->elem4, g->ctr);
+  PG_LAUNCH(pf, K_LINK_BUILD, 0.0, k_cnt_sink_chain, dim3(grid_for(N)),
+            dim3(kBlock), 0, s, sink_flag, sink_rank, sink_kids, g->elem4,
+            g->ctr);
   const int nl = g->nlevels;
   const int64_t Lmax = 2 * (int64_t)N + 1;
   const int64_t ns1 = level_size(Lmax, 1);
   const int64_t thr1 = (ns1 + kVPerThread1 - 1) / kVPerThread1;
-  // two elements (8 B each) and two column reads per finite vertex
-  PG_LAUNCH_NF(pf, K_LR_SUM1, 18.0, k_vlr_sum1<D>, dim3(grid_for(thr1)),
-               dim3(kBlock), 0, s, N, g->elem, g->pidx, kVPerThread1,
+  // two elements (16 B each) per finite vertex
+  PG_LAUNCH_NF(pf, K_LR_SUM1, 32.0, k_vlr_sum1<D>, dim3(grid_for(thr1)),
+               dim3(kBlock), 0, s, N, g->elem4, kVPerThread1,
                g->vsum[0], g->lv[0].next, g->ctr);
   for (int k = 1; k < nl; ++k) {
     const int64_t nsk = level_size(Lmax, k + 1);
@@ -594,9 +642,9 @@ static void enqueue_count_t(pg_game *g, hipStream_t s) {
                  g->lv[k - 1].next, g->vsum[k - 1], k, g->vbase[k],
                  g->vbase[k - 1], g->ctr);
   }
-  // two elements and two column reads per finite vertex, one count row
-  PG_LAUNCH_NF(pf, K_LR_EMIT1, 18.0 + 4.0 * D, k_vlr_emit1<D>,
-               dim3(grid_for(thr1)), dim3(kBlock), 0, s, N, g->elem, g->pidx,
+  // two elements (16 B each) and one count row per finite vertex
+  PG_LAUNCH_NF(pf, K_LR_EMIT1, 32.0 + 4.0 * D, k_vlr_emit1<D>,
+               dim3(grid_for(thr1)), dim3(kBlock), 0, s, N, g->elem4,
                kVPerThread1, g->vbase[0], g->cnt, g->ctr);
 }
 
@@ -622,7 +670,7 @@ static void enqueue_count_switch_t(pg_game *g, bool odd, hipStream_t s) {
       PG_LAUNCH(pf, K_ODD_SWITCH,
                 (28.0 + 4.0 * D) * cnt + (5.0 + 4.0 * D) * g->m_odd,
                 k_cnt_odd_switch<D>, dim3(grid_for(cnt)), dim3(kBlock), 0, s,
-                N, cnt, g->odd_ids, g->off, g->tgt, g->rs, g->cnt,
+                N, cnt, g->odd_ids, g->off, g->tgt, g->cnt,
                 g->odd_cols, g->pri, g->sp, g->ctr);
   } else {
     const int64_t cnt = N - g->n_odd;
@@ -631,7 +679,7 @@ static void enqueue_count_switch_t(pg_game *g, bool odd, hipStream_t s) {
                 (28.0 + 4.0 * D) * cnt +
                     (5.0 + 4.0 * D) * (g->m_aug - g->m_odd),
                 k_cnt_even_switch<D>, dim3(grid_for(cnt)), dim3(kBlock), 0, s,
-                N, cnt, g->even_ids, g->off, g->tgt, g->rs, g->cnt,
+                N, cnt, g->even_ids, g->off, g->tgt, g->cnt,
                 g->odd_cols, g->pri, g->sp, g->ctr);
   }
   sum_dist(g->ctr, C_DIST_SW, C_SWITCH, s, pf);

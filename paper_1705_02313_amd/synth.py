@@ -164,8 +164,13 @@ def mixed_batch(count: int, seed_base: int, nmin: int = 1000,
 
 def config_game(config: int, k: int = 0) -> dict:
     """The workloads by index: 0 small random, 1 1M random, 2 10M random
-    (int64 offsets), 3 8M long chain."""
+    (int64 offsets), 3 8M long chain, 5 10M random with 4 repeated
+    priorities (the paper's regime), 6 1M random with 4 priorities."""
     seed = CONFIG_SEED_BASE * config + k
+    if config == 5:
+        return few_priorities_game(10_000_000, 2, 5, 4, seed)
+    if config == 6:
+        return few_priorities_game(1_000_000, 2, 10, 4, seed)
     if config == 0:
         return random_game(1000, 2, 5, seed)
     if config == 1:
