@@ -44,6 +44,33 @@ __global__ void k_check_targets(const int32_t *tgt, int64_t m, int64_t n,
   if (t < 0 || (int64_t)t >= n) atomicOr(&ctr[C_ERR], ERR_INVAL);
 }
 
+__global__ void k_dup_check(const uint32_t *sk, int64_t n, int32_t *flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > 0 && i < n && sk[i] == sk[i - 1]) *flag = 1;
+}
+
+__global__ void k_max_i32(const int32_t *a, int64_t n, int32_t *out) {
+  int32_t mx = -1;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    mx = a[i] > mx ? a[i] : mx;
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    const int32_t y = __shfl_down(mx, o, kWave);
+    mx = y > mx ? y : mx;
+  }
+  if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(out, mx);
+}
+
+// One bit per priority value: a bit found set already is a repeat.
+__global__ void k_dup_bits(const int32_t *pri, int64_t n, uint32_t *bits,
+                           int32_t *flag) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const uint32_t p = (uint32_t)pri[v];
+  const uint32_t b = 1u << (p & 31u);
+  if (atomicOr(&bits[p >> 5], b) & b) *flag = 1;
+}
+
 __global__ void k_check_vertices(const uint8_t *owner, const int32_t *pri,
                                  int64_t n, int32_t *ctr) {
   int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -407,7 +434,7 @@ pg_status check_err(pg_game *g, const char *what) {
 pg_status load_modified(int64_t n, int64_t m, const void *offsets,
                         const int32_t *targets, const uint8_t *owner,
                         const int32_t *priority, uint32_t flags, hipStream_t s,
-                        pg_game *g, bool dense) {
+                        pg_game *g, LoadMode mode) {
   const bool dev = flags & PG_PTR_DEVICE;
   g->n = n;
   g->m = m;
@@ -462,6 +489,59 @@ pg_status load_modified(int64_t n, int64_t m, const void *offsets,
     return pg_fail(PG_EINVAL,
                    "targets must lie in [0, n), owners in {0, 1} and "
                    "priorities be >= 0");
+
+  g->dense = mode == kLoadCount;
+  if (mode == kLoadAuto) {
+    // repeated input priorities select count valuations.  Fewer values
+    // than vertices repeat by pigeonhole; otherwise one bit per priority
+    // value when the largest is below 32 n (each word then serves a few
+    // scattered vertices), else a sort of the priorities and a look at
+    // neighbours
+    fill_i32(g->ctr + C_MISC, -1, 1, s);
+    hipLaunchKernelGGL(k_max_i32, dim3(512), dim3(kBlock), 0, s, pri_in, n,
+                       g->ctr + C_MISC);
+    PG_TRY(sync_ctr(g, s));
+    const int64_t maxpri = g->hctr[C_MISC];
+    fill_i32(g->ctr + C_MISC, 0, 1, s);
+    if (maxpri + 1 < n) {
+      g->dense = true;
+    } else if (maxpri < 32 * n) {
+      uint32_t *bits = nullptr;
+      const int64_t words = maxpri / 32 + 1;
+      PG_TRY(dev_alloc(&bits, words));
+      tmp.p.push_back(bits);
+      fill_i32((int32_t *)bits, 0, words, s);
+      hipLaunchKernelGGL(k_dup_bits, dim3(grid_for(n)), dim3(kBlock), 0, s,
+                         pri_in, n, bits, g->ctr + C_MISC);
+      PG_TRY(sync_ctr(g, s));
+      g->dense = g->hctr[C_MISC] != 0;
+    } else {
+      uint32_t *k0 = nullptr, *v0 = nullptr, *k1 = nullptr, *v1 = nullptr;
+      uint32_t *tc = nullptr;
+      uint8_t *st = nullptr;
+      PG_TRY(dev_alloc(&k0, n));
+      tmp.p.push_back(k0);
+      PG_TRY(dev_alloc(&v0, n));
+      tmp.p.push_back(v0);
+      PG_TRY(dev_alloc(&k1, n));
+      tmp.p.push_back(k1);
+      PG_TRY(dev_alloc(&v1, n));
+      tmp.p.push_back(v1);
+      PG_TRY(dev_alloc(&tc, 256 * radix_tiles(n)));
+      tmp.p.push_back(tc);
+      PG_TRY(dev_alloc(&st, (int64_t)radix_scan_tmp_bytes(n) + 16));
+      tmp.p.push_back(st);
+      PG_HIP(hipMemcpyAsync(k0, pri_in, sizeof(int32_t) * n,
+                            hipMemcpyDeviceToDevice, s));
+      const int w = radix_sort(k0, v0, k1, v1, n, 32, tc, st, s, nullptr,
+                               nullptr, true);
+      hipLaunchKernelGGL(k_dup_check, dim3(grid_for(n)), dim3(kBlock), 0, s,
+                         w ? k1 : k0, n, g->ctr + C_MISC);
+      PG_TRY(sync_ctr(g, s));
+      g->dense = g->hctr[C_MISC] != 0;
+    }
+  }
+  const bool dense = g->dense;
 
   int64_t nxp = 0;
   uint8_t *inx = nullptr;
@@ -667,28 +747,13 @@ pg_status pg_load_csr(int64_t n, int64_t m, const void *offsets,
     return pg_fail(PG_EDEVICE, "no HIP device");
   }
   hipStream_t s = (hipStream_t)hip_stream;
-  // rank valuations unless asked for counts; repeated priorities switch to
-  // counts (the modified game is then built again with the dummies at 0)
-  bool dense = flags & PG_COUNT_VALUATION;
-  pg_status st;
-  for (;;) {
-    st = load_modified(n, m, offsets, targets, owner, priority, flags, s, g,
-                       dense);
-    if (st == PG_OK) st = alloc_state(g, g->n_aug);
-    if (st == PG_OK) st = finalize_state(g, s, true, !dense);
-    if (st == PG_OK || dense || !(g->hctr && (g->hctr[C_ERR] & ERR_DUPPRI)))
-      break;
-    (void)hipStreamSynchronize(s);
-    const int dev = g->device;
-    free_game(g);
-    g = new (std::nothrow) pg_game();
-    if (!g) return pg_fail(PG_ENOMEM, "host allocation failed");
-    g->device = dev;
-    g_last_error.clear();
-    dense = true;
-  }
-  if (st == PG_OK && dense) st = count_setup(g, s);
-  g->dense = dense;
+  // count valuations when asked for or when the priorities repeat
+  pg_status st =
+      load_modified(n, m, offsets, targets, owner, priority, flags, s, g,
+                    (flags & PG_COUNT_VALUATION) ? kLoadCount : kLoadAuto);
+  if (st == PG_OK) st = alloc_state(g, g->n_aug);
+  if (st == PG_OK) st = finalize_state(g, s, true, !g->dense);
+  if (st == PG_OK && g->dense) st = count_setup(g, s);
   g->careful = flags & PG_CAREFUL_WALKS;
   if (st != PG_OK) {
     (void)hipStreamSynchronize(s);

@@ -259,23 +259,6 @@ __global__ void k_batch_ctl2(int G, uint8_t *run, uint8_t *pending,
   cnt_even[s] = 0;
 }
 
-// flag when two neighbours of a sorted key array are equal
-__global__ void k_dup_check(const uint32_t *sk, int64_t n, int32_t *flag) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i > 0 && i < n && sk[i] == sk[i - 1]) *flag = 1;
-}
-
-__global__ void k_max_i32(const int32_t *a, int64_t n, int32_t *out) {
-  int32_t mx = -1;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    mx = a[i] > mx ? a[i] : mx;
-  for (int o = kWave / 2; o > 0; o >>= 1) {
-    const int32_t y = __shfl_down(mx, o, kWave);
-    mx = y > mx ? y : mx;
-  }
-  if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(out, mx);
-}
 
 }  // namespace pgk
 
@@ -552,7 +535,7 @@ pg_status pg_batch_submit(pg_batch *b, int64_t n, int64_t m,
   }
   bg->g->device = b->device;
   pg_status st = load_modified(n, m, offsets, targets, owner, priority, flags,
-                               s, bg->g);
+                               s, bg->g, kLoadRank);
   if (st == PG_OK && (bg->g->n_aug > b->cap_v || bg->g->m_aug > b->cap_e))
     st = pg_fail(PG_ENOMEM, "game larger than the batch capacity");
   if (st == PG_OK) st = dev_alloc(&bg->saved, bg->g->n_aug);

@@ -332,10 +332,17 @@ pg_status sync_ctr(pg_game *g, hipStream_t s);
 void free_game(pg_game *g);
 pg_status alloc_state(pg_game *g, int64_t cap);
 pg_status check_err(pg_game *g, const char *what);
+// flag when two neighbours of a sorted key array are equal
+__global__ void k_dup_check(const uint32_t *sk, int64_t n, int32_t *flag);
+// *out = max(*out, max of a[0..n)); *out must start at or below it
+__global__ void k_max_i32(const int32_t *a, int64_t n, int32_t *out);
+// kLoadAuto: count valuations when the input priorities repeat (sets
+// g->dense); kLoadRank / kLoadCount: that representation.
+enum LoadMode { kLoadRank = 0, kLoadCount = 1, kLoadAuto = 2 };
 pg_status load_modified(int64_t n, int64_t m, const void *offsets,
                         const int32_t *targets, const uint8_t *owner,
                         const int32_t *priority, uint32_t flags, hipStream_t s,
-                        pg_game *g, bool dense = false);
+                        pg_game *g, LoadMode mode);
 // distinct: reject repeated priorities (rank valuations)
 pg_status finalize_state(pg_game *g, hipStream_t s, bool init_sp,
                          bool distinct = true);

@@ -104,10 +104,7 @@ __global__ void k_cnt_compact(int32_t N, const uint8_t *__restrict__ rs,
   if (ctr[C_ABORT]) return;
   const int32_t nF = ctr[C_NFIN];
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v == 0) {  // the head carries no weight
-    elem[0].y = N;
-    elem[0].z = 0;
-  }
+  if (v == 0) elem[0] = make_int4(-1, N, 0, 0);  // the head: no weight
   if (v >= N) return;
   const uint8_t st = rs[v];
   if (st == 2) cnt[v * D] = -1;
@@ -120,11 +117,10 @@ __global__ void k_cnt_compact(int32_t N, const uint8_t *__restrict__ rs,
   fpos[v] = f;
   fvert[f] = (int32_t)v;
   start[f] = 2 * f + 1;
+  // whole 16-byte elements (the links are filled in by the next kernels)
   const int32_t col = pidx[v];
-  elem[2 * f + 1].y = (int32_t)v;
-  elem[2 * f + 1].z = col;
-  elem[2 * f + 2].y = (int32_t)v | (int32_t)0x80000000;
-  elem[2 * f + 2].z = col;
+  elem[2 * f + 1] = make_int4(-1, (int32_t)v, col, 0);
+  elem[2 * f + 2] = make_int4(-1, (int32_t)v | (int32_t)0x80000000, col, 0);
 }
 
 // Every finite v whose parent is not the sink appends the tour of its

@@ -136,3 +136,13 @@ def test_count_all_top_and_single_vertices():
                "owner": np.array([owner], np.uint8),
                "pri": np.array([pri], np.int32)}
         _check_solve(one, count_valuation=True)
+
+
+def test_count_sparse_huge_priorities():
+    """Repeated priorities far above 32 n take the sorting repeat check."""
+    g = synth.few_priorities_game(3000, 1, 5, 3, 13)
+    g["pri"] = np.array([0, 1 << 29, (1 << 29) + 1], np.int32)[g["pri"]]
+    out = _check_solve(g)
+    with Game.from_dict(g) as d:
+        assert d.d >= 3 and d.values[-1] >= (1 << 29)
+    assert out["stats"]["n_valuations"] >= 1
