@@ -349,7 +349,7 @@ void free_game(pg_game *g) {
                   g->sk1,      g->sv1,      g->tile_cnt, g->scan_tmp,
                   g->kids,     g->fh,       g->pos,      g->elem,
                   g->ctr,      g->u64tmp,   g->cvals,    g->pidx,
-                  g->cnt,      g->elem4};
+                  g->cnt,      g->elem4,    g->rs1};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (int k = 0; k < 8; ++k) {
@@ -389,6 +389,7 @@ pg_status alloc_state(pg_game *g, int64_t cap) {
   PG_TRY(dev_alloc(&g->sv1, N));
   g->tiles = radix_tiles(N);
   PG_TRY(dev_alloc(&g->tile_cnt, 256 * g->tiles));
+  PG_TRY(dev_alloc(&g->rs1, onesweep_words(N)));
   g->scan_tmp_bytes = radix_scan_tmp_bytes(N);
   size_t s2 = scan_excl_u32(nullptr, nullptr, N, nullptr, 0);
   if (s2 > g->scan_tmp_bytes) g->scan_tmp_bytes = s2;
@@ -422,6 +423,8 @@ pg_status check_err(pg_game *g, const char *what) {
                    "the play graph has a cycle whose largest priority is odd");
   if (e & (ERR_LISTWALK | ERR_RANKCOUNT))
     return pg_fail(PG_EINTERNAL, "list ranking failed a consistency check");
+  if (e & ERR_SORT)
+    return pg_fail(PG_EINTERNAL, "radix sort look-back timed out");
   return PG_OK;
 }
 

@@ -42,6 +42,7 @@ enum ErrBit : int {
   ERR_INVAL = 4,         // input validation failed
   ERR_DUPPRI = 8,        // repeated priority
   ERR_RANKCOUNT = 16,    // list ranking did not emit every finite vertex
+  ERR_SORT = 32,         // a radix-sort look-back gave up waiting
 };
 
 // Kernel kinds for the optional event profiler (pg_profile_* in pg.h).
@@ -155,6 +156,7 @@ struct pg_game {
   // sorting
   uint32_t *sk0 = nullptr, *sv0 = nullptr, *sk1 = nullptr, *sv1 = nullptr;
   uint32_t *tile_cnt = nullptr;  // [256 * tiles]
+  uint32_t *rs1 = nullptr;       // [onesweep_words(n_aug)] one-sweep sort
   int64_t tiles = 0;
   void *scan_tmp = nullptr;      // device-wide scan partials
   size_t scan_tmp_bytes = 0;
@@ -276,6 +278,15 @@ int radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
                hipStream_t s, Prof *prof = nullptr,
                const int32_t *gate = nullptr, bool index_values = false);
 size_t radix_scan_tmp_bytes(int64_t n);
+
+// The same sort in one kernel per 8-bit pass (decoupled look-back); `work`
+// holds onesweep_words(n) words; a look-back that waits too long sets
+// ERR_SORT in *err.
+int64_t onesweep_words(int64_t n);
+int radix_sort_1s(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
+                  int64_t n, int bits, uint32_t *work, int32_t *err,
+                  hipStream_t s, Prof *prof = nullptr,
+                  const int32_t *gate = nullptr, bool index_values = false);
 
 }  // namespace pgk
 

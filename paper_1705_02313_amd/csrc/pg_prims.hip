@@ -337,4 +337,256 @@ int radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
   return cur;
 }
 
+// ---------------------------------------------------------------------------
+// one-sweep stable LSD radix sort, 8-bit digits: one kernel builds the digit
+// histograms of every pass; then each pass is one kernel in which a tile
+// (taken in launch order from a counter) ranks its 4096 keys in LDS, learns
+// its global offset per digit by decoupled look-back over the tiles before
+// it, and writes each digit's run out contiguously.  A tile waits only on
+// tiles that took their number earlier and never wait on later ones, so the
+// look-back always ends; a bounded spin turns a broken protocol into an
+// error instead of a hang.
+// ---------------------------------------------------------------------------
+constexpr int k1sItems = 16;
+constexpr int k1sTile = kBlock * k1sItems;   // 4096 keys per tile
+constexpr uint32_t kStAgg = 1u << 30;        // tile count published
+constexpr uint32_t kStPre = 1u << 31;        // inclusive prefix published
+constexpr uint32_t kStVal = (1u << 30) - 1;
+constexpr int kSpinMax = 1 << 22;
+constexpr int k1sMaxPasses = 4;
+constexpr int k1sCopies = 64;   // histogram copies (blocks spread over them)
+
+int64_t onesweep_tiles(int64_t n) { return (n + k1sTile - 1) / k1sTile; }
+
+// work buffer: [counters 4 | histograms 64 copies x 4 x 256 | bases 4 x 256
+//               | status 4 x tiles x 256]
+constexpr int64_t k1sHistWords = (int64_t)k1sCopies * k1sMaxPasses * 256;
+
+int64_t onesweep_words(int64_t n) {
+  return 4 + k1sHistWords + k1sMaxPasses * 256 +
+         k1sMaxPasses * onesweep_tiles(n) * 256;
+}
+
+// lanes of the wave (among `valid` ones) whose 8-bit digit equals mine
+__device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
+  uint64_t peers = __ballot(valid);
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const bool bit = (d >> b) & 1u;
+    const uint64_t bb = __ballot(bit);
+    peers &= bit ? bb : ~bb;
+  }
+  return peers;
+}
+
+// Counts every digit of every pass, one block per 4096-key tile.  Each lane
+// loads its 16 keys at once (all in flight); then keys are counted 64 at a
+// time per wave: the lowest lane of each group of equal digits adds the
+// group's size to the wave's own counters, so no two lanes ever update one
+// counter at once (the keys are skewed: many vertices share a parent).
+__global__ __launch_bounds__(kBlock) void k_1s_hist(const uint32_t *keys,
+                                                    int64_t n, int passes,
+                                                    uint32_t *glob,
+                                                    const int32_t *gate) {
+  if (gate && *gate) return;
+  constexpr int kWaveItems = k1sTile / kRsWaves / kWave;   // 16
+  __shared__ uint32_t h[kRsWaves][k1sMaxPasses][256];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+  for (int p = 0; p < k1sMaxPasses; ++p)
+    for (int j = lane; j < 256; j += kWave) h[w][p][j] = 0;
+  const int64_t base =
+      (int64_t)blockIdx.x * k1sTile + w * (k1sTile / kRsWaves);
+  uint32_t k[kWaveItems];
+#pragma unroll
+  for (int r = 0; r < kWaveItems; ++r) {
+    const int64_t i = base + r * kWave + lane;
+    k[r] = i < n ? keys[i] : 0u;
+  }
+  for (int p = 0; p < passes; ++p) {
+#pragma unroll
+    for (int r = 0; r < kWaveItems; ++r) {
+      const bool valid = base + r * kWave + lane < n;
+      const uint32_t d = (k[r] >> (8 * p)) & 255u;
+      const uint64_t peers = digit_peers(d, valid);
+      if (valid && __popcll(peers & lt) == 0)
+        h[w][p][d] += (uint32_t)__popcll(peers);
+    }
+  }
+  __syncthreads();
+  // blocks add into one of k1sCopies copies: one counter hit by every block
+  // serialises on its address
+  uint32_t *copy = glob + (int64_t)(blockIdx.x % k1sCopies) *
+                              (k1sMaxPasses * 256);
+  for (int p = 0; p < passes; ++p) {
+    uint32_t t = 0;
+#pragma unroll
+    for (int j = 0; j < kRsWaves; ++j) t += h[j][p][threadIdx.x];
+    if (t) atomicAdd(&copy[p * 256 + threadIdx.x], t);
+  }
+}
+
+// digit bases of every pass: exclusive scans of the histograms
+__global__ __launch_bounds__(kBlock) void k_1s_base(const uint32_t *glob,
+                                                    int passes,
+                                                    uint32_t *base,
+                                                    const int32_t *gate) {
+  if (gate && *gate) return;
+  for (int p = 0; p < passes; ++p) {
+    uint32_t c = 0;
+    for (int j = 0; j < k1sCopies; ++j)
+      c += glob[(int64_t)j * (k1sMaxPasses * 256) + p * 256 + threadIdx.x];
+    uint32_t tot;
+    base[p * 256 + threadIdx.x] = block_excl_scan<uint32_t>(c, &tot);
+  }
+}
+
+__device__ __forceinline__ uint32_t ld_status(const uint32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void st_status(uint32_t *p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wave w of a tile owns the tile's keys [1024 w, 1024 w + 1024), 64 at a
+// time in order, so wave order then round order then lane order is input
+// order: ranks come out stable without barriers inside the loop.
+__global__ __launch_bounds__(kBlock) void k_1s_pass(
+    const uint32_t *kin, const uint32_t *__restrict__ vin, uint32_t *kout,
+    uint32_t *vout, int64_t n, int shift, const uint32_t *__restrict__ dbase,
+    uint32_t *status, uint32_t *tile_ctr, int32_t *err, const int32_t *gate) {
+  if (gate && *gate) return;
+  constexpr int kWaveItems = k1sTile / kRsWaves / kWave;   // 16
+  __shared__ uint32_t s_tile;
+  __shared__ uint32_t lk[k1sTile];
+  __shared__ uint32_t lv[k1sTile];
+  __shared__ uint32_t wc[kRsWaves][256];   // per wave: digit counts, then
+                                           // the wave's first slot per digit
+  __shared__ uint32_t start[256], goff[256];
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int w = tid / kWave;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+  if (tid == 0) s_tile = atomicAdd(tile_ctr, 1u);
+  for (int j = lane; j < 256; j += kWave) wc[w][j] = 0;
+  __syncthreads();
+  const uint32_t tile = s_tile;
+  const int64_t base = (int64_t)tile * k1sTile;
+  const int64_t rem = n - base;
+  const int tn = rem < k1sTile ? (int)rem : k1sTile;   // keys of this tile
+  uint32_t k[kWaveItems], v[kWaveItems], rk[kWaveItems];
+#pragma unroll
+  for (int r = 0; r < kWaveItems; ++r) {
+    const int j = w * (k1sTile / kRsWaves) + r * kWave + lane;
+    const bool valid = j < tn;
+    k[r] = valid ? kin[base + j] : 0u;
+    v[r] = valid ? (vin ? vin[base + j] : (uint32_t)(base + j)) : 0u;
+    const uint32_t d = (k[r] >> shift) & 255u;
+    const uint64_t peers = digit_peers(d, valid);
+    const uint32_t before = (uint32_t)__popcll(peers & lt);
+    const uint32_t cur = wc[w][d];
+    rk[r] = cur + before;
+    if (valid && before == 0) wc[w][d] = cur + (uint32_t)__popcll(peers);
+  }
+  __syncthreads();
+  // thread t: digit t of the tile
+  uint32_t c[kRsWaves], cnt = 0;
+#pragma unroll
+  for (int j = 0; j < kRsWaves; ++j) {
+    c[j] = wc[j][tid];
+    cnt += c[j];
+  }
+  // publish this tile's count at once (its prefix, for the first tile)
+  st_status(&status[(int64_t)tile * 256 + tid],
+            (tile == 0 ? kStPre : kStAgg) | cnt);
+  uint32_t tot;
+  const uint32_t st0 = block_excl_scan<uint32_t>(cnt, &tot);
+  start[tid] = st0;
+  uint32_t o = st0;
+#pragma unroll
+  for (int j = 0; j < kRsWaves; ++j) {
+    wc[j][tid] = o;
+    o += c[j];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kWaveItems; ++r) {
+    const int j = w * (k1sTile / kRsWaves) + r * kWave + lane;
+    if (j < tn) {
+      const uint32_t slot = wc[w][(k[r] >> shift) & 255u] + rk[r];
+      lk[slot] = k[r];
+      lv[slot] = v[r];
+    }
+  }
+  // decoupled look-back for digit tid
+  uint32_t excl = 0;
+  if (tile > 0) {
+    int64_t t = (int64_t)tile - 1;
+    int spins = 0;
+    for (;;) {
+      const uint32_t sv = ld_status(&status[t * 256 + tid]);
+      if (!(sv & (kStAgg | kStPre))) {
+        if (++spins > kSpinMax) {
+          atomicOr(err, ERR_SORT);
+          break;
+        }
+        continue;
+      }
+      excl += sv & kStVal;
+      if ((sv & kStPre) || t == 0) break;
+      --t;
+    }
+    st_status(&status[(int64_t)tile * 256 + tid], kStPre | (excl + cnt));
+  }
+  goff[tid] = dbase[tid] + excl;
+  __syncthreads();
+  // each digit's run goes out contiguously
+#pragma unroll 4
+  for (int r = 0; r < k1sItems; ++r) {
+    const int sl = r * kBlock + tid;
+    if (sl < tn) {
+      const uint32_t key = lk[sl];
+      const uint32_t d = (key >> shift) & 255u;
+      const uint32_t pos = goff[d] + (uint32_t)sl - start[d];
+      kout[pos] = key;
+      vout[pos] = lv[sl];
+    }
+  }
+}
+
+int radix_sort_1s(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
+                  int64_t n, int bits, uint32_t *work, int32_t *err,
+                  hipStream_t s, Prof *prof, const int32_t *gate,
+                  bool index_values) {
+  if (n <= 0 || bits <= 0) return 0;
+  const int passes = (bits + 7) / 8;
+  const int64_t tiles = onesweep_tiles(n);
+  uint32_t *ctr = work, *glob = work + 4, *base = glob + k1sHistWords;
+  uint32_t *status = base + k1sMaxPasses * 256;
+  // counters and histograms, then the status words of every pass
+  fill_i32((int32_t *)ctr, 0, 4 + k1sHistWords, s, prof);
+  fill_i32((int32_t *)status, 0, (int64_t)passes * tiles * 256, s, prof);
+  // keys read once for all digits
+  PG_LAUNCH(prof, K_RS_UPSWEEP, 4.0 * n, k_1s_hist, dim3((unsigned)tiles),
+            dim3(kBlock), 0, s, k0, n, passes, glob, gate);
+  PG_LAUNCH(prof, K_RS_SCAN, 0.0, k_1s_base, dim3(1), dim3(kBlock), 0, s,
+            glob, passes, base, gate);
+  int cur = 0;
+  for (int p = 0; p < passes; ++p) {
+    uint32_t *ki = cur ? k1 : k0;
+    const uint32_t *vi =
+        cur ? v1 : ((index_values && p == 0) ? nullptr : v0);
+    uint32_t *ko = cur ? k0 : k1, *vo = cur ? v0 : v1;
+    // keys and values read and written (16 B), 1 KiB of status per tile
+    PG_LAUNCH(prof, K_RS_DOWNSWEEP, 16.0 * n + 1024.0 * tiles, k_1s_pass,
+              dim3((unsigned)tiles), dim3(kBlock), 0, s, ki, vi, ko, vo, n,
+              8 * p, base + p * 256, status + (int64_t)p * tiles * 256,
+              ctr + p, err, gate);
+    cur ^= 1;
+  }
+  return cur;
+}
+
 }  // namespace pgk

@@ -694,9 +694,9 @@ static void enqueue_rank(pg_game *g, hipStream_t s) {
   const int32_t *gate = g->ctr + C_ABORT;
   // the root walks wrote the keys in signed-priority order; the values are
   // the positions in that order
-  const int which = radix_sort(g->sk0, g->sv0, g->sk1, g->sv1, N,
-                               g->sort_bits, g->tile_cnt, g->scan_tmp, s, pf,
-                               gate, true);
+  const int which = radix_sort_1s(g->sk0, g->sv0, g->sk1, g->sv1, N,
+                                  g->sort_bits, g->rs1, g->ctr + C_ERR, s, pf,
+                                  gate, true);
   const uint32_t *skS = which ? g->sk1 : g->sk0;
   const uint32_t *svS = which ? g->sv1 : g->sv0;
   // the finite count is only known on the device: size grids for N
@@ -786,6 +786,8 @@ static pg_status check_ctr(pg_game *g) {
     return pg_fail(PG_EINTERNAL, "list ranking walk exceeded its bound");
   if (e & ERR_RANKCOUNT)
     return pg_fail(PG_EINTERNAL, "list ranking lost elements");
+  if (e & ERR_SORT)
+    return pg_fail(PG_EINTERNAL, "radix sort look-back timed out");
   return PG_OK;
 }
 
