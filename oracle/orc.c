@@ -392,11 +392,14 @@ typedef struct {
  * Algorithm 1 on the (already modified) game.  sigma/tau are in-out (the
  * caller passes the initial strategies).  key[n+1] receives the last
  * valuation.  trace (nullable, capacity trace_cap) receives the hash of every
- * valuation's key array, in order.  Returns a status code.
+ * valuation's key array, in order.  reset != 0 is SI-Reset (section 6, the
+ * best-response experiment): every best response starts again from the
+ * initial Odd strategy (the first entry of each row) instead of the previous
+ * best response.  Returns a status code.
  */
 int orc_solve(int64_t n, const int64_t *off, const int32_t *tgt,
               const uint8_t *owner, const int32_t *pri, int method,
-              int64_t max_major, int64_t max_inner,
+              int64_t max_major, int64_t max_inner, int reset,
               int32_t *sigma, int32_t *tau, int32_t *key,
               orc_stats *st, uint64_t *trace, int64_t trace_cap)
 {
@@ -410,6 +413,9 @@ int orc_solve(int64_t n, const int64_t *off, const int32_t *tgt,
         int64_t inner = 0, c;
         if (max_major > 0 && nmaj >= max_major) { rc = ORC_EITERLIMIT; break; }
         ++nmaj;
+        if (reset)
+            for (v = 0; v < n; ++v)
+                if (owner[v]) tau[v] = tgt[off[v]];
         for (;;) {
             if (max_inner > 0 && inner >= max_inner) { rc = ORC_EITERLIMIT; break; }
             for (v = 0; v < n; ++v) succ[v] = owner[v] ? tau[v] : sigma[v];

@@ -22,6 +22,7 @@ SINK = -1
 KEY_TOP = 2**31 - 1
 OK, EINVAL, EINADMISSIBLE, EITERLIMIT, ENOMEM = 0, 1, 2, 3, 4
 RANK_KRUSKAL, RANK_PATHSORT = 0, 1
+BR_SI, BR_SI_RESET, BR_BELLMAN_FORD = 0, 1, 2
 
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
@@ -69,7 +70,8 @@ def lib():
         L.orc_order_by_pri.argtypes = [_I64, _P, _P]
         L.orc_solve.restype = ctypes.c_int
         L.orc_solve.argtypes = [_I64, _P, _P, _P, _P, ctypes.c_int, _I64, _I64,
-                                _P, _P, _P, ctypes.POINTER(Stats), _P, _I64]
+                                ctypes.c_int, _P, _P, _P,
+                                ctypes.POINTER(Stats), _P, _I64]
         L.orc_dense_preprocess.restype = _I64
         L.orc_dense_preprocess.argtypes = [_I64] + [_P] * 9
         L.orc_dense_priorities.restype = _I64
@@ -85,8 +87,12 @@ def lib():
         L.orc_dense_even_switch.argtypes = [_I64, _P, _P, _P, _I64, _P, _P,
                                             _P, _P]
         L.orc_dense_solve.restype = ctypes.c_int
-        L.orc_dense_solve.argtypes = [_I64, _P, _P, _P, _P, _I64, _I64, _P, _P,
-                                      _P, _P, ctypes.POINTER(Stats), _P, _I64]
+        L.orc_dense_solve.argtypes = [_I64, _P, _P, _P, _P, _I64, _I64,
+                                      ctypes.c_int, _P, _P, _P, _P,
+                                      ctypes.POINTER(Stats), _P, _I64]
+        L.orc_dense_bellman_ford.restype = _I64
+        L.orc_dense_bellman_ford.argtypes = [_I64, _P, _P, _P, _P, _I64, _P,
+                                             _P, _P, _P, _P]
         _lib = L
     return _lib
 
@@ -205,9 +211,11 @@ def initial_strategies(g: dict):
 
 def solve(game: dict, preprocess_game: bool = True,
           method: int = RANK_KRUSKAL, trace: bool = False,
-          max_major: int = 0, max_inner: int = 0, aug: dict = None) -> dict:
+          max_major: int = 0, max_inner: int = 0, aug: dict = None,
+          reset: bool = False) -> dict:
     """Algorithm 1; returns winners, strategies, counts, the last key array
-    and (with trace) the hash of every valuation."""
+    and (with trace) the hash of every valuation.  reset: SI-Reset (every
+    best response starts from the initial Odd strategy)."""
     g = aug if aug is not None else (
         preprocess(game) if preprocess_game else identity(game))
     n = int(g["n"])
@@ -220,7 +228,8 @@ def solve(game: dict, preprocess_game: bool = True,
                          _ptr(_c(g["targets"], np.int32)),
                          _ptr(_c(g["owner"], np.uint8)),
                          _ptr(_c(g["pri"], np.int32)), method, max_major,
-                         max_inner, _ptr(sigma), _ptr(tau), _ptr(key),
+                         max_inner, int(reset), _ptr(sigma), _ptr(tau),
+                         _ptr(key),
                          ctypes.byref(st), _ptr(tr) if trace else None, cap)
     n0 = int(g["n_orig"])
     winner = (key[:n0] != KEY_TOP).astype(np.uint8)
@@ -320,10 +329,11 @@ def dense_even_switch(g: dict, counts, top, values, sigma) -> tuple:
 
 def dense_solve(game: dict, preprocess_game: bool = True, trace: bool = False,
                 max_major: int = 0, max_inner: int = 0,
-                aug: dict = None) -> dict:
+                aug: dict = None, br: int = BR_SI) -> dict:
     """Algorithm 1 with count valuations; returns winners, strategies,
     counts, the last valuation (counts, top, values) and with trace the two
-    hashes (counts, top flags) of every valuation."""
+    hashes (counts, top flags) of every valuation.  br: BR_SI, BR_SI_RESET
+    or BR_BELLMAN_FORD (n_valuations then counts Bellman-Ford rounds)."""
     g = aug if aug is not None else (
         dense_preprocess(game) if preprocess_game else identity(game))
     n = int(g["n"])
@@ -339,7 +349,7 @@ def dense_solve(game: dict, preprocess_game: bool = True, trace: bool = False,
                                _ptr(_c(g["targets"], np.int32)),
                                _ptr(_c(g["owner"], np.uint8)),
                                _ptr(_c(g["pri"], np.int32)), max_major,
-                               max_inner, _ptr(sigma), _ptr(tau),
+                               max_inner, int(br), _ptr(sigma), _ptr(tau),
                                _ptr(counts), _ptr(top), ctypes.byref(st),
                                _ptr(tr) if trace else None, cap)
     n0 = int(g["n_orig"])
@@ -353,3 +363,19 @@ def dense_solve(game: dict, preprocess_game: bool = True, trace: bool = False,
             "n_odd_switches": int(st.n_odd_switches),
             "trace": tr[:min(2 * nv, cap)].reshape(-1, 2).copy()
             if trace else None}
+
+
+def dense_bellman_ford(g: dict, sigma) -> dict:
+    """Bellman-Ford best response against sigma on a count game: returns
+    tau, counts, top (no path to the sink), values and the number of rounds."""
+    values, idx = dense_priorities(g["pri"])
+    n, d = int(g["n"]), values.size
+    tau = _c(initial_strategies(g)[1], np.int32).copy()
+    counts = np.zeros((n + 1, d), np.int32)
+    top = np.zeros(max(n, 1), np.uint8)
+    r = lib().orc_dense_bellman_ford(
+        n, _ptr(_c(g["offsets"], np.int64)), _ptr(_c(g["targets"], np.int32)),
+        _ptr(_c(g["owner"], np.uint8)), _ptr(idx), d, _ptr(values),
+        _ptr(_c(sigma, np.int32)), _ptr(tau), _ptr(counts), _ptr(top))
+    return {"tau": tau, "counts": counts, "top": top[:n].copy(),
+            "values": values, "rounds": int(r)}

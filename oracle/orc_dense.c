@@ -17,7 +17,10 @@
  *     when p is odd the smaller count is.  Top is above every L.
  *   - section 3, "The algorithm" (sigma_init and the preprocessing) and
  *     "Switching rules" (greedy all-switches);
- *   - section 4, All_Odd and Algorithm 1.
+ *   - section 4, All_Odd and Algorithm 1;
+ *   - section 4 (best responses as shortest paths) and section 6 (the
+ *     best-response experiment): Bellman-Ford best responses, and SI-Reset,
+ *     which starts every best response from the initial Odd strategy.
  *
  * The valuation is the natural sequential algorithm: follow each play until
  * the sink, a vertex whose valuation is already known, or a vertex of the
@@ -288,12 +291,86 @@ int64_t orc_dense_even_switch(int64_t n, const int64_t *off,
     return count;
 }
 
+/*
+ * Bellman-Ford best response against sigma (section 4: with sigma
+ * admissible, a best response is a shortest path to the sink for each vertex
+ * under the valuation order, odd priorities acting as negative weights).
+ * Labels are count vectors; a vertex without a path to the sink yet has no
+ * label, which compares as top.  Jacobi rounds: every vertex recomputes its
+ * label from the previous round's labels -- an Even vertex from sigma(v), an
+ * Odd vertex from the least labelled successor -- plus one at pri(v), until
+ * a round changes nothing (that round is counted).  Then tau(v) is the first
+ * row position of least final label, counts/top hold the labels as
+ * valuations (no label = top), and the number of rounds is returned.
+ */
+int64_t orc_dense_bellman_ford(int64_t n, const int64_t *off,
+                               const int32_t *tgt, const uint8_t *owner,
+                               const int32_t *idx, int64_t d,
+                               const int32_t *values, const int32_t *sigma,
+                               int32_t *tau, int32_t *counts, uint8_t *top)
+{
+    size_t rows = (size_t)(n + 1) * (size_t)(d ? d : 1);
+    int32_t *nl = (int32_t *)calloc(rows, sizeof(int32_t));
+    uint8_t *ntop = (uint8_t *)malloc((size_t)(n ? n : 1));
+    int64_t v, e, j, rounds = 0;
+    int changed = 1;
+    if (!nl || !ntop) { free(nl); free(ntop); return -1; }
+    memset(counts, 0, sizeof(int32_t) * rows);
+    for (v = 0; v < n; ++v) top[v] = 1;
+    while (changed) {
+        changed = 0;
+        ++rounds;
+        for (v = 0; v < n; ++v) {
+            int64_t best = -1;
+            int32_t *row = nl + v * d;
+            if (owner[v] == 0) {
+                best = sigma[v] < 0 ? n : sigma[v];
+                if (best < n && top[best]) best = -1;
+            } else {
+                for (e = off[v]; e < off[v + 1]; ++e) {
+                    int64_t u = tgt[e];
+                    if (top[u]) continue;
+                    if (best < 0 ||
+                        dense_cmp(n, d, values, counts, top, u, best) < 0)
+                        best = u;
+                }
+            }
+            ntop[v] = best < 0;
+            for (j = 0; j < d; ++j)
+                row[j] = best < 0 ? 0 : counts[best * d + j];
+            if (best >= 0) row[idx[v]] += 1;
+        }
+        for (v = 0; v < n; ++v) {
+            if (ntop[v] != top[v]) changed = 1;
+            for (j = 0; j < d && !changed; ++j)
+                if (nl[v * d + j] != counts[v * d + j]) changed = 1;
+        }
+        for (v = 0; v < n; ++v) {
+            top[v] = ntop[v];
+            for (j = 0; j < d; ++j) counts[v * d + j] = nl[v * d + j];
+        }
+    }
+    for (v = 0; v < n; ++v) {
+        int32_t best;
+        if (owner[v] != 1) continue;
+        best = tgt[off[v]];
+        for (e = off[v] + 1; e < off[v + 1]; ++e)
+            if (dense_cmp(n, d, values, counts, top, tgt[e], best) < 0)
+                best = tgt[e];
+        tau[v] = best;
+    }
+    free(nl); free(ntop);
+    return rounds;
+}
+
 typedef struct {
     int64_t n_major;
     int64_t n_valuations;
     int64_t n_even_switches;
     int64_t n_odd_switches;
 } orc_dense_stats;
+
+enum { ORC_BR_SI = 0, ORC_BR_SI_RESET = 1, ORC_BR_BELLMAN_FORD = 2 };
 
 /*
  * Algorithm 1 on the (already modified) game, as orc_solve but with count
@@ -302,12 +379,17 @@ typedef struct {
  * (d = number of distinct priorities, values[] as orc_dense_priorities
  * returns them).  trace (nullable, capacity trace_cap) receives, per
  * valuation, the hash of its counts followed by the hash of its top flags.
+ * br selects the best response: ORC_BR_SI (Algorithm 1), ORC_BR_SI_RESET
+ * (each best response starts from the initial Odd strategy) or
+ * ORC_BR_BELLMAN_FORD (orc_dense_bellman_ford; n_valuations then counts its
+ * rounds and nothing is traced).
  */
 int orc_dense_solve(int64_t n, const int64_t *off, const int32_t *tgt,
                     const uint8_t *owner, const int32_t *pri,
-                    int64_t max_major, int64_t max_inner, int32_t *sigma,
-                    int32_t *tau, int32_t *counts, uint8_t *top,
-                    orc_dense_stats *st, uint64_t *trace, int64_t trace_cap)
+                    int64_t max_major, int64_t max_inner, int br,
+                    int32_t *sigma, int32_t *tau, int32_t *counts,
+                    uint8_t *top, orc_dense_stats *st, uint64_t *trace,
+                    int64_t trace_cap)
 {
     size_t nn = (size_t)(n ? n : 1);
     int32_t *succ = (int32_t *)malloc(sizeof(int32_t) * nn);
@@ -325,6 +407,15 @@ int orc_dense_solve(int64_t n, const int64_t *off, const int32_t *tgt,
         int64_t inner = 0, c;
         if (max_major > 0 && nmaj >= max_major) { rc = ORC_EITERLIMIT; break; }
         ++nmaj;
+        if (br == ORC_BR_SI_RESET)
+            for (v = 0; v < n; ++v)
+                if (owner[v]) tau[v] = tgt[off[v]];
+        if (br == ORC_BR_BELLMAN_FORD) {
+            int64_t r = orc_dense_bellman_ford(n, off, tgt, owner, idx, d,
+                                               values, sigma, tau, counts, top);
+            if (r < 0) { rc = ORC_ENOMEM; break; }
+            nval += r;
+        } else
         for (;;) {
             if (max_inner > 0 && inner >= max_inner) { rc = ORC_EITERLIMIT; break; }
             for (v = 0; v < n; ++v) succ[v] = owner[v] ? tau[v] : sigma[v];

@@ -14,7 +14,10 @@ pins:
     vertices alike);
   * the preprocessing reading of this path: the same X, X' and redirected
     edges as the rank path, dummies at priority 0, originals raised by 2,
-    winners kept.
+    winners kept;
+  * the best-response variants of section 6: Bellman-Ford labels and round
+    counts against the literal oracle's Bellman-Ford and against SI's best
+    responses; SI-Reset and Bellman-Ford leave the outer loop unchanged.
 """
 from __future__ import annotations
 
@@ -234,3 +237,62 @@ def test_dense_preprocess_reading(seed):
     from tests.test_oracle_pins import _odd_subgraph_acyclic
     assert _odd_subgraph_acyclic(lit)
     np.testing.assert_array_equal(zielonka(dn)[:n], zielonka(g))
+
+
+# ---------------------------------------------------------------------------
+# best-response variants (section 4; section 6, Table 2's SI / SI-Reset /
+# Bellman-Ford comparison)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", range(20))
+def test_dense_bellman_ford_matches_literal_and_si(seed):
+    """At every major iteration of the SI run: the C oracle's Bellman-Ford
+    labels and round count equal the literal oracle's, the labels equal SI's
+    best-response valuations, and its tau realises them."""
+    g = _few(seed, nmin=5, nmax=60)
+    aug = orc.dense_preprocess(g)
+    lit = L.solve(aug, preprocess_game=False)
+    rows = L.rows_of(aug)
+    for sigma, tau, val in lit["majors"]:
+        bf = orc.dense_bellman_ford(aug, sigma)
+        lab, rounds = L.bellman_ford(aug, lit["vals"], rows, sigma)
+        assert bf["rounds"] == rounds
+        for v in range(aug["n"]):
+            for ref in (lab[v], val[v]):
+                if ref is L.TOP:
+                    assert bf["top"][v] == 1
+                else:
+                    assert bf["top"][v] == 0
+                    np.testing.assert_array_equal(bf["counts"][v], ref)
+        succ = np.where(aug["owner"] == 1, bf["tau"], sigma).astype(np.int32)
+        c2, t2, _, rc = orc.dense_valuation(succ, aug["pri"])
+        assert rc == orc.OK
+        np.testing.assert_array_equal(t2, bf["top"])
+        np.testing.assert_array_equal(c2, bf["counts"])
+
+
+@pytest.mark.parametrize("seed", range(15))
+def test_dense_best_response_variants_same_outer_run(seed):
+    """The outer loop sees only valuations, which every best response gives
+    alike: the same sigma at the end, winners and major iterations."""
+    g = _few(seed, nmin=20, nmax=400)
+    si = orc.dense_solve(g)
+    for br in (orc.BR_SI_RESET, orc.BR_BELLMAN_FORD):
+        r = orc.dense_solve(g, br=br)
+        assert r["status"] == orc.OK
+        np.testing.assert_array_equal(r["winner"], si["winner"])
+        np.testing.assert_array_equal(r["sigma"], si["sigma"])
+        assert r["n_major"] == si["n_major"]
+        np.testing.assert_array_equal(r["top"], si["top"])
+        np.testing.assert_array_equal(r["counts"], si["counts"])
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_si_reset_rank_oracle(seed):
+    g = synth.random_game(50 + 30 * seed, 1 + seed % 3, 5, 4000 + seed)
+    si = orc.solve(g)
+    rs = orc.solve(g, reset=True)
+    assert rs["status"] == orc.OK
+    for k in ("winner", "sigma", "key"):
+        np.testing.assert_array_equal(rs[k], si[k])
+    assert rs["n_major"] == si["n_major"]
+    assert rs["n_valuations"] >= rs["n_major"]
