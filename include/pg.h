@@ -219,11 +219,31 @@ pg_status pg_best_response(pg_game *game, const int32_t *sigma, int32_t *tau,
                            int32_t max_inner, uint32_t flags,
                            void *hip_stream);
 
+/*
+ * Best responses of pg_solve (section 4; section 6 compares the three):
+ *   PG_BR_SI             one-player strategy improvement, each best response
+ *                        starting from the previous one (Algorithm 1)
+ *   PG_BR_SI_RESET       the same, each best response starting again from
+ *                        the initial Odd strategy (first entry of each row)
+ *   PG_BR_BELLMAN_FORD   shortest paths to the sink under the valuation
+ *                        order by Jacobi rounds of Bellman-Ford (count
+ *                        valuations only); tau(v) is then the first row
+ *                        position of least valuation.  n_valuations counts
+ *                        its rounds.
+ * All three give the same valuations, hence the same outer iterations,
+ * final sigma and winners; tau can differ where successors tie.
+ */
+enum {
+    PG_BR_SI = 0,
+    PG_BR_SI_RESET = 1,
+    PG_BR_BELLMAN_FORD = 2
+};
+
 typedef struct pg_solve_opts {
     int32_t max_major;      /* cap on outer iterations (0 = none)            */
     int32_t max_inner;      /* cap on valuations per best response (0=none)  */
     uint32_t flags;         /* PG_PTR_DEVICE for the output buffers          */
-    int32_t reserved;
+    int32_t best_response;  /* PG_BR_* (0 = PG_BR_SI)                        */
 } pg_solve_opts;
 
 typedef struct pg_stats {
@@ -243,7 +263,8 @@ typedef struct pg_stats {
  * vertex switches; by Theorem 1 the vertices of key PG_KEY_TOP are then
  * exactly Even's winning set.
  *
- *   opts     nullable (no caps; host outputs)
+ *   opts     nullable (no caps; host outputs; PG_BR_SI).  PG_EINVAL for
+ *            PG_BR_BELLMAN_FORD on a game with rank valuations.
  *   winner   n outputs (original vertices): 0 = W_Even, 1 = W_Odd
  *   sigma    n_aug outputs (nullable): the final sigma* (PG_SINK for the
  *            sink); vertices Even wins never map to the sink

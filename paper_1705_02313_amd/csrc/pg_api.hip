@@ -278,6 +278,16 @@ __global__ void k_count_odd_edges(const int64_t *off, const uint8_t *owner,
 }
 
 // Theorem 1: W_Even is the set of vertices whose final valuation is top
+// SI-Reset: every Odd vertex back to the first entry of its row.
+__global__ void k_sp_reset_odd(const int64_t *off, const int32_t *tgt,
+                               const uint8_t *owner, const int32_t *pri,
+                               int2 *sp, int32_t N) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= N || owner[v] != 1) return;
+  const int32_t u = tgt[off[v]];
+  sp[v] = make_int2(u, pri[u]);
+}
+
 // Theorem 1: Even wins exactly where the final valuation is top (the walks
 // of the last valuation marked those vertices with rs = 2).
 __global__ void k_winner(const uint8_t *rs, uint8_t *winner, int64_t n) {
@@ -349,7 +359,7 @@ void free_game(pg_game *g) {
                   g->sk1,      g->sv1,      g->tile_cnt, g->scan_tmp,
                   g->kids,     g->fh,       g->pos,      g->elem,
                   g->ctr,      g->u64tmp,   g->cvals,    g->pidx,
-                  g->cnt,      g->elem4,    g->rs1};
+                  g->cnt,      g->elem4,    g->rs1,      g->cnt2};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (int k = 0; k < 8; ++k) {
@@ -895,6 +905,11 @@ pg_status pg_solve(pg_game *g, const pg_solve_opts *opts, uint8_t *winner,
   pg_solve_opts o{};
   if (opts) o = *opts;
   const bool dev = o.flags & PG_PTR_DEVICE;
+  if (o.best_response < PG_BR_SI || o.best_response > PG_BR_BELLMAN_FORD)
+    return pg_fail(PG_EINVAL, "unknown best-response selector");
+  if (o.best_response == PG_BR_BELLMAN_FORD && !g->dense)
+    return pg_fail(PG_EINVAL, "Bellman-Ford best responses need a game with "
+                              "count valuations");
   const auto t0 = std::chrono::steady_clock::now();
   const int64_t N = g->n_aug;
   hipLaunchKernelGGL(k_sp_init, dim3(grid_for(N)), dim3(kBlock), 0, s, g->off,
@@ -908,7 +923,16 @@ pg_status pg_solve(pg_game *g, const pg_solve_opts *opts, uint8_t *winner,
       break;
     }
     ++n_major;
-    st = inner_loop(g, o.max_inner, s, &n_val, &n_odd);
+    if (o.best_response == PG_BR_SI_RESET)
+      hipLaunchKernelGGL(k_sp_reset_odd, dim3(grid_for(N)), dim3(kBlock), 0, s,
+                         g->off, g->tgt, g->owner, g->pri, g->sp, (int32_t)N);
+    if (o.best_response == PG_BR_BELLMAN_FORD) {
+      int64_t rounds = 0;
+      st = bf_best_response(g, s, &rounds);
+      n_val += rounds;
+    } else {
+      st = inner_loop(g, o.max_inner, s, &n_val, &n_odd);
+    }
     if (st != PG_OK) break;
     int32_t c = 0;
     st = switch_device(g, false, s, &c);

@@ -184,6 +184,7 @@ struct pg_game {
   int32_t *cvals = nullptr;   // [32] the same on the device
   uint8_t *pidx = nullptr;    // [n_aug] column of each vertex's priority
   int32_t *cnt = nullptr;     // [(n_aug+1) * dw] counts; row n_aug: the sink
+  int32_t *cnt2 = nullptr;    // the same size: Bellman-Ford's second buffer
   int4 *elem4 = nullptr;      // [2*n_aug+2] {next, vertex | up bit, column}
   int32_t *vsum[8] = {};      // per level: dw ints per splitter
   int32_t *vbase[8] = {};
@@ -315,6 +316,9 @@ int count_levels(int64_t n_aug, int dw);
 void enqueue_count(pg_game *g, hipStream_t s);
 // All_Odd (odd) or All_Even on count valuations; counts into C_DIST_SW.
 void enqueue_count_switch(pg_game *g, bool odd, hipStream_t s);
+// Bellman-Ford best response against the sigma in g->sp: labels into
+// g->cnt, tau into g->sp, finite/top into g->rs; *rounds = Jacobi rounds.
+pg_status bf_best_response(pg_game *g, hipStream_t s, int64_t *rounds);
 // counts[(n_aug+1) * d] row-major (top rows zero) and top[n_aug]
 pg_status export_counts(pg_game *g, int32_t *counts, uint8_t *top, bool dev,
                         hipStream_t s);

@@ -497,6 +497,96 @@ __global__ __launch_bounds__(kBlock) void k_cnt_even_switch(
   count_block(&ctr[C_DIST_SW], sw);
 }
 
+// ---------------------------------------------------------------------------
+// Bellman-Ford best responses (section 4: shortest paths to the sink under
+// the valuation order; section 6 compares them with one-player SI).  Labels
+// are count rows; a vertex without a path to the sink yet carries the top
+// marker.  Jacobi rounds read one buffer and write the other.
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ void k_bf_init(int32_t N, int32_t *lab) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v > N) return;
+  int32_t z[D] = {};
+  if (v < N) z[0] = -1;   // no label yet; the sink's row stays zero
+  store_vec<D>(lab + v * D, z);
+}
+
+// An Even vertex takes sigma(v)'s label, an Odd vertex its least successor
+// label (top when none has a label), plus one at pri(v).  Counts the
+// vertices whose label changed.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_bf_round(
+    int32_t N, const int64_t *__restrict__ off,
+    const int32_t *__restrict__ tgt, const uint8_t *__restrict__ owner,
+    const uint8_t *__restrict__ pidx, const int2 *__restrict__ sp,
+    const int32_t *__restrict__ old, int32_t *nw, uint32_t odd_cols,
+    int32_t *ctr) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool changed = false;
+  if (v < N) {
+    int32_t bv[D];
+    bool bt;
+    if (owner[v] == 0) {
+      bt = load_val<D>(old, sp[v].x, bv);
+    } else {
+      const int64_t e0 = off[v], e1 = off[v + 1];
+      bt = load_val<D>(old, tgt[e0], bv);
+      for (int64_t e = e0 + 1; e < e1; ++e) {
+        int32_t uv[D];
+        const bool ut = load_val<D>(old, tgt[e], uv);
+        if (vcmp<D>(ut, uv, bt, bv, odd_cols) < 0) {
+          bt = ut;
+#pragma unroll
+          for (int i = 0; i < D; ++i) bv[i] = uv[i];
+        }
+      }
+    }
+    if (bt) {
+#pragma unroll
+      for (int i = 0; i < D; ++i) bv[i] = i == 0 ? -1 : 0;
+    } else {
+      add_unit<D>(bv, pidx[v], 1);
+    }
+    int32_t ov[D];
+    load_vec<D>(old + v * D, ov);
+#pragma unroll
+    for (int i = 0; i < D; ++i) changed |= ov[i] != bv[i];
+    store_vec<D>(nw + v * D, bv);
+  }
+  count_block(&ctr[C_DIST_SW], changed);
+}
+
+// At the fixpoint: tau(v) = the first row position of least label, and the
+// finite/top classification the winners are read from.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_bf_finish(
+    int32_t N, const int64_t *__restrict__ off,
+    const int32_t *__restrict__ tgt, const uint8_t *__restrict__ owner,
+    const int32_t *__restrict__ lab, uint32_t odd_cols,
+    const int32_t *__restrict__ pri, int2 *sp, uint8_t *rs) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= N) return;
+  rs[v] = lab[v * D] < 0 ? 2 : 1;
+  if (owner[v] != 1) return;
+  const int64_t e0 = off[v], e1 = off[v + 1];
+  int32_t best = tgt[e0];
+  int32_t bv[D];
+  bool bt = load_val<D>(lab, best, bv);
+  for (int64_t e = e0 + 1; e < e1; ++e) {
+    const int32_t u = tgt[e];
+    int32_t uv[D];
+    const bool ut = load_val<D>(lab, u, uv);
+    if (vcmp<D>(ut, uv, bt, bv, odd_cols) < 0) {
+      best = u;
+      bt = ut;
+#pragma unroll
+      for (int i = 0; i < D; ++i) bv[i] = uv[i];
+    }
+  }
+  sp[v] = make_int2(best, pri[best]);
+}
+
 // counts out[(N+1) * d] (rows of top vertices zero) and top[N]
 template <int D>
 __global__ void k_cnt_export(int32_t N, int d, const uint8_t *rs,
@@ -565,6 +655,8 @@ pg_status count_setup(pg_game *g, hipStream_t s) {
   // count rows; the sink's row stays zero
   PG_TRY(dev_alloc(&g->cnt, (N + 1) * g->dw));
   fill_i32(g->cnt, 0, (N + 1) * g->dw, s);
+  PG_TRY(dev_alloc(&g->cnt2, (N + 1) * g->dw));
+  fill_i32(g->cnt2, 0, (N + 1) * g->dw, s);
   int64_t size = 2 * N + 1;
   for (int k = 0; k < 8; ++k) {
     const int64_t ns = (size + kStride - 1) / kStride;
@@ -687,6 +779,50 @@ void enqueue_count_switch(pg_game *g, bool odd, hipStream_t s) {
     case 8: enqueue_count_switch_t<8>(g, odd, s); break;
     case 16: enqueue_count_switch_t<16>(g, odd, s); break;
     default: enqueue_count_switch_t<32>(g, odd, s); break;
+  }
+}
+
+template <int D>
+static pg_status bf_best_response_t(pg_game *g, hipStream_t s,
+                                    int64_t *rounds) {
+  const int32_t N = (int32_t)g->n_aug;
+  Prof *pf = &g->prof;
+  hipLaunchKernelGGL(k_bf_init<D>, dim3(grid_for(N + 1)), dim3(kBlock), 0, s,
+                     N, g->cnt);
+  int64_t r = 0;
+  for (;;) {
+    if (r > (int64_t)N + 2)
+      return pg_fail(PG_EINTERNAL, "Bellman-Ford did not reach a fixpoint");
+    fill_i32(g->ctr + C_DIST_SW, 0, kDistSlots * kDistStride, s, pf);
+    fill_i32(g->ctr + C_SWITCH, 0, 1, s, pf);
+    // every vertex: its label and its row's labels; Odd rows dominate
+    PG_LAUNCH(pf, K_ODD_SWITCH, (16.0 + 8.0 * D) * N + (4.0 + 4.0 * D) *
+                                    g->m_aug,
+              k_bf_round<D>, dim3(grid_for(N)), dim3(kBlock), 0, s, N, g->off,
+              g->tgt, g->owner, g->pidx, g->sp, g->cnt, g->cnt2, g->odd_cols,
+              g->ctr);
+    sum_dist(g->ctr, C_DIST_SW, C_SWITCH, s, pf);
+    PG_HIP(hipMemcpyAsync(g->hctr, g->ctr, sizeof(int32_t) * C_COUNT,
+                          hipMemcpyDeviceToHost, s));
+    PG_HIP(hipStreamSynchronize(s));
+    if (g->prof.on) g->prof.flush();
+    std::swap(g->cnt, g->cnt2);
+    ++r;
+    if (g->hctr[C_SWITCH] == 0) break;
+  }
+  hipLaunchKernelGGL(k_bf_finish<D>, dim3(grid_for(N)), dim3(kBlock), 0, s, N,
+                     g->off, g->tgt, g->owner, g->cnt, g->odd_cols, g->pri,
+                     g->sp, g->rs);
+  *rounds = r;
+  return PG_OK;
+}
+
+pg_status bf_best_response(pg_game *g, hipStream_t s, int64_t *rounds) {
+  switch (g->dw) {
+    case 4: return bf_best_response_t<4>(g, s, rounds);
+    case 8: return bf_best_response_t<8>(g, s, rounds);
+    case 16: return bf_best_response_t<16>(g, s, rounds);
+    default: return bf_best_response_t<32>(g, s, rounds);
   }
 }
 

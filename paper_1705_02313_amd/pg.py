@@ -22,6 +22,7 @@ PG_SINK = -1
 PG_KEY_TOP = 2**31 - 1
 PG_PTR_DEVICE, PG_NO_PREPROCESS, PG_OFFSETS_I32 = 1, 2, 4
 PG_CAREFUL_WALKS, PG_COUNT_VALUATION = 8, 16
+PG_BR_SI, PG_BR_SI_RESET, PG_BR_BELLMAN_FORD = 0, 1, 2
 
 STATUS_NAMES = {0: "PG_OK", 1: "PG_EINVAL", 2: "PG_ENOMEM", 3: "PG_EDEVICE",
                 4: "PG_EITERLIMIT", 5: "PG_EINADMISSIBLE", 6: "PG_EINTERNAL"}
@@ -45,7 +46,7 @@ class PgError(RuntimeError):
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [("max_major", ctypes.c_int32), ("max_inner", ctypes.c_int32),
-                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32)]
+                ("flags", ctypes.c_uint32), ("best_response", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -286,8 +287,9 @@ class Game:
                                       self._flags, _stream(self.device)))
         return tau, key, int(nv.value)
 
-    def solve(self, max_major: int = 0, max_inner: int = 0) -> dict:
-        opts = SolveOpts(max_major, max_inner, self._flags, 0)
+    def solve(self, max_major: int = 0, max_inner: int = 0,
+              best_response: int = PG_BR_SI) -> dict:
+        opts = SolveOpts(max_major, max_inner, self._flags, best_response)
         winner = self._out(self.n, np.uint8)
         sigma = self._out(self.n_aug, np.int32)
         tau = self._out(self.n_aug, np.int32)

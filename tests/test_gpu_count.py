@@ -11,7 +11,8 @@ import pytest
 
 from oracle import orc
 from paper_1705_02313_amd import synth
-from paper_1705_02313_amd.pg import PG_EINVAL, Game, PgError
+from paper_1705_02313_amd.pg import (PG_BR_BELLMAN_FORD, PG_BR_SI_RESET,
+                                     PG_EINVAL, Game, PgError)
 from tests.helpers import dense_oracle_trajectory, to_np
 
 pytestmark = pytest.mark.gpu
@@ -146,3 +147,39 @@ def test_count_sparse_huge_priorities():
     with Game.from_dict(g) as d:
         assert d.d >= 3 and d.values[-1] >= (1 << 29)
     assert out["stats"]["n_valuations"] >= 1
+
+
+@pytest.mark.parametrize("br", [PG_BR_SI_RESET, PG_BR_BELLMAN_FORD])
+@pytest.mark.parametrize("n,d,seed", [(500, 2, 21), (20000, 4, 22),
+                                      (5000, 9, 23)])
+def test_count_best_response_variants(br, n, d, seed):
+    """SI-Reset and Bellman-Ford (section 6's best-response comparison)
+    against the oracle: strategies, winners, outer iterations, and the
+    number of valuations (SI-Reset) or Bellman-Ford rounds."""
+    g = synth.few_priorities_game(n, 2, 5, d, seed)
+    ref = orc.dense_solve(g, br=br)
+    assert ref["status"] == orc.OK
+    with Game.from_dict(g) as dev:
+        out = dev.solve(best_response=br)
+    np.testing.assert_array_equal(to_np(out["winner"]), ref["winner"])
+    np.testing.assert_array_equal(to_np(out["sigma"]), ref["sigma"])
+    np.testing.assert_array_equal(to_np(out["tau"]), ref["tau"])
+    assert out["stats"]["n_major"] == ref["n_major"]
+    assert out["stats"]["n_valuations"] == ref["n_valuations"]
+
+
+def test_rank_si_reset_and_bellman_ford_errors():
+    g = synth.random_game(3000, 2, 5, 24)
+    ref = orc.solve(g, reset=True)
+    with Game.from_dict(g) as dev:
+        out = dev.solve(best_response=PG_BR_SI_RESET)
+        np.testing.assert_array_equal(to_np(out["winner"]), ref["winner"])
+        np.testing.assert_array_equal(to_np(out["sigma"]), ref["sigma"])
+        np.testing.assert_array_equal(to_np(out["tau"]), ref["tau"])
+        assert out["stats"]["n_valuations"] == ref["n_valuations"]
+        with pytest.raises(PgError) as e:
+            dev.solve(best_response=PG_BR_BELLMAN_FORD)
+        assert e.value.status == PG_EINVAL
+        with pytest.raises(PgError) as e:
+            dev.solve(best_response=7)
+        assert e.value.status == PG_EINVAL
