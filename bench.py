@@ -26,8 +26,10 @@ Workloads (seeded, synthetic; see paper_1705_02313_amd/synth.py):
 
 Printed: one JSON line with the driver's fields plus "roofline" (the kernel
 that takes the most time, its algorithmic bytes over its event-timed
-duration against 8 TB/s) and "cpu_baseline" (the CPU oracle timed on this
-host on a bounded sample of the same workload).
+duration against 8 TB/s, from up to two profiled steps run after the timed
+steps) and "cpu_baseline" (the CPU oracle timed on this host on a bounded
+sample of the same workload).  --best-response picks the best responses
+(section 6's comparison: SI, SI-Reset, Bellman-Ford on count games).
 """
 from __future__ import annotations
 
@@ -238,6 +240,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the per-kernel event profiler")
+    ap.add_argument("--best-response", default="si",
+                    choices=["si", "reset", "bf"],
+                    help="best responses: one-player SI (Algorithm 1), "
+                         "SI-Reset, or Bellman-Ford (count games)")
     ap.add_argument("--mix-games", type=int, default=1024,
                     help="games in the batched/served workload")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -268,6 +274,7 @@ def main():
     from paper_1705_02313_amd import synth
     from paper_1705_02313_amd.pg import Game
 
+    br = {"si": 0, "reset": 1, "bf": 2}[args.best_response]
     desc, cfg = WORKLOADS[args.workload]
     log(f"generating {args.workload}: {desc}")
     t0 = time.perf_counter()
@@ -288,7 +295,7 @@ def main():
         t_b = time.perf_counter()
         if profile:
             g.profile(True)
-        out = g.solve()
+        out = g.solve(best_response=br)
         torch.cuda.synchronize()
         t_c = time.perf_counter()
         prof = g.profile_read() if profile else {}
@@ -312,7 +319,7 @@ def main():
     t_start = time.perf_counter()
     ev0.record()
     for i in range(args.steps):
-        r = step(not args.no_profile)
+        r = step(False)
         runs.append(r)
         log(f"step {i}: {r['total'] * 1e3:.1f} ms (load {r['load'] * 1e3:.1f}, "
             f"solve {r['solve'] * 1e3:.1f}, valuations "
@@ -330,12 +337,19 @@ def main():
     solve_s = [r["solve"] for r in runs]
     load_s = [r["load"] for r in runs]
 
-    # roofline of the dominant kernel (summed over the timed steps)
+    # Roofline of the dominant kernel.  The library's event profiler records
+    # a pair of HIP events around every kernel on its stream; those events
+    # drain the stream between kernels (8 % of the step at 10M vertices,
+    # more on small games), so the timed steps above run without it and the
+    # kernel table comes from profiled steps of the same job right after.
     roof = None
     kernels = {}
+    prof_steps = 0
     if not args.no_profile:
+        prof_steps = max(1, min(args.steps, 2))
+        pruns = [step(True) for _ in range(prof_steps)]
         agg = {}
-        for r in runs:
+        for r in pruns:
             for k, d in r["prof"].items():
                 a = agg.setdefault(k, {"ms": 0.0, "calls": 0, "bytes": 0.0})
                 a["ms"] += d["ms"]
@@ -354,7 +368,9 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "avg_launch_us": round(1e3 * a["ms"] / a["calls"], 2),
                 "bytes_per_launch": round(a["bytes"] / a["calls"]),
-                "traffic": counter_traffic(args.workload, dom)}
+                "traffic": counter_traffic(args.workload, dom),
+                "measured_over": f"{prof_steps} profiled steps of the same "
+                                 "job after the timed steps"}
 
     line = {
         "metric": "edges/s per best-response iteration",
@@ -379,6 +395,7 @@ def main():
         "load_seconds_median": statistics.median(load_s),
         "n_major": runs[0]["stats"]["n_major"],
         "n_valuations": nval,
+        "best_response": args.best_response,
         "ms_per_iteration": 1e3 * statistics.median(solve_s) / nval,
         "w_even": int((win == 0).sum()),
         "event_ms_total": ev0.elapsed_time(ev1),
