@@ -67,7 +67,8 @@ enum {
     PG_NO_PREPROCESS = 2u,  /* pg_load_csr: do not insert dummy vertices     */
     PG_OFFSETS_I32 = 4u,    /* pg_load_csr: offsets are int32, not int64     */
     PG_CAREFUL_WALKS = 8u,  /* pg_load_csr: host-driven walk rounds (below)  */
-    PG_COUNT_VALUATION = 16u /* pg_load_csr: count valuations (below)        */
+    PG_COUNT_VALUATION = 16u,/* pg_load_csr: count valuations (below)        */
+    PG_NO_GRAPH = 32u       /* pg_load_csr: launch every kernel one by one   */
 };
 
 /*
@@ -82,7 +83,7 @@ enum {
  *   owner     n bytes: 0 = Even, 1 = Odd
  *   priority  n int32 priorities, >= 0 (they may repeat; see below)
  *   flags     PG_PTR_DEVICE, PG_NO_PREPROCESS, PG_OFFSETS_I32,
- *             PG_CAREFUL_WALKS, PG_COUNT_VALUATION
+ *             PG_CAREFUL_WALKS, PG_COUNT_VALUATION, PG_NO_GRAPH
  *
  * Two representations of valuations (section 3, "Valuations").  With
  * pairwise distinct priorities a finite valuation is the set of priorities
@@ -111,6 +112,12 @@ enum {
  * followed by a read-back of the count of open walks) when those leave work.
  * PG_CAREFUL_WALKS makes every valuation of this game take the host-driven
  * rounds directly: slower, same results; it exists to test that path.
+ *
+ * A best-response iteration (walks, valuation, All_Odd) of pg_solve and
+ * pg_best_response is captured once per game as a HIP graph (on a stream of
+ * the library's own) and replayed on the caller's stream; the event
+ * profiler and the host-driven fallback launch kernels one by one.
+ * PG_NO_GRAPH launches every kernel one by one: same results.
  *
  * The inputs may be freed when the call returns.  Errors: PG_EINVAL for a
  * malformed game (bad offsets, a terminal vertex, a target out of range, an

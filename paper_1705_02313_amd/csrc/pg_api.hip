@@ -370,6 +370,9 @@ void free_game(pg_game *g) {
     if (g->vbase[k]) (void)hipFree(g->vbase[k]);
   }
   if (g->hctr) (void)hipHostFree(g->hctr);
+  for (hipGraphExec_t &ex : g->iter_exec)
+    if (ex) (void)hipGraphExecDestroy(ex);
+  if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
   g->prof.release();
   delete g;
 }
@@ -768,6 +771,7 @@ pg_status pg_load_csr(int64_t n, int64_t m, const void *offsets,
   if (st == PG_OK) st = finalize_state(g, s, true, !g->dense);
   if (st == PG_OK && g->dense) st = count_setup(g, s);
   g->careful = flags & PG_CAREFUL_WALKS;
+  g->use_graph = !(flags & PG_NO_GRAPH);
   if (st != PG_OK) {
     (void)hipStreamSynchronize(s);
     free_game(g);

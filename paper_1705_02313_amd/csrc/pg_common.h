@@ -133,6 +133,11 @@ struct pg_game {
   int64_t n_odd = 0, m_odd = 0;  // Odd vertices and the edges of their rows
   int sort_bits = 0;             // bits of a parent id key (ids 0..n_aug+1)
   bool careful = false;          // PG_CAREFUL_WALKS: host-driven walk rounds
+  // one best-response iteration (walks, valuation, All_Odd) captured as a
+  // HIP graph per ng/cand pair and replayed (unless PG_NO_GRAPH)
+  bool use_graph = false;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t iter_exec[2] = {nullptr, nullptr};
 
   // modified game, device resident
   int64_t *off = nullptr;   // [n_aug+1]

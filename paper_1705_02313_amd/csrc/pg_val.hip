@@ -793,16 +793,54 @@ static pg_status check_ctr(pg_game *g) {
 
 // One valuation (and, with odd_switch, the All_Odd step after it) with one
 // host synchronisation on the common path.
+// Captures one best-response iteration (fixed sizes and buffers: every size
+// a kernel needs is read on the device) on a private stream, as a graph for
+// the current ng/cand pair.
+static pg_status capture_iteration(pg_game *g, hipGraphExec_t *ex) {
+  if (!g->cap_stream)
+    PG_HIP(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
+  hipStream_t cs = g->cap_stream;
+  PG_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  enqueue_walks(g, cs);
+  enqueue_values(g, cs);
+  fill_i32(g->ctr + C_SWITCH, 0, 1, cs, &g->prof);
+  enqueue_any_switch(g, true, cs);
+  hipGraph_t gr = nullptr;
+  hipError_t e = hipStreamEndCapture(cs, &gr);
+  if (e == hipSuccess) e = hipGraphInstantiate(ex, gr, nullptr, nullptr, 0);
+  if (gr) (void)hipGraphDestroy(gr);
+  if (e != hipSuccess) {
+    *ex = nullptr;
+    return pg_fail(PG_EDEVICE, std::string("graph capture: ") +
+                                   hipGetErrorString(e));
+  }
+  return PG_OK;
+}
+
 static pg_status run_valuation(pg_game *g, hipStream_t s, bool odd_switch,
                                int32_t *count, int64_t *n_finite) {
   g->nlevels = g->dense ? count_levels(g->n_aug, g->dw)
                         : plan_levels(g->n_aug);
-  if (g->careful) PG_TRY(careful_walks(g, s));
-  else enqueue_walks(g, s);
-  enqueue_values(g, s);
-  if (odd_switch) {
-    fill_i32(g->ctr + C_SWITCH, 0, 1, s, &g->prof);
-    enqueue_any_switch(g, true, s);
+  bool replayed = false;
+  if (odd_switch && g->use_graph && !g->careful && !g->prof.on) {
+    hipGraphExec_t &ex = g->iter_exec[g->par];
+    if (!ex && capture_iteration(g, &ex) != PG_OK) {
+      g->use_graph = false;  // capture refused: stay eager from now on
+      (void)hipGetLastError();
+    }
+    if (ex) {
+      PG_HIP(hipGraphLaunch(ex, s));
+      replayed = true;
+    }
+  }
+  if (!replayed) {
+    if (g->careful) PG_TRY(careful_walks(g, s));
+    else enqueue_walks(g, s);
+    enqueue_values(g, s);
+    if (odd_switch) {
+      fill_i32(g->ctr + C_SWITCH, 0, 1, s, &g->prof);
+      enqueue_any_switch(g, true, s);
+    }
   }
   pg_status st = read_ctr(g, s);
   if (st != PG_OK) return st;

@@ -21,7 +21,7 @@ PG_EITERLIMIT, PG_EINADMISSIBLE, PG_EINTERNAL = 4, 5, 6
 PG_SINK = -1
 PG_KEY_TOP = 2**31 - 1
 PG_PTR_DEVICE, PG_NO_PREPROCESS, PG_OFFSETS_I32 = 1, 2, 4
-PG_CAREFUL_WALKS, PG_COUNT_VALUATION = 8, 16
+PG_CAREFUL_WALKS, PG_COUNT_VALUATION, PG_NO_GRAPH = 8, 16, 32
 PG_BR_SI, PG_BR_SI_RESET, PG_BR_BELLMAN_FORD = 0, 1, 2
 
 STATUS_NAMES = {0: "PG_OK", 1: "PG_EINVAL", 2: "PG_ENOMEM", 3: "PG_EDEVICE",
@@ -146,12 +146,13 @@ def _stream(device: bool):
 class Game:
     """A game loaded on the device (modified by preprocessing unless
     ``preprocess=False``; ``careful_walks=True`` sets PG_CAREFUL_WALKS,
-    ``count_valuation=True`` PG_COUNT_VALUATION).  Games whose priorities
-    repeat use count valuations by themselves (``self.d > 0``)."""
+    ``count_valuation=True`` PG_COUNT_VALUATION, ``graph=False``
+    PG_NO_GRAPH).  Games whose priorities repeat use count valuations by
+    themselves (``self.d > 0``)."""
 
     def __init__(self, offsets, targets, owner, priority, n: int = None,
                  preprocess: bool = True, careful_walks: bool = False,
-                 count_valuation: bool = False):
+                 count_valuation: bool = False, graph: bool = True):
         device = _is_torch(targets)
         if device:
             import torch
@@ -178,7 +179,8 @@ class Game:
             (0 if preprocess else PG_NO_PREPROCESS) | \
             (PG_OFFSETS_I32 if off_i32 else 0) | \
             (PG_CAREFUL_WALKS if careful_walks else 0) | \
-            (PG_COUNT_VALUATION if count_valuation else 0)
+            (PG_COUNT_VALUATION if count_valuation else 0) | \
+            (0 if graph else PG_NO_GRAPH)
         h = ctypes.c_void_p()
         _check(lib().pg_load_csr(n, m, _ptr(offsets), _ptr(targets),
                                  _ptr(owner), _ptr(priority), flags,
@@ -196,10 +198,11 @@ class Game:
 
     @classmethod
     def from_dict(cls, g: dict, device: bool = False, preprocess: bool = True,
-                  careful_walks: bool = False, count_valuation: bool = False):
+                  careful_walks: bool = False, count_valuation: bool = False,
+                  graph: bool = True):
         kw = {"n": int(g["n"]), "preprocess": preprocess,
               "careful_walks": careful_walks,
-              "count_valuation": count_valuation}
+              "count_valuation": count_valuation, "graph": graph}
         if device:
             import torch
             t = {k: torch.from_numpy(np.ascontiguousarray(g[k])).cuda()
