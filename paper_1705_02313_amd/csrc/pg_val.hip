@@ -573,7 +573,12 @@ constexpr int kFullSteps = 8;     // plain-walk budget of the full passes
 constexpr int kWalkSteps = 64;    // shortcut-walk budget of one round
 constexpr int kFastRounds = 3;    // rounds enqueued without looking back
 constexpr int kMaxRounds = 64;    // rounds of the careful path before failing
-constexpr int kPerThread1 = 4;    // level-1 sublists per thread
+// level-1 sublists per thread: 4 when the list is long enough to fill the
+// chip with a quarter of the threads (measured best at 13M vertices), fewer
+// on smaller games, whose few long walks would otherwise run on few waves
+static int per_thread1(int64_t ns1) {
+  return ns1 >= 4 * (int64_t)131072 ? 4 : (ns1 >= 2 * (int64_t)131072 ? 2 : 1);
+}
 
 static pg_status read_ctr(pg_game *g, hipStream_t s) {
   PG_HIP(hipMemcpyAsync(g->hctr, g->ctr, sizeof(int32_t) * C_COUNT,
@@ -711,6 +716,7 @@ static void enqueue_rank(pg_game *g, hipStream_t s) {
   const int nl = g->nlevels;
   const int64_t Lmax = 2 * (int64_t)N + 2;
   const int64_t ns1 = level_size(Lmax, 1);
+  const int kPerThread1 = per_thread1(ns1);
   const int64_t thr1 = (ns1 + kPerThread1 - 1) / kPerThread1;
   // 8 B per list element (2 per finite vertex) and 8 B per splitter
   PG_LAUNCH_NF(pf, K_LR_SUM1, 16.5, k_lr_sum1, dim3(grid_for(thr1)),
