@@ -277,7 +277,6 @@ __global__ void k_count_odd_edges(const int64_t *off, const uint8_t *owner,
   }
 }
 
-// Theorem 1: W_Even is the set of vertices whose final valuation is top
 // SI-Reset: every Odd vertex back to the first entry of its row.
 __global__ void k_sp_reset_odd(const int64_t *off, const int32_t *tgt,
                                const uint8_t *owner, const int32_t *pri,
@@ -341,6 +340,68 @@ pg_status copy_out(void *dst, const void *src, size_t bytes, bool device,
   return PG_OK;
 }
 
+thread_local DevPool *tl_pool = nullptr;
+
+pg_status DevPool::alloc(void **p, size_t bytes, bool host) {
+  const size_t b = bucket(bytes);
+  auto &fl = host ? host_free[b] : dev_free[b];
+  if (!fl.empty()) {
+    *p = fl.back();
+    fl.pop_back();
+    return PG_OK;
+  }
+  hipError_t e = host ? hipHostMalloc(p, b, hipHostMallocDefault)
+                      : hipMalloc(p, b);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return pg_fail(PG_ENOMEM, std::string("pool allocation failed: ") +
+                                  hipGetErrorString(e));
+  }
+  (host ? host_size : dev_size)[*p] = b;
+  return PG_OK;
+}
+
+bool DevPool::release(void *p) {
+  auto it = dev_size.find(p);
+  if (it != dev_size.end()) {
+    dev_free[it->second].push_back(p);
+    return true;
+  }
+  it = host_size.find(p);
+  if (it != host_size.end()) {
+    host_free[it->second].push_back(p);
+    return true;
+  }
+  return false;
+}
+
+void DevPool::clear() {
+  for (auto &kv : dev_size) (void)hipFree(kv.first);
+  for (auto &kv : host_size) (void)hipHostFree(kv.first);
+  dev_size.clear();
+  host_size.clear();
+  dev_free.clear();
+  host_free.clear();
+}
+
+void dev_free(void *p) {
+  if (!p) return;
+  if (tl_pool && tl_pool->release(p)) return;
+  (void)hipFree(p);
+}
+
+void host_free(void *p) {
+  if (!p) return;
+  if (tl_pool && tl_pool->release(p)) return;
+  (void)hipHostFree(p);
+}
+
+pg_status host_alloc(void **p, size_t bytes) {
+  if (tl_pool) return tl_pool->alloc(p, bytes, true);
+  PG_HIP(hipHostMalloc(p, bytes, hipHostMallocDefault));
+  return PG_OK;
+}
+
 pg_status sync_ctr(pg_game *g, hipStream_t s) {
   PG_HIP(hipMemcpyAsync(g->hctr, g->ctr, sizeof(int32_t) * C_COUNT,
                         hipMemcpyDeviceToHost, s));
@@ -360,16 +421,15 @@ void free_game(pg_game *g) {
                   g->kids,     g->fh,       g->pos,      g->elem,
                   g->ctr,      g->u64tmp,   g->cvals,    g->pidx,
                   g->cnt,      g->elem4,    g->rs1,      g->cnt2};
-  for (void *p : ptrs)
-    if (p) (void)hipFree(p);
+  for (void *p : ptrs) dev_free(p);
   for (int k = 0; k < 8; ++k) {
-    if (g->lv[k].sum) (void)hipFree(g->lv[k].sum);
-    if (g->lv[k].next) (void)hipFree(g->lv[k].next);
-    if (g->lv[k].base) (void)hipFree(g->lv[k].base);
-    if (g->vsum[k]) (void)hipFree(g->vsum[k]);
-    if (g->vbase[k]) (void)hipFree(g->vbase[k]);
+    dev_free(g->lv[k].sum);
+    dev_free(g->lv[k].next);
+    dev_free(g->lv[k].base);
+    dev_free(g->vsum[k]);
+    dev_free(g->vbase[k]);
   }
-  if (g->hctr) (void)hipHostFree(g->hctr);
+  host_free(g->hctr);
   for (hipGraphExec_t &ex : g->iter_exec)
     if (ex) (void)hipGraphExecDestroy(ex);
   if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
@@ -454,8 +514,7 @@ pg_status load_modified(int64_t n, int64_t m, const void *offsets,
   const bool dev = flags & PG_PTR_DEVICE;
   g->n = n;
   g->m = m;
-  PG_HIP(hipHostMalloc((void **)&g->hctr, sizeof(int32_t) * C_COUNT,
-                       hipHostMallocDefault));
+  PG_TRY(host_alloc((void **)&g->hctr, sizeof(int32_t) * C_COUNT));
   PG_TRY(dev_alloc(&g->ctr, C_TOTAL));
   fill_i32(g->ctr, 0, C_TOTAL, s);
 
@@ -465,7 +524,7 @@ pg_status load_modified(int64_t n, int64_t m, const void *offsets,
   uint8_t *own_in = nullptr;
   struct Tmp {
     std::vector<void *> p;
-    ~Tmp() { for (void *x : p) if (x) (void)hipFree(x); }
+    ~Tmp() { for (void *x : p) dev_free(x); }
   } tmp;
   PG_TRY(dev_alloc(&off_in, n + 1));
   tmp.p.push_back(off_in);

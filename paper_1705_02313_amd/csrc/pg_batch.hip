@@ -19,6 +19,14 @@
 // the next rebuild.  Rebuilds happen when queued games fit (admission by the
 // arena's vertex and edge capacity, first come first served) or when finished
 // games hold a quarter of the arena.
+//
+// A rebuild sorts nothing: every game's signed-priority order (odd
+// priorities descending, then even ascending) is computed once at submission,
+// and since the games' priority ranges are disjoint and grow with the slot,
+// the arena's order is the games' odd parts in decreasing slot order followed
+// by their even parts in increasing slot order.  Games leaving the arena are
+// freed at the next rebuild, once the step that used them has finished, so a
+// rebuild never waits for the device.
 #include <chrono>
 #include <deque>
 #include <map>
@@ -36,9 +44,14 @@ struct GameDesc {
   int2 *saved;        // [n_aug] strategies in the game's own ids
   uint8_t *res_winner;
   int32_t *res_sigma, *res_tau;
+  const int32_t *rvperm;  // [n_aug] the game's vertices in signed order
+  const int32_t *rvrank;  // [n_aug] position of each vertex in that order
   int64_t vb, eb;     // first arena vertex / edge
+  int64_t odd_pos;    // arena position of the game's first odd-priority vertex
+  int64_t even_pos;   // arena position of its first even-priority vertex
   int32_t n_aug, n_orig;
   int64_t m_aug;
+  int32_t n_oddpri;   // vertices of odd priority
   int32_t poff;       // priority offset (even)
   int32_t init;       // 1: start from the initial strategies
 };
@@ -59,7 +72,7 @@ __global__ void k_arena_vertices(const GameDesc *__restrict__ d,
                                   const int64_t *__restrict__ vstart, int G,
                                   int32_t N, int64_t M, int64_t *off,
                                   uint8_t *owner, int32_t *pri, int32_t *gid,
-                                  int2 *sp) {
+                                  int32_t *rvpos, uint32_t *oddf, int2 *sp) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v == 0) off[N] = M;
   if (v >= N) return;
@@ -67,9 +80,14 @@ __global__ void k_arena_vertices(const GameDesc *__restrict__ d,
   const GameDesc &g = d[s];
   const int64_t lv = v - g.vb;
   off[v] = g.eb + g.off[lv];
-  owner[v] = g.owner[lv];
+  const uint8_t ow = g.owner[lv];
+  owner[v] = ow;
+  oddf[v] = ow == 1;
   pri[v] = g.pri[lv] + g.poff;
   gid[v] = s;
+  const int32_t r = g.rvrank[lv];
+  rvpos[v] = (int32_t)(r < g.n_oddpri ? g.odd_pos + r
+                                      : g.even_pos + (r - g.n_oddpri));
   int32_t x;
   if (g.init) {
     x = g.owner[lv] ? (int32_t)(g.vb + g.tgt[g.off[lv]]) : N;
@@ -78,6 +96,21 @@ __global__ void k_arena_vertices(const GameDesc *__restrict__ d,
     x = (l == g.n_aug) ? N : (int32_t)(g.vb + l);
   }
   sp[v].x = x;
+}
+
+// The arena's signed-priority order by position: odd positions come from the
+// games in decreasing slot order, even positions in increasing slot order
+// (pstart: the first position of each segment, in position order).
+__global__ void k_arena_perm(const GameDesc *__restrict__ d,
+                             const int64_t *__restrict__ pstart, int G,
+                             int32_t N, int32_t *perm) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int j = find_game(pstart, 2 * G, i);
+  const int s = j < G ? G - 1 - j : j - G;
+  const GameDesc &g = d[s];
+  const int64_t r = j < G ? i - g.odd_pos : g.n_oddpri + (i - g.even_pos);
+  perm[i] = (int32_t)(g.vb + g.rvperm[r]);
 }
 
 __global__ void k_arena_edges(const GameDesc *__restrict__ d,
@@ -128,6 +161,13 @@ __global__ void k_arena_export(const GameDesc *__restrict__ d,
   g.res_sigma[lv] = even ? lx : PG_SINK;
   g.res_tau[lv] = even ? PG_SINK : lx;
   if (lv < g.n_orig) g.res_winner[lv] = key[v] == PG_KEY_TOP ? 0 : 1;
+}
+
+// Odd vertices of a game (into the distributed counter C_DIST_NF)
+__global__ void k_count_owner_odd(const uint8_t *owner, int64_t n,
+                                  int32_t *ctr) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  count_block(&ctr[C_DIST_NF], v < n && owner[v] == 1);
 }
 
 // counts one per switching lane into cnt[game]; one atomic per wave when the
@@ -278,17 +318,22 @@ struct BGame {
   int2 *saved = nullptr;
   uint8_t *res_winner = nullptr;
   int32_t *res_sigma = nullptr, *res_tau = nullptr;
+  int32_t *rvperm = nullptr, *rvrank = nullptr;  // the game's signed order
+  int64_t n_oddpri = 0, n_odd = 0, m_odd = 0;
   pg_stats st{};
   bool in_arena = false;    // still occupies arena vertices
   bool polled = false;      // results handed out; free once out of the arena
 };
 
+// (call with the batch's pool set, see PoolScope)
 void free_bgame(BGame *b) {
   if (!b) return;
-  if (b->saved) (void)hipFree(b->saved);
-  if (b->res_winner) (void)hipFree(b->res_winner);
-  if (b->res_sigma) (void)hipFree(b->res_sigma);
-  if (b->res_tau) (void)hipFree(b->res_tau);
+  dev_free(b->saved);
+  dev_free(b->res_winner);
+  dev_free(b->res_sigma);
+  dev_free(b->res_tau);
+  dev_free(b->rvperm);
+  dev_free(b->rvrank);
   free_game(b->g);
   delete b;
 }
@@ -305,17 +350,22 @@ struct pg_batch {
   std::map<int64_t, BGame *> games;
   std::deque<BGame *> queue;
   std::vector<BGame *> built;      // games of the current arena, by slot
+  std::vector<BGame *> grave;      // left the arena; freed at the next rebuild
+  DevPool pool;                    // memory of the submitted games
   int64_t done_vertices = 0;       // arena vertices of finished games
   // per-slot device state
   GameDesc *d_desc = nullptr;
   int64_t *d_vstart = nullptr, *d_estart = nullptr;
+  int64_t *d_pstart = nullptr;     // [2 G] signed-order segment starts
   int32_t *d_gid = nullptr;
   uint8_t *d_run = nullptr, *d_pending = nullptr, *d_newly = nullptr;
   int32_t *d_cnt_odd = nullptr, *d_cnt_even = nullptr;
   int32_t *d_nval = nullptr, *d_nmaj = nullptr;
   int64_t *d_sw_odd = nullptr, *d_sw_even = nullptr;
   int32_t *d_i32 = nullptr;        // scratch
-  // host mirrors
+  // host mirrors and staging
+  std::vector<GameDesc> h_desc;
+  std::vector<int64_t> h_vstart, h_estart, h_pstart;
   std::vector<uint8_t> h_newly;
   std::vector<int32_t> h_nval, h_nmaj;
   std::vector<int64_t> h_sw_odd, h_sw_even;
@@ -340,6 +390,7 @@ pg_status batch_alloc(pg_batch *b) {
   PG_TRY(dev_alloc(&b->d_desc, G));
   PG_TRY(dev_alloc(&b->d_vstart, G));
   PG_TRY(dev_alloc(&b->d_estart, G));
+  PG_TRY(dev_alloc(&b->d_pstart, 2 * (int64_t)G));
   PG_TRY(dev_alloc(&b->d_gid, b->cap_v));
   PG_TRY(dev_alloc(&b->d_run, G));
   PG_TRY(dev_alloc(&b->d_pending, G));
@@ -361,9 +412,15 @@ pg_status batch_alloc(pg_batch *b) {
 
 void batch_release(pg_batch *b) {
   if (!b) return;
-  for (auto &kv : b->games) free_bgame(kv.second);
+  {
+    PoolScope ps(&b->pool);
+    for (auto &kv : b->games) free_bgame(kv.second);
+    for (BGame *g : b->grave) free_bgame(g);
+  }
+  b->pool.clear();
   free_game(b->arena);
-  void *ptrs[] = {b->d_desc,    b->d_vstart,  b->d_estart,  b->d_gid,
+  void *ptrs[] = {b->d_desc,    b->d_vstart,  b->d_estart,  b->d_pstart,
+                  b->d_gid,
                   b->d_run,     b->d_pending, b->d_newly,   b->d_cnt_odd,
                   b->d_cnt_even, b->d_nval,   b->d_nmaj,    b->d_sw_odd,
                   b->d_sw_even, b->d_i32};
@@ -373,17 +430,21 @@ void batch_release(pg_batch *b) {
 }
 
 // Copies the live games' strategies out of the arena, then lays out the
-// arena again with the live games plus queued games that fit.
+// arena again with the live games plus queued games that fit.  Nothing here
+// waits for the device: games that leave are freed at the next rebuild, after
+// the step that last used them has been synchronised.
 pg_status rebuild(pg_batch *b, bool *built_any) {
   hipStream_t s = b->stream;
   pg_game *a = b->arena;
+  {
+    PoolScope ps(&b->pool);
+    for (BGame *g : b->grave) free_bgame(g);
+  }
+  b->grave.clear();
   // save strategies of games still running
-  if (!b->built.empty() && a->n_aug > 0) {
+  if (!b->built.empty() && a->n_aug > 0)
     hipLaunchKernelGGL(k_arena_save, dim3(grid_for(a->n_aug)), dim3(kBlock), 0,
                        s, b->d_desc, b->d_gid, a->sp, (int32_t)a->n_aug);
-    // the copies must be done before games leaving the arena are freed
-    PG_HIP(hipStreamSynchronize(s));
-  }
   std::vector<BGame *> next;
   int64_t nv = 0, ne = 0;
   for (BGame *g : b->built)
@@ -395,7 +456,7 @@ pg_status rebuild(pg_batch *b, bool *built_any) {
       g->in_arena = false;
       if (g->polled) {
         b->games.erase(g->ticket);
-        free_bgame(g);
+        b->grave.push_back(g);
       }
     }
   while (!b->queue.empty()) {
@@ -409,15 +470,27 @@ pg_status rebuild(pg_batch *b, bool *built_any) {
     nv += g->g->n_aug;
     ne += g->g->m_aug;
   }
-  std::vector<GameDesc> desc(next.size());
-  std::vector<int64_t> vstart(next.size()), estart(next.size());
-  // iteration counters continue across rebuilds
-  std::vector<int32_t> nval(next.size()), nmaj(next.size());
-  std::vector<int64_t> swo(next.size()), swe(next.size());
-  int64_t vb = 0, eb = 0, poff = 0;
-  for (size_t i = 0; i < next.size(); ++i) {
+  const int G = (int)next.size();
+  // host staging that lives until the copies below have run (the next
+  // synchronisation of the stream happens at the end of the step)
+  b->h_desc.resize(G);
+  b->h_vstart.resize(G);
+  b->h_estart.resize(G);
+  b->h_pstart.resize(2 * (size_t)G);
+  b->h_nval.assign(G, 0);
+  b->h_nmaj.assign(G, 0);
+  b->h_sw_odd.assign(G, 0);
+  b->h_sw_even.assign(G, 0);
+  int64_t odd_total = 0, n_odd = 0, m_odd = 0;
+  for (BGame *g : next) {
+    odd_total += g->n_oddpri;
+    n_odd += g->n_odd;
+    m_odd += g->m_odd;
+  }
+  int64_t vb = 0, eb = 0, poff = 0, even_pos = odd_total;
+  for (int i = 0; i < G; ++i) {
     BGame *g = next[i];
-    GameDesc &d = desc[i];
+    GameDesc &d = b->h_desc[i];
     d.off = g->g->off;
     d.tgt = g->g->tgt;
     d.owner = g->g->owner;
@@ -426,64 +499,92 @@ pg_status rebuild(pg_batch *b, bool *built_any) {
     d.res_winner = g->res_winner;
     d.res_sigma = g->res_sigma;
     d.res_tau = g->res_tau;
+    d.rvperm = g->rvperm;
+    d.rvrank = g->rvrank;
     d.vb = vb;
     d.eb = eb;
     d.n_aug = (int32_t)g->g->n_aug;
     d.n_orig = (int32_t)g->g->n;
     d.m_aug = g->g->m_aug;
+    d.n_oddpri = (int32_t)g->n_oddpri;
     d.poff = (int32_t)poff;
     d.init = g->started ? 0 : 1;
-    vstart[i] = vb;
-    estart[i] = eb;
-    nval[i] = (int32_t)g->st.n_valuations;
-    nmaj[i] = (int32_t)g->st.n_major;
-    swo[i] = g->st.n_odd_switches;
-    swe[i] = g->st.n_even_switches;
+    d.even_pos = even_pos;
+    even_pos += g->g->n_aug - g->n_oddpri;
+    b->h_vstart[i] = vb;
+    b->h_estart[i] = eb;
+    b->h_nval[i] = (int32_t)g->st.n_valuations;
+    b->h_nmaj[i] = (int32_t)g->st.n_major;
+    b->h_sw_odd[i] = g->st.n_odd_switches;
+    b->h_sw_even[i] = g->st.n_even_switches;
     vb += g->g->n_aug;
     eb += g->g->m_aug;
     poff += (int64_t)g->maxpri + 1;
     poff += poff & 1;
     if (poff > 2000000000LL)
       return pg_fail(PG_ENOMEM, "batch: priority space of the arena exhausted");
-    g->slot = (int)i;
+    g->slot = i;
     g->started = true;
     g->in_arena = true;
   }
+  // odd-priority parts in decreasing slot order (higher slots hold the
+  // larger priorities, which come first), then the even parts
+  int64_t odd_pos = 0;
+  for (int i = G - 1; i >= 0; --i) {
+    b->h_desc[i].odd_pos = odd_pos;
+    b->h_pstart[G - 1 - i] = odd_pos;
+    odd_pos += next[i]->n_oddpri;
+  }
+  for (int i = 0; i < G; ++i) b->h_pstart[G + i] = b->h_desc[i].even_pos;
   b->built = next;
   b->done_vertices = 0;
-  *built_any = !next.empty();
-  const int G = (int)next.size();
+  *built_any = G > 0;
   a->n = a->n_aug = vb;
   a->m = a->m_aug = eb;
   if (G == 0) return PG_OK;
-  PG_HIP(hipMemcpyAsync(b->d_desc, desc.data(), sizeof(GameDesc) * G,
+  PG_HIP(hipMemcpyAsync(b->d_desc, b->h_desc.data(), sizeof(GameDesc) * G,
                         hipMemcpyHostToDevice, s));
-  PG_HIP(hipMemcpyAsync(b->d_vstart, vstart.data(), sizeof(int64_t) * G,
+  PG_HIP(hipMemcpyAsync(b->d_vstart, b->h_vstart.data(), sizeof(int64_t) * G,
                         hipMemcpyHostToDevice, s));
-  PG_HIP(hipMemcpyAsync(b->d_estart, estart.data(), sizeof(int64_t) * G,
+  PG_HIP(hipMemcpyAsync(b->d_estart, b->h_estart.data(), sizeof(int64_t) * G,
                         hipMemcpyHostToDevice, s));
+  PG_HIP(hipMemcpyAsync(b->d_pstart, b->h_pstart.data(),
+                        sizeof(int64_t) * 2 * G, hipMemcpyHostToDevice, s));
   const int32_t N = (int32_t)vb;
+  uint32_t *oddf = a->sk0, *oscan = a->sk1;
   hipLaunchKernelGGL(k_arena_vertices, dim3(grid_for(N)), dim3(kBlock), 0, s,
                      b->d_desc, b->d_vstart, G, N, eb, a->off, a->owner, a->pri,
-                     b->d_gid, a->sp);
+                     b->d_gid, a->rvpos, oddf, a->sp);
   hipLaunchKernelGGL(k_arena_edges, dim3(grid_for(eb)), dim3(kBlock), 0, s,
                      b->d_desc, b->d_estart, G, eb, a->tgt);
   hipLaunchKernelGGL(k_arena_sp_pri, dim3(grid_for(N)), dim3(kBlock), 0, s,
                      a->pri, a->sp, N);
+  hipLaunchKernelGGL(k_arena_perm, dim3(grid_for(N)), dim3(kBlock), 0, s,
+                     b->d_desc, b->d_pstart, G, N, a->perm);
+  // the two players' vertex lists (their sizes are known on the host)
+  scan_excl_u32(oddf, oscan, N, a->scan_tmp, s);
+  hipLaunchKernelGGL(k_split_players, dim3(grid_for(N)), dim3(kBlock), 0, s,
+                     a->owner, oscan, a->odd_ids, a->even_ids, N);
+  int bits = 1;
+  while ((int64_t(1) << bits) <= (int64_t)N + 1) ++bits;
+  a->sort_bits = bits;
+  a->n_oddpri = (int32_t)odd_total;
+  a->n_odd = n_odd;
+  a->m_odd = m_odd;
+  fill_i32(a->ctr, 0, C_TOTAL, s);
   fill_u8(b->d_run, 1, G, s);
   fill_u8(b->d_pending, 0, G, s);
   fill_u8(b->d_newly, 0, G, s);
   fill_i32(b->d_cnt_odd, 0, G, s);
   fill_i32(b->d_cnt_even, 0, G, s);
-  PG_HIP(hipMemcpyAsync(b->d_nval, nval.data(), 4 * (size_t)G,
+  PG_HIP(hipMemcpyAsync(b->d_nval, b->h_nval.data(), 4 * (size_t)G,
                         hipMemcpyHostToDevice, s));
-  PG_HIP(hipMemcpyAsync(b->d_nmaj, nmaj.data(), 4 * (size_t)G,
+  PG_HIP(hipMemcpyAsync(b->d_nmaj, b->h_nmaj.data(), 4 * (size_t)G,
                         hipMemcpyHostToDevice, s));
-  PG_HIP(hipMemcpyAsync(b->d_sw_odd, swo.data(), 8 * (size_t)G,
+  PG_HIP(hipMemcpyAsync(b->d_sw_odd, b->h_sw_odd.data(), 8 * (size_t)G,
                         hipMemcpyHostToDevice, s));
-  PG_HIP(hipMemcpyAsync(b->d_sw_even, swe.data(), 8 * (size_t)G,
+  PG_HIP(hipMemcpyAsync(b->d_sw_even, b->h_sw_even.data(), 8 * (size_t)G,
                         hipMemcpyHostToDevice, s));
-  PG_TRY(finalize_state(a, s, false));
   valuation_reset(a, s);
   return PG_OK;
 }
@@ -526,6 +627,7 @@ pg_status pg_batch_submit(pg_batch *b, int64_t n, int64_t m,
   if (!b || !ticket) return pg_fail(PG_EINVAL, "NULL argument");
   if (n < 1 || m < n) return pg_fail(PG_EINVAL, "need n >= 1 and m >= n");
   hipStream_t s = b->stream;
+  PoolScope ps(&b->pool);   // the game's memory comes from the batch's pool
   BGame *bg = new (std::nothrow) BGame();
   if (!bg) return pg_fail(PG_ENOMEM, "host allocation failed");
   bg->g = new (std::nothrow) pg_game();
@@ -542,34 +644,47 @@ pg_status pg_batch_submit(pg_batch *b, int64_t n, int64_t m,
   if (st == PG_OK) st = dev_alloc(&bg->res_winner, n);
   if (st == PG_OK) st = dev_alloc(&bg->res_sigma, bg->g->n_aug);
   if (st == PG_OK) st = dev_alloc(&bg->res_tau, bg->g->n_aug);
+  if (st == PG_OK) st = dev_alloc(&bg->rvperm, bg->g->n_aug);
+  if (st == PG_OK) st = dev_alloc(&bg->rvrank, bg->g->n_aug);
   if (st == PG_OK) {
-    // largest priority of the modified game (for the arena offsets)
-    fill_i32(b->d_i32, -1, 1, s);
-    hipLaunchKernelGGL(k_max_i32, dim3(256), dim3(kBlock), 0, s, bg->g->pri,
-                       bg->g->n_aug, b->d_i32);
-    int32_t mx = 0;
-    hipError_t e = hipMemcpyAsync(&mx, b->d_i32, 4, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) st = pg_fail(PG_EDEVICE, hipGetErrorString(e));
-    bg->maxpri = mx;
-  }
-  if (st == PG_OK) {
-    // distinct priorities: sort them in the arena's sort buffers (calls on
-    // one batch do not overlap, so no step is using them now)
+    // the largest priority (for the arena offsets), the game's own
+    // signed-priority order (sorted in the arena's sort buffers: calls on
+    // one batch do not overlap, so no step is using them now; a repeated
+    // priority is an error), and its Odd vertex and edge counts
     pg_game *a = b->arena;
-    const int64_t N = bg->g->n_aug;
+    pg_game *gg = bg->g;
+    const int64_t N = gg->n_aug;
+    fill_i32(gg->ctr, 0, C_TOTAL, s);
+    fill_i32(b->d_i32, -1, 1, s);
+    hipLaunchKernelGGL(k_max_i32, dim3(256), dim3(kBlock), 0, s, gg->pri, N,
+                       b->d_i32);
     hipLaunchKernelGGL(k_rv_keys, dim3(grid_for(N)), dim3(kBlock), 0, s,
-                       bg->g->pri, a->sk0, a->sv0, N);
+                       gg->pri, a->sk0, a->sv0, N);
     const int w = radix_sort(a->sk0, a->sv0, a->sk1, a->sv1, N, 32,
                              a->tile_cnt, a->scan_tmp, s);
-    fill_i32(b->d_i32, 0, 1, s);
-    hipLaunchKernelGGL(k_dup_check, dim3(grid_for(N)), dim3(kBlock), 0, s,
-                       w ? a->sk1 : a->sk0, N, b->d_i32);
-    int32_t dup = 0;
-    hipError_t e = hipMemcpyAsync(&dup, b->d_i32, 4, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    hipLaunchKernelGGL(k_rv_finish, dim3(grid_for(N)), dim3(kBlock), 0, s,
+                       w ? a->sk1 : a->sk0, w ? a->sv1 : a->sv0, bg->rvperm,
+                       bg->rvrank, N, 1, gg->ctr);
+    sum_dist(gg->ctr, C_DIST_MISC, C_MISC, s);
+    hipLaunchKernelGGL(k_count_owner_odd, dim3(grid_for(N)), dim3(kBlock), 0,
+                       s, gg->owner, N, gg->ctr);
+    sum_dist(gg->ctr, C_DIST_NF, C_NFIN, s);
+    fill_i32((int32_t *)a->u64tmp, 0, 2, s);
+    hipLaunchKernelGGL(k_count_odd_edges, dim3(256), dim3(kBlock), 0, s,
+                       gg->off, gg->owner, N, a->u64tmp);
+    int32_t mx = 0;
+    unsigned long long me = 0;
+    hipError_t e = hipMemcpyAsync(&mx, b->d_i32, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(&me, a->u64tmp, sizeof(me), hipMemcpyDeviceToHost, s);
     if (e != hipSuccess) st = pg_fail(PG_EDEVICE, hipGetErrorString(e));
-    else if (dup) st = pg_fail(PG_EINVAL, "priorities must be pairwise distinct");
+    if (st == PG_OK) st = sync_ctr(gg, s);
+    if (st == PG_OK && (gg->hctr[C_ERR] & ERR_DUPPRI))
+      st = pg_fail(PG_EINVAL, "priorities must be pairwise distinct");
+    bg->maxpri = mx;
+    bg->n_oddpri = gg->hctr[C_MISC];
+    bg->n_odd = gg->hctr[C_NFIN];
+    bg->m_odd = (int64_t)me;
   }
   if (st != PG_OK) {
     (void)hipStreamSynchronize(s);
@@ -694,6 +809,7 @@ pg_status pg_batch_poll(pg_batch *b, int64_t ticket, int32_t *done,
   g->polled = true;
   if (!g->in_arena) {
     b->games.erase(it);
+    PoolScope ps(&b->pool);
     free_bgame(g);
   }  // else: still laid out in the arena; released at the next rebuild
   return PG_OK;

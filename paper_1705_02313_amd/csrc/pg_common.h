@@ -4,7 +4,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/pg.h"
@@ -329,13 +331,56 @@ pg_status export_counts(pg_game *g, int32_t *counts, uint8_t *top, bool dev,
                         hipStream_t s);
 }  // namespace pgk
 
+// ---- device memory ---------------------------------------------------------
+namespace pgk {
+// Size-bucketed memory for the many small games of a batch: blocks (device,
+// and pinned host for the counter mirrors) go back to free lists by
+// power-of-two size instead of to hipFree, which waits for the device, and
+// come back from them instead of from hipMalloc.  Everything is released by
+// clear() when the batch is freed.
+struct DevPool {
+  std::map<size_t, std::vector<void *>> dev_free, host_free;
+  std::unordered_map<void *, size_t> dev_size, host_size;
+  static size_t bucket(size_t bytes) {
+    size_t b = 256;
+    while (b < bytes) b <<= 1;
+    return b;
+  }
+  pg_status alloc(void **p, size_t bytes, bool host);
+  bool release(void *p);   // false: not a block of this pool
+  void clear();
+};
+// allocations of the calling thread go to this pool while it is set
+extern thread_local DevPool *tl_pool;
+struct PoolScope {
+  DevPool *prev;
+  explicit PoolScope(DevPool *p) : prev(tl_pool) { tl_pool = p; }
+  ~PoolScope() { tl_pool = prev; }
+};
+void dev_free(void *p);            // to the current pool, else hipFree
+void host_free(void *p);           // to the current pool, else hipHostFree
+pg_status host_alloc(void **p, size_t bytes);
+}  // namespace pgk
+
 // ---- loading helpers shared by single games and batches (pg_api.hip) ------
 namespace pgk {
 __global__ void k_rv_keys(const int32_t *pri, uint32_t *sk, uint32_t *sv,
                           int64_t n);
+// perm/rvpos from the sorted signed keys; odd-priority count into
+// C_DIST_MISC; ERR_DUPPRI on a repeat when check_dup
+__global__ void k_rv_finish(const uint32_t *skS, const uint32_t *svS,
+                            int32_t *perm, int32_t *rvpos, int64_t n,
+                            int check_dup, int32_t *ctr);
+__global__ void k_odd_flags(const uint8_t *owner, uint32_t *f, int64_t n);
+__global__ void k_split_players(const uint8_t *owner, const uint32_t *oscan,
+                                int32_t *odd_ids, int32_t *even_ids,
+                                int64_t n);
+__global__ void k_count_odd_edges(const int64_t *off, const uint8_t *owner,
+                                  int64_t n, unsigned long long *out);
 template <typename T>
 pg_status dev_alloc(T **p, int64_t count) {
   size_t bytes = sizeof(T) * (size_t)(count > 0 ? count : 1);
+  if (tl_pool) return tl_pool->alloc((void **)p, bytes, false);
   hipError_t e = hipMalloc((void **)p, bytes);
   if (e != hipSuccess) {
     *p = nullptr;
