@@ -49,10 +49,10 @@ enum ErrBit : int {
 
 // Kernel kinds for the optional event profiler (pg_profile_* in pg.h).
 enum KId : int {
-  K_FILL = 0, K_NG_WALK, K_NG_ROUND, K_ROOT_WALK, K_ROOT_ROUND, K_SORT_KEYS,
-  K_RS_UPSWEEP, K_RS_SCAN, K_RS_DOWNSWEEP, K_LINK_INFO, K_LINK_BUILD,
+  K_FILL = 0, K_NG_WALK, K_NG_ROUND, K_ROOT_WALK, K_ROOT_ROUND,
+  K_SORT_HIST, K_SCAN, K_SORT_PASS, K_LINK_INFO, K_LINK_BUILD,
   K_LR_SUM1, K_LR_SUMK, K_LR_TOP, K_LR_DISTK, K_LR_EMIT1, K_ODD_SWITCH,
-  K_EVEN_SWITCH, K_PREP, K_OTHER, K_COUNT
+  K_EVEN_SWITCH, K_OTHER, K_COUNT
 };
 extern const char *const kKernelNames[K_COUNT];
 

@@ -7,11 +7,10 @@
 namespace pgk {
 
 const char *const kKernelNames[K_COUNT] = {
-    "fill",        "ng_walk",     "ng_round",      "root_walk",
-    "root_round",  "sort_keys",   "radix_upsweep", "radix_scan",
-    "radix_downsweep", "link_info", "link_build",  "lr_sum1",
-    "lr_sumk",     "lr_top",      "lr_distk",      "lr_emit1",
-    "odd_switch",  "even_switch", "preprocess",    "other"};
+    "fill",       "ng_walk",   "ng_round",   "root_walk",  "root_round",
+    "sort_hist",  "scan",      "sort_pass",  "link_info",  "link_build",
+    "lr_sum1",    "lr_sumk",   "lr_top",     "lr_distk",   "lr_emit1",
+    "odd_switch", "even_switch", "other"};
 
 hipEvent_t Prof::get() {
   if (!pool.empty()) {
@@ -198,15 +197,15 @@ static void scan_rec(const T *in, T *out, int64_t n, T *tmp, hipStream_t s,
                      Prof *prof, const int32_t *gate) {
   if (n <= 0) return;
   if (n <= kScanTile) {
-    PG_LAUNCH(prof, K_RS_SCAN, 2.0 * sizeof(T) * n, k_scan_down<T>, dim3(1),
+    PG_LAUNCH(prof, K_SCAN, 2.0 * sizeof(T) * n, k_scan_down<T>, dim3(1),
               dim3(kBlock), 0, s, in, out, (const T *)nullptr, n, gate);
     return;
   }
   int64_t t = (n + kScanTile - 1) / kScanTile;
-  PG_LAUNCH(prof, K_RS_SCAN, 1.0 * sizeof(T) * n, k_scan_reduce<T>,
+  PG_LAUNCH(prof, K_SCAN, 1.0 * sizeof(T) * n, k_scan_reduce<T>,
             dim3((unsigned)t), dim3(kBlock), 0, s, in, tmp, n, gate);
   scan_rec<T>(tmp, tmp, t, tmp + t, s, prof, gate);
-  PG_LAUNCH(prof, K_RS_SCAN, 2.0 * sizeof(T) * n, k_scan_down<T>,
+  PG_LAUNCH(prof, K_SCAN, 2.0 * sizeof(T) * n, k_scan_down<T>,
             dim3((unsigned)t), dim3(kBlock), 0, s, in, out, (const T *)tmp, n,
             gate);
 }
@@ -325,11 +324,11 @@ int radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
     uint32_t *ko = cur ? k0 : k1, *vo = cur ? v0 : v1;
     // algorithmic bytes: keys read (4 B) and 1 KiB of counts per tile;
     // then keys and values read and written (16 B)
-    PG_LAUNCH(prof, K_RS_UPSWEEP, 4.0 * n + 1024.0 * tiles, k_rs_upsweep,
+    PG_LAUNCH(prof, K_SORT_HIST, 4.0 * n + 1024.0 * tiles, k_rs_upsweep,
               dim3((unsigned)tiles), dim3(kBlock), 0, s, ki, n, shift,
               tile_cnt, tiles, gate);
     scan_excl_u32(tile_cnt, tile_cnt, 256 * tiles, scan_tmp, s, prof, gate);
-    PG_LAUNCH(prof, K_RS_DOWNSWEEP, 16.0 * n + 1024.0 * tiles, k_rs_downsweep,
+    PG_LAUNCH(prof, K_SORT_PASS, 16.0 * n + 1024.0 * tiles, k_rs_downsweep,
               dim3((unsigned)tiles), dim3(kBlock), 0, s, ki, vi, ko, vo, n,
               shift, tile_cnt, tiles, gate);
     cur ^= 1;
@@ -569,9 +568,9 @@ int radix_sort_1s(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
   fill_i32((int32_t *)ctr, 0, 4 + k1sHistWords, s, prof);
   fill_i32((int32_t *)status, 0, (int64_t)passes * tiles * 256, s, prof);
   // keys read once for all digits
-  PG_LAUNCH(prof, K_RS_UPSWEEP, 4.0 * n, k_1s_hist, dim3((unsigned)tiles),
+  PG_LAUNCH(prof, K_SORT_HIST, 4.0 * n, k_1s_hist, dim3((unsigned)tiles),
             dim3(kBlock), 0, s, k0, n, passes, glob, gate);
-  PG_LAUNCH(prof, K_RS_SCAN, 0.0, k_1s_base, dim3(1), dim3(kBlock), 0, s,
+  PG_LAUNCH(prof, K_SCAN, 0.0, k_1s_base, dim3(1), dim3(kBlock), 0, s,
             glob, passes, base, gate);
   int cur = 0;
   for (int p = 0; p < passes; ++p) {
@@ -580,7 +579,7 @@ int radix_sort_1s(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
         cur ? v1 : ((index_values && p == 0) ? nullptr : v0);
     uint32_t *ko = cur ? k0 : k1, *vo = cur ? v0 : v1;
     // keys and values read and written (16 B), 1 KiB of status per tile
-    PG_LAUNCH(prof, K_RS_DOWNSWEEP, 16.0 * n + 1024.0 * tiles, k_1s_pass,
+    PG_LAUNCH(prof, K_SORT_PASS, 16.0 * n + 1024.0 * tiles, k_1s_pass,
               dim3((unsigned)tiles), dim3(kBlock), 0, s, ki, vi, ko, vo, n,
               8 * p, base + p * 256, status + (int64_t)p * tiles * 256,
               ctr + p, err, gate);

@@ -568,7 +568,7 @@ __global__ __launch_bounds__(kBlock) void k_even_switch(
 namespace pgk {
 
 // A wave lasts as long as its longest walk, so the full passes stop early and
-// leave long walks to compact worklist rounds (which also take shortcuts).
+// leave long walks to dense rounds (which also take shortcuts).
 constexpr int kFullSteps = 8;     // plain-walk budget of the full passes
 constexpr int kWalkSteps = 64;    // shortcut-walk budget of one round
 constexpr int kFastRounds = 3;    // rounds enqueued without looking back
