@@ -25,9 +25,11 @@
  *  - Calls on one game must not overlap; different games are independent.
  *
  * Game model (section 2, "Parity games"): vertices 0..n-1, each owned by Even
- * (0) or Odd (1), each with a priority and at least one outgoing edge.  The
- * library needs pairwise distinct priorities: it represents a valuation by
- * its rank, which is exact only when no priority repeats.
+ * (0) or Odd (1), each with a priority and at least one outgoing edge.  With
+ * pairwise distinct priorities the library represents a valuation by its
+ * rank (rank valuations); when priorities repeat it keeps the paper's count
+ * vectors (count valuations, at most 32 distinct priorities; see
+ * pg_load_csr).
  *
  * The modified game (section 3, "A modified game" and "The algorithm"): a
  * sink s gets an implicit edge from every Even vertex; preprocessing then
@@ -265,10 +267,10 @@ typedef struct pg_stats {
 /*
  * pg_solve -- Algorithm 1 from the initial strategies to the end.  The outer
  * loop switches Even by greedy all-switches (section 3, "Switching rules"):
- * among the sink (option 0) and the row, the first option of greatest key
- * replaces sigma(v) if its key is strictly greater.  It stops when no Even
- * vertex switches; by Theorem 1 the vertices of key PG_KEY_TOP are then
- * exactly Even's winning set.
+ * among the sink (option 0) and the row, the first option of greatest
+ * valuation replaces sigma(v) if its valuation is strictly greater.  It
+ * stops when no Even vertex switches; by Theorem 1 the vertices whose
+ * valuation is then top are exactly Even's winning set.
  *
  *   opts     nullable (no caps; host outputs; PG_BR_SI).  PG_EINVAL for
  *            PG_BR_BELLMAN_FORD on a game with rank valuations.
@@ -311,9 +313,13 @@ pg_status pg_profile_read(const pg_game *game, int32_t kind, const char **name,
  *                  games (the HBM footprint budget) and max_games games.
  * pg_batch_submit  validates and preprocesses one game (arguments as
  *                  pg_load_csr) and queues it; returns a ticket.  PG_ENOMEM
- *                  if the game alone exceeds the arena.  Queued games join
- *                  the arena, first come first served, at a step where they
- *                  fit beside the games already in it.
+ *                  if the game alone exceeds the arena; PG_EINVAL for
+ *                  repeated priorities (batches take games with rank
+ *                  valuations only: the arena ranks all its games together).
+ *                  Queued games join the arena, first come first served, at
+ *                  a step where they fit beside the games already in it.  A
+ *                  game's memory comes from a pool that the batch keeps
+ *                  until pg_batch_free.
  * pg_batch_step    admits queued games that fit (and drops finished ones
  *                  when they hold a quarter of the arena), then advances
  *                  every live game once.  Outputs (nullable): games running,
