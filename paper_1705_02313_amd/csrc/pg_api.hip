@@ -191,6 +191,39 @@ __global__ void k_rv_finish(const uint32_t *skS, const uint32_t *svS,
   count_block(&ctr[C_DIST_MISC], odd);
 }
 
+// Relabelling: vertex i of the new game is vertex from[i] of the old one,
+// and a target t of the old game becomes to[t].  Rows keep their edge order
+// (so the first entry of a row stays the first).  k_relabel_vertices writes
+// the new row lengths into off2 (scanned afterwards; off2[n] = 0 before the
+// scan), the owners and the priorities; k_relabel_rows copies the rows.
+// With from = perm, to = rvpos a game goes into signed order; with from =
+// rvpos, to = perm it comes back.
+__global__ void k_relabel_vertices(const int64_t *off, const uint8_t *owner,
+                                   const int32_t *pri, const int32_t *from,
+                                   int64_t *off2, uint8_t *owner2,
+                                   int32_t *pri2, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > n) return;
+  if (i == n) {
+    off2[n] = 0;
+    return;
+  }
+  const int32_t v = from[i];
+  off2[i] = off[v + 1] - off[v];
+  owner2[i] = owner[v];
+  pri2[i] = pri[v];
+}
+
+__global__ void k_relabel_rows(const int64_t *off, const int32_t *tgt,
+                               const int32_t *from, const int32_t *to,
+                               const int64_t *off2, int32_t *tgt2, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t v = from[i];
+  const int64_t e0 = off[v], len = off[v + 1] - e0, o = off2[i];
+  for (int64_t k = 0; k < len; ++k) tgt2[o + k] = to[tgt[e0 + k]];
+}
+
 // Odd vertices and Even vertices as two increasing lists (for the switch
 // kernels), from the exclusive scan `oscan` of the Odd flags.
 __global__ void k_split_players(const uint8_t *owner, const uint32_t *oscan,
@@ -223,39 +256,62 @@ __global__ void k_sp_init(const int64_t *off, const int32_t *tgt,
 
 
 
+// The strategy arrays at the C ABI use the caller's vertex ids; for a
+// relabeled game perm/rvpos translate them (both null otherwise).
 __global__ void k_sp_import(const uint8_t *owner, const int32_t *pri,
-                            const int32_t *sigma, const int32_t *tau, int2 *sp,
-                            int32_t N, int32_t *ctr) {
-  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= N) return;
-  const bool even = owner[v] == 0;
+                            const int32_t *sigma, const int32_t *tau,
+                            const int32_t *perm, const int32_t *rvpos,
+                            int2 *sp, int32_t N, int32_t *ctr) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int32_t v = perm ? perm[i] : (int32_t)i;
+  const bool even = owner[i] == 0;
   int32_t s = even ? sigma[v] : tau[v];
   if (even && s == PG_SINK) {
     s = N;
   } else if (s < 0 || s >= N) {
     atomicOr(&ctr[C_ERR], ERR_INVAL);
     s = N;
+  } else if (rvpos) {
+    s = rvpos[s];
   }
-  sp[v] = make_int2(s, s == N ? 2147483647 : pri[s]);
+  sp[i] = make_int2(s, s == N ? 2147483647 : pri[s]);
 }
 
 __global__ void k_sp_export(const uint8_t *owner, const int2 *sp,
+                            const int32_t *perm, const int32_t *rvpos,
                             int32_t *sigma, int32_t *tau, int32_t N) {
   int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= N) return;
-  const int32_t s = sp[v].x;
-  const bool even = owner[v] == 0;
+  const int32_t i = rvpos ? rvpos[v] : (int32_t)v;
+  int32_t s = sp[i].x;
+  if (perm && s != N) s = perm[s];
+  const bool even = owner[i] == 0;
   if (sigma) sigma[v] = even ? (s == N ? PG_SINK : s) : PG_SINK;
   if (tau) tau[v] = even ? PG_SINK : s;
 }
 
 __global__ void k_initial(const int64_t *off, const int32_t *tgt,
-                          const uint8_t *owner, int32_t *sigma, int32_t *tau,
+                          const uint8_t *owner, const int32_t *perm,
+                          const int32_t *rvpos, int32_t *sigma, int32_t *tau,
                           int32_t N) {
   int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= N) return;
+  const int32_t i = rvpos ? rvpos[v] : (int32_t)v;
   if (sigma) sigma[v] = PG_SINK;
-  if (tau) tau[v] = owner[v] ? tgt[off[v]] : PG_SINK;
+  if (tau) {
+    const int32_t t = owner[i] ? tgt[off[i]] : PG_SINK;
+    tau[v] = (perm && t != PG_SINK) ? perm[t] : t;
+  }
+}
+
+// Rank keys in the caller's ids: key2[v] = key[rvpos[v]]; the sink's key
+// (index N) stays where it is.
+__global__ void k_key_export(const int32_t *key, const int32_t *rvpos,
+                             int32_t *key2, int32_t N) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v > N) return;
+  key2[v] = key[v == N ? N : rvpos[v]];
 }
 
 // Edges of the Odd rows (for the switch kernels' byte counts): a grid-stride
@@ -289,9 +345,10 @@ __global__ void k_sp_reset_odd(const int64_t *off, const int32_t *tgt,
 
 // Theorem 1: Even wins exactly where the final valuation is top (the walks
 // of the last valuation marked those vertices with rs = 2).
-__global__ void k_winner(const uint8_t *rs, uint8_t *winner, int64_t n) {
+__global__ void k_winner(const uint8_t *rs, const int32_t *rvpos,
+                         uint8_t *winner, int64_t n) {
   int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < n) winner[v] = rs[v] == 2 ? 0 : 1;
+  if (v < n) winner[v] = rs[rvpos ? rvpos[v] : v] == 2 ? 0 : 1;
 }
 
 }  // namespace pgk
@@ -683,9 +740,39 @@ pg_status load_modified(int64_t n, int64_t m, const void *offsets,
   return PG_OK;
 }
 
+// Rebuilds a game of N vertices and M edges with vertex i taken from vertex
+// from[i] and targets mapped by `to` (see k_relabel_vertices).  The new
+// arrays are allocated; the old ones are left to the caller.
+static pg_status relabel_game(const int64_t *off, const int32_t *tgt,
+                              const uint8_t *owner, const int32_t *pri,
+                              const int32_t *from, const int32_t *to,
+                              int64_t N, int64_t M, int64_t **off2,
+                              int32_t **tgt2, uint8_t **owner2,
+                              int32_t **pri2, hipStream_t s) {
+  PG_TRY(dev_alloc(off2, N + 1));
+  PG_TRY(dev_alloc(tgt2, M));
+  PG_TRY(dev_alloc(owner2, N));
+  PG_TRY(dev_alloc(pri2, N));
+  struct Tmp {
+    uint8_t *p = nullptr;
+    ~Tmp() { dev_free(p); }
+  } stmp;
+  const size_t need = scan_excl_i64(nullptr, nullptr, N + 1, nullptr, s);
+  PG_TRY(dev_alloc(&stmp.p, (int64_t)need + 16));
+  hipLaunchKernelGGL(k_relabel_vertices, dim3(grid_for(N + 1)), dim3(kBlock),
+                     0, s, off, owner, pri, from, *off2, *owner2, *pri2, N);
+  scan_excl_i64(*off2, *off2, N + 1, stmp.p, s);
+  hipLaunchKernelGGL(k_relabel_rows, dim3(grid_for(N)), dim3(kBlock), 0, s,
+                     off, tgt, from, to, *off2, *tgt2, N);
+  PG_HIP(hipStreamSynchronize(s));
+  return PG_OK;
+}
+
 // The signed-priority order (and the distinctness check), the initial play
 // graph and the two players' vertex lists of the modified game in g->off,
-// g->tgt, g->owner, g->pri (state allocated by alloc_state).
+// g->tgt, g->owner, g->pri (state allocated by alloc_state).  A game with
+// distinct priorities (rank valuations) is then stored in signed order
+// (pg_game::relabeled).
 pg_status finalize_state(pg_game *g, hipStream_t s, bool init_sp,
                          bool distinct) {
   const int64_t N = g->n_aug;
@@ -701,11 +788,36 @@ pg_status finalize_state(pg_game *g, hipStream_t s, bool init_sp,
                      which ? g->sk1 : g->sk0, which ? g->sv1 : g->sv0, g->perm,
                      g->rvpos, N, (int)distinct, g->ctr);
   sum_dist(g->ctr, C_DIST_MISC, C_MISC, s);
+  PG_TRY(sync_ctr(g, s));
+  PG_TRY(check_err(g, "invalid game"));
+  if (distinct) {
+    int64_t *off2 = nullptr;
+    int32_t *tgt2 = nullptr, *pri2 = nullptr;
+    uint8_t *owner2 = nullptr;
+    pg_status st = relabel_game(g->off, g->tgt, g->owner, g->pri, g->perm,
+                                g->rvpos, N, g->m_aug, &off2, &tgt2, &owner2,
+                                &pri2, s);
+    if (st != PG_OK) {
+      (void)hipStreamSynchronize(s);
+      dev_free(off2);
+      dev_free(tgt2);
+      dev_free(owner2);
+      dev_free(pri2);
+      return st;
+    }
+    dev_free(g->off);
+    dev_free(g->tgt);
+    dev_free(g->owner);
+    dev_free(g->pri);
+    g->off = off2;
+    g->tgt = tgt2;
+    g->owner = owner2;
+    g->pri = pri2;
+    g->relabeled = true;
+  }
   if (init_sp)
     hipLaunchKernelGGL(k_sp_init, dim3(grid_for(N)), dim3(kBlock), 0, s,
                        g->off, g->tgt, g->owner, g->pri, g->sp, (int32_t)N);
-  PG_TRY(sync_ctr(g, s));
-  PG_TRY(check_err(g, "invalid game"));
   g->n_oddpri = g->hctr[C_MISC];
   // the two players' vertex lists and the Odd rows' edge count
   uint32_t *flags = g->sk0, *oscan = g->sk1;
@@ -730,6 +842,15 @@ pg_status finalize_state(pg_game *g, hipStream_t s, bool init_sp,
   return PG_OK;
 }
 
+// The maps between the caller's vertex ids and a relabeled game's (null for
+// a game stored in the caller's order).
+static const int32_t *io_perm(const pg_game *g) {
+  return g->relabeled ? g->perm : nullptr;
+}
+static const int32_t *io_rvpos(const pg_game *g) {
+  return g->relabeled ? g->rvpos : nullptr;
+}
+
 // Stages caller strategy arrays (host or device) into the play graph.
 pg_status import_strats(pg_game *g, const int32_t *sigma, const int32_t *tau,
                         bool dev, hipStream_t s) {
@@ -743,7 +864,8 @@ pg_status import_strats(pg_game *g, const int32_t *sigma, const int32_t *tau,
   }
   fill_i32(g->ctr, 0, C_COUNT, s);
   hipLaunchKernelGGL(k_sp_import, dim3(grid_for(N)), dim3(kBlock), 0, s,
-                     g->owner, g->pri, ds, dt, g->sp, (int32_t)N, g->ctr);
+                     g->owner, g->pri, ds, dt, io_perm(g), io_rvpos(g), g->sp,
+                     (int32_t)N, g->ctr);
   PG_TRY(sync_ctr(g, s));
   if (g->hctr[C_ERR] & ERR_INVAL)
     return pg_fail(PG_EINVAL,
@@ -759,7 +881,8 @@ pg_status export_strats(pg_game *g, int32_t *sigma, int32_t *tau, bool dev,
   int32_t *ds = dev ? sigma : (sigma ? g->wl0 : nullptr);
   int32_t *dt = dev ? tau : (tau ? g->wl1 : nullptr);
   hipLaunchKernelGGL(k_sp_export, dim3(grid_for(N)), dim3(kBlock), 0, s,
-                     g->owner, g->sp, ds, dt, (int32_t)N);
+                     g->owner, g->sp, io_perm(g), io_rvpos(g), ds, dt,
+                     (int32_t)N);
   if (!dev) {
     if (sigma) PG_TRY(copy_out(sigma, g->wl0, sizeof(int32_t) * N, false, s));
     if (tau) PG_TRY(copy_out(tau, g->wl1, sizeof(int32_t) * N, false, s));
@@ -768,8 +891,17 @@ pg_status export_strats(pg_game *g, int32_t *sigma, int32_t *tau, bool dev,
   return PG_OK;
 }
 
+// Rank keys in the caller's ids.  Host output of a relabeled game is staged
+// in g->elem, which every valuation rebuilds before reading it.
 pg_status export_keys(pg_game *g, int32_t *key, bool dev, hipStream_t s) {
-  return copy_out(key, g->key, sizeof(int32_t) * (g->n_aug + 1), dev, s);
+  const int64_t N = g->n_aug;
+  if (!g->relabeled)
+    return copy_out(key, g->key, sizeof(int32_t) * (N + 1), dev, s);
+  int32_t *dk = dev ? key : (int32_t *)g->elem;
+  hipLaunchKernelGGL(k_key_export, dim3(grid_for(N + 1)), dim3(kBlock), 0, s,
+                     g->key, g->rvpos, dk, (int32_t)N);
+  if (!dev) PG_TRY(copy_out(key, dk, sizeof(int32_t) * (N + 1), false, s));
+  return PG_OK;
 }
 
 }  // namespace pgk
@@ -866,15 +998,45 @@ pg_status pg_export_game(const pg_game *gc, int64_t *offsets, int32_t *targets,
   DevGuard guard(g->device);
   hipStream_t s = (hipStream_t)hip_stream;
   const bool dev = flags & PG_PTR_DEVICE;
-  if (offsets)
-    PG_TRY(copy_out(offsets, g->off, sizeof(int64_t) * (g->n_aug + 1), dev, s));
-  if (targets)
-    PG_TRY(copy_out(targets, g->tgt, sizeof(int32_t) * g->m_aug, dev, s));
-  if (owner) PG_TRY(copy_out(owner, g->owner, g->n_aug, dev, s));
-  if (priority)
-    PG_TRY(copy_out(priority, g->pri, sizeof(int32_t) * g->n_aug, dev, s));
+  // a relabeled game goes back to the caller's vertex ids first
+  struct Tmp {
+    int64_t *off = nullptr;
+    int32_t *tgt = nullptr, *pri = nullptr;
+    uint8_t *owner = nullptr;
+    ~Tmp() {
+      dev_free(off);
+      dev_free(tgt);
+      dev_free(owner);
+      dev_free(pri);
+    }
+  } ext;
+  const int64_t *off = g->off;
+  const int32_t *tgt = g->tgt, *pri = g->pri;
+  const uint8_t *own = g->owner;
+  if (g->relabeled) {
+    pg_status st = relabel_game(g->off, g->tgt, g->owner, g->pri, g->rvpos,
+                                g->perm, g->n_aug, g->m_aug, &ext.off,
+                                &ext.tgt, &ext.owner, &ext.pri, s);
+    if (st != PG_OK) {
+      (void)hipStreamSynchronize(s);
+      return st;
+    }
+    off = ext.off;
+    tgt = ext.tgt;
+    own = ext.owner;
+    pri = ext.pri;
+  }
+  pg_status st = PG_OK;
+  if (st == PG_OK && offsets)
+    st = copy_out(offsets, off, sizeof(int64_t) * (g->n_aug + 1), dev, s);
+  if (st == PG_OK && targets)
+    st = copy_out(targets, tgt, sizeof(int32_t) * g->m_aug, dev, s);
+  if (st == PG_OK && owner) st = copy_out(owner, own, g->n_aug, dev, s);
+  if (st == PG_OK && priority)
+    st = copy_out(priority, pri, sizeof(int32_t) * g->n_aug, dev, s);
+  // the temporaries are freed only after the copies ran
   PG_HIP(hipStreamSynchronize(s));
-  return PG_OK;
+  return st;
 }
 
 pg_status pg_initial_strategies(pg_game *g, int32_t *sigma, int32_t *tau,
@@ -887,7 +1049,8 @@ pg_status pg_initial_strategies(pg_game *g, int32_t *sigma, int32_t *tau,
   int32_t *ds = dev ? sigma : (sigma ? g->wl0 : nullptr);
   int32_t *dt = dev ? tau : (tau ? g->wl1 : nullptr);
   hipLaunchKernelGGL(k_initial, dim3(grid_for(N)), dim3(kBlock), 0, s, g->off,
-                     g->tgt, g->owner, ds, dt, (int32_t)N);
+                     g->tgt, g->owner, io_perm(g), io_rvpos(g), ds, dt,
+                     (int32_t)N);
   if (!dev) {
     if (sigma) PG_TRY(copy_out(sigma, g->wl0, sizeof(int32_t) * N, false, s));
     if (tau) PG_TRY(copy_out(tau, g->wl1, sizeof(int32_t) * N, false, s));
@@ -1017,7 +1180,7 @@ pg_status pg_solve(pg_game *g, const pg_solve_opts *opts, uint8_t *winner,
   uint8_t *dw = winner;
   if (!dev) dw = (uint8_t *)g->wl0;
   hipLaunchKernelGGL(k_winner, dim3(grid_for(g->n)), dim3(kBlock), 0, s,
-                     g->rs, dw, g->n);
+                     g->rs, io_rvpos(g), dw, g->n);
   if (!dev) PG_TRY(copy_out(winner, dw, g->n, false, s));
   PG_HIP(hipStreamSynchronize(s));
   PG_TRY(export_strats(g, sigma, tau, dev, s));

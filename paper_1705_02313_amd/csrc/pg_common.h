@@ -146,7 +146,13 @@ struct pg_game {
   int32_t *tgt = nullptr;   // [m_aug]
   uint8_t *owner = nullptr; // [n_aug]
   int32_t *pri = nullptr;   // [n_aug]
-  int32_t *perm = nullptr;  // [n_aug] vertices in signed-priority order
+  // Signed-priority order: perm[i] is the i-th vertex in that order, rvpos
+  // (below) its inverse.  A rank-valuation game is stored in that order
+  // (relabeled): internal vertex i is the caller's vertex perm[i], with its
+  // row in the caller's edge order, so the valuation kernels use neither map
+  // and the two only translate vertex ids at the C ABI.
+  int32_t *perm = nullptr;  // [n_aug]
+  bool relabeled = false;
 
   // play graph and valuation state
   // [n_aug+1] {successor (the sink is n_aug), priority of that successor}
@@ -202,6 +208,15 @@ struct pg_game {
 
   pgk::Prof prof;
 };
+
+// The signed-order maps the valuation kernels take: none for a relabeled
+// game, whose vertex ids already are positions in that order.
+inline const int32_t *kernel_rvpos(const pg_game *g) {
+  return g->relabeled ? nullptr : g->rvpos;
+}
+inline const int32_t *kernel_perm(const pg_game *g) {
+  return g->relabeled ? nullptr : g->perm;
+}
 
 // ---- error reporting (pg_api.hip) -----------------------------------------
 pg_status pg_fail(pg_status st, const std::string &msg);

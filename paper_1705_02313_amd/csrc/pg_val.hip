@@ -185,8 +185,9 @@ __device__ __forceinline__ int root_walk(int32_t N, const int32_t *ng,
 }
 
 // Full pass: a plain walk along the ng chain (one load per step).  Writes
-// the vertex's sort key at its signed-priority position (its parent when
-// finite, N + 1 when top).  Also clears the other ng/cand pair (used by the
+// the vertex's sort key at its signed-priority position rvpos[v], or at v
+// when rvpos is null (a relabeled game): its parent when finite, N + 1 when
+// top.  Also clears the other ng/cand pair (used by the
 // next valuation) and this valuation's Euler-list per-vertex state.  An
 // undecided vertex keeps rs = 0 and records where its walk stopped in rcand
 // (-2: its own ng is still open).  With `dist`, undecided vertices are
@@ -220,7 +221,7 @@ __global__ __launch_bounds__(kBlock) void k_root_full(
     else if (r == N + 1) fate = 2;
     if (fate) {
       rs[v] = (uint8_t)fate;
-      sk[rvpos[v]] = fate == 1 ? (uint32_t)p : (uint32_t)(N + 1);
+      sk[rvpos ? rvpos[v] : v] = fate == 1 ? (uint32_t)p : (uint32_t)(N + 1);
       if (fate == 2) key[v] = PG_KEY_TOP;
     } else {
       rcand[v] = r;
@@ -246,7 +247,8 @@ __global__ __launch_bounds__(kBlock) void k_root_round(
       if (fate) {
         __hip_atomic_store(&rs[v], (uint8_t)fate, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
-        sk[rvpos[v]] = fate == 1 ? (uint32_t)ng[v] : (uint32_t)(N + 1);
+        sk[rvpos ? rvpos[v] : v] =
+            fate == 1 ? (uint32_t)ng[v] : (uint32_t)(N + 1);
         if (fate == 2) key[v] = PG_KEY_TOP;
       } else {
         st_relaxed(&rcand[v], r);
@@ -263,9 +265,10 @@ __global__ __launch_bounds__(kBlock) void k_root_round(
 // ---------------------------------------------------------------------------
 // Euler list of the ng tree
 // ---------------------------------------------------------------------------
-// Sorted position i (0 <= i < nF) holds vertex kids[i] with parent skS[i].
-// Elements: 0 enters the root (the sink), 1 leaves it; 2i+2 enters kids[i],
-// 2i+3 leaves it.
+// Sorted position i (0 <= i < nF) holds vertex kids[i] with parent skS[i];
+// svS[i] is its signed-order position, the vertex itself when perm is null
+// (a relabeled game).  Elements: 0 enters the root (the sink), 1 leaves it;
+// 2i+2 enters kids[i], 2i+3 leaves it.
 __global__ __launch_bounds__(kBlock) void k_link_info(
     int32_t N, int32_t n_oddpri, const uint32_t *__restrict__ skS,
     const uint32_t *__restrict__ svS, const int32_t *__restrict__ perm,
@@ -280,7 +283,7 @@ __global__ __launch_bounds__(kBlock) void k_link_info(
     return;
   }
   const uint32_t r = svS[i];
-  const int32_t c = perm[r];
+  const int32_t c = perm ? perm[r] : (int32_t)r;
   kids[i] = c;
   pos[c] = (int32_t)i;
   // fh[p]: first child position + 1 and, in bit 31, whether the last child
@@ -620,15 +623,17 @@ static void enqueue_walks(pg_game *g, hipStream_t s) {
     PG_LAUNCH(pf, K_NG_ROUND, 4.0 * N, k_ng_round, dim3(grid_for(N)),
               dim3(kBlock), 0, s, N, g->sp, g->pri, ng, cand, g->ctr,
               (int)(r == kFastRounds), kWalkSteps, (int32_t *)nullptr);
-  // own ng 4, parent's ng 4, rvpos 4, sort key 4, rs 1; resets 12
-  PG_LAUNCH(pf, K_ROOT_WALK, 29.0 * N, k_root_full, dim3(grid_for(N)),
-            dim3(kBlock), 0, s, N, ng, g->rs, g->rcand, g->key, g->ctr,
-            kFullSteps, ngn, candn, g->fh, g->rvpos, g->sk0,
+  // own ng 4, parent's ng 4, sort key 4, rs 1 (+ rvpos 4 unless
+  // relabeled); resets 12
+  const int32_t *rvpos = kernel_rvpos(g);
+  PG_LAUNCH(pf, K_ROOT_WALK, (rvpos ? 29.0 : 25.0) * N, k_root_full,
+            dim3(grid_for(N)), dim3(kBlock), 0, s, N, ng, g->rs, g->rcand,
+            g->key, g->ctr, kFullSteps, ngn, candn, g->fh, rvpos, g->sk0,
             (int32_t *)nullptr);
   for (int r = 1; r <= kFastRounds; ++r)
     PG_LAUNCH(pf, K_ROOT_ROUND, 1.0 * N, k_root_round, dim3(grid_for(N)),
               dim3(kBlock), 0, s, N, ng, g->rs, g->rcand, g->key, g->ctr,
-              (int)(r == kFastRounds), kWalkSteps, g->rvpos, g->sk0,
+              (int)(r == kFastRounds), kWalkSteps, rvpos, g->sk0,
               (int32_t *)nullptr);
   sum_dist(g->ctr, C_DIST_NF, C_NFIN, s, pf);
 }
@@ -673,10 +678,12 @@ static pg_status careful_walks(pg_game *g, hipStream_t s) {
   }
   fill_i32(g->ctr + C_NFIN, 0, 1, s, pf);
   fill_i32(g->ctr + C_DIST_NF, 0, kDistSlots * kDistStride, s, pf);
+  const int32_t *rvpos = kernel_rvpos(g);
   PG_TRY(counted(g, s, [&](int32_t *dist) {
-    PG_LAUNCH(pf, K_ROOT_WALK, 29.0 * N, k_root_full, dim3(grid_for(N)),
-              dim3(kBlock), 0, s, N, ng, g->rs, g->rcand, g->key, g->ctr,
-              kFullSteps, ngn, candn, g->fh, g->rvpos, g->sk0, dist);
+    PG_LAUNCH(pf, K_ROOT_WALK, (rvpos ? 29.0 : 25.0) * N, k_root_full,
+              dim3(grid_for(N)), dim3(kBlock), 0, s, N, ng, g->rs, g->rcand,
+              g->key, g->ctr, kFullSteps, ngn, candn, g->fh, rvpos, g->sk0,
+              dist);
   }, &open));
   for (int r = 0; open > 0; ++r) {
     if (r >= kMaxRounds)
@@ -684,7 +691,7 @@ static pg_status careful_walks(pg_game *g, hipStream_t s) {
     PG_TRY(counted(g, s, [&](int32_t *dist) {
       PG_LAUNCH(pf, K_ROOT_ROUND, 1.0 * N, k_root_round, dim3(grid_for(N)),
                 dim3(kBlock), 0, s, N, ng, g->rs, g->rcand, g->key, g->ctr,
-                0, kWalkSteps, g->rvpos, g->sk0, dist);
+                0, kWalkSteps, rvpos, g->sk0, dist);
     }, &open));
   }
   sum_dist(g->ctr, C_DIST_NF, C_NFIN, s, pf);
@@ -705,10 +712,12 @@ static void enqueue_rank(pg_game *g, hipStream_t s) {
   const uint32_t *skS = which ? g->sk1 : g->sk0;
   const uint32_t *svS = which ? g->sv1 : g->sv0;
   // the finite count is only known on the device: size grids for N
-  // keys, values, perm 12; kids, pos 8; fh at segment ends
-  PG_LAUNCH_NF(pf, K_LINK_INFO, 22.0, k_link_info, dim3(grid_for(N)),
-               dim3(kBlock), 0, s, N, g->n_oddpri, skS, svS, g->perm,
-               g->kids, g->pos, g->fh, g->ctr);
+  // keys, values 8 (+ perm 4 unless relabeled); kids, pos 8; fh at
+  // segment ends
+  const int32_t *perm = kernel_perm(g);
+  PG_LAUNCH_NF(pf, K_LINK_INFO, perm ? 22.0 : 18.0, k_link_info,
+               dim3(grid_for(N)), dim3(kBlock), 0, s, N, g->n_oddpri, skS, svS,
+               perm, g->kids, g->pos, g->fh, g->ctr);
   // keys, values, kids 12; fh 4; two elements 16; pos at segment ends
   PG_LAUNCH_NF(pf, K_LINK_BUILD, 34.0, k_link_build, dim3(grid_for(N)),
                dim3(kBlock), 0, s, N, g->n_oddpri, skS, svS, g->kids,

@@ -146,3 +146,27 @@ def test_device_pointers_same_as_host(pglib):
     np.testing.assert_array_equal(to_np(a["sigma"]), to_np(b["sigma"]))
     np.testing.assert_array_equal(to_np(a["tau"]), to_np(b["tau"]))
     assert a["stats"]["n_valuations"] == b["stats"]["n_valuations"]
+
+
+def test_device_pointers_boundary_calls(pglib):
+    """Initial strategies, valuations and best responses with device arrays:
+    vertex ids in and out are the caller's (the library stores a rank game
+    in signed-priority order and translates at the C ABI)."""
+    g = synth.random_game(7000, 2, 6, 78)
+    aug = orc.preprocess(g)
+    sigma, tau = orc.initial_strategies(aug)
+    with Game.from_dict(g, device=True) as d:
+        ds, dt = d.initial_strategies()
+        np.testing.assert_array_equal(to_np(ds), sigma)
+        np.testing.assert_array_equal(to_np(dt), tau)
+        traj = list(oracle_trajectory(aug))
+        for k in (0, len(traj) // 2, len(traj) - 1):
+            s_k, t_k, key = traj[k]
+            dkey, nf = d.valuation(s_k, t_k)
+            np.testing.assert_array_equal(to_np(dkey), key,
+                                          err_msg=f"valuation {k}")
+        ref = orc.solve(g)
+        out = d.solve()
+        _assert_solve_equal(ref, out)
+        dtau, dkey, _ = d.best_response(ref["sigma"], ref["tau"])
+        np.testing.assert_array_equal(to_np(dtau), ref["tau"])
