@@ -183,7 +183,9 @@ struct pg_game {
   int32_t *rvpos = nullptr;  // [n_aug] position of each vertex in perm
   int32_t *odd_ids = nullptr;   // [n_odd]  Odd vertices, increasing
   int32_t *even_ids = nullptr;  // [n_aug - n_odd] Even vertices, increasing
-  int2 *elem = nullptr;      // [2*n_aug+2] {next element or -1, node | weight bit}
+  // [2*n_aug+2] {next element or -1, node | weight bits}; a leaf's second
+  // slot holds {its parent, 0}
+  int2 *elem = nullptr;
 
   pgk::RankLevel lv[8];
   int nlevels = 0;

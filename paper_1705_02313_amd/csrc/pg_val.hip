@@ -24,8 +24,8 @@
 //   sort    stable radix sort of the finite vertices (taken in signed-priority
 //           order) by ng: each node's children end up contiguous and ordered
 //   euler   the Euler-tour list of the ng tree (section 5, "Formal
-//           reduction"): enter/leave elements per node, one weighted element
-//           per node marking its in-order point
+//           reduction"): enter/leave elements per inner node, one element
+//           per leaf; each node's in-order point is marked on one element
 //   rank    list ranking by sublists (section 5, "List ranking"): splitters
 //           at fixed element strides, every sublist summed by one thread, the
 //           reduced list ranked recursively and finally in LDS by pointer
@@ -268,7 +268,9 @@ __global__ __launch_bounds__(kBlock) void k_root_round(
 // Sorted position i (0 <= i < nF) holds vertex kids[i] with parent skS[i];
 // svS[i] is its signed-order position, the vertex itself when perm is null
 // (a relabeled game).  Elements: 0 enters the root (the sink), 1 leaves it;
-// 2i+2 enters kids[i], 2i+3 leaves it.
+// 2i+2 enters kids[i], 2i+3 leaves it.  A leaf is visited by element 2i+2
+// alone: the list skips 2i+3, which holds the leaf's parent.  Splitters sit
+// at even indices (multiples of the stride), so none is such a slot.
 __global__ __launch_bounds__(kBlock) void k_link_info(
     int32_t N, int32_t n_oddpri, const uint32_t *__restrict__ skS,
     const uint32_t *__restrict__ svS, const int32_t *__restrict__ perm,
@@ -316,25 +318,34 @@ __global__ __launch_bounds__(kBlock) void k_link_build(
   const bool seg_end = (i == nF - 1) || (skS[i + 1] != p);
   const uint32_t f = fh[c];
   const int32_t fc = (int32_t)(f & 0x7fffffffu) - 1;
-  // enter c: first child of c, or straight to leaving c.  It carries the
-  // parent's in-order point when c is the parent's first even child.
+  // c is the parent's first even child: the parent's in-order point comes
+  // just before c's subtree
   const bool wd = ev && (seg_start || svS[i - 1] < (uint32_t)n_oddpri);
-  elem[2 * i + 2] =
-      make_int2(fc >= 0 ? 2 * fc + 2 : (int32_t)(2 * i + 3),
-                (int32_t)p | ((int32_t)wd << 31));
-  // leave c: next sibling, else leave the parent.  It carries c's own
-  // in-order point when c has no even child.
-  const bool wu = (fc < 0) || !(f >> 31);
+  // after c's subtree: the next sibling, else leave the parent
   int32_t nx;
   if (!seg_end) nx = (int32_t)(2 * i + 4);
   else nx = (p == (uint32_t)N) ? 1 : 2 * pos[p] + 3;
+  if (fc < 0) {
+    // a leaf (most vertices of the tree): one element visits it, carrying
+    // the parent's point (bit 30, the parent kept in the unused odd slot
+    // beside it) and then its own (bit 31)
+    elem[2 * i + 2] =
+        make_int2(nx, c | (int32_t)0x80000000 | ((int32_t)wd << 30));
+    elem[2 * i + 3] = make_int2((int32_t)p, 0);
+    return;
+  }
+  // enter c: its first child, carrying the parent's point when wd
+  elem[2 * i + 2] = make_int2(2 * fc + 2, (int32_t)p | ((int32_t)wd << 31));
+  // leave c: carries c's own point when c has no even child
+  const bool wu = !(f >> 31);
   elem[2 * i + 3] = make_int2(nx, c | ((int32_t)wu << 31));
 }
 
 // ---------------------------------------------------------------------------
 // list ranking by sublists
 // ---------------------------------------------------------------------------
-// Level 0 walks the Euler list (weights are the top bits of elem[].y); level k
+// Level 0 walks the Euler list (weights are bits 31 and 30 of elem[].y, the
+// second only on leaves that carry their parent's point); level k
 // walks the list of level-(k-1) splitters (int weights).  Splitters are the
 // elements whose index is a multiple of the stride; element 0 (the list head)
 // is one.  Every size comes from the finite count on the device.
@@ -354,7 +365,7 @@ __global__ __launch_bounds__(kBlock) void k_lr_sum1(
     int64_t steps = 0;
     for (;;) {
       const int2 el = elem[e];
-      acc += (int32_t)((uint32_t)el.y >> 31);
+      acc += (int32_t)((uint32_t)el.y >> 31) + ((el.y >> 30) & 1);
       e = el.x;
       if (e < 0 || e % kStride == 0) break;
       if (++steps > L) { atomicOr(&ctr[C_ERR], ERR_LISTWALK); e = -1; break; }
@@ -462,7 +473,7 @@ __global__ __launch_bounds__(kBlock) void k_lr_distk(
 }
 
 // Final pass over the Euler list: every weighted element emits the key of
-// its node.
+// its node (a leaf with bit 30 first its parent's, then its own).
 __global__ __launch_bounds__(kBlock) void k_lr_emit1(
     const int2 *__restrict__ elem, int per_thread,
     const int32_t *__restrict__ sbase, int32_t *key, const int32_t *ctr) {
@@ -478,7 +489,8 @@ __global__ __launch_bounds__(kBlock) void k_lr_emit1(
     int32_t b = sbase[j];
     for (int64_t steps = 0; steps <= L; ++steps) {
       const int2 el = elem[e];
-      if (el.y < 0) key[el.y & 0x7fffffff] = b++;
+      if (el.y & 0x40000000) key[elem[e + 1].x] = b++;  // a leaf's parent
+      if (el.y < 0) key[el.y & 0x3fffffff] = b++;
       e = el.x;
       if (e < 0 || e % kStride == 0) break;
     }
@@ -727,8 +739,10 @@ static void enqueue_rank(pg_game *g, hipStream_t s) {
   const int64_t ns1 = level_size(Lmax, 1);
   const int kPerThread1 = per_thread1(ns1);
   const int64_t thr1 = (ns1 + kPerThread1 - 1) / kPerThread1;
-  // 8 B per list element (2 per finite vertex) and 8 B per splitter
-  PG_LAUNCH_NF(pf, K_LR_SUM1, 16.5, k_lr_sum1, dim3(grid_for(thr1)),
+  // 8 B per list element and 8 B per splitter (2 F / 32 of them).  The list
+  // has one element per leaf and two per inner vertex: counted at one per
+  // finite vertex, its least length
+  PG_LAUNCH_NF(pf, K_LR_SUM1, 8.5, k_lr_sum1, dim3(grid_for(thr1)),
             dim3(kBlock), 0, s, g->elem, kPerThread1, g->lv[0].sum,
             g->lv[0].next, g->ctr);
   for (int k = 1; k < nl; ++k) {
@@ -749,8 +763,9 @@ static void enqueue_rank(pg_game *g, hipStream_t s) {
               dim3(grid_for(nsk)), dim3(kBlock), 0, s, g->lv[k - 1].next,
               g->lv[k - 1].sum, k, g->lv[k].base, g->lv[k - 1].base, g->ctr);
   }
-  // 8 B per list element, 4 B per splitter, one 4 B key per finite vertex
-  PG_LAUNCH_NF(pf, K_LR_EMIT1, 20.25, k_lr_emit1, dim3(grid_for(thr1)),
+  // 8 B per list element (at least one per finite vertex), 4 B per
+  // splitter, one 4 B key per finite vertex
+  PG_LAUNCH_NF(pf, K_LR_EMIT1, 12.25, k_lr_emit1, dim3(grid_for(thr1)),
             dim3(kBlock), 0, s, g->elem, kPerThread1, g->lv[0].base, g->key,
             g->ctr);
 }
