@@ -433,13 +433,30 @@ __global__ __launch_bounds__(kBlock) void k_cnt_odd_switch(
   if (t < count) {
     const int32_t v = ids[t];
     const int64_t e0 = off[v], e1 = off[v + 1];
+    // the current choice is normally in the row: its valuation comes with
+    // the row's loads (a strategy given at the C ABI may name another vertex)
+    const int32_t cur = sp[v].x;
+    int32_t cv[D];
+    bool ct = false, have_c = false;
     int32_t best = tgt[e0];
     int32_t bv[D];
     bool bt = load_val<D>(cnt, best, bv);
+    if (best == cur) {
+      ct = bt;
+      have_c = true;
+#pragma unroll
+      for (int i = 0; i < D; ++i) cv[i] = bv[i];
+    }
     for (int64_t e = e0 + 1; e < e1; ++e) {
       const int32_t u = tgt[e];
       int32_t uv[D];
       const bool ut = load_val<D>(cnt, u, uv);
+      if (u == cur) {
+        ct = ut;
+        have_c = true;
+#pragma unroll
+        for (int i = 0; i < D; ++i) cv[i] = uv[i];
+      }
       if (vcmp<D>(ut, uv, bt, bv, odd_cols) < 0) {
         best = u;
         bt = ut;
@@ -447,9 +464,7 @@ __global__ __launch_bounds__(kBlock) void k_cnt_odd_switch(
         for (int i = 0; i < D; ++i) bv[i] = uv[i];
       }
     }
-    const int32_t cur = sp[v].x;
-    int32_t cv[D];
-    const bool ct = load_val<D>(cnt, cur, cv);
+    if (!have_c) ct = load_val<D>(cnt, cur, cv);
     if (vcmp<D>(bt, bv, ct, cv, odd_cols) < 0) {
       sp[v] = make_int2(best, pri[best]);
       sw = true;
@@ -472,6 +487,11 @@ __global__ __launch_bounds__(kBlock) void k_cnt_even_switch(
   if (t < count) {
     const int32_t v = ids[t];
     const int64_t e0 = off[v], e1 = off[v + 1];
+    // the current choice is the sink (the zero vector) or normally in the
+    // row (see All_Odd)
+    const int32_t cur = sp[v].x;
+    int32_t cv[D] = {};
+    bool ct = false, have_c = cur == N;
     int32_t best = N;
     int32_t bv[D] = {};
     bool bt = false;
@@ -479,6 +499,12 @@ __global__ __launch_bounds__(kBlock) void k_cnt_even_switch(
       const int32_t u = tgt[e];
       int32_t uv[D];
       const bool ut = load_val<D>(cnt, u, uv);
+      if (u == cur) {
+        ct = ut;
+        have_c = true;
+#pragma unroll
+        for (int i = 0; i < D; ++i) cv[i] = uv[i];
+      }
       if (vcmp<D>(ut, uv, bt, bv, odd_cols) > 0) {
         best = u;
         bt = ut;
@@ -486,9 +512,7 @@ __global__ __launch_bounds__(kBlock) void k_cnt_even_switch(
         for (int i = 0; i < D; ++i) bv[i] = uv[i];
       }
     }
-    const int32_t cur = sp[v].x;
-    int32_t cv[D];
-    const bool ct = load_val<D>(cnt, cur, cv);
+    if (!have_c) ct = load_val<D>(cnt, cur, cv);
     if (vcmp<D>(bt, bv, ct, cv, odd_cols) > 0) {
       sp[v] = make_int2(best, best == N ? 2147483647 : pri[best]);
       sw = true;

@@ -519,7 +519,10 @@ __global__ __launch_bounds__(kBlock) void k_odd_switch(
     const int32_t v = ids[t];
     const int64_t e0 = off[v], e1 = off[v + 1];
     const int32_t cur = sp[v].x;
-    const int32_t kc = key[cur];
+    // the current choice is normally in the row: its key comes with the
+    // row's gathers (a strategy given at the C ABI may name another vertex)
+    int32_t kc = 0;
+    bool have_kc = false;
     int32_t best = -1;
     int32_t kb = 0;
     for (int64_t b = e0; b < e1; b += kRowBatch) {
@@ -529,9 +532,12 @@ __global__ __launch_bounds__(kBlock) void k_odd_switch(
 #pragma unroll
       for (int j = 0; j < kRowBatch; ++j) k[j] = (u[j] >= 0) ? key[u[j]] : 0;
 #pragma unroll
-      for (int j = 0; j < kRowBatch; ++j)
+      for (int j = 0; j < kRowBatch; ++j) {
         if (u[j] >= 0 && (best < 0 || k[j] < kb)) { kb = k[j]; best = u[j]; }
+        if (u[j] == cur) { kc = k[j]; have_kc = true; }
+      }
     }
+    if (!have_kc) kc = key[cur];
     if (kb < kc) {
       sp[v] = make_int2(best, pri[best]);
       sw = true;
@@ -554,9 +560,11 @@ __global__ __launch_bounds__(kBlock) void k_even_switch(
     const int32_t v = ids[t];
     const int64_t e0 = off[v], e1 = off[v + 1];
     const int32_t cur = sp[v].x;
-    const int32_t kc = key[cur];
+    // the current choice is the sink or normally in the row (see All_Odd)
     int32_t best = N;
     int32_t kb = key[N];
+    int32_t kc = kb;
+    bool have_kc = cur == N;
     for (int64_t b = e0; b < e1; b += kRowBatch) {
       int32_t u[kRowBatch], k[kRowBatch];
 #pragma unroll
@@ -564,9 +572,12 @@ __global__ __launch_bounds__(kBlock) void k_even_switch(
 #pragma unroll
       for (int j = 0; j < kRowBatch; ++j) k[j] = (u[j] >= 0) ? key[u[j]] : 0;
 #pragma unroll
-      for (int j = 0; j < kRowBatch; ++j)
+      for (int j = 0; j < kRowBatch; ++j) {
         if (u[j] >= 0 && k[j] > kb) { kb = k[j]; best = u[j]; }
+        if (u[j] == cur) { kc = k[j]; have_kc = true; }
+      }
     }
+    if (!have_kc) kc = key[cur];
     if (kb > kc) {
       sp[v] = make_int2(best, best == N ? 2147483647 : pri[best]);
       sw = true;

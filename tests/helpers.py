@@ -75,3 +75,23 @@ def dense_oracle_trajectory(aug: dict, max_vals: int = 10**9):
         sigma, c = orc.dense_even_switch(aug, counts, top, values, sigma)
         if c == 0:
             return
+
+
+def off_row_tau(aug: dict, tau, k: int, seed: int):
+    """tau with k Odd vertices pointed at Even vertices outside their rows
+    (a strategy the C ABI accepts).  While every Even vertex takes the sink,
+    such a play stays admissible."""
+    rng = np.random.default_rng(seed)
+    own = np.asarray(aug["owner"])
+    off = np.asarray(aug["offsets"])
+    tgt = np.asarray(aug["targets"])
+    evens = np.flatnonzero(own == 0)
+    odds = np.flatnonzero(own == 1)
+    t = np.array(tau, dtype=np.int32, copy=True)
+    for v in rng.choice(odds, size=min(k, odds.size), replace=False):
+        row = set(tgt[off[v]:off[v + 1]].tolist())
+        u = int(rng.choice(evens))
+        while u in row:
+            u = int(rng.choice(evens))
+        t[v] = u
+    return t

@@ -13,7 +13,7 @@ from oracle import orc
 from paper_1705_02313_amd import synth
 from paper_1705_02313_amd.pg import (PG_BR_BELLMAN_FORD, PG_BR_SI_RESET,
                                      PG_EINVAL, Game, PgError)
-from tests.helpers import dense_oracle_trajectory, to_np
+from tests.helpers import dense_oracle_trajectory, off_row_tau, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -183,3 +183,28 @@ def test_rank_si_reset_and_bellman_ford_errors():
         with pytest.raises(PgError) as e:
             dev.solve(best_response=7)
         assert e.value.status == PG_EINVAL
+
+
+def test_count_best_response_from_strategy_outside_rows():
+    """As the rank test: Odd choices outside their rows are compared by
+    their own count rows, as the oracle does."""
+    g = synth.few_priorities_game(3000, 2, 5, 4, 21)
+    aug = orc.dense_preprocess(g)
+    sigma, tau = orc.initial_strategies(aug)
+    tau = off_row_tau(aug, tau, 200, 2)
+    t = tau.copy()
+    nval = 0
+    while True:
+        succ = np.where(aug["owner"] == 1, t, sigma).astype(np.int32)
+        counts, top, values, rc = orc.dense_valuation(succ, aug["pri"])
+        assert rc == 0
+        nval += 1
+        t, c = orc.dense_odd_switch(aug, counts, top, values, t)
+        if c == 0:
+            break
+    with Game.from_dict(g) as dev:
+        assert dev.d == values.size
+        dtau, key, dn = dev.best_response(sigma, tau)
+    assert key is None
+    np.testing.assert_array_equal(to_np(dtau), t)
+    assert dn == nval

@@ -10,7 +10,7 @@ import pytest
 from oracle import orc
 from paper_1705_02313_amd import synth
 from paper_1705_02313_amd.pg import Game
-from tests.helpers import oracle_trajectory, to_np
+from tests.helpers import off_row_tau, oracle_trajectory, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -170,3 +170,28 @@ def test_device_pointers_boundary_calls(pglib):
         _assert_solve_equal(ref, out)
         dtau, dkey, _ = d.best_response(ref["sigma"], ref["tau"])
         np.testing.assert_array_equal(to_np(dtau), ref["tau"])
+
+
+def test_best_response_from_strategy_outside_rows(pglib):
+    """Odd strategies may name vertices outside their rows at the C ABI:
+    the current choice's key is then read on its own, as the oracle does."""
+    g = synth.random_game(3000, 2, 5, 6)
+    aug = orc.preprocess(g)
+    sigma, tau = orc.initial_strategies(aug)
+    tau = off_row_tau(aug, tau, 200, 1)
+    by_pri = orc.order_by_pri(aug["pri"])
+    t = tau.copy()
+    nval = 0
+    while True:
+        succ = np.where(aug["owner"] == 1, t, sigma).astype(np.int32)
+        key, _, rc = orc.valuation(succ, aug["pri"], by_pri=by_pri)
+        assert rc == 0
+        nval += 1
+        t, c = orc.odd_switch(aug, key, t)
+        if c == 0:
+            break
+    with Game.from_dict(g) as dev:
+        dtau, dkey, dn = dev.best_response(sigma, tau)
+    np.testing.assert_array_equal(to_np(dtau), t)
+    np.testing.assert_array_equal(to_np(dkey), key)
+    assert dn == nval
