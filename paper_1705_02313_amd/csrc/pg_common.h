@@ -26,6 +26,7 @@ enum Counter : int {
   C_ABORT = 3,        // nonzero: bounded rounds left work; later kernels skip
   C_MISC = 4,         // scratch counter (preprocessing changes, odd count,
                       // open vertices of host-driven walk rounds)
+  C_NINNER = 5,       // finite vertices whose parent is not the sink
   C_COUNT = 32,       // the part copied back to the host
   // Hot counts are spread over kDistSlots slots kDistStride ints apart (one
   // atomic per block into slot blockIdx % kDistSlots) and summed by one
@@ -50,7 +51,7 @@ enum ErrBit : int {
 // Kernel kinds for the optional event profiler (pg_profile_* in pg.h).
 enum KId : int {
   K_FILL = 0, K_NG_WALK, K_NG_ROUND, K_ROOT_WALK, K_ROOT_ROUND,
-  K_SORT_HIST, K_SCAN, K_SORT_PASS, K_LINK_INFO, K_LINK_BUILD,
+  K_SORT_SPLIT, K_SORT_HIST, K_SCAN, K_SORT_PASS, K_LINK_INFO, K_LINK_BUILD,
   K_LR_SUM1, K_LR_SUMK, K_LR_TOP, K_LR_DISTK, K_LR_EMIT1, K_ODD_SWITCH,
   K_EVEN_SWITCH, K_OTHER, K_COUNT
 };
@@ -67,9 +68,11 @@ struct Prof {
     int kid;
     double bytes;     // fixed part
     double per_nf;    // plus this many bytes per finite vertex
+    double per_ni;    // and per finite vertex whose parent is not the sink
     hipEvent_t a, b;
   };
-  double nf = 0.0;    // finite count of the valuation being flushed
+  double nf = 0.0;    // counts of the valuation being flushed
+  double ni = 0.0;
   std::vector<hipEvent_t> pool;
   std::vector<Pend> pend;
   hipEvent_t get();
@@ -83,12 +86,13 @@ struct ProfScope {
   hipStream_t s;
   Prof::Pend e{};
   ProfScope(Prof *prof, int kid, double bytes, hipStream_t st,
-            double per_nf = 0.0)
+            double per_nf = 0.0, double per_ni = 0.0)
       : p(prof && prof->on ? prof : nullptr), s(st) {
     if (!p) return;
     e.kid = kid;
     e.bytes = bytes;
     e.per_nf = per_nf;
+    e.per_ni = per_ni;
     e.a = p->get();
     e.b = p->get();
     (void)hipEventRecord(e.a, s);
@@ -113,6 +117,16 @@ struct ProfScope {
   do {                                                                        \
     ::pgk::ProfScope ps_((prof), (kid), 0.0, (stream), (double)(per_nf));    \
     hipLaunchKernelGGL(kern, grid, block, smem, stream, __VA_ARGS__);         \
+  } while (0)
+
+// Same, with `per_nf` bytes per finite vertex and `per_ni` per finite vertex
+// whose parent is not the sink (both read back with the counters).
+#define PG_LAUNCH_NI(prof, kid, bytes, per_nf, per_ni, kern, grid, block,   \
+                     smem, stream, ...)                                    \
+  do {                                                                     \
+    ::pgk::ProfScope ps_((prof), (kid), (double)(bytes), (stream),         \
+                         (double)(per_nf), (double)(per_ni));              \
+    hipLaunchKernelGGL(kern, grid, block, smem, stream, __VA_ARGS__);      \
   } while (0)
 
 // Per-level arrays of the recursive sublist list ranking.
@@ -304,14 +318,20 @@ int radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
                const int32_t *gate = nullptr, bool index_values = false);
 size_t radix_scan_tmp_bytes(int64_t n);
 
-// The same sort in one kernel per 8-bit pass (decoupled look-back); `work`
-// holds onesweep_words(n) words; a look-back that waits too long sets
-// ERR_SORT in *err.
+// The parent sort of a valuation (one kernel per 8-bit pass, decoupled
+// look-back).  k0[i] is the parent of the vertex at signed-order position i:
+// npar for the sink, above npar for a top vertex.  Finite vertices come out
+// grouped by parent, stably: position i < n_inner (*n_inner on the device,
+// also in ctr[C_NINNER]) holds parent skS[i] and position svS[i]; a position
+// n_inner <= i < nF = ctr[C_NFIN] holds a child of the sink, at
+// svS[n_inner + nF - 1 - i].  Returns which pair holds skS/svS (1: k1/v1).
+// `work` holds onesweep_words(n) words; a look-back that waits too long sets
+// ERR_SORT, a finite count that disagrees with the keys ERR_RANKCOUNT.
 int64_t onesweep_words(int64_t n);
-int radix_sort_1s(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
-                  int64_t n, int bits, uint32_t *work, int32_t *err,
-                  hipStream_t s, Prof *prof = nullptr,
-                  const int32_t *gate = nullptr, bool index_values = false);
+int parent_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
+                int64_t n, uint32_t npar, int bits, uint32_t *work,
+                int32_t *ctr, hipStream_t s, Prof *prof,
+                const uint32_t **n_inner);
 
 }  // namespace pgk
 

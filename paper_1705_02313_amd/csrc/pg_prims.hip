@@ -8,9 +8,9 @@ namespace pgk {
 
 const char *const kKernelNames[K_COUNT] = {
     "fill",       "ng_walk",   "ng_round",   "root_walk",  "root_round",
-    "sort_hist",  "scan",      "sort_pass",  "link_info",  "link_build",
-    "lr_sum1",    "lr_sumk",   "lr_top",     "lr_distk",   "lr_emit1",
-    "odd_switch", "even_switch", "other"};
+    "sort_split", "sort_hist", "scan",       "sort_pass",  "link_info",
+    "link_build", "lr_sum1",   "lr_sumk",    "lr_top",     "lr_distk",
+    "lr_emit1",   "odd_switch", "even_switch", "other"};
 
 hipEvent_t Prof::get() {
   if (!pool.empty()) {
@@ -29,7 +29,7 @@ void Prof::flush() {
     if (hipEventElapsedTime(&t, p.a, p.b) == hipSuccess) {
       ms[p.kid] += t;
       calls[p.kid] += 1;
-      bytes[p.kid] += p.bytes + p.per_nf * nf;
+      bytes[p.kid] += p.bytes + p.per_nf * nf + p.per_ni * ni;
     }
     pool.push_back(p.a);
     pool.push_back(p.b);
@@ -337,8 +337,11 @@ int radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
 }
 
 // ---------------------------------------------------------------------------
-// one-sweep stable LSD radix sort, 8-bit digits: one kernel builds the digit
-// histograms of every pass; then each pass is one kernel in which a tile
+// one-sweep stable LSD radix sort, 8-bit digits (the parent sort of a
+// valuation): a split pass sets the sink's children aside (they are already
+// in order) and compacts the other finite vertices; one kernel builds the
+// digit histograms of every pass over that prefix; then each pass is one
+// kernel in which a tile
 // (taken in launch order from a counter) ranks its 4096 keys in LDS, learns
 // its global offset per digit by decoupled look-back over the tiles before
 // it, and writes each digit's run out contiguously.  A tile waits only on
@@ -357,13 +360,16 @@ constexpr int k1sCopies = 64;   // histogram copies (blocks spread over them)
 
 int64_t onesweep_tiles(int64_t n) { return (n + k1sTile - 1) / k1sTile; }
 
-// work buffer: [counters 4 | histograms 64 copies x 4 x 256 | bases 4 x 256
-//               | status 4 x tiles x 256]
+// work buffer: [counters 8 | histograms 64 copies x 4 x 256 | bases 4 x 256
+//               | status 4 x tiles x 256 | split status 2 x tiles]
+// counters: 0-3 tile numbers of the digit passes, 4 of the split pass,
+// 5 the prefix length (finite vertices whose parent is not the sink)
+constexpr int k1sCounters = 8;
 constexpr int64_t k1sHistWords = (int64_t)k1sCopies * k1sMaxPasses * 256;
 
 int64_t onesweep_words(int64_t n) {
-  return 4 + k1sHistWords + k1sMaxPasses * 256 +
-         k1sMaxPasses * onesweep_tiles(n) * 256;
+  return k1sCounters + k1sHistWords + k1sMaxPasses * 256 +
+         k1sMaxPasses * onesweep_tiles(n) * 256 + 2 * onesweep_tiles(n);
 }
 
 // lanes of the wave (among `valid` ones) whose 8-bit digit equals mine
@@ -384,10 +390,13 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
 // group's size to the wave's own counters, so no two lanes ever update one
 // counter at once (the keys are skewed: many vertices share a parent).
 __global__ __launch_bounds__(kBlock) void k_1s_hist(const uint32_t *keys,
-                                                    int64_t n, int passes,
+                                                    const uint32_t *n_dev,
+                                                    int passes,
                                                     uint32_t *glob,
                                                     const int32_t *gate) {
   if (gate && *gate) return;
+  const int64_t n = *n_dev;
+  if ((int64_t)blockIdx.x * k1sTile >= n) return;   // grid sized for the most
   constexpr int kWaveItems = k1sTile / kRsWaves / kWave;   // 16
   __shared__ uint32_t h[kRsWaves][k1sMaxPasses][256];
   const int lane = threadIdx.x & (kWave - 1);
@@ -454,9 +463,15 @@ __device__ __forceinline__ void st_status(uint32_t *p, uint32_t v) {
 // order: ranks come out stable without barriers inside the loop.
 __global__ __launch_bounds__(kBlock) void k_1s_pass(
     const uint32_t *kin, const uint32_t *__restrict__ vin, uint32_t *kout,
-    uint32_t *vout, int64_t n, int shift, const uint32_t *__restrict__ dbase,
-    uint32_t *status, uint32_t *tile_ctr, int32_t *err, const int32_t *gate) {
+    uint32_t *vout, const uint32_t *n_dev, int shift,
+    const uint32_t *__restrict__ dbase, uint32_t *status, uint32_t *tile_ctr,
+    int32_t *err, const int32_t *gate) {
   if (gate && *gate) return;
+  const int64_t n = *n_dev;
+  // the grid is sized for the most keys: blocks past the tiles needed leave
+  // before taking a tile number, so the ones that stay take exactly the
+  // numbers of the tiles there are
+  if ((int64_t)blockIdx.x * k1sTile >= n) return;
   constexpr int kWaveItems = k1sTile / kRsWaves / kWave;   // 16
   __shared__ uint32_t s_tile;
   __shared__ uint32_t lk[k1sTile];
@@ -476,12 +491,18 @@ __global__ __launch_bounds__(kBlock) void k_1s_pass(
   const int64_t rem = n - base;
   const int tn = rem < k1sTile ? (int)rem : k1sTile;   // keys of this tile
   uint32_t k[kWaveItems], v[kWaveItems], rk[kWaveItems];
+  // every load in flight before the first ballot waits on one
 #pragma unroll
   for (int r = 0; r < kWaveItems; ++r) {
     const int j = w * (k1sTile / kRsWaves) + r * kWave + lane;
     const bool valid = j < tn;
     k[r] = valid ? kin[base + j] : 0u;
-    v[r] = valid ? (vin ? vin[base + j] : (uint32_t)(base + j)) : 0u;
+    v[r] = valid ? vin[base + j] : 0u;
+  }
+#pragma unroll
+  for (int r = 0; r < kWaveItems; ++r) {
+    const int j = w * (k1sTile / kRsWaves) + r * kWave + lane;
+    const bool valid = j < tn;
     const uint32_t d = (k[r] >> shift) & 255u;
     const uint64_t peers = digit_peers(d, valid);
     const uint32_t before = (uint32_t)__popcll(peers & lt);
@@ -555,34 +576,144 @@ __global__ __launch_bounds__(kBlock) void k_1s_pass(
   }
 }
 
-int radix_sort_1s(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
-                  int64_t n, int bits, uint32_t *work, int32_t *err,
-                  hipStream_t s, Prof *prof, const int32_t *gate,
-                  bool index_values) {
-  if (n <= 0 || bits <= 0) return 0;
+// Split pass of the parent sort: key < npar (the vertex has an inner
+// parent) goes to kout/vout in input order with its index as value; key ==
+// npar (a child of the sink) only needs its index, written to cout at
+// nF - 1 - (its rank among the sink's children), so that the prefix length
+// need not be known; larger keys (top vertices) are dropped.  Tiles find
+// their offsets for the two classes by decoupled look-back (two status
+// words per tile); the last tile publishes the prefix length and checks that
+// the two classes add up to the finite count.
+__global__ __launch_bounds__(kBlock) void k_ps_split(
+    const uint32_t *kin, int64_t n, uint32_t npar, uint32_t *kout,
+    uint32_t *vout, uint32_t *cout, uint32_t *status, uint32_t *tile_ctr,
+    uint32_t *n_inner, int32_t *ctr) {
+  if (ctr[C_ABORT]) return;
+  constexpr int kWaveItems = k1sTile / kRsWaves / kWave;   // 16
+  __shared__ uint32_t s_tile;
+  __shared__ uint32_t wcnt[2][kRsWaves];
+  __shared__ uint32_t s_excl[2], s_total[2];
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int w = tid / kWave;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+  if (tid == 0) s_tile = atomicAdd(tile_ctr, 1u);
+  __syncthreads();
+  const uint32_t tile = s_tile;
+  const int64_t base = (int64_t)tile * k1sTile + w * (k1sTile / kRsWaves);
+  uint32_t k[kWaveItems], r0[kWaveItems], r1[kWaveItems];
+  uint32_t c0 = 0, c1 = 0;
+#pragma unroll
+  for (int r = 0; r < kWaveItems; ++r) {
+    const int64_t i = base + r * kWave + lane;
+    k[r] = i < n ? kin[i] : 0xffffffffu;
+  }
+#pragma unroll
+  for (int r = 0; r < kWaveItems; ++r) {
+    const uint64_t b0 = __ballot(k[r] < npar);
+    const uint64_t b1 = __ballot(k[r] == npar);
+    r0[r] = c0 + (uint32_t)__popcll(b0 & lt);
+    r1[r] = c1 + (uint32_t)__popcll(b1 & lt);
+    c0 += (uint32_t)__popcll(b0);
+    c1 += (uint32_t)__popcll(b1);
+  }
+  if (lane == 0) {
+    wcnt[0][w] = c0;
+    wcnt[1][w] = c1;
+  }
+  __syncthreads();
+  if (tid < 2) {
+    uint32_t cnt = 0;
+    for (int j = 0; j < kRsWaves; ++j) cnt += wcnt[tid][j];
+    st_status(&status[(int64_t)tile * 2 + tid],
+              (tile == 0 ? kStPre : kStAgg) | cnt);
+    uint32_t excl = 0;
+    if (tile > 0) {
+      int64_t t = (int64_t)tile - 1;
+      int spins = 0;
+      for (;;) {
+        const uint32_t sv = ld_status(&status[t * 2 + tid]);
+        if (!(sv & (kStAgg | kStPre))) {
+          if (++spins > kSpinMax) {
+            atomicOr(&ctr[C_ERR], ERR_SORT);
+            break;
+          }
+          continue;
+        }
+        excl += sv & kStVal;
+        if ((sv & kStPre) || t == 0) break;
+        --t;
+      }
+      st_status(&status[(int64_t)tile * 2 + tid], kStPre | (excl + cnt));
+    }
+    s_excl[tid] = excl;
+    s_total[tid] = excl + cnt;
+  }
+  __syncthreads();
+  const int64_t nf = ctr[C_NFIN];
+  if (tid == 0 && (int64_t)(tile + 1) * k1sTile >= n) {
+    *n_inner = s_total[0];
+    ctr[C_NINNER] = (int32_t)s_total[0];
+    if ((int64_t)s_total[0] + s_total[1] != nf)
+      atomicOr(&ctr[C_ERR], ERR_RANKCOUNT);
+  }
+  uint32_t o0 = s_excl[0], o1 = s_excl[1];
+  for (int j = 0; j < w; ++j) {
+    o0 += wcnt[0][j];
+    o1 += wcnt[1][j];
+  }
+#pragma unroll
+  for (int r = 0; r < kWaveItems; ++r) {
+    const int64_t i = base + r * kWave + lane;
+    if (k[r] < npar) {
+      const uint32_t q = o0 + r0[r];
+      kout[q] = k[r];
+      vout[q] = (uint32_t)i;
+    } else if (k[r] == npar) {
+      const int64_t q = (int64_t)o1 + r1[r];
+      if (q < nf) cout[nf - 1 - q] = (uint32_t)i;   // else flagged above
+    }
+  }
+}
+
+int parent_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
+                int64_t n, uint32_t npar, int bits, uint32_t *work,
+                int32_t *ctr, hipStream_t s, Prof *prof,
+                const uint32_t **n_inner) {
   const int passes = (bits + 7) / 8;
   const int64_t tiles = onesweep_tiles(n);
-  uint32_t *ctr = work, *glob = work + 4, *base = glob + k1sHistWords;
+  uint32_t *wctr = work, *glob = work + k1sCounters;
+  uint32_t *base = glob + k1sHistWords;
   uint32_t *status = base + k1sMaxPasses * 256;
-  // counters and histograms, then the status words of every pass
-  fill_i32((int32_t *)ctr, 0, 4 + k1sHistWords, s, prof);
+  uint32_t *sstat = status + (int64_t)k1sMaxPasses * tiles * 256;
+  uint32_t *ni = wctr + 5;
+  const int32_t *gate = ctr + C_ABORT;
+  *n_inner = ni;
+  fill_i32((int32_t *)wctr, 0, k1sCounters + k1sHistWords, s, prof);
   fill_i32((int32_t *)status, 0, (int64_t)passes * tiles * 256, s, prof);
-  // keys read once for all digits
-  PG_LAUNCH(prof, K_SORT_HIST, 4.0 * n, k_1s_hist, dim3((unsigned)tiles),
-            dim3(kBlock), 0, s, k0, n, passes, glob, gate);
+  fill_i32((int32_t *)sstat, 0, 2 * tiles, s, prof);
+  // the digit passes alternate between the pairs and end in pair 0 after
+  // an odd number of passes: the sink's children go straight to that pair
+  const int fin = (passes & 1) ? 0 : 1;
+  // keys read (4 B each); 8 B per inner child, 4 B per child of the sink
+  PG_LAUNCH_NI(prof, K_SORT_SPLIT, 4.0 * n, 4.0, 4.0, k_ps_split,
+               dim3((unsigned)tiles), dim3(kBlock), 0, s, k0, n, npar, k1,
+               v1, fin ? v1 : v0, sstat, wctr + 4, ni, ctr);
+  // the prefix's keys, read once for all digits
+  PG_LAUNCH_NI(prof, K_SORT_HIST, 0.0, 0.0, 4.0, k_1s_hist,
+               dim3((unsigned)tiles), dim3(kBlock), 0, s, k1, ni, passes,
+               glob, gate);
   PG_LAUNCH(prof, K_SCAN, 0.0, k_1s_base, dim3(1), dim3(kBlock), 0, s,
             glob, passes, base, gate);
-  int cur = 0;
+  int cur = 1;
   for (int p = 0; p < passes; ++p) {
-    uint32_t *ki = cur ? k1 : k0;
-    const uint32_t *vi =
-        cur ? v1 : ((index_values && p == 0) ? nullptr : v0);
+    uint32_t *ki = cur ? k1 : k0, *vi = cur ? v1 : v0;
     uint32_t *ko = cur ? k0 : k1, *vo = cur ? v0 : v1;
-    // keys and values read and written (16 B), 1 KiB of status per tile
-    PG_LAUNCH(prof, K_SORT_PASS, 16.0 * n + 1024.0 * tiles, k_1s_pass,
-              dim3((unsigned)tiles), dim3(kBlock), 0, s, ki, vi, ko, vo, n,
-              8 * p, base + p * 256, status + (int64_t)p * tiles * 256,
-              ctr + p, err, gate);
+    // keys and values read and written (16 B), 1 KiB of status per 4096
+    PG_LAUNCH_NI(prof, K_SORT_PASS, 0.0, 0.0, 16.25, k_1s_pass,
+                 dim3((unsigned)tiles), dim3(kBlock), 0, s, ki, vi, ko, vo,
+                 ni, 8 * p, base + p * 256, status + (int64_t)p * tiles * 256,
+                 wctr + p, ctr + C_ERR, gate);
     cur ^= 1;
   }
   return cur;

@@ -271,37 +271,52 @@ __global__ __launch_bounds__(kBlock) void k_root_round(
 // 2i+2 enters kids[i], 2i+3 leaves it.  A leaf is visited by element 2i+2
 // alone: the list skips 2i+3, which holds the leaf's parent.  Splitters sit
 // at even indices (multiples of the stride), so none is such a slot.
+// Sorted position i < nF as the parent sort leaves it: i < ni holds parent
+// skS[i] and signed-order position svS[i]; the rest are the sink's children,
+// their positions stored reversed at the top of svS.
+__device__ __forceinline__ uint32_t ps_key(const uint32_t *skS, int64_t i,
+                                           int64_t ni, int32_t N) {
+  return i < ni ? skS[i] : (uint32_t)N;
+}
+__device__ __forceinline__ uint32_t ps_val(const uint32_t *svS, int64_t i,
+                                           int64_t ni, int64_t nF) {
+  return svS[i < ni ? i : ni + nF - 1 - i];
+}
+
 __global__ __launch_bounds__(kBlock) void k_link_info(
     int32_t N, int32_t n_oddpri, const uint32_t *__restrict__ skS,
-    const uint32_t *__restrict__ svS, const int32_t *__restrict__ perm,
-    int32_t *kids, int32_t *pos, uint32_t *fh, int32_t *ctr) {
-  if (ctr[C_ABORT]) return;
-  const int32_t nF = ctr[C_NFIN];
+    const uint32_t *__restrict__ svS, const uint32_t *__restrict__ n_inner,
+    const int32_t *__restrict__ perm, int32_t *kids, int32_t *pos,
+    uint32_t *fh, int32_t *ctr) {
+  if (ctr[C_ABORT] || (ctr[C_ERR] & ERR_RANKCOUNT)) return;
+  const int64_t nF = ctr[C_NFIN], ni = *n_inner;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nF) return;
-  const uint32_t p = skS[i];
+  const uint32_t p = ps_key(skS, i, ni, N);
   if (p > (uint32_t)N) {  // finite count and sort keys disagree
     atomicOr(&ctr[C_ERR], ERR_RANKCOUNT);
     return;
   }
-  const uint32_t r = svS[i];
+  const uint32_t r = ps_val(svS, i, ni, nF);
   const int32_t c = perm ? perm[r] : (int32_t)r;
   kids[i] = c;
   pos[c] = (int32_t)i;
   // fh[p]: first child position + 1 and, in bit 31, whether the last child
   // has an even priority; the two parts come from different threads
-  if (i == 0 || skS[i - 1] != p) atomicOr(&fh[p], (uint32_t)(i + 1));
-  if ((i == nF - 1 || skS[i + 1] != p) && r >= (uint32_t)n_oddpri)
+  if (i == 0 || ps_key(skS, i - 1, ni, N) != p)
+    atomicOr(&fh[p], (uint32_t)(i + 1));
+  if ((i == nF - 1 || ps_key(skS, i + 1, ni, N) != p) &&
+      r >= (uint32_t)n_oddpri)
     atomicOr(&fh[p], 0x80000000u);
 }
 
 __global__ __launch_bounds__(kBlock) void k_link_build(
     int32_t N, int32_t n_oddpri, const uint32_t *__restrict__ skS,
-    const uint32_t *__restrict__ svS, const int32_t *__restrict__ kids,
-    const int32_t *__restrict__ pos, const uint32_t *__restrict__ fh,
-    int2 *elem, const int32_t *ctr) {
+    const uint32_t *__restrict__ svS, const uint32_t *__restrict__ n_inner,
+    const int32_t *__restrict__ kids, const int32_t *__restrict__ pos,
+    const uint32_t *__restrict__ fh, int2 *elem, const int32_t *ctr) {
   if (ctr[C_ABORT] || (ctr[C_ERR] & ERR_RANKCOUNT)) return;
-  const int32_t nF = ctr[C_NFIN];
+  const int64_t nF = ctr[C_NFIN], ni = *n_inner;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) {
     const uint32_t f = fh[N];
@@ -312,15 +327,16 @@ __global__ __launch_bounds__(kBlock) void k_link_build(
   }
   if (i >= nF) return;
   const int32_t c = kids[i];
-  const uint32_t p = skS[i];
-  const bool ev = svS[i] >= (uint32_t)n_oddpri;
-  const bool seg_start = (i == 0) || (skS[i - 1] != p);
-  const bool seg_end = (i == nF - 1) || (skS[i + 1] != p);
+  const uint32_t p = ps_key(skS, i, ni, N);
+  const bool ev = ps_val(svS, i, ni, nF) >= (uint32_t)n_oddpri;
+  const bool seg_start = (i == 0) || (ps_key(skS, i - 1, ni, N) != p);
+  const bool seg_end = (i == nF - 1) || (ps_key(skS, i + 1, ni, N) != p);
   const uint32_t f = fh[c];
   const int32_t fc = (int32_t)(f & 0x7fffffffu) - 1;
   // c is the parent's first even child: the parent's in-order point comes
   // just before c's subtree
-  const bool wd = ev && (seg_start || svS[i - 1] < (uint32_t)n_oddpri);
+  const bool wd = ev && (seg_start || ps_val(svS, i - 1, ni, nF) <
+                                          (uint32_t)n_oddpri);
   // after c's subtree: the next sibling, else leave the parent
   int32_t nx;
   if (!seg_end) nx = (int32_t)(2 * i + 4);
@@ -612,6 +628,7 @@ static pg_status read_ctr(pg_game *g, hipStream_t s) {
   PG_HIP(hipStreamSynchronize(s));
   if (g->prof.on) {
     g->prof.nf = (double)g->hctr[C_NFIN];
+    g->prof.ni = (double)g->hctr[C_NINNER];
     g->prof.flush();
   }
   return PG_OK;
@@ -726,25 +743,26 @@ static pg_status careful_walks(pg_game *g, hipStream_t s) {
 static void enqueue_rank(pg_game *g, hipStream_t s) {
   const int32_t N = (int32_t)g->n_aug;
   Prof *pf = &g->prof;
-  const int32_t *gate = g->ctr + C_ABORT;
-  // the root walks wrote the keys in signed-priority order; the values are
-  // the positions in that order
-  const int which = radix_sort_1s(g->sk0, g->sv0, g->sk1, g->sv1, N,
-                                  g->sort_bits, g->rs1, g->ctr + C_ERR, s, pf,
-                                  gate, true);
+  // the root walks wrote the keys in signed-priority order (the sort's
+  // values are the positions in that order); sizes past the sort are only
+  // known on the device: grids are sized for N
+  const uint32_t *n_inner = nullptr;
+  const int which = parent_sort(g->sk0, g->sv0, g->sk1, g->sv1, N,
+                                (uint32_t)N, g->sort_bits, g->rs1, g->ctr, s,
+                                pf, &n_inner);
   const uint32_t *skS = which ? g->sk1 : g->sk0;
   const uint32_t *svS = which ? g->sv1 : g->sv0;
-  // the finite count is only known on the device: size grids for N
-  // keys, values 8 (+ perm 4 unless relabeled); kids, pos 8; fh at
-  // segment ends
+  // values 4 (+ perm 4 unless relabeled); kids, pos 8; fh at segment ends
+  // about 2; keys 4 per inner child
   const int32_t *perm = kernel_perm(g);
-  PG_LAUNCH_NF(pf, K_LINK_INFO, perm ? 22.0 : 18.0, k_link_info,
+  PG_LAUNCH_NI(pf, K_LINK_INFO, 0.0, perm ? 18.0 : 14.0, 4.0, k_link_info,
                dim3(grid_for(N)), dim3(kBlock), 0, s, N, g->n_oddpri, skS, svS,
-               perm, g->kids, g->pos, g->fh, g->ctr);
-  // keys, values, kids 12; fh 4; two elements 16; pos at segment ends
-  PG_LAUNCH_NF(pf, K_LINK_BUILD, 34.0, k_link_build, dim3(grid_for(N)),
-               dim3(kBlock), 0, s, N, g->n_oddpri, skS, svS, g->kids,
-               g->pos, g->fh, g->elem, g->ctr);
+               n_inner, perm, g->kids, g->pos, g->fh, g->ctr);
+  // values, kids 8; fh 4; two elements 16; pos at segment ends about 2;
+  // keys 4 per inner child
+  PG_LAUNCH_NI(pf, K_LINK_BUILD, 0.0, 30.0, 4.0, k_link_build,
+               dim3(grid_for(N)), dim3(kBlock), 0, s, N, g->n_oddpri, skS, svS,
+               n_inner, g->kids, g->pos, g->fh, g->elem, g->ctr);
   const int nl = g->nlevels;
   const int64_t Lmax = 2 * (int64_t)N + 2;
   const int64_t ns1 = level_size(Lmax, 1);
