@@ -27,8 +27,11 @@ Workloads (seeded, synthetic; see paper_1705_02313_amd/synth.py):
 Printed: one JSON line with the driver's fields plus "roofline" (the kernel
 that takes the most time, its algorithmic bytes over its event-timed
 duration against 8 TB/s, from up to two profiled steps run after the timed
-steps) and "cpu_baseline" (the CPU oracle timed on this host on a bounded
-sample of the same workload).  --best-response picks the best responses
+steps), "iteration_roofline" (every kernel's algorithmic bytes per
+best-response iteration over the iteration's unprofiled time, against the
+same peak, with the counter bytes when they are current) and
+"cpu_baseline" (the CPU oracle timed on this host on a bounded sample of
+the same workload).  --best-response picks the best responses
 (section 6's comparison: SI, SI-Reset, Bellman-Ford on count games).
 """
 from __future__ import annotations
@@ -343,6 +346,7 @@ def main():
     # more on small games), so the timed steps above run without it and the
     # kernel table comes from profiled steps of the same job right after.
     roof = None
+    iteration_roof = None
     kernels = {}
     prof_steps = 0
     if not args.no_profile:
@@ -371,6 +375,25 @@ def main():
                 "traffic": counter_traffic(args.workload, dom),
                 "measured_over": f"{prof_steps} profiled steps of the same "
                                  "job after the timed steps"}
+        # The whole best-response iteration against the same peak: every
+        # kernel's algorithmic bytes per iteration over the unprofiled time
+        # of an iteration (host time between launches included), and the
+        # counter bytes where every kernel kind has them.
+        it_bytes = sum(a["bytes"] for a in agg.values()) / (prof_steps * nval)
+        it_s = statistics.median(r["solve"] for r in runs) / nval
+        traffic = {k: counter_traffic(args.workload, k) for k in agg}
+        it_traffic = None
+        if all(v is not None for v in traffic.values()):
+            it_traffic = sum(traffic[k] * agg[k]["calls"] for k in agg) / (
+                prof_steps * nval)
+        iteration_roof = {
+            "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
+            "alg_bytes": round(it_bytes),
+            "achieved": round(it_bytes / it_s / 1e9, 1),
+            "frac": round(it_bytes / it_s / 1e9 / HBM_PEAK_GBS, 4),
+            "traffic": round(it_traffic) if it_traffic else None,
+            "traffic_GBps": (round(it_traffic / it_s / 1e9, 1)
+                             if it_traffic else None)}
 
     line = {
         "metric": "edges/s per best-response iteration",
@@ -400,6 +423,7 @@ def main():
         "w_even": int((win == 0).sum()),
         "event_ms_total": ev0.elapsed_time(ev1),
         "roofline": roof,
+        "iteration_roofline": iteration_roof,
         "kernels": kernels,
     }
     if not args.no_cpu_baseline:

@@ -530,15 +530,12 @@ pg_status alloc_state(pg_game *g, int64_t cap) {
   fill_i32(g->pos, 0, N + 1, 0);
   PG_TRY(dev_alloc(&g->elem, 2 * N + 2));
   // sublist levels for the longest possible Euler list
-  int64_t size = 2 * N + 2;
-  for (int k = 0; k < 7; ++k) {
-    const int stride = 32;
-    const int64_t ns = (size + stride - 1) / stride;
+  for (int k = 0; k < 8; ++k) {
+    const int64_t ns = level_size(2 * N + 2, k + 1);
     PG_TRY(dev_alloc(&g->lv[k].sum, ns));
     PG_TRY(dev_alloc(&g->lv[k].next, ns));
     PG_TRY(dev_alloc(&g->lv[k].base, ns));
-    size = ns;
-    if (size <= 1) break;
+    if (ns <= 1) break;
   }
   return PG_OK;
 }

@@ -276,11 +276,18 @@ __device__ __forceinline__ void st_relaxed(int32_t *p, int32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-constexpr int kStride = 32;        // splitter stride at every level
+// Splitter strides of the sublist ranking: the Euler list (level 0) is walked
+// by many threads at once and is bound by its loads; the reduced lists are
+// short, and a level's time is its longest sublist walk (sublist lengths are
+// about geometric, so the longest is near stride x ln(sublists)): there a
+// small stride wins
+constexpr int kStride = 32;        // level 0 -> 1
+constexpr int kStrideUp = 8;       // level k -> k + 1 for k >= 1
 
 // size of level k of the sublist ranking for an Euler list of L elements
 __device__ __host__ __forceinline__ int64_t level_size(int64_t L, int k) {
-  for (int j = 0; j < k; ++j) L = (L + kStride - 1) / kStride;
+  if (k >= 1) L = (L + kStride - 1) / kStride;
+  for (int j = 1; j < k; ++j) L = (L + kStrideUp - 1) / kStrideUp;
   return L;
 }
 

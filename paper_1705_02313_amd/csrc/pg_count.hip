@@ -250,7 +250,7 @@ __global__ __launch_bounds__(kBlock) void k_vlr_sumk(
   const int64_t nsplit = level_size(L, level + 1);
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= nsplit) return;
-  int64_t e = j * kStride;
+  int64_t e = j * kStrideUp;
   int32_t acc[D] = {};
   int64_t steps = 0;
   for (;;) {
@@ -259,7 +259,7 @@ __global__ __launch_bounds__(kBlock) void k_vlr_sumk(
 #pragma unroll
     for (int i = 0; i < D; ++i) acc[i] += w[i];
     e = lnext[e];
-    if (e < 0 || e % kStride == 0) break;
+    if (e < 0 || e % kStrideUp == 0) break;
     if (++steps > size) {
       atomicOr(&ctr[C_ERR], ERR_LISTWALK);
       e = -1;
@@ -267,7 +267,7 @@ __global__ __launch_bounds__(kBlock) void k_vlr_sumk(
     }
   }
   store_vec<D>(vsum + j * D, acc);
-  next[j] = e < 0 ? -1 : (int32_t)(e / kStride);
+  next[j] = e < 0 ? -1 : (int32_t)(e / kStrideUp);
 }
 
 // The top level (at most vtop_max(D) nodes, head = 0) in one block: suffix
@@ -339,7 +339,7 @@ __global__ __launch_bounds__(kBlock) void k_vlr_distk(
   const int64_t nsplit = level_size(L, level + 1);
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= nsplit) return;
-  int64_t e = j * kStride;
+  int64_t e = j * kStrideUp;
   int32_t b[D];
   load_vec<D>(sbase + j * D, b);
   for (int64_t steps = 0; steps <= size; ++steps) {
@@ -349,7 +349,7 @@ __global__ __launch_bounds__(kBlock) void k_vlr_distk(
 #pragma unroll
     for (int i = 0; i < D; ++i) b[i] += w[i];
     e = lnext[e];
-    if (e < 0 || e % kStride == 0) break;
+    if (e < 0 || e % kStrideUp == 0) break;
   }
 }
 
@@ -681,13 +681,11 @@ pg_status count_setup(pg_game *g, hipStream_t s) {
   fill_i32(g->cnt, 0, (N + 1) * g->dw, s);
   PG_TRY(dev_alloc(&g->cnt2, (N + 1) * g->dw));
   fill_i32(g->cnt2, 0, (N + 1) * g->dw, s);
-  int64_t size = 2 * N + 1;
   for (int k = 0; k < 8; ++k) {
-    const int64_t ns = (size + kStride - 1) / kStride;
+    const int64_t ns = level_size(2 * N + 1, k + 1);
     PG_TRY(dev_alloc(&g->vsum[k], ns * g->dw));
     PG_TRY(dev_alloc(&g->vbase[k], ns * g->dw));
-    size = ns;
-    if (size <= 1) break;
+    if (ns <= 1) break;
   }
   PG_HIP(hipStreamSynchronize(s));
   return PG_OK;

@@ -400,13 +400,13 @@ __global__ __launch_bounds__(kBlock) void k_lr_sumk(
   const int64_t nsplit = level_size(L, level + 1);
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= nsplit) return;
-  int64_t e = j * kStride;
+  int64_t e = j * kStrideUp;
   int32_t acc = 0;
   int64_t steps = 0;
   for (;;) {
     acc += lw[e];
     e = lnext[e];
-    if (e < 0 || e % kStride == 0) break;
+    if (e < 0 || e % kStrideUp == 0) break;
     if (++steps > size) {
       atomicOr(&ctr[C_ERR], ERR_LISTWALK);
       e = -1;
@@ -414,7 +414,7 @@ __global__ __launch_bounds__(kBlock) void k_lr_sumk(
     }
   }
   sum[j] = acc;
-  next[j] = e < 0 ? -1 : (int32_t)(e / kStride);
+  next[j] = e < 0 ? -1 : (int32_t)(e / kStrideUp);
 }
 
 // Ranks the top list (at most kTopMax elements, head = 0) inside one block
@@ -478,13 +478,13 @@ __global__ __launch_bounds__(kBlock) void k_lr_distk(
   const int64_t nsplit = level_size(L, level + 1);
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= nsplit) return;
-  int64_t e = j * kStride;
+  int64_t e = j * kStrideUp;
   int32_t b = sbase[j];
   for (int64_t steps = 0; steps <= size; ++steps) {
     lbase[e] = b;
     b += lw[e];
     e = lnext[e];
-    if (e < 0 || e % kStride == 0) break;
+    if (e < 0 || e % kStrideUp == 0) break;
   }
 }
 
