@@ -772,13 +772,13 @@ static void enqueue_count_switch_t(pg_game *g, bool odd, hipStream_t s) {
   const int32_t N = (int32_t)g->n_aug;
   Prof *pf = &g->prof;
   fill_i32(g->ctr + C_DIST_SW, 0, kDistSlots * kDistStride, s, pf);
-  // per vertex: id 4, two offsets 16, current choice 8 and its row; per
-  // edge: target 4, its top flag 1 and its count row 4 D
+  // per vertex: id 4, two offsets 16, current choice 8 (its row is one of
+  // the row's); per edge: target 4, its top flag 1 and its count row 4 D
   if (odd) {
     const int64_t cnt = g->n_odd;
     if (cnt > 0)
       PG_LAUNCH(pf, K_ODD_SWITCH,
-                (28.0 + 4.0 * D) * cnt + (5.0 + 4.0 * D) * g->m_odd,
+                28.0 * cnt + (5.0 + 4.0 * D) * g->m_odd,
                 k_cnt_odd_switch<D>, dim3(grid_for(cnt)), dim3(kBlock), 0, s,
                 N, cnt, g->odd_ids, g->off, g->tgt, g->cnt,
                 g->odd_cols, g->pri, g->sp, g->ctr);
@@ -786,7 +786,7 @@ static void enqueue_count_switch_t(pg_game *g, bool odd, hipStream_t s) {
     const int64_t cnt = N - g->n_odd;
     if (cnt > 0)
       PG_LAUNCH(pf, K_EVEN_SWITCH,
-                (28.0 + 4.0 * D) * cnt +
+                28.0 * cnt +
                     (5.0 + 4.0 * D) * (g->m_aug - g->m_odd),
                 k_cnt_even_switch<D>, dim3(grid_for(cnt)), dim3(kBlock), 0, s,
                 N, cnt, g->even_ids, g->off, g->tgt, g->cnt,

@@ -802,12 +802,10 @@ static void enqueue_rank(pg_game *g, hipStream_t s) {
 static void enqueue_switch(pg_game *g, bool odd, hipStream_t s) {
   const int32_t N = (int32_t)g->n_aug;
   Prof *pf = &g->prof;
-  // offsets (8 B per row) and owners for every vertex; for the player's own
-  // rows the targets and the key of each target (8 B per edge), the current
-  // choice and its key (12 B per vertex)
   fill_i32(g->ctr + C_DIST_SW, 0, kDistSlots * kDistStride, s, pf);
   // per vertex: id 4, two offsets 16, current choice 8 (read and write
-  // counted once) and its key 4 -> 28; per edge: target 4 and its key 4
+  // counted once; its key is one of the row's) -> 28; per edge: target 4
+  // and its key 4
   if (odd) {
     const int64_t cnt = g->n_odd;
     if (cnt > 0)
