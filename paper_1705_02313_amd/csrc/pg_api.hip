@@ -740,12 +740,12 @@ pg_status load_modified(int64_t n, int64_t m, const void *offsets,
 // Rebuilds a game of N vertices and M edges with vertex i taken from vertex
 // from[i] and targets mapped by `to` (see k_relabel_vertices).  The new
 // arrays are allocated; the old ones are left to the caller.
-static pg_status relabel_game(const int64_t *off, const int32_t *tgt,
-                              const uint8_t *owner, const int32_t *pri,
-                              const int32_t *from, const int32_t *to,
-                              int64_t N, int64_t M, int64_t **off2,
-                              int32_t **tgt2, uint8_t **owner2,
-                              int32_t **pri2, hipStream_t s) {
+pg_status relabel_game(const int64_t *off, const int32_t *tgt,
+                       const uint8_t *owner, const int32_t *pri,
+                       const int32_t *from, const int32_t *to,
+                       int64_t N, int64_t M, int64_t **off2,
+                       int32_t **tgt2, uint8_t **owner2,
+                       int32_t **pri2, hipStream_t s) {
   PG_TRY(dev_alloc(off2, N + 1));
   PG_TRY(dev_alloc(tgt2, M));
   PG_TRY(dev_alloc(owner2, N));

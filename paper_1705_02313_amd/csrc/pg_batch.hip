@@ -37,29 +37,47 @@
 namespace pgk {
 
 struct GameDesc {
+  // the game in its own signed-priority order (local id = position)
   const int64_t *off;
   const int32_t *tgt;
   const uint8_t *owner;
   const int32_t *pri;
-  int2 *saved;        // [n_aug] strategies in the game's own ids
+  int2 *saved;        // [n_aug] strategies in local ids
   uint8_t *res_winner;
   int32_t *res_sigma, *res_tau;
-  const int32_t *rvperm;  // [n_aug] the game's vertices in signed order
-  const int32_t *rvrank;  // [n_aug] position of each vertex in that order
-  int64_t vb, eb;     // first arena vertex / edge
-  int64_t odd_pos;    // arena position of the game's first odd-priority vertex
-  int64_t even_pos;   // arena position of its first even-priority vertex
+  const int32_t *rvperm;  // [n_aug] local id -> the caller's vertex id
+  int64_t odd_pos;    // arena id of the game's first odd-priority vertex
+  int64_t even_pos;   // arena id of its first even-priority vertex
+  int64_t odd_eb;     // arena edge of the first row of its odd part
+  int64_t even_eb;    // arena edge of the first row of its even part
+  int64_t e_split;    // local edge of the first row of its even part
   int32_t n_aug, n_orig;
   int64_t m_aug;
-  int32_t n_oddpri;   // vertices of odd priority
+  int32_t n_oddpri;   // vertices of odd priority (local ids 0..n_oddpri-1)
   int32_t poff;       // priority offset (even)
   int32_t init;       // 1: start from the initial strategies
 };
 
-// index of the game whose range [start[s], start[s+1]) holds x
-__device__ __forceinline__ int find_game(const int64_t *start, int G,
-                                         int64_t x) {
-  int lo = 0, hi = G - 1;
+// Arena ids are positions in the arena's signed-priority order: the games'
+// odd-priority parts in decreasing slot order (higher slots hold the larger
+// priorities), then their even parts in increasing slot order; each part is
+// a run of the game's local ids.  Rows follow in the same order, so the
+// arena is one CSR made of 2 G segments.
+__device__ __forceinline__ int32_t to_arena(const GameDesc &g, int32_t t) {
+  return (int32_t)(t < g.n_oddpri ? g.odd_pos + t
+                                  : g.even_pos + (t - g.n_oddpri));
+}
+__device__ __forceinline__ int32_t to_local(const GameDesc &g, int64_t x,
+                                            int64_t odd_total) {
+  return (int32_t)(x < odd_total ? x - g.odd_pos
+                                 : g.n_oddpri + (x - g.even_pos));
+}
+
+// index of the segment whose range [start[j], start[j+1]) holds x (empty
+// segments share their start with the next one and are never returned)
+__device__ __forceinline__ int find_seg(const int64_t *start, int S,
+                                        int64_t x) {
+  int lo = 0, hi = S - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
     if (start[mid] <= x) lo = mid;
@@ -68,49 +86,38 @@ __device__ __forceinline__ int find_game(const int64_t *start, int G,
   return lo;
 }
 
+// segment j < G: the odd part of slot G - 1 - j; else the even part of j - G
+__device__ __forceinline__ int seg_game(int j, int G, bool *odd) {
+  *odd = j < G;
+  return j < G ? G - 1 - j : j - G;
+}
+
 __global__ void k_arena_vertices(const GameDesc *__restrict__ d,
                                   const int64_t *__restrict__ vstart, int G,
                                   int32_t N, int64_t M, int64_t *off,
                                   uint8_t *owner, int32_t *pri, int32_t *gid,
-                                  int32_t *rvpos, uint32_t *oddf, int2 *sp) {
+                                  uint32_t *oddf, int2 *sp) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v == 0) off[N] = M;
   if (v >= N) return;
-  const int s = find_game(vstart, G, v);
+  bool oddp;
+  const int s = seg_game(find_seg(vstart, 2 * G, v), G, &oddp);
   const GameDesc &g = d[s];
-  const int64_t lv = v - g.vb;
-  off[v] = g.eb + g.off[lv];
+  const int64_t lv = oddp ? v - g.odd_pos : g.n_oddpri + (v - g.even_pos);
+  off[v] = (oddp ? g.odd_eb : g.even_eb - g.e_split) + g.off[lv];
   const uint8_t ow = g.owner[lv];
   owner[v] = ow;
   oddf[v] = ow == 1;
   pri[v] = g.pri[lv] + g.poff;
   gid[v] = s;
-  const int32_t r = g.rvrank[lv];
-  rvpos[v] = (int32_t)(r < g.n_oddpri ? g.odd_pos + r
-                                      : g.even_pos + (r - g.n_oddpri));
   int32_t x;
   if (g.init) {
-    x = g.owner[lv] ? (int32_t)(g.vb + g.tgt[g.off[lv]]) : N;
+    x = ow ? to_arena(g, g.tgt[g.off[lv]]) : N;
   } else {
     const int32_t l = g.saved[lv].x;
-    x = (l == g.n_aug) ? N : (int32_t)(g.vb + l);
+    x = (l == g.n_aug) ? N : to_arena(g, l);
   }
   sp[v].x = x;
-}
-
-// The arena's signed-priority order by position: odd positions come from the
-// games in decreasing slot order, even positions in increasing slot order
-// (pstart: the first position of each segment, in position order).
-__global__ void k_arena_perm(const GameDesc *__restrict__ d,
-                             const int64_t *__restrict__ pstart, int G,
-                             int32_t N, int32_t *perm) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  const int j = find_game(pstart, 2 * G, i);
-  const int s = j < G ? G - 1 - j : j - G;
-  const GameDesc &g = d[s];
-  const int64_t r = j < G ? i - g.odd_pos : g.n_oddpri + (i - g.even_pos);
-  perm[i] = (int32_t)(g.vb + g.rvperm[r]);
 }
 
 __global__ void k_arena_edges(const GameDesc *__restrict__ d,
@@ -118,8 +125,11 @@ __global__ void k_arena_edges(const GameDesc *__restrict__ d,
                               int64_t M, int32_t *tgt) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= M) return;
-  const int s = find_game(estart, G, e);
-  tgt[e] = (int32_t)(d[s].vb + d[s].tgt[e - d[s].eb]);
+  bool oddp;
+  const int s = seg_game(find_seg(estart, 2 * G, e), G, &oddp);
+  const GameDesc &g = d[s];
+  const int64_t le = oddp ? e - g.odd_eb : g.e_split + (e - g.even_eb);
+  tgt[e] = to_arena(g, g.tgt[le]);
 }
 
 // the priority of each vertex's successor (second half of sp)
@@ -131,36 +141,45 @@ __global__ void k_arena_sp_pri(const int32_t *pri, int2 *sp, int32_t N) {
   sp[v].y = (x == N) ? 2147483647 : pri[x];
 }
 
-// strategies of the arena back into each live game's own ids
+// strategies of the arena back into each live game's local ids
 __global__ void k_arena_save(const GameDesc *__restrict__ d,
                              const int32_t *__restrict__ gid, const int2 *sp,
-                             int32_t N) {
+                             int32_t N, int64_t odd_total) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= N) return;
   const GameDesc &g = d[gid[v]];
   const int32_t x = sp[v].x;
-  g.saved[v - g.vb].x = (x == N) ? g.n_aug : (int32_t)(x - g.vb);
+  g.saved[to_local(g, v, odd_total)].x =
+      (x == N) ? g.n_aug : to_local(g, x, odd_total);
 }
 
-// results of the games that finished in this step (Theorem 1: W_Even is the
-// set of top keys)
+// results of the games that finished in this step, in the caller's ids
+// (Theorem 1: W_Even is the set of top keys)
 __global__ void k_arena_export(const GameDesc *__restrict__ d,
                                const int32_t *__restrict__ gid,
                                const uint8_t *__restrict__ newly_done,
                                const int2 *sp, const int32_t *key,
-                               const uint8_t *owner, int32_t N) {
+                               const uint8_t *owner, int32_t N,
+                               int64_t odd_total) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= N) return;
   const int s = gid[v];
   if (!newly_done[s]) return;
   const GameDesc &g = d[s];
-  const int64_t lv = v - g.vb;
+  const int32_t c = g.rvperm[to_local(g, v, odd_total)];
   const int32_t x = sp[v].x;
-  const int32_t lx = (x == N) ? PG_SINK : (int32_t)(x - g.vb);
+  const int32_t cx =
+      (x == N) ? PG_SINK : g.rvperm[to_local(g, x, odd_total)];
   const bool even = owner[v] == 0;
-  g.res_sigma[lv] = even ? lx : PG_SINK;
-  g.res_tau[lv] = even ? PG_SINK : lx;
-  if (lv < g.n_orig) g.res_winner[lv] = key[v] == PG_KEY_TOP ? 0 : 1;
+  g.res_sigma[c] = even ? cx : PG_SINK;
+  g.res_tau[c] = even ? PG_SINK : cx;
+  if (c < g.n_orig) g.res_winner[c] = key[v] == PG_KEY_TOP ? 0 : 1;
+}
+
+// first edge of the even-priority rows of a game stored in signed order
+__global__ void k_part_edge(const int64_t *off, const int32_t *ctr,
+                            int64_t *out) {
+  out[0] = off[ctr[C_MISC]];
 }
 
 // Odd vertices of a game (into the distributed counter C_DIST_NF)
@@ -201,8 +220,11 @@ __global__ __launch_bounds__(kBlock) void k_batch_odd(
     s = gid[v];
     if (run[s]) {
       const int64_t e0 = off[v], e1 = off[v + 1];
+      // the current choice's key comes with the row's gathers when it is in
+      // the row (it always is in a batch: strategies start from the rows)
       const int32_t cur = sp[v].x;
-      const int32_t kc = key[cur];
+      int32_t kc = 0;
+      bool have_kc = false;
       int32_t best = -1, kb = 0;
       for (int64_t b = e0; b < e1; b += kRowBatchB) {
         int32_t u[kRowBatchB], k[kRowBatchB];
@@ -212,9 +234,12 @@ __global__ __launch_bounds__(kBlock) void k_batch_odd(
 #pragma unroll
         for (int j = 0; j < kRowBatchB; ++j) k[j] = (u[j] >= 0) ? key[u[j]] : 0;
 #pragma unroll
-        for (int j = 0; j < kRowBatchB; ++j)
+        for (int j = 0; j < kRowBatchB; ++j) {
           if (u[j] >= 0 && (best < 0 || k[j] < kb)) { kb = k[j]; best = u[j]; }
+          if (u[j] == cur) { kc = k[j]; have_kc = true; }
+        }
       }
+      if (!have_kc) kc = key[cur];
       if (kb < kc) {
         sp[v] = make_int2(best, pri[best]);
         sw = true;
@@ -238,9 +263,11 @@ __global__ __launch_bounds__(kBlock) void k_batch_even(
     s = gid[v];
     if (pending[s]) {
       const int64_t e0 = off[v], e1 = off[v + 1];
+      // the current choice is the sink or in the row (see k_batch_odd)
       const int32_t cur = sp[v].x;
-      const int32_t kc = key[cur];
       int32_t best = N, kb = key[N];
+      int32_t kc = kb;
+      bool have_kc = cur == N;
       for (int64_t b = e0; b < e1; b += kRowBatchB) {
         int32_t u[kRowBatchB], k[kRowBatchB];
 #pragma unroll
@@ -249,9 +276,12 @@ __global__ __launch_bounds__(kBlock) void k_batch_even(
 #pragma unroll
         for (int j = 0; j < kRowBatchB; ++j) k[j] = (u[j] >= 0) ? key[u[j]] : 0;
 #pragma unroll
-        for (int j = 0; j < kRowBatchB; ++j)
+        for (int j = 0; j < kRowBatchB; ++j) {
           if (u[j] >= 0 && k[j] > kb) { kb = k[j]; best = u[j]; }
+          if (u[j] == cur) { kc = k[j]; have_kc = true; }
+        }
       }
+      if (!have_kc) kc = key[cur];
       if (kb > kc) {
         sp[v] = make_int2(best, best == N ? 2147483647 : pri[best]);
         sw = true;
@@ -318,8 +348,11 @@ struct BGame {
   int2 *saved = nullptr;
   uint8_t *res_winner = nullptr;
   int32_t *res_sigma = nullptr, *res_tau = nullptr;
-  int32_t *rvperm = nullptr, *rvrank = nullptr;  // the game's signed order
+  // the game's signed order: position -> the caller's id, and back (the
+  // game is stored in that order from submission on)
+  int32_t *rvperm = nullptr, *rvrank = nullptr;
   int64_t n_oddpri = 0, n_odd = 0, m_odd = 0;
+  int64_t e_split = 0;      // first edge of the even-priority rows
   pg_stats st{};
   bool in_arena = false;    // still occupies arena vertices
   bool polled = false;      // results handed out; free once out of the arena
@@ -355,8 +388,9 @@ struct pg_batch {
   int64_t done_vertices = 0;       // arena vertices of finished games
   // per-slot device state
   GameDesc *d_desc = nullptr;
-  int64_t *d_vstart = nullptr, *d_estart = nullptr;
-  int64_t *d_pstart = nullptr;     // [2 G] signed-order segment starts
+  // [2 G] first arena vertex / edge of each segment (odd parts by
+  // decreasing slot, then even parts by increasing slot)
+  int64_t *d_pstart = nullptr, *d_estart = nullptr;
   int32_t *d_gid = nullptr;
   uint8_t *d_run = nullptr, *d_pending = nullptr, *d_newly = nullptr;
   int32_t *d_cnt_odd = nullptr, *d_cnt_even = nullptr;
@@ -365,7 +399,7 @@ struct pg_batch {
   int32_t *d_i32 = nullptr;        // scratch
   // host mirrors and staging
   std::vector<GameDesc> h_desc;
-  std::vector<int64_t> h_vstart, h_estart, h_pstart;
+  std::vector<int64_t> h_pstart, h_estart;
   std::vector<uint8_t> h_newly;
   std::vector<int32_t> h_nval, h_nmaj;
   std::vector<int64_t> h_sw_odd, h_sw_even;
@@ -378,6 +412,7 @@ pg_status batch_alloc(pg_batch *b) {
   if (!a) return pg_fail(PG_ENOMEM, "host allocation failed");
   b->arena = a;
   a->device = b->device;
+  a->relabeled = true;   // arena ids are signed-order positions
   PG_HIP(hipHostMalloc((void **)&a->hctr, sizeof(int32_t) * C_COUNT,
                        hipHostMallocDefault));
   PG_TRY(dev_alloc(&a->ctr, C_TOTAL));
@@ -388,8 +423,7 @@ pg_status batch_alloc(pg_batch *b) {
   PG_TRY(alloc_state(a, b->cap_v));
   const int G = b->max_games;
   PG_TRY(dev_alloc(&b->d_desc, G));
-  PG_TRY(dev_alloc(&b->d_vstart, G));
-  PG_TRY(dev_alloc(&b->d_estart, G));
+  PG_TRY(dev_alloc(&b->d_estart, 2 * (int64_t)G));
   PG_TRY(dev_alloc(&b->d_pstart, 2 * (int64_t)G));
   PG_TRY(dev_alloc(&b->d_gid, b->cap_v));
   PG_TRY(dev_alloc(&b->d_run, G));
@@ -419,7 +453,7 @@ void batch_release(pg_batch *b) {
   }
   b->pool.clear();
   free_game(b->arena);
-  void *ptrs[] = {b->d_desc,    b->d_vstart,  b->d_estart,  b->d_pstart,
+  void *ptrs[] = {b->d_desc,    b->d_estart,  b->d_pstart,
                   b->d_gid,
                   b->d_run,     b->d_pending, b->d_newly,   b->d_cnt_odd,
                   b->d_cnt_even, b->d_nval,   b->d_nmaj,    b->d_sw_odd,
@@ -444,7 +478,8 @@ pg_status rebuild(pg_batch *b, bool *built_any) {
   // save strategies of games still running
   if (!b->built.empty() && a->n_aug > 0)
     hipLaunchKernelGGL(k_arena_save, dim3(grid_for(a->n_aug)), dim3(kBlock), 0,
-                       s, b->d_desc, b->d_gid, a->sp, (int32_t)a->n_aug);
+                       s, b->d_desc, b->d_gid, a->sp, (int32_t)a->n_aug,
+                       (int64_t)a->n_oddpri);
   std::vector<BGame *> next;
   int64_t nv = 0, ne = 0;
   for (BGame *g : b->built)
@@ -474,20 +509,17 @@ pg_status rebuild(pg_batch *b, bool *built_any) {
   // host staging that lives until the copies below have run (the next
   // synchronisation of the stream happens at the end of the step)
   b->h_desc.resize(G);
-  b->h_vstart.resize(G);
-  b->h_estart.resize(G);
   b->h_pstart.resize(2 * (size_t)G);
+  b->h_estart.resize(2 * (size_t)G);
   b->h_nval.assign(G, 0);
   b->h_nmaj.assign(G, 0);
   b->h_sw_odd.assign(G, 0);
   b->h_sw_even.assign(G, 0);
-  int64_t odd_total = 0, n_odd = 0, m_odd = 0;
+  int64_t n_odd = 0, m_odd = 0, poff = 0;
   for (BGame *g : next) {
-    odd_total += g->n_oddpri;
     n_odd += g->n_odd;
     m_odd += g->m_odd;
   }
-  int64_t vb = 0, eb = 0, poff = 0, even_pos = odd_total;
   for (int i = 0; i < G; ++i) {
     BGame *g = next[i];
     GameDesc &d = b->h_desc[i];
@@ -500,25 +532,17 @@ pg_status rebuild(pg_batch *b, bool *built_any) {
     d.res_sigma = g->res_sigma;
     d.res_tau = g->res_tau;
     d.rvperm = g->rvperm;
-    d.rvrank = g->rvrank;
-    d.vb = vb;
-    d.eb = eb;
+    d.e_split = g->e_split;
     d.n_aug = (int32_t)g->g->n_aug;
     d.n_orig = (int32_t)g->g->n;
     d.m_aug = g->g->m_aug;
     d.n_oddpri = (int32_t)g->n_oddpri;
     d.poff = (int32_t)poff;
     d.init = g->started ? 0 : 1;
-    d.even_pos = even_pos;
-    even_pos += g->g->n_aug - g->n_oddpri;
-    b->h_vstart[i] = vb;
-    b->h_estart[i] = eb;
     b->h_nval[i] = (int32_t)g->st.n_valuations;
     b->h_nmaj[i] = (int32_t)g->st.n_major;
     b->h_sw_odd[i] = g->st.n_odd_switches;
     b->h_sw_even[i] = g->st.n_even_switches;
-    vb += g->g->n_aug;
-    eb += g->g->m_aug;
     poff += (int64_t)g->maxpri + 1;
     poff += poff & 1;
     if (poff > 2000000000LL)
@@ -527,15 +551,30 @@ pg_status rebuild(pg_batch *b, bool *built_any) {
     g->started = true;
     g->in_arena = true;
   }
-  // odd-priority parts in decreasing slot order (higher slots hold the
-  // larger priorities, which come first), then the even parts
-  int64_t odd_pos = 0;
-  for (int i = G - 1; i >= 0; --i) {
-    b->h_desc[i].odd_pos = odd_pos;
-    b->h_pstart[G - 1 - i] = odd_pos;
-    odd_pos += next[i]->n_oddpri;
+  // the 2 G segments in arena order: odd parts by decreasing slot (higher
+  // slots hold the larger priorities, which come first), then even parts
+  int64_t vb = 0, eb = 0;
+  for (int j = 0; j < 2 * G; ++j) {
+    const bool oddp = j < G;
+    const int i = oddp ? G - 1 - j : j - G;
+    BGame *g = next[i];
+    GameDesc &d = b->h_desc[i];
+    b->h_pstart[j] = vb;
+    b->h_estart[j] = eb;
+    if (oddp) {
+      d.odd_pos = vb;
+      d.odd_eb = eb;
+      vb += g->n_oddpri;
+      eb += g->e_split;
+    } else {
+      d.even_pos = vb;
+      d.even_eb = eb;
+      vb += g->g->n_aug - g->n_oddpri;
+      eb += g->g->m_aug - g->e_split;
+    }
   }
-  for (int i = 0; i < G; ++i) b->h_pstart[G + i] = b->h_desc[i].even_pos;
+  int64_t odd_total = 0;
+  for (BGame *g : next) odd_total += g->n_oddpri;
   b->built = next;
   b->done_vertices = 0;
   *built_any = G > 0;
@@ -544,23 +583,19 @@ pg_status rebuild(pg_batch *b, bool *built_any) {
   if (G == 0) return PG_OK;
   PG_HIP(hipMemcpyAsync(b->d_desc, b->h_desc.data(), sizeof(GameDesc) * G,
                         hipMemcpyHostToDevice, s));
-  PG_HIP(hipMemcpyAsync(b->d_vstart, b->h_vstart.data(), sizeof(int64_t) * G,
-                        hipMemcpyHostToDevice, s));
-  PG_HIP(hipMemcpyAsync(b->d_estart, b->h_estart.data(), sizeof(int64_t) * G,
-                        hipMemcpyHostToDevice, s));
   PG_HIP(hipMemcpyAsync(b->d_pstart, b->h_pstart.data(),
+                        sizeof(int64_t) * 2 * G, hipMemcpyHostToDevice, s));
+  PG_HIP(hipMemcpyAsync(b->d_estart, b->h_estart.data(),
                         sizeof(int64_t) * 2 * G, hipMemcpyHostToDevice, s));
   const int32_t N = (int32_t)vb;
   uint32_t *oddf = a->sk0, *oscan = a->sk1;
   hipLaunchKernelGGL(k_arena_vertices, dim3(grid_for(N)), dim3(kBlock), 0, s,
-                     b->d_desc, b->d_vstart, G, N, eb, a->off, a->owner, a->pri,
-                     b->d_gid, a->rvpos, oddf, a->sp);
+                     b->d_desc, b->d_pstart, G, N, eb, a->off, a->owner,
+                     a->pri, b->d_gid, oddf, a->sp);
   hipLaunchKernelGGL(k_arena_edges, dim3(grid_for(eb)), dim3(kBlock), 0, s,
                      b->d_desc, b->d_estart, G, eb, a->tgt);
   hipLaunchKernelGGL(k_arena_sp_pri, dim3(grid_for(N)), dim3(kBlock), 0, s,
                      a->pri, a->sp, N);
-  hipLaunchKernelGGL(k_arena_perm, dim3(grid_for(N)), dim3(kBlock), 0, s,
-                     b->d_desc, b->d_pstart, G, N, a->perm);
   // the two players' vertex lists (their sizes are known on the host)
   scan_excl_u32(oddf, oscan, N, a->scan_tmp, s);
   hipLaunchKernelGGL(k_split_players, dim3(grid_for(N)), dim3(kBlock), 0, s,
@@ -672,12 +707,37 @@ pg_status pg_batch_submit(pg_batch *b, int64_t n, int64_t m,
     fill_i32((int32_t *)a->u64tmp, 0, 2, s);
     hipLaunchKernelGGL(k_count_odd_edges, dim3(256), dim3(kBlock), 0, s,
                        gg->off, gg->owner, N, a->u64tmp);
+    // the game is stored in its signed order from here on (its rows keep
+    // their edge order); the even-priority rows start at off[n_oddpri]
+    int64_t *off2 = nullptr;
+    int32_t *tgt2 = nullptr, *pri2 = nullptr;
+    uint8_t *own2 = nullptr;
+    st = relabel_game(gg->off, gg->tgt, gg->owner, gg->pri, bg->rvperm,
+                      bg->rvrank, N, gg->m_aug, &off2, &tgt2, &own2, &pri2, s);
+    dev_free(st == PG_OK ? gg->off : off2);
+    dev_free(st == PG_OK ? (void *)gg->tgt : (void *)tgt2);
+    dev_free(st == PG_OK ? gg->owner : own2);
+    dev_free(st == PG_OK ? gg->pri : pri2);
+    if (st == PG_OK) {
+      gg->off = off2;
+      gg->tgt = tgt2;
+      gg->owner = own2;
+      gg->pri = pri2;
+      gg->relabeled = true;
+      hipLaunchKernelGGL(k_part_edge, dim3(1), dim3(1), 0, s, gg->off,
+                         gg->ctr, (int64_t *)(a->u64tmp + 1));
+    }
     int32_t mx = 0;
     unsigned long long me = 0;
+    int64_t es = 0;
     hipError_t e = hipMemcpyAsync(&mx, b->d_i32, 4, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess)
       e = hipMemcpyAsync(&me, a->u64tmp, sizeof(me), hipMemcpyDeviceToHost, s);
-    if (e != hipSuccess) st = pg_fail(PG_EDEVICE, hipGetErrorString(e));
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(&es, a->u64tmp + 1, sizeof(es),
+                         hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess && st == PG_OK)
+      st = pg_fail(PG_EDEVICE, hipGetErrorString(e));
     if (st == PG_OK) st = sync_ctr(gg, s);
     if (st == PG_OK && (gg->hctr[C_ERR] & ERR_DUPPRI))
       st = pg_fail(PG_EINVAL, "priorities must be pairwise distinct");
@@ -685,6 +745,7 @@ pg_status pg_batch_submit(pg_batch *b, int64_t n, int64_t m,
     bg->n_oddpri = gg->hctr[C_MISC];
     bg->n_odd = gg->hctr[C_NFIN];
     bg->m_odd = (int64_t)me;
+    bg->e_split = es;
   }
   if (st != PG_OK) {
     (void)hipStreamSynchronize(s);
@@ -752,7 +813,7 @@ pg_status pg_batch_step(pg_batch *b, int32_t *n_live, int32_t *n_queued,
                        b->d_sw_odd, b->d_sw_even, b->d_newly);
     hipLaunchKernelGGL(k_arena_export, dim3(grid_for(N)), dim3(kBlock), 0, s,
                        b->d_desc, b->d_gid, b->d_newly, a->sp, a->key,
-                       a->owner, N);
+                       a->owner, N, (int64_t)a->n_oddpri);
     PG_HIP(hipMemcpyAsync(b->h_newly.data(), b->d_newly, G,
                           hipMemcpyDeviceToHost, s));
     PG_HIP(hipMemcpyAsync(b->h_nval.data(), b->d_nval, 4 * (size_t)G,

@@ -455,4 +455,13 @@ pg_status load_modified(int64_t n, int64_t m, const void *offsets,
 // distinct: reject repeated priorities (rank valuations)
 pg_status finalize_state(pg_game *g, hipStream_t s, bool init_sp,
                          bool distinct = true);
+// A game of N vertices and M edges rebuilt with vertex i taken from vertex
+// from[i] and every target t mapped to to[t]; rows keep their edge order.
+// The new arrays are allocated (the old ones are the caller's); returns
+// after the stream has drained.
+pg_status relabel_game(const int64_t *off, const int32_t *tgt,
+                       const uint8_t *owner, const int32_t *pri,
+                       const int32_t *from, const int32_t *to, int64_t N,
+                       int64_t M, int64_t **off2, int32_t **tgt2,
+                       uint8_t **owner2, int32_t **pri2, hipStream_t s);
 }  // namespace pgk
