@@ -277,7 +277,12 @@ typedef struct pg_stats {
  *   winner   n outputs (original vertices): 0 = W_Even, 1 = W_Odd
  *   sigma    n_aug outputs (nullable): the final sigma* (PG_SINK for the
  *            sink); vertices Even wins never map to the sink
- *   tau      n_aug outputs (nullable): the final tau* = br(sigma*)
+ *   tau      n_aug outputs (nullable): the final tau* = br(sigma*), with
+ *            an Odd choice of a dummy d_w given as w (the dummy only stands
+ *            in the middle of the original edge to w), so the Odd choices of
+ *            the n original vertices are edges of the original game.
+ *            pg_best_response keeps dummies as they are (its tau is an
+ *            input again)
  *   stats    nullable
  */
 pg_status pg_solve(pg_game *game, const pg_solve_opts *opts, uint8_t *winner,

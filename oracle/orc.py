@@ -209,6 +209,19 @@ def initial_strategies(g: dict):
     return sigma, tau
 
 
+def report_tau(g: dict, tau) -> np.ndarray:
+    """tau as a solve reports it: an Odd choice of a dummy d_w (section 3,
+    "The algorithm": the dummy only stands in the middle of the original
+    edge to w) is reported as w, so the Odd choices of the original
+    vertices are edges of the original game."""
+    t = np.array(tau, dtype=np.int32, copy=True)
+    n0 = int(g["n_orig"])
+    dummy_of = np.asarray(g["dummy_of"], dtype=np.int32)
+    d = t >= n0
+    t[d] = dummy_of[t[d] - n0]
+    return t
+
+
 def solve(game: dict, preprocess_game: bool = True,
           method: int = RANK_KRUSKAL, trace: bool = False,
           max_major: int = 0, max_inner: int = 0, aug: dict = None,
@@ -234,7 +247,8 @@ def solve(game: dict, preprocess_game: bool = True,
     n0 = int(g["n_orig"])
     winner = (key[:n0] != KEY_TOP).astype(np.uint8)
     return {"aug": g, "status": int(rc), "winner": winner, "sigma": sigma,
-            "tau": tau, "key": key, "n_major": int(st.n_major),
+            "tau": tau, "tau_orig": report_tau(g, tau), "key": key,
+            "n_major": int(st.n_major),
             "n_valuations": int(st.n_valuations),
             "n_even_switches": int(st.n_even_switches),
             "n_odd_switches": int(st.n_odd_switches),
@@ -357,7 +371,8 @@ def dense_solve(game: dict, preprocess_game: bool = True, trace: bool = False,
     winner = (top[:n0] == 0).astype(np.uint8)
     nv = int(st.n_valuations)
     return {"aug": g, "status": int(rc), "winner": winner, "sigma": sigma,
-            "tau": tau, "counts": counts, "top": top, "values": values,
+            "tau": tau, "tau_orig": report_tau(g, tau), "counts": counts,
+            "top": top, "values": values,
             "n_major": int(st.n_major), "n_valuations": nv,
             "n_even_switches": int(st.n_even_switches),
             "n_odd_switches": int(st.n_odd_switches),

@@ -278,15 +278,24 @@ __global__ void k_sp_import(const uint8_t *owner, const int32_t *pri,
   sp[i] = make_int2(s, s == N ? 2147483647 : pri[s]);
 }
 
+// With `report` (the outputs of a solve), an Odd choice of a dummy d_w
+// (caller id >= n_orig) is given as w, the only entry of the dummy's row:
+// the dummy stands in the middle of the original edge to w (section 3).
 __global__ void k_sp_export(const uint8_t *owner, const int2 *sp,
                             const int32_t *perm, const int32_t *rvpos,
-                            int32_t *sigma, int32_t *tau, int32_t N) {
+                            const int64_t *off, const int32_t *tgt,
+                            int64_t n_orig, int report, int32_t *sigma,
+                            int32_t *tau, int32_t N) {
   int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= N) return;
   const int32_t i = rvpos ? rvpos[v] : (int32_t)v;
-  int32_t s = sp[i].x;
-  if (perm && s != N) s = perm[s];
+  const int32_t si = sp[i].x;
+  int32_t s = (perm && si != N) ? perm[si] : si;
   const bool even = owner[i] == 0;
+  if (report && !even && s != N && s >= n_orig) {
+    const int32_t w = tgt[off[si]];
+    s = perm ? perm[w] : w;
+  }
   if (sigma) sigma[v] = even ? (s == N ? PG_SINK : s) : PG_SINK;
   if (tau) tau[v] = even ? PG_SINK : s;
 }
@@ -872,14 +881,14 @@ pg_status import_strats(pg_game *g, const int32_t *sigma, const int32_t *tau,
 }
 
 pg_status export_strats(pg_game *g, int32_t *sigma, int32_t *tau, bool dev,
-                        hipStream_t s) {
+                        hipStream_t s, bool report) {
   const int64_t N = g->n_aug;
   if (!sigma && !tau) return PG_OK;
   int32_t *ds = dev ? sigma : (sigma ? g->wl0 : nullptr);
   int32_t *dt = dev ? tau : (tau ? g->wl1 : nullptr);
   hipLaunchKernelGGL(k_sp_export, dim3(grid_for(N)), dim3(kBlock), 0, s,
-                     g->owner, g->sp, io_perm(g), io_rvpos(g), ds, dt,
-                     (int32_t)N);
+                     g->owner, g->sp, io_perm(g), io_rvpos(g), g->off, g->tgt,
+                     g->n, (int)report, ds, dt, (int32_t)N);
   if (!dev) {
     if (sigma) PG_TRY(copy_out(sigma, g->wl0, sizeof(int32_t) * N, false, s));
     if (tau) PG_TRY(copy_out(tau, g->wl1, sizeof(int32_t) * N, false, s));
@@ -1112,7 +1121,7 @@ pg_status pg_best_response(pg_game *g, const int32_t *sigma, int32_t *tau,
   pg_status st = inner_loop(g, max_inner, s, &nv, &nsw);
   if (n_valuations) *n_valuations = (int32_t)nv;
   if (st != PG_OK) return st;
-  PG_TRY(export_strats(g, nullptr, tau, dev, s));
+  PG_TRY(export_strats(g, nullptr, tau, dev, s, false));
   if (key) PG_TRY(export_keys(g, key, dev, s));
   PG_HIP(hipStreamSynchronize(s));
   return PG_OK;
@@ -1180,7 +1189,7 @@ pg_status pg_solve(pg_game *g, const pg_solve_opts *opts, uint8_t *winner,
                      g->rs, io_rvpos(g), dw, g->n);
   if (!dev) PG_TRY(copy_out(winner, dw, g->n, false, s));
   PG_HIP(hipStreamSynchronize(s));
-  PG_TRY(export_strats(g, sigma, tau, dev, s));
+  PG_TRY(export_strats(g, sigma, tau, dev, s, true));
   const auto t1 = std::chrono::steady_clock::now();
   if (stats) stats->seconds = std::chrono::duration<double>(t1 - t0).count();
   return PG_OK;

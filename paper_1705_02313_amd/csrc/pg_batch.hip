@@ -154,7 +154,7 @@ __global__ void k_arena_save(const GameDesc *__restrict__ d,
 }
 
 // results of the games that finished in this step, in the caller's ids
-// (Theorem 1: W_Even is the set of top keys)
+// (Theorem 1: W_Even is the set of top keys), as pg_solve gives them
 __global__ void k_arena_export(const GameDesc *__restrict__ d,
                                const int32_t *__restrict__ gid,
                                const uint8_t *__restrict__ newly_done,
@@ -168,9 +168,15 @@ __global__ void k_arena_export(const GameDesc *__restrict__ d,
   const GameDesc &g = d[s];
   const int32_t c = g.rvperm[to_local(g, v, odd_total)];
   const int32_t x = sp[v].x;
-  const int32_t cx =
-      (x == N) ? PG_SINK : g.rvperm[to_local(g, x, odd_total)];
   const bool even = owner[v] == 0;
+  int32_t cx = PG_SINK;
+  if (x != N) {
+    const int32_t lx = to_local(g, x, odd_total);
+    cx = g.rvperm[lx];
+    // an Odd choice of a dummy d_w is reported as w, the only entry of the
+    // dummy's row (as pg_solve reports it)
+    if (!even && cx >= g.n_orig) cx = g.rvperm[g.tgt[g.off[lx]]];
+  }
   g.res_sigma[c] = even ? cx : PG_SINK;
   g.res_tau[c] = even ? PG_SINK : cx;
   if (c < g.n_orig) g.res_winner[c] = key[v] == PG_KEY_TOP ? 0 : 1;

@@ -95,3 +95,51 @@ def off_row_tau(aug: dict, tau, k: int, seed: int):
             u = int(rng.choice(evens))
         t[v] = u
     return t
+
+
+def stands_for(aug_off, aug_tgt, n_orig: int) -> np.ndarray:
+    """For every vertex of a modified game, the original vertex it stands
+    for: itself, or w for a dummy d_w (whose row is [w])."""
+    off = np.asarray(aug_off, np.int64)
+    tgt = np.asarray(aug_tgt)
+    n = off.size - 1
+    sf = np.arange(n, dtype=np.int64)
+    if n > n_orig:
+        sf[n_orig:] = tgt[off[n_orig:n]]
+    return sf
+
+
+def tau_to_aug(aug_off, aug_tgt, owner, tau, n_orig: int) -> np.ndarray:
+    """A solve's reported tau (dummy choices given as their w) back in the
+    modified game's ids: each Odd choice becomes the row entry that stands
+    for it (unique: an edge to w is either kept or redirected to d_w)."""
+    off = np.asarray(aug_off, np.int64)
+    tgt = np.asarray(aug_tgt, np.int64)
+    own = np.asarray(owner)
+    tau = np.asarray(tau, np.int64)
+    n = off.size - 1
+    sf = stands_for(off, tgt, n_orig)
+    src = np.repeat(np.arange(n), np.diff(off))
+    hit = (own[src] == 1) & (sf[tgt] == tau[src])
+    out = tau.copy()
+    # the first matching edge of each Odd row (rows are contiguous)
+    e = np.flatnonzero(hit)
+    first = np.full(n, -1, np.int64)
+    first[src[e][::-1]] = e[::-1]
+    odd = own == 1
+    assert (first[odd] >= 0).all(), "a reported Odd choice is not a row edge"
+    out[odd] = tgt[first[odd]]
+    return out.astype(np.int32)
+
+
+def is_original_edge(game: dict, tau, n_orig: int) -> bool:
+    """Whether every Odd original vertex's choice in tau is an edge of the
+    original game."""
+    off = np.asarray(game["offsets"], np.int64)
+    tgt = np.asarray(game["targets"], np.int64)
+    own = np.asarray(game["owner"])
+    tau = np.asarray(tau, np.int64)[:n_orig]
+    src = np.repeat(np.arange(n_orig), np.diff(off[:n_orig + 1]))
+    ok = np.zeros(n_orig, bool)
+    ok[src[tgt == tau[src]]] = True
+    return bool(ok[own[:n_orig] == 1].all())

@@ -16,7 +16,8 @@ import pytest
 
 from paper_1705_02313_amd import synth
 from paper_1705_02313_amd.pg import Game
-from tests.helpers import KEY_TOP, np_hash, to_np
+from tests.helpers import (KEY_TOP, is_original_edge, np_hash, tau_to_aug,
+                           to_np)
 
 pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -30,10 +31,10 @@ def _golden(name):
         return json.load(f)["data"]
 
 
-def _final_checks(dev: Game, out):
-    """No switchable edge at the end; closure of the winning sets."""
+def _final_checks(dev: Game, out, tau):
+    """No switchable edge at the end; closure of the winning sets (tau in
+    the modified game's ids)."""
     sigma = to_np(out["sigma"])
-    tau = to_np(out["tau"])
     key, _ = dev.valuation(sigma, tau)
     key = to_np(key).astype(np.int64)
     ex = dev.export()
@@ -79,8 +80,15 @@ def _run(game, gold, device=True):
         assert np_hash(to_np(out["winner"]).astype(np.int32)) == \
             gold["winner_hash"]
         assert np_hash(to_np(out["sigma"])) == gold["sigma_hash"]
-        assert np_hash(to_np(out["tau"])) == gold["tau_hash"]
-        _final_checks(dev, out)
+        # the reported tau names original vertices for the original ones;
+        # back in the modified game's ids it is the stored one
+        tau = to_np(out["tau"])
+        assert is_original_edge(game, tau, dev.n)
+        ex = dev.export()
+        tau = tau_to_aug(ex["offsets"], ex["targets"], ex["owner"], tau,
+                         dev.n)
+        assert np_hash(tau) == gold["tau_hash"]
+        _final_checks(dev, out, tau)
 
 
 def test_config0_twenty_seeds():

@@ -23,7 +23,7 @@ from oracle import literal as L
 from oracle import orc
 from oracle.zielonka import zielonka
 from paper_1705_02313_amd import synth
-from tests.helpers import np_hash
+from tests.helpers import is_original_edge, np_hash, tau_to_aug
 
 
 # ---------------------------------------------------------------------------
@@ -469,3 +469,26 @@ def test_generators_deterministic_and_well_formed(kind):
                 assert v not in row
             else:
                 assert (v + 1) % n in row
+
+
+def test_reported_tau_is_a_strategy_of_the_original_game():
+    """A solve reports an Odd choice of a dummy d_w as w (section 3: the
+    dummy stands in the middle of the original edge to w).  The Odd choices
+    of the original vertices are then edges of the original game, and
+    mapping them back to the row entries that stand for them gives the
+    modified game's strategy again."""
+    seen_dummy = False
+    games = [synth.random_game(3000, 2, 5, s) for s in range(3)]
+    games += [synth.chain_game(3000, 4), synth.random_game(8, 2, 3, 1)]
+    for g in games:
+        for r in (orc.solve(g), orc.dense_solve(g, preprocess_game=True)):
+            aug = r["aug"]
+            n0 = int(g["n"])
+            odd = np.asarray(aug["owner"]) == 1
+            seen_dummy |= bool((r["tau"][odd] >= n0).any())
+            assert is_original_edge(g, r["tau_orig"], n0)
+            back = tau_to_aug(aug["offsets"], aug["targets"], aug["owner"],
+                              r["tau_orig"], n0)
+            np.testing.assert_array_equal(back, r["tau"])
+            np.testing.assert_array_equal(r["tau_orig"][~odd], r["tau"][~odd])
+    assert seen_dummy
