@@ -29,7 +29,9 @@ that takes the most time, its algorithmic bytes over its event-timed
 duration against 8 TB/s, from up to two profiled steps run after the timed
 steps), "iteration_roofline" (every kernel's algorithmic bytes per
 best-response iteration over the iteration's unprofiled time, against the
-same peak, with the counter bytes when they are current) and
+same peak; the method's least bytes per iteration likewise; the counter
+bytes when they are current; and a measured 1 GiB copy rate), on c3
+"deep_list_valuation" (one valuation of a play through every vertex) and
 "cpu_baseline" (the CPU oracle timed on this host on a bounded sample of
 the same workload).  --best-response picks the best responses
 (section 6's comparison: SI, SI-Reset, Bellman-Ford on count games).
@@ -103,6 +105,78 @@ def counter_traffic(workload: str, kind: str):
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 5) -> float:
+    """Device-to-device copy rate on this GPU in GB/s (bytes read plus bytes
+    written), the practical ceiling beside the 8 TB/s specification."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ts = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b) / 1e3)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / statistics.median(ts) / 1e9
+
+
+def method_min_bytes(n_aug: int, m_aug: int, offset_bytes: int) -> int:
+    """The method's own least I/O per best-response iteration: the CSR
+    offsets and targets, one key gather per edge, per vertex its owner, its
+    strategy read and written and its current choice's key (13 B) and its
+    successor and priority reads and key write (12 B), and 12 B per element
+    of an Euler list of 2 n' elements."""
+    return (offset_bytes * (n_aug + 1) + 8 * m_aug + 25 * n_aug +
+            12 * 2 * n_aug)
+
+
+def deep_list_valuation(arrs, n: int, reps: int = 5) -> dict:
+    """One valuation of a play through every vertex: each original vertex i
+    takes the row entry standing for i + 1 (mod n; a dummy d_w stands for
+    w), each dummy its only entry, and one Even vertex the sink, so the
+    finite part is one list about as deep as the modified game.  Wall time
+    of pg_valuation on device arrays (median of `reps`)."""
+    import torch
+    from paper_1705_02313_amd.pg import Game
+    with Game(arrs["offsets"], arrs["targets"], arrs["owner"], arrs["pri"],
+              n=n) as g:
+        ex = g.export()
+        off, tgt, own = ex["offsets"], ex["targets"], ex["owner"]
+        N = ex["n"]
+        sf = np.arange(N, dtype=np.int64)
+        sf[n:] = tgt[off[n:N]]
+        want = np.concatenate([(np.arange(n) + 1) % n, sf[n:]])
+        src = np.repeat(np.arange(N), np.diff(off))
+        hit = sf[tgt] == want[src]
+        e = np.flatnonzero(hit)
+        first = np.full(N, -1, np.int64)
+        first[src[e][::-1]] = e[::-1]
+        assert (first >= 0).all()
+        nxt = tgt[first].astype(np.int32)
+        sigma = np.where(own == 0, nxt, -1).astype(np.int32)
+        tau = np.where(own == 1, nxt, -1).astype(np.int32)
+        even = np.flatnonzero(own[:n] == 0)
+        sigma[even[len(even) // 2]] = -1
+        ds = torch.from_numpy(sigma).cuda()
+        dt = torch.from_numpy(tau).cuda()
+        _, nf = g.valuation(ds, dt)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            g.valuation(ds, dt)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+    return {"ms_median": 1e3 * statistics.median(ts), "finite": nf,
+            "n_aug": int(N), "reps": reps}
 
 
 def cpu_baseline(game: dict, iters: int = 3, counts: bool = False) -> dict:
@@ -386,14 +460,20 @@ def main():
         if all(v is not None for v in traffic.values()):
             it_traffic = sum(traffic[k] * agg[k]["calls"] for k in agg) / (
                 prof_steps * nval)
+        n_aug, m_aug = runs[0]["aug"][0], runs[0]["aug"][1]
+        b_min = method_min_bytes(n_aug, m_aug,
+                                 np.asarray(game["offsets"]).itemsize)
         iteration_roof = {
             "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
             "alg_bytes": round(it_bytes),
             "achieved": round(it_bytes / it_s / 1e9, 1),
             "frac": round(it_bytes / it_s / 1e9 / HBM_PEAK_GBS, 4),
+            "method_min_bytes": b_min,
+            "method_min_frac": round(b_min / it_s / 1e9 / HBM_PEAK_GBS, 4),
             "traffic": round(it_traffic) if it_traffic else None,
             "traffic_GBps": (round(it_traffic / it_s / 1e9, 1)
-                             if it_traffic else None)}
+                             if it_traffic else None),
+            "copy_GBps": round(copy_bandwidth(), 1)}
 
     line = {
         "metric": "edges/s per best-response iteration",
@@ -420,12 +500,17 @@ def main():
         "n_valuations": nval,
         "best_response": args.best_response,
         "ms_per_iteration": 1e3 * statistics.median(solve_s) / nval,
+        "aug_edges_per_s": runs[0]["aug"][1] * nval /
+        statistics.median(solve_s),
         "w_even": int((win == 0).sum()),
         "event_ms_total": ev0.elapsed_time(ev1),
         "roofline": roof,
         "iteration_roofline": iteration_roof,
         "kernels": kernels,
     }
+    if args.workload == "c3":
+        log("deep-list valuation")
+        line["deep_list_valuation"] = deep_list_valuation(arrs, game["n"])
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample of the same workload")
         line["cpu_baseline"] = cpu_baseline(game,
