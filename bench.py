@@ -321,6 +321,9 @@ def main():
                     choices=["si", "reset", "bf"],
                     help="best responses: one-player SI (Algorithm 1), "
                          "SI-Reset, or Bellman-Ford (count games)")
+    ap.add_argument("--host-reduced-list", action="store_true",
+                    help="rank the reduced list on the host (the paper's "
+                         "GPU-LR split), to measure it against the device")
     ap.add_argument("--mix-games", type=int, default=1024,
                     help="games in the batched/served workload")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -367,7 +370,7 @@ def main():
     def step(profile: bool):
         t_a = time.perf_counter()
         g = Game(arrs["offsets"], arrs["targets"], arrs["owner"], arrs["pri"],
-                 n=game["n"])
+                 n=game["n"], host_reduced_list=args.host_reduced_list)
         torch.cuda.synchronize()
         t_b = time.perf_counter()
         if profile:
@@ -499,6 +502,7 @@ def main():
         "n_major": runs[0]["stats"]["n_major"],
         "n_valuations": nval,
         "best_response": args.best_response,
+        "host_reduced_list": args.host_reduced_list,
         "ms_per_iteration": 1e3 * statistics.median(solve_s) / nval,
         "aug_edges_per_s": runs[0]["aug"][1] * nval /
         statistics.median(solve_s),

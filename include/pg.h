@@ -70,7 +70,9 @@ enum {
     PG_OFFSETS_I32 = 4u,    /* pg_load_csr: offsets are int32, not int64     */
     PG_CAREFUL_WALKS = 8u,  /* pg_load_csr: host-driven walk rounds (below)  */
     PG_COUNT_VALUATION = 16u,/* pg_load_csr: count valuations (below)        */
-    PG_NO_GRAPH = 32u       /* pg_load_csr: launch every kernel one by one   */
+    PG_NO_GRAPH = 32u,      /* pg_load_csr: launch every kernel one by one   */
+    PG_HOST_REDUCED_LIST = 64u /* pg_load_csr: rank the reduced list on the
+                                  host (the paper's GPU-LR split; below)     */
 };
 
 /*
@@ -85,7 +87,8 @@ enum {
  *   owner     n bytes: 0 = Even, 1 = Odd
  *   priority  n int32 priorities, >= 0 (they may repeat; see below)
  *   flags     PG_PTR_DEVICE, PG_NO_PREPROCESS, PG_OFFSETS_I32,
- *             PG_CAREFUL_WALKS, PG_COUNT_VALUATION, PG_NO_GRAPH
+ *             PG_CAREFUL_WALKS, PG_COUNT_VALUATION, PG_NO_GRAPH,
+ *             PG_HOST_REDUCED_LIST
  *
  * Two representations of valuations (section 3, "Valuations").  With
  * pairwise distinct priorities a finite valuation is the set of priorities
@@ -120,6 +123,14 @@ enum {
  * the library's own) and replayed on the caller's stream; the event
  * profiler and the host-driven fallback launch kernels one by one.
  * PG_NO_GRAPH launches every kernel one by one: same results.
+ *
+ * PG_HOST_REDUCED_LIST (rank valuations; ignored for count valuations) is
+ * the split of the paper's GPU-LR implementation (section 6): the device
+ * builds the Euler list and sums its sublists, the host ranks the reduced
+ * list (one walk from the head over a copy of it) and the device emits the
+ * keys.  Same results; each valuation then waits for the host and no graph
+ * is captured.  It exists to measure that split against the device-only
+ * ranking.
  *
  * The inputs may be freed when the call returns.  Errors: PG_EINVAL for a
  * malformed game (bad offsets, a terminal vertex, a target out of range, an

@@ -496,6 +496,7 @@ void free_game(pg_game *g) {
     dev_free(g->vbase[k]);
   }
   host_free(g->hctr);
+  host_free(g->h_rl);
   for (hipGraphExec_t &ex : g->iter_exec)
     if (ex) (void)hipGraphExecDestroy(ex);
   if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
@@ -969,6 +970,7 @@ pg_status pg_load_csr(int64_t n, int64_t m, const void *offsets,
   if (st == PG_OK && g->dense) st = count_setup(g, s);
   g->careful = flags & PG_CAREFUL_WALKS;
   g->use_graph = !(flags & PG_NO_GRAPH);
+  g->host_rl = (flags & PG_HOST_REDUCED_LIST) && !g->dense;
   if (st != PG_OK) {
     (void)hipStreamSynchronize(s);
     free_game(g);

@@ -149,6 +149,10 @@ struct pg_game {
   int64_t n_odd = 0, m_odd = 0;  // Odd vertices and the edges of their rows
   int sort_bits = 0;             // bits of a parent id key (ids 0..n_aug+1)
   bool careful = false;          // PG_CAREFUL_WALKS: host-driven walk rounds
+  // PG_HOST_REDUCED_LIST: the host ranks the level-1 reduced list (pinned
+  // next, sum and base arrays in h_rl)
+  bool host_rl = false;
+  int32_t *h_rl = nullptr;
   // one best-response iteration (walks, valuation, All_Odd) captured as a
   // HIP graph per ng/cand pair and replayed (unless PG_NO_GRAPH)
   bool use_graph = false;

@@ -739,8 +739,9 @@ static pg_status careful_walks(pg_game *g, hipStream_t s) {
   return PG_OK;
 }
 
-// sort, Euler list and list ranking; every kernel skips when C_ABORT is set.
-static void enqueue_rank(pg_game *g, hipStream_t s) {
+// sort, Euler list and the level-1 sublist sums; every kernel skips when
+// C_ABORT is set.
+static void enqueue_rank_list(pg_game *g, hipStream_t s) {
   const int32_t N = (int32_t)g->n_aug;
   Prof *pf = &g->prof;
   // the root walks wrote the keys in signed-priority order (the sort's
@@ -774,7 +775,19 @@ static void enqueue_rank(pg_game *g, hipStream_t s) {
   PG_LAUNCH_NF(pf, K_LR_SUM1, 8.5, k_lr_sum1, dim3(grid_for(thr1)),
             dim3(kBlock), 0, s, g->elem, kPerThread1, g->lv[0].sum,
             g->lv[0].next, g->ctr);
-  for (int k = 1; k < nl; ++k) {
+}
+
+// The reduced lists ranked on the device (unless the level-1 bases come
+// from the host), then every level-1 sublist walked again to emit the keys.
+static void enqueue_rank_emit(pg_game *g, hipStream_t s, bool device_reduced) {
+  const int32_t N = (int32_t)g->n_aug;
+  Prof *pf = &g->prof;
+  const int nl = g->nlevels;
+  const int64_t Lmax = 2 * (int64_t)N + 2;
+  const int64_t ns1 = level_size(Lmax, 1);
+  const int kPerThread1 = per_thread1(ns1);
+  const int64_t thr1 = (ns1 + kPerThread1 - 1) / kPerThread1;
+  for (int k = 1; device_reduced && k < nl; ++k) {
     const int64_t nsk = level_size(Lmax, k + 1);
     // 8 B per element of the level-k list (about 2 nF / 32^k elements)
     PG_LAUNCH_NF(pf, K_LR_SUMK,
@@ -782,10 +795,11 @@ static void enqueue_rank(pg_game *g, hipStream_t s) {
               dim3(grid_for(nsk)), dim3(kBlock), 0, s, g->lv[k - 1].next,
               g->lv[k - 1].sum, k, g->lv[k].sum, g->lv[k].next, g->ctr);
   }
-  PG_LAUNCH(pf, K_LR_TOP, 12.0 * level_size(Lmax, nl), k_lr_top, dim3(1),
-            dim3(kTopThreads), 0, s, g->lv[nl - 1].next, g->lv[nl - 1].sum, nl,
-            g->lv[nl - 1].base, g->ctr);
-  for (int k = nl - 1; k >= 1; --k) {
+  if (device_reduced)
+    PG_LAUNCH(pf, K_LR_TOP, 12.0 * level_size(Lmax, nl), k_lr_top, dim3(1),
+              dim3(kTopThreads), 0, s, g->lv[nl - 1].next, g->lv[nl - 1].sum,
+              nl, g->lv[nl - 1].base, g->ctr);
+  for (int k = nl - 1; device_reduced && k >= 1; --k) {
     const int64_t nsk = level_size(Lmax, k + 1);
     PG_LAUNCH_NF(pf, K_LR_DISTK,
                  24.0 * (double)level_size(Lmax, k) / (double)Lmax, k_lr_distk,
@@ -825,8 +839,54 @@ static void enqueue_switch(pg_game *g, bool odd, hipStream_t s) {
 // The valuation after the walks: rank keys (distinct priorities) or count
 // vectors (pg_count.hip).
 static void enqueue_values(pg_game *g, hipStream_t s) {
-  if (g->dense) enqueue_count(g, s);
-  else enqueue_rank(g, s);
+  if (g->dense) {
+    enqueue_count(g, s);
+  } else {
+    enqueue_rank_list(g, s);
+    enqueue_rank_emit(g, s, true);
+  }
+}
+
+// The split of the paper's GPU-LR (PG_HOST_REDUCED_LIST, rank valuations):
+// the device builds the list and sums the level-1 sublists, the host ranks
+// the reduced list (one walk from the head) and the device emits the keys.
+static pg_status host_reduced_rank(pg_game *g, hipStream_t s) {
+  enqueue_rank_list(g, s);
+  PG_TRY(read_ctr(g, s));
+  if (g->hctr[C_ABORT] || g->hctr[C_ERR]) return PG_OK;  // the caller looks
+  const int64_t nF = g->hctr[C_NFIN];
+  const int64_t ns = level_size(2 * nF + 2, 1);
+  const int64_t cap = level_size(2 * g->n_aug + 2, 1);
+  if (!g->h_rl) {
+    void *p = nullptr;
+    PG_TRY(host_alloc(&p, sizeof(int32_t) * 3 * (size_t)cap));
+    g->h_rl = (int32_t *)p;
+  }
+  int32_t *hn = g->h_rl, *hs = g->h_rl + cap, *hb = g->h_rl + 2 * cap;
+  PG_HIP(hipMemcpyAsync(hn, g->lv[0].next, sizeof(int32_t) * ns,
+                        hipMemcpyDeviceToHost, s));
+  PG_HIP(hipMemcpyAsync(hs, g->lv[0].sum, sizeof(int32_t) * ns,
+                        hipMemcpyDeviceToHost, s));
+  PG_HIP(hipStreamSynchronize(s));
+  int64_t acc = 0, steps = 0;
+  for (int64_t j = 0; j >= 0; j = hn[j]) {
+    if (++steps > ns || j >= ns)
+      return pg_fail(PG_EINTERNAL, "reduced list walk exceeded its bound");
+    hb[j] = (int32_t)acc;
+    acc += hs[j];
+  }
+  if (acc != nF + 1)
+    return pg_fail(PG_EINTERNAL, "list ranking lost elements");
+  PG_HIP(hipMemcpyAsync(g->lv[0].base, hb, sizeof(int32_t) * ns,
+                        hipMemcpyHostToDevice, s));
+  enqueue_rank_emit(g, s, false);
+  return PG_OK;
+}
+
+static pg_status values(pg_game *g, hipStream_t s) {
+  if (g->host_rl && !g->dense) return host_reduced_rank(g, s);
+  enqueue_values(g, s);
+  return PG_OK;
 }
 
 static void enqueue_any_switch(pg_game *g, bool odd, hipStream_t s) {
@@ -879,7 +939,8 @@ static pg_status run_valuation(pg_game *g, hipStream_t s, bool odd_switch,
   g->nlevels = g->dense ? count_levels(g->n_aug, g->dw)
                         : plan_levels(g->n_aug);
   bool replayed = false;
-  if (odd_switch && g->use_graph && !g->careful && !g->prof.on) {
+  if (odd_switch && g->use_graph && !g->careful && !g->prof.on &&
+      !g->host_rl) {
     hipGraphExec_t &ex = g->iter_exec[g->par];
     if (!ex && capture_iteration(g, &ex) != PG_OK) {
       g->use_graph = false;  // capture refused: stay eager from now on
@@ -893,7 +954,7 @@ static pg_status run_valuation(pg_game *g, hipStream_t s, bool odd_switch,
   if (!replayed) {
     if (g->careful) PG_TRY(careful_walks(g, s));
     else enqueue_walks(g, s);
-    enqueue_values(g, s);
+    PG_TRY(values(g, s));
     if (odd_switch) {
       fill_i32(g->ctr + C_SWITCH, 0, 1, s, &g->prof);
       enqueue_any_switch(g, true, s);
@@ -906,7 +967,8 @@ static pg_status run_valuation(pg_game *g, hipStream_t s, bool odd_switch,
     // redo everything after the walks (the gated kernels did nothing)
     st = careful_walks(g, s);
     if (st != PG_OK) return st;
-    enqueue_values(g, s);
+    st = values(g, s);
+    if (st != PG_OK) return st;
     if (odd_switch) {
       fill_i32(g->ctr + C_SWITCH, 0, 1, s, &g->prof);
       enqueue_any_switch(g, true, s);

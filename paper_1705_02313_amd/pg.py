@@ -22,6 +22,7 @@ PG_SINK = -1
 PG_KEY_TOP = 2**31 - 1
 PG_PTR_DEVICE, PG_NO_PREPROCESS, PG_OFFSETS_I32 = 1, 2, 4
 PG_CAREFUL_WALKS, PG_COUNT_VALUATION, PG_NO_GRAPH = 8, 16, 32
+PG_HOST_REDUCED_LIST = 64
 PG_BR_SI, PG_BR_SI_RESET, PG_BR_BELLMAN_FORD = 0, 1, 2
 
 STATUS_NAMES = {0: "PG_OK", 1: "PG_EINVAL", 2: "PG_ENOMEM", 3: "PG_EDEVICE",
@@ -147,12 +148,14 @@ class Game:
     """A game loaded on the device (modified by preprocessing unless
     ``preprocess=False``; ``careful_walks=True`` sets PG_CAREFUL_WALKS,
     ``count_valuation=True`` PG_COUNT_VALUATION, ``graph=False``
-    PG_NO_GRAPH).  Games whose priorities repeat use count valuations by
-    themselves (``self.d > 0``)."""
+    PG_NO_GRAPH, ``host_reduced_list=True`` PG_HOST_REDUCED_LIST).  Games
+    whose priorities repeat use count valuations by themselves
+    (``self.d > 0``)."""
 
     def __init__(self, offsets, targets, owner, priority, n: int = None,
                  preprocess: bool = True, careful_walks: bool = False,
-                 count_valuation: bool = False, graph: bool = True):
+                 count_valuation: bool = False, graph: bool = True,
+                 host_reduced_list: bool = False):
         device = _is_torch(targets)
         if device:
             import torch
@@ -180,7 +183,8 @@ class Game:
             (PG_OFFSETS_I32 if off_i32 else 0) | \
             (PG_CAREFUL_WALKS if careful_walks else 0) | \
             (PG_COUNT_VALUATION if count_valuation else 0) | \
-            (0 if graph else PG_NO_GRAPH)
+            (0 if graph else PG_NO_GRAPH) | \
+            (PG_HOST_REDUCED_LIST if host_reduced_list else 0)
         h = ctypes.c_void_p()
         _check(lib().pg_load_csr(n, m, _ptr(offsets), _ptr(targets),
                                  _ptr(owner), _ptr(priority), flags,
@@ -199,10 +203,11 @@ class Game:
     @classmethod
     def from_dict(cls, g: dict, device: bool = False, preprocess: bool = True,
                   careful_walks: bool = False, count_valuation: bool = False,
-                  graph: bool = True):
+                  graph: bool = True, host_reduced_list: bool = False):
         kw = {"n": int(g["n"]), "preprocess": preprocess,
               "careful_walks": careful_walks,
-              "count_valuation": count_valuation, "graph": graph}
+              "count_valuation": count_valuation, "graph": graph,
+              "host_reduced_list": host_reduced_list}
         if device:
             import torch
             t = {k: torch.from_numpy(np.ascontiguousarray(g[k])).cuda()

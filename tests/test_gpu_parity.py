@@ -195,3 +195,22 @@ def test_best_response_from_strategy_outside_rows(pglib):
     np.testing.assert_array_equal(to_np(dtau), t)
     np.testing.assert_array_equal(to_np(dkey), key)
     assert dn == nval
+
+
+def test_host_reduced_list_split(pglib):
+    """PG_HOST_REDUCED_LIST (the host ranks the reduced list, the paper's
+    GPU-LR split): the same keys along a trajectory and the same solve."""
+    for n, seed, kind in [(3000, 21, "rnd"), (4000, 22, "chain")]:
+        g = synth.random_game(n, 2, 5, seed) if kind == "rnd" else \
+            synth.chain_game(n, seed)
+        aug = orc.preprocess(g)
+        _say("host reduced list", kind, n, seed)
+        with Game.from_dict(g, host_reduced_list=True) as dev:
+            traj = list(oracle_trajectory(aug))
+            for k in (0, len(traj) // 2, len(traj) - 1):
+                sigma, tau, key = traj[k]
+                dkey, nf = dev.valuation(sigma, tau)
+                np.testing.assert_array_equal(to_np(dkey), key,
+                                              err_msg=f"valuation {k}")
+        ref, out = _solve_both(g, host_reduced_list=True)
+        _assert_solve_equal(ref, out)
