@@ -33,7 +33,8 @@ same peak; the method's least bytes per iteration likewise; the counter
 bytes when they are current; and a measured 1 GiB copy rate), on c3
 "deep_list_valuation" (one valuation of a play through every vertex) and
 "cpu_baseline" (the CPU oracle timed on this host on a bounded sample of
-the same workload).  --best-response picks the best responses
+the same workload), with "cpu_lr_baseline" beside it for rank valuations
+(the multi-core CPU-LR baseline on the same sample).  --best-response picks the best responses
 (section 6's comparison: SI, SI-Reset, Bellman-Ford on count games).
 """
 from __future__ import annotations
@@ -179,15 +180,18 @@ def deep_list_valuation(arrs, n: int, reps: int = 5) -> dict:
             "n_aug": int(N), "reps": reps}
 
 
-def cpu_baseline(game: dict, iters: int = 3, counts: bool = False) -> dict:
+def cpu_baseline(game: dict, iters: int = 3, counts: bool = False):
     """The CPU oracle on this host: its preprocessing, then the first `iters`
     best-response iterations (valuation + All_Odd) of Algorithm 1 (with the
-    count-valuation oracle when `counts`)."""
+    count-valuation oracle when `counts`).  For rank valuations the
+    multi-core CPU-LR baseline (baselines/cpu_lr.c, the paper's CPU-LR) is
+    timed on the same iterations; returns (oracle, cpu_lr or None)."""
     from oracle import orc
     t0 = time.perf_counter()
     aug = orc.dense_preprocess(game) if counts else orc.preprocess(game)
     t_pre = time.perf_counter() - t0
     sigma, tau = orc.initial_strategies(aug)
+    sigma0, tau0 = sigma.copy(), tau.copy()
     by_pri = None if counts else orc.order_by_pri(aug["pri"])
     times = []
     for _ in range(iters):
@@ -203,13 +207,24 @@ def cpu_baseline(game: dict, iters: int = 3, counts: bool = False) -> dict:
         if c == 0:
             break
     t_iter = statistics.median(times)
-    return {"value": game["m"] / t_iter, "unit": "edges/s per best-response "
-            "iteration", "cores": 1, "kind": "oracle",
-            "sample": f"oracle preprocessing ({t_pre:.2f} s, not in value) "
-                      f"then {len(times)} best-response iterations "
-                      "(valuation + All_Odd) from the initial strategies, "
-                      f"median {t_iter:.3f} s each, single thread",
-            "host_cpu": _host_cpu()}
+    oracle = {"value": game["m"] / t_iter, "unit": "edges/s per "
+              "best-response iteration", "cores": 1, "kind": "oracle",
+              "sample": f"oracle preprocessing ({t_pre:.2f} s, not in value) "
+                        f"then {len(times)} best-response iterations "
+                        "(valuation + All_Odd) from the initial strategies, "
+                        f"median {t_iter:.3f} s each, single thread",
+              "host_cpu": _host_cpu()}
+    lr = None
+    if not counts:
+        from baselines import cpu_lr
+        r = cpu_lr.time_iterations(aug, sigma0, tau0, iters=len(times))
+        lr = {"value": game["m"] / r["seconds_median"],
+              "unit": "edges/s per best-response iteration",
+              "cores": r["threads"], "kind": "cpu-lr",
+              "sample": f"the same {len(times)} iterations on the same "
+                        "modified game, multi-core list ranking (OpenMP), "
+                        f"median {r['seconds_median']:.3f} s each"}
+    return oracle, lr
 
 
 def _host_cpu() -> str:
@@ -517,8 +532,8 @@ def main():
         line["deep_list_valuation"] = deep_list_valuation(arrs, game["n"])
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample of the same workload")
-        line["cpu_baseline"] = cpu_baseline(game,
-                                            counts=runs[0]["aug"][2] > 0)
+        line["cpu_baseline"], line["cpu_lr_baseline"] = cpu_baseline(
+            game, counts=runs[0]["aug"][2] > 0)
     else:
         line["cpu_baseline"] = None
     print(json.dumps(line), flush=True)
