@@ -370,7 +370,8 @@ int count_levels(int64_t n_aug, int dw);
 // Euler list and vector list ranking after the walks; gated by C_ABORT.
 void enqueue_count(pg_game *g, hipStream_t s);
 // All_Odd (odd) or All_Even on count valuations; counts into C_DIST_SW.
-void enqueue_count_switch(pg_game *g, bool odd, hipStream_t s);
+// fresh: the switch counters are still zero from this valuation's clearing
+void enqueue_count_switch(pg_game *g, bool odd, hipStream_t s, bool fresh);
 // Bellman-Ford best response against the sigma in g->sp: labels into
 // g->cnt, tau into g->sp, finite/top into g->rs; *rounds = Jacobi rounds.
 pg_status bf_best_response(pg_game *g, hipStream_t s, int64_t *rounds);

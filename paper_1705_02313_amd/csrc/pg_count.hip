@@ -768,10 +768,14 @@ void enqueue_count(pg_game *g, hipStream_t s) {
 }
 
 template <int D>
-static void enqueue_count_switch_t(pg_game *g, bool odd, hipStream_t s) {
+static void enqueue_count_switch_t(pg_game *g, bool odd, hipStream_t s,
+                                   bool fresh) {
   const int32_t N = (int32_t)g->n_aug;
   Prof *pf = &g->prof;
-  fill_i32(g->ctr + C_DIST_SW, 0, kDistSlots * kDistStride, s, pf);
+  if (!fresh) {
+    fill_i32(g->ctr + C_DIST_SW, 0, kDistSlots * kDistStride, s, pf);
+    fill_i32(g->ctr + C_SWITCH, 0, 1, s, pf);
+  }
   // per vertex: id 4, two offsets 16, current choice 8 (its row is one of
   // the row's); per edge: target 4, its top flag 1 and its count row 4 D
   if (odd) {
@@ -795,12 +799,12 @@ static void enqueue_count_switch_t(pg_game *g, bool odd, hipStream_t s) {
   sum_dist(g->ctr, C_DIST_SW, C_SWITCH, s, pf);
 }
 
-void enqueue_count_switch(pg_game *g, bool odd, hipStream_t s) {
+void enqueue_count_switch(pg_game *g, bool odd, hipStream_t s, bool fresh) {
   switch (g->dw) {
-    case 4: enqueue_count_switch_t<4>(g, odd, s); break;
-    case 8: enqueue_count_switch_t<8>(g, odd, s); break;
-    case 16: enqueue_count_switch_t<16>(g, odd, s); break;
-    default: enqueue_count_switch_t<32>(g, odd, s); break;
+    case 4: enqueue_count_switch_t<4>(g, odd, s, fresh); break;
+    case 8: enqueue_count_switch_t<8>(g, odd, s, fresh); break;
+    case 16: enqueue_count_switch_t<16>(g, odd, s, fresh); break;
+    default: enqueue_count_switch_t<32>(g, odd, s, fresh); break;
   }
 }
 

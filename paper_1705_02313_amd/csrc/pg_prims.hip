@@ -65,6 +65,18 @@ __global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
   for (; i < n; i += stride) p[i] = v;
 }
 
+// zeroes three ranges in one launch (the parent sort's work buffer)
+__global__ void k_zero3(int32_t *a, int64_t na, int32_t *b, int64_t nb,
+                        int32_t *c, int64_t nc) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < na + nb + nc; i += stride) {
+    if (i < na) a[i] = 0;
+    else if (i < na + nb) b[i - na] = 0;
+    else c[i - na - nb] = 0;
+  }
+}
+
 __global__ void k_fill_u8(uint8_t *p, uint8_t v, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -689,9 +701,14 @@ int parent_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
   uint32_t *ni = wctr + 5;
   const int32_t *gate = ctr + C_ABORT;
   *n_inner = ni;
-  fill_i32((int32_t *)wctr, 0, k1sCounters + k1sHistWords, s, prof);
-  fill_i32((int32_t *)status, 0, (int64_t)passes * tiles * 256, s, prof);
-  fill_i32((int32_t *)sstat, 0, 2 * tiles, s, prof);
+  {
+    const int64_t na = k1sCounters + k1sHistWords;
+    const int64_t nb = (int64_t)passes * tiles * 256, nc = 2 * tiles;
+    PG_LAUNCH(prof, K_FILL, 4.0 * (na + nb + nc), k_zero3,
+              dim3(capped_grid(na + nb + nc)), dim3(kBlock), 0, s,
+              (int32_t *)wctr, na, (int32_t *)status, nb, (int32_t *)sstat,
+              nc);
+  }
   // the digit passes alternate between the pairs and end in pair 0 after
   // an odd number of passes: the sink's children go straight to that pair
   const int fin = (passes & 1) ? 0 : 1;

@@ -813,10 +813,15 @@ static void enqueue_rank_emit(pg_game *g, hipStream_t s, bool device_reduced) {
             g->ctr);
 }
 
-static void enqueue_switch(pg_game *g, bool odd, hipStream_t s) {
+// fresh: the switch counters are still zero from the valuation's own
+// clearing (an iteration: walks, valuation, All_Odd in one sequence)
+static void enqueue_switch(pg_game *g, bool odd, hipStream_t s, bool fresh) {
   const int32_t N = (int32_t)g->n_aug;
   Prof *pf = &g->prof;
-  fill_i32(g->ctr + C_DIST_SW, 0, kDistSlots * kDistStride, s, pf);
+  if (!fresh) {
+    fill_i32(g->ctr + C_DIST_SW, 0, kDistSlots * kDistStride, s, pf);
+    fill_i32(g->ctr + C_SWITCH, 0, 1, s, pf);
+  }
   // per vertex: id 4, two offsets 16, current choice 8 (read and write
   // counted once; its key is one of the row's) -> 28; per edge: target 4
   // and its key 4
@@ -889,9 +894,10 @@ static pg_status values(pg_game *g, hipStream_t s) {
   return PG_OK;
 }
 
-static void enqueue_any_switch(pg_game *g, bool odd, hipStream_t s) {
-  if (g->dense) enqueue_count_switch(g, odd, s);
-  else enqueue_switch(g, odd, s);
+static void enqueue_any_switch(pg_game *g, bool odd, hipStream_t s,
+                               bool fresh) {
+  if (g->dense) enqueue_count_switch(g, odd, s, fresh);
+  else enqueue_switch(g, odd, s, fresh);
 }
 
 static pg_status check_ctr(pg_game *g) {
@@ -920,8 +926,7 @@ static pg_status capture_iteration(pg_game *g, hipGraphExec_t *ex) {
   PG_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
   enqueue_walks(g, cs);
   enqueue_values(g, cs);
-  fill_i32(g->ctr + C_SWITCH, 0, 1, cs, &g->prof);
-  enqueue_any_switch(g, true, cs);
+  enqueue_any_switch(g, true, cs, true);
   hipGraph_t gr = nullptr;
   hipError_t e = hipStreamEndCapture(cs, &gr);
   if (e == hipSuccess) e = hipGraphInstantiate(ex, gr, nullptr, nullptr, 0);
@@ -956,8 +961,7 @@ static pg_status run_valuation(pg_game *g, hipStream_t s, bool odd_switch,
     else enqueue_walks(g, s);
     PG_TRY(values(g, s));
     if (odd_switch) {
-      fill_i32(g->ctr + C_SWITCH, 0, 1, s, &g->prof);
-      enqueue_any_switch(g, true, s);
+      enqueue_any_switch(g, true, s, true);
     }
   }
   pg_status st = read_ctr(g, s);
@@ -970,8 +974,7 @@ static pg_status run_valuation(pg_game *g, hipStream_t s, bool odd_switch,
     st = values(g, s);
     if (st != PG_OK) return st;
     if (odd_switch) {
-      fill_i32(g->ctr + C_SWITCH, 0, 1, s, &g->prof);
-      enqueue_any_switch(g, true, s);
+      enqueue_any_switch(g, true, s, true);
     }
     st = read_ctr(g, s);
     if (st != PG_OK) return st;
@@ -993,9 +996,8 @@ pg_status iteration_device(pg_game *g, hipStream_t s, int32_t *count) {
 }
 
 pg_status switch_device(pg_game *g, bool odd, hipStream_t s, int32_t *count) {
-  fill_i32(g->ctr + C_SWITCH, 0, 1, s, &g->prof);
   fill_i32(g->ctr + C_ABORT, 0, 1, s, &g->prof);
-  enqueue_any_switch(g, odd, s);
+  enqueue_any_switch(g, odd, s, false);
   pg_status st = read_ctr(g, s);
   if (st != PG_OK) return st;
   *count = g->hctr[C_SWITCH];
