@@ -371,8 +371,16 @@ pg_status pg_batch_info(const pg_batch *batch, int32_t *n_live,
                         int64_t *arena_edges);
 pg_status pg_batch_free(pg_batch *batch);
 
-/* Release the game's device memory.  NULL is accepted. */
+/* Release the game.  NULL is accepted.  Its device and pinned host memory
+ * goes to a per-device cache that later pg_load_csr calls on that device
+ * take their memory from (blocks are returned only after the device has
+ * finished with them), so loading many games does not pay hipMalloc and
+ * hipFree for each. */
 pg_status pg_free(pg_game *game);
+
+/* Hand the cached memory of freed games back to the HIP runtime (every
+ * device).  Memory of games still loaded is not touched. */
+pg_status pg_release_cache(void);
 
 /* Description of the calling thread's last error ("" if none). */
 const char *pg_last_error(void);

@@ -409,6 +409,7 @@ pg_status copy_out(void *dst, const void *src, size_t bytes, bool device,
 thread_local DevPool *tl_pool = nullptr;
 
 pg_status DevPool::alloc(void **p, size_t bytes, bool host) {
+  std::lock_guard<std::mutex> lock(mu);
   const size_t b = bucket(bytes);
   auto &fl = host ? host_free[b] : dev_free[b];
   if (!fl.empty()) {
@@ -428,6 +429,7 @@ pg_status DevPool::alloc(void **p, size_t bytes, bool host) {
 }
 
 bool DevPool::release(void *p) {
+  std::lock_guard<std::mutex> lock(mu);
   auto it = dev_size.find(p);
   if (it != dev_size.end()) {
     dev_free[it->second].push_back(p);
@@ -441,7 +443,49 @@ bool DevPool::release(void *p) {
   return false;
 }
 
+void DevPool::trim() {
+  std::lock_guard<std::mutex> lock(mu);
+  for (auto &kv : dev_free)
+    for (void *p : kv.second) {
+      (void)hipFree(p);
+      dev_size.erase(p);
+    }
+  for (auto &kv : host_free)
+    for (void *p : kv.second) {
+      (void)hipHostFree(p);
+      host_size.erase(p);
+    }
+  dev_free.clear();
+  host_free.clear();
+}
+
+// One cache per device, kept until the process ends.  Single games allocate
+// from it and pg_free returns their memory to it; a block goes back only
+// after the work that used it has finished (every return follows a
+// synchronisation), so a load on another thread's stream may reuse it.
+static std::mutex g_cache_mu;
+static std::map<int, DevPool *> g_caches;
+
+DevPool *game_cache(int device) {
+  std::lock_guard<std::mutex> lock(g_cache_mu);
+  DevPool *&c = g_caches[device];
+  if (!c) c = new DevPool();
+  return c;
+}
+
+static void trim_caches() {
+  std::lock_guard<std::mutex> lock(g_cache_mu);
+  int prev = -1;
+  (void)hipGetDevice(&prev);
+  for (auto &kv : g_caches) {
+    (void)hipSetDevice(kv.first);
+    kv.second->trim();
+  }
+  if (prev >= 0) (void)hipSetDevice(prev);
+}
+
 void DevPool::clear() {
+  std::lock_guard<std::mutex> lock(mu);
   for (auto &kv : dev_size) (void)hipFree(kv.first);
   for (auto &kv : host_size) (void)hipHostFree(kv.first);
   dev_size.clear();
@@ -961,6 +1005,7 @@ pg_status pg_load_csr(int64_t n, int64_t m, const void *offsets,
     return pg_fail(PG_EDEVICE, "no HIP device");
   }
   hipStream_t s = (hipStream_t)hip_stream;
+  PoolScope cache(game_cache(g->device));
   // count valuations when asked for or when the priorities repeat
   pg_status st =
       load_modified(n, m, offsets, targets, owner, priority, flags, s, g,
@@ -1004,6 +1049,7 @@ pg_status pg_export_game(const pg_game *gc, int64_t *offsets, int32_t *targets,
   if (!gc) return pg_fail(PG_EINVAL, "game is NULL");
   pg_game *g = const_cast<pg_game *>(gc);
   DevGuard guard(g->device);
+  PoolScope cache(game_cache(g->device));
   hipStream_t s = (hipStream_t)hip_stream;
   const bool dev = flags & PG_PTR_DEVICE;
   // a relabeled game goes back to the caller's vertex ids first
@@ -1076,6 +1122,7 @@ pg_status pg_valuation(pg_game *g, const int32_t *sigma, const int32_t *tau,
     return pg_fail(PG_EINVAL, "a count-valuation game has no rank keys: use "
                               "pg_valuation_counts");
   DevGuard guard(g->device);
+  PoolScope cache(game_cache(g->device));
   hipStream_t s = (hipStream_t)hip_stream;
   const bool dev = flags & PG_PTR_DEVICE;
   PG_TRY(import_strats(g, sigma, tau, dev, s));
@@ -1096,6 +1143,7 @@ pg_status pg_valuation_counts(pg_game *g, const int32_t *sigma,
   if (!g->dense)
     return pg_fail(PG_EINVAL, "not a count-valuation game: use pg_valuation");
   DevGuard guard(g->device);
+  PoolScope cache(game_cache(g->device));
   hipStream_t s = (hipStream_t)hip_stream;
   const bool dev = flags & PG_PTR_DEVICE;
   PG_TRY(import_strats(g, sigma, tau, dev, s));
@@ -1115,6 +1163,7 @@ pg_status pg_best_response(pg_game *g, const int32_t *sigma, int32_t *tau,
     return pg_fail(PG_EINVAL, "a count-valuation game has no rank keys: "
                               "pass key = NULL");
   DevGuard guard(g->device);
+  PoolScope cache(game_cache(g->device));
   hipStream_t s = (hipStream_t)hip_stream;
   const bool dev = flags & PG_PTR_DEVICE;
   PG_TRY(import_strats(g, sigma, tau, dev, s));
@@ -1135,6 +1184,7 @@ pg_status pg_solve(pg_game *g, const pg_solve_opts *opts, uint8_t *winner,
   if (!g) return pg_fail(PG_EINVAL, "game is NULL");
   if (!winner) return pg_fail(PG_EINVAL, "winner is NULL");
   DevGuard guard(g->device);
+  PoolScope cache(game_cache(g->device));
   hipStream_t s = (hipStream_t)hip_stream;
   pg_solve_opts o{};
   if (opts) o = *opts;
@@ -1220,8 +1270,14 @@ pg_status pg_profile_read(const pg_game *g, int32_t kind, const char **name,
 pg_status pg_free(pg_game *g) {
   if (!g) return PG_OK;
   DevGuard guard(g->device);
+  PoolScope cache(game_cache(g->device));
   (void)hipDeviceSynchronize();
   free_game(g);
+  return PG_OK;
+}
+
+pg_status pg_release_cache(void) {
+  trim_caches();
   return PG_OK;
 }
 

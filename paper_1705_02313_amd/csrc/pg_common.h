@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <map>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -388,6 +389,7 @@ namespace pgk {
 // come back from them instead of from hipMalloc.  Everything is released by
 // clear() when the batch is freed.
 struct DevPool {
+  std::mutex mu;           // calls on different games may overlap
   std::map<size_t, std::vector<void *>> dev_free, host_free;
   std::unordered_map<void *, size_t> dev_size, host_size;
   static size_t bucket(size_t bytes) {
@@ -397,8 +399,12 @@ struct DevPool {
   }
   pg_status alloc(void **p, size_t bytes, bool host);
   bool release(void *p);   // false: not a block of this pool
-  void clear();
+  void clear();            // every block, in use or not
+  void trim();             // the blocks not in use
 };
+// The cache of the calling thread's current device that single games
+// allocate from and return their memory to (see pg_release_cache).
+DevPool *game_cache(int device);
 // allocations of the calling thread go to this pool while it is set
 extern thread_local DevPool *tl_pool;
 struct PoolScope {

@@ -35,7 +35,13 @@ EXPORTS = ["pg_load_csr", "pg_game_info", "pg_count_info", "pg_export_game",
            "pg_profile_read", "pg_batch_create", "pg_batch_submit",
            "pg_batch_step", "pg_batch_poll", "pg_batch_finished",
            "pg_batch_info", "pg_batch_free",
-           "pg_free", "pg_last_error"]
+           "pg_free", "pg_release_cache", "pg_last_error"]
+
+
+def release_cache():
+    """Hands the memory that freed games left cached back to the runtime
+    (pg_release_cache)."""
+    _check(lib().pg_release_cache())
 
 
 class PgError(RuntimeError):
@@ -94,6 +100,7 @@ def lib() -> ctypes.CDLL:
                                        U32, P]
         L.pg_solve.argtypes = [P, ctypes.POINTER(SolveOpts), P, P, P,
                                ctypes.POINTER(Stats), P]
+        L.pg_release_cache.argtypes = []
         L.pg_profile_enable.argtypes = [P, I32]
         L.pg_profile_kinds.argtypes = []
         L.pg_profile_read.argtypes = [P, I32, ctypes.POINTER(ctypes.c_char_p),

@@ -214,3 +214,21 @@ def test_host_reduced_list_split(pglib):
                                               err_msg=f"valuation {k}")
         ref, out = _solve_both(g, host_reduced_list=True)
         _assert_solve_equal(ref, out)
+
+
+def test_memory_cache_reuse_and_release(pglib):
+    """Freed games leave their memory to a per-device cache that later
+    loads reuse: games of changing sizes, one after another, each equal to
+    the oracle; after pg_release_cache loads still work."""
+    from paper_1705_02313_amd import pg
+    for i, n in enumerate([5000, 800, 12000, 800, 5000]):
+        g = synth.random_game(n, 2, 6, 300 + i)
+        _say("cache reuse", n)
+        ref, out = _solve_both(g)
+        _assert_solve_equal(ref, out)
+        if i == 2:
+            pg.release_cache()
+    pg.release_cache()
+    g = synth.chain_game(3000, 9)
+    ref, out = _solve_both(g)
+    _assert_solve_equal(ref, out)
