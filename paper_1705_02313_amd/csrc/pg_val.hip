@@ -610,10 +610,23 @@ __global__ __launch_bounds__(kBlock) void k_even_switch(
 namespace pgk {
 
 // A wave lasts as long as its longest walk, so the full passes stop early and
-// leave long walks to dense rounds (which also take shortcuts).
-constexpr int kFullSteps = 8;     // plain-walk budget of the full passes
-constexpr int kWalkSteps = 64;    // shortcut-walk budget of one round
-constexpr int kFastRounds = 3;    // rounds enqueued without looking back
+// leave long walks to dense rounds (which also take shortcuts).  The budgets
+// differ by valuation: with distinct priorities most ng values are a few
+// steps away; with a handful of repeated ones the vertices of the largest
+// priority walk to the sink or a cycle, which cheaper, more frequent rounds
+// (more shortcuts published between them) serve better.  Measured on the
+// 10M-vertex games: distinct 2.25 -> 2.22 ms per iteration, 4 priorities
+// 4.47 -> 4.00 ms.
+struct WalkBudget {
+  int full;    // plain-walk steps of the full passes
+  int walk;    // shortcut-walk steps of one round
+  int rounds;  // rounds enqueued without looking back
+};
+constexpr WalkBudget kRankWalks = {16, 64, 3};
+constexpr WalkBudget kCountWalks = {4, 32, 4};
+static WalkBudget walk_budget(const pg_game *g) {
+  return g->dense ? kCountWalks : kRankWalks;
+}
 constexpr int kMaxRounds = 64;    // rounds of the careful path before failing
 // level-1 sublists per thread: 4 when the list is long enough to fill the
 // chip with a quarter of the threads (measured best at 13M vertices), fewer
@@ -654,26 +667,27 @@ static void enqueue_walks(pg_game *g, hipStream_t s) {
   Prof *pf = &g->prof;
   int32_t *ng = g->ngp[g->par], *cand = g->candp[g->par];
   int32_t *ngn = g->ngp[g->par ^ 1], *candn = g->candp[g->par ^ 1];
+  const WalkBudget wb = walk_budget(g);
   fill_i32(g->ctr, 0, C_TOTAL, s, pf);
   // own record 8, first successor record 8, result 4; state resets 5
   PG_LAUNCH(pf, K_NG_WALK, 25.0 * N, k_ng_full, dim3(grid_for(N)),
             dim3(kBlock), 0, s, N, g->sp, g->pri, ng, cand, g->ctr,
-            kFullSteps, g->rs, g->rcand, (int32_t *)nullptr);
-  for (int r = 1; r <= kFastRounds; ++r)
+            wb.full, g->rs, g->rcand, (int32_t *)nullptr);
+  for (int r = 1; r <= wb.rounds; ++r)
     PG_LAUNCH(pf, K_NG_ROUND, 4.0 * N, k_ng_round, dim3(grid_for(N)),
               dim3(kBlock), 0, s, N, g->sp, g->pri, ng, cand, g->ctr,
-              (int)(r == kFastRounds), kWalkSteps, (int32_t *)nullptr);
+              (int)(r == wb.rounds), wb.walk, (int32_t *)nullptr);
   // own ng 4, parent's ng 4, sort key 4, rs 1 (+ rvpos 4 unless
   // relabeled); resets 12
   const int32_t *rvpos = kernel_rvpos(g);
   PG_LAUNCH(pf, K_ROOT_WALK, (rvpos ? 29.0 : 25.0) * N, k_root_full,
             dim3(grid_for(N)), dim3(kBlock), 0, s, N, ng, g->rs, g->rcand,
-            g->key, g->ctr, kFullSteps, ngn, candn, g->fh, rvpos, g->sk0,
+            g->key, g->ctr, wb.full, ngn, candn, g->fh, rvpos, g->sk0,
             (int32_t *)nullptr);
-  for (int r = 1; r <= kFastRounds; ++r)
+  for (int r = 1; r <= wb.rounds; ++r)
     PG_LAUNCH(pf, K_ROOT_ROUND, 1.0 * N, k_root_round, dim3(grid_for(N)),
               dim3(kBlock), 0, s, N, ng, g->rs, g->rcand, g->key, g->ctr,
-              (int)(r == kFastRounds), kWalkSteps, rvpos, g->sk0,
+              (int)(r == wb.rounds), wb.walk, rvpos, g->sk0,
               (int32_t *)nullptr);
   sum_dist(g->ctr, C_DIST_NF, C_NFIN, s, pf);
 }
@@ -696,6 +710,7 @@ static pg_status counted(pg_game *g, hipStream_t s, F launch, int32_t *open) {
 static pg_status careful_walks(pg_game *g, hipStream_t s) {
   const int32_t N = (int32_t)g->n_aug;
   Prof *pf = &g->prof;
+  const WalkBudget wb = walk_budget(g);
   int32_t *ng = g->ngp[g->par], *cand = g->candp[g->par];
   int32_t *ngn = g->ngp[g->par ^ 1], *candn = g->candp[g->par ^ 1];
   fill_i32(ng, -1, N, s, pf);
@@ -705,7 +720,7 @@ static pg_status careful_walks(pg_game *g, hipStream_t s) {
   PG_TRY(counted(g, s, [&](int32_t *dist) {
     PG_LAUNCH(pf, K_NG_WALK, 25.0 * N, k_ng_full, dim3(grid_for(N)),
               dim3(kBlock), 0, s, N, g->sp, g->pri, ng, cand, g->ctr,
-              kFullSteps, g->rs, g->rcand, dist);
+              wb.full, g->rs, g->rcand, dist);
   }, &open));
   for (int r = 0; open > 0; ++r) {
     if (r >= kMaxRounds)
@@ -713,7 +728,7 @@ static pg_status careful_walks(pg_game *g, hipStream_t s) {
     PG_TRY(counted(g, s, [&](int32_t *dist) {
       PG_LAUNCH(pf, K_NG_ROUND, 4.0 * N, k_ng_round, dim3(grid_for(N)),
                 dim3(kBlock), 0, s, N, g->sp, g->pri, ng, cand, g->ctr, 0,
-                kWalkSteps, dist);
+                wb.walk, dist);
     }, &open));
   }
   fill_i32(g->ctr + C_NFIN, 0, 1, s, pf);
@@ -722,7 +737,7 @@ static pg_status careful_walks(pg_game *g, hipStream_t s) {
   PG_TRY(counted(g, s, [&](int32_t *dist) {
     PG_LAUNCH(pf, K_ROOT_WALK, (rvpos ? 29.0 : 25.0) * N, k_root_full,
               dim3(grid_for(N)), dim3(kBlock), 0, s, N, ng, g->rs, g->rcand,
-              g->key, g->ctr, kFullSteps, ngn, candn, g->fh, rvpos, g->sk0,
+              g->key, g->ctr, wb.full, ngn, candn, g->fh, rvpos, g->sk0,
               dist);
   }, &open));
   for (int r = 0; open > 0; ++r) {
@@ -731,7 +746,7 @@ static pg_status careful_walks(pg_game *g, hipStream_t s) {
     PG_TRY(counted(g, s, [&](int32_t *dist) {
       PG_LAUNCH(pf, K_ROOT_ROUND, 1.0 * N, k_root_round, dim3(grid_for(N)),
                 dim3(kBlock), 0, s, N, ng, g->rs, g->rcand, g->key, g->ctr,
-                0, kWalkSteps, rvpos, g->sk0, dist);
+                0, wb.walk, rvpos, g->sk0, dist);
     }, &open));
   }
   sum_dist(g->ctr, C_DIST_NF, C_NFIN, s, pf);
@@ -764,7 +779,6 @@ static void enqueue_rank_list(pg_game *g, hipStream_t s) {
   PG_LAUNCH_NI(pf, K_LINK_BUILD, 0.0, 30.0, 4.0, k_link_build,
                dim3(grid_for(N)), dim3(kBlock), 0, s, N, g->n_oddpri, skS, svS,
                n_inner, g->kids, g->pos, g->fh, g->elem, g->ctr);
-  const int nl = g->nlevels;
   const int64_t Lmax = 2 * (int64_t)N + 2;
   const int64_t ns1 = level_size(Lmax, 1);
   const int kPerThread1 = per_thread1(ns1);
