@@ -327,7 +327,10 @@ pg_status pg_profile_read(const pg_game *game, int32_t kind, const char **name,
  *
  * pg_batch_create  an arena for up to max_vertices / max_edges of modified
  *                  games (the HBM footprint budget) and max_games games.
- * pg_batch_submit  validates and preprocesses one game (arguments as
+ * pg_batch_submit  (may be called from another thread than the other
+ *                  pg_batch_* calls: it works on a stream of the batch's
+ *                  own and takes the batch's lock only to queue the game)
+ *                  validates and preprocesses one game (arguments as
  *                  pg_load_csr) and queues it; returns a ticket.  PG_ENOMEM
  *                  if the game alone exceeds the arena; PG_EINVAL for
  *                  repeated priorities (batches take games with rank
@@ -336,10 +339,13 @@ pg_status pg_profile_read(const pg_game *game, int32_t kind, const char **name,
  *                  a step where they fit beside the games already in it.  A
  *                  game's memory comes from a pool that the batch keeps
  *                  until pg_batch_free.
- * pg_batch_step    admits queued games that fit (and drops finished ones
- *                  when they hold a quarter of the arena), then advances
- *                  every live game once.  Outputs (nullable): games running,
- *                  games queued, games finished by this step.
+ * pg_batch_step    lays the arena out again when finished games hold a
+ *                  quarter of it, or to admit queued games that fit: once
+ *                  they add up to an eighth of the arena's vertices, once
+ *                  one has waited 8 steps, or when no game is running; then
+ *                  advances every live game once.  Outputs (nullable):
+ *                  games running, games queued, games finished by this
+ *                  step.
  * pg_batch_poll    done = 1 once the game has finished; then writes its
  *                  winner (n), sigma and tau (n_aug, as pg_solve) and
  *                  stats, and releases the ticket.  flags: PG_PTR_DEVICE for

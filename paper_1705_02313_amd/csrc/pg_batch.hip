@@ -382,6 +382,12 @@ void free_bgame(BGame *b) {
 struct pg_batch {
   int device = 0;
   hipStream_t stream = nullptr;
+  // Submissions may run on another thread while steps run: they preprocess
+  // on a stream of their own, in memory of their own (the pool is
+  // thread-safe), and take `mu` only to queue the finished game; steps,
+  // polls and queries hold `mu` throughout.
+  hipStream_t sub_stream = nullptr;
+  std::mutex mu;
   int64_t cap_v = 0, cap_e = 0;
   int max_games = 0;
   pg_game *arena = nullptr;
@@ -392,6 +398,7 @@ struct pg_batch {
   std::vector<BGame *> grave;      // left the arena; freed at the next rebuild
   DevPool pool;                    // memory of the submitted games
   int64_t done_vertices = 0;       // arena vertices of finished games
+  int64_t queued_steps = 0;        // steps taken while a fitting game waited
   // per-slot device state
   GameDesc *d_desc = nullptr;
   // [2 G] first arena vertex / edge of each segment (odd parts by
@@ -419,6 +426,7 @@ pg_status batch_alloc(pg_batch *b) {
   b->arena = a;
   a->device = b->device;
   a->relabeled = true;   // arena ids are signed-order positions
+  PG_HIP(hipStreamCreateWithFlags(&b->sub_stream, hipStreamNonBlocking));
   PG_HIP(hipHostMalloc((void **)&a->hctr, sizeof(int32_t) * C_COUNT,
                        hipHostMallocDefault));
   PG_TRY(dev_alloc(&a->ctr, C_TOTAL));
@@ -452,6 +460,10 @@ pg_status batch_alloc(pg_batch *b) {
 
 void batch_release(pg_batch *b) {
   if (!b) return;
+  if (b->sub_stream) {
+    (void)hipStreamSynchronize(b->sub_stream);
+    (void)hipStreamDestroy(b->sub_stream);
+  }
   {
     PoolScope ps(&b->pool);
     for (auto &kv : b->games) free_bgame(kv.second);
@@ -667,7 +679,7 @@ pg_status pg_batch_submit(pg_batch *b, int64_t n, int64_t m,
                           uint32_t flags, int64_t *ticket) {
   if (!b || !ticket) return pg_fail(PG_EINVAL, "NULL argument");
   if (n < 1 || m < n) return pg_fail(PG_EINVAL, "need n >= 1 and m >= n");
-  hipStream_t s = b->stream;
+  hipStream_t s = b->sub_stream;
   PoolScope ps(&b->pool);   // the game's memory comes from the batch's pool
   BGame *bg = new (std::nothrow) BGame();
   if (!bg) return pg_fail(PG_ENOMEM, "host allocation failed");
@@ -687,32 +699,56 @@ pg_status pg_batch_submit(pg_batch *b, int64_t n, int64_t m,
   if (st == PG_OK) st = dev_alloc(&bg->res_tau, bg->g->n_aug);
   if (st == PG_OK) st = dev_alloc(&bg->rvperm, bg->g->n_aug);
   if (st == PG_OK) st = dev_alloc(&bg->rvrank, bg->g->n_aug);
+  // the submission's own scratch (steps may be using the arena's)
+  struct Scratch {
+    uint32_t *k0 = nullptr, *v0 = nullptr, *k1 = nullptr, *v1 = nullptr;
+    uint32_t *tc = nullptr;
+    uint8_t *st = nullptr;
+    int64_t *i64 = nullptr;   // [3] max priority, Odd-row edges, even split
+    ~Scratch() {
+      for (void *p : {(void *)k0, (void *)v0, (void *)k1, (void *)v1,
+                      (void *)tc, (void *)st, (void *)i64})
+        dev_free(p);
+    }
+  } sc;
+  if (st == PG_OK) {
+    const int64_t N = bg->g->n_aug;
+    st = dev_alloc(&sc.k0, N);
+    if (st == PG_OK) st = dev_alloc(&sc.v0, N);
+    if (st == PG_OK) st = dev_alloc(&sc.k1, N);
+    if (st == PG_OK) st = dev_alloc(&sc.v1, N);
+    if (st == PG_OK) st = dev_alloc(&sc.tc, 256 * radix_tiles(N));
+    if (st == PG_OK)
+      st = dev_alloc(&sc.st, (int64_t)radix_scan_tmp_bytes(N) + 16);
+    if (st == PG_OK) st = dev_alloc(&sc.i64, 3);
+  }
   if (st == PG_OK) {
     // the largest priority (for the arena offsets), the game's own
-    // signed-priority order (sorted in the arena's sort buffers: calls on
-    // one batch do not overlap, so no step is using them now; a repeated
-    // priority is an error), and its Odd vertex and edge counts
-    pg_game *a = b->arena;
+    // signed-priority order (a repeated priority is an error), and its Odd
+    // vertex and edge counts
     pg_game *gg = bg->g;
     const int64_t N = gg->n_aug;
+    int32_t *d_max = (int32_t *)sc.i64;
+    unsigned long long *d_me = (unsigned long long *)(sc.i64 + 1);
+    int64_t *d_es = sc.i64 + 2;
     fill_i32(gg->ctr, 0, C_TOTAL, s);
-    fill_i32(b->d_i32, -1, 1, s);
+    fill_i32((int32_t *)sc.i64, 0, 6, s);
+    fill_i32(d_max, -1, 1, s);
     hipLaunchKernelGGL(k_max_i32, dim3(256), dim3(kBlock), 0, s, gg->pri, N,
-                       b->d_i32);
+                       d_max);
     hipLaunchKernelGGL(k_rv_keys, dim3(grid_for(N)), dim3(kBlock), 0, s,
-                       gg->pri, a->sk0, a->sv0, N);
-    const int w = radix_sort(a->sk0, a->sv0, a->sk1, a->sv1, N, 32,
-                             a->tile_cnt, a->scan_tmp, s);
+                       gg->pri, sc.k0, sc.v0, N);
+    const int w = radix_sort(sc.k0, sc.v0, sc.k1, sc.v1, N, 32, sc.tc, sc.st,
+                             s);
     hipLaunchKernelGGL(k_rv_finish, dim3(grid_for(N)), dim3(kBlock), 0, s,
-                       w ? a->sk1 : a->sk0, w ? a->sv1 : a->sv0, bg->rvperm,
+                       w ? sc.k1 : sc.k0, w ? sc.v1 : sc.v0, bg->rvperm,
                        bg->rvrank, N, 1, gg->ctr);
     sum_dist(gg->ctr, C_DIST_MISC, C_MISC, s);
     hipLaunchKernelGGL(k_count_owner_odd, dim3(grid_for(N)), dim3(kBlock), 0,
                        s, gg->owner, N, gg->ctr);
     sum_dist(gg->ctr, C_DIST_NF, C_NFIN, s);
-    fill_i32((int32_t *)a->u64tmp, 0, 2, s);
     hipLaunchKernelGGL(k_count_odd_edges, dim3(256), dim3(kBlock), 0, s,
-                       gg->off, gg->owner, N, a->u64tmp);
+                       gg->off, gg->owner, N, d_me);
     // the game is stored in its signed order from here on (its rows keep
     // their edge order); the even-priority rows start at off[n_oddpri]
     int64_t *off2 = nullptr;
@@ -731,17 +767,16 @@ pg_status pg_batch_submit(pg_batch *b, int64_t n, int64_t m,
       gg->pri = pri2;
       gg->relabeled = true;
       hipLaunchKernelGGL(k_part_edge, dim3(1), dim3(1), 0, s, gg->off,
-                         gg->ctr, (int64_t *)(a->u64tmp + 1));
+                         gg->ctr, d_es);
     }
     int32_t mx = 0;
     unsigned long long me = 0;
     int64_t es = 0;
-    hipError_t e = hipMemcpyAsync(&mx, b->d_i32, 4, hipMemcpyDeviceToHost, s);
+    hipError_t e = hipMemcpyAsync(&mx, d_max, 4, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess)
-      e = hipMemcpyAsync(&me, a->u64tmp, sizeof(me), hipMemcpyDeviceToHost, s);
+      e = hipMemcpyAsync(&me, d_me, sizeof(me), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess)
-      e = hipMemcpyAsync(&es, a->u64tmp + 1, sizeof(es),
-                         hipMemcpyDeviceToHost, s);
+      e = hipMemcpyAsync(&es, d_es, sizeof(es), hipMemcpyDeviceToHost, s);
     if (e != hipSuccess && st == PG_OK)
       st = pg_fail(PG_EDEVICE, hipGetErrorString(e));
     if (st == PG_OK) st = sync_ctr(gg, s);
@@ -758,11 +793,12 @@ pg_status pg_batch_submit(pg_batch *b, int64_t n, int64_t m,
     free_bgame(bg);
     return st;
   }
-  bg->ticket = b->next_ticket++;
   bg->st.n = n;
   bg->st.m = m;
   bg->st.n_aug = bg->g->n_aug;
   bg->st.m_aug = bg->g->m_aug;
+  std::lock_guard<std::mutex> lock(b->mu);
+  bg->ticket = b->next_ticket++;
   b->games[bg->ticket] = bg;
   b->queue.push_back(bg);
   *ticket = bg->ticket;
@@ -772,27 +808,49 @@ pg_status pg_batch_submit(pg_batch *b, int64_t n, int64_t m,
 pg_status pg_batch_step(pg_batch *b, int32_t *n_live, int32_t *n_queued,
                         int32_t *n_finished) {
   if (!b) return pg_fail(PG_EINVAL, "batch is NULL");
+  std::lock_guard<std::mutex> lock(b->mu);
   hipStream_t s = b->stream;
   pg_game *a = b->arena;
-  // rebuild when queued games can come in or finished games hold a quarter
-  // of the arena
+  // Rebuild when finished games hold a quarter of the arena, or to admit
+  // queued games: once those that fit (first come, first served) add up to
+  // an eighth of the arena's vertices, once a fitting game has waited
+  // kAdmitSteps steps, or when nothing is live.  A rebuild costs about a
+  // step, so admitting one small game per step would double the steps'
+  // cost under a steady stream of arrivals.
+  constexpr int64_t kAdmitSteps = 8;
   int64_t live_v = 0, live_e = 0;
+  int running = 0;
   for (BGame *g : b->built)
     if (g->state == B_LIVE) {
       live_v += g->g->n_aug;
       live_e += g->g->m_aug;
+      ++running;
     }
   bool admit = false;
   if (!b->queue.empty()) {
-    BGame *q = b->queue.front();
-    admit = live_v + q->g->n_aug <= b->cap_v &&
-            live_e + q->g->m_aug <= b->cap_e;
+    int64_t v = live_v, e = live_e, add_v = 0;
+    int fit = 0;
+    for (BGame *q : b->queue) {
+      if (v + q->g->n_aug > b->cap_v || e + q->g->m_aug > b->cap_e ||
+          running + fit >= b->max_games)
+        break;
+      v += q->g->n_aug;
+      e += q->g->m_aug;
+      add_v += q->g->n_aug;
+      ++fit;
+    }
+    if (fit > 0) {
+      admit = 8 * add_v >= b->cap_v || b->queued_steps >= kAdmitSteps ||
+              running == 0;
+      if (!admit) ++b->queued_steps;
+    }
   }
   const bool shrink = a->n_aug > 0 && 4 * b->done_vertices >= a->n_aug;
   const bool empty = live_v == 0;
   if (admit || shrink || (empty && !b->built.empty())) {
     bool any = false;
     PG_TRY(rebuild(b, &any));
+    b->queued_steps = 0;
   }
   int32_t finished = 0;
   const int G = (int)b->built.size();
@@ -859,6 +917,7 @@ pg_status pg_batch_poll(pg_batch *b, int64_t ticket, int32_t *done,
                         uint8_t *winner, int32_t *sigma, int32_t *tau,
                         pg_stats *stats, uint32_t flags) {
   if (!b || !done) return pg_fail(PG_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lock(b->mu);
   auto it = b->games.find(ticket);
   if (it == b->games.end()) return pg_fail(PG_EINVAL, "unknown ticket");
   BGame *g = it->second;
@@ -885,6 +944,7 @@ pg_status pg_batch_poll(pg_batch *b, int64_t ticket, int32_t *done,
 pg_status pg_batch_finished(const pg_batch *b, int64_t *tickets,
                             int32_t capacity, int32_t *count) {
   if (!b || !count) return pg_fail(PG_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lock(const_cast<pg_batch *>(b)->mu);
   int32_t c = 0;
   for (const auto &kv : b->games) {
     const BGame *g = kv.second;
@@ -901,6 +961,7 @@ pg_status pg_batch_info(const pg_batch *b, int32_t *n_live,
                         int32_t *n_queued, int64_t *arena_vertices,
                         int64_t *arena_edges) {
   if (!b) return pg_fail(PG_EINVAL, "batch is NULL");
+  std::lock_guard<std::mutex> lock(const_cast<pg_batch *>(b)->mu);
   int32_t c = 0;
   for (BGame *g : b->built) c += g->state == B_LIVE;
   if (n_live) *n_live = c;

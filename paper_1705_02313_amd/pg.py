@@ -363,10 +363,10 @@ class Batch:
         _check(lib().pg_batch_create(max_vertices, max_edges, max_games,
                                      stream, ctypes.byref(h)))
         self._h = h
-        self._sizes = {}
 
     def submit(self, g: dict, device: bool = False) -> int:
-        """Queues a game (dict as produced by synth); returns its ticket."""
+        """Queues a game (dict as produced by synth); returns its ticket.
+        May run on another thread than step() (pg_batch_submit)."""
         if device:
             import torch
             arr = {k: torch.from_numpy(np.ascontiguousarray(g[k])).cuda()
@@ -393,7 +393,6 @@ class Batch:
                                      _ptr(arr["targets"]), _ptr(arr["owner"]),
                                      _ptr(arr["pri"]), flags,
                                      ctypes.byref(t)))
-        self._sizes[int(t.value)] = int(g["n"])
         return int(t.value)
 
     def step(self):
@@ -411,7 +410,7 @@ class Batch:
                                    None, None, ctypes.byref(st), 0))
         if not done.value:
             return None
-        n = self._sizes[ticket]
+        n = int(st.n)
         n_aug = int(st.n_aug)
         winner = np.empty(n, np.uint8)
         sigma = np.empty(n_aug, np.int32)
@@ -419,7 +418,6 @@ class Batch:
         _check(lib().pg_batch_poll(self._h, ticket, ctypes.byref(done),
                                    _ptr(winner), _ptr(sigma), _ptr(tau),
                                    ctypes.byref(st), 0))
-        del self._sizes[ticket]
         return {"winner": winner, "sigma": sigma, "tau": tau,
                 "stats": st.as_dict()}
 

@@ -108,3 +108,39 @@ def test_batch_errors():
         h = synth.random_game(300, 2, 5, 3)
         t = b.submit(h)
         _check(h, _drain(b, [t])[t])
+
+
+def test_submissions_from_another_thread():
+    """pg_batch_submit may run on another thread while this one steps the
+    batch (submissions preprocess on the batch's own stream and take its
+    lock only to queue the game): every result equals the oracle's."""
+    import threading
+    import time
+    games = _mix(24, 7300, nmin=300, nmax=12000)
+    biggest = max(orc.preprocess(g)["n"] for g in games)
+    edges = max(orc.preprocess(g)["m"] for g in games)
+    tickets, failure = [], []
+
+    def submitter():
+        try:
+            for g in games:
+                tickets.append(b.submit(g))
+                time.sleep(0.0005)
+        except Exception as e:
+            failure.append(e)
+
+    with Batch(4 * biggest, 4 * edges) as b:
+        th = threading.Thread(target=submitter)
+        th.start()
+        out = {}
+        for _ in range(200000):
+            b.step()
+            for t in b.finished():
+                out[t] = b.poll(t)
+            if not th.is_alive() and len(out) == len(games):
+                break
+        th.join()
+    assert not failure
+    assert len(out) == len(games)
+    for g, t in zip(games, tickets):
+        _check(g, out[t])
