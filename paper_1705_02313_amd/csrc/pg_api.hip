@@ -33,7 +33,7 @@ __global__ void k_check_offsets(const int64_t *off, int64_t n, int64_t m,
   bool bad = (b <= a) || (b > m) || (a < 0);
   if (v == 0 && a != 0) bad = true;
   if (v == n - 1 && b != m) bad = true;
-  if (bad) atomicOr(&ctr[C_ERR], ERR_INVAL);
+  if (bad) atomicOr(&ctr[C_ERR], ERR_OFFSETS);
 }
 
 __global__ void k_check_targets(const int32_t *tgt, int64_t m, int64_t n,
@@ -656,18 +656,18 @@ pg_status load_modified(int64_t n, int64_t m, const void *offsets,
   PG_TRY(copy_in(own_in, owner, n, dev, s));
   PG_TRY(copy_in(pri_in, priority, sizeof(int32_t) * n, dev, s));
 
+  // the three checks are independent: one synchronisation
   hipLaunchKernelGGL(k_check_offsets, dim3(grid_for(n)), dim3(kBlock), 0, s,
                      off_in, n, m, g->ctr);
-  PG_TRY(sync_ctr(g, s));
-  if (g->hctr[C_ERR])
-    return pg_fail(PG_EINVAL,
-                   "offsets must start at 0, end at m and give every vertex "
-                   "a non-empty row");
   hipLaunchKernelGGL(k_check_targets, dim3(grid_for(m)), dim3(kBlock), 0, s,
                      tgt_in, m, n, g->ctr);
   hipLaunchKernelGGL(k_check_vertices, dim3(grid_for(n)), dim3(kBlock), 0, s,
                      own_in, pri_in, n, g->ctr);
   PG_TRY(sync_ctr(g, s));
+  if (g->hctr[C_ERR] & ERR_OFFSETS)
+    return pg_fail(PG_EINVAL,
+                   "offsets must start at 0, end at m and give every vertex "
+                   "a non-empty row");
   if (g->hctr[C_ERR])
     return pg_fail(PG_EINVAL,
                    "targets must lie in [0, n), owners in {0, 1} and "
@@ -786,8 +786,8 @@ pg_status load_modified(int64_t n, int64_t m, const void *offsets,
                        m, K, (int)dense, off_in, tgt_in, own_in, pri_in, inx,
                        xp, did, g->off, g->tgt, g->owner, g->pri, g->ctr);
   }
-  PG_TRY(sync_ctr(g, s));
-  PG_TRY(check_err(g, "a priority exceeds INT32_MAX after preprocessing"));
+  // a priority above INT32_MAX (ERR_INVAL) is reported at the caller's
+  // next synchronisation: the wrapped values only make later keys wrong
   return PG_OK;
 }
 
@@ -799,7 +799,7 @@ pg_status relabel_game(const int64_t *off, const int32_t *tgt,
                        const int32_t *from, const int32_t *to,
                        int64_t N, int64_t M, int64_t **off2,
                        int32_t **tgt2, uint8_t **owner2,
-                       int32_t **pri2, hipStream_t s) {
+                       int32_t **pri2, hipStream_t s, bool drain) {
   PG_TRY(dev_alloc(off2, N + 1));
   PG_TRY(dev_alloc(tgt2, M));
   PG_TRY(dev_alloc(owner2, N));
@@ -815,7 +815,7 @@ pg_status relabel_game(const int64_t *off, const int32_t *tgt,
   scan_excl_i64(*off2, *off2, N + 1, stmp.p, s);
   hipLaunchKernelGGL(k_relabel_rows, dim3(grid_for(N)), dim3(kBlock), 0, s,
                      off, tgt, from, to, *off2, *tgt2, N);
-  PG_HIP(hipStreamSynchronize(s));
+  if (drain) PG_HIP(hipStreamSynchronize(s));
   return PG_OK;
 }
 
@@ -830,7 +830,9 @@ pg_status finalize_state(pg_game *g, hipStream_t s, bool init_sp,
   int bits = 1;
   while ((int64_t(1) << bits) <= N + 1) ++bits;
   g->sort_bits = bits;
-  fill_i32(g->ctr, 0, C_TOTAL, s);
+  // every counter but the error bits, which may hold the preprocessing's
+  // priority overflow
+  fill_i32(g->ctr + 1, 0, C_TOTAL - 1, s);
   hipLaunchKernelGGL(k_rv_keys, dim3(grid_for(N)), dim3(kBlock), 0, s, g->pri,
                      g->sk0, g->sv0, N);
   int which = radix_sort(g->sk0, g->sv0, g->sk1, g->sv1, N, 32, g->tile_cnt,
@@ -840,7 +842,7 @@ pg_status finalize_state(pg_game *g, hipStream_t s, bool init_sp,
                      g->rvpos, N, (int)distinct, g->ctr);
   sum_dist(g->ctr, C_DIST_MISC, C_MISC, s);
   PG_TRY(sync_ctr(g, s));
-  PG_TRY(check_err(g, "invalid game"));
+  PG_TRY(check_err(g, "a priority exceeds INT32_MAX after preprocessing"));
   if (distinct) {
     int64_t *off2 = nullptr;
     int32_t *tgt2 = nullptr, *pri2 = nullptr;

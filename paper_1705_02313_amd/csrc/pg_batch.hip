@@ -731,7 +731,9 @@ pg_status pg_batch_submit(pg_batch *b, int64_t n, int64_t m,
     int32_t *d_max = (int32_t *)sc.i64;
     unsigned long long *d_me = (unsigned long long *)(sc.i64 + 1);
     int64_t *d_es = sc.i64 + 2;
-    fill_i32(gg->ctr, 0, C_TOTAL, s);
+    // every counter but the error bits (the preprocessing's priority
+    // overflow is read with the rest below)
+    fill_i32(gg->ctr + 1, 0, C_TOTAL - 1, s);
     fill_i32((int32_t *)sc.i64, 0, 6, s);
     fill_i32(d_max, -1, 1, s);
     hipLaunchKernelGGL(k_max_i32, dim3(256), dim3(kBlock), 0, s, gg->pri, N,
@@ -754,8 +756,11 @@ pg_status pg_batch_submit(pg_batch *b, int64_t n, int64_t m,
     int64_t *off2 = nullptr;
     int32_t *tgt2 = nullptr, *pri2 = nullptr;
     uint8_t *own2 = nullptr;
+    // without a drain: the batch's pool is reused in this stream's order
+    // (submissions run on it; steps only return memory to the pool)
     st = relabel_game(gg->off, gg->tgt, gg->owner, gg->pri, bg->rvperm,
-                      bg->rvrank, N, gg->m_aug, &off2, &tgt2, &own2, &pri2, s);
+                      bg->rvrank, N, gg->m_aug, &off2, &tgt2, &own2, &pri2, s,
+                      false);
     dev_free(st == PG_OK ? gg->off : off2);
     dev_free(st == PG_OK ? (void *)gg->tgt : (void *)tgt2);
     dev_free(st == PG_OK ? gg->owner : own2);
@@ -780,6 +785,9 @@ pg_status pg_batch_submit(pg_batch *b, int64_t n, int64_t m,
     if (e != hipSuccess && st == PG_OK)
       st = pg_fail(PG_EDEVICE, hipGetErrorString(e));
     if (st == PG_OK) st = sync_ctr(gg, s);
+    if (st == PG_OK && (gg->hctr[C_ERR] & ERR_INVAL))
+      st = pg_fail(PG_EINVAL,
+                   "a priority exceeds INT32_MAX after preprocessing");
     if (st == PG_OK && (gg->hctr[C_ERR] & ERR_DUPPRI))
       st = pg_fail(PG_EINVAL, "priorities must be pairwise distinct");
     bg->maxpri = mx;

@@ -47,6 +47,7 @@ enum ErrBit : int {
   ERR_DUPPRI = 8,        // repeated priority
   ERR_RANKCOUNT = 16,    // list ranking did not emit every finite vertex
   ERR_SORT = 32,         // a radix-sort look-back gave up waiting
+  ERR_OFFSETS = 64,      // input validation: bad CSR offsets
 };
 
 // Kernel kinds for the optional event profiler (pg_profile_* in pg.h).
@@ -468,11 +469,14 @@ pg_status finalize_state(pg_game *g, hipStream_t s, bool init_sp,
                          bool distinct = true);
 // A game of N vertices and M edges rebuilt with vertex i taken from vertex
 // from[i] and every target t mapped to to[t]; rows keep their edge order.
-// The new arrays are allocated (the old ones are the caller's); returns
-// after the stream has drained.
+// The new arrays are allocated (the old ones are the caller's).  With
+// `drain` it returns after the stream has drained; without, its scratch goes
+// back to the current pool at once, which is safe only when that pool is
+// reused in the order of this stream (a batch's submissions).
 pg_status relabel_game(const int64_t *off, const int32_t *tgt,
                        const uint8_t *owner, const int32_t *pri,
                        const int32_t *from, const int32_t *to, int64_t N,
                        int64_t M, int64_t **off2, int32_t **tgt2,
-                       uint8_t **owner2, int32_t **pri2, hipStream_t s);
+                       uint8_t **owner2, int32_t **pri2, hipStream_t s,
+                       bool drain = true);
 }  // namespace pgk

@@ -104,6 +104,13 @@ def test_batch_errors():
         with pytest.raises(PgError) as e:
             b.submit(g)
         assert e.value.status == PG_EINVAL
+        # the preprocessing shift pushes a priority past INT32_MAX
+        g = synth.random_game(200, 2, 5, 8)
+        g["pri"] = g["pri"].copy()
+        g["pri"][0] = 2**31 - 2
+        with pytest.raises(PgError) as e:
+            b.submit(g)
+        assert e.value.status == PG_EINVAL
         # the batch still works
         h = synth.random_game(300, 2, 5, 3)
         t = b.submit(h)
