@@ -71,8 +71,10 @@ enum {
     PG_CAREFUL_WALKS = 8u,  /* pg_load_csr: host-driven walk rounds (below)  */
     PG_COUNT_VALUATION = 16u,/* pg_load_csr: count valuations (below)        */
     PG_NO_GRAPH = 32u,      /* pg_load_csr: launch every kernel one by one   */
-    PG_HOST_REDUCED_LIST = 64u /* pg_load_csr: rank the reduced list on the
+    PG_HOST_REDUCED_LIST = 64u,/* pg_load_csr: rank the reduced list on the
                                   host (the paper's GPU-LR split; below)     */
+    PG_SWITCH_ROWS = 128u,  /* pg_load_csr: All_Odd reads rows (below)       */
+    PG_SWITCH_BUCKETS = 256u /* pg_load_csr: All_Odd by buckets (below)      */
 };
 
 /*
@@ -88,7 +90,7 @@ enum {
  *   priority  n int32 priorities, >= 0 (they may repeat; see below)
  *   flags     PG_PTR_DEVICE, PG_NO_PREPROCESS, PG_OFFSETS_I32,
  *             PG_CAREFUL_WALKS, PG_COUNT_VALUATION, PG_NO_GRAPH,
- *             PG_HOST_REDUCED_LIST
+ *             PG_HOST_REDUCED_LIST, PG_SWITCH_ROWS, PG_SWITCH_BUCKETS
  *
  * Two representations of valuations (section 3, "Valuations").  With
  * pairwise distinct priorities a finite valuation is the set of priorities
@@ -132,11 +134,20 @@ enum {
  * is captured.  It exists to measure that split against the device-only
  * ranking.
  *
+ * All_Odd (section 4) of a rank-valuation game with at least 2^20 edges in
+ * Odd rows runs over a bucketed copy of those edges made at load (about
+ * 24 bytes per edge): one kernel gathers the keys in target order and
+ * regroups them by blocks of Odd vertices, a second takes each vertex's
+ * least entry in LDS.  Same results as reading each row's keys, with
+ * coalesced instead of random memory traffic.  PG_SWITCH_BUCKETS takes the
+ * bucketed form at any size, PG_SWITCH_ROWS never (both: PG_EINVAL); count
+ * valuations always read rows.
+ *
  * The inputs may be freed when the call returns.  Errors: PG_EINVAL for a
  * malformed game (bad offsets, a terminal vertex, a target out of range, an
  * owner not in {0,1}, a negative priority, a shifted priority above
  * INT32_MAX, too many vertices, more than 32 distinct priorities with count
- * valuations), PG_ENOMEM, PG_EDEVICE.
+ * valuations, both PG_SWITCH_ flags), PG_ENOMEM, PG_EDEVICE.
  */
 pg_status pg_load_csr(int64_t n, int64_t m, const void *offsets,
                       const int32_t *targets, const uint8_t *owner,

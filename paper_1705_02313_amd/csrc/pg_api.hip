@@ -530,7 +530,9 @@ void free_game(pg_game *g) {
                   g->sk1,      g->sv1,      g->tile_cnt, g->scan_tmp,
                   g->kids,     g->fh,       g->pos,      g->elem,
                   g->ctr,      g->u64tmp,   g->cvals,    g->pidx,
-                  g->cnt,      g->elem4,    g->rs1,      g->cnt2};
+                  g->cnt,      g->elem4,    g->rs1,      g->cnt2,
+                  g->tsw_t,    g->tsw_slot, g->tsw_g,    g->tsw_tz,
+                  g->tsw_sz,   g->tsw_bs,   g->tsw_r};
   for (void *p : ptrs) dev_free(p);
   for (int k = 0; k < 8; ++k) {
     dev_free(g->lv[k].sum);
@@ -1000,6 +1002,9 @@ pg_status pg_load_csr(int64_t n, int64_t m, const void *offsets,
     return pg_fail(PG_EINVAL, "a game array is NULL");
   if ((flags & PG_OFFSETS_I32) && m > 0x7fffffffLL)
     return pg_fail(PG_EINVAL, "int32 offsets cannot address m edges");
+  if ((flags & PG_SWITCH_ROWS) && (flags & PG_SWITCH_BUCKETS))
+    return pg_fail(PG_EINVAL,
+                   "PG_SWITCH_ROWS and PG_SWITCH_BUCKETS exclude each other");
   pg_game *g = new (std::nothrow) pg_game();
   if (!g) return pg_fail(PG_ENOMEM, "host allocation failed");
   if (hipGetDevice(&g->device) != hipSuccess) {
@@ -1015,6 +1020,12 @@ pg_status pg_load_csr(int64_t n, int64_t m, const void *offsets,
   if (st == PG_OK) st = alloc_state(g, g->n_aug);
   if (st == PG_OK) st = finalize_state(g, s, true, !g->dense);
   if (st == PG_OK && g->dense) st = count_setup(g, s);
+  // All_Odd over the bucketed layout: rank valuations, large Odd rows or
+  // PG_SWITCH_BUCKETS, unless PG_SWITCH_ROWS
+  if (st == PG_OK && !g->dense && !(flags & PG_SWITCH_ROWS) &&
+      ((flags & PG_SWITCH_BUCKETS) || g->m_odd >= kTswMinEdges) &&
+      tsw_fits(g->n_odd, g->m_odd))
+    st = tsw_build(g, s);
   g->careful = flags & PG_CAREFUL_WALKS;
   g->use_graph = !(flags & PG_NO_GRAPH);
   g->host_rl = (flags & PG_HOST_REDUCED_LIST) && !g->dense;

@@ -55,7 +55,7 @@ enum KId : int {
   K_FILL = 0, K_NG_WALK, K_NG_ROUND, K_ROOT_WALK, K_ROOT_ROUND,
   K_SORT_SPLIT, K_SORT_HIST, K_SCAN, K_SORT_PASS, K_LINK_INFO, K_LINK_BUILD,
   K_LR_SUM1, K_LR_SUMK, K_LR_TOP, K_LR_DISTK, K_LR_EMIT1, K_ODD_SWITCH,
-  K_EVEN_SWITCH, K_OTHER, K_COUNT
+  K_EVEN_SWITCH, K_ODD_STAGE, K_OTHER, K_COUNT
 };
 extern const char *const kKernelNames[K_COUNT];
 
@@ -160,6 +160,16 @@ struct pg_game {
   bool use_graph = false;
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t iter_exec[2] = {nullptr, nullptr};
+  // All_Odd over the bucketed edge layout (pg_switch.hip): the Odd rows'
+  // edges in target order (tsw_t) with each edge's slot in its chunk
+  // (tsw_slot) and that slot's place in bucket order (tsw_g); per place the
+  // target (tsw_tz) and the vertex within its bucket (tsw_sz); bucket starts
+  // (tsw_bs, tsw_nb + 1); keys in bucket order each step (tsw_r)
+  bool tsw = false;
+  int64_t tsw_nb = 0, tsw_nc = 0;
+  int32_t *tsw_t = nullptr, *tsw_g = nullptr, *tsw_tz = nullptr;
+  int32_t *tsw_bs = nullptr, *tsw_r = nullptr;
+  uint16_t *tsw_slot = nullptr, *tsw_sz = nullptr;
 
   // modified game, device resident
   int64_t *off = nullptr;   // [n_aug+1]
@@ -374,6 +384,14 @@ void enqueue_count(pg_game *g, hipStream_t s);
 // All_Odd (odd) or All_Even on count valuations; counts into C_DIST_SW.
 // fresh: the switch counters are still zero from this valuation's clearing
 void enqueue_count_switch(pg_game *g, bool odd, hipStream_t s, bool fresh);
+// All_Odd over a bucketed edge layout (pg_switch.hip; rank valuations).
+// tsw_fits: the layout's indices fit its 32-bit fields.
+bool tsw_fits(int64_t n_odd, int64_t m_odd);
+pg_status tsw_build(pg_game *g, hipStream_t s);
+void enqueue_tsw_odd(pg_game *g, hipStream_t s);
+// Odd-row edges from which a single game takes the bucketed layout by
+// default (smaller games read rows directly)
+constexpr int64_t kTswMinEdges = int64_t(1) << 20;
 // Bellman-Ford best response against the sigma in g->sp: labels into
 // g->cnt, tau into g->sp, finite/top into g->rs; *rounds = Jacobi rounds.
 pg_status bf_best_response(pg_game *g, hipStream_t s, int64_t *rounds);

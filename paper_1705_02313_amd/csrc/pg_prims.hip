@@ -10,7 +10,7 @@ const char *const kKernelNames[K_COUNT] = {
     "fill",       "ng_walk",   "ng_round",   "root_walk",  "root_round",
     "sort_split", "sort_hist", "scan",       "sort_pass",  "link_info",
     "link_build", "lr_sum1",   "lr_sumk",    "lr_top",     "lr_distk",
-    "lr_emit1",   "odd_switch", "even_switch", "other"};
+    "lr_emit1",   "odd_switch", "even_switch", "odd_stage", "other"};
 
 hipEvent_t Prof::get() {
   if (!pool.empty()) {

@@ -839,7 +839,9 @@ static void enqueue_switch(pg_game *g, bool odd, hipStream_t s, bool fresh) {
   // per vertex: id 4, two offsets 16, current choice 8 (read and write
   // counted once; its key is one of the row's) -> 28; per edge: target 4
   // and its key 4
-  if (odd) {
+  if (odd && g->tsw) {
+    enqueue_tsw_odd(g, s);
+  } else if (odd) {
     const int64_t cnt = g->n_odd;
     if (cnt > 0)
       PG_LAUNCH(pf, K_ODD_SWITCH, 28.0 * cnt + 8.0 * g->m_odd, k_odd_switch,

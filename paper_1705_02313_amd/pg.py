@@ -23,6 +23,7 @@ PG_KEY_TOP = 2**31 - 1
 PG_PTR_DEVICE, PG_NO_PREPROCESS, PG_OFFSETS_I32 = 1, 2, 4
 PG_CAREFUL_WALKS, PG_COUNT_VALUATION, PG_NO_GRAPH = 8, 16, 32
 PG_HOST_REDUCED_LIST = 64
+PG_SWITCH_ROWS, PG_SWITCH_BUCKETS = 128, 256
 PG_BR_SI, PG_BR_SI_RESET, PG_BR_BELLMAN_FORD = 0, 1, 2
 
 STATUS_NAMES = {0: "PG_OK", 1: "PG_EINVAL", 2: "PG_ENOMEM", 3: "PG_EDEVICE",
@@ -155,14 +156,18 @@ class Game:
     """A game loaded on the device (modified by preprocessing unless
     ``preprocess=False``; ``careful_walks=True`` sets PG_CAREFUL_WALKS,
     ``count_valuation=True`` PG_COUNT_VALUATION, ``graph=False``
-    PG_NO_GRAPH, ``host_reduced_list=True`` PG_HOST_REDUCED_LIST).  Games
-    whose priorities repeat use count valuations by themselves
+    PG_NO_GRAPH, ``host_reduced_list=True`` PG_HOST_REDUCED_LIST,
+    ``switch="rows"`` PG_SWITCH_ROWS and ``switch="buckets"``
+    PG_SWITCH_BUCKETS; ``switch=None`` lets the library choose by size).
+    Games whose priorities repeat use count valuations by themselves
     (``self.d > 0``)."""
 
     def __init__(self, offsets, targets, owner, priority, n: int = None,
                  preprocess: bool = True, careful_walks: bool = False,
                  count_valuation: bool = False, graph: bool = True,
-                 host_reduced_list: bool = False):
+                 host_reduced_list: bool = False, switch: str = None):
+        if switch not in (None, "rows", "buckets"):
+            raise ValueError("switch must be None, 'rows' or 'buckets'")
         device = _is_torch(targets)
         if device:
             import torch
@@ -191,7 +196,9 @@ class Game:
             (PG_CAREFUL_WALKS if careful_walks else 0) | \
             (PG_COUNT_VALUATION if count_valuation else 0) | \
             (0 if graph else PG_NO_GRAPH) | \
-            (PG_HOST_REDUCED_LIST if host_reduced_list else 0)
+            (PG_HOST_REDUCED_LIST if host_reduced_list else 0) | \
+            {None: 0, "rows": PG_SWITCH_ROWS,
+             "buckets": PG_SWITCH_BUCKETS}[switch]
         h = ctypes.c_void_p()
         _check(lib().pg_load_csr(n, m, _ptr(offsets), _ptr(targets),
                                  _ptr(owner), _ptr(priority), flags,
@@ -210,11 +217,12 @@ class Game:
     @classmethod
     def from_dict(cls, g: dict, device: bool = False, preprocess: bool = True,
                   careful_walks: bool = False, count_valuation: bool = False,
-                  graph: bool = True, host_reduced_list: bool = False):
+                  graph: bool = True, host_reduced_list: bool = False,
+                  switch: str = None):
         kw = {"n": int(g["n"]), "preprocess": preprocess,
               "careful_walks": careful_walks,
               "count_valuation": count_valuation, "graph": graph,
-              "host_reduced_list": host_reduced_list}
+              "host_reduced_list": host_reduced_list, "switch": switch}
         if device:
             import torch
             t = {k: torch.from_numpy(np.ascontiguousarray(g[k])).cuda()
