@@ -141,7 +141,9 @@ enum {
  * least entry in LDS.  Same results as reading each row's keys, with
  * coalesced instead of random memory traffic.  PG_SWITCH_BUCKETS takes the
  * bucketed form at any size, PG_SWITCH_ROWS never (both: PG_EINVAL); count
- * valuations always read rows.
+ * valuations always read rows.  When the layout does not fit in device
+ * memory the load keeps the row form, unless PG_SWITCH_BUCKETS asked for it
+ * (then PG_ENOMEM).
  *
  * The inputs may be freed when the call returns.  Errors: PG_EINVAL for a
  * malformed game (bad offsets, a terminal vertex, a target out of range, an

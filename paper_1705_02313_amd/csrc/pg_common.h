@@ -388,6 +388,8 @@ void enqueue_count_switch(pg_game *g, bool odd, hipStream_t s, bool fresh);
 // tsw_fits: the layout's indices fit its 32-bit fields.
 bool tsw_fits(int64_t n_odd, int64_t m_odd);
 pg_status tsw_build(pg_game *g, hipStream_t s);
+// frees the layout (after the stream has drained); the row form serves
+void tsw_release(pg_game *g);
 void enqueue_tsw_odd(pg_game *g, hipStream_t s);
 // Odd-row edges from which a single game takes the bucketed layout by
 // default (smaller games read rows directly)

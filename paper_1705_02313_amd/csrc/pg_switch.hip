@@ -21,9 +21,9 @@
 // Finite keys are pairwise distinct, so the least (key, target) pair names
 // the row's first entry of least key; when the least key is top no switch
 // happens, whichever top entry it names.  The layout is three stable radix
-// sorts at load: the edges by target; by (chunk, bucket), which gives each
-// edge's slot in its chunk; by bucket, which gives each slot's place in its
-// bucket.
+// sorts at load: the edges by target; those by bucket, which gives each
+// edge's place in bucket order; the places by chunk, which gives each edge's
+// slot in its chunk.
 #include "pg_common.h"
 
 namespace pgk {
@@ -69,47 +69,45 @@ __global__ void k_tsw_expand(const int32_t *ids, const int64_t *off,
   }
 }
 
-// in target order: keep the targets and list positions; sort key
-// chunk * nb + bucket
-__global__ void k_tsw_key2(uint32_t *kt, const uint32_t *vo, int32_t *tx,
-                           int32_t *ox, int64_t m, int64_t nb) {
+// in target order: keep the targets and list positions; sort key the bucket
+__global__ void k_tsw_keep(uint32_t *kt, const uint32_t *vo, int32_t *tx,
+                           int32_t *ox, int64_t m) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= m) return;
   const uint32_t o = vo[j];
   tx[j] = (int32_t)kt[j];
   ox[j] = (int32_t)o;
-  kt[j] = (uint32_t)((j / kTswChunk) * nb + o / kTswBucket);
+  kt[j] = o / kTswBucket;
 }
 
-// w[q] = the edge (target-order index) at chunk-sorted position q
-__global__ void k_tsw_slot(const uint32_t *w, uint16_t *slot, uint32_t *posw,
-                           int64_t m) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= m) return;
-  const uint32_t j = w[q];
-  slot[j] = (uint16_t)(q % kTswChunk);
-  posw[j] = (uint32_t)q;
-}
-
-__global__ void k_tsw_key3(const int32_t *ox, uint32_t *kb, int64_t m) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < m) kb[j] = (uint32_t)ox[j] / kTswBucket;
-}
-
-// z[p] = the edge at bucket-sorted position p, zb[p] its bucket
-__global__ void k_tsw_final(const uint32_t *z, const uint32_t *zb,
-                            const int32_t *tx, const int32_t *ox,
-                            const uint32_t *posw, int32_t *tz, uint16_t *sz,
-                            int32_t *gpos, int32_t *bs, int64_t m, int64_t nb) {
+// z[p] = the edge (target-order index) at bucket-order place p, zb[p] its
+// bucket: each place's target, vertex within the bucket and the bucket
+// starts; sort key the edge's chunk (the places stay in bucket order within
+// a chunk)
+__global__ void k_tsw_places(const uint32_t *z, const uint32_t *zb,
+                             const int32_t *tx, const int32_t *ox,
+                             int32_t *tz, uint16_t *sz, int32_t *bs,
+                             uint32_t *kc, int64_t m, int64_t nb) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= m) return;
   const uint32_t j = z[p];
   tz[p] = tx[j];
   sz[p] = (uint16_t)((uint32_t)ox[j] % kTswBucket);
-  gpos[posw[j]] = (int32_t)p;
+  kc[p] = j / kTswChunk;
   const uint32_t b = zb[p];
   if (p == 0 || zb[p - 1] != b) bs[b] = (int32_t)p;
   if (p == m - 1) bs[nb] = (int32_t)m;
+}
+
+// w[q] = the place of the edge in chunk-sorted position q: slot q % chunk
+// of its chunk
+__global__ void k_tsw_slots(const uint32_t *w, const uint32_t *z,
+                            uint16_t *slot, int32_t *gpos, int64_t m) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m) return;
+  const uint32_t p = w[q];
+  gpos[q] = (int32_t)p;
+  slot[z[p]] = (uint16_t)(q % kTswChunk);
 }
 
 // ---- the step (every valuation) --------------------------------------------
@@ -239,8 +237,8 @@ pg_status tsw_build(pg_game *g, hipStream_t s) {
   PG_TRY(dev_alloc(&g->tsw_bs, nb + 1));
   g->tsw_nb = nb;
   g->tsw_nc = nc;
-  // temporaries: four sort buffers, the chunk-order positions, the
-  // scans' and sorts' scratch
+  // temporaries: four sort buffers, a fifth key buffer, the scans' and
+  // sorts' scratch
   uint32_t *a[5] = {};
   uint32_t *tiles = nullptr;
   void *tmp = nullptr;
@@ -269,30 +267,40 @@ pg_status tsw_build(pg_game *g, hipStream_t s) {
   scan_excl_u32(a[4], a[4], no + 1, tmp, s);
   hipLaunchKernelGGL(k_tsw_expand, dim3(grid_for(no)), dim3(kBlock), 0, s,
                      g->odd_ids, g->off, g->tgt, a[4], a[0], a[1], no);
-  // by target
+  // by target; targets and list positions in that order go to tsw_t and
+  // tsw_r (free until the first step)
   int w = radix_sort(a[0], a[1], a[2], a[3], m, bits_for(g->n_aug), tiles,
                      tmp, s);
   uint32_t *k0 = a[2 * w], *v0 = a[2 * w + 1];
   uint32_t *k1 = a[2 - 2 * w], *v1 = a[3 - 2 * w];
-  // targets and list positions in target order kept in tsw_t and tsw_r
-  hipLaunchKernelGGL(k_tsw_key2, dim3(grid_for(m)), dim3(kBlock), 0, s, k0,
-                     v0, g->tsw_t, g->tsw_r, m, nb);
-  // by (chunk, bucket): slots within each chunk
-  w = radix_sort(k0, v0, k1, v1, m, bits_for(nc * nb - 1), tiles, tmp, s,
+  hipLaunchKernelGGL(k_tsw_keep, dim3(grid_for(m)), dim3(kBlock), 0, s, k0,
+                     v0, g->tsw_t, g->tsw_r, m);
+  // by bucket (stable: target order within a bucket) -> places
+  w = radix_sort(k0, v0, k1, v1, m, bits_for(nb - 1), tiles, tmp, s, nullptr,
+                 nullptr, true);
+  uint32_t *zk = w ? k1 : k0, *zv = w ? v1 : v0;
+  uint32_t *fk = w ? k0 : k1, *fv = w ? v0 : v1;   // the free pair
+  hipLaunchKernelGGL(k_tsw_places, dim3(grid_for(m)), dim3(kBlock), 0, s, zv,
+                     zk, g->tsw_t, g->tsw_r, g->tsw_tz, g->tsw_sz, g->tsw_bs,
+                     a[4], m, nb);
+  // places by chunk (stable: bucket order within a chunk) -> slots
+  w = radix_sort(a[4], zk, fk, fv, m, bits_for(nc - 1), tiles, tmp, s,
                  nullptr, nullptr, true);
-  hipLaunchKernelGGL(k_tsw_slot, dim3(grid_for(m)), dim3(kBlock), 0, s,
-                     w ? v1 : v0, g->tsw_slot, a[4], m);
-  // by bucket: places within buckets
-  hipLaunchKernelGGL(k_tsw_key3, dim3(grid_for(m)), dim3(kBlock), 0, s,
-                     g->tsw_r, a[0], m);
-  w = radix_sort(a[0], a[1], a[2], a[3], m, bits_for(nb - 1), tiles, tmp, s,
-                 nullptr, nullptr, true);
-  hipLaunchKernelGGL(k_tsw_final, dim3(grid_for(m)), dim3(kBlock), 0, s,
-                     a[2 * w + 1], a[2 * w], g->tsw_t, g->tsw_r, a[4],
-                     g->tsw_tz, g->tsw_sz, g->tsw_g, g->tsw_bs, m, nb);
+  hipLaunchKernelGGL(k_tsw_slots, dim3(grid_for(m)), dim3(kBlock), 0, s,
+                     w ? fv : zk, zv, g->tsw_slot, g->tsw_g, m);
   PG_HIP(hipGetLastError());
   g->tsw = true;
   return PG_OK;
+}
+
+void tsw_release(pg_game *g) {
+  void *ptrs[] = {g->tsw_t, g->tsw_slot, g->tsw_g, g->tsw_tz,
+                  g->tsw_sz, g->tsw_bs,   g->tsw_r};
+  for (void *p : ptrs) dev_free(p);
+  g->tsw_t = g->tsw_g = g->tsw_tz = g->tsw_bs = g->tsw_r = nullptr;
+  g->tsw_slot = g->tsw_sz = nullptr;
+  g->tsw = false;
+  g->tsw_nb = g->tsw_nc = 0;
 }
 
 void enqueue_tsw_odd(pg_game *g, hipStream_t s) {

@@ -141,3 +141,23 @@ def test_switch_flags_exclude_each_other():
     assert rc == PG_EINVAL
     with pytest.raises(ValueError):
         Game.from_dict(g, switch="both")  # rejected before the C ABI
+
+
+@pytest.mark.parametrize("n_odd", [2048, 4096])
+def test_bucketed_exact_bucket_and_chunk_boundaries(n_odd):
+    """Odd vertices filling whole buckets (2,048 each) and Odd rows filling
+    whole chunks (16,384 edges each): no ragged tail anywhere."""
+    rng = np.random.default_rng(n_odd)
+    n = 2 * n_odd
+    deg = np.where(np.arange(n) < n_odd, 8, rng.integers(2, 6, n))
+    off = np.zeros(n + 1, np.int64)
+    off[1:] = np.cumsum(deg)
+    g = {"n": n, "m": int(off[-1]), "offsets": off,
+         "targets": rng.integers(0, n, int(off[-1])).astype(np.int32),
+         "owner": (np.arange(n) < n_odd).astype(np.uint8),
+         "pri": rng.permutation(n).astype(np.int32)}
+    aug = orc.preprocess(g)
+    own = aug["owner"]
+    assert int((own == 1).sum()) == n_odd
+    assert int(np.diff(aug["offsets"])[own == 1].sum()) == 8 * n_odd
+    _check(g, "buckets")
