@@ -94,21 +94,35 @@ __global__ void k_x_init(const uint8_t *owner, uint8_t *inx, int64_t n) {
   if (v < n) inx[v] = owner[v] == 1;
 }
 
+// One round of the greatest fixpoint X (rounds update inx in place).  X
+// only shrinks, so a member's row is scanned from the entry that last
+// showed a successor in X (wit[v], relative to the row; 0 at first): the
+// entries before it have left X for good.  Over all rounds each row is read
+// about once.
 __global__ void k_x_round(const int64_t *__restrict__ off,
                           const int32_t *__restrict__ tgt, uint8_t *inx,
-                          int64_t n, int32_t *ctr) {
+                          uint32_t *wit, int64_t n, int32_t *ctr) {
   int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool drop = false;
   if (v < n && __hip_atomic_load(&inx[v], __ATOMIC_RELAXED,
                                  __HIP_MEMORY_SCOPE_AGENT)) {
+    const int64_t e0 = off[v], end = off[v + 1];
+    const uint32_t w0 = wit[v];
+    int64_t e = e0 + w0;
     bool any = false;
-    for (int64_t e = off[v], end = off[v + 1]; e < end && !any; ++e)
-      any = __hip_atomic_load(&inx[tgt[e]], __ATOMIC_RELAXED,
-                              __HIP_MEMORY_SCOPE_AGENT) != 0;
+    for (; e < end; ++e)
+      if (__hip_atomic_load(&inx[tgt[e]], __ATOMIC_RELAXED,
+                            __HIP_MEMORY_SCOPE_AGENT)) {
+        any = true;
+        break;
+      }
     if (!any) {
       __hip_atomic_store(&inx[v], (uint8_t)0, __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
       drop = true;
+    } else if (e - e0 != (int64_t)w0) {
+      // a witness beyond 32 bits of row offset is not kept (rescan)
+      wit[v] = (e - e0 <= 0xffffffffLL) ? (uint32_t)(e - e0) : 0u;
     }
   }
   // a change flag: most waves find it already set and only read it
@@ -740,13 +754,15 @@ pg_status load_modified(int64_t n, int64_t m, const void *offsets,
     tmp.p.push_back(did);
     hipLaunchKernelGGL(k_x_init, dim3(grid_for(n)), dim3(kBlock), 0, s, own_in,
                        inx, n);
+    // xp holds the rounds' row witnesses until X is known
+    fill_i32((int32_t *)xp, 0, n, s);
     for (int64_t round = 0;; round += 4) {
       if (round > 4 * n + 64)
         return pg_fail(PG_EINTERNAL, "preprocessing did not converge");
       fill_i32(g->ctr + C_MISC, 0, 1, s);
       for (int k = 0; k < 4; ++k)
         hipLaunchKernelGGL(k_x_round, dim3(grid_for(n)), dim3(kBlock), 0, s,
-                           off_in, tgt_in, inx, n, g->ctr);
+                           off_in, tgt_in, inx, xp, n, g->ctr);
       PG_TRY(sync_ctr(g, s));
       if (g->hctr[C_MISC] == 0) break;
     }

@@ -28,7 +28,7 @@
 
 namespace pgk {
 
-constexpr int kTswChunk = 16384;   // edges per stage block (64 KiB of LDS)
+constexpr int kTswChunk = 32768;   // edges per stage block (128 KiB of LDS)
 constexpr int kTswBucket = 2048;   // Odd vertices per min block
 
 // Adds n (per thread) to the distributed counter at `dist`.  Every thread of
@@ -112,7 +112,7 @@ __global__ void k_tsw_slots(const uint32_t *w, const uint32_t *z,
 
 // ---- the step (every valuation) --------------------------------------------
 
-constexpr int kTswStageBlock = 512;
+constexpr int kTswStageBlock = 1024;
 constexpr int kTswMinBlock = 256;
 constexpr int kTswUnroll = 8;
 
@@ -215,12 +215,9 @@ static int bits_for(int64_t max_value) {
   return b;
 }
 
+// places, slots and bucket starts are int32
 bool tsw_fits(int64_t n_odd, int64_t m_odd) {
-  if (n_odd <= 0 || m_odd <= 0 || m_odd >= (int64_t(1) << 31) - kTswChunk)
-    return false;
-  const int64_t nb = (n_odd + kTswBucket - 1) / kTswBucket;
-  const int64_t nc = (m_odd + kTswChunk - 1) / kTswChunk;
-  return nc * nb < (int64_t(1) << 32);
+  return n_odd > 0 && m_odd > 0 && m_odd < (int64_t(1) << 31) - kTswChunk;
 }
 
 pg_status tsw_build(pg_game *g, hipStream_t s) {

@@ -39,7 +39,7 @@ def _check(g, switch):
 
 
 # n chosen so that the Odd vertices fill one bucket (2,048) or several with a
-# ragged last one, and the Odd rows one chunk (16,384 edges) or many
+# ragged last one, and the Odd rows one chunk (32,768 edges) or many
 @pytest.mark.parametrize("n,kind,seed", [
     (3, "rnd", 1), (40, "rnd", 2), (3000, "rnd", 3), (4095, "rnd", 4),
     (4097, "rnd", 5), (20011, "rnd", 6), (60000, "rnd", 7),
@@ -143,10 +143,10 @@ def test_switch_flags_exclude_each_other():
         Game.from_dict(g, switch="both")  # rejected before the C ABI
 
 
-@pytest.mark.parametrize("n_odd", [2048, 4096])
+@pytest.mark.parametrize("n_odd", [2048, 4096, 8192])
 def test_bucketed_exact_bucket_and_chunk_boundaries(n_odd):
-    """Odd vertices filling whole buckets (2,048 each) and Odd rows filling
-    whole chunks (16,384 edges each): no ragged tail anywhere."""
+    """Odd vertices filling whole buckets (2,048 each) and Odd rows (8 edges
+    each) filling half a chunk, one chunk or two (32,768 edges each)."""
     rng = np.random.default_rng(n_odd)
     n = 2 * n_odd
     deg = np.where(np.arange(n) < n_odd, 8, rng.integers(2, 6, n))
@@ -161,3 +161,17 @@ def test_bucketed_exact_bucket_and_chunk_boundaries(n_odd):
     assert int((own == 1).sum()) == n_odd
     assert int(np.diff(aug["offsets"])[own == 1].sum()) == 8 * n_odd
     _check(g, "buckets")
+
+
+def test_bucketed_flag_ignored_by_count_valuations():
+    """Count valuations read rows whatever the flag says: same solve as the
+    oracle's."""
+    g = synth.few_priorities_game(5000, 2, 5, 4, 3)
+    ref = orc.dense_solve(g)
+    with Game.from_dict(g, switch="buckets") as d:
+        assert d.d == ref["values"].size
+        out = d.solve()
+    np.testing.assert_array_equal(to_np(out["winner"]), ref["winner"])
+    np.testing.assert_array_equal(to_np(out["sigma"]), ref["sigma"])
+    np.testing.assert_array_equal(to_np(out["tau"]), ref["tau_orig"])
+    assert out["stats"]["n_valuations"] == ref["n_valuations"]
