@@ -143,7 +143,8 @@ enum {
  * bucketed form at any size, PG_SWITCH_ROWS never (both: PG_EINVAL); count
  * valuations always read rows.  When the layout does not fit in device
  * memory the load keeps the row form, unless PG_SWITCH_BUCKETS asked for it
- * (then PG_ENOMEM).
+ * (then PG_ENOMEM); so does a device that cannot give one block 128 KiB of
+ * LDS (with either flag setting).
  *
  * The inputs may be freed when the call returns.  Errors: PG_EINVAL for a
  * malformed game (bad offsets, a terminal vertex, a target out of range, an

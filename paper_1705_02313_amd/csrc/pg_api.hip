@@ -1040,7 +1040,7 @@ pg_status pg_load_csr(int64_t n, int64_t m, const void *offsets,
   // PG_SWITCH_BUCKETS, unless PG_SWITCH_ROWS
   if (st == PG_OK && !g->dense && !(flags & PG_SWITCH_ROWS) &&
       ((flags & PG_SWITCH_BUCKETS) || g->m_odd >= kTswMinEdges) &&
-      tsw_fits(g->n_odd, g->m_odd)) {
+      tsw_fits(g->device, g->n_odd, g->m_odd)) {
     st = tsw_build(g, s);
     // without room for the layout the row form serves (same results)
     if (st == PG_ENOMEM && !(flags & PG_SWITCH_BUCKETS)) {

@@ -385,8 +385,9 @@ void enqueue_count(pg_game *g, hipStream_t s);
 // fresh: the switch counters are still zero from this valuation's clearing
 void enqueue_count_switch(pg_game *g, bool odd, hipStream_t s, bool fresh);
 // All_Odd over a bucketed edge layout (pg_switch.hip; rank valuations).
-// tsw_fits: the layout's indices fit its 32-bit fields.
-bool tsw_fits(int64_t n_odd, int64_t m_odd);
+// tsw_fits: the layout's indices fit its 32-bit fields and the device
+// gives a block the stage kernel's LDS.
+bool tsw_fits(int device, int64_t n_odd, int64_t m_odd);
 pg_status tsw_build(pg_game *g, hipStream_t s);
 // frees the layout (after the stream has drained); the row form serves
 void tsw_release(pg_game *g);

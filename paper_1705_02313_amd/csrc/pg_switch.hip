@@ -215,14 +215,21 @@ static int bits_for(int64_t max_value) {
   return b;
 }
 
-// places, slots and bucket starts are int32
-bool tsw_fits(int64_t n_odd, int64_t m_odd) {
+// places, slots and bucket starts are int32; the stage kernel's chunk
+// needs its LDS in one block
+bool tsw_fits(int device, int64_t n_odd, int64_t m_odd) {
+  int lds = 0;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock,
+                            device) != hipSuccess ||
+      lds < (int)sizeof(int32_t) * kTswChunk)
+    return false;
   return n_odd > 0 && m_odd > 0 && m_odd < (int64_t(1) << 31) - kTswChunk;
 }
 
 pg_status tsw_build(pg_game *g, hipStream_t s) {
   const int64_t no = g->n_odd, m = g->m_odd;
-  if (!tsw_fits(no, m)) return pg_fail(PG_EINVAL, "no bucketed layout");
+  if (!tsw_fits(g->device, no, m))
+    return pg_fail(PG_EINVAL, "no bucketed layout");
   const int64_t nb = (no + kTswBucket - 1) / kTswBucket;
   const int64_t nc = (m + kTswChunk - 1) / kTswChunk;
   PG_TRY(dev_alloc(&g->tsw_t, m));
