@@ -42,3 +42,37 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(pg, "_lib", None)
     with pytest.raises(ImportError):
         pg.lib()
+
+
+def header_constants():
+    """NAME = value entries of the header's enums and its integer #defines."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    out = {}
+    for name, val in re.findall(r"\b(PG_[A-Z0-9_]+)\s*=\s*([0-9]+)u?\b", text):
+        out[name] = int(val)
+    for name, val in re.findall(r"#define\s+(PG_[A-Z0-9_]+)\s+\(?(-?[0-9]+)\)?",
+                                text):
+        out[name] = int(val)
+    return out
+
+
+def test_binding_constants_mirror_the_header():
+    from paper_1705_02313_amd import pg
+    consts = header_constants()
+    for name in ("PG_OK", "PG_EINVAL", "PG_ENOMEM", "PG_EDEVICE",
+                 "PG_EITERLIMIT", "PG_EINADMISSIBLE", "PG_EINTERNAL",
+                 "PG_PTR_DEVICE", "PG_NO_PREPROCESS", "PG_OFFSETS_I32",
+                 "PG_CAREFUL_WALKS", "PG_COUNT_VALUATION", "PG_NO_GRAPH",
+                 "PG_HOST_REDUCED_LIST", "PG_SWITCH_ROWS", "PG_SWITCH_BUCKETS",
+                 "PG_BR_SI", "PG_BR_SI_RESET", "PG_BR_BELLMAN_FORD",
+                 "PG_SINK", "PG_KEY_TOP"):
+        assert name in consts, name
+        if hasattr(pg, name):
+            assert getattr(pg, name) == consts[name], name
+    # the load flags are distinct bits
+    flags = [consts[k] for k in consts if k in (
+        "PG_PTR_DEVICE", "PG_NO_PREPROCESS", "PG_OFFSETS_I32",
+        "PG_CAREFUL_WALKS", "PG_COUNT_VALUATION", "PG_NO_GRAPH",
+        "PG_HOST_REDUCED_LIST", "PG_SWITCH_ROWS", "PG_SWITCH_BUCKETS")]
+    assert all(f & (f - 1) == 0 for f in flags)
+    assert len(set(flags)) == len(flags)
