@@ -397,10 +397,11 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
 }
 
 // Counts every digit of every pass, one block per 4096-key tile.  Each lane
-// loads its 16 keys at once (all in flight); then keys are counted 64 at a
-// time per wave: the lowest lane of each group of equal digits adds the
-// group's size to the wave's own counters, so no two lanes ever update one
-// counter at once (the keys are skewed: many vertices share a parent).
+// loads its 16 keys at once (all in flight); then each wave adds its keys to
+// its own LDS counters with atomics.  Lanes of a wave that hit one counter
+// are serialised by the LDS, which costs less than finding the groups of
+// equal digits with ballots (eight per digit): on the 10M-vertex random game
+// 47 -> 13 us per valuation.
 __global__ __launch_bounds__(kBlock) void k_1s_hist(const uint32_t *keys,
                                                     const uint32_t *n_dev,
                                                     int passes,
@@ -413,7 +414,6 @@ __global__ __launch_bounds__(kBlock) void k_1s_hist(const uint32_t *keys,
   __shared__ uint32_t h[kRsWaves][k1sMaxPasses][256];
   const int lane = threadIdx.x & (kWave - 1);
   const int w = threadIdx.x / kWave;
-  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
   for (int p = 0; p < k1sMaxPasses; ++p)
     for (int j = lane; j < 256; j += kWave) h[w][p][j] = 0;
   const int64_t base =
@@ -424,14 +424,13 @@ __global__ __launch_bounds__(kBlock) void k_1s_hist(const uint32_t *keys,
     const int64_t i = base + r * kWave + lane;
     k[r] = i < n ? keys[i] : 0u;
   }
+  __syncthreads();
   for (int p = 0; p < passes; ++p) {
 #pragma unroll
     for (int r = 0; r < kWaveItems; ++r) {
       const bool valid = base + r * kWave + lane < n;
       const uint32_t d = (k[r] >> (8 * p)) & 255u;
-      const uint64_t peers = digit_peers(d, valid);
-      if (valid && __popcll(peers & lt) == 0)
-        h[w][p][d] += (uint32_t)__popcll(peers);
+      if (valid) atomicAdd(&h[w][p][d], 1u);
     }
   }
   __syncthreads();
