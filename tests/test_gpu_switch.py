@@ -175,3 +175,25 @@ def test_bucketed_flag_ignored_by_count_valuations():
     np.testing.assert_array_equal(to_np(out["sigma"]), ref["sigma"])
     np.testing.assert_array_equal(to_np(out["tau"]), ref["tau_orig"])
     assert out["stats"]["n_valuations"] == ref["n_valuations"]
+
+
+@pytest.mark.parametrize("opts", [{"careful_walks": True}, {"graph": False},
+                                  {"host_reduced_list": True}],
+                         ids=["careful", "eager", "host_list"])
+@pytest.mark.parametrize("kind", ["rnd", "chain"])
+def test_bucketed_with_other_load_flags(opts, kind):
+    """The bucketed step under host-driven walk rounds (and the rerun after
+    bounded rounds leave work), eager launches, and the host-ranked reduced
+    list: the oracle's solve each time."""
+    g = synth.random_game(30000, 2, 6, 51) if kind == "rnd" else \
+        synth.chain_game(40000, 52)
+    ref = orc.solve(g)
+    assert ref["status"] == 0
+    _say("bucketed with", opts, kind)
+    with Game.from_dict(g, switch="buckets", **opts) as d:
+        out = d.solve()
+    np.testing.assert_array_equal(to_np(out["winner"]), ref["winner"])
+    np.testing.assert_array_equal(to_np(out["sigma"]), ref["sigma"])
+    np.testing.assert_array_equal(to_np(out["tau"]), ref["tau_orig"])
+    assert out["stats"]["n_valuations"] == ref["n_valuations"]
+    assert out["stats"]["n_odd_switches"] == ref["n_odd_switches"]
