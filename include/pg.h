@@ -399,7 +399,9 @@ pg_status pg_batch_free(pg_batch *batch);
 pg_status pg_free(pg_game *game);
 
 /* Hand the cached memory of freed games back to the HIP runtime (every
- * device).  Memory of games still loaded is not touched. */
+ * device).  Memory of games still loaded is not touched.  Small blocks are
+ * carved from shared slabs of 32; a slab goes back once none of its blocks
+ * belongs to a loaded game (its free blocks stay cached until then). */
 pg_status pg_release_cache(void);
 
 /* Description of the calling thread's last error ("" if none). */

@@ -426,51 +426,93 @@ pg_status DevPool::alloc(void **p, size_t bytes, bool host) {
   std::lock_guard<std::mutex> lock(mu);
   const size_t b = bucket(bytes);
   auto &fl = host ? host_free[b] : dev_free[b];
-  if (!fl.empty()) {
-    *p = fl.back();
-    fl.pop_back();
-    return PG_OK;
+  if (fl.empty()) {
+    const bool slab = b <= kSlabBlockMax;
+    const size_t total = slab ? b * kSlabBlocks : b;
+    void *base = nullptr;
+    hipError_t e = host ? hipHostMalloc(&base, total, hipHostMallocDefault)
+                        : hipMalloc(&base, total);
+    if (e != hipSuccess) {
+      *p = nullptr;
+      return pg_fail(PG_ENOMEM, std::string("pool allocation failed: ") +
+                                    hipGetErrorString(e));
+    }
+    auto &sizes = host ? host_size : dev_size;
+    if (slab) {
+      Slab sl;
+      sl.base = base;
+      sl.block = b;
+      sl.host = host;
+      slabs.push_back(sl);
+      // blocks handed out from the end of the free list: keep the slab's
+      // first block last so that it is taken first
+      for (size_t k = kSlabBlocks; k-- > 0;) {
+        void *q = (char *)base + k * b;
+        sizes[q] = b;
+        slab_of[q] = slabs.size() - 1;
+        fl.push_back(q);
+      }
+    } else {
+      sizes[base] = b;
+      fl.push_back(base);
+    }
   }
-  hipError_t e = host ? hipHostMalloc(p, b, hipHostMallocDefault)
-                      : hipMalloc(p, b);
-  if (e != hipSuccess) {
-    *p = nullptr;
-    return pg_fail(PG_ENOMEM, std::string("pool allocation failed: ") +
-                                  hipGetErrorString(e));
-  }
-  (host ? host_size : dev_size)[*p] = b;
+  *p = fl.back();
+  fl.pop_back();
+  auto it = slab_of.find(*p);
+  if (it != slab_of.end()) ++slabs[it->second].in_use;
   return PG_OK;
 }
 
 bool DevPool::release(void *p) {
   std::lock_guard<std::mutex> lock(mu);
   auto it = dev_size.find(p);
-  if (it != dev_size.end()) {
-    dev_free[it->second].push_back(p);
-    return true;
+  bool host = false;
+  if (it == dev_size.end()) {
+    it = host_size.find(p);
+    if (it == host_size.end()) return false;
+    host = true;
   }
-  it = host_size.find(p);
-  if (it != host_size.end()) {
-    host_free[it->second].push_back(p);
-    return true;
-  }
-  return false;
+  (host ? host_free : dev_free)[it->second].push_back(p);
+  auto si = slab_of.find(p);
+  if (si != slab_of.end()) --slabs[si->second].in_use;
+  return true;
 }
 
 void DevPool::trim() {
   std::lock_guard<std::mutex> lock(mu);
-  for (auto &kv : dev_free)
-    for (void *p : kv.second) {
-      (void)hipFree(p);
-      dev_size.erase(p);
+  // slabs none of whose blocks is in use leave with all their blocks
+  std::vector<bool> gone(slabs.size(), false);
+  for (size_t i = 0; i < slabs.size(); ++i)
+    gone[i] = slabs[i].base && slabs[i].in_use == 0;
+  for (int h = 0; h < 2; ++h) {
+    auto &lists = h ? host_free : dev_free;
+    auto &sizes = h ? host_size : dev_size;
+    for (auto &kv : lists) {
+      std::vector<void *> keep;
+      for (void *q : kv.second) {
+        auto si = slab_of.find(q);
+        if (si == slab_of.end()) {
+          // a block of its own, not in use
+          if (h) (void)hipHostFree(q);
+          else (void)hipFree(q);
+          sizes.erase(q);
+        } else if (gone[si->second]) {
+          sizes.erase(q);
+          slab_of.erase(si);
+        } else {
+          keep.push_back(q);
+        }
+      }
+      kv.second.swap(keep);
     }
-  for (auto &kv : host_free)
-    for (void *p : kv.second) {
-      (void)hipHostFree(p);
-      host_size.erase(p);
+  }
+  for (size_t i = 0; i < slabs.size(); ++i)
+    if (gone[i]) {
+      if (slabs[i].host) (void)hipHostFree(slabs[i].base);
+      else (void)hipFree(slabs[i].base);
+      slabs[i].base = nullptr;   // the index stays: other blocks name theirs
     }
-  dev_free.clear();
-  host_free.clear();
 }
 
 // One cache per device, kept until the process ends.  Single games allocate
@@ -500,12 +542,21 @@ static void trim_caches() {
 
 void DevPool::clear() {
   std::lock_guard<std::mutex> lock(mu);
-  for (auto &kv : dev_size) (void)hipFree(kv.first);
-  for (auto &kv : host_size) (void)hipHostFree(kv.first);
+  for (auto &kv : dev_size)
+    if (!slab_of.count(kv.first)) (void)hipFree(kv.first);
+  for (auto &kv : host_size)
+    if (!slab_of.count(kv.first)) (void)hipHostFree(kv.first);
+  for (Slab &sl : slabs)
+    if (sl.base) {
+      if (sl.host) (void)hipHostFree(sl.base);
+      else (void)hipFree(sl.base);
+    }
   dev_size.clear();
   host_size.clear();
   dev_free.clear();
   host_free.clear();
+  slabs.clear();
+  slab_of.clear();
 }
 
 void dev_free(void *p) {

@@ -410,10 +410,25 @@ namespace pgk {
 // power-of-two size instead of to hipFree, which waits for the device, and
 // come back from them instead of from hipMalloc.  Everything is released by
 // clear() when the batch is freed.
+// Blocks of up to kSlabBlockMax bytes are carved from slabs of
+// kSlabBlocks blocks (one runtime allocation instead of one per block: a
+// game allocates a dozen small buffers, and a first pass over many games
+// otherwise pays a hipMalloc or hipHostMalloc for each); a slab goes back to
+// the runtime once none of its blocks is in use.
 struct DevPool {
+  static constexpr size_t kSlabBlockMax = size_t(1) << 20;
+  static constexpr size_t kSlabBlocks = 32;
+  struct Slab {
+    void *base = nullptr;
+    size_t block = 0;
+    bool host = false;
+    int64_t in_use = 0;
+  };
   std::mutex mu;           // calls on different games may overlap
   std::map<size_t, std::vector<void *>> dev_free, host_free;
   std::unordered_map<void *, size_t> dev_size, host_size;
+  std::vector<Slab> slabs;
+  std::unordered_map<void *, size_t> slab_of;   // block -> index in slabs
   static size_t bucket(size_t bytes) {
     size_t b = 256;
     while (b < bytes) b <<= 1;

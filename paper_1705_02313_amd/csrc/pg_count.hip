@@ -858,13 +858,17 @@ pg_status export_counts(pg_game *g, int32_t *counts, uint8_t *top, bool dev,
   const int64_t nc = (N + 1) * g->d;
   int32_t *dc = counts;
   uint8_t *dt = top;
+  // temporaries go back to where they came from (the game cache while a
+  // call holds it) once the stream has drained
   struct Tmp {
     void *p[2] = {nullptr, nullptr};
+    hipStream_t s = nullptr;
     ~Tmp() {
-      for (void *x : p)
-        if (x) (void)hipFree(x);
+      if (p[0] || p[1]) (void)hipStreamSynchronize(s);
+      for (void *x : p) dev_free(x);
     }
   } tmp;
+  tmp.s = s;
   if (!dev) {
     PG_TRY(dev_alloc(&dc, nc));
     tmp.p[0] = dc;
