@@ -232,3 +232,29 @@ def test_memory_cache_reuse_and_release(pglib):
     g = synth.chain_game(3000, 9)
     ref, out = _solve_both(g)
     _assert_solve_equal(ref, out)
+
+
+def test_cache_release_with_a_game_still_loaded(pglib):
+    """pg_release_cache while a game is loaded keeps the slabs that game's
+    blocks live in; both games still solve like the oracle, and once every
+    game is freed and the cache released the device memory is back."""
+    import torch
+    from paper_1705_02313_amd import pg
+    pg.release_cache()
+    torch.cuda.synchronize()
+    free0, _ = torch.cuda.mem_get_info()
+    g1 = synth.random_game(20000, 2, 6, 401)
+    g2 = synth.random_game(9000, 2, 6, 402)
+    d1 = Game.from_dict(g1)
+    with Game.from_dict(g2):
+        pass                      # its blocks go back to the cache
+    pg.release_cache()            # d1's slabs stay, with their free blocks
+    out1 = d1.solve()
+    _assert_solve_equal(orc.solve(g1), out1)
+    ref2, out2 = _solve_both(g2)  # reuses the cached blocks
+    _assert_solve_equal(ref2, out2)
+    d1.free()
+    pg.release_cache()
+    torch.cuda.synchronize()
+    free1, _ = torch.cuda.mem_get_info()
+    assert free1 >= free0 - (64 << 20), (free0, free1)
