@@ -74,7 +74,8 @@ enum {
     PG_HOST_REDUCED_LIST = 64u,/* pg_load_csr: rank the reduced list on the
                                   host (the paper's GPU-LR split; below)     */
     PG_SWITCH_ROWS = 128u,  /* pg_load_csr: All_Odd reads rows (below)       */
-    PG_SWITCH_BUCKETS = 256u /* pg_load_csr: All_Odd by buckets (below)      */
+    PG_SWITCH_BUCKETS = 256u,/* pg_load_csr: All_Odd by buckets (below)      */
+    PG_KEEP_DUMMIES = 512u  /* pg_solve: tau in the modified game's ids      */
 };
 
 /*
@@ -276,8 +277,37 @@ enum {
 typedef struct pg_solve_opts {
     int32_t max_major;      /* cap on outer iterations (0 = none)            */
     int32_t max_inner;      /* cap on valuations per best response (0=none)  */
-    uint32_t flags;         /* PG_PTR_DEVICE for the output buffers          */
+    uint32_t flags;         /* PG_PTR_DEVICE for init_sigma, init_tau and the
+                               output buffers; PG_KEEP_DUMMIES (below)       */
     int32_t best_response;  /* PG_BR_* (0 = PG_BR_SI)                        */
+    /* Warm start (nullable; n_aug entries each, in the modified game's ids
+     * as pg_valuation takes them): the run starts from these strategies
+     * instead of sigma_init and the first entry of every row.  init_sigma
+     * must be admissible (section 3).  A run stopped by a cap hands back
+     * its current strategies (pg_solve, PG_EITERLIMIT); started from them
+     * with PG_KEEP_DUMMIES it continues exactly where it stopped.          */
+    const int32_t *init_sigma;
+    const int32_t *init_tau;
+    /* Per-valuation trace (host arrays, each nullable, trace_cap entries;
+     * entry i belongs to the i-th valuation of the run; beyond trace_cap
+     * nothing is written; stats->n_traced says how many were):
+     *   trace_key_hash   h = h * 1099511628211 + (uint32_t)key[v] + 1 over
+     *                    the keys of pg_valuation's output, v = 0..n_aug
+     *                    (the sink last), starting from h = 0, modulo 2^64
+     *                    (rank valuations; 0 for count valuations; computed
+     *                    on the device, one extra kernel per valuation)
+     *   trace_finite     vertices with a finite play, the sink included
+     *   trace_switches   Odd vertices switched by the All_Odd step that
+     *                    follows the valuation (0 ends a best response)
+     *   trace_ms         device time of the best-response iteration (the
+     *                    valuation and its All_Odd step) between two HIP
+     *                    events on the call's stream                      */
+    int32_t trace_cap;
+    int32_t reserved;
+    uint64_t *trace_key_hash;
+    int64_t *trace_finite;
+    int64_t *trace_switches;
+    float *trace_ms;
 } pg_solve_opts;
 
 typedef struct pg_stats {
@@ -287,10 +317,15 @@ typedef struct pg_stats {
     int64_t n_odd_switches; /* vertices switched by All_Odd, summed          */
     int64_t n_even_switches;/* vertices switched by All_Even, summed         */
     double seconds;         /* wall time of the solve on the host clock      */
+    double iteration_ms;    /* device time of the best-response iterations,
+                               summed (HIP events on the call's stream
+                               around each; 0 for Bellman-Ford and batches) */
+    int64_t n_traced;       /* entries written to the trace arrays           */
 } pg_stats;
 
 /*
- * pg_solve -- Algorithm 1 from the initial strategies to the end.  The outer
+ * pg_solve -- Algorithm 1 from the initial strategies (or opts->init_sigma,
+ * opts->init_tau) to the end.  The outer
  * loop switches Even by greedy all-switches (section 3, "Switching rules"):
  * among the sink (option 0) and the row, the first option of greatest
  * valuation replaces sigma(v) if its valuation is strictly greater.  It
@@ -298,17 +333,27 @@ typedef struct pg_stats {
  * valuation is then top are exactly Even's winning set.
  *
  *   opts     nullable (no caps; host outputs; PG_BR_SI).  PG_EINVAL for
- *            PG_BR_BELLMAN_FORD on a game with rank valuations.
+ *            PG_BR_BELLMAN_FORD on a game with rank valuations or a
+ *            negative trace_cap.  The trace covers the iterations of one-
+ *            player strategy improvement (Bellman-Ford rounds are not
+ *            traced).
  *   winner   n outputs (original vertices): 0 = W_Even, 1 = W_Odd
  *   sigma    n_aug outputs (nullable): the final sigma* (PG_SINK for the
  *            sink); vertices Even wins never map to the sink
  *   tau      n_aug outputs (nullable): the final tau* = br(sigma*), with
  *            an Odd choice of a dummy d_w given as w (the dummy only stands
  *            in the middle of the original edge to w), so the Odd choices of
- *            the n original vertices are edges of the original game.
- *            pg_best_response keeps dummies as they are (its tau is an
- *            input again)
+ *            the n original vertices are edges of the original game; with
+ *            PG_KEEP_DUMMIES in opts->flags the dummy itself (the form
+ *            pg_best_response and init_tau use)
  *   stats    nullable
+ *
+ * When a cap stops the run (PG_EITERLIMIT: max_major outer iterations
+ * done, or max_inner valuations in one best response), winner is not
+ * written, but sigma and tau (when given) receive the strategies reached:
+ * a checkpoint.  A later pg_solve with them as init_sigma and init_tau
+ * (PG_KEEP_DUMMIES form) takes exactly the remaining iterations of the
+ * uninterrupted run.
  */
 pg_status pg_solve(pg_game *game, const pg_solve_opts *opts, uint8_t *winner,
                    int32_t *sigma, int32_t *tau, pg_stats *stats,

@@ -271,7 +271,8 @@ __global__ void k_sp_init(const int64_t *off, const int32_t *tgt,
 
 
 // The strategy arrays at the C ABI use the caller's vertex ids; for a
-// relabeled game perm/rvpos translate them (both null otherwise).
+// relabeled game perm/rvpos translate them (both null otherwise).  A null
+// sigma (tau) leaves the Even (Odd) entries of sp as they are.
 __global__ void k_sp_import(const uint8_t *owner, const int32_t *pri,
                             const int32_t *sigma, const int32_t *tau,
                             const int32_t *perm, const int32_t *rvpos,
@@ -280,7 +281,9 @@ __global__ void k_sp_import(const uint8_t *owner, const int32_t *pri,
   if (i >= N) return;
   const int32_t v = perm ? perm[i] : (int32_t)i;
   const bool even = owner[i] == 0;
-  int32_t s = even ? sigma[v] : tau[v];
+  const int32_t *strat = even ? sigma : tau;
+  if (!strat) return;  // that player keeps its current choices
+  int32_t s = strat[v];
   if (even && s == PG_SINK) {
     s = N;
   } else if (s < 0 || s >= N) {
@@ -335,6 +338,37 @@ __global__ void k_key_export(const int32_t *key, const int32_t *rvpos,
   int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v > N) return;
   key2[v] = key[v == N ? N : rvpos[v]];
+}
+
+// Polynomial hash of the keys in the caller's ids (the order k_key_export
+// writes): h = sum over v of ((uint32)key'[v] + 1) * M^(N - v) mod 2^64,
+// which is the value of h = h * M + key'[v] + 1 folded from v = 0 to N.
+// Each thread raises M by square-and-multiply; one atomic per block.
+constexpr unsigned long long kHashMul = 1099511628211ull;
+__global__ void k_key_hash(const int32_t *key, const int32_t *rvpos,
+                           int32_t N, unsigned long long *out) {
+  __shared__ unsigned long long part[kBlock / kWave];
+  unsigned long long acc = 0;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v <= N;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t k = key[(v == N || !rvpos) ? v : rvpos[v]];
+    unsigned long long e = (unsigned long long)(N - v), pw = 1ull,
+                       b = kHashMul;
+    while (e) {
+      if (e & 1ull) pw *= b;
+      b *= b;
+      e >>= 1;
+    }
+    acc += ((unsigned long long)(uint32_t)k + 1ull) * pw;
+  }
+  for (int o = kWave / 2; o > 0; o >>= 1) acc += __shfl_down(acc, o, kWave);
+  if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x / kWave] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int w = 0; w < kBlock / kWave; ++w) t += part[w];
+    atomicAdd(out, t);
+  }
 }
 
 // Edges of the Odd rows (for the switch kernels' byte counts): a grid-stride
@@ -611,6 +645,8 @@ void free_game(pg_game *g) {
   for (hipGraphExec_t &ex : g->iter_exec)
     if (ex) (void)hipGraphExecDestroy(ex);
   if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
+  if (g->ev_a) (void)hipEventDestroy(g->ev_a);
+  if (g->ev_b) (void)hipEventDestroy(g->ev_b);
   g->prof.release();
   delete g;
 }
@@ -693,14 +729,21 @@ pg_status load_modified(int64_t n, int64_t m, const void *offsets,
   PG_TRY(dev_alloc(&g->ctr, C_TOTAL));
   fill_i32(g->ctr, 0, C_TOTAL, s);
 
-  // input copies
+  // input copies.  The temporaries go back to the shared per-device cache
+  // only after the stream has drained: the kernels queued last (the
+  // modified game's build, or the copies) still read them, and a load on
+  // another thread may take a returned block at once.
   int64_t *off_in = nullptr;
   int32_t *tgt_in = nullptr, *pri_in = nullptr;
   uint8_t *own_in = nullptr;
   struct Tmp {
+    hipStream_t s;
     std::vector<void *> p;
-    ~Tmp() { for (void *x : p) dev_free(x); }
-  } tmp;
+    ~Tmp() {
+      if (!p.empty()) (void)hipStreamSynchronize(s);
+      for (void *x : p) dev_free(x);
+    }
+  } tmp{s, {}};
   PG_TRY(dev_alloc(&off_in, n + 1));
   tmp.p.push_back(off_in);
   PG_TRY(dev_alloc(&tgt_in, m));
@@ -979,10 +1022,11 @@ pg_status import_strats(pg_game *g, const int32_t *sigma, const int32_t *tau,
   const int64_t N = g->n_aug;
   const int32_t *ds = sigma, *dt = tau;
   if (!dev) {
-    PG_TRY(copy_in(g->wl0, sigma, sizeof(int32_t) * N, false, s));
-    PG_TRY(copy_in(g->wl1, tau, sizeof(int32_t) * N, false, s));
-    ds = g->wl0;
-    dt = g->wl1;
+    // a null array leaves that player's choices as they are
+    if (sigma) PG_TRY(copy_in(g->wl0, sigma, sizeof(int32_t) * N, false, s));
+    if (tau) PG_TRY(copy_in(g->wl1, tau, sizeof(int32_t) * N, false, s));
+    ds = sigma ? g->wl0 : nullptr;
+    dt = tau ? g->wl1 : nullptr;
   }
   fill_i32(g->ctr, 0, C_COUNT, s);
   hipLaunchKernelGGL(k_sp_import, dim3(grid_for(N)), dim3(kBlock), 0, s,
@@ -1030,15 +1074,44 @@ pg_status export_keys(pg_game *g, int32_t *key, bool dev, hipStream_t s) {
 
 namespace {
 
+// The per-valuation trace of pg_solve (pg_solve_opts.trace_*): counts and
+// times go straight to the host arrays; key hashes are summed on the device
+// into dhash and copied out once at the end.
+struct Trace {
+  const pg_solve_opts *o = nullptr;
+  int64_t n = 0;
+  unsigned long long *dhash = nullptr;
+  void record(pg_game *g, hipStream_t s, int32_t switches, int64_t nf) {
+    if (!o || n >= o->trace_cap) return;
+    if (o->trace_finite) o->trace_finite[n] = nf;
+    if (o->trace_switches) o->trace_switches[n] = switches;
+    if (o->trace_ms) o->trace_ms[n] = g->last_ms;
+    if (dhash && !g->dense) {
+      // the next iteration overwrites the keys: it is ordered after this
+      // kernel on the same stream
+      const int32_t N = (int32_t)g->n_aug;
+      hipLaunchKernelGGL(k_key_hash, dim3(grid_for(N + 1) < 2048u
+                                              ? grid_for(N + 1) : 2048u),
+                         dim3(kBlock), 0, s, g->key,
+                         g->relabeled ? g->rvpos : nullptr, N, dhash + n);
+    }
+    ++n;
+  }
+};
+
 // The inner loop of Algorithm 1 on the play graph in g->sp.
 pg_status inner_loop(pg_game *g, int32_t max_inner, hipStream_t s,
-                     int64_t *n_val, int64_t *n_sw) {
+                     int64_t *n_val, int64_t *n_sw, Trace *tr = nullptr,
+                     double *iter_ms = nullptr) {
   int32_t inner = 0;
   for (;;) {
     if (max_inner > 0 && inner >= max_inner)
       return pg_fail(PG_EITERLIMIT, "best response: valuation cap reached");
     int32_t c = 0;
-    PG_TRY(iteration_device(g, s, &c));
+    int64_t nf = 0;
+    PG_TRY(iteration_device(g, s, &c, &nf));
+    if (iter_ms) *iter_ms += g->last_ms;
+    if (tr) tr->record(g, s, c, nf);
     ++inner;
     ++*n_val;
     *n_sw += c;
@@ -1282,12 +1355,28 @@ pg_status pg_solve(pg_game *g, const pg_solve_opts *opts, uint8_t *winner,
   if (o.best_response == PG_BR_BELLMAN_FORD && !g->dense)
     return pg_fail(PG_EINVAL, "Bellman-Ford best responses need a game with "
                               "count valuations");
+  if (o.trace_cap < 0) return pg_fail(PG_EINVAL, "trace_cap < 0");
   const auto t0 = std::chrono::steady_clock::now();
   const int64_t N = g->n_aug;
   hipLaunchKernelGGL(k_sp_init, dim3(grid_for(N)), dim3(kBlock), 0, s, g->off,
                      g->tgt, g->owner, g->pri, g->sp, (int32_t)N);
+  // warm start: the given strategies replace the initial ones
+  if (o.init_sigma || o.init_tau)
+    PG_TRY(import_strats(g, o.init_sigma, o.init_tau, dev, s));
   valuation_reset(g, s);
+  Trace tr;
+  tr.o = &o;
+  struct HashBuf {
+    unsigned long long *p = nullptr;
+    ~HashBuf() { dev_free(p); }
+  } hb;
+  if (o.trace_key_hash && o.trace_cap > 0) {
+    PG_TRY(dev_alloc(&hb.p, o.trace_cap));
+    fill_i32((int32_t *)hb.p, 0, 2 * (int64_t)o.trace_cap, s);
+    tr.dhash = hb.p;
+  }
   int64_t n_major = 0, n_val = 0, n_odd = 0, n_even = 0;
+  double iter_ms = 0.0;
   pg_status st = PG_OK;
   for (;;) {
     if (o.max_major > 0 && n_major >= o.max_major) {
@@ -1303,7 +1392,7 @@ pg_status pg_solve(pg_game *g, const pg_solve_opts *opts, uint8_t *winner,
       st = bf_best_response(g, s, &rounds);
       n_val += rounds;
     } else {
-      st = inner_loop(g, o.max_inner, s, &n_val, &n_odd);
+      st = inner_loop(g, o.max_inner, s, &n_val, &n_odd, &tr, &iter_ms);
     }
     if (st != PG_OK) break;
     int32_t c = 0;
@@ -1312,6 +1401,17 @@ pg_status pg_solve(pg_game *g, const pg_solve_opts *opts, uint8_t *winner,
     n_even += c;
     if (c == 0) break;
   }
+  if (tr.dhash && tr.n > 0) {
+    // the trace is the caller's even when the run stopped early
+    const std::string err = pg_last_error();
+    PG_HIP(hipMemcpyAsync(o.trace_key_hash, tr.dhash,
+                          sizeof(uint64_t) * (size_t)tr.n,
+                          hipMemcpyDeviceToHost, s));
+    PG_HIP(hipStreamSynchronize(s));
+    if (st != PG_OK) pg_fail(st, err);
+  }
+  if (o.trace_key_hash && g->dense)
+    for (int64_t i = 0; i < tr.n; ++i) o.trace_key_hash[i] = 0;
   if (stats) {
     stats->n = g->n;
     stats->m = g->m;
@@ -1321,6 +1421,15 @@ pg_status pg_solve(pg_game *g, const pg_solve_opts *opts, uint8_t *winner,
     stats->n_valuations = n_val;
     stats->n_odd_switches = n_odd;
     stats->n_even_switches = n_even;
+    stats->iteration_ms = iter_ms;
+    stats->n_traced = tr.n;
+  }
+  const bool report = !(o.flags & PG_KEEP_DUMMIES);
+  if (st == PG_EITERLIMIT) {
+    // a checkpoint: the strategies reached, from which a warm start resumes
+    const std::string err = pg_last_error();
+    PG_TRY(export_strats(g, sigma, tau, dev, s, report));
+    return pg_fail(st, err);
   }
   if (st != PG_OK) return st;
   uint8_t *dw = winner;
@@ -1329,7 +1438,7 @@ pg_status pg_solve(pg_game *g, const pg_solve_opts *opts, uint8_t *winner,
                      g->rs, io_rvpos(g), dw, g->n);
   if (!dev) PG_TRY(copy_out(winner, dw, g->n, false, s));
   PG_HIP(hipStreamSynchronize(s));
-  PG_TRY(export_strats(g, sigma, tau, dev, s, true));
+  PG_TRY(export_strats(g, sigma, tau, dev, s, report));
   const auto t1 = std::chrono::steady_clock::now();
   if (stats) stats->seconds = std::chrono::duration<double>(t1 - t0).count();
   return PG_OK;

@@ -239,6 +239,10 @@ struct pg_game {
   int32_t *hctr = nullptr;   // pinned host mirror
 
   pgk::Prof prof;
+  // HIP events around each best-response iteration on the call's stream
+  // (created at first use); the last iteration's device time
+  hipEvent_t ev_a = nullptr, ev_b = nullptr;
+  float last_ms = 0.0f;
 };
 
 // The signed-order maps the valuation kernels take: none for a relabeled
@@ -367,8 +371,11 @@ pg_status valuation_device(pg_game *g, hipStream_t s, int64_t *n_finite_out);
 // One All_Odd (odd = true) or All_Even step on g->sp from g->key.
 pg_status switch_device(pg_game *g, bool odd, hipStream_t s, int32_t *count);
 // One best-response iteration (valuation, then All_Odd) with a single
-// host synchronisation; returns the number of Odd switches.
-pg_status iteration_device(pg_game *g, hipStream_t s, int32_t *count);
+// host synchronisation; returns the number of Odd switches and (nullable)
+// the finite vertices, the sink included.  g->last_ms receives the
+// iteration's device time between two HIP events on s.
+pg_status iteration_device(pg_game *g, hipStream_t s, int32_t *count,
+                           int64_t *n_finite = nullptr);
 }  // namespace pgk
 
 // ---- count valuations (pg_count.hip) ---------------------------------------

@@ -959,6 +959,11 @@ static pg_status run_valuation(pg_game *g, hipStream_t s, bool odd_switch,
                                int32_t *count, int64_t *n_finite) {
   g->nlevels = g->dense ? count_levels(g->n_aug, g->dw)
                         : plan_levels(g->n_aug);
+  if (!g->ev_a) {
+    PG_HIP(hipEventCreate(&g->ev_a));
+    PG_HIP(hipEventCreate(&g->ev_b));
+  }
+  PG_HIP(hipEventRecord(g->ev_a, s));
   bool replayed = false;
   if (odd_switch && g->use_graph && !g->careful && !g->prof.on &&
       !g->host_rl) {
@@ -980,6 +985,7 @@ static pg_status run_valuation(pg_game *g, hipStream_t s, bool odd_switch,
       enqueue_any_switch(g, true, s, true);
     }
   }
+  PG_HIP(hipEventRecord(g->ev_b, s));
   pg_status st = read_ctr(g, s);
   if (st != PG_OK) return st;
   if (g->hctr[C_ABORT]) {
@@ -992,9 +998,12 @@ static pg_status run_valuation(pg_game *g, hipStream_t s, bool odd_switch,
     if (odd_switch) {
       enqueue_any_switch(g, true, s, true);
     }
+    PG_HIP(hipEventRecord(g->ev_b, s));
     st = read_ctr(g, s);
     if (st != PG_OK) return st;
   }
+  if (hipEventElapsedTime(&g->last_ms, g->ev_a, g->ev_b) != hipSuccess)
+    g->last_ms = 0.0f;
   g->par ^= 1;
   st = check_ctr(g);
   if (st != PG_OK) return st;
@@ -1007,8 +1016,9 @@ pg_status valuation_device(pg_game *g, hipStream_t s, int64_t *n_finite_out) {
   return run_valuation(g, s, false, nullptr, n_finite_out);
 }
 
-pg_status iteration_device(pg_game *g, hipStream_t s, int32_t *count) {
-  return run_valuation(g, s, true, count, nullptr);
+pg_status iteration_device(pg_game *g, hipStream_t s, int32_t *count,
+                           int64_t *n_finite) {
+  return run_valuation(g, s, true, count, n_finite);
 }
 
 pg_status switch_device(pg_game *g, bool odd, hipStream_t s, int32_t *count) {

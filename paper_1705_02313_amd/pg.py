@@ -24,6 +24,7 @@ PG_PTR_DEVICE, PG_NO_PREPROCESS, PG_OFFSETS_I32 = 1, 2, 4
 PG_CAREFUL_WALKS, PG_COUNT_VALUATION, PG_NO_GRAPH = 8, 16, 32
 PG_HOST_REDUCED_LIST = 64
 PG_SWITCH_ROWS, PG_SWITCH_BUCKETS = 128, 256
+PG_KEEP_DUMMIES = 512
 PG_BR_SI, PG_BR_SI_RESET, PG_BR_BELLMAN_FORD = 0, 1, 2
 
 STATUS_NAMES = {0: "PG_OK", 1: "PG_EINVAL", 2: "PG_ENOMEM", 3: "PG_EDEVICE",
@@ -54,7 +55,13 @@ class PgError(RuntimeError):
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [("max_major", ctypes.c_int32), ("max_inner", ctypes.c_int32),
-                ("flags", ctypes.c_uint32), ("best_response", ctypes.c_int32)]
+                ("flags", ctypes.c_uint32), ("best_response", ctypes.c_int32),
+                ("init_sigma", ctypes.c_void_p), ("init_tau", ctypes.c_void_p),
+                ("trace_cap", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("trace_key_hash", ctypes.c_void_p),
+                ("trace_finite", ctypes.c_void_p),
+                ("trace_switches", ctypes.c_void_p),
+                ("trace_ms", ctypes.c_void_p)]
 
 
 class Stats(ctypes.Structure):
@@ -63,10 +70,31 @@ class Stats(ctypes.Structure):
                 ("n_major", ctypes.c_int64), ("n_valuations", ctypes.c_int64),
                 ("n_odd_switches", ctypes.c_int64),
                 ("n_even_switches", ctypes.c_int64),
-                ("seconds", ctypes.c_double)]
+                ("seconds", ctypes.c_double),
+                ("iteration_ms", ctypes.c_double),
+                ("n_traced", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def write_trace_jsonl(path: str, out: dict, extra: dict = None):
+    """Appends one JSON line per traced valuation of a solve (the dict
+    Game.solve(trace=...) returns): its index, key hash, finite vertices,
+    Odd switches and device milliseconds, plus the `extra` fields."""
+    import json
+    tr = out.get("trace")
+    if tr is None:
+        raise ValueError("the solve was run without a trace")
+    with open(path, "a") as f:
+        for i in range(len(tr["finite"])):
+            rec = {"valuation": i, "key_hash": int(tr["key_hash"][i]),
+                   "finite": int(tr["finite"][i]),
+                   "odd_switches": int(tr["switches"][i]),
+                   "device_ms": float(tr["ms"][i])}
+            if extra:
+                rec.update(extra)
+            f.write(json.dumps(rec) + "\n")
 
 
 _lib = None
@@ -311,17 +339,45 @@ class Game:
         return tau, key, int(nv.value)
 
     def solve(self, max_major: int = 0, max_inner: int = 0,
-              best_response: int = PG_BR_SI) -> dict:
-        opts = SolveOpts(max_major, max_inner, self._flags, best_response)
+              best_response: int = PG_BR_SI, init_sigma=None, init_tau=None,
+              trace: int = 0, keep_dummies: bool = False,
+              checkpoint: bool = False) -> dict:
+        """Algorithm 1 (pg_solve).  init_sigma / init_tau: a warm start (in
+        the modified game's ids).  trace: valuations to trace (key hash,
+        finite vertices, switches, device ms; out["trace"]).  keep_dummies:
+        tau in the modified game's ids (PG_KEEP_DUMMIES).  checkpoint: a
+        cap that stops the run returns {"stopped": True, "sigma", "tau",
+        "stats"} instead of raising."""
+        flags = self._flags | (PG_KEEP_DUMMIES if keep_dummies else 0)
+        isg = None if init_sigma is None else self._in(init_sigma)
+        itau = None if init_tau is None else self._in(init_tau)
+        tr = None
+        if trace:
+            tr = {"key_hash": np.zeros(trace, np.uint64),
+                  "finite": np.zeros(trace, np.int64),
+                  "switches": np.zeros(trace, np.int64),
+                  "ms": np.zeros(trace, np.float32)}
+        opts = SolveOpts(max_major, max_inner, flags, best_response,
+                         _ptr(isg), _ptr(itau), int(trace), 0,
+                         *([_ptr(tr[k]) for k in ("key_hash", "finite",
+                                                  "switches", "ms")]
+                           if tr else [None] * 4))
         winner = self._out(self.n, np.uint8)
         sigma = self._out(self.n_aug, np.int32)
         tau = self._out(self.n_aug, np.int32)
         st = Stats()
-        _check(lib().pg_solve(self._h, ctypes.byref(opts), _ptr(winner),
-                              _ptr(sigma), _ptr(tau), ctypes.byref(st),
-                              _stream(self.device)))
+        rc = lib().pg_solve(self._h, ctypes.byref(opts), _ptr(winner),
+                            _ptr(sigma), _ptr(tau), ctypes.byref(st),
+                            _stream(self.device))
+        if tr is not None:
+            k = int(st.n_traced)
+            tr = {key: v[:k].copy() for key, v in tr.items()}
+        if rc == PG_EITERLIMIT and checkpoint:
+            return {"stopped": True, "sigma": sigma, "tau": tau,
+                    "stats": st.as_dict(), "trace": tr}
+        _check(rc)
         return {"winner": winner, "sigma": sigma, "tau": tau,
-                "stats": st.as_dict()}
+                "stats": st.as_dict(), "trace": tr}
 
     def profile(self, on: bool = True):
         """Enables (and clears) or disables the per-kernel event profiler."""
@@ -387,6 +443,9 @@ class Batch:
             arr["targets"] = arr["targets"].to(torch.int32)
             arr["owner"] = arr["owner"].to(torch.uint8)
             arr["pri"] = arr["pri"].to(torch.int32)
+            # pg_batch_submit reads them on the batch's own stream: the
+            # copies and conversions queued on torch's stream finish first
+            torch.cuda.current_stream().synchronize()
         else:
             off = np.ascontiguousarray(g["offsets"])
             flags = PG_OFFSETS_I32 if off.dtype == np.int32 else 0

@@ -71,12 +71,23 @@ def _run(game, gold, device=True):
         s0, t0 = dev.initial_strategies()
         k0, _ = dev.valuation(s0, t0)
         assert np_hash(to_np(k0)) == gold["trace"][0]
-        out = dev.solve()
+        out = dev.solve(trace=len(gold["trace"]) + 8)
         st = out["stats"]
         assert st["n_major"] == gold["n_major"]
         assert st["n_valuations"] == gold["n_valuations"]
         assert st["n_odd_switches"] == gold["n_odd_switches"]
         assert st["n_even_switches"] == gold["n_even_switches"]
+        # every valuation of the run, bit for bit (hash of all n_aug + 1
+        # keys in the caller's ids), and the last one
+        tr = out["trace"]
+        assert st["n_traced"] == len(gold["trace"])
+        got = [int(x) for x in tr["key_hash"]]
+        bad = [i for i, (a, b) in enumerate(zip(got, gold["trace"]))
+               if a != b]
+        assert not bad, f"valuations {bad[:10]} differ from the oracle's"
+        assert got[-1] == gold["key_hash"]
+        assert (tr["switches"][:-1] >= 0).all() and tr["switches"][-1] == 0
+        assert int(tr["switches"].sum()) == gold["n_odd_switches"]
         assert np_hash(to_np(out["winner"]).astype(np.int32)) == \
             gold["winner_hash"]
         assert np_hash(to_np(out["sigma"])) == gold["sigma_hash"]
@@ -91,15 +102,33 @@ def _run(game, gold, device=True):
         _final_checks(dev, out, tau)
 
 
-def test_config0_twenty_seeds():
+def _int32_offsets(game):
+    g = dict(game)
+    g["offsets"] = np.asarray(game["offsets"]).astype(np.int32)
+    return g
+
+
+@pytest.mark.parametrize("offsets", ["int64", "int32"])
+def test_config0_twenty_seeds(offsets):
     gold = _golden("c0s")
     for seed, gd in gold.items():
-        print("c0 seed", seed, flush=True)
-        _run(synth.random_game(1000, 2, 5, int(seed)), gd, device=False)
+        print("c0 seed", seed, offsets, flush=True)
+        g = synth.random_game(1000, 2, 5, int(seed))
+        if offsets == "int32":
+            g = _int32_offsets(g)
+            assert np.asarray(g["offsets"]).dtype == np.int32
+        _run(g, gd, device=(offsets == "int32"))
 
 
-@pytest.mark.parametrize("cfg", [1, 2, 3])
-def test_full_size_config(cfg):
+# the workloads' own offset widths: int32 for configs 1 and 3, int64 for
+# config 2; the other width as well where it can address the edges
+@pytest.mark.parametrize("cfg,offsets", [(1, "int32"), (1, "int64"),
+                                         (2, "int64"), (3, "int32"),
+                                         (3, "int64")])
+def test_full_size_config(cfg, offsets):
     gold = _golden(f"c{cfg}")
-    print("config", cfg, flush=True)
-    _run(synth.config_game(cfg), gold)
+    print("config", cfg, offsets, flush=True)
+    g = synth.config_game(cfg)
+    if offsets == "int32":
+        g = _int32_offsets(g)
+    _run(g, gold)

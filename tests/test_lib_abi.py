@@ -64,7 +64,7 @@ def test_binding_constants_mirror_the_header():
                  "PG_PTR_DEVICE", "PG_NO_PREPROCESS", "PG_OFFSETS_I32",
                  "PG_CAREFUL_WALKS", "PG_COUNT_VALUATION", "PG_NO_GRAPH",
                  "PG_HOST_REDUCED_LIST", "PG_SWITCH_ROWS", "PG_SWITCH_BUCKETS",
-                 "PG_BR_SI", "PG_BR_SI_RESET", "PG_BR_BELLMAN_FORD",
+                 "PG_KEEP_DUMMIES", "PG_BR_SI", "PG_BR_SI_RESET", "PG_BR_BELLMAN_FORD",
                  "PG_SINK", "PG_KEY_TOP"):
         assert name in consts, name
         if hasattr(pg, name):
@@ -73,6 +73,38 @@ def test_binding_constants_mirror_the_header():
     flags = [consts[k] for k in consts if k in (
         "PG_PTR_DEVICE", "PG_NO_PREPROCESS", "PG_OFFSETS_I32",
         "PG_CAREFUL_WALKS", "PG_COUNT_VALUATION", "PG_NO_GRAPH",
-        "PG_HOST_REDUCED_LIST", "PG_SWITCH_ROWS", "PG_SWITCH_BUCKETS")]
+        "PG_HOST_REDUCED_LIST", "PG_SWITCH_ROWS", "PG_SWITCH_BUCKETS",
+        "PG_KEEP_DUMMIES")]
     assert all(f & (f - 1) == 0 for f in flags)
     assert len(set(flags)) == len(flags)
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """The ctypes mirrors of pg_solve_opts and pg_stats have the header's
+    size and field offsets (a C program built with gcc prints them)."""
+    import shutil
+    import subprocess
+    from paper_1705_02313_amd import pg
+    if not shutil.which("gcc"):
+        pytest.skip("no gcc")
+    prog = ["#include <stddef.h>", "#include <stdio.h>",
+            f'#include "{HEADER}"', "int main(void) {"]
+    for cname, cls in (("pg_solve_opts", pg.SolveOpts),
+                       ("pg_stats", pg.Stats)):
+        prog.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            prog.append(f'printf("{cname} {f} %zu\\n", '
+                        f'offsetof({cname}, {f}));')
+    prog.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(prog))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True,
+                         text=True).stdout.split("\n")
+    got = {tuple(ln.split()[:2]): int(ln.split()[2]) for ln in out if ln}
+    for cname, cls in (("pg_solve_opts", pg.SolveOpts),
+                       ("pg_stats", pg.Stats)):
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
