@@ -24,17 +24,33 @@ Workloads (seeded, synthetic; see paper_1705_02313_amd/synth.py):
       and served as a Poisson stream at 1.5 mu under an arena budget of a
       quarter of the mix's modified vertices (latency p50/p99)
 
-Printed: one JSON line with the driver's fields plus "roofline" (the kernel
-that takes the most time, its algorithmic bytes over its event-timed
-duration against 8 TB/s, from up to two profiled steps run after the timed
-steps), "iteration_roofline" (every kernel's algorithmic bytes per
-best-response iteration over the iteration's unprofiled time, against the
-same peak; the method's least bytes per iteration likewise; the counter
-bytes when they are current; and a measured 1 GiB copy rate), on c3
-"deep_list_valuation" (one valuation of a play through every vertex) and
-"cpu_baseline" (the CPU oracle timed on this host on a bounded sample of
-the same workload), with "cpu_lr_baseline" beside it for rank valuations
-(the multi-core CPU-LR baseline on the same sample).  --best-response picks the best responses
+Printed: one JSON line with the driver's fields plus
+  "roofline"   the best-response iteration (one replay of its HIP graph:
+               walks, valuation, All_Odd) as the unit: the method's least
+               bytes per iteration (CSR offsets and targets, one key gather
+               per edge, 25 B per vertex, 12 B per element of a 2n'-element
+               Euler list) over the iteration's average device time, taken
+               with HIP events on the solve's stream around every iteration
+               of the timed steps, against 8 TB/s; "traffic" is the
+               rocprofv3 counter bytes per iteration (FETCH_SIZE +
+               WRITE_SIZE scaled on a plain copy: bytes through the L2's
+               fabric port, Infinity Cache hits included, so an upper bound
+               on HBM bytes) when they were taken on the current sources
+  "dominant_kernel"  the kernel with the largest summed time in up to two
+               profiled steps after the timed steps, its own algorithmic
+               bytes over its event-timed duration
+  "iteration_bytes"  every kernel's algorithmic bytes per iteration, the
+               counter bytes, a measured 1 GiB copy rate
+  "mix"        (c2 runs, unless --no-mix) the 1,024-game batched/served
+               workload: games/s one at a time, batched and served, p50/p99
+               latency, identical results, a roofline fraction and the CPU
+               oracle on a sample of the mix
+  "cpu_baseline"  the CPU oracle timed on this host, pinned to one core, on
+               a bounded sample of the same workload, with
+               "cpu_lr_baseline" beside it for rank valuations (the
+               multi-core CPU-LR baseline on the same sample)
+and on c3 "deep_list_valuation" (one valuation of a play through every
+vertex).  --best-response picks the best responses
 (section 6's comparison: SI, SI-Reset, Bellman-Ford on count games).
 """
 from __future__ import annotations
@@ -180,6 +196,37 @@ def deep_list_valuation(arrs, n: int, reps: int = 5) -> dict:
             "n_aug": int(N), "reps": reps}
 
 
+class one_core:
+    """Pins this process to one CPU (the first it may use) inside the block,
+    so that the oracle's timing uses exactly one core; the previous
+    affinity comes back at the end (no re-exec, no child process)."""
+
+    def __enter__(self):
+        self.prev = None
+        try:
+            self.prev = os.sched_getaffinity(0)
+            self.core = min(self.prev)
+            os.sched_setaffinity(0, {self.core})
+        except (AttributeError, OSError):
+            self.core = None
+        return self
+
+    def __exit__(self, *exc):
+        if self.prev is not None:
+            os.sched_setaffinity(0, self.prev)
+
+
+def host_info() -> dict:
+    """The host's CPU model, its logical CPU count and the CPUs this process
+    may use."""
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = None
+    return {"cpu": _host_cpu(), "nproc": os.cpu_count(),
+            "usable_cpus": usable}
+
+
 def cpu_baseline(game: dict, iters: int = 3, counts: bool = False):
     """The CPU oracle on this host: its preprocessing, then the first `iters`
     best-response iterations (valuation + All_Odd) of Algorithm 1 (with the
@@ -187,33 +234,35 @@ def cpu_baseline(game: dict, iters: int = 3, counts: bool = False):
     multi-core CPU-LR baseline (baselines/cpu_lr.c, the paper's CPU-LR) is
     timed on the same iterations; returns (oracle, cpu_lr or None)."""
     from oracle import orc
-    t0 = time.perf_counter()
-    aug = orc.dense_preprocess(game) if counts else orc.preprocess(game)
-    t_pre = time.perf_counter() - t0
-    sigma, tau = orc.initial_strategies(aug)
-    sigma0, tau0 = sigma.copy(), tau.copy()
-    by_pri = None if counts else orc.order_by_pri(aug["pri"])
-    times = []
-    for _ in range(iters):
-        t1 = time.perf_counter()
-        succ = np.where(aug["owner"] == 1, tau, sigma).astype(np.int32)
-        if counts:
-            cnt, top, values, rc = orc.dense_valuation(succ, aug["pri"])
-            tau, c = orc.dense_odd_switch(aug, cnt, top, values, tau)
-        else:
-            key, _, rc = orc.valuation(succ, aug["pri"], by_pri=by_pri)
-            tau, c = orc.odd_switch(aug, key, tau)
-        times.append(time.perf_counter() - t1)
-        if c == 0:
-            break
+    with one_core() as pin:
+        t0 = time.perf_counter()
+        aug = orc.dense_preprocess(game) if counts else orc.preprocess(game)
+        t_pre = time.perf_counter() - t0
+        sigma, tau = orc.initial_strategies(aug)
+        sigma0, tau0 = sigma.copy(), tau.copy()
+        by_pri = None if counts else orc.order_by_pri(aug["pri"])
+        times = []
+        for _ in range(iters):
+            t1 = time.perf_counter()
+            succ = np.where(aug["owner"] == 1, tau, sigma).astype(np.int32)
+            if counts:
+                cnt, top, values, rc = orc.dense_valuation(succ, aug["pri"])
+                tau, c = orc.dense_odd_switch(aug, cnt, top, values, tau)
+            else:
+                key, _, rc = orc.valuation(succ, aug["pri"], by_pri=by_pri)
+                tau, c = orc.odd_switch(aug, key, tau)
+            times.append(time.perf_counter() - t1)
+            if c == 0:
+                break
     t_iter = statistics.median(times)
     oracle = {"value": game["m"] / t_iter, "unit": "edges/s per "
               "best-response iteration", "cores": 1, "kind": "oracle",
               "sample": f"oracle preprocessing ({t_pre:.2f} s, not in value) "
                         f"then {len(times)} best-response iterations "
                         "(valuation + All_Odd) from the initial strategies, "
-                        f"median {t_iter:.3f} s each, single thread",
-              "host_cpu": _host_cpu()}
+                        f"median {t_iter:.3f} s each, single thread pinned "
+                        f"to CPU {pin.core}",
+              "host": host_info()}
     lr = None
     if not counts:
         from baselines import cpu_lr
@@ -238,15 +287,19 @@ def _host_cpu() -> str:
     return "unknown"
 
 
-def bench_mix(args) -> dict:
-    """The batched/served workload; see the module docstring."""
+def run_mix(n_games: int, oracle_budget_s: float = 10.0) -> dict:
+    """The batched/served workload: one-at-a-time solves, every game present
+    at t = 0 (the calibration rate mu), then a Poisson stream at 1.5 mu
+    under an arena budget of a quarter of the mix; the CPU oracle on the
+    first games of the mix, pinned to one core, for about
+    `oracle_budget_s`."""
     import torch
     from paper_1705_02313_amd import synth
     from paper_1705_02313_amd.pg import Game
     from paper_1705_02313_amd.serve import poisson_arrivals, serve
 
     t0 = time.perf_counter()
-    games = synth.mixed_batch(args.mix_games, 4000)
+    games = synth.mixed_batch(n_games, 4000)
     log(f"generated {len(games)} games in {time.perf_counter() - t0:.1f}s, "
         f"sum n = {sum(g['n'] for g in games)}")
     torch.cuda.set_device(0)
@@ -292,34 +345,83 @@ def bench_mix(args) -> dict:
         f"{served:.1f} games/s, p50 {np.percentile(lat, 50) * 1e3:.1f} ms, "
         f"p99 {np.percentile(lat, 99) * 1e3:.1f} ms")
     ident = same(rb) and same(rs)
+    # the method's least bytes over every iteration of every game
+    mix_bytes = sum(
+        method_min_bytes(int(r["stats"]["n_aug"]), int(r["stats"]["m_aug"]),
+                         np.asarray(g["offsets"]).itemsize) *
+        int(r["stats"]["n_valuations"]) for g, r in zip(games, solo))
+
+    def frac(seconds):
+        return round(mix_bytes / seconds / 1e9 / HBM_PEAK_GBS, 4)
+
+    # the oracle, one game after another, on one core
+    from oracle import orc
+    done = 0
+    with one_core() as pin:
+        t0 = time.perf_counter()
+        while done < len(games) and time.perf_counter() - t0 < oracle_budget_s:
+            orc.solve(games[done])
+            done += 1
+        t_orc = time.perf_counter() - t0
+    edges_done = sum(g["m"] for g in games[:done])
+    edges_all = sum(g["m"] for g in games)
     return {
-        "metric": "batched games/s",
-        "value": served,
-        "unit": "games/s",
-        "n_gpus": 1,
-        "steps": 1,
-        "warmup": 0,
-        "ms_per_step": rs["makespan"] * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int32",
-        "data": "synthetic",
-        "config": {"workload": WORKLOADS["c4"][0], "games": len(games),
-                   "sum_n": int(sum(g["n"] for g in games)),
-                   "sum_n_aug": int(n_aug_total),
-                   "arena_budget_vertices": int(budget_v),
-                   "arrivals": "Poisson, rate 1.5 x batched calibration rate"},
+        "workload": WORKLOADS["c4"][0],
+        "games": len(games),
+        "sum_n": int(sum(g["n"] for g in games)),
+        "sum_n_aug": int(n_aug_total),
+        "sum_valuations": int(sum(r["stats"]["n_valuations"] for r in solo)),
+        "arena_budget_vertices": int(budget_v),
+        "arrivals": "Poisson, rate 1.5 x batched calibration rate",
         "served_games_per_s": served,
+        "served_makespan_s": rs["makespan"],
         "latency_p50_ms": float(np.percentile(lat, 50) * 1e3),
         "latency_p99_ms": float(np.percentile(lat, 99) * 1e3),
         "batched_all_at_once_games_per_s": mu,
         "one_at_a_time_games_per_s": len(games) / t_solo,
         "speedup_served_vs_one_at_a_time": served * t_solo / len(games),
+        "speedup_batched_vs_one_at_a_time": mu * t_solo / len(games),
         "identical_to_one_at_a_time": bool(ident),
         "served_steps": rs["steps"],
-        "roofline": None,
-        "cpu_baseline": None,
+        "roofline": {"bound": "hbm", "unit": "fraction of 8 TB/s",
+                     "method_min_bytes_all_games": int(mix_bytes),
+                     "served_frac": frac(rs["makespan"]),
+                     "batched_frac": frac(rb["makespan"]),
+                     "one_at_a_time_frac": frac(t_solo)},
+        "cpu_baseline": {
+            "value": done / t_orc, "unit": "games/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"the first {done} games of the mix solved one after "
+                      f"another by the oracle ({t_orc:.1f} s, pinned to CPU "
+                      f"{pin.core}); {edges_done} of the mix's {edges_all} "
+                      "edges",
+            "host": host_info()},
+    }
+
+
+def bench_mix(args) -> dict:
+    """The batched/served workload as the headline line."""
+    mix = run_mix(args.mix_games)
+    return {
+        "metric": "batched games/s",
+        "value": mix["served_games_per_s"],
+        "unit": "games/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 0,
+        "ms_per_step": mix["served_makespan_s"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": mix["workload"], "games": mix["games"],
+                   "sum_n": mix["sum_n"], "sum_n_aug": mix["sum_n_aug"],
+                   "arena_budget_vertices": mix["arena_budget_vertices"],
+                   "arrivals": mix["arrivals"]},
+        **{k: v for k, v in mix.items()
+           if k not in ("workload", "games", "sum_n", "sum_n_aug",
+                        "arena_budget_vertices", "arrivals")},
     }
 
 
@@ -339,6 +441,8 @@ def main():
     ap.add_argument("--host-reduced-list", action="store_true",
                     help="rank the reduced list on the host (the paper's "
                          "GPU-LR split), to measure it against the device")
+    ap.add_argument("--no-mix", action="store_true",
+                    help="leave the batched/served mix out of a c2 run")
     ap.add_argument("--mix-games", type=int, default=1024,
                     help="games in the batched/served workload")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -432,13 +536,45 @@ def main():
     solve_s = [r["solve"] for r in runs]
     load_s = [r["load"] for r in runs]
 
-    # Roofline of the dominant kernel.  The library's event profiler records
-    # a pair of HIP events around every kernel on its stream; those events
-    # drain the stream between kernels (8 % of the step at 10M vertices,
-    # more on small games), so the timed steps above run without it and the
-    # kernel table comes from profiled steps of the same job right after.
+    # Roofline of the best-response iteration (one replay of its HIP graph)
+    # from the timed steps: the library records HIP events on the solve's
+    # stream around every iteration (pg_stats.iteration_ms, summed).
+    n_aug, m_aug = runs[0]["aug"][0], runs[0]["aug"][1]
+    b_min = method_min_bytes(n_aug, m_aug,
+                             np.asarray(game["offsets"]).itemsize)
+    it_ev_s = statistics.median(r["stats"]["iteration_ms"] for r in runs) \
+        / 1e3 / nval
+    it_wall_s = statistics.median(r["solve"] for r in runs) / nval
     roof = None
-    iteration_roof = None
+    if it_ev_s > 0:
+        roof = {"bound": "hbm",
+                "kernel": "best-response iteration (one HIP-graph replay: "
+                          "ng and root walks, parent sort, Euler list, list "
+                          "ranking, All_Odd)",
+                "achieved": round(b_min / it_ev_s / 1e9, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(b_min / it_ev_s / 1e9 / HBM_PEAK_GBS, 4),
+                "avg_launch_us": round(it_ev_s * 1e6, 2),
+                "bytes_per_launch": b_min,
+                "launches": nval * args.steps,
+                "traffic": None,
+                "traffic_kind": "rocprofv3 FETCH_SIZE + WRITE_SIZE per "
+                                "iteration, each scaled by its reading on a "
+                                "plain copy: bytes through the L2's fabric "
+                                "port (Infinity Cache hits included)",
+                "wall_us_per_iteration": round(it_wall_s * 1e6, 2),
+                "wall_frac": round(b_min / it_wall_s / 1e9 / HBM_PEAK_GBS,
+                                   4),
+                "measured_over": f"HIP events around each of the "
+                                 f"{nval * args.steps} iterations of the "
+                                 "timed steps"}
+
+    # Per-kernel figures: the library's event profiler records a pair of
+    # HIP events around every kernel on its stream; those events drain the
+    # stream between kernels, so they come from profiled steps of the same
+    # job after the timed ones.
+    dominant = None
+    iteration_bytes = None
     kernels = {}
     prof_steps = 0
     if not args.no_profile:
@@ -459,38 +595,30 @@ def main():
         dom = max(agg, key=lambda k: agg[k]["ms"])
         a = agg[dom]
         achieved = a["bytes"] / (a["ms"] / 1e3) / 1e9
-        roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "avg_launch_us": round(1e3 * a["ms"] / a["calls"], 2),
-                "bytes_per_launch": round(a["bytes"] / a["calls"]),
-                "traffic": counter_traffic(args.workload, dom),
-                "measured_over": f"{prof_steps} profiled steps of the same "
-                                 "job after the timed steps"}
-        # The whole best-response iteration against the same peak: every
-        # kernel's algorithmic bytes per iteration over the unprofiled time
-        # of an iteration (host time between launches included), and the
-        # counter bytes where every kernel kind has them.
+        dominant = {"kernel": dom, "achieved": round(achieved, 1),
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "avg_launch_us": round(1e3 * a["ms"] / a["calls"], 2),
+                    "bytes_per_launch": round(a["bytes"] / a["calls"]),
+                    "traffic": counter_traffic(args.workload, dom),
+                    "measured_over": f"{prof_steps} profiled steps of the "
+                                     "same job after the timed steps"}
         it_bytes = sum(a["bytes"] for a in agg.values()) / (prof_steps * nval)
-        it_s = statistics.median(r["solve"] for r in runs) / nval
         traffic = {k: counter_traffic(args.workload, k) for k in agg}
         it_traffic = None
         if all(v is not None for v in traffic.values()):
             it_traffic = sum(traffic[k] * agg[k]["calls"] for k in agg) / (
                 prof_steps * nval)
-        n_aug, m_aug = runs[0]["aug"][0], runs[0]["aug"][1]
-        b_min = method_min_bytes(n_aug, m_aug,
-                                 np.asarray(game["offsets"]).itemsize)
-        iteration_roof = {
-            "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
-            "alg_bytes": round(it_bytes),
-            "achieved": round(it_bytes / it_s / 1e9, 1),
-            "frac": round(it_bytes / it_s / 1e9 / HBM_PEAK_GBS, 4),
+        if roof is not None and it_traffic:
+            roof["traffic"] = round(it_traffic)
+        iteration_bytes = {
+            "kernel_alg_bytes": round(it_bytes),
+            "kernel_alg_frac": (round(it_bytes / it_ev_s / 1e9 /
+                                      HBM_PEAK_GBS, 4) if it_ev_s else None),
             "method_min_bytes": b_min,
-            "method_min_frac": round(b_min / it_s / 1e9 / HBM_PEAK_GBS, 4),
-            "traffic": round(it_traffic) if it_traffic else None,
-            "traffic_GBps": (round(it_traffic / it_s / 1e9, 1)
-                             if it_traffic else None),
+            "counter_bytes": round(it_traffic) if it_traffic else None,
+            "counter_GBps": (round(it_traffic / it_ev_s / 1e9, 1)
+                             if it_traffic and it_ev_s else None),
             "copy_GBps": round(copy_bandwidth(), 1)}
 
     line = {
@@ -524,7 +652,8 @@ def main():
         "w_even": int((win == 0).sum()),
         "event_ms_total": ev0.elapsed_time(ev1),
         "roofline": roof,
-        "iteration_roofline": iteration_roof,
+        "dominant_kernel": dominant,
+        "iteration_bytes": iteration_bytes,
         "kernels": kernels,
     }
     if args.workload == "c3":
@@ -536,6 +665,9 @@ def main():
             game, counts=runs[0]["aug"][2] > 0)
     else:
         line["cpu_baseline"] = None
+    if args.workload == "c2" and not args.no_mix:
+        log("batched/served mix")
+        line["mix"] = run_mix(args.mix_games)
     print(json.dumps(line), flush=True)
 
 

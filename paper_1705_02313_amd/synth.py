@@ -34,7 +34,7 @@ Recipes (all draws from ``numpy.random.Generator(PCG64(seed))``):
   experiments, whose games have 2 to 4 distinct priorities.
 * ``mixed_batch`` -- the batched workload: game g uses seed base+g,
   n_g = round(exp(U(ln nmin, ln nmax))) and a random game with out-degree
-  uniform in [2, 8].
+  uniform in [2, 8] and int32 offsets.
 """
 from __future__ import annotations
 
@@ -158,25 +158,28 @@ def mixed_batch(count: int, seed_base: int, nmin: int = 1000,
                                                  np.log(nmax))))))
         n_g = max(n_g, 2)
         sub_seed = int(rng.integers(0, 2**62))
-        games.append(random_game(n_g, dmin, dmax, sub_seed))
+        games.append(random_game(n_g, dmin, dmax, sub_seed,
+                                 offsets_dtype=np.int32))
     return games
 
 
 def config_game(config: int, k: int = 0) -> dict:
-    """The workloads by index: 0 small random, 1 1M random, 2 10M random
-    (int64 offsets), 3 8M long chain, 5 10M random with 4 repeated
-    priorities (the paper's regime), 6 1M random with 4 priorities."""
+    """The workloads by index: 0 small random, 1 1M random, 2 10M random,
+    3 8M long chain, 5 10M random with 4 repeated priorities (the paper's
+    regime), 6 1M random with 4 priorities.  Offsets are int64 for the
+    10M-vertex games and int32 for the others."""
     seed = CONFIG_SEED_BASE * config + k
+    i32 = np.int32
     if config == 5:
         return few_priorities_game(10_000_000, 2, 5, 4, seed)
     if config == 6:
-        return few_priorities_game(1_000_000, 2, 10, 4, seed)
+        return few_priorities_game(1_000_000, 2, 10, 4, seed, i32)
     if config == 0:
-        return random_game(1000, 2, 5, seed)
+        return random_game(1000, 2, 5, seed, i32)
     if config == 1:
-        return random_game(1_000_000, 2, 10, seed)
+        return random_game(1_000_000, 2, 10, seed, i32)
     if config == 2:
         return random_game(10_000_000, 2, 5, seed)
     if config == 3:
-        return chain_game(8_000_000, seed)
+        return chain_game(8_000_000, seed, i32)
     raise ValueError(f"unknown config {config}")

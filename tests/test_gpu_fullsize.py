@@ -102,9 +102,9 @@ def _run(game, gold, device=True):
         _final_checks(dev, out, tau)
 
 
-def _int32_offsets(game):
+def _offsets(game, dtype):
     g = dict(game)
-    g["offsets"] = np.asarray(game["offsets"]).astype(np.int32)
+    g["offsets"] = np.asarray(game["offsets"]).astype(dtype)
     return g
 
 
@@ -113,10 +113,8 @@ def test_config0_twenty_seeds(offsets):
     gold = _golden("c0s")
     for seed, gd in gold.items():
         print("c0 seed", seed, offsets, flush=True)
-        g = synth.random_game(1000, 2, 5, int(seed))
-        if offsets == "int32":
-            g = _int32_offsets(g)
-            assert np.asarray(g["offsets"]).dtype == np.int32
+        g = _offsets(synth.random_game(1000, 2, 5, int(seed)), offsets)
+        assert np.asarray(g["offsets"]).dtype == np.dtype(offsets)
         _run(g, gd, device=(offsets == "int32"))
 
 
@@ -128,7 +126,5 @@ def test_config0_twenty_seeds(offsets):
 def test_full_size_config(cfg, offsets):
     gold = _golden(f"c{cfg}")
     print("config", cfg, offsets, flush=True)
-    g = synth.config_game(cfg)
-    if offsets == "int32":
-        g = _int32_offsets(g)
+    g = _offsets(synth.config_game(cfg), offsets)
     _run(g, gold)

@@ -118,8 +118,9 @@ def test_warm_start_one_side_only():
         _assert_final(d.solve(init_tau=tau0), ref)
         _assert_final(d.solve(init_sigma=sigma0), ref)
         with pytest.raises(PgError) as e:
+            # an Even vertex's entry (Odd entries of sigma are ignored)
             bad = sigma0.copy()
-            bad[0] = d.n_aug + 5
+            bad[int(np.flatnonzero(aug["owner"] == 0)[0])] = d.n_aug + 5
             d.solve(init_sigma=bad)
         assert e.value.status == PG_EINVAL
 
