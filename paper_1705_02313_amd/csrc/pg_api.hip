@@ -628,6 +628,7 @@ void free_game(pg_game *g) {
                   g->wl1,      g->rs,       g->sk0,      g->sv0,
                   g->sk1,      g->sv1,      g->tile_cnt, g->scan_tmp,
                   g->kids,     g->fh,       g->pos,      g->elem,
+                  g->aux,
                   g->ctr,      g->u64tmp,   g->cvals,    g->pidx,
                   g->cnt,      g->elem4,    g->rs1,      g->cnt2,
                   g->tsw_t,    g->tsw_slot, g->tsw_g,    g->tsw_tz,
@@ -686,6 +687,7 @@ pg_status alloc_state(pg_game *g, int64_t cap) {
   PG_TRY(dev_alloc(&g->pos, N + 1));
   fill_i32(g->pos, 0, N + 1, 0);
   PG_TRY(dev_alloc(&g->elem, 2 * N + 2));
+  PG_TRY(dev_alloc(&g->aux, 2 * N + 2));
   // sublist levels for the longest possible Euler list
   for (int k = 0; k < 8; ++k) {
     const int64_t ns = level_size(2 * N + 2, k + 1);

@@ -205,17 +205,23 @@ struct pg_game {
   size_t scan_tmp_bytes = 0;
 
   // Euler list of the nearest-greater-ancestor tree
-  int32_t *kids = nullptr;   // [n_aug]   vertices in (parent, signed-priority) order
-  // [n_aug+1] 0 for a leaf, else (sorted position of the first child + 1),
-  // with bit 31 set when the last child has an even priority
-  uint32_t *fh = nullptr;
+  int32_t *kids = nullptr;   // [n_aug]   count valuations: compacted vertices
+  // [n_aug+1] rank valuations: {0, 0} for a leaf, else the sorted positions
+  // of the first and the last child, + 1 each (count valuations: the list
+  // starts, as int32)
+  uint2 *fh = nullptr;
+  // where the last parent sort left its sorted keys, and the device word
+  // holding its count of inner positions
+  const uint32_t *ps_k = nullptr, *ps_ni = nullptr;
   int32_t *pos = nullptr;    // [n_aug+1] sorted position of each finite vertex
   int32_t *rvpos = nullptr;  // [n_aug] position of each vertex in perm
   int32_t *odd_ids = nullptr;   // [n_odd]  Odd vertices, increasing
   int32_t *even_ids = nullptr;  // [n_aug - n_odd] Even vertices, increasing
-  // [2*n_aug+2] {next element or -1, node | weight bits}; a leaf's second
-  // slot holds {its parent, 0}
+  // [2*n_aug+2] {next element or -1, node | weight bits}
   int2 *elem = nullptr;
+  // [2*n_aug+2] per element carrying a point: {level-1 sublist, weight
+  // before the element in that sublist}
+  int2 *aux = nullptr;
 
   pgk::RankLevel lv[8];
   int nlevels = 0;

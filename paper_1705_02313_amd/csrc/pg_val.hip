@@ -195,16 +195,16 @@ __device__ __forceinline__ int root_walk(int32_t N, const int32_t *ng,
 __global__ __launch_bounds__(kBlock) void k_root_full(
     int32_t N, const int32_t *ng, uint8_t *rs, int32_t *rcand, int32_t *key,
     int32_t *ctr, int steps, int32_t *ng_next, int32_t *cand_next,
-    uint32_t *fh, const int32_t *__restrict__ rvpos, uint32_t *sk,
+    uint2 *fh, const int32_t *__restrict__ rvpos, uint32_t *sk,
     int32_t *dist) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0) fh[N] = 0u;
+  if (i == 0) fh[N] = make_uint2(0u, 0u);
   int fate = 0;
   if (i < N) {
     const int32_t v = (int32_t)i;
     ng_next[v] = -1;
     cand_next[v] = -1;
-    fh[v] = 0u;
+    fh[v] = make_uint2(0u, 0u);
     const int32_t p = ng[v];
     int32_t r = p;
     if (r < 0) {
@@ -265,15 +265,12 @@ __global__ __launch_bounds__(kBlock) void k_root_round(
 // ---------------------------------------------------------------------------
 // Euler list of the ng tree
 // ---------------------------------------------------------------------------
-// Sorted position i (0 <= i < nF) holds vertex kids[i] with parent skS[i];
-// svS[i] is its signed-order position, the vertex itself when perm is null
-// (a relabeled game).  Elements: 0 enters the root (the sink), 1 leaves it;
-// 2i+2 enters kids[i], 2i+3 leaves it.  A leaf is visited by element 2i+2
-// alone: the list skips 2i+3, which holds the leaf's parent.  Splitters sit
-// at even indices (multiples of the stride), so none is such a slot.
-// Sorted position i < nF as the parent sort leaves it: i < ni holds parent
-// skS[i] and signed-order position svS[i]; the rest are the sink's children,
-// their positions stored reversed at the top of svS.
+// Sorted position i (0 <= i < nF) holds the vertex at signed-order position
+// svS[i] (the vertex itself in a relabeled game) with parent skS[i]: as the
+// parent sort leaves them, i < ni holds an inner parent, the rest are the
+// sink's children, their positions stored reversed at the top of svS.
+// Splitters of the list ranking sit at even element indices (multiples of
+// the stride): every even index from 2 on is the element of a position.
 __device__ __forceinline__ uint32_t ps_key(const uint32_t *skS, int64_t i,
                                            int64_t ni, int32_t N) {
   return i < ni ? skS[i] : (uint32_t)N;
@@ -283,78 +280,90 @@ __device__ __forceinline__ uint32_t ps_val(const uint32_t *svS, int64_t i,
   return svS[i < ni ? i : ni + nF - 1 - i];
 }
 
+// fh[p] = {first, last} sorted position of p's children, + 1 each, for
+// every inner parent p (a vertex with children; the sink's children are the
+// positions from ni on).  The root walks clear fh to {0, 0}, so a vertex
+// whose fh.x is 0 is a leaf.  Plain stores: the first and the last position
+// of a segment write different words.
 __global__ __launch_bounds__(kBlock) void k_link_info(
-    int32_t N, int32_t n_oddpri, const uint32_t *__restrict__ skS,
-    const uint32_t *__restrict__ svS, const uint32_t *__restrict__ n_inner,
-    const int32_t *__restrict__ perm, int32_t *kids, int32_t *pos,
-    uint32_t *fh, int32_t *ctr) {
+    int32_t N, const uint32_t *__restrict__ skS,
+    const uint32_t *__restrict__ n_inner, uint2 *fh, int32_t *ctr) {
   if (ctr[C_ABORT] || (ctr[C_ERR] & ERR_RANKCOUNT)) return;
-  const int64_t nF = ctr[C_NFIN], ni = *n_inner;
+  const int64_t ni = *n_inner;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nF) return;
-  const uint32_t p = ps_key(skS, i, ni, N);
-  if (p > (uint32_t)N) {  // finite count and sort keys disagree
+  if (i >= ni) return;
+  const uint32_t p = skS[i];
+  if (p >= (uint32_t)N) {  // inner parents are vertices
     atomicOr(&ctr[C_ERR], ERR_RANKCOUNT);
     return;
   }
-  const uint32_t r = ps_val(svS, i, ni, nF);
-  const int32_t c = perm ? perm[r] : (int32_t)r;
-  kids[i] = c;
-  pos[c] = (int32_t)i;
-  // fh[p]: first child position + 1 and, in bit 31, whether the last child
-  // has an even priority; the two parts come from different threads
-  if (i == 0 || ps_key(skS, i - 1, ni, N) != p)
-    atomicOr(&fh[p], (uint32_t)(i + 1));
-  if ((i == nF - 1 || ps_key(skS, i + 1, ni, N) != p) &&
-      r >= (uint32_t)n_oddpri)
-    atomicOr(&fh[p], 0x80000000u);
+  uint32_t *f = reinterpret_cast<uint32_t *>(fh);
+  if (i == 0 || skS[i - 1] != p) f[2 * p] = (uint32_t)(i + 1);
+  if (i == ni - 1 || skS[i + 1] != p) f[2 * p + 1] = (uint32_t)(i + 1);
 }
 
+// Elements: 0 enters the root (the sink), 1 leaves it; 2i+2 enters the
+// vertex at sorted position i (a leaf: visits it); 2i+3, when i is the last
+// child of an inner parent p, leaves p.  So the last child links to its
+// parent's leave element next door, and the parent's own position, which
+// knows where its children end (fh), links that element onward: no vertex
+// needs its own sorted position.  Each node's in-order point is marked on
+// one element: the enter element of its first even child, or its leave
+// element when no child is even.  A leaf -- most vertices of the tree on
+// random games -- is visited by one element, which carries the parent's
+// point (bit 30, when the leaf is the parent's first even child) and its own
+// (bit 31).
 __global__ __launch_bounds__(kBlock) void k_link_build(
     int32_t N, int32_t n_oddpri, const uint32_t *__restrict__ skS,
     const uint32_t *__restrict__ svS, const uint32_t *__restrict__ n_inner,
-    const int32_t *__restrict__ kids, const int32_t *__restrict__ pos,
-    const uint32_t *__restrict__ fh, int2 *elem, const int32_t *ctr) {
+    const int32_t *__restrict__ perm, const uint2 *__restrict__ fh,
+    int2 *elem, int32_t *ctr) {
   if (ctr[C_ABORT] || (ctr[C_ERR] & ERR_RANKCOUNT)) return;
   const int64_t nF = ctr[C_NFIN], ni = *n_inner;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0) {
-    const uint32_t f = fh[N];
-    const int32_t first = (int32_t)(f & 0x7fffffffu) - 1;
-    elem[0] = make_int2(first >= 0 ? 2 * first + 2 : 1, N);
-    const int w = (first < 0 || !(f >> 31)) ? 1 : 0;
-    elem[1] = make_int2(-1, N | (w << 31));
+  int32_t *el = reinterpret_cast<int32_t *>(elem);   // .x at 2e, .y at 2e+1
+  if (nF == 0) {   // the sink alone: its point on its leave element
+    if (i == 0) {
+      elem[0] = make_int2(1, N);
+      elem[1] = make_int2(-1, N | (int32_t)0x80000000);
+    }
+    return;
   }
   if (i >= nF) return;
-  const int32_t c = kids[i];
   const uint32_t p = ps_key(skS, i, ni, N);
-  const bool ev = ps_val(svS, i, ni, nF) >= (uint32_t)n_oddpri;
+  const uint32_t r = ps_val(svS, i, ni, nF);
+  const int32_t c = perm ? perm[r] : (int32_t)r;
+  const bool ev = r >= (uint32_t)n_oddpri;
   const bool seg_start = (i == 0) || (ps_key(skS, i - 1, ni, N) != p);
   const bool seg_end = (i == nF - 1) || (ps_key(skS, i + 1, ni, N) != p);
-  const uint32_t f = fh[c];
-  const int32_t fc = (int32_t)(f & 0x7fffffffu) - 1;
   // c is the parent's first even child: the parent's in-order point comes
   // just before c's subtree
   const bool wd = ev && (seg_start || ps_val(svS, i - 1, ni, nF) <
                                           (uint32_t)n_oddpri);
   // after c's subtree: the next sibling, else leave the parent
-  int32_t nx;
-  if (!seg_end) nx = (int32_t)(2 * i + 4);
-  else nx = (p == (uint32_t)N) ? 1 : 2 * pos[p] + 3;
-  if (fc < 0) {
-    // a leaf (most vertices of the tree): one element visits it, carrying
-    // the parent's point (bit 30, the parent kept in the unused odd slot
-    // beside it) and then its own (bit 31)
+  const int32_t nx = !seg_end ? (int32_t)(2 * i + 4)
+                              : (p == (uint32_t)N ? 1 : (int32_t)(2 * i + 3));
+  if (p == (uint32_t)N && seg_start) elem[0] = make_int2((int32_t)(2 * i + 2), N);
+  if (seg_end) {
+    // leave the parent: it carries the parent's point when c, its last
+    // child, is odd (then no child is even)
+    const int32_t w = ev ? 0 : (int32_t)0x80000000;
+    if (p == (uint32_t)N) elem[1] = make_int2(-1, N | w);
+    else el[2 * (2 * i + 3) + 1] = (int32_t)p | w;
+  }
+  const uint2 f = fh[c];
+  if (f.x == 0) {
+    // a leaf: one element visits it, carrying the parent's point (bit 30)
+    // and then its own (bit 31)
     elem[2 * i + 2] =
         make_int2(nx, c | (int32_t)0x80000000 | ((int32_t)wd << 30));
-    elem[2 * i + 3] = make_int2((int32_t)p, 0);
     return;
   }
   // enter c: its first child, carrying the parent's point when wd
-  elem[2 * i + 2] = make_int2(2 * fc + 2, (int32_t)p | ((int32_t)wd << 31));
-  // leave c: carries c's own point when c has no even child
-  const bool wu = !(f >> 31);
-  elem[2 * i + 3] = make_int2(nx, c | ((int32_t)wu << 31));
+  elem[2 * i + 2] =
+      make_int2((int32_t)(2 * f.x), (int32_t)p | ((int32_t)wd << 31));
+  // leave c, next to its last child: on to c's continuation
+  el[2 * (2 * (int64_t)f.y + 1)] = nx;
 }
 
 // ---------------------------------------------------------------------------
@@ -365,9 +374,12 @@ __global__ __launch_bounds__(kBlock) void k_link_build(
 // walks the list of level-(k-1) splitters (int weights).  Splitters are the
 // elements whose index is a multiple of the stride; element 0 (the list head)
 // is one.  Every size comes from the finite count on the device.
+// Also records, for every element that carries a point, its sublist and
+// the sublist's weight before it (aux), so that the keys can be emitted by
+// one pass over sorted positions instead of a second walk.
 __global__ __launch_bounds__(kBlock) void k_lr_sum1(
     const int2 *__restrict__ elem, int per_thread, int32_t *sum,
-    int32_t *next, int32_t *ctr) {
+    int32_t *next, int2 *aux, int32_t *ctr) {
   if (ctr[C_ABORT]) return;
   const int64_t L = 2 * (int64_t)ctr[C_NFIN] + 2;
   const int64_t nsplit = level_size(L, 1);
@@ -381,7 +393,9 @@ __global__ __launch_bounds__(kBlock) void k_lr_sum1(
     int64_t steps = 0;
     for (;;) {
       const int2 el = elem[e];
-      acc += (int32_t)((uint32_t)el.y >> 31) + ((el.y >> 30) & 1);
+      const int32_t w = (int32_t)((uint32_t)el.y >> 31) + ((el.y >> 30) & 1);
+      if (w) aux[e] = make_int2((int32_t)j, acc);
+      acc += w;
       e = el.x;
       if (e < 0 || e % kStride == 0) break;
       if (++steps > L) { atomicOr(&ctr[C_ERR], ERR_LISTWALK); e = -1; break; }
@@ -488,27 +502,41 @@ __global__ __launch_bounds__(kBlock) void k_lr_distk(
   }
 }
 
-// Final pass over the Euler list: every weighted element emits the key of
-// its node (a leaf with bit 30 first its parent's, then its own).
+// Keys, one sorted position per thread: each element of the position that
+// carries a point emits the key of its node, the rank of its sublist's
+// start plus the weight before it in the sublist (aux); a leaf with bit 30
+// first its parent's, then its own.  Position nF - 1 (the sink's last
+// child) also takes the sink's leave element.
 __global__ __launch_bounds__(kBlock) void k_lr_emit1(
-    const int2 *__restrict__ elem, int per_thread,
+    int32_t N, const int2 *__restrict__ elem, const int2 *__restrict__ aux,
+    const uint32_t *__restrict__ skS, const uint32_t *__restrict__ n_inner,
     const int32_t *__restrict__ sbase, int32_t *key, const int32_t *ctr) {
   if (ctr[C_ABORT]) return;
-  const int64_t L = 2 * (int64_t)ctr[C_NFIN] + 2;
-  const int64_t nsplit = level_size(L, 1);
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
-  for (int k = 0; k < per_thread; ++k) {
-    const int64_t j = t + (int64_t)k * nthreads;
-    if (j >= nsplit) break;
-    int64_t e = j * kStride;
-    int32_t b = sbase[j];
-    for (int64_t steps = 0; steps <= L; ++steps) {
-      const int2 el = elem[e];
-      if (el.y & 0x40000000) key[elem[e + 1].x] = b++;  // a leaf's parent
-      if (el.y < 0) key[el.y & 0x3fffffff] = b++;
-      e = el.x;
-      if (e < 0 || e % kStride == 0) break;
+  const int64_t nF = ctr[C_NFIN], ni = *n_inner;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > nF || (i == nF && nF > 0)) return;
+  if (i == (nF > 0 ? nF - 1 : 0)) {
+    const int2 el = elem[1];
+    if (el.y < 0) {
+      const int2 a = aux[1];
+      key[N] = sbase[a.x] + a.y;
+    }
+    if (nF == 0) return;
+  }
+  const uint32_t p = ps_key(skS, i, ni, N);
+  const int2 el = elem[2 * i + 2];
+  if (el.y & (int32_t)0xC0000000) {
+    const int2 a = aux[2 * i + 2];
+    int32_t b = sbase[a.x] + a.y;
+    if (el.y & 0x40000000) key[p] = b++;          // a leaf's parent
+    if (el.y < 0) key[el.y & 0x3fffffff] = b;
+  }
+  if (p != (uint32_t)N &&
+      (i == nF - 1 || ps_key(skS, i + 1, ni, N) != p)) {
+    const int2 lv = elem[2 * i + 3];               // leaves p
+    if (lv.y < 0) {
+      const int2 a = aux[2 * i + 3];
+      key[lv.y & 0x3fffffff] = sbase[a.x] + a.y;
     }
   }
 }
@@ -768,17 +796,18 @@ static void enqueue_rank_list(pg_game *g, hipStream_t s) {
                                 pf, &n_inner);
   const uint32_t *skS = which ? g->sk1 : g->sk0;
   const uint32_t *svS = which ? g->sv1 : g->sv0;
-  // values 4 (+ perm 4 unless relabeled); kids, pos 8; fh at segment ends
-  // about 2; keys 4 per inner child
+  g->ps_k = skS;
+  g->ps_ni = n_inner;
+  // inner keys 4; fh at segment ends about 2 per inner child
+  PG_LAUNCH_NI(pf, K_LINK_INFO, 0.0, 0.0, 6.0, k_link_info,
+               dim3(grid_for(N)), dim3(kBlock), 0, s, N, skS, n_inner, g->fh,
+               g->ctr);
+  // keys and values 8 (+ perm 4 unless relabeled); fh 8; one element 8,
+  // and per inner child about 8 more (leave elements)
   const int32_t *perm = kernel_perm(g);
-  PG_LAUNCH_NI(pf, K_LINK_INFO, 0.0, perm ? 18.0 : 14.0, 4.0, k_link_info,
+  PG_LAUNCH_NI(pf, K_LINK_BUILD, 0.0, perm ? 28.0 : 24.0, 8.0, k_link_build,
                dim3(grid_for(N)), dim3(kBlock), 0, s, N, g->n_oddpri, skS, svS,
-               n_inner, perm, g->kids, g->pos, g->fh, g->ctr);
-  // values, kids 8; fh 4; two elements 16; pos at segment ends about 2;
-  // keys 4 per inner child
-  PG_LAUNCH_NI(pf, K_LINK_BUILD, 0.0, 30.0, 4.0, k_link_build,
-               dim3(grid_for(N)), dim3(kBlock), 0, s, N, g->n_oddpri, skS, svS,
-               n_inner, g->kids, g->pos, g->fh, g->elem, g->ctr);
+               n_inner, perm, g->fh, g->elem, g->ctr);
   const int64_t Lmax = 2 * (int64_t)N + 2;
   const int64_t ns1 = level_size(Lmax, 1);
   const int kPerThread1 = per_thread1(ns1);
@@ -788,19 +817,16 @@ static void enqueue_rank_list(pg_game *g, hipStream_t s) {
   // finite vertex, its least length
   PG_LAUNCH_NF(pf, K_LR_SUM1, 8.5, k_lr_sum1, dim3(grid_for(thr1)),
             dim3(kBlock), 0, s, g->elem, kPerThread1, g->lv[0].sum,
-            g->lv[0].next, g->ctr);
+            g->lv[0].next, g->aux, g->ctr);
 }
 
 // The reduced lists ranked on the device (unless the level-1 bases come
-// from the host), then every level-1 sublist walked again to emit the keys.
+// from the host), then the keys emitted from sorted positions.
 static void enqueue_rank_emit(pg_game *g, hipStream_t s, bool device_reduced) {
   const int32_t N = (int32_t)g->n_aug;
   Prof *pf = &g->prof;
   const int nl = g->nlevels;
   const int64_t Lmax = 2 * (int64_t)N + 2;
-  const int64_t ns1 = level_size(Lmax, 1);
-  const int kPerThread1 = per_thread1(ns1);
-  const int64_t thr1 = (ns1 + kPerThread1 - 1) / kPerThread1;
   for (int k = 1; device_reduced && k < nl; ++k) {
     const int64_t nsk = level_size(Lmax, k + 1);
     // 8 B per element of the level-k list (about 2 nF / 32^k elements)
@@ -820,11 +846,11 @@ static void enqueue_rank_emit(pg_game *g, hipStream_t s, bool device_reduced) {
               dim3(grid_for(nsk)), dim3(kBlock), 0, s, g->lv[k - 1].next,
               g->lv[k - 1].sum, k, g->lv[k].base, g->lv[k - 1].base, g->ctr);
   }
-  // 8 B per list element (at least one per finite vertex), 4 B per
-  // splitter, one 4 B key per finite vertex
-  PG_LAUNCH_NF(pf, K_LR_EMIT1, 12.25, k_lr_emit1, dim3(grid_for(thr1)),
-            dim3(kBlock), 0, s, g->elem, kPerThread1, g->lv[0].base, g->key,
-            g->ctr);
+  // per finite vertex: its key and element 12, the element's record 8, a
+  // 4 B key written; leave elements of inner parents about 8 per inner child
+  PG_LAUNCH_NI(pf, K_LR_EMIT1, 0.0, 24.0, 8.0, k_lr_emit1,
+               dim3(grid_for(N + 1)), dim3(kBlock), 0, s, N, g->elem, g->aux,
+               g->ps_k, g->ps_ni, g->lv[0].base, g->key, g->ctr);
 }
 
 // fresh: the switch counters are still zero from the valuation's own
