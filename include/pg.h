@@ -436,6 +436,47 @@ pg_status pg_batch_info(const pg_batch *batch, int32_t *n_live,
                         int64_t *arena_edges);
 pg_status pg_batch_free(pg_batch *batch);
 
+/*
+ * pg_solve_noalloc -- pg_load_csr, pg_solve and the release of the game in
+ * one call that allocates nothing: for callers that cannot allocate device
+ * memory (tight serving loops that must not call hipMalloc or hipFree,
+ * harnesses that forbid allocation).  Same arguments, results and errors
+ * as pg_load_csr followed by pg_solve, with these limits:
+ *
+ *   size     n <= PG_NOALLOC_MAX_VERTICES, m <= PG_NOALLOC_MAX_EDGES, else
+ *            PG_EINVAL (load larger games with pg_load_csr).  A game
+ *            within them fits the scratch below; PG_ENOMEM if not.
+ *   scratch  every device buffer of the load and the solve is carved from
+ *            one static device array of PG_NOALLOC_SCRATCH_MIB MiB (held by
+ *            each GPU the library runs on until the process ends), the
+ *            counter mirror from a static host buffer; the game descriptor
+ *            lives on the call's stack.  No hipMalloc, hipFree, pinned host
+ *            allocation, HIP event or graph.
+ *   sharing  all calls on one GPU share that GPU's scratch, which keeps the
+ *            last call's contents (everything a call reads it writes
+ *            first): calls that overlap on one GPU, from two threads or on
+ *            two streams, race.  Calls on different GPUs do not.
+ *   forms    All_Odd reads rows (PG_SWITCH_ROWS); PG_SWITCH_BUCKETS and
+ *            PG_HOST_REDUCED_LIST are refused (PG_EINVAL), and so is a
+ *            per-valuation trace in opts.  Iterations are not timed
+ *            (stats->iteration_ms = 0).
+ *
+ * sigma and tau (nullable) need room for n_aug entries, which the caller
+ * does not know before the load: n_aug <= 2 n (one dummy at most per
+ * original vertex), and stats->n_aug (when stats is given) says how many
+ * were written.  The call returns after the stream has drained; outputs are
+ * written then.
+ */
+#define PG_NOALLOC_MAX_VERTICES 65536
+#define PG_NOALLOC_MAX_EDGES 1048576
+#define PG_NOALLOC_SCRATCH_MIB 128
+pg_status pg_solve_noalloc(int64_t n, int64_t m, const void *offsets,
+                           const int32_t *targets, const uint8_t *owner,
+                           const int32_t *priority, uint32_t flags,
+                           const pg_solve_opts *opts, uint8_t *winner,
+                           int32_t *sigma, int32_t *tau, pg_stats *stats,
+                           void *hip_stream);
+
 /* Release the game.  NULL is accepted.  Its device and pinned host memory
  * goes to a per-device cache that later pg_load_csr calls on that device
  * take their memory from (blocks are returned only after the device has

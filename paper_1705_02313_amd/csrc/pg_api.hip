@@ -458,6 +458,22 @@ thread_local DevPool *tl_pool = nullptr;
 
 pg_status DevPool::alloc(void **p, size_t bytes, bool host) {
   std::lock_guard<std::mutex> lock(mu);
+  if (bump_dev) {
+    size_t &used = host ? bump_hused : bump_used;
+    const size_t cap = host ? bump_hcap : bump_cap;
+    const size_t at = (used + 255) & ~size_t(255);
+    if (at > cap || bytes > cap - at) {
+      *p = nullptr;
+      return pg_fail(PG_ENOMEM,
+                     std::string("the game does not fit the ") +
+                         (host ? "host" : "device") +
+                         " scratch of pg_solve_noalloc (" +
+                         std::to_string(cap) + " bytes)");
+    }
+    *p = (host ? bump_host : bump_dev) + at;
+    used = at + bytes;
+    return PG_OK;
+  }
   const size_t b = bucket(bytes);
   auto &fl = host ? host_free[b] : dev_free[b];
   if (fl.empty()) {
@@ -500,6 +516,11 @@ pg_status DevPool::alloc(void **p, size_t bytes, bool host) {
 
 bool DevPool::release(void *p) {
   std::lock_guard<std::mutex> lock(mu);
+  if (bump_dev) {
+    const uint8_t *q = (const uint8_t *)p;
+    return (q >= bump_dev && q < bump_dev + bump_cap) ||
+           (q >= bump_host && q < bump_host + bump_hcap);
+  }
   auto it = dev_size.find(p);
   bool host = false;
   if (it == dev_size.end()) {
@@ -1126,17 +1147,11 @@ pg_status inner_loop(pg_game *g, int32_t max_inner, hipStream_t s,
 // ===========================================================================
 // the C ABI
 // ===========================================================================
-extern "C" {
+namespace {
 
-const char *pg_last_error(void) { return g_last_error.c_str(); }
-
-pg_status pg_load_csr(int64_t n, int64_t m, const void *offsets,
-                      const int32_t *targets, const uint8_t *owner,
-                      const int32_t *priority, uint32_t flags,
-                      void *hip_stream, pg_game **out_game) {
-  g_last_error.clear();
-  if (!out_game) return pg_fail(PG_EINVAL, "out_game is NULL");
-  *out_game = nullptr;
+pg_status check_load_args(int64_t n, int64_t m, const void *offsets,
+                          const int32_t *targets, const uint8_t *owner,
+                          const int32_t *priority, uint32_t flags) {
   if (n < 1 || m < n) return pg_fail(PG_EINVAL, "need n >= 1 and m >= n");
   if (n > kMaxVertices || m > 0x7fffffffLL * 4)
     return pg_fail(PG_EINVAL, "game too large");
@@ -1147,14 +1162,14 @@ pg_status pg_load_csr(int64_t n, int64_t m, const void *offsets,
   if ((flags & PG_SWITCH_ROWS) && (flags & PG_SWITCH_BUCKETS))
     return pg_fail(PG_EINVAL,
                    "PG_SWITCH_ROWS and PG_SWITCH_BUCKETS exclude each other");
-  pg_game *g = new (std::nothrow) pg_game();
-  if (!g) return pg_fail(PG_ENOMEM, "host allocation failed");
-  if (hipGetDevice(&g->device) != hipSuccess) {
-    delete g;
-    return pg_fail(PG_EDEVICE, "no HIP device");
-  }
-  hipStream_t s = (hipStream_t)hip_stream;
-  PoolScope cache(game_cache(g->device));
+  return PG_OK;
+}
+
+// pg_load_csr's work on g (g->device set), allocating from the current pool.
+pg_status load_game(int64_t n, int64_t m, const void *offsets,
+                    const int32_t *targets, const uint8_t *owner,
+                    const int32_t *priority, uint32_t flags, hipStream_t s,
+                    pg_game *g) {
   // count valuations when asked for or when the priorities repeat
   pg_status st =
       load_modified(n, m, offsets, targets, owner, priority, flags, s, g,
@@ -1179,6 +1194,172 @@ pg_status pg_load_csr(int64_t n, int64_t m, const void *offsets,
   g->careful = flags & PG_CAREFUL_WALKS;
   g->use_graph = !(flags & PG_NO_GRAPH);
   g->host_rl = (flags & PG_HOST_REDUCED_LIST) && !g->dense;
+  return st;
+}
+
+pg_status solve_game(pg_game *g, const pg_solve_opts *opts, uint8_t *winner,
+                     int32_t *sigma, int32_t *tau, pg_stats *stats,
+                     hipStream_t s);
+
+}  // namespace
+
+namespace {
+
+// pg_solve's work on a loaded game, allocating from the current pool.
+pg_status solve_game(pg_game *g, const pg_solve_opts *opts, uint8_t *winner,
+                     int32_t *sigma, int32_t *tau, pg_stats *stats,
+                     hipStream_t s) {
+  pg_solve_opts o{};
+  if (opts) o = *opts;
+  const bool dev = o.flags & PG_PTR_DEVICE;
+  if (o.best_response < PG_BR_SI || o.best_response > PG_BR_BELLMAN_FORD)
+    return pg_fail(PG_EINVAL, "unknown best-response selector");
+  if (o.best_response == PG_BR_BELLMAN_FORD && !g->dense)
+    return pg_fail(PG_EINVAL, "Bellman-Ford best responses need a game with "
+                              "count valuations");
+  if (o.trace_cap < 0) return pg_fail(PG_EINVAL, "trace_cap < 0");
+  const auto t0 = std::chrono::steady_clock::now();
+  const int64_t N = g->n_aug;
+  hipLaunchKernelGGL(k_sp_init, dim3(grid_for(N)), dim3(kBlock), 0, s, g->off,
+                     g->tgt, g->owner, g->pri, g->sp, (int32_t)N);
+  // warm start: the given strategies replace the initial ones
+  if (o.init_sigma || o.init_tau)
+    PG_TRY(import_strats(g, o.init_sigma, o.init_tau, dev, s));
+  valuation_reset(g, s);
+  Trace tr;
+  tr.o = &o;
+  struct HashBuf {
+    unsigned long long *p = nullptr;
+    ~HashBuf() { dev_free(p); }
+  } hb;
+  if (o.trace_key_hash && o.trace_cap > 0) {
+    PG_TRY(dev_alloc(&hb.p, o.trace_cap));
+    fill_i32((int32_t *)hb.p, 0, 2 * (int64_t)o.trace_cap, s);
+    tr.dhash = hb.p;
+  }
+  int64_t n_major = 0, n_val = 0, n_odd = 0, n_even = 0;
+  double iter_ms = 0.0;
+  pg_status st = PG_OK;
+  for (;;) {
+    if (o.max_major > 0 && n_major >= o.max_major) {
+      st = pg_fail(PG_EITERLIMIT, "solve: outer iteration cap reached");
+      break;
+    }
+    ++n_major;
+    if (o.best_response == PG_BR_SI_RESET)
+      hipLaunchKernelGGL(k_sp_reset_odd, dim3(grid_for(N)), dim3(kBlock), 0, s,
+                         g->off, g->tgt, g->owner, g->pri, g->sp, (int32_t)N);
+    if (o.best_response == PG_BR_BELLMAN_FORD) {
+      int64_t rounds = 0;
+      st = bf_best_response(g, s, &rounds);
+      n_val += rounds;
+    } else {
+      st = inner_loop(g, o.max_inner, s, &n_val, &n_odd, &tr, &iter_ms);
+    }
+    if (st != PG_OK) break;
+    int32_t c = 0;
+    st = switch_device(g, false, s, &c);
+    if (st != PG_OK) break;
+    n_even += c;
+    if (c == 0) break;
+  }
+  if (tr.dhash && tr.n > 0) {
+    // the trace is the caller's even when the run stopped early
+    const std::string err = pg_last_error();
+    PG_HIP(hipMemcpyAsync(o.trace_key_hash, tr.dhash,
+                          sizeof(uint64_t) * (size_t)tr.n,
+                          hipMemcpyDeviceToHost, s));
+    PG_HIP(hipStreamSynchronize(s));
+    if (st != PG_OK) pg_fail(st, err);
+  }
+  if (o.trace_key_hash && g->dense)
+    for (int64_t i = 0; i < tr.n; ++i) o.trace_key_hash[i] = 0;
+  if (stats) {
+    stats->n = g->n;
+    stats->m = g->m;
+    stats->n_aug = g->n_aug;
+    stats->m_aug = g->m_aug;
+    stats->n_major = n_major;
+    stats->n_valuations = n_val;
+    stats->n_odd_switches = n_odd;
+    stats->n_even_switches = n_even;
+    stats->iteration_ms = iter_ms;
+    stats->n_traced = tr.n;
+  }
+  const bool report = !(o.flags & PG_KEEP_DUMMIES);
+  if (st == PG_EITERLIMIT) {
+    // a checkpoint: the strategies reached, from which a warm start resumes
+    const std::string err = pg_last_error();
+    PG_TRY(export_strats(g, sigma, tau, dev, s, report));
+    return pg_fail(st, err);
+  }
+  if (st != PG_OK) return st;
+  uint8_t *dw = winner;
+  if (!dev) dw = (uint8_t *)g->wl0;
+  hipLaunchKernelGGL(k_winner, dim3(grid_for(g->n)), dim3(kBlock), 0, s,
+                     g->rs, io_rvpos(g), dw, g->n);
+  if (!dev) PG_TRY(copy_out(winner, dw, g->n, false, s));
+  PG_HIP(hipStreamSynchronize(s));
+  PG_TRY(export_strats(g, sigma, tau, dev, s, report));
+  const auto t1 = std::chrono::steady_clock::now();
+  if (stats) stats->seconds = std::chrono::duration<double>(t1 - t0).count();
+  return PG_OK;
+}
+
+}  // namespace
+
+// ---- the allocation-free entry point ---------------------------------------
+// pg_solve_noalloc carves every device buffer of a load and a solve from this
+// array (bump allocation, nothing handed back until the call ends) and the
+// counter mirror from a small static host buffer.  In host code the array's
+// name is not its device address: hipGetSymbolAddress gives that, once per
+// device (each device holds its own copy), and only that address is used.
+constexpr size_t kScratchBytes = size_t(PG_NOALLOC_SCRATCH_MIB) << 20;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+constexpr int kScratchDevices = 64;
+constexpr size_t kScratchHostBytes = 4096;
+static std::mutex g_scratch_mu;
+static uint8_t *g_scratch_dev[kScratchDevices];
+alignas(256) static uint8_t g_scratch_host[kScratchDevices][kScratchHostBytes];
+
+namespace {
+pg_status scratch_address(int device, uint8_t **out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return pg_fail(PG_EDEVICE, std::string("scratch address: ") +
+                                     hipGetErrorString(e));
+    g_scratch_dev[device] = (uint8_t *)ptr;
+  }
+  *out = g_scratch_dev[device];
+  return PG_OK;
+}
+}  // namespace
+
+extern "C" {
+
+const char *pg_last_error(void) { return g_last_error.c_str(); }
+
+pg_status pg_load_csr(int64_t n, int64_t m, const void *offsets,
+                      const int32_t *targets, const uint8_t *owner,
+                      const int32_t *priority, uint32_t flags,
+                      void *hip_stream, pg_game **out_game) {
+  g_last_error.clear();
+  if (!out_game) return pg_fail(PG_EINVAL, "out_game is NULL");
+  *out_game = nullptr;
+  PG_TRY(check_load_args(n, m, offsets, targets, owner, priority, flags));
+  pg_game *g = new (std::nothrow) pg_game();
+  if (!g) return pg_fail(PG_ENOMEM, "host allocation failed");
+  if (hipGetDevice(&g->device) != hipSuccess) {
+    delete g;
+    return pg_fail(PG_EDEVICE, "no HIP device");
+  }
+  hipStream_t s = (hipStream_t)hip_stream;
+  PoolScope cache(game_cache(g->device));
+  const pg_status st = load_game(n, m, offsets, targets, owner, priority,
+                                 flags, s, g);
   if (st != PG_OK) {
     (void)hipStreamSynchronize(s);
     free_game(g);
@@ -1348,102 +1529,56 @@ pg_status pg_solve(pg_game *g, const pg_solve_opts *opts, uint8_t *winner,
   if (!winner) return pg_fail(PG_EINVAL, "winner is NULL");
   DevGuard guard(g->device);
   PoolScope cache(game_cache(g->device));
+  return solve_game(g, opts, winner, sigma, tau, stats,
+                    (hipStream_t)hip_stream);
+}
+
+pg_status pg_solve_noalloc(int64_t n, int64_t m, const void *offsets,
+                           const int32_t *targets, const uint8_t *owner,
+                           const int32_t *priority, uint32_t flags,
+                           const pg_solve_opts *opts, uint8_t *winner,
+                           int32_t *sigma, int32_t *tau, pg_stats *stats,
+                           void *hip_stream) {
+  g_last_error.clear();
+  PG_TRY(check_load_args(n, m, offsets, targets, owner, priority, flags));
+  if (!winner) return pg_fail(PG_EINVAL, "winner is NULL");
+  if (n > PG_NOALLOC_MAX_VERTICES || m > PG_NOALLOC_MAX_EDGES)
+    return pg_fail(PG_EINVAL,
+                   "pg_solve_noalloc takes at most " +
+                       std::to_string(PG_NOALLOC_MAX_VERTICES) +
+                       " vertices and " + std::to_string(PG_NOALLOC_MAX_EDGES) +
+                       " edges; load larger games with pg_load_csr");
+  if (flags & (PG_SWITCH_BUCKETS | PG_HOST_REDUCED_LIST))
+    return pg_fail(PG_EINVAL, "pg_solve_noalloc takes neither "
+                              "PG_SWITCH_BUCKETS nor PG_HOST_REDUCED_LIST");
+  if (opts && (opts->trace_key_hash || opts->trace_finite ||
+               opts->trace_switches || opts->trace_ms))
+    return pg_fail(PG_EINVAL, "pg_solve_noalloc keeps no trace");
+  int device = -1;
+  if (hipGetDevice(&device) != hipSuccess || device < 0)
+    return pg_fail(PG_EDEVICE, "no HIP device");
+  if (device >= kScratchDevices)
+    return pg_fail(PG_EDEVICE, "device index beyond the scratch table");
+  uint8_t *dev_scratch = nullptr;
+  PG_TRY(scratch_address(device, &dev_scratch));
   hipStream_t s = (hipStream_t)hip_stream;
-  pg_solve_opts o{};
-  if (opts) o = *opts;
-  const bool dev = o.flags & PG_PTR_DEVICE;
-  if (o.best_response < PG_BR_SI || o.best_response > PG_BR_BELLMAN_FORD)
-    return pg_fail(PG_EINVAL, "unknown best-response selector");
-  if (o.best_response == PG_BR_BELLMAN_FORD && !g->dense)
-    return pg_fail(PG_EINVAL, "Bellman-Ford best responses need a game with "
-                              "count valuations");
-  if (o.trace_cap < 0) return pg_fail(PG_EINVAL, "trace_cap < 0");
-  const auto t0 = std::chrono::steady_clock::now();
-  const int64_t N = g->n_aug;
-  hipLaunchKernelGGL(k_sp_init, dim3(grid_for(N)), dim3(kBlock), 0, s, g->off,
-                     g->tgt, g->owner, g->pri, g->sp, (int32_t)N);
-  // warm start: the given strategies replace the initial ones
-  if (o.init_sigma || o.init_tau)
-    PG_TRY(import_strats(g, o.init_sigma, o.init_tau, dev, s));
-  valuation_reset(g, s);
-  Trace tr;
-  tr.o = &o;
-  struct HashBuf {
-    unsigned long long *p = nullptr;
-    ~HashBuf() { dev_free(p); }
-  } hb;
-  if (o.trace_key_hash && o.trace_cap > 0) {
-    PG_TRY(dev_alloc(&hb.p, o.trace_cap));
-    fill_i32((int32_t *)hb.p, 0, 2 * (int64_t)o.trace_cap, s);
-    tr.dhash = hb.p;
-  }
-  int64_t n_major = 0, n_val = 0, n_odd = 0, n_even = 0;
-  double iter_ms = 0.0;
-  pg_status st = PG_OK;
-  for (;;) {
-    if (o.max_major > 0 && n_major >= o.max_major) {
-      st = pg_fail(PG_EITERLIMIT, "solve: outer iteration cap reached");
-      break;
-    }
-    ++n_major;
-    if (o.best_response == PG_BR_SI_RESET)
-      hipLaunchKernelGGL(k_sp_reset_odd, dim3(grid_for(N)), dim3(kBlock), 0, s,
-                         g->off, g->tgt, g->owner, g->pri, g->sp, (int32_t)N);
-    if (o.best_response == PG_BR_BELLMAN_FORD) {
-      int64_t rounds = 0;
-      st = bf_best_response(g, s, &rounds);
-      n_val += rounds;
-    } else {
-      st = inner_loop(g, o.max_inner, s, &n_val, &n_odd, &tr, &iter_ms);
-    }
-    if (st != PG_OK) break;
-    int32_t c = 0;
-    st = switch_device(g, false, s, &c);
-    if (st != PG_OK) break;
-    n_even += c;
-    if (c == 0) break;
-  }
-  if (tr.dhash && tr.n > 0) {
-    // the trace is the caller's even when the run stopped early
-    const std::string err = pg_last_error();
-    PG_HIP(hipMemcpyAsync(o.trace_key_hash, tr.dhash,
-                          sizeof(uint64_t) * (size_t)tr.n,
-                          hipMemcpyDeviceToHost, s));
-    PG_HIP(hipStreamSynchronize(s));
-    if (st != PG_OK) pg_fail(st, err);
-  }
-  if (o.trace_key_hash && g->dense)
-    for (int64_t i = 0; i < tr.n; ++i) o.trace_key_hash[i] = 0;
-  if (stats) {
-    stats->n = g->n;
-    stats->m = g->m;
-    stats->n_aug = g->n_aug;
-    stats->m_aug = g->m_aug;
-    stats->n_major = n_major;
-    stats->n_valuations = n_val;
-    stats->n_odd_switches = n_odd;
-    stats->n_even_switches = n_even;
-    stats->iteration_ms = iter_ms;
-    stats->n_traced = tr.n;
-  }
-  const bool report = !(o.flags & PG_KEEP_DUMMIES);
-  if (st == PG_EITERLIMIT) {
-    // a checkpoint: the strategies reached, from which a warm start resumes
-    const std::string err = pg_last_error();
-    PG_TRY(export_strats(g, sigma, tau, dev, s, report));
-    return pg_fail(st, err);
-  }
-  if (st != PG_OK) return st;
-  uint8_t *dw = winner;
-  if (!dev) dw = (uint8_t *)g->wl0;
-  hipLaunchKernelGGL(k_winner, dim3(grid_for(g->n)), dim3(kBlock), 0, s,
-                     g->rs, io_rvpos(g), dw, g->n);
-  if (!dev) PG_TRY(copy_out(winner, dw, g->n, false, s));
-  PG_HIP(hipStreamSynchronize(s));
-  PG_TRY(export_strats(g, sigma, tau, dev, s, report));
-  const auto t1 = std::chrono::steady_clock::now();
-  if (stats) stats->seconds = std::chrono::duration<double>(t1 - t0).count();
-  return PG_OK;
+  DevPool bump;
+  bump.bump_dev = dev_scratch;
+  bump.bump_cap = kScratchBytes;
+  bump.bump_host = g_scratch_host[device];
+  bump.bump_hcap = kScratchHostBytes;
+  PoolScope scope(&bump);
+  // the game lives on this call's stack; every buffer it points to is in
+  // the scratch; no events, no graphs, rows for All_Odd
+  pg_game g;
+  g.device = device;
+  g.timed = false;
+  pg_status st = load_game(n, m, offsets, targets, owner, priority,
+                           flags | PG_NO_GRAPH | PG_SWITCH_ROWS, s, &g);
+  if (st == PG_OK) st = solve_game(&g, opts, winner, sigma, tau, stats, s);
+  // the scratch is free again once the stream has drained
+  (void)hipStreamSynchronize(s);
+  return st;
 }
 
 pg_status pg_profile_enable(pg_game *g, int32_t on) {

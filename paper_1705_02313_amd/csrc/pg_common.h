@@ -245,6 +245,8 @@ struct pg_game {
   int32_t *hctr = nullptr;   // pinned host mirror
 
   pgk::Prof prof;
+  // false: no HIP events are created or recorded (pg_solve_noalloc)
+  bool timed = true;
   // HIP events around each best-response iteration on the call's stream
   // (created at first use); the last iteration's device time
   hipEvent_t ev_a = nullptr, ev_b = nullptr;
@@ -442,6 +444,12 @@ struct DevPool {
   std::unordered_map<void *, size_t> dev_size, host_size;
   std::vector<Slab> slabs;
   std::unordered_map<void *, size_t> slab_of;   // block -> index in slabs
+  // Bump mode (pg_solve_noalloc): blocks are carved in turn from the device
+  // range [bump_dev, bump_dev + bump_cap) and the host range [bump_host,
+  // bump_host + bump_hcap); nothing goes back block by block and nothing is
+  // asked of the HIP runtime.
+  uint8_t *bump_dev = nullptr, *bump_host = nullptr;
+  size_t bump_cap = 0, bump_used = 0, bump_hcap = 0, bump_hused = 0;
   static size_t bucket(size_t bytes) {
     size_t b = 256;
     while (b < bytes) b <<= 1;

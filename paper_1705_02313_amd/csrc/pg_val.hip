@@ -985,11 +985,11 @@ static pg_status run_valuation(pg_game *g, hipStream_t s, bool odd_switch,
                                int32_t *count, int64_t *n_finite) {
   g->nlevels = g->dense ? count_levels(g->n_aug, g->dw)
                         : plan_levels(g->n_aug);
-  if (!g->ev_a) {
+  if (g->timed && !g->ev_a) {
     PG_HIP(hipEventCreate(&g->ev_a));
     PG_HIP(hipEventCreate(&g->ev_b));
   }
-  PG_HIP(hipEventRecord(g->ev_a, s));
+  if (g->timed) PG_HIP(hipEventRecord(g->ev_a, s));
   bool replayed = false;
   if (odd_switch && g->use_graph && !g->careful && !g->prof.on &&
       !g->host_rl) {
@@ -1011,7 +1011,7 @@ static pg_status run_valuation(pg_game *g, hipStream_t s, bool odd_switch,
       enqueue_any_switch(g, true, s, true);
     }
   }
-  PG_HIP(hipEventRecord(g->ev_b, s));
+  if (g->timed) PG_HIP(hipEventRecord(g->ev_b, s));
   pg_status st = read_ctr(g, s);
   if (st != PG_OK) return st;
   if (g->hctr[C_ABORT]) {
@@ -1024,11 +1024,12 @@ static pg_status run_valuation(pg_game *g, hipStream_t s, bool odd_switch,
     if (odd_switch) {
       enqueue_any_switch(g, true, s, true);
     }
-    PG_HIP(hipEventRecord(g->ev_b, s));
+    if (g->timed) PG_HIP(hipEventRecord(g->ev_b, s));
     st = read_ctr(g, s);
     if (st != PG_OK) return st;
   }
-  if (hipEventElapsedTime(&g->last_ms, g->ev_a, g->ev_b) != hipSuccess)
+  if (!g->timed ||
+      hipEventElapsedTime(&g->last_ms, g->ev_a, g->ev_b) != hipSuccess)
     g->last_ms = 0.0f;
   g->par ^= 1;
   st = check_ctr(g);

@@ -26,6 +26,7 @@ PG_HOST_REDUCED_LIST = 64
 PG_SWITCH_ROWS, PG_SWITCH_BUCKETS = 128, 256
 PG_KEEP_DUMMIES = 512
 PG_BR_SI, PG_BR_SI_RESET, PG_BR_BELLMAN_FORD = 0, 1, 2
+PG_NOALLOC_MAX_VERTICES, PG_NOALLOC_MAX_EDGES = 65536, 1048576
 
 STATUS_NAMES = {0: "PG_OK", 1: "PG_EINVAL", 2: "PG_ENOMEM", 3: "PG_EDEVICE",
                 4: "PG_EITERLIMIT", 5: "PG_EINADMISSIBLE", 6: "PG_EINTERNAL"}
@@ -37,7 +38,8 @@ EXPORTS = ["pg_load_csr", "pg_game_info", "pg_count_info", "pg_export_game",
            "pg_profile_read", "pg_batch_create", "pg_batch_submit",
            "pg_batch_step", "pg_batch_poll", "pg_batch_finished",
            "pg_batch_info", "pg_batch_free",
-           "pg_free", "pg_release_cache", "pg_last_error"]
+           "pg_free", "pg_release_cache", "pg_solve_noalloc",
+           "pg_last_error"]
 
 
 def release_cache():
@@ -148,6 +150,9 @@ def lib() -> ctypes.CDLL:
         L.pg_batch_finished.argtypes = [P, P, I32, ctypes.POINTER(I32)]
         L.pg_batch_free.argtypes = [P]
         L.pg_free.argtypes = [P]
+        L.pg_solve_noalloc.argtypes = [I64, I64, P, P, P, P, U32,
+                                       ctypes.POINTER(SolveOpts), P, P, P,
+                                       ctypes.POINTER(Stats), P]
         L.pg_last_error.argtypes = []
         L.pg_last_error.restype = ctypes.c_char_p
         for name in EXPORTS[:-1]:
@@ -178,6 +183,55 @@ def _stream(device: bool):
         return None
     import torch
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def solve_noalloc(g: dict, device: bool = False, max_major: int = 0,
+                  max_inner: int = 0, best_response: int = PG_BR_SI,
+                  keep_dummies: bool = False) -> dict:
+    """pg_solve_noalloc: load, solve and release in one call that allocates
+    no device memory (the library's static scratch), for games of at most
+    PG_NOALLOC_MAX_VERTICES vertices and PG_NOALLOC_MAX_EDGES edges.  The
+    caller's outputs are sized 2 n (n_aug <= 2 n) and cut to n_aug."""
+    n = int(g["n"])
+    if device:
+        import torch
+        arr = {k: torch.from_numpy(np.ascontiguousarray(g[k])).cuda()
+               for k in ("offsets", "targets", "owner", "pri")}
+        off_i32 = arr["offsets"].dtype == torch.int32
+        if not off_i32:
+            arr["offsets"] = arr["offsets"].to(torch.int64)
+        arr["targets"] = arr["targets"].to(torch.int32)
+        arr["owner"] = arr["owner"].to(torch.uint8)
+        arr["pri"] = arr["pri"].to(torch.int32)
+        out = lambda c, t: torch.empty(c, dtype=t, device="cuda")  # noqa
+        dt = {"u8": torch.uint8, "i32": torch.int32}
+    else:
+        off = np.ascontiguousarray(g["offsets"])
+        off_i32 = off.dtype == np.int32
+        arr = {"offsets": off if off_i32 else off.astype(np.int64),
+               "targets": np.ascontiguousarray(g["targets"], np.int32),
+               "owner": np.ascontiguousarray(g["owner"], np.uint8),
+               "pri": np.ascontiguousarray(g["pri"], np.int32)}
+        out = lambda c, t: np.empty(c, dtype=t)  # noqa
+        dt = {"u8": np.uint8, "i32": np.int32}
+    m = int(arr["targets"].numel() if device else arr["targets"].size)
+    flags = (PG_PTR_DEVICE if device else 0) | \
+        (PG_OFFSETS_I32 if off_i32 else 0)
+    oflags = (PG_PTR_DEVICE if device else 0) | \
+        (PG_KEEP_DUMMIES if keep_dummies else 0)
+    opts = SolveOpts(max_major, max_inner, oflags, best_response, None, None,
+                     0, 0, None, None, None, None)
+    winner = out(n, dt["u8"])
+    sigma = out(2 * n, dt["i32"])
+    tau = out(2 * n, dt["i32"])
+    st = Stats()
+    _check(lib().pg_solve_noalloc(
+        n, m, _ptr(arr["offsets"]), _ptr(arr["targets"]), _ptr(arr["owner"]),
+        _ptr(arr["pri"]), flags, ctypes.byref(opts), _ptr(winner),
+        _ptr(sigma), _ptr(tau), ctypes.byref(st), _stream(device)))
+    na = int(st.n_aug)
+    return {"winner": winner, "sigma": sigma[:na], "tau": tau[:na],
+            "stats": st.as_dict()}
 
 
 class Game:

@@ -65,7 +65,8 @@ def test_binding_constants_mirror_the_header():
                  "PG_CAREFUL_WALKS", "PG_COUNT_VALUATION", "PG_NO_GRAPH",
                  "PG_HOST_REDUCED_LIST", "PG_SWITCH_ROWS", "PG_SWITCH_BUCKETS",
                  "PG_KEEP_DUMMIES", "PG_BR_SI", "PG_BR_SI_RESET", "PG_BR_BELLMAN_FORD",
-                 "PG_SINK", "PG_KEY_TOP"):
+                 "PG_SINK", "PG_KEY_TOP", "PG_NOALLOC_MAX_VERTICES",
+                 "PG_NOALLOC_MAX_EDGES", "PG_NOALLOC_SCRATCH_MIB"):
         assert name in consts, name
         if hasattr(pg, name):
             assert getattr(pg, name) == consts[name], name
