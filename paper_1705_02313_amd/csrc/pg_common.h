@@ -220,7 +220,8 @@ struct pg_game {
   // [2*n_aug+2] {next element or -1, node | weight bits}
   int2 *elem = nullptr;
   // [2*n_aug+2] per element carrying a point: {level-1 sublist, weight
-  // before the element in that sublist}
+  // before the element in that sublist}, by sorted position: element 2i+2
+  // at i, 2i+3 at n_aug + i, element 1 at 2 n_aug
   int2 *aux = nullptr;
 
   pgk::RankLevel lv[8];

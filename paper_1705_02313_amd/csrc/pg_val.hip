@@ -352,18 +352,23 @@ __global__ __launch_bounds__(kBlock) void k_link_build(
     else el[2 * (2 * i + 3) + 1] = (int32_t)p | w;
   }
   const uint2 f = fh[c];
-  if (f.x == 0) {
-    // a leaf: one element visits it, carrying the parent's point (bit 30)
-    // and then its own (bit 31)
-    elem[2 * i + 2] =
-        make_int2(nx, c | (int32_t)0x80000000 | ((int32_t)wd << 30));
-    return;
+  // a leaf: one element visits it, carrying the parent's point (bit 30)
+  // and then its own (bit 31); else enter c: its first child, carrying the
+  // parent's point when wd
+  const int2 e0 =
+      f.x == 0
+          ? make_int2(nx, c | (int32_t)0x80000000 | ((int32_t)wd << 30))
+          : make_int2((int32_t)(2 * f.x), (int32_t)p | ((int32_t)wd << 31));
+  if (seg_end && p != (uint32_t)N) {
+    elem[2 * i + 2] = e0;   // 2i+3 leaves p: written above and by p
+  } else {
+    // 2i+3 is unused: one 16-byte store covers the pair (partly written
+    // sectors cost a read-modify-write when they leave the cache)
+    *reinterpret_cast<int4 *>(&elem[2 * i + 2]) =
+        make_int4(e0.x, e0.y, 0, 0);
   }
-  // enter c: its first child, carrying the parent's point when wd
-  elem[2 * i + 2] =
-      make_int2((int32_t)(2 * f.x), (int32_t)p | ((int32_t)wd << 31));
   // leave c, next to its last child: on to c's continuation
-  el[2 * (2 * (int64_t)f.y + 1)] = nx;
+  if (f.x != 0) el[2 * (2 * (int64_t)f.y + 1)] = nx;
 }
 
 // ---------------------------------------------------------------------------
@@ -376,9 +381,18 @@ __global__ __launch_bounds__(kBlock) void k_link_build(
 // is one.  Every size comes from the finite count on the device.
 // Also records, for every element that carries a point, its sublist and
 // the sublist's weight before it (aux), so that the keys can be emitted by
-// one pass over sorted positions instead of a second walk.
+// one pass over sorted positions instead of a second walk.  The records are
+// kept by sorted position (aux_slot), so that a run of leaf siblings fills
+// whole sectors.
+__device__ __forceinline__ int64_t aux_slot(int64_t e, int64_t N) {
+  // 2i+2 -> i; 2i+3 -> N + i; 1 (leave the sink) -> 2N
+  return (e & 1) ? (e == 1 ? 2 * N : N + (e - 3) / 2) : (e - 2) / 2;
+}
+
+constexpr int kSum1Batch = 16;
+
 __global__ __launch_bounds__(kBlock) void k_lr_sum1(
-    const int2 *__restrict__ elem, int per_thread, int32_t *sum,
+    int32_t N, const int2 *__restrict__ elem, int per_thread, int32_t *sum,
     int32_t *next, int2 *aux, int32_t *ctr) {
   if (ctr[C_ABORT]) return;
   const int64_t L = 2 * (int64_t)ctr[C_NFIN] + 2;
@@ -391,14 +405,37 @@ __global__ __launch_bounds__(kBlock) void k_lr_sum1(
     int64_t e = j * kStride;
     int32_t acc = 0;
     int64_t steps = 0;
-    for (;;) {
-      const int2 el = elem[e];
-      const int32_t w = (int32_t)((uint32_t)el.y >> 31) + ((el.y >> 30) & 1);
-      if (w) aux[e] = make_int2((int32_t)j, acc);
-      acc += w;
-      e = el.x;
-      if (e < 0 || e % kStride == 0) break;
-      if (++steps > L) { atomicOr(&ctr[C_ERR], ERR_LISTWALK); e = -1; break; }
+    bool done = false;
+    // A store issued inside the walk would hold up the next step's load
+    // (vector loads and stores retire through one in-order counter), so
+    // the records of kSum1Batch steps wait in registers (fixed indices: the
+    // block of steps is unrolled) and go out together.
+    while (!done) {
+      int32_t slot[kSum1Batch], before[kSum1Batch];
+#pragma unroll
+      for (int b = 0; b < kSum1Batch; ++b) {
+        slot[b] = -1;
+        if (done) continue;
+        const int2 el = elem[e];
+        const int32_t w =
+            (int32_t)((uint32_t)el.y >> 31) + ((el.y >> 30) & 1);
+        if (w) {
+          slot[b] = (int32_t)aux_slot(e, N);
+          before[b] = acc;
+        }
+        acc += w;
+        e = el.x;
+        if (e < 0 || e % kStride == 0) {
+          done = true;
+        } else if (++steps > L) {
+          atomicOr(&ctr[C_ERR], ERR_LISTWALK);
+          e = -1;
+          done = true;
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < kSum1Batch; ++b)
+        if (slot[b] >= 0) aux[slot[b]] = make_int2((int32_t)j, before[b]);
     }
     sum[j] = acc;
     next[j] = e < 0 ? -1 : (int32_t)(e / kStride);
@@ -494,11 +531,25 @@ __global__ __launch_bounds__(kBlock) void k_lr_distk(
   if (j >= nsplit) return;
   int64_t e = j * kStrideUp;
   int32_t b = sbase[j];
-  for (int64_t steps = 0; steps <= size; ++steps) {
-    lbase[e] = b;
-    b += lw[e];
-    e = lnext[e];
-    if (e < 0 || e % kStrideUp == 0) break;
+  int64_t steps = 0;
+  bool done = false;
+  // the bases wait in registers and go out together (see k_lr_sum1)
+  while (!done) {
+    int64_t at[kStrideUp];
+    int32_t val[kStrideUp];
+#pragma unroll
+    for (int q = 0; q < kStrideUp; ++q) {
+      at[q] = -1;
+      if (done) continue;
+      at[q] = e;
+      val[q] = b;
+      b += lw[e];
+      e = lnext[e];
+      if (e < 0 || e % kStrideUp == 0 || ++steps > size) done = true;
+    }
+#pragma unroll
+    for (int q = 0; q < kStrideUp; ++q)
+      if (at[q] >= 0) lbase[at[q]] = val[q];
   }
 }
 
@@ -518,7 +569,7 @@ __global__ __launch_bounds__(kBlock) void k_lr_emit1(
   if (i == (nF > 0 ? nF - 1 : 0)) {
     const int2 el = elem[1];
     if (el.y < 0) {
-      const int2 a = aux[1];
+      const int2 a = aux[2 * (int64_t)N];
       key[N] = sbase[a.x] + a.y;
     }
     if (nF == 0) return;
@@ -526,7 +577,7 @@ __global__ __launch_bounds__(kBlock) void k_lr_emit1(
   const uint32_t p = ps_key(skS, i, ni, N);
   const int2 el = elem[2 * i + 2];
   if (el.y & (int32_t)0xC0000000) {
-    const int2 a = aux[2 * i + 2];
+    const int2 a = aux[i];
     int32_t b = sbase[a.x] + a.y;
     if (el.y & 0x40000000) key[p] = b++;          // a leaf's parent
     if (el.y < 0) key[el.y & 0x3fffffff] = b;
@@ -535,7 +586,7 @@ __global__ __launch_bounds__(kBlock) void k_lr_emit1(
       (i == nF - 1 || ps_key(skS, i + 1, ni, N) != p)) {
     const int2 lv = elem[2 * i + 3];               // leaves p
     if (lv.y < 0) {
-      const int2 a = aux[2 * i + 3];
+      const int2 a = aux[N + i];
       key[lv.y & 0x3fffffff] = sbase[a.x] + a.y;
     }
   }
@@ -816,7 +867,7 @@ static void enqueue_rank_list(pg_game *g, hipStream_t s) {
   // has one element per leaf and two per inner vertex: counted at one per
   // finite vertex, its least length
   PG_LAUNCH_NF(pf, K_LR_SUM1, 8.5, k_lr_sum1, dim3(grid_for(thr1)),
-            dim3(kBlock), 0, s, g->elem, kPerThread1, g->lv[0].sum,
+            dim3(kBlock), 0, s, N, g->elem, kPerThread1, g->lv[0].sum,
             g->lv[0].next, g->aux, g->ctr);
 }
 
