@@ -477,6 +477,45 @@ pg_status pg_solve_noalloc(int64_t n, int64_t m, const void *offsets,
                            int32_t *sigma, int32_t *tau, pg_stats *stats,
                            void *hip_stream);
 
+/*
+ * Tuning of the rank valuation (games with distinct priorities): launch and
+ * walk parameters that change the speed of a valuation, never its result.
+ * pg_load_csr (and each batch arena) takes them from a table measured on
+ * MI355X per size class of n_aug (pg_tuning_table);
+ * paper_1705_02313_amd/tune.py measures the table again.
+ *
+ *   stride0      list ranking (section 5, "List ranking"): every stride0-th
+ *                element of the Euler list is a splitter; 8, 16, 32 or 64
+ *   per_thread   level-1 sublists walked by one thread: 1, 2, 4 or 8
+ *   walk_full    plain play steps of the full ng pass and ng-chain steps
+ *                of the full root pass: 2..64
+ *   walk_round   shortcut steps of one later round: 8..256
+ *   walk_rounds  rounds enqueued before the host looks: 1..8 (a vertex
+ *                still open after them is finished on the host-driven path)
+ *   walk_block   threads per block of the full ng and root passes: 64, 128
+ *                or 256
+ *
+ * pg_set_tuning: PG_EINVAL for a value outside these sets or a game with
+ * count valuations; the new values serve the next valuation (a captured
+ * iteration graph is captured again).
+ * pg_tuning_table: copies up to `capacity` entries (nullable arrays) and
+ * returns the table's length; entry i serves games with n_aug >= min_n_aug[i]
+ * below the next entry's bound.
+ */
+typedef struct pg_tuning {
+    int32_t stride0;
+    int32_t per_thread;
+    int32_t walk_full;
+    int32_t walk_round;
+    int32_t walk_rounds;
+    int32_t walk_block;
+} pg_tuning;
+
+pg_status pg_get_tuning(const pg_game *game, pg_tuning *tuning);
+pg_status pg_set_tuning(pg_game *game, const pg_tuning *tuning);
+int32_t pg_tuning_table(pg_tuning *entries, int64_t *min_n_aug,
+                        int32_t capacity);
+
 /* Release the game.  NULL is accepted.  Its device and pinned host memory
  * goes to a per-device cache that later pg_load_csr calls on that device
  * take their memory from (blocks are returned only after the device has

@@ -711,7 +711,7 @@ pg_status alloc_state(pg_game *g, int64_t cap) {
   PG_TRY(dev_alloc(&g->aux, 2 * N + 2));
   // sublist levels for the longest possible Euler list
   for (int k = 0; k < 8; ++k) {
-    const int64_t ns = level_size(2 * N + 2, k + 1);
+    const int64_t ns = level_size(2 * N + 2, k + 1, kStrideMin);
     PG_TRY(dev_alloc(&g->lv[k].sum, ns));
     PG_TRY(dev_alloc(&g->lv[k].next, ns));
     PG_TRY(dev_alloc(&g->lv[k].base, ns));
@@ -1194,6 +1194,7 @@ pg_status load_game(int64_t n, int64_t m, const void *offsets,
   g->careful = flags & PG_CAREFUL_WALKS;
   g->use_graph = !(flags & PG_NO_GRAPH);
   g->host_rl = (flags & PG_HOST_REDUCED_LIST) && !g->dense;
+  if (st == PG_OK && !g->dense) apply_tuning(g, tuning_for(g->n_aug));
   return st;
 }
 

@@ -599,6 +599,8 @@ pg_status rebuild(pg_batch *b, bool *built_any) {
   a->n = a->n_aug = vb;
   a->m = a->m_aug = eb;
   if (G == 0) return PG_OK;
+  // the launch and walk parameters of the arena's size class
+  a->tune = tuning_for(vb);
   PG_HIP(hipMemcpyAsync(b->d_desc, b->h_desc.data(), sizeof(GameDesc) * G,
                         hipMemcpyHostToDevice, s));
   PG_HIP(hipMemcpyAsync(b->d_pstart, b->h_pstart.data(),

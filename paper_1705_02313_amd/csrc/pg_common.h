@@ -246,6 +246,8 @@ struct pg_game {
   int32_t *hctr = nullptr;   // pinned host mirror
 
   pgk::Prof prof;
+  // launch and walk parameters of the rank valuation (pg_tuning)
+  pg_tuning tune{32, 1, 16, 64, 3, 256};
   // false: no HIP events are created or recorded (pg_solve_noalloc)
   bool timed = true;
   // HIP events around each best-response iteration on the call's stream
@@ -310,12 +312,16 @@ __device__ __forceinline__ void st_relaxed(int32_t *p, int32_t v) {
 // short, and a level's time is its longest sublist walk (sublist lengths are
 // about geometric, so the longest is near stride x ln(sublists)): there a
 // small stride wins
-constexpr int kStride = 32;        // level 0 -> 1
+constexpr int kStride = 32;        // level 0 -> 1 (count valuations; rank
+                                   // valuations take pg_tuning::stride0)
 constexpr int kStrideUp = 8;       // level k -> k + 1 for k >= 1
+constexpr int kStrideMin = 8;      // least stride0 (sizes the level arrays)
 
 // size of level k of the sublist ranking for an Euler list of L elements
-__device__ __host__ __forceinline__ int64_t level_size(int64_t L, int k) {
-  if (k >= 1) L = (L + kStride - 1) / kStride;
+// whose level-0 stride is s0
+__device__ __host__ __forceinline__ int64_t level_size(int64_t L, int k,
+                                                       int s0 = kStride) {
+  if (k >= 1) L = (L + s0 - 1) / s0;
   for (int j = 1; j < k; ++j) L = (L + kStrideUp - 1) / kStrideUp;
   return L;
 }
@@ -373,6 +379,11 @@ int parent_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
 
 // ---- valuation and switching (pg_val.hip) ---------------------------------
 namespace pgk {
+// The table entry for a rank game of n_aug vertices (pg_tune.hip).
+pg_tuning tuning_for(int64_t n_aug);
+bool tuning_valid(const pg_tuning &t);
+// Applies t to g (rank valuations); drops captured iteration graphs.
+void apply_tuning(pg_game *g, const pg_tuning &t);
 // Clears the walk state; call once before a sequence of valuations.
 void valuation_reset(pg_game *g, hipStream_t s);
 // One valuation of the play graph held in g->sp; writes g->key.

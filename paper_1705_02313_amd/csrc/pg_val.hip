@@ -392,17 +392,17 @@ __device__ __forceinline__ int64_t aux_slot(int64_t e, int64_t N) {
 constexpr int kSum1Batch = 16;
 
 __global__ __launch_bounds__(kBlock) void k_lr_sum1(
-    int32_t N, const int2 *__restrict__ elem, int per_thread, int32_t *sum,
-    int32_t *next, int2 *aux, int32_t *ctr) {
+    int32_t N, const int2 *__restrict__ elem, int per_thread, int s0,
+    int32_t *sum, int32_t *next, int2 *aux, int32_t *ctr) {
   if (ctr[C_ABORT]) return;
   const int64_t L = 2 * (int64_t)ctr[C_NFIN] + 2;
-  const int64_t nsplit = level_size(L, 1);
+  const int64_t nsplit = level_size(L, 1, s0);
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
   for (int k = 0; k < per_thread; ++k) {
     const int64_t j = t + (int64_t)k * nthreads;
     if (j >= nsplit) break;
-    int64_t e = j * kStride;
+    int64_t e = j * s0;
     int32_t acc = 0;
     int64_t steps = 0;
     bool done = false;
@@ -425,7 +425,7 @@ __global__ __launch_bounds__(kBlock) void k_lr_sum1(
         }
         acc += w;
         e = el.x;
-        if (e < 0 || e % kStride == 0) {
+        if (e < 0 || e % s0 == 0) {
           done = true;
         } else if (++steps > L) {
           atomicOr(&ctr[C_ERR], ERR_LISTWALK);
@@ -438,17 +438,17 @@ __global__ __launch_bounds__(kBlock) void k_lr_sum1(
         if (slot[b] >= 0) aux[slot[b]] = make_int2((int32_t)j, before[b]);
     }
     sum[j] = acc;
-    next[j] = e < 0 ? -1 : (int32_t)(e / kStride);
+    next[j] = e < 0 ? -1 : (int32_t)(e / s0);
   }
 }
 
 __global__ __launch_bounds__(kBlock) void k_lr_sumk(
     const int32_t *__restrict__ lnext, const int32_t *__restrict__ lw,
-    int level, int32_t *sum, int32_t *next, int32_t *ctr) {
+    int level, int s0, int32_t *sum, int32_t *next, int32_t *ctr) {
   if (ctr[C_ABORT]) return;
   const int64_t L = 2 * (int64_t)ctr[C_NFIN] + 2;
-  const int64_t size = level_size(L, level);
-  const int64_t nsplit = level_size(L, level + 1);
+  const int64_t size = level_size(L, level, s0);
+  const int64_t nsplit = level_size(L, level + 1, s0);
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= nsplit) return;
   int64_t e = j * kStrideUp;
@@ -475,11 +475,11 @@ constexpr int kTopThreads = 1024;
 
 __global__ __launch_bounds__(kTopThreads) void k_lr_top(
     const int32_t *__restrict__ lnext, const int32_t *__restrict__ lw,
-    int level, int32_t *base, int32_t *ctr) {
+    int level, int s0, int32_t *base, int32_t *ctr) {
   if (ctr[C_ABORT]) return;
   const int32_t nF = ctr[C_NFIN];
   const int64_t L0 = 2 * (int64_t)nF + 2;
-  const int32_t L = (int32_t)level_size(L0, level);
+  const int32_t L = (int32_t)level_size(L0, level, s0);
   __shared__ int32_t nx[kTopMax];
   __shared__ int32_t sm[kTopMax];
   constexpr int per = kTopMax / kTopThreads;
@@ -521,12 +521,12 @@ __global__ __launch_bounds__(kTopThreads) void k_lr_top(
 // Hands each element of a level-k sublist its exclusive rank.
 __global__ __launch_bounds__(kBlock) void k_lr_distk(
     const int32_t *__restrict__ lnext, const int32_t *__restrict__ lw,
-    int level, const int32_t *__restrict__ sbase, int32_t *lbase,
+    int level, int s0, const int32_t *__restrict__ sbase, int32_t *lbase,
     const int32_t *ctr) {
   if (ctr[C_ABORT]) return;
   const int64_t L = 2 * (int64_t)ctr[C_NFIN] + 2;
-  const int64_t size = level_size(L, level);
-  const int64_t nsplit = level_size(L, level + 1);
+  const int64_t size = level_size(L, level, s0);
+  const int64_t nsplit = level_size(L, level + 1, s0);
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= nsplit) return;
   int64_t e = j * kStrideUp;
@@ -701,18 +701,18 @@ struct WalkBudget {
   int walk;    // shortcut-walk steps of one round
   int rounds;  // rounds enqueued without looking back
 };
-constexpr WalkBudget kRankWalks = {16, 64, 3};
+// Rank games take theirs from the game's tuning (pg_tune.hip: per size
+// class, measured); count games keep these.
 constexpr WalkBudget kCountWalks = {4, 32, 4};
 static WalkBudget walk_budget(const pg_game *g) {
-  return g->dense ? kCountWalks : kRankWalks;
+  if (g->dense) return kCountWalks;
+  return {g->tune.walk_full, g->tune.walk_round, g->tune.walk_rounds};
+}
+// threads per block of the full ng and root passes
+static int walk_block(const pg_game *g) {
+  return g->dense ? kBlock : g->tune.walk_block;
 }
 constexpr int kMaxRounds = 64;    // rounds of the careful path before failing
-// level-1 sublists per thread: 4 when the list is long enough to fill the
-// chip with a quarter of the threads (measured best at 13M vertices), fewer
-// on smaller games, whose few long walks would otherwise run on few waves
-static int per_thread1(int64_t ns1) {
-  return ns1 >= 4 * (int64_t)131072 ? 4 : (ns1 >= 2 * (int64_t)131072 ? 2 : 1);
-}
 
 static pg_status read_ctr(pg_game *g, hipStream_t s) {
   PG_HIP(hipMemcpyAsync(g->hctr, g->ctr, sizeof(int32_t) * C_COUNT,
@@ -727,10 +727,10 @@ static pg_status read_ctr(pg_game *g, hipStream_t s) {
 }
 
 // number of walking levels of the sublist ranking for the longest list
-static int plan_levels(int64_t N) {
+static int plan_levels(int64_t N, int s0) {
   const int64_t Lmax = 2 * N + 2;
   int k = 1;
-  while (level_size(Lmax, k) > kTopMax) ++k;
+  while (level_size(Lmax, k, s0) > kTopMax) ++k;
   return k;
 }
 
@@ -749,8 +749,9 @@ static void enqueue_walks(pg_game *g, hipStream_t s) {
   const WalkBudget wb = walk_budget(g);
   fill_i32(g->ctr, 0, C_TOTAL, s, pf);
   // own record 8, first successor record 8, result 4; state resets 5
-  PG_LAUNCH(pf, K_NG_WALK, 25.0 * N, k_ng_full, dim3(grid_for(N)),
-            dim3(kBlock), 0, s, N, g->sp, g->pri, ng, cand, g->ctr,
+  const int wblk = walk_block(g);
+  PG_LAUNCH(pf, K_NG_WALK, 25.0 * N, k_ng_full, dim3(grid_for(N, wblk)),
+            dim3(wblk), 0, s, N, g->sp, g->pri, ng, cand, g->ctr,
             wb.full, g->rs, g->rcand, (int32_t *)nullptr);
   for (int r = 1; r <= wb.rounds; ++r)
     PG_LAUNCH(pf, K_NG_ROUND, 4.0 * N, k_ng_round, dim3(grid_for(N)),
@@ -760,9 +761,9 @@ static void enqueue_walks(pg_game *g, hipStream_t s) {
   // relabeled); resets 12
   const int32_t *rvpos = kernel_rvpos(g);
   PG_LAUNCH(pf, K_ROOT_WALK, (rvpos ? 29.0 : 25.0) * N, k_root_full,
-            dim3(grid_for(N)), dim3(kBlock), 0, s, N, ng, g->rs, g->rcand,
-            g->key, g->ctr, wb.full, ngn, candn, g->fh, rvpos, g->sk0,
-            (int32_t *)nullptr);
+            dim3(grid_for(N, wblk)), dim3(wblk), 0, s, N, ng, g->rs,
+            g->rcand, g->key, g->ctr, wb.full, ngn, candn, g->fh, rvpos,
+            g->sk0, (int32_t *)nullptr);
   for (int r = 1; r <= wb.rounds; ++r)
     PG_LAUNCH(pf, K_ROOT_ROUND, 1.0 * N, k_root_round, dim3(grid_for(N)),
               dim3(kBlock), 0, s, N, ng, g->rs, g->rcand, g->key, g->ctr,
@@ -796,9 +797,10 @@ static pg_status careful_walks(pg_game *g, hipStream_t s) {
   fill_i32(cand, -1, N, s, pf);
   fill_i32(g->ctr, 0, C_TOTAL, s, pf);
   int32_t open = 0;
+  const int wblk = walk_block(g);
   PG_TRY(counted(g, s, [&](int32_t *dist) {
-    PG_LAUNCH(pf, K_NG_WALK, 25.0 * N, k_ng_full, dim3(grid_for(N)),
-              dim3(kBlock), 0, s, N, g->sp, g->pri, ng, cand, g->ctr,
+    PG_LAUNCH(pf, K_NG_WALK, 25.0 * N, k_ng_full, dim3(grid_for(N, wblk)),
+              dim3(wblk), 0, s, N, g->sp, g->pri, ng, cand, g->ctr,
               wb.full, g->rs, g->rcand, dist);
   }, &open));
   for (int r = 0; open > 0; ++r) {
@@ -815,9 +817,9 @@ static pg_status careful_walks(pg_game *g, hipStream_t s) {
   const int32_t *rvpos = kernel_rvpos(g);
   PG_TRY(counted(g, s, [&](int32_t *dist) {
     PG_LAUNCH(pf, K_ROOT_WALK, (rvpos ? 29.0 : 25.0) * N, k_root_full,
-              dim3(grid_for(N)), dim3(kBlock), 0, s, N, ng, g->rs, g->rcand,
-              g->key, g->ctr, wb.full, ngn, candn, g->fh, rvpos, g->sk0,
-              dist);
+              dim3(grid_for(N, wblk)), dim3(wblk), 0, s, N, ng, g->rs,
+              g->rcand, g->key, g->ctr, wb.full, ngn, candn, g->fh, rvpos,
+              g->sk0, dist);
   }, &open));
   for (int r = 0; open > 0; ++r) {
     if (r >= kMaxRounds)
@@ -859,15 +861,16 @@ static void enqueue_rank_list(pg_game *g, hipStream_t s) {
   PG_LAUNCH_NI(pf, K_LINK_BUILD, 0.0, perm ? 28.0 : 24.0, 8.0, k_link_build,
                dim3(grid_for(N)), dim3(kBlock), 0, s, N, g->n_oddpri, skS, svS,
                n_inner, perm, g->fh, g->elem, g->ctr);
+  const int s0 = g->tune.stride0;
   const int64_t Lmax = 2 * (int64_t)N + 2;
-  const int64_t ns1 = level_size(Lmax, 1);
-  const int kPerThread1 = per_thread1(ns1);
-  const int64_t thr1 = (ns1 + kPerThread1 - 1) / kPerThread1;
-  // 8 B per list element and 8 B per splitter (2 F / 32 of them).  The list
-  // has one element per leaf and two per inner vertex: counted at one per
-  // finite vertex, its least length
-  PG_LAUNCH_NF(pf, K_LR_SUM1, 8.5, k_lr_sum1, dim3(grid_for(thr1)),
-            dim3(kBlock), 0, s, N, g->elem, kPerThread1, g->lv[0].sum,
+  const int64_t ns1 = level_size(Lmax, 1, s0);
+  const int per1 = g->tune.per_thread;
+  const int64_t thr1 = (ns1 + per1 - 1) / per1;
+  // 8 B per list element and 8 B per splitter (2 F / s0 of them), a record
+  // of 8 B per point.  The list has one element per leaf and two per inner
+  // vertex: counted at one per finite vertex, its least length
+  PG_LAUNCH_NF(pf, K_LR_SUM1, 16.5, k_lr_sum1, dim3(grid_for(thr1)),
+            dim3(kBlock), 0, s, N, g->elem, per1, s0, g->lv[0].sum,
             g->lv[0].next, g->aux, g->ctr);
 }
 
@@ -877,25 +880,28 @@ static void enqueue_rank_emit(pg_game *g, hipStream_t s, bool device_reduced) {
   const int32_t N = (int32_t)g->n_aug;
   Prof *pf = &g->prof;
   const int nl = g->nlevels;
+  const int s0 = g->tune.stride0;
   const int64_t Lmax = 2 * (int64_t)N + 2;
   for (int k = 1; device_reduced && k < nl; ++k) {
-    const int64_t nsk = level_size(Lmax, k + 1);
-    // 8 B per element of the level-k list (about 2 nF / 32^k elements)
+    const int64_t nsk = level_size(Lmax, k + 1, s0);
+    // 8 B per element of the level-k list (about 2 nF / s0 / 8^(k-1))
     PG_LAUNCH_NF(pf, K_LR_SUMK,
-                 16.0 * (double)level_size(Lmax, k) / (double)Lmax, k_lr_sumk,
-              dim3(grid_for(nsk)), dim3(kBlock), 0, s, g->lv[k - 1].next,
-              g->lv[k - 1].sum, k, g->lv[k].sum, g->lv[k].next, g->ctr);
+                 16.0 * (double)level_size(Lmax, k, s0) / (double)Lmax,
+                 k_lr_sumk, dim3(grid_for(nsk)), dim3(kBlock), 0, s,
+                 g->lv[k - 1].next, g->lv[k - 1].sum, k, s0, g->lv[k].sum,
+                 g->lv[k].next, g->ctr);
   }
   if (device_reduced)
-    PG_LAUNCH(pf, K_LR_TOP, 12.0 * level_size(Lmax, nl), k_lr_top, dim3(1),
-              dim3(kTopThreads), 0, s, g->lv[nl - 1].next, g->lv[nl - 1].sum,
-              nl, g->lv[nl - 1].base, g->ctr);
+    PG_LAUNCH(pf, K_LR_TOP, 12.0 * level_size(Lmax, nl, s0), k_lr_top,
+              dim3(1), dim3(kTopThreads), 0, s, g->lv[nl - 1].next,
+              g->lv[nl - 1].sum, nl, s0, g->lv[nl - 1].base, g->ctr);
   for (int k = nl - 1; device_reduced && k >= 1; --k) {
-    const int64_t nsk = level_size(Lmax, k + 1);
+    const int64_t nsk = level_size(Lmax, k + 1, s0);
     PG_LAUNCH_NF(pf, K_LR_DISTK,
-                 24.0 * (double)level_size(Lmax, k) / (double)Lmax, k_lr_distk,
-              dim3(grid_for(nsk)), dim3(kBlock), 0, s, g->lv[k - 1].next,
-              g->lv[k - 1].sum, k, g->lv[k].base, g->lv[k - 1].base, g->ctr);
+                 24.0 * (double)level_size(Lmax, k, s0) / (double)Lmax,
+                 k_lr_distk, dim3(grid_for(nsk)), dim3(kBlock), 0, s,
+                 g->lv[k - 1].next, g->lv[k - 1].sum, k, s0, g->lv[k].base,
+                 g->lv[k - 1].base, g->ctr);
   }
   // per finite vertex: its key and element 12, the element's record 8, a
   // 4 B key written; leave elements of inner parents about 8 per inner child
@@ -953,8 +959,8 @@ static pg_status host_reduced_rank(pg_game *g, hipStream_t s) {
   PG_TRY(read_ctr(g, s));
   if (g->hctr[C_ABORT] || g->hctr[C_ERR]) return PG_OK;  // the caller looks
   const int64_t nF = g->hctr[C_NFIN];
-  const int64_t ns = level_size(2 * nF + 2, 1);
-  const int64_t cap = level_size(2 * g->n_aug + 2, 1);
+  const int64_t ns = level_size(2 * nF + 2, 1, g->tune.stride0);
+  const int64_t cap = level_size(2 * g->n_aug + 2, 1, kStrideMin);
   if (!g->h_rl) {
     void *p = nullptr;
     PG_TRY(host_alloc(&p, sizeof(int32_t) * 3 * (size_t)cap));
@@ -1035,7 +1041,7 @@ static pg_status capture_iteration(pg_game *g, hipGraphExec_t *ex) {
 static pg_status run_valuation(pg_game *g, hipStream_t s, bool odd_switch,
                                int32_t *count, int64_t *n_finite) {
   g->nlevels = g->dense ? count_levels(g->n_aug, g->dw)
-                        : plan_levels(g->n_aug);
+                        : plan_levels(g->n_aug, g->tune.stride0);
   if (g->timed && !g->ev_a) {
     PG_HIP(hipEventCreate(&g->ev_a));
     PG_HIP(hipEventCreate(&g->ev_b));

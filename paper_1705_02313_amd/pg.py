@@ -39,6 +39,7 @@ EXPORTS = ["pg_load_csr", "pg_game_info", "pg_count_info", "pg_export_game",
            "pg_batch_step", "pg_batch_poll", "pg_batch_finished",
            "pg_batch_info", "pg_batch_free",
            "pg_free", "pg_release_cache", "pg_solve_noalloc",
+           "pg_get_tuning", "pg_set_tuning", "pg_tuning_table",
            "pg_last_error"]
 
 
@@ -150,6 +151,10 @@ def lib() -> ctypes.CDLL:
         L.pg_batch_finished.argtypes = [P, P, I32, ctypes.POINTER(I32)]
         L.pg_batch_free.argtypes = [P]
         L.pg_free.argtypes = [P]
+        L.pg_get_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
+        L.pg_set_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
+        L.pg_tuning_table.argtypes = [ctypes.POINTER(Tuning),
+                                      ctypes.POINTER(I64), I32]
         L.pg_solve_noalloc.argtypes = [I64, I64, P, P, P, P, U32,
                                        ctypes.POINTER(SolveOpts), P, P, P,
                                        ctypes.POINTER(Stats), P]
@@ -157,6 +162,7 @@ def lib() -> ctypes.CDLL:
         L.pg_last_error.restype = ctypes.c_char_p
         for name in EXPORTS[:-1]:
             getattr(L, name).restype = ctypes.c_int
+        L.pg_tuning_table.restype = ctypes.c_int32
         _lib = L
     return _lib
 
@@ -183,6 +189,26 @@ def _stream(device: bool):
         return None
     import torch
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Tuning(ctypes.Structure):
+    """pg_tuning: launch and walk parameters of the rank valuation."""
+    _fields_ = [("stride0", ctypes.c_int32), ("per_thread", ctypes.c_int32),
+                ("walk_full", ctypes.c_int32), ("walk_round", ctypes.c_int32),
+                ("walk_rounds", ctypes.c_int32),
+                ("walk_block", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+def tuning_table() -> list:
+    """The library's table: [(min_n_aug, tuning dict), ...]."""
+    n = int(lib().pg_tuning_table(None, None, 0))
+    ent = (Tuning * n)()
+    lo = (ctypes.c_int64 * n)()
+    lib().pg_tuning_table(ent, lo, n)
+    return [(int(lo[i]), ent[i].as_dict()) for i in range(n)]
 
 
 def solve_noalloc(g: dict, device: bool = False, max_major: int = 0,
@@ -432,6 +458,19 @@ class Game:
         _check(rc)
         return {"winner": winner, "sigma": sigma, "tau": tau,
                 "stats": st.as_dict(), "trace": tr}
+
+    def tuning(self) -> dict:
+        """The game's launch and walk parameters (pg_get_tuning)."""
+        t = Tuning()
+        _check(lib().pg_get_tuning(self._h, ctypes.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, **kw):
+        """Replaces some of the parameters (pg_set_tuning)."""
+        cur = self.tuning()
+        cur.update(kw)
+        t = Tuning(**cur)
+        _check(lib().pg_set_tuning(self._h, ctypes.byref(t)))
 
     def profile(self, on: bool = True):
         """Enables (and clears) or disables the per-kernel event profiler."""

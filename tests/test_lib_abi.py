@@ -91,7 +91,7 @@ def test_binding_structs_match_the_header(tmp_path):
     prog = ["#include <stddef.h>", "#include <stdio.h>",
             f'#include "{HEADER}"', "int main(void) {"]
     for cname, cls in (("pg_solve_opts", pg.SolveOpts),
-                       ("pg_stats", pg.Stats)):
+                       ("pg_stats", pg.Stats), ("pg_tuning", pg.Tuning)):
         prog.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
         for f, _ in cls._fields_:
             prog.append(f'printf("{cname} {f} %zu\\n", '
@@ -105,7 +105,24 @@ def test_binding_structs_match_the_header(tmp_path):
                          text=True).stdout.split("\n")
     got = {tuple(ln.split()[:2]): int(ln.split()[2]) for ln in out if ln}
     for cname, cls in (("pg_solve_opts", pg.SolveOpts),
-                       ("pg_stats", pg.Stats)):
+                       ("pg_stats", pg.Stats), ("pg_tuning", pg.Tuning)):
         assert got[(cname, "size")] == ctypes.sizeof(cls), cname
         for f, _ in cls._fields_:
             assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
+
+
+def test_tuning_table_is_ordered_and_valid():
+    """The table read through the library (no device needed): entries by
+    increasing size bound from 0, every value in its documented set."""
+    from paper_1705_02313_amd import pg
+    table = pg.tuning_table()
+    assert table and table[0][0] == 0
+    bounds = [lo for lo, _ in table]
+    assert bounds == sorted(set(bounds))
+    for _, t in table:
+        assert t["stride0"] in (8, 16, 32, 64)
+        assert t["per_thread"] in (1, 2, 4, 8)
+        assert 2 <= t["walk_full"] <= 64
+        assert 8 <= t["walk_round"] <= 256
+        assert 1 <= t["walk_rounds"] <= 8
+        assert t["walk_block"] in (64, 128, 256)
