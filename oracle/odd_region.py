@@ -181,12 +181,16 @@ def subgame(game, keep):
     return sub, ids
 
 
-def solve(game) -> dict:
+def solve(game, counts: bool = None) -> dict:
     """Algorithm 1 on the game without Odd's own winning part A: winners
     of the whole game, and sigma*, tau* of the vertices outside A (in the
     original ids; PG_SINK (-1) for the vertices of A in both), counts of
-    the run on G'."""
+    the run on G'.  Valuations as sets of priorities (ranks) when the
+    game's priorities are pairwise distinct, else as count vectors (section
+    3, "Valuations"); `counts` forces the choice."""
     n = int(game["n"])
+    if counts is None:
+        counts = np.unique(np.asarray(game["pri"])).size < n
     X = odd_avoid_set(game)
     R = odd_cycle_region(game, X)
     A = odd_attractor(game, R)
@@ -199,7 +203,8 @@ def solve(game) -> dict:
            "n_even_switches": 0, "status": 0}
     if keep.any():
         sub, ids = subgame(game, keep)
-        ref = orc.solve(sub, preprocess_game=False)
+        ref = (orc.dense_solve(sub, preprocess_game=False) if counts
+               else orc.solve(sub, preprocess_game=False))
         out["status"] = ref["status"]
         winner[ids] = ref["winner"]
         s, t = ref["sigma"], ref["tau"]

@@ -32,6 +32,15 @@ Recipes (all draws from ``numpy.random.Generator(PCG64(seed))``):
   same seed; priorities drawn uniformly from [0, d) by a second, independent
   stream (``PCG64([seed, 1])``), so they repeat: the regime of the paper's
   experiments, whose games have 2 to 4 distinct priorities.
+* ``odd_cycles_game`` -- structure for Odd's own cycles: about n/3
+  vertices in disjoint Odd cycles of lengths uniform in [1, 6] (length 1 is
+  a self-loop), each cycle of length >= 3 with probability 1/2 given one
+  chord between two members that are not already joined; about n/3 Odd
+  tail vertices, each with one edge to a uniformly drawn earlier vertex
+  (cycle or tail) and, with probability 1/4, a second edge to a uniform
+  Even vertex; the rest Even, each with 1 to 3 distinct uniform
+  successors.  pri = permutation(n), or uniform in [0, d) when d > 0.  Vertex
+  ids are shuffled by a uniform permutation at the end.
 * ``mixed_batch`` -- the batched workload: game g uses seed base+g,
   n_g = round(exp(U(ln nmin, ln nmax))) and a random game with out-degree
   uniform in [2, 8] and int32 offsets.
@@ -41,7 +50,7 @@ from __future__ import annotations
 import numpy as np
 
 __all__ = ["random_game", "chain_game", "few_priorities_game", "mixed_batch",
-           "config_game", "CONFIG_SEED_BASE"]
+           "odd_cycles_game", "config_game", "CONFIG_SEED_BASE"]
 
 CONFIG_SEED_BASE = 1000
 
@@ -146,6 +155,56 @@ def few_priorities_game(n: int, dmin: int, dmax: int, d: int, seed: int,
     rng = np.random.Generator(np.random.PCG64([seed, 1]))
     g["pri"] = rng.integers(0, d, size=n).astype(np.int32)
     return g
+
+
+def odd_cycles_game(n: int, seed: int, d: int = 0,
+                    offsets_dtype=np.int64) -> dict:
+    """Odd cycles (some with chords), Odd tails into them, Even rest."""
+    if n < 9:
+        raise ValueError("odd_cycles_game needs n >= 9")
+    rng = _rng(seed)
+    rows = []
+    owner = []
+    n_cyc = n // 3
+    while len(rows) < n_cyc:
+        L = int(rng.integers(1, 7))
+        base = len(rows)
+        mem = [[base + (i + 1) % L] for i in range(L)]
+        if L >= 3 and rng.random() < 0.5:
+            a, b = (int(x) for x in rng.integers(0, L, size=2))
+            if b != (a + 1) % L:
+                mem[a].append(base + b)
+        rows.extend(mem)
+        owner.extend([1] * L)
+    n_cyc = len(rows)
+    n_tail = min(n // 3, n - n_cyc - 1)
+    n_even = n - n_cyc - n_tail
+    first_even = n_cyc + n_tail
+    for t in range(n_tail):
+        v = n_cyc + t
+        r = [int(rng.integers(0, v))]
+        if rng.random() < 0.25:
+            r.append(first_even + int(rng.integers(0, n_even)))
+        rows.append(r)
+        owner.append(1)
+    for _ in range(n_even):
+        k = int(rng.integers(1, 4))
+        rows.append([int(x) for x in rng.choice(n, size=k, replace=False)])
+        owner.append(0)
+    # shuffle ids: new id of old vertex i is p[i]
+    p = rng.permutation(n)
+    inv = np.argsort(p)
+    rows = [sorted(int(p[w]) for w in rows[int(inv[v])]) for v in range(n)]
+    owner = np.asarray(owner, np.uint8)[inv]
+    if d > 0:
+        pri = rng.integers(0, d, size=n).astype(np.int32)
+    else:
+        pri = rng.permutation(n).astype(np.int32)
+    deg = np.array([len(r) for r in rows], np.int64)
+    flat = np.array([w for r in rows for w in r], np.int64)
+    offsets, targets = _rows_to_csr(deg, flat, offsets_dtype)
+    return {"n": n, "m": int(deg.sum()), "offsets": offsets,
+            "targets": targets, "owner": owner, "pri": pri}
 
 
 def mixed_batch(count: int, seed_base: int, nmin: int = 1000,

@@ -25,6 +25,10 @@ def _games():
                                      6100 + seed))
     out.append(synth.chain_game(500, 6200))
     out.append(synth.chain_game(64, 6201))
+    # Odd cycles with and without odd maxima, chords, tails (R short of X)
+    for seed in range(8):
+        out.append(synth.odd_cycles_game([9, 14, 60, 400][seed % 4],
+                                         6400 + seed, d=3 if seed >= 6 else 0))
     return out
 
 
@@ -35,7 +39,7 @@ def _succ(game):
             for v in range(int(game["n"]))]
 
 
-@pytest.mark.parametrize("i", range(54))
+@pytest.mark.parametrize("i", range(62))
 def test_winners_equal_zielonka_and_the_dummy_path(i):
     g = _games()[i]
     r = odd_region.solve(g)
@@ -89,6 +93,16 @@ def test_region_against_cycle_enumeration(seed):
     np.testing.assert_array_equal(odd_region.solve(g)["winner"], zielonka(g))
 
 
+@pytest.mark.parametrize("seed", range(24))
+def test_region_against_cycle_enumeration_on_cycle_soups(seed):
+    g = synth.odd_cycles_game([9, 12, 15][seed % 3], 6500 + seed,
+                              d=4 if seed % 2 else 0)
+    X = odd_region.odd_avoid_set(g)
+    R = odd_region.odd_cycle_region(g, X)
+    assert set(np.flatnonzero(R)) == _brute_region(g, X)
+    np.testing.assert_array_equal(odd_region.solve(g)["winner"], zielonka(g))
+
+
 def test_self_loops_and_even_cycles():
     # 0 (Odd, pri 3) -> 0 self loop: Odd wins alone
     # 1 (Odd, pri 2) <-> 2 (Odd, pri 0): an even cycle of Odd vertices only
@@ -108,7 +122,7 @@ def test_self_loops_and_even_cycles():
     assert r["sigma"][3] == 1 and r["sigma"][0] == -1 and r["tau"][0] == -1
 
 
-@pytest.mark.parametrize("i", range(54))
+@pytest.mark.parametrize("i", range(62))
 def test_attractor_closure_and_admissible_rest(i):
     g = _games()[i]
     r = odd_region.solve(g)
