@@ -328,9 +328,10 @@ def run_mix(n_games: int, oracle_budget_s: float = 10.0) -> dict:
         return len(res["results"]) == len(games)
 
     cap_v, cap_e = n_aug_total + 1, m_aug_total + 1
-    # calibration: every game present at t = 0
+    # calibration: every game present at t = 0 (submitted before the first
+    # step, so that every step holds every unfinished game)
     zeros = np.zeros(len(games))
-    rb = serve(games, zeros, cap_v, cap_e)
+    rb = serve(games, zeros, cap_v, cap_e, submit_thread=False)
     mu = len(games) / rb["makespan"]
     log(f"batched (all at t=0): {rb['makespan']:.2f}s, {mu:.1f} games/s, "
         f"{rb['steps']} steps")
@@ -338,13 +339,22 @@ def run_mix(n_games: int, oracle_budget_s: float = 10.0) -> dict:
     arr = poisson_arrivals(len(games), 1.5 * mu, 4242)
     budget_v = max(cap_v // 4, max(int(r["stats"]["n_aug"]) for r in solo) + 1)
     budget_e = max(cap_e // 4, max(int(r["stats"]["m_aug"]) for r in solo) + 1)
-    rs = serve(games, arr, budget_v, budget_e)
+    # submissions between steps (a submitter thread of its own lowers the
+    # latency only below the calibration rate and costs throughput above it)
+    rs = serve(games, arr, budget_v, budget_e, submit_thread=False)
     lat = rs["latency"]
     served = len(games) / rs["makespan"]
     log(f"served (Poisson 1.5 mu, quarter arena): {rs['makespan']:.2f}s, "
         f"{served:.1f} games/s, p50 {np.percentile(lat, 50) * 1e3:.1f} ms, "
         f"p99 {np.percentile(lat, 99) * 1e3:.1f} ms")
-    ident = same(rb) and same(rs)
+    # the same stream at the calibration rate: latency below saturation
+    arr1 = poisson_arrivals(len(games), mu, 4243)
+    r1 = serve(games, arr1, budget_v, budget_e, submit_thread=False)
+    lat1 = r1["latency"]
+    log(f"served (Poisson 1.0 mu): {len(games) / r1['makespan']:.1f} "
+        f"games/s, p50 {np.percentile(lat1, 50) * 1e3:.1f} ms, "
+        f"p99 {np.percentile(lat1, 99) * 1e3:.1f} ms")
+    ident = same(rb) and same(rs) and same(r1)
     # the method's least bytes over every iteration of every game
     mix_bytes = sum(
         method_min_bytes(int(r["stats"]["n_aug"]), int(r["stats"]["m_aug"]),
@@ -383,6 +393,11 @@ def run_mix(n_games: int, oracle_budget_s: float = 10.0) -> dict:
         "speedup_batched_vs_one_at_a_time": mu * t_solo / len(games),
         "identical_to_one_at_a_time": bool(ident),
         "served_steps": rs["steps"],
+        "at_calibration_rate": {
+            "arrivals": "Poisson, rate 1.0 x batched calibration rate",
+            "served_games_per_s": len(games) / r1["makespan"],
+            "latency_p50_ms": float(np.percentile(lat1, 50) * 1e3),
+            "latency_p99_ms": float(np.percentile(lat1, 99) * 1e3)},
         "roofline": {"bound": "hbm", "unit": "fraction of 8 TB/s",
                      "method_min_bytes_all_games": int(mix_bytes),
                      "served_frac": frac(rs["makespan"]),
@@ -425,6 +440,46 @@ def bench_mix(args) -> dict:
     }
 
 
+def odd_region_run(arrs, game: dict, winner_dummies, reps: int = 2) -> dict:
+    """The same game loaded with PG_ODD_REGION (Odd's own winning region
+    removed, no dummies): the reduced game's size and the per-iteration time
+    beside the dummy path's, after one untimed run.  The winners must be
+    those of the dummy path."""
+    import torch
+    from paper_1705_02313_amd.pg import Game
+    runs = []
+    for i in range(reps + 1):
+        torch.cuda.synchronize()
+        t_a = time.perf_counter()
+        g = Game(arrs["offsets"], arrs["targets"], arrs["owner"], arrs["pri"],
+                 n=game["n"], odd_region=True)
+        torch.cuda.synchronize()
+        t_b = time.perf_counter()
+        out = g.solve()
+        torch.cuda.synchronize()
+        t_c = time.perf_counter()
+        g.free()
+        if i:
+            runs.append((t_b - t_a, t_c - t_b, out["stats"]))
+    win = out["winner"].cpu().numpy()
+    if not np.array_equal(win, winner_dummies):
+        raise RuntimeError("PG_ODD_REGION winners differ from the dummy "
+                           "path's")
+    st = runs[0][2]
+    nval = int(st["n_valuations"])
+    solve_s = statistics.median(r[1] for r in runs)
+    it_ev = statistics.median(r[2]["iteration_ms"] for r in runs) / max(nval,
+                                                                        1)
+    return {"n_aug": int(st["n_aug"]), "m_aug": int(st["m_aug"]),
+            "removed": int(game["n"] - st["n_aug"]),
+            "n_major": int(st["n_major"]), "n_valuations": nval,
+            "load_seconds_median": statistics.median(r[0] for r in runs),
+            "solve_seconds_median": solve_s,
+            "ms_per_iteration": 1e3 * solve_s / max(nval, 1),
+            "event_ms_per_iteration": it_ev,
+            "winners_equal_dummy_path": True, "reps": reps}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -443,6 +498,9 @@ def main():
                          "GPU-LR split), to measure it against the device")
     ap.add_argument("--no-mix", action="store_true",
                     help="leave the batched/served mix out of a c2 run")
+    ap.add_argument("--no-odd-region", action="store_true",
+                    help="leave out the run that removes Odd's own region "
+                         "instead of inserting dummies (PG_ODD_REGION)")
     ap.add_argument("--mix-games", type=int, default=1024,
                     help="games in the batched/served workload")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -656,6 +714,9 @@ def main():
         "iteration_bytes": iteration_bytes,
         "kernels": kernels,
     }
+    if not args.no_odd_region and args.best_response == "si":
+        log("admissibility without dummies (PG_ODD_REGION)")
+        line["odd_region"] = odd_region_run(arrs, game, win)
     if args.workload == "c3":
         log("deep-list valuation")
         line["deep_list_valuation"] = deep_list_valuation(arrs, game["n"])

@@ -75,7 +75,9 @@ enum {
                                   host (the paper's GPU-LR split; below)     */
     PG_SWITCH_ROWS = 128u,  /* pg_load_csr: All_Odd reads rows (below)       */
     PG_SWITCH_BUCKETS = 256u,/* pg_load_csr: All_Odd by buckets (below)      */
-    PG_KEEP_DUMMIES = 512u  /* pg_solve: tau in the modified game's ids      */
+    PG_KEEP_DUMMIES = 512u, /* pg_solve: tau in the modified game's ids      */
+    PG_ODD_REGION = 1024u   /* pg_load_csr: admissibility without dummies
+                               (below)                                       */
 };
 
 /*
@@ -91,7 +93,8 @@ enum {
  *   priority  n int32 priorities, >= 0 (they may repeat; see below)
  *   flags     PG_PTR_DEVICE, PG_NO_PREPROCESS, PG_OFFSETS_I32,
  *             PG_CAREFUL_WALKS, PG_COUNT_VALUATION, PG_NO_GRAPH,
- *             PG_HOST_REDUCED_LIST, PG_SWITCH_ROWS, PG_SWITCH_BUCKETS
+ *             PG_HOST_REDUCED_LIST, PG_SWITCH_ROWS, PG_SWITCH_BUCKETS,
+ *             PG_ODD_REGION
  *
  * Two representations of valuations (section 3, "Valuations").  With
  * pairwise distinct priorities a finite valuation is the set of priorities
@@ -114,6 +117,24 @@ enum {
  * the original priorities are raised by 2 when there is a dummy.  Both keep
  * the order and parity of the original priorities below which the dummies
  * lie, so every winner is kept.
+ *
+ * PG_ODD_REGION replaces the dummies (section 3 offers them as one simple
+ * preprocessing, not the only one): from X the load computes R, the vertices of X
+ * from which Odd, moving inside X, reaches a cycle whose largest priority
+ * is odd (strongly connected components of X peeled on the device by
+ * colouring rounds), and A, Odd's attractor of R.  Odd wins A on its own;
+ * the stored game is the original one without A (rows lose their edges
+ * into A; ids renumbered in increasing original id), in which every
+ * all-Odd cycle has an even largest priority, so the initial strategy is
+ * admissible there and no dummy is needed.  n_aug, m_aug (pg_game_info,
+ * pg_stats) are that game's sizes (n_aug may be 0: Odd wins everything) and
+ * pg_export_game returns it.  Such a game takes pg_solve (and pg_stats,
+ * pg_count_info, pg_*_tuning, profiling) only: pg_valuation,
+ * pg_valuation_counts, pg_best_response and pg_initial_strategies give
+ * PG_EINVAL, and so does a batch.  With PG_NO_PREPROCESS: PG_EINVAL.  The
+ * colouring needs one round per level of the components' condensation
+ * (each round removes every colour's root), so a game whose X holds long
+ * chains of components loads slowly; the dummies stay the default.
  *
  * Every valuation first walks the play graph with a fixed number of device
  * rounds and falls back by itself to rounds driven from the host (each one
@@ -348,6 +369,12 @@ typedef struct pg_stats {
  *            pg_best_response and init_tau use)
  *   stats    nullable
  *
+ * For a game loaded with PG_ODD_REGION, winner, sigma and tau (and
+ * init_sigma, init_tau) have n entries in the original ids: a vertex of
+ * Odd's own region A has winner 1 and PG_SINK in sigma and tau, the others
+ * the results of the game without A, whose strategies never lead into A.
+ * A start strategy that chooses a vertex of A: PG_EINVAL.
+ *
  * When a cap stops the run (PG_EITERLIMIT: max_major outer iterations
  * done, or max_inner valuations in one best response), winner is not
  * written, but sigma and tau (when given) receive the strategies reached:
@@ -393,7 +420,8 @@ pg_status pg_profile_read(const pg_game *game, int32_t kind, const char **name,
  *                  pg_load_csr) and queues it; returns a ticket.  PG_ENOMEM
  *                  if the game alone exceeds the arena; PG_EINVAL for
  *                  repeated priorities (batches take games with rank
- *                  valuations only: the arena ranks all its games together).
+ *                  valuations only: the arena ranks all its games together,
+ *                  and for PG_ODD_REGION).
  *                  Queued games join the arena, first come first served, at
  *                  a step where they fit beside the games already in it.  A
  *                  game's memory comes from a pool that the batch keeps
@@ -464,7 +492,7 @@ pg_status pg_batch_free(pg_batch *batch);
  * sigma and tau (nullable) need room for n_aug entries, which the caller
  * does not know before the load: n_aug <= 2 n (one dummy at most per
  * original vertex), and stats->n_aug (when stats is given) says how many
- * were written.  The call returns after the stream has drained; outputs are
+ * were written; with PG_ODD_REGION n entries, as pg_solve.  The call returns after the stream has drained; outputs are
  * written then.
  */
 #define PG_NOALLOC_MAX_VERTICES 65536

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpgsi.so")
 SOURCES = ["pg_prims.hip", "pg_val.hip", "pg_count.hip", "pg_api.hip",
-           "pg_batch.hip", "pg_switch.hip", "pg_tune.hip"]
+           "pg_batch.hip", "pg_switch.hip", "pg_tune.hip", "pg_oddregion.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("PG_OFFLOAD_ARCH", "gfx950")

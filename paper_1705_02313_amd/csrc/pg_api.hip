@@ -1,5 +1,6 @@
 // The C ABI (include/pg.h): game loading and validation, the admissibility
 // preprocessing, strategy import/export and the loops of Algorithm 1.
+#include <algorithm>
 #include <chrono>
 #include <cstring>
 #include <string>
@@ -649,7 +650,7 @@ void free_game(pg_game *g) {
                   g->wl1,      g->rs,       g->sk0,      g->sv0,
                   g->sk1,      g->sv1,      g->tile_cnt, g->scan_tmp,
                   g->kids,     g->fh,       g->pos,      g->elem,
-                  g->aux,
+                  g->aux,      g->or_new,   g->or_orig,
                   g->ctr,      g->u64tmp,   g->cvals,    g->pidx,
                   g->cnt,      g->elem4,    g->rs1,      g->cnt2,
                   g->tsw_t,    g->tsw_slot, g->tsw_g,    g->tsw_tz,
@@ -882,6 +883,12 @@ pg_status load_modified(int64_t n, int64_t m, const void *offsets,
                            off_in, tgt_in, inx, xp, n, g->ctr);
       PG_TRY(sync_ctr(g, s));
       if (g->hctr[C_MISC] == 0) break;
+    }
+    if (flags & PG_ODD_REGION) {
+      // no dummies: the game without Odd's own winning region instead
+      g->odd_region = true;
+      return odd_region_reduce(g, s, n, m, off_in, tgt_in, own_in, pri_in,
+                               inx);
     }
     fill_i32((int32_t *)xp, 0, n, s);
     hipLaunchKernelGGL(k_xp_mark, dim3(grid_for(n)), dim3(kBlock), 0, s,
@@ -1162,6 +1169,9 @@ pg_status check_load_args(int64_t n, int64_t m, const void *offsets,
   if ((flags & PG_SWITCH_ROWS) && (flags & PG_SWITCH_BUCKETS))
     return pg_fail(PG_EINVAL,
                    "PG_SWITCH_ROWS and PG_SWITCH_BUCKETS exclude each other");
+  if ((flags & PG_ODD_REGION) && (flags & PG_NO_PREPROCESS))
+    return pg_fail(PG_EINVAL,
+                   "PG_ODD_REGION and PG_NO_PREPROCESS exclude each other");
   return PG_OK;
 }
 
@@ -1174,6 +1184,8 @@ pg_status load_game(int64_t n, int64_t m, const void *offsets,
   pg_status st =
       load_modified(n, m, offsets, targets, owner, priority, flags, s, g,
                     (flags & PG_COUNT_VALUATION) ? kLoadCount : kLoadAuto);
+  // Odd's own region may be the whole game: nothing left to solve
+  if (st == PG_OK && g->odd_region && g->n_aug == 0) return PG_OK;
   if (st == PG_OK) st = alloc_state(g, g->n_aug);
   if (st == PG_OK) st = finalize_state(g, s, true, !g->dense);
   if (st == PG_OK && g->dense) st = count_setup(g, s);
@@ -1206,6 +1218,30 @@ pg_status solve_game(pg_game *g, const pg_solve_opts *opts, uint8_t *winner,
 
 namespace {
 
+// pg_solve on a PG_ODD_REGION game that Odd's own region covers: Odd wins
+// every vertex and no strategy is left (PG_SINK everywhere)
+pg_status solve_all_removed(pg_game *g, uint8_t *winner, int32_t *sigma,
+                            int32_t *tau, pg_stats *stats, bool dev,
+                            hipStream_t s) {
+  const int64_t n = g->n;
+  if (dev) {
+    fill_u8(winner, 1, n, s);
+    if (sigma) fill_i32(sigma, PG_SINK, n, s);
+    if (tau) fill_i32(tau, PG_SINK, n, s);
+    PG_HIP(hipStreamSynchronize(s));
+  } else {
+    std::fill(winner, winner + n, uint8_t(1));
+    if (sigma) std::fill(sigma, sigma + n, int32_t(PG_SINK));
+    if (tau) std::fill(tau, tau + n, int32_t(PG_SINK));
+  }
+  if (stats) {
+    *stats = pg_stats{};
+    stats->n = g->n;
+    stats->m = g->m;
+  }
+  return PG_OK;
+}
+
 // pg_solve's work on a loaded game, allocating from the current pool.
 pg_status solve_game(pg_game *g, const pg_solve_opts *opts, uint8_t *winner,
                      int32_t *sigma, int32_t *tau, pg_stats *stats,
@@ -1221,11 +1257,42 @@ pg_status solve_game(pg_game *g, const pg_solve_opts *opts, uint8_t *winner,
   if (o.trace_cap < 0) return pg_fail(PG_EINVAL, "trace_cap < 0");
   const auto t0 = std::chrono::steady_clock::now();
   const int64_t N = g->n_aug;
+  if (g->odd_region && N == 0) return solve_all_removed(g, winner, sigma, tau,
+                                                        stats, dev, s);
+  // the reduced game's strategies and winners (PG_ODD_REGION): its own ids
+  struct OrBuf {
+    int32_t *s2 = nullptr, *t2 = nullptr;
+    uint8_t *w2 = nullptr;
+    ~OrBuf() {
+      dev_free(s2);
+      dev_free(t2);
+      dev_free(w2);
+    }
+  } ob;
+  if (g->odd_region) {
+    PG_TRY(dev_alloc(&ob.s2, N));
+    PG_TRY(dev_alloc(&ob.t2, N));
+    PG_TRY(dev_alloc(&ob.w2, N));
+  }
+  // sigma and tau out: directly, or through the reduced game's ids
+  auto strats_out = [&](bool report) -> pg_status {
+    if (!g->odd_region) return export_strats(g, sigma, tau, dev, s, report);
+    if (!sigma && !tau) return PG_OK;
+    PG_TRY(export_strats(g, sigma ? ob.s2 : nullptr, tau ? ob.t2 : nullptr,
+                         true, s, false));
+    return odd_region_strats_out(g, ob.s2, ob.t2, sigma, tau, dev, s);
+  };
   hipLaunchKernelGGL(k_sp_init, dim3(grid_for(N)), dim3(kBlock), 0, s, g->off,
                      g->tgt, g->owner, g->pri, g->sp, (int32_t)N);
   // warm start: the given strategies replace the initial ones
-  if (o.init_sigma || o.init_tau)
+  if ((o.init_sigma || o.init_tau) && g->odd_region) {
+    PG_TRY(odd_region_strats_in(g, o.init_sigma, o.init_tau, dev, s, ob.s2,
+                                ob.t2));
+    PG_TRY(import_strats(g, o.init_sigma ? ob.s2 : nullptr,
+                         o.init_tau ? ob.t2 : nullptr, true, s));
+  } else if (o.init_sigma || o.init_tau) {
     PG_TRY(import_strats(g, o.init_sigma, o.init_tau, dev, s));
+  }
   valuation_reset(g, s);
   Trace tr;
   tr.o = &o;
@@ -1291,17 +1358,23 @@ pg_status solve_game(pg_game *g, const pg_solve_opts *opts, uint8_t *winner,
   if (st == PG_EITERLIMIT) {
     // a checkpoint: the strategies reached, from which a warm start resumes
     const std::string err = pg_last_error();
-    PG_TRY(export_strats(g, sigma, tau, dev, s, report));
+    PG_TRY(strats_out(report));
     return pg_fail(st, err);
   }
   if (st != PG_OK) return st;
-  uint8_t *dw = winner;
-  if (!dev) dw = (uint8_t *)g->wl0;
-  hipLaunchKernelGGL(k_winner, dim3(grid_for(g->n)), dim3(kBlock), 0, s,
-                     g->rs, io_rvpos(g), dw, g->n);
-  if (!dev) PG_TRY(copy_out(winner, dw, g->n, false, s));
-  PG_HIP(hipStreamSynchronize(s));
-  PG_TRY(export_strats(g, sigma, tau, dev, s, report));
+  if (g->odd_region) {
+    hipLaunchKernelGGL(k_winner, dim3(grid_for(N)), dim3(kBlock), 0, s, g->rs,
+                       io_rvpos(g), ob.w2, N);
+    PG_TRY(odd_region_winner_out(g, ob.w2, winner, dev, s));
+  } else {
+    uint8_t *dw = winner;
+    if (!dev) dw = (uint8_t *)g->wl0;
+    hipLaunchKernelGGL(k_winner, dim3(grid_for(g->n)), dim3(kBlock), 0, s,
+                       g->rs, io_rvpos(g), dw, g->n);
+    if (!dev) PG_TRY(copy_out(winner, dw, g->n, false, s));
+    PG_HIP(hipStreamSynchronize(s));
+  }
+  PG_TRY(strats_out(report));
   const auto t1 = std::chrono::steady_clock::now();
   if (stats) stats->seconds = std::chrono::duration<double>(t1 - t0).count();
   return PG_OK;
@@ -1335,6 +1408,17 @@ pg_status scratch_address(int device, uint8_t **out) {
     g_scratch_dev[device] = (uint8_t *)ptr;
   }
   *out = g_scratch_dev[device];
+  return PG_OK;
+}
+}  // namespace
+
+namespace {
+// per-vertex arrays of the calls below are in the stored game's ids, which
+// for PG_ODD_REGION are not the caller's
+pg_status solve_only(const pg_game *g) {
+  if (g->odd_region)
+    return pg_fail(PG_EINVAL, "a game loaded with PG_ODD_REGION supports "
+                              "pg_solve (not the per-vertex calls)");
   return PG_OK;
 }
 }  // namespace
@@ -1441,6 +1525,7 @@ pg_status pg_export_game(const pg_game *gc, int64_t *offsets, int32_t *targets,
 pg_status pg_initial_strategies(pg_game *g, int32_t *sigma, int32_t *tau,
                                 uint32_t flags, void *hip_stream) {
   if (!g) return pg_fail(PG_EINVAL, "game is NULL");
+  PG_TRY(solve_only(g));
   DevGuard guard(g->device);
   hipStream_t s = (hipStream_t)hip_stream;
   const bool dev = flags & PG_PTR_DEVICE;
@@ -1462,6 +1547,7 @@ pg_status pg_valuation(pg_game *g, const int32_t *sigma, const int32_t *tau,
                        int32_t *key, int64_t *n_finite, uint32_t flags,
                        void *hip_stream) {
   if (!g) return pg_fail(PG_EINVAL, "game is NULL");
+  PG_TRY(solve_only(g));
   if (!sigma || !tau || !key) return pg_fail(PG_EINVAL, "NULL argument");
   if (g->dense)
     return pg_fail(PG_EINVAL, "a count-valuation game has no rank keys: use "
@@ -1484,6 +1570,7 @@ pg_status pg_valuation_counts(pg_game *g, const int32_t *sigma,
                               uint8_t *top, int64_t *n_finite, uint32_t flags,
                               void *hip_stream) {
   if (!g) return pg_fail(PG_EINVAL, "game is NULL");
+  PG_TRY(solve_only(g));
   if (!sigma || !tau || !counts) return pg_fail(PG_EINVAL, "NULL argument");
   if (!g->dense)
     return pg_fail(PG_EINVAL, "not a count-valuation game: use pg_valuation");
@@ -1503,6 +1590,7 @@ pg_status pg_best_response(pg_game *g, const int32_t *sigma, int32_t *tau,
                            int32_t max_inner, uint32_t flags,
                            void *hip_stream) {
   if (!g) return pg_fail(PG_EINVAL, "game is NULL");
+  PG_TRY(solve_only(g));
   if (!sigma || !tau) return pg_fail(PG_EINVAL, "NULL argument");
   if (key && g->dense)
     return pg_fail(PG_EINVAL, "a count-valuation game has no rank keys: "

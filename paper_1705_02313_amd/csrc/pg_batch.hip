@@ -155,12 +155,15 @@ __global__ void k_arena_save(const GameDesc *__restrict__ d,
 
 // results of the games that finished in this step, in the caller's ids
 // (Theorem 1: W_Even is the set of top keys), as pg_solve gives them
+// (all kernels after the valuation return at once when its bounded walks
+// left vertices open: the host then redoes the step on the careful path)
 __global__ void k_arena_export(const GameDesc *__restrict__ d,
                                const int32_t *__restrict__ gid,
                                const uint8_t *__restrict__ newly_done,
                                const int2 *sp, const int32_t *key,
                                const uint8_t *owner, int32_t N,
-                               int64_t odd_total) {
+                               int64_t odd_total, const int32_t *ctr) {
+  if (ctr[C_ABORT]) return;
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= N) return;
   const int s = gid[v];
@@ -260,7 +263,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_even(
     const int64_t *__restrict__ off, const int32_t *__restrict__ tgt,
     const int32_t *__restrict__ key, const int32_t *__restrict__ pri, int2 *sp,
     const int32_t *__restrict__ gid, const uint8_t *__restrict__ pending,
-    int32_t *cnt) {
+    int32_t *cnt, const int32_t *ctr) {
+  if (ctr[C_ABORT]) return;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool sw = false;
   int s = 0;
@@ -301,7 +305,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_even(
 // loop and starts an All_Even step (one more outer iteration).
 __global__ void k_batch_ctl1(int G, const uint8_t *run, const int32_t *cnt_odd,
                              uint8_t *pending, int32_t *n_val,
-                             int32_t *n_major) {
+                             int32_t *n_major, const int32_t *ctr) {
+  if (ctr[C_ABORT]) return;
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= G) return;
   pending[s] = 0;
@@ -317,7 +322,8 @@ __global__ void k_batch_ctl1(int G, const uint8_t *run, const int32_t *cnt_odd,
 __global__ void k_batch_ctl2(int G, uint8_t *run, uint8_t *pending,
                              int32_t *cnt_odd, int32_t *cnt_even,
                              int64_t *sw_odd, int64_t *sw_even,
-                             uint8_t *newly_done) {
+                             uint8_t *newly_done, const int32_t *ctr) {
+  if (ctr[C_ABORT]) return;
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= G) return;
   newly_done[s] = 0;
@@ -410,6 +416,17 @@ struct pg_batch {
   int32_t *d_nval = nullptr, *d_nmaj = nullptr;
   int64_t *d_sw_odd = nullptr, *d_sw_even = nullptr;
   int32_t *d_i32 = nullptr;        // scratch
+  // a step (walks, valuation, switches, control, export, the results to
+  // h_res) captured per arena layout and ng/cand pair; dropped at rebuild
+  hipGraphExec_t step_exec[2] = {nullptr, nullptr};
+  bool use_graph = true;
+  // steps since the last rebuild: a layout is captured only once it has
+  // served kEagerSteps steps (admissions under a steady stream rebuild
+  // every few steps, and a capture costs about as much as a step)
+  int64_t steps_in_layout = 0;
+  // pinned: per slot newly finished (G bytes, then padding to 8), n_val,
+  // n_major (4 G each), Odd and Even switches (8 G each)
+  uint8_t *h_res = nullptr;
   // host mirrors and staging
   std::vector<GameDesc> h_desc;
   std::vector<int64_t> h_pstart, h_estart;
@@ -419,6 +436,23 @@ struct pg_batch {
 };
 
 namespace {
+
+// the pinned result block of a step (see pg_batch::h_res)
+size_t res_off_nval(int G) { return ((size_t)G + 7) & ~size_t(7); }
+size_t res_off_nmaj(int G) { return res_off_nval(G) + 4 * (size_t)G; }
+size_t res_off_swodd(int G) {
+  return (res_off_nmaj(G) + 4 * (size_t)G + 7) & ~size_t(7);
+}
+size_t res_off_sweven(int G) { return res_off_swodd(G) + 8 * (size_t)G; }
+size_t res_bytes(int G) { return res_off_sweven(G) + 8 * (size_t)G; }
+
+void drop_step_graphs(pg_batch *b) {
+  for (hipGraphExec_t &ex : b->step_exec)
+    if (ex) {
+      (void)hipGraphExecDestroy(ex);
+      ex = nullptr;
+    }
+}
 
 pg_status batch_alloc(pg_batch *b) {
   pg_game *a = new (std::nothrow) pg_game();
@@ -455,6 +489,7 @@ pg_status batch_alloc(pg_batch *b) {
   b->h_nmaj.resize(G);
   b->h_sw_odd.resize(G);
   b->h_sw_even.resize(G);
+  PG_HIP(hipHostMalloc((void **)&b->h_res, res_bytes(G), hipHostMallocDefault));
   return PG_OK;
 }
 
@@ -470,6 +505,8 @@ void batch_release(pg_batch *b) {
     for (BGame *g : b->grave) free_bgame(g);
   }
   b->pool.clear();
+  drop_step_graphs(b);
+  if (b->h_res) (void)hipHostFree(b->h_res);
   free_game(b->arena);
   void *ptrs[] = {b->d_desc,    b->d_estart,  b->d_pstart,
                   b->d_gid,
@@ -488,6 +525,8 @@ void batch_release(pg_batch *b) {
 pg_status rebuild(pg_batch *b, bool *built_any) {
   hipStream_t s = b->stream;
   pg_game *a = b->arena;
+  drop_step_graphs(b);   // the arena's sizes and slots change
+  b->steps_in_layout = 0;
   {
     PoolScope ps(&b->pool);
     for (BGame *g : b->grave) free_bgame(g);
@@ -644,6 +683,104 @@ pg_status rebuild(pg_batch *b, bool *built_any) {
   return PG_OK;
 }
 
+// The kernels of a step after the valuation: All_Odd of every live game,
+// the inner-loop control, All_Even of the games whose All_Odd switched
+// nothing, the outer-loop control, the results of games that finished, and
+// the per-slot counts and the counters to the host (h_res, hctr).
+void enqueue_step_rest(pg_batch *b, hipStream_t s) {
+  pg_game *a = b->arena;
+  const int G = (int)b->built.size();
+  const int32_t N = (int32_t)a->n_aug;
+  if (a->n_odd > 0)
+    hipLaunchKernelGGL(k_batch_odd, dim3(grid_for(a->n_odd)), dim3(kBlock), 0,
+                       s, a->n_odd, a->odd_ids, a->off, a->tgt, a->key,
+                       a->pri, a->sp, b->d_gid, b->d_run, b->d_cnt_odd,
+                       a->ctr);
+  hipLaunchKernelGGL(k_batch_ctl1, dim3(grid_for(G)), dim3(kBlock), 0, s, G,
+                     b->d_run, b->d_cnt_odd, b->d_pending, b->d_nval,
+                     b->d_nmaj, a->ctr);
+  const int64_t ne = N - a->n_odd;
+  if (ne > 0)
+    hipLaunchKernelGGL(k_batch_even, dim3(grid_for(ne)), dim3(kBlock), 0, s,
+                       N, ne, a->even_ids, a->off, a->tgt, a->key, a->pri,
+                       a->sp, b->d_gid, b->d_pending, b->d_cnt_even, a->ctr);
+  hipLaunchKernelGGL(k_batch_ctl2, dim3(grid_for(G)), dim3(kBlock), 0, s, G,
+                     b->d_run, b->d_pending, b->d_cnt_odd, b->d_cnt_even,
+                     b->d_sw_odd, b->d_sw_even, b->d_newly, a->ctr);
+  hipLaunchKernelGGL(k_arena_export, dim3(grid_for(N)), dim3(kBlock), 0, s,
+                     b->d_desc, b->d_gid, b->d_newly, a->sp, a->key, a->owner,
+                     N, (int64_t)a->n_oddpri, a->ctr);
+  uint8_t *r = b->h_res;
+  (void)hipMemcpyAsync(r, b->d_newly, G, hipMemcpyDeviceToHost, s);
+  (void)hipMemcpyAsync(r + res_off_nval(G), b->d_nval, 4 * (size_t)G,
+                       hipMemcpyDeviceToHost, s);
+  (void)hipMemcpyAsync(r + res_off_nmaj(G), b->d_nmaj, 4 * (size_t)G,
+                       hipMemcpyDeviceToHost, s);
+  (void)hipMemcpyAsync(r + res_off_swodd(G), b->d_sw_odd, 8 * (size_t)G,
+                       hipMemcpyDeviceToHost, s);
+  (void)hipMemcpyAsync(r + res_off_sweven(G), b->d_sw_even, 8 * (size_t)G,
+                       hipMemcpyDeviceToHost, s);
+  (void)hipMemcpyAsync(a->hctr, a->ctr, sizeof(int32_t) * C_COUNT,
+                       hipMemcpyDeviceToHost, s);
+}
+
+// One step of every live game: replayed from the graph of the current
+// layout and ng/cand pair (captured at first use after each rebuild), else
+// launched one kernel at a time; one host synchronisation.  When the bounded
+// walks left vertices open, the careful walks, the valuation and the rest
+// of the step run again (the gated kernels did nothing).
+constexpr int64_t kEagerSteps = 2;
+
+pg_status step_device(pg_batch *b, hipStream_t s) {
+  pg_game *a = b->arena;
+  bool ran = false;
+  if (b->use_graph && b->steps_in_layout++ >= kEagerSteps) {
+    hipGraphExec_t &ex = b->step_exec[a->par];
+    if (!ex) {
+      if (!a->cap_stream &&
+          hipStreamCreateWithFlags(&a->cap_stream, hipStreamNonBlocking) !=
+              hipSuccess) {
+        a->cap_stream = nullptr;
+        b->use_graph = false;
+      }
+      hipStream_t cs = a->cap_stream;
+      hipError_t e = cs ? hipStreamBeginCapture(
+                              cs, hipStreamCaptureModeThreadLocal)
+                        : hipErrorInvalidValue;
+      if (e == hipSuccess) {
+        enqueue_valuation(a, cs);
+        enqueue_step_rest(b, cs);
+        hipGraph_t gr = nullptr;
+        e = hipStreamEndCapture(cs, &gr);
+        if (e == hipSuccess)
+          e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+        if (gr) (void)hipGraphDestroy(gr);
+      }
+      if (e != hipSuccess) {   // capture refused: launch eagerly from now on
+        ex = nullptr;
+        b->use_graph = false;
+        (void)hipGetLastError();
+      }
+    }
+    if (ex) {
+      PG_HIP(hipGraphLaunch(ex, s));
+      ran = true;
+    }
+  }
+  if (!ran) {
+    enqueue_valuation(a, s);
+    enqueue_step_rest(b, s);
+  }
+  PG_HIP(hipStreamSynchronize(s));
+  if (a->hctr[C_ABORT]) {
+    PG_TRY(redo_valuation(a, s));
+    enqueue_step_rest(b, s);
+    PG_HIP(hipStreamSynchronize(s));
+  }
+  a->par ^= 1;
+  return valuation_status(a);
+}
+
 }  // namespace
 
 extern "C" {
@@ -681,6 +818,8 @@ pg_status pg_batch_submit(pg_batch *b, int64_t n, int64_t m,
                           uint32_t flags, int64_t *ticket) {
   if (!b || !ticket) return pg_fail(PG_EINVAL, "NULL argument");
   if (n < 1 || m < n) return pg_fail(PG_EINVAL, "need n >= 1 and m >= n");
+  if (flags & PG_ODD_REGION)
+    return pg_fail(PG_EINVAL, "a batch does not take PG_ODD_REGION games");
   hipStream_t s = b->sub_stream;
   PoolScope ps(&b->pool);   // the game's memory comes from the batch's pool
   BGame *bg = new (std::nothrow) BGame();
@@ -867,38 +1006,15 @@ pg_status pg_batch_step(pg_batch *b, int32_t *n_live, int32_t *n_queued,
   bool live = false;
   for (BGame *g : b->built) live |= g->state == B_LIVE;
   if (live) {
-    PG_TRY(valuation_device(a, s, nullptr));
-    const int32_t N = (int32_t)a->n_aug;
-    if (a->n_odd > 0)
-      hipLaunchKernelGGL(k_batch_odd, dim3(grid_for(a->n_odd)), dim3(kBlock), 0,
-                         s, a->n_odd, a->odd_ids, a->off, a->tgt, a->key,
-                         a->pri, a->sp, b->d_gid, b->d_run, b->d_cnt_odd,
-                         a->ctr);
-    hipLaunchKernelGGL(k_batch_ctl1, dim3(grid_for(G)), dim3(kBlock), 0, s, G,
-                       b->d_run, b->d_cnt_odd, b->d_pending, b->d_nval,
-                       b->d_nmaj);
-    const int64_t ne = N - a->n_odd;
-    if (ne > 0)
-      hipLaunchKernelGGL(k_batch_even, dim3(grid_for(ne)), dim3(kBlock), 0, s,
-                         N, ne, a->even_ids, a->off, a->tgt, a->key, a->pri,
-                         a->sp, b->d_gid, b->d_pending, b->d_cnt_even);
-    hipLaunchKernelGGL(k_batch_ctl2, dim3(grid_for(G)), dim3(kBlock), 0, s, G,
-                       b->d_run, b->d_pending, b->d_cnt_odd, b->d_cnt_even,
-                       b->d_sw_odd, b->d_sw_even, b->d_newly);
-    hipLaunchKernelGGL(k_arena_export, dim3(grid_for(N)), dim3(kBlock), 0, s,
-                       b->d_desc, b->d_gid, b->d_newly, a->sp, a->key,
-                       a->owner, N, (int64_t)a->n_oddpri);
-    PG_HIP(hipMemcpyAsync(b->h_newly.data(), b->d_newly, G,
-                          hipMemcpyDeviceToHost, s));
-    PG_HIP(hipMemcpyAsync(b->h_nval.data(), b->d_nval, 4 * (size_t)G,
-                          hipMemcpyDeviceToHost, s));
-    PG_HIP(hipMemcpyAsync(b->h_nmaj.data(), b->d_nmaj, 4 * (size_t)G,
-                          hipMemcpyDeviceToHost, s));
-    PG_HIP(hipMemcpyAsync(b->h_sw_odd.data(), b->d_sw_odd, 8 * (size_t)G,
-                          hipMemcpyDeviceToHost, s));
-    PG_HIP(hipMemcpyAsync(b->h_sw_even.data(), b->d_sw_even, 8 * (size_t)G,
-                          hipMemcpyDeviceToHost, s));
-    PG_HIP(hipStreamSynchronize(s));
+    PG_TRY(step_device(b, s));
+    const uint8_t *r = b->h_res;
+    for (int i = 0; i < G; ++i) {
+      b->h_newly[i] = r[i];
+      b->h_nval[i] = ((const int32_t *)(r + res_off_nval(G)))[i];
+      b->h_nmaj[i] = ((const int32_t *)(r + res_off_nmaj(G)))[i];
+      b->h_sw_odd[i] = ((const int64_t *)(r + res_off_swodd(G)))[i];
+      b->h_sw_even[i] = ((const int64_t *)(r + res_off_sweven(G)))[i];
+    }
     for (int i = 0; i < G; ++i) {
       BGame *g = b->built[i];
       if (g->state != B_LIVE) continue;

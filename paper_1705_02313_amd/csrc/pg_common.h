@@ -183,6 +183,13 @@ struct pg_game {
   // and the two only translate vertex ids at the C ABI.
   int32_t *perm = nullptr;  // [n_aug]
   bool relabeled = false;
+  // PG_ODD_REGION: the stored game is the original one minus Odd's own
+  // winning region A (pg_oddregion.hip); or_new[v] is vertex v's id in it
+  // (-1 for A), or_orig[u] the original id of its vertex u
+  bool odd_region = false;
+  int64_t or_removed = 0;     // |A|
+  int32_t *or_new = nullptr;  // [n]
+  int32_t *or_orig = nullptr; // [n_aug]
 
   // play graph and valuation state
   // [n_aug+1] {successor (the sink is n_aug), priority of that successor}
@@ -388,6 +395,14 @@ void apply_tuning(pg_game *g, const pg_tuning &t);
 void valuation_reset(pg_game *g, hipStream_t s);
 // One valuation of the play graph held in g->sp; writes g->key.
 pg_status valuation_device(pg_game *g, hipStream_t s, int64_t *n_finite_out);
+// The walks and the valuation of g->sp with no host synchronisation (for
+// graph capture); the counters are not read back.
+void enqueue_valuation(pg_game *g, hipStream_t s);
+// After a valuation whose bounded walks left vertices open (C_ABORT read
+// back into g->hctr): the host-driven walks and the valuation again.
+pg_status redo_valuation(pg_game *g, hipStream_t s);
+// The error bits of the counters read back in g->hctr, as a status.
+pg_status valuation_status(pg_game *g);
 // One All_Odd (odd = true) or All_Even step on g->sp from g->key.
 pg_status switch_device(pg_game *g, bool odd, hipStream_t s, int32_t *count);
 // One best-response iteration (valuation, then All_Odd) with a single
@@ -533,6 +548,27 @@ pg_status load_modified(int64_t n, int64_t m, const void *offsets,
                         const int32_t *targets, const uint8_t *owner,
                         const int32_t *priority, uint32_t flags, hipStream_t s,
                         pg_game *g, LoadMode mode);
+// PG_ODD_REGION (pg_oddregion.hip): from X (inx, the vertices from which
+// Odd avoids Even forever) and the validated input copies, builds the game
+// without Odd's own winning region in g->off, g->tgt, g->owner, g->pri and
+// the id maps g->or_new, g->or_orig; g->n_aug may be 0
+pg_status odd_region_reduce(pg_game *g, hipStream_t s, int64_t n, int64_t m,
+                            const int64_t *off, const int32_t *tgt,
+                            const uint8_t *owner, const int32_t *pri,
+                            const uint8_t *inx);
+// strategies in original ids (n entries, host or device) to the reduced
+// game's ids (device, n_aug entries; an entry naming a removed vertex or out
+// of range becomes INT32_MAX, which import_strats rejects); and back (a
+// removed vertex gets PG_SINK in both)
+pg_status odd_region_strats_in(pg_game *g, const int32_t *sigma,
+                               const int32_t *tau, bool dev, hipStream_t s,
+                               int32_t *s2, int32_t *t2);
+pg_status odd_region_strats_out(pg_game *g, const int32_t *s2,
+                                const int32_t *t2, int32_t *sigma,
+                                int32_t *tau, bool dev, hipStream_t s);
+// winners of the reduced game (device) to the original ids (removed: Odd)
+pg_status odd_region_winner_out(pg_game *g, const uint8_t *w2,
+                                uint8_t *winner, bool dev, hipStream_t s);
 // distinct: reject repeated priorities (rank valuations)
 pg_status finalize_state(pg_game *g, hipStream_t s, bool init_sp,
                          bool distinct = true);

@@ -73,6 +73,8 @@ pg_status pg_set_tuning(pg_game *g, const pg_tuning *t) {
   if (!g || !t) return pg_fail(PG_EINVAL, "NULL argument");
   if (g->dense)
     return pg_fail(PG_EINVAL, "tuning applies to rank valuations");
+  if (g->n_aug == 0)
+    return pg_fail(PG_EINVAL, "no vertex is left to solve in this game");
   if (!pgk::tuning_valid(*t))
     return pg_fail(PG_EINVAL, "a tuning value is outside its range");
   // a graph may still run on the game's stream: drain it before the

@@ -1096,6 +1096,20 @@ static pg_status run_valuation(pg_game *g, hipStream_t s, bool odd_switch,
   return PG_OK;
 }
 
+void enqueue_valuation(pg_game *g, hipStream_t s) {
+  g->nlevels = g->dense ? count_levels(g->n_aug, g->dw)
+                        : plan_levels(g->n_aug, g->tune.stride0);
+  enqueue_walks(g, s);
+  enqueue_values(g, s);
+}
+
+pg_status redo_valuation(pg_game *g, hipStream_t s) {
+  PG_TRY(careful_walks(g, s));
+  return values(g, s);
+}
+
+pg_status valuation_status(pg_game *g) { return check_ctr(g); }
+
 pg_status valuation_device(pg_game *g, hipStream_t s, int64_t *n_finite_out) {
   return run_valuation(g, s, false, nullptr, n_finite_out);
 }

@@ -25,6 +25,7 @@ PG_CAREFUL_WALKS, PG_COUNT_VALUATION, PG_NO_GRAPH = 8, 16, 32
 PG_HOST_REDUCED_LIST = 64
 PG_SWITCH_ROWS, PG_SWITCH_BUCKETS = 128, 256
 PG_KEEP_DUMMIES = 512
+PG_ODD_REGION = 1024
 PG_BR_SI, PG_BR_SI_RESET, PG_BR_BELLMAN_FORD = 0, 1, 2
 PG_NOALLOC_MAX_VERTICES, PG_NOALLOC_MAX_EDGES = 65536, 1048576
 
@@ -266,14 +267,17 @@ class Game:
     ``count_valuation=True`` PG_COUNT_VALUATION, ``graph=False``
     PG_NO_GRAPH, ``host_reduced_list=True`` PG_HOST_REDUCED_LIST,
     ``switch="rows"`` PG_SWITCH_ROWS and ``switch="buckets"``
-    PG_SWITCH_BUCKETS; ``switch=None`` lets the library choose by size).
-    Games whose priorities repeat use count valuations by themselves
-    (``self.d > 0``)."""
+    PG_SWITCH_BUCKETS; ``switch=None`` lets the library choose by size;
+    ``odd_region=True`` PG_ODD_REGION: Odd's own winning region is removed
+    instead of inserting dummies, and solve() then takes and returns n
+    entries in the original ids).  Games whose priorities repeat use count
+    valuations by themselves (``self.d > 0``)."""
 
     def __init__(self, offsets, targets, owner, priority, n: int = None,
                  preprocess: bool = True, careful_walks: bool = False,
                  count_valuation: bool = False, graph: bool = True,
-                 host_reduced_list: bool = False, switch: str = None):
+                 host_reduced_list: bool = False, switch: str = None,
+                 odd_region: bool = False):
         if switch not in (None, "rows", "buckets"):
             raise ValueError("switch must be None, 'rows' or 'buckets'")
         device = _is_torch(targets)
@@ -306,13 +310,15 @@ class Game:
             (0 if graph else PG_NO_GRAPH) | \
             (PG_HOST_REDUCED_LIST if host_reduced_list else 0) | \
             {None: 0, "rows": PG_SWITCH_ROWS,
-             "buckets": PG_SWITCH_BUCKETS}[switch]
+             "buckets": PG_SWITCH_BUCKETS}[switch] | \
+            (PG_ODD_REGION if odd_region else 0)
         h = ctypes.c_void_p()
         _check(lib().pg_load_csr(n, m, _ptr(offsets), _ptr(targets),
                                  _ptr(owner), _ptr(priority), flags,
                                  _stream(device), ctypes.byref(h)))
         self._h = h
         self.device = device
+        self.odd_region = bool(odd_region)
         vals = [ctypes.c_int64() for _ in range(4)]
         _check(lib().pg_game_info(self._h, *[ctypes.byref(v) for v in vals]))
         self.n, self.m, self.n_aug, self.m_aug = [int(v.value) for v in vals]
@@ -326,11 +332,12 @@ class Game:
     def from_dict(cls, g: dict, device: bool = False, preprocess: bool = True,
                   careful_walks: bool = False, count_valuation: bool = False,
                   graph: bool = True, host_reduced_list: bool = False,
-                  switch: str = None):
+                  switch: str = None, odd_region: bool = False):
         kw = {"n": int(g["n"]), "preprocess": preprocess,
               "careful_walks": careful_walks,
               "count_valuation": count_valuation, "graph": graph,
-              "host_reduced_list": host_reduced_list, "switch": switch}
+              "host_reduced_list": host_reduced_list, "switch": switch,
+              "odd_region": odd_region}
         if device:
             import torch
             t = {k: torch.from_numpy(np.ascontiguousarray(g[k])).cuda()
@@ -443,8 +450,9 @@ class Game:
                                                   "switches", "ms")]
                            if tr else [None] * 4))
         winner = self._out(self.n, np.uint8)
-        sigma = self._out(self.n_aug, np.int32)
-        tau = self._out(self.n_aug, np.int32)
+        ns = self.n if self.odd_region else self.n_aug
+        sigma = self._out(ns, np.int32)
+        tau = self._out(ns, np.int32)
         st = Stats()
         rc = lib().pg_solve(self._h, ctypes.byref(opts), _ptr(winner),
                             _ptr(sigma), _ptr(tau), ctypes.byref(st),

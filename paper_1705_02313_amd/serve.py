@@ -1,15 +1,19 @@
 """Continuous-batching request loop over the batch C ABI.
 
-Requests (games) arrive over time.  The loop hands every arrived game to the
-batch, which admits queued games first come first served as arena space
-(the HBM-footprint budget given at creation) frees up, advances every game in
-the arena by one best-response iteration per step, and reports finished
+Requests (games) arrive over time.  A submitter thread hands every game to
+the batch when it arrives (validation and preprocessing run on the batch's
+submission stream, pg_batch_submit), while the loop advances every game in
+the arena by one best-response iteration per step (pg_batch_step, which
+admits queued games first come first served as arena space -- the
+HBM-footprint budget given at creation -- frees up) and collects finished
 games, whose latency is completion time minus arrival time.  Games that
 arrive while others are being solved join the next step that has room for
-them: their work overlaps with the games already on the device.
+them: their preprocessing and then their work overlap with the games
+already on the device.
 """
 from __future__ import annotations
 
+import threading
 import time
 
 import numpy as np
@@ -18,9 +22,15 @@ from .pg import Batch
 
 
 def serve(games, arrivals, max_vertices: int, max_edges: int,
-          keep_results: bool = True, clock=time.perf_counter) -> dict:
-    """Solves `games` arriving at `arrivals` (seconds from the start, sorted).
+          keep_results: bool = True, clock=time.perf_counter,
+          submit_thread: bool = False) -> dict:
+    """Solves `games` arriving at `arrivals` (seconds from the start).
 
+    Without `submit_thread` (default) the loop submits the games that have
+    arrived between steps, so each step sees every game that arrived before
+    it; with it submissions run on a thread of their own, overlapping the
+    steps (lower latency below saturation, fewer games per second near it:
+    the steps then hold fewer games each).
     Returns {"results": {i: result dict}, "latency": [...], "arrival",
     "completion", "makespan", "steps"}.
     """
@@ -30,32 +40,75 @@ def serve(games, arrivals, max_vertices: int, max_edges: int,
     completion = np.full(n, np.nan)
     results = {}
     ticket_of = {}
-    nxt = 0
+    lock = threading.Lock()
+    submitted = threading.Event()   # set after every submission
+    state = {"count": 0, "error": None}
     steps = 0
     with Batch(max_vertices, max_edges) as b:
         t0 = clock()
+
+        def submit(i):
+            t = b.submit(games[i])
+            with lock:
+                ticket_of[t] = i
+                state["count"] += 1
+            submitted.set()
+
+        def submitter():
+            try:
+                for k in range(n):
+                    i = int(order[k])
+                    wait = arrivals[i] - (clock() - t0)
+                    if wait > 0:
+                        time.sleep(wait)
+                    submit(i)
+            except Exception as e:   # reported by the loop
+                state["error"] = e
+                submitted.set()
+
+        th = None
+        nxt = 0
+        if submit_thread:
+            th = threading.Thread(target=submitter, daemon=True)
+            th.start()
         done = 0
-        while done < n:
-            now = clock() - t0
-            # admit every request that has arrived by now
-            while nxt < n and arrivals[order[nxt]] <= now:
-                i = int(order[nxt])
-                ticket_of[b.submit(games[i])] = i
-                nxt += 1
-            info_live, queued, _ = b.step()
-            steps += 1
-            for t in b.finished():
-                r = b.poll(t)
-                i = ticket_of.pop(t)
-                completion[i] = clock() - t0
-                if keep_results:
-                    results[i] = r
-                done += 1
-            if info_live == 0 and queued == 0 and nxt < n and done < n:
-                # idle until the next arrival
-                wait = arrivals[order[nxt]] - (clock() - t0)
-                if wait > 0:
-                    time.sleep(min(wait, 0.05))
+        try:
+            while done < n:
+                if state["error"] is not None:
+                    raise state["error"]
+                if th is None:
+                    # admit every request that has arrived by now
+                    now = clock() - t0
+                    while nxt < n and arrivals[order[nxt]] <= now:
+                        submit(int(order[nxt]))
+                        nxt += 1
+                info_live, queued, _ = b.step()
+                steps += 1
+                for t in b.finished():
+                    r = b.poll(t)
+                    while True:
+                        with lock:
+                            i = ticket_of.pop(t, None)
+                        if i is not None:
+                            break
+                        time.sleep(1e-5)   # the submitter is storing it
+                    completion[i] = clock() - t0
+                    if keep_results:
+                        results[i] = r
+                    done += 1
+                if info_live == 0 and queued == 0 and done < n:
+                    # idle until the next submission
+                    if th is None:
+                        if nxt < n:
+                            wait = arrivals[order[nxt]] - (clock() - t0)
+                            if wait > 0:
+                                time.sleep(min(wait, 0.05))
+                    else:
+                        submitted.wait(0.05)
+                        submitted.clear()
+        finally:
+            if th is not None:
+                th.join()
         makespan = clock() - t0
     latency = completion - arrivals
     return {"results": results, "latency": latency, "arrival": arrivals,

@@ -151,3 +151,20 @@ def test_submissions_from_another_thread():
     assert len(out) == len(games)
     for g, t in zip(games, tickets):
         _check(g, out[t])
+
+
+@pytest.mark.parametrize("thread", [True, False])
+def test_serve_with_and_without_a_submitter_thread(thread):
+    """serve(): submissions on their own thread (overlapping the steps) or
+    between steps; either way every game's result is the oracle's."""
+    from paper_1705_02313_amd.serve import poisson_arrivals, serve
+    games = _mix(20, 7300)
+    nv = sum(int(g["n"]) for g in games)
+    ne = sum(int(g["m"]) for g in games)
+    arr = poisson_arrivals(len(games), 400.0, 7301)
+    r = serve(games, arr, nv // 2 + 40000, ne // 2 + 200000,
+              submit_thread=thread)
+    assert len(r["results"]) == len(games)
+    assert (r["latency"] >= 0).all()
+    for i, g in enumerate(games):
+        _check(g, r["results"][i])

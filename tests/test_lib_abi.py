@@ -126,3 +126,29 @@ def test_tuning_table_is_ordered_and_valid():
         assert 8 <= t["walk_round"] <= 256
         assert 1 <= t["walk_rounds"] <= 8
         assert t["walk_block"] in (64, 128, 256)
+
+
+def test_odd_region_flag_conflict_is_refused_before_the_device():
+    """PG_ODD_REGION with PG_NO_PREPROCESS is refused by the argument checks,
+    which run before any device call."""
+    import numpy as np
+    from paper_1705_02313_amd import pg
+    consts = header_constants()
+    assert consts["PG_ODD_REGION"] == pg.PG_ODD_REGION
+    flags = [consts[k] for k in consts if k.startswith("PG_") and k in (
+        "PG_PTR_DEVICE", "PG_NO_PREPROCESS", "PG_OFFSETS_I32",
+        "PG_CAREFUL_WALKS", "PG_COUNT_VALUATION", "PG_NO_GRAPH",
+        "PG_HOST_REDUCED_LIST", "PG_SWITCH_ROWS", "PG_SWITCH_BUCKETS",
+        "PG_KEEP_DUMMIES", "PG_ODD_REGION")]
+    assert len(set(flags)) == len(flags) == 11
+    off = np.array([0, 1, 2], np.int64)
+    tgt = np.array([1, 0], np.int32)
+    own = np.array([1, 1], np.uint8)
+    pri = np.array([0, 1], np.int32)
+    h = ctypes.c_void_p()
+    L = pg.lib()
+    rc = L.pg_load_csr(2, 2, pg._ptr(off), pg._ptr(tgt), pg._ptr(own),
+                       pg._ptr(pri), pg.PG_ODD_REGION | pg.PG_NO_PREPROCESS,
+                       None, ctypes.byref(h))
+    assert rc == pg.PG_EINVAL
+    assert b"PG_ODD_REGION" in L.pg_last_error()
