@@ -426,6 +426,18 @@ pg_status pg_profile_read(const pg_game *game, int32_t kind, const char **name,
  *                  a step where they fit beside the games already in it.  A
  *                  game's memory comes from a pool that the batch keeps
  *                  until pg_batch_free.
+ * pg_batch_submit_many  submits count games at once (arrays of their
+ *                  arguments; flags shared): the same checks, preprocessing
+ *                  and queueing as count pg_batch_submit calls in order, but
+ *                  done together over the games' disjoint union, a few dozen
+ *                  kernels and a handful of synchronisations for the whole
+ *                  call instead of for each game.  status[i] is game i's
+ *                  outcome (as pg_batch_submit would return it) and
+ *                  tickets[i] its ticket (-1 if refused; pg_last_error
+ *                  holds the message of a refused game).  The call returns
+ *                  PG_OK when every game got its status, else the error
+ *                  that stopped it (games not queued then carry it too).
+ *                  Games larger than 2^29 - 1 vertices: PG_EINVAL.
  * pg_batch_step    lays the arena out again when finished games hold a
  *                  quarter of it, or to admit queued games that fit: once
  *                  they add up to an eighth of the arena's vertices, once
@@ -452,6 +464,13 @@ pg_status pg_batch_submit(pg_batch *batch, int64_t n, int64_t m,
                           const void *offsets, const int32_t *targets,
                           const uint8_t *owner, const int32_t *priority,
                           uint32_t flags, int64_t *ticket);
+pg_status pg_batch_submit_many(pg_batch *batch, int32_t count,
+                               const int64_t *n, const int64_t *m,
+                               const void *const *offsets,
+                               const int32_t *const *targets,
+                               const uint8_t *const *owner,
+                               const int32_t *const *priority, uint32_t flags,
+                               int64_t *tickets, pg_status *status);
 pg_status pg_batch_step(pg_batch *batch, int32_t *n_live, int32_t *n_queued,
                         int32_t *n_finished);
 pg_status pg_batch_poll(pg_batch *batch, int64_t ticket, int32_t *done,

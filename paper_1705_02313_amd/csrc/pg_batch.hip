@@ -342,6 +342,254 @@ __global__ void k_batch_ctl2(int G, uint8_t *run, uint8_t *pending,
 }
 
 
+// ---------------------------------------------------------------------------
+// Submissions in bulk: the games of one pg_batch_submit_many call are
+// validated and preprocessed together over their disjoint union.  Game g's
+// vertices are union ids vs[g] .. vs[g+1]-1 and its edges es[g] .. es[g+1]-1;
+// its modified game (originals, then its dummies) takes ids ab[g] ..
+// ab[g+1]-1 and edges aeb[g] .. aeb[g+1]-1.  Every kernel below works per
+// vertex or per edge and writes what the single-game path writes for that
+// game, in its own ids.
+// ---------------------------------------------------------------------------
+// the last g with starts[g] <= x (starts increasing, count >= 1)
+__device__ __forceinline__ int bm_game(const int64_t *starts, int count,
+                                       int64_t x) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (starts[mid] <= x) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// per-game sums: one atomic per wave for the lanes of the wave's first game
+// (games are contiguous, so that is nearly every lane), one per lane for the
+// others.  Every lane of the wave must call it.
+__device__ __forceinline__ void bm_add(unsigned long long *sum, int g,
+                                       unsigned long long x) {
+  const int g0 = __shfl(g, 0);
+  unsigned long long part = g == g0 ? x : 0ull;
+  for (int o = kWave / 2; o > 0; o >>= 1) part += __shfl_xor(part, o);
+  if ((threadIdx.x & (kWave - 1)) == 0 && part) atomicAdd(&sum[g0], part);
+  if (g != g0 && x) atomicAdd(&sum[g], x);
+}
+
+__device__ __forceinline__ void bm_max(int32_t *mx, int g, int32_t x) {
+  const int g0 = __shfl(g, 0);
+  int32_t part = g == g0 ? x : -1;
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    const int32_t y = __shfl_xor(part, o);
+    part = y > part ? y : part;
+  }
+  if ((threadIdx.x & (kWave - 1)) == 0 && part >= 0) atomicMax(&mx[g0], part);
+  if (g != g0 && x >= 0) atomicMax(&mx[g], x);
+}
+
+// offsets: raw holds each game's n_g + 1 entries from ostart[g] on
+template <typename OffT>
+__global__ void k_bm_offsets(const OffT *raw, const int64_t *ostart,
+                             const int64_t *vs, const int64_t *es, int count,
+                             int64_t *uoff, int32_t *err) {
+  const int64_t R = ostart[count];
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= R) return;
+  const int g = bm_game(ostart, count, j);
+  const int64_t i = j - ostart[g];
+  const int64_t ng = vs[g + 1] - vs[g], mg = es[g + 1] - es[g];
+  const int64_t x = (int64_t)raw[j];
+  bool bad = i == 0 && x != 0;
+  if (i == ng) {
+    bad |= x != mg;
+  } else {
+    bad |= (int64_t)raw[j + 1] <= x;
+    uoff[vs[g] + i] = es[g] + x;
+  }
+  if (j == R - 1) uoff[vs[count]] = es[count];
+  if (bad) atomicOr(&err[g], ERR_OFFSETS);
+}
+
+// targets to union ids (in place)
+__global__ void k_bm_targets(int32_t *tgt, const int64_t *vs,
+                             const int64_t *es, int count, int32_t *err) {
+  const int64_t M = es[count];
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= M) return;
+  const int g = bm_game(es, count, e);
+  const int32_t t = tgt[e];
+  if (t < 0 || (int64_t)t >= vs[g + 1] - vs[g]) {
+    atomicOr(&err[g], ERR_INVAL);
+    tgt[e] = (int32_t)vs[g];
+  } else {
+    tgt[e] = (int32_t)(vs[g] + t);
+  }
+}
+
+__global__ void k_bm_vertices(const uint8_t *owner, const int32_t *pri,
+                              const int64_t *vs, int count, int32_t *gid,
+                              int32_t *err) {
+  const int64_t N = vs[count];
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= N) return;
+  const int g = bm_game(vs, count, v);
+  gid[v] = g;
+  if (owner[v] > 1 || pri[v] < 0) atomicOr(&err[g], ERR_INVAL);
+}
+
+// dummies per game and the union rank of each game's first one
+__global__ void k_bm_dummies(const int64_t *vs, int count,
+                             const uint32_t *did, const uint32_t *xp,
+                             int64_t *nxp, uint32_t *dbase) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= count) return;
+  const int64_t a = vs[g], z = vs[g + 1] - 1;
+  dbase[g] = did[a];
+  nxp[g] = (int64_t)did[z] + xp[z] - did[a];
+}
+
+// the modified games (as k_aug_build for rank valuations): originals keep
+// their rows, an edge between members of X goes to the dummy of its
+// target, the dummy of the j-th member w of X' (in increasing w) is the
+// game's vertex n_g + j: Even, priority j, row [w]; originals raised by K[g]
+__global__ void k_bm_aug(int64_t N, const int64_t *uoff, const int32_t *utgt,
+                         const uint8_t *uown, const int32_t *upri,
+                         const uint8_t *inx, const uint32_t *xp,
+                         const uint32_t *did, const int32_t *gid,
+                         const int64_t *vs, const int64_t *es,
+                         const int64_t *K, const int64_t *ab,
+                         const int64_t *aeb, const uint32_t *dbase, int count,
+                         int64_t *aoff, int32_t *atgt, uint8_t *aown,
+                         int32_t *apri, int32_t *agid, int32_t *err) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= N) return;
+  const int g = gid[v];
+  const int64_t i = v - vs[g];
+  const int64_t ng = vs[g + 1] - vs[g], mg = es[g + 1] - es[g];
+  const int64_t a = ab[g] + i;
+  const int64_t eb = aeb[g] - es[g];   // union edge -> modified union edge
+  aoff[a] = uoff[v] + eb;
+  const bool vx = inx[v] != 0;
+  for (int64_t e = uoff[v], end = uoff[v + 1]; e < end; ++e) {
+    const int32_t w = utgt[e];
+    const int64_t t = (vx && inx[w]) ? ng + (int64_t)(did[w] - dbase[g])
+                                     : (int64_t)w - vs[g];
+    atgt[e + eb] = (int32_t)(ab[g] + t);
+  }
+  aown[a] = uown[v];
+  const int64_t p = (int64_t)upri[v] + K[g];
+  if (p > 2147483647LL) atomicOr(&err[g], ERR_INVAL);
+  apri[a] = (int32_t)p;
+  agid[a] = g;
+  if (xp[v]) {
+    const int64_t j = (int64_t)(did[v] - dbase[g]);
+    const int64_t d = ab[g] + ng + j;
+    aown[d] = 0;
+    apri[d] = (int32_t)j;
+    atgt[aeb[g] + mg + j] = (int32_t)a;
+    aoff[d] = aeb[g] + mg + j;
+    agid[d] = g;
+  }
+  if (v == N - 1) aoff[ab[count]] = aeb[count];
+}
+
+__device__ __forceinline__ uint32_t bm_signed_key(int32_t pri) {
+  const uint32_t p = (uint32_t)pri;
+  return (p & 1u) ? (0x7fffffffu - p) : (0x80000000u + p);
+}
+
+// the game of each vertex of the sorted order, as the key of the stable sort
+// that groups the games
+__global__ void k_bm_gidkeys(const uint32_t *sv, const int32_t *agid,
+                             uint32_t *k, int64_t n) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) k[p] = (uint32_t)agid[sv[p]];
+}
+
+struct BmOut {
+  int64_t *off;
+  int32_t *tgt;
+  uint8_t *owner;
+  int32_t *pri;
+  int32_t *rvperm;
+};
+
+// position p of the grouped signed order holds vertex a of game g at rank
+// p - ab[g]: the game's perm and the union's rank map, each row's length,
+// the repeat check and the odd-priority count
+__global__ void k_bm_rank(int64_t NA, const uint32_t *sv, const int32_t *agid,
+                          const int32_t *apri, const int64_t *aoff,
+                          const int64_t *ab, const BmOut *out, int32_t *urank,
+                          int64_t *len, unsigned long long *n_oddpri,
+                          int32_t *err) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int g = 0;
+  unsigned long long odd = 0;
+  if (p < NA) {
+    const int32_t a = (int32_t)sv[p];
+    g = agid[a];
+    const int64_t r = p - ab[g];
+    if (out[g].rvperm) out[g].rvperm[r] = (int32_t)(a - ab[g]);
+    urank[a] = (int32_t)r;
+    len[p] = aoff[a + 1] - aoff[a];
+    const uint32_t key = bm_signed_key(apri[a]);
+    odd = key < 0x80000000u;
+    if (r > 0 && bm_signed_key(apri[sv[p - 1]]) == key)
+      atomicOr(&err[g], ERR_DUPPRI);
+    if (p == NA - 1) len[NA] = 0;
+  } else {
+    g = agid[sv[NA - 1]];
+  }
+  bm_add(n_oddpri, g, odd);
+}
+
+// each game stored in its signed order (rows keep their edge order), with
+// its largest priority, Odd vertices and the edges of their rows
+__global__ void k_bm_relabel(int64_t NA, const uint32_t *sv,
+                             const int32_t *agid, const int64_t *aoff,
+                             const int32_t *atgt, const uint8_t *aown,
+                             const int32_t *apri, const int32_t *urank,
+                             const int64_t *lscan, const int64_t *ab,
+                             const int64_t *aeb, const BmOut *out,
+                             int32_t *maxpri, unsigned long long *n_odd,
+                             unsigned long long *m_odd) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int g = 0;
+  int32_t pr = -1;
+  unsigned long long odd = 0, oe = 0;
+  if (p < NA) {
+    const int32_t a = (int32_t)sv[p];
+    g = agid[a];
+    const int64_t r = p - ab[g];
+    const BmOut o = out[g];
+    const int64_t e0 = aoff[a], e1 = aoff[a + 1];
+    pr = apri[a];
+    odd = aown[a] == 1;
+    oe = odd ? (unsigned long long)(e1 - e0) : 0ull;
+    if (o.off) {
+      const int64_t at = lscan[p] - aeb[g];
+      o.off[r] = at;
+      if (p + 1 == ab[g + 1]) o.off[r + 1] = at + (e1 - e0);
+      for (int64_t e = e0; e < e1; ++e) o.tgt[at + (e - e0)] = urank[atgt[e]];
+      o.owner[r] = aown[a];
+      o.pri[r] = pr;
+    }
+  } else {
+    g = agid[sv[NA - 1]];
+  }
+  bm_max(maxpri, g, pr);
+  bm_add(n_odd, g, odd);
+  bm_add(m_odd, g, oe);
+}
+
+// the first edge of each game's even-priority rows
+__global__ void k_bm_split(const BmOut *out, const unsigned long long *n_oddpri,
+                           int count, int64_t *e_split) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= count) return;
+  e_split[g] = out[g].off ? out[g].off[n_oddpri[g]] : 0;
+}
+
+
 }  // namespace pgk
 
 using namespace pgk;
@@ -781,6 +1029,336 @@ pg_status step_device(pg_batch *b, hipStream_t s) {
   return valuation_status(a);
 }
 
+// pg_batch_submit_many's work on the games `idx` (indices into the call's
+// arrays), all of whose arguments passed the host checks.  Games the device
+// checks reject get their status and are left out; the call then runs again
+// on the others (the union must hold valid games only).
+pg_status submit_union(pg_batch *b, const std::vector<int> &idx,
+                       const int64_t *n, const int64_t *m,
+                       const void *const *offsets,
+                       const int32_t *const *targets,
+                       const uint8_t *const *owner,
+                       const int32_t *const *priority, uint32_t flags,
+                       int64_t *tickets, pg_status *status) {
+  const int count = (int)idx.size();
+  if (count == 0) return PG_OK;
+  hipStream_t s = b->sub_stream;
+  const bool dev = flags & PG_PTR_DEVICE;
+  const bool i32 = flags & PG_OFFSETS_I32;
+  std::vector<int64_t> hv(count + 1, 0), he(count + 1, 0), ho(count + 1, 0);
+  for (int k = 0; k < count; ++k) {
+    hv[k + 1] = hv[k] + n[idx[k]];
+    he[k + 1] = he[k] + m[idx[k]];
+    ho[k + 1] = ho[k] + n[idx[k]] + 1;
+  }
+  const int64_t N = hv[count], M = he[count], R = ho[count];
+  // temporaries: returned to the batch's pool once the stream has drained
+  struct Tmp {
+    hipStream_t s;
+    std::vector<void *> p;
+    ~Tmp() {
+      if (!p.empty()) (void)hipStreamSynchronize(s);
+      for (void *x : p) dev_free(x);
+    }
+  } tmp{s, {}};
+  auto alloc = [&](auto **ptr, int64_t c) -> pg_status {
+    PG_TRY(dev_alloc(ptr, c));
+    tmp.p.push_back((void *)*ptr);
+    return PG_OK;
+  };
+  // game tables: vs, es, ostart (count + 1 each), later K, ab, aeb
+  int64_t *tab = nullptr;
+  PG_TRY(alloc(&tab, 6 * (int64_t)(count + 1)));
+  int64_t *d_vs = tab, *d_es = tab + (count + 1), *d_os = tab + 2 * (count + 1);
+  int64_t *d_K = tab + 3 * (count + 1), *d_ab = tab + 4 * (count + 1);
+  int64_t *d_aeb = tab + 5 * (count + 1);
+  std::vector<int64_t> htab(6 * (size_t)(count + 1), 0);
+  std::copy(hv.begin(), hv.end(), htab.begin());
+  std::copy(he.begin(), he.end(), htab.begin() + (count + 1));
+  std::copy(ho.begin(), ho.end(), htab.begin() + 2 * (count + 1));
+  PG_HIP(hipMemcpyAsync(tab, htab.data(), sizeof(int64_t) * 3 * (count + 1),
+                        hipMemcpyHostToDevice, s));
+  // the inputs, one slice per game
+  void *raw = nullptr;
+  int64_t *uoff = nullptr;
+  int32_t *utgt = nullptr, *upri = nullptr, *gid = nullptr, *err = nullptr;
+  uint8_t *uown = nullptr;
+  if (i32) PG_TRY(alloc((int32_t **)&raw, R));
+  else PG_TRY(alloc((int64_t **)&raw, R));
+  PG_TRY(alloc(&uoff, N + 1));
+  PG_TRY(alloc(&utgt, M));
+  PG_TRY(alloc(&uown, N));
+  PG_TRY(alloc(&upri, N));
+  PG_TRY(alloc(&gid, N));
+  PG_TRY(alloc(&err, count));
+  const size_t ob = i32 ? 4 : 8;
+  for (int k = 0; k < count; ++k) {
+    const int q = idx[k];
+    PG_TRY(copy_in((uint8_t *)raw + ob * ho[k], offsets[q],
+                   ob * (n[q] + 1), dev, s));
+    PG_TRY(copy_in(utgt + he[k], targets[q], sizeof(int32_t) * m[q], dev, s));
+    PG_TRY(copy_in(uown + hv[k], owner[q], n[q], dev, s));
+    PG_TRY(copy_in(upri + hv[k], priority[q], sizeof(int32_t) * n[q], dev,
+                   s));
+  }
+  fill_i32(err, 0, count, s);
+  if (i32)
+    hipLaunchKernelGGL(k_bm_offsets<int32_t>, dim3(grid_for(R)),
+                       dim3(kBlock), 0, s, (const int32_t *)raw, d_os, d_vs,
+                       d_es, count, uoff, err);
+  else
+    hipLaunchKernelGGL(k_bm_offsets<int64_t>, dim3(grid_for(R)),
+                       dim3(kBlock), 0, s, (const int64_t *)raw, d_os, d_vs,
+                       d_es, count, uoff, err);
+  hipLaunchKernelGGL(k_bm_targets, dim3(grid_for(M)), dim3(kBlock), 0, s,
+                     utgt, d_vs, d_es, count, err);
+  hipLaunchKernelGGL(k_bm_vertices, dim3(grid_for(N)), dim3(kBlock), 0, s,
+                     uown, upri, d_vs, count, gid, err);
+  std::vector<int32_t> herr(count);
+  PG_HIP(hipMemcpyAsync(herr.data(), err, sizeof(int32_t) * count,
+                        hipMemcpyDeviceToHost, s));
+  PG_HIP(hipStreamSynchronize(s));
+  {
+    std::vector<int> ok;
+    for (int k = 0; k < count; ++k) {
+      if (herr[k] & ERR_OFFSETS)
+        status[idx[k]] = pg_fail(PG_EINVAL,
+                                 "offsets must start at 0, end at m and give "
+                                 "every vertex a non-empty row");
+      else if (herr[k])
+        status[idx[k]] = pg_fail(PG_EINVAL,
+                                 "targets must lie in [0, n), owners in "
+                                 "{0, 1} and priorities be >= 0");
+      else
+        ok.push_back(idx[k]);
+    }
+    if ((int)ok.size() < count)
+      return submit_union(b, ok, n, m, offsets, targets, owner, priority,
+                          flags, tickets, status);
+  }
+
+  // X and its members with a predecessor in X (section 3, "The algorithm")
+  uint8_t *inx = nullptr;
+  uint32_t *wit = nullptr, *did = nullptr;
+  int32_t *ctr = nullptr;
+  PG_TRY(alloc(&inx, N));
+  PG_TRY(alloc(&wit, N));
+  PG_TRY(alloc(&did, N));
+  PG_TRY(alloc(&ctr, C_COUNT));
+  int32_t hflag = 0;
+  hipLaunchKernelGGL(k_x_init, dim3(grid_for(N)), dim3(kBlock), 0, s, uown,
+                     inx, N);
+  fill_i32((int32_t *)wit, 0, N, s);
+  for (int64_t round = 0;; round += 4) {
+    if (round > 4 * N + 64)
+      return pg_fail(PG_EINTERNAL, "preprocessing did not converge");
+    fill_i32(ctr, 0, C_COUNT, s);
+    for (int k = 0; k < 4; ++k)
+      hipLaunchKernelGGL(k_x_round, dim3(grid_for(N)), dim3(kBlock), 0, s,
+                         uoff, utgt, inx, wit, N, ctr);
+    PG_HIP(hipMemcpyAsync(&hflag, ctr + C_MISC, sizeof(int32_t),
+                          hipMemcpyDeviceToHost, s));
+    PG_HIP(hipStreamSynchronize(s));
+    if (hflag == 0) break;
+  }
+  uint32_t *xp = wit;   // the witnesses are done with
+  fill_i32((int32_t *)xp, 0, N, s);
+  hipLaunchKernelGGL(k_xp_mark, dim3(grid_for(N)), dim3(kBlock), 0, s, uoff,
+                     utgt, inx, xp, N);
+  {
+    void *stmp = nullptr;
+    const size_t need = scan_excl_u32(nullptr, nullptr, N, nullptr, s);
+    PG_TRY(alloc((uint8_t **)&stmp, (int64_t)need + 16));
+    scan_excl_u32(xp, did, N, stmp, s);
+  }
+  int64_t *nxp = nullptr;
+  uint32_t *dbase = nullptr;
+  PG_TRY(alloc(&nxp, count));
+  PG_TRY(alloc(&dbase, count));
+  hipLaunchKernelGGL(k_bm_dummies, dim3(grid_for(count)), dim3(kBlock), 0, s,
+                     d_vs, count, did, xp, nxp, dbase);
+  std::vector<int64_t> hnxp(count);
+  PG_HIP(hipMemcpyAsync(hnxp.data(), nxp, sizeof(int64_t) * count,
+                        hipMemcpyDeviceToHost, s));
+  PG_HIP(hipStreamSynchronize(s));
+
+  // the modified games' sizes, places and priority shifts; games that do not
+  // fit the arena are refused here (their rows are still built, not kept)
+  std::vector<char> keep(count, 1);
+  int64_t *hK = htab.data() + 3 * (count + 1);
+  int64_t *hab = htab.data() + 4 * (count + 1);
+  int64_t *haeb = htab.data() + 5 * (count + 1);
+  for (int k = 0; k < count; ++k) {
+    const int q = idx[k];
+    const int64_t na = n[q] + hnxp[k], ma = m[q] + hnxp[k];
+    hK[k] = hnxp[k] + (hnxp[k] & 1);
+    hab[k + 1] = hab[k] + na;
+    haeb[k + 1] = haeb[k] + ma;
+    if (na > kMaxVertices) {
+      status[q] = pg_fail(PG_EINVAL, "too many vertices after preprocessing");
+      keep[k] = 0;
+    } else if (na > b->cap_v || ma > b->cap_e) {
+      status[q] = pg_fail(PG_ENOMEM, "game larger than the batch capacity");
+      keep[k] = 0;
+    }
+  }
+  const int64_t NA = hab[count], MA = haeb[count];
+  if (NA > kMaxVertices)
+    return pg_fail(PG_EINTERNAL, "submission union too large");
+  PG_HIP(hipMemcpyAsync(d_K, hK, sizeof(int64_t) * 3 * (count + 1),
+                        hipMemcpyHostToDevice, s));
+  int64_t *aoff = nullptr;
+  int32_t *atgt = nullptr, *apri = nullptr, *agid = nullptr;
+  uint8_t *aown = nullptr;
+  PG_TRY(alloc(&aoff, NA + 1));
+  PG_TRY(alloc(&atgt, MA));
+  PG_TRY(alloc(&aown, NA));
+  PG_TRY(alloc(&apri, NA));
+  PG_TRY(alloc(&agid, NA));
+  hipLaunchKernelGGL(k_bm_aug, dim3(grid_for(N)), dim3(kBlock), 0, s, N, uoff,
+                     utgt, uown, upri, inx, xp, did, gid, d_vs, d_es, d_K,
+                     d_ab, d_aeb, dbase, count, aoff, atgt, aown, apri, agid,
+                     err);
+
+  // each game's signed-priority order: sort by the signed key, then stably
+  // by game
+  uint32_t *k0 = nullptr, *v0 = nullptr, *k1 = nullptr, *v1 = nullptr;
+  uint32_t *tc = nullptr;
+  uint8_t *rtmp = nullptr;
+  PG_TRY(alloc(&k0, NA));
+  PG_TRY(alloc(&v0, NA));
+  PG_TRY(alloc(&k1, NA));
+  PG_TRY(alloc(&v1, NA));
+  PG_TRY(alloc(&tc, 256 * radix_tiles(NA)));
+  PG_TRY(alloc(&rtmp, (int64_t)radix_scan_tmp_bytes(NA) + 16));
+  hipLaunchKernelGGL(k_rv_keys, dim3(grid_for(NA)), dim3(kBlock), 0, s, apri,
+                     k0, v0, NA);
+  int w = radix_sort(k0, v0, k1, v1, NA, 32, tc, rtmp, s);
+  uint32_t *svs = w ? v1 : v0, *kx = w ? k0 : k1, *vx = w ? v0 : v1;
+  uint32_t *kg = w ? k1 : k0;
+  hipLaunchKernelGGL(k_bm_gidkeys, dim3(grid_for(NA)), dim3(kBlock), 0, s,
+                     svs, agid, kg, NA);
+  int gbits = 1;
+  while ((int64_t(1) << gbits) < count) ++gbits;
+  const int w2 = radix_sort(kg, svs, kx, vx, NA, gbits, tc, rtmp, s);
+  const uint32_t *sv = w2 ? vx : svs;
+
+  // the games' own arrays (kept games only) and their pointer table
+  std::vector<BGame *> made(count, nullptr);
+  struct Made {
+    hipStream_t s;
+    std::vector<BGame *> *v;
+    ~Made() {
+      bool any = false;
+      for (BGame *g : *v) any |= g != nullptr;
+      if (!any) return;
+      (void)hipStreamSynchronize(s);   // no kernel may still write them
+      for (BGame *g : *v) free_bgame(g);
+    }
+  } made_guard{s, &made};
+  std::vector<BmOut> hout(count, BmOut{nullptr, nullptr, nullptr, nullptr,
+                                       nullptr});
+  for (int k = 0; k < count; ++k) {
+    if (!keep[k]) continue;
+    const int q = idx[k];
+    const int64_t na = hab[k + 1] - hab[k], ma = haeb[k + 1] - haeb[k];
+    BGame *bg = new (std::nothrow) BGame();
+    if (!bg) return pg_fail(PG_ENOMEM, "host allocation failed");
+    made[k] = bg;
+    bg->g = new (std::nothrow) pg_game();
+    if (!bg->g) return pg_fail(PG_ENOMEM, "host allocation failed");
+    pg_game *gg = bg->g;
+    gg->device = b->device;
+    gg->n = n[q];
+    gg->m = m[q];
+    gg->n_aug = na;
+    gg->m_aug = ma;
+    gg->relabeled = true;
+    PG_TRY(dev_alloc(&gg->off, na + 1));
+    PG_TRY(dev_alloc(&gg->tgt, ma));
+    PG_TRY(dev_alloc(&gg->owner, na));
+    PG_TRY(dev_alloc(&gg->pri, na));
+    PG_TRY(dev_alloc(&bg->rvperm, na));
+    PG_TRY(dev_alloc(&bg->saved, na));
+    PG_TRY(dev_alloc(&bg->res_winner, n[q]));
+    PG_TRY(dev_alloc(&bg->res_sigma, na));
+    PG_TRY(dev_alloc(&bg->res_tau, na));
+    hout[k] = BmOut{gg->off, gg->tgt, gg->owner, gg->pri, bg->rvperm};
+  }
+  BmOut *dout = nullptr;
+  PG_TRY(alloc((uint8_t **)&dout, (int64_t)sizeof(BmOut) * count));
+  PG_HIP(hipMemcpyAsync(dout, hout.data(), sizeof(BmOut) * count,
+                        hipMemcpyHostToDevice, s));
+  int32_t *urank = nullptr, *maxpri = nullptr;
+  int64_t *len = nullptr, *lscan = nullptr, *esplit = nullptr;
+  unsigned long long *cnt = nullptr;   // [3 count] odd priorities, Odd, edges
+  PG_TRY(alloc(&urank, NA));
+  PG_TRY(alloc(&len, NA + 1));
+  PG_TRY(alloc(&lscan, NA + 1));
+  PG_TRY(alloc(&maxpri, count));
+  PG_TRY(alloc(&esplit, count));
+  PG_TRY(alloc(&cnt, 3 * (int64_t)count));
+  fill_i32((int32_t *)cnt, 0, 6 * (int64_t)count, s);
+  fill_i32(maxpri, -1, count, s);
+  hipLaunchKernelGGL(k_bm_rank, dim3(grid_for(NA)), dim3(kBlock), 0, s, NA,
+                     sv, agid, apri, aoff, d_ab, dout, urank, len, cnt, err);
+  {
+    void *stmp = nullptr;
+    const size_t need = scan_excl_i64(nullptr, nullptr, NA + 1, nullptr, s);
+    PG_TRY(alloc((uint8_t **)&stmp, (int64_t)need + 16));
+    scan_excl_i64(len, lscan, NA + 1, stmp, s);
+  }
+  hipLaunchKernelGGL(k_bm_relabel, dim3(grid_for(NA)), dim3(kBlock), 0, s,
+                     NA, sv, agid, aoff, atgt, aown, apri, urank, lscan, d_ab,
+                     d_aeb, dout, maxpri, cnt + count, cnt + 2 * count);
+  hipLaunchKernelGGL(k_bm_split, dim3(grid_for(count)), dim3(kBlock), 0, s,
+                     dout, cnt, count, esplit);
+  std::vector<int32_t> hmax(count);
+  std::vector<unsigned long long> hcnt(3 * (size_t)count);
+  std::vector<int64_t> hsplit(count);
+  PG_HIP(hipMemcpyAsync(herr.data(), err, sizeof(int32_t) * count,
+                        hipMemcpyDeviceToHost, s));
+  PG_HIP(hipMemcpyAsync(hmax.data(), maxpri, sizeof(int32_t) * count,
+                        hipMemcpyDeviceToHost, s));
+  PG_HIP(hipMemcpyAsync(hcnt.data(), cnt, sizeof(uint64_t) * 3 * count,
+                        hipMemcpyDeviceToHost, s));
+  PG_HIP(hipMemcpyAsync(hsplit.data(), esplit, sizeof(int64_t) * count,
+                        hipMemcpyDeviceToHost, s));
+  PG_HIP(hipStreamSynchronize(s));
+
+  std::lock_guard<std::mutex> lock(b->mu);
+  for (int k = 0; k < count; ++k) {
+    BGame *bg = made[k];
+    if (!bg) continue;
+    const int q = idx[k];
+    if (herr[k] & ERR_INVAL) {
+      status[q] = pg_fail(PG_EINVAL,
+                          "a priority exceeds INT32_MAX after preprocessing");
+      continue;
+    }
+    if (herr[k] & ERR_DUPPRI) {
+      status[q] = pg_fail(PG_EINVAL, "priorities must be pairwise distinct");
+      continue;
+    }
+    bg->maxpri = hmax[k];
+    bg->n_oddpri = (int64_t)hcnt[k];
+    bg->n_odd = (int64_t)hcnt[count + k];
+    bg->m_odd = (int64_t)hcnt[2 * count + k];
+    bg->e_split = hsplit[k];
+    bg->st.n = n[q];
+    bg->st.m = m[q];
+    bg->st.n_aug = bg->g->n_aug;
+    bg->st.m_aug = bg->g->m_aug;
+    bg->ticket = b->next_ticket++;
+    b->games[bg->ticket] = bg;
+    b->queue.push_back(bg);
+    tickets[q] = bg->ticket;
+    status[q] = PG_OK;
+    made[k] = nullptr;   // the batch owns it now
+  }
+  return PG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -952,6 +1530,58 @@ pg_status pg_batch_submit(pg_batch *b, int64_t n, int64_t m,
   b->queue.push_back(bg);
   *ticket = bg->ticket;
   return PG_OK;
+}
+
+pg_status pg_batch_submit_many(pg_batch *b, int32_t count, const int64_t *n,
+                               const int64_t *m, const void *const *offsets,
+                               const int32_t *const *targets,
+                               const uint8_t *const *owner,
+                               const int32_t *const *priority, uint32_t flags,
+                               int64_t *tickets, pg_status *status) {
+  if (!b || count < 0) return pg_fail(PG_EINVAL, "bad batch or count");
+  if (count == 0) return PG_OK;
+  if (!n || !m || !offsets || !targets || !owner || !priority || !tickets ||
+      !status)
+    return pg_fail(PG_EINVAL, "NULL argument");
+  if (flags & PG_ODD_REGION)
+    return pg_fail(PG_EINVAL, "a batch does not take PG_ODD_REGION games");
+  std::vector<int> idx;
+  for (int32_t q = 0; q < count; ++q) {
+    tickets[q] = -1;
+    status[q] = PG_OK;
+    if (n[q] < 1 || m[q] < n[q])
+      status[q] = pg_fail(PG_EINVAL, "need n >= 1 and m >= n");
+    else if (n[q] > kMaxVertices / 2)
+      status[q] = pg_fail(PG_EINVAL, "game too large for a batch");
+    else if (!offsets[q] || !targets[q] || !owner[q] || !priority[q])
+      status[q] = pg_fail(PG_EINVAL, "a game array is NULL");
+    else if ((flags & PG_OFFSETS_I32) && m[q] > 0x7fffffffLL)
+      status[q] = pg_fail(PG_EINVAL, "int32 offsets cannot address m edges");
+    if (status[q] == PG_OK) idx.push_back(q);
+  }
+  PoolScope ps(&b->pool);   // the games' memory comes from the batch's pool
+  // chunks of at most 2^28 vertices, so that a chunk's modified games
+  // (at most twice its vertices) keep 32-bit ids
+  size_t at = 0;
+  pg_status st = PG_OK;
+  while (at < idx.size() && st == PG_OK) {
+    std::vector<int> part;
+    int64_t nv = 0;
+    while (at < idx.size() &&
+           (part.empty() || nv + n[idx[at]] <= (int64_t(1) << 28))) {
+      nv += n[idx[at]];
+      part.push_back(idx[at++]);
+    }
+    st = submit_union(b, part, n, m, offsets, targets, owner, priority, flags,
+                      tickets, status);
+  }
+  if (st != PG_OK) {
+    (void)hipStreamSynchronize(b->sub_stream);
+    // what was not queued carries the call's error
+    for (int q : idx)
+      if (tickets[q] < 0 && status[q] == PG_OK) status[q] = st;
+  }
+  return st;
 }
 
 pg_status pg_batch_step(pg_batch *b, int32_t *n_live, int32_t *n_queued,

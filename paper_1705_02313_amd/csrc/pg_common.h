@@ -506,6 +506,15 @@ pg_status host_alloc(void **p, size_t bytes);
 namespace pgk {
 __global__ void k_rv_keys(const int32_t *pri, uint32_t *sk, uint32_t *sv,
                           int64_t n);
+// the admissibility preprocessing's kernels (pg_api.hip): X starts as the Odd
+// vertices; a round removes members without a successor in X (wit: each
+// row's last witness; ctr[C_MISC] set on a change); xp marks the members of
+// X with a predecessor in X
+__global__ void k_x_init(const uint8_t *owner, uint8_t *inx, int64_t n);
+__global__ void k_x_round(const int64_t *off, const int32_t *tgt, uint8_t *inx,
+                          uint32_t *wit, int64_t n, int32_t *ctr);
+__global__ void k_xp_mark(const int64_t *off, const int32_t *tgt,
+                          const uint8_t *inx, uint32_t *xp, int64_t n);
 // perm/rvpos from the sorted signed keys; odd-priority count into
 // C_DIST_MISC; ERR_DUPPRI on a repeat when check_dup
 __global__ void k_rv_finish(const uint32_t *skS, const uint32_t *svS,

@@ -37,6 +37,7 @@ EXPORTS = ["pg_load_csr", "pg_game_info", "pg_count_info", "pg_export_game",
            "pg_best_response",
            "pg_solve", "pg_profile_enable", "pg_profile_kinds",
            "pg_profile_read", "pg_batch_create", "pg_batch_submit",
+           "pg_batch_submit_many",
            "pg_batch_step", "pg_batch_poll", "pg_batch_finished",
            "pg_batch_info", "pg_batch_free",
            "pg_free", "pg_release_cache", "pg_solve_noalloc",
@@ -143,6 +144,8 @@ def lib() -> ctypes.CDLL:
         L.pg_batch_create.argtypes = [I64, I64, I32, P, ctypes.POINTER(P)]
         L.pg_batch_submit.argtypes = [P, I64, I64, P, P, P, P, U32,
                                       ctypes.POINTER(I64)]
+        L.pg_batch_submit_many.argtypes = [P, I32, P, P, P, P, P, P, U32, P,
+                                           P]
         L.pg_batch_step.argtypes = [P] + [ctypes.POINTER(I32)] * 3
         L.pg_batch_poll.argtypes = [P, I64, ctypes.POINTER(I32), P, P, P,
                                     ctypes.POINTER(Stats), U32]
@@ -562,6 +565,43 @@ class Batch:
                                      _ptr(arr["pri"]), flags,
                                      ctypes.byref(t)))
         return int(t.value)
+
+    def submit_many(self, games: list) -> list:
+        """Queues several games in one call (pg_batch_submit_many): their
+        preprocessing runs over their disjoint union.  Returns one entry per
+        game: its ticket, or the PgError that refused it."""
+        if not games:
+            return []
+        i32 = all(np.asarray(g["offsets"]).dtype == np.int32 for g in games)
+        odt = np.int32 if i32 else np.int64
+        keep = []   # the arrays must live until the call returns
+        cnt = len(games)
+        ns = np.array([int(g["n"]) for g in games], np.int64)
+        ms = np.array([int(g["m"]) for g in games], np.int64)
+        ptrs = {k: (ctypes.c_void_p * cnt)() for k in
+                ("offsets", "targets", "owner", "pri")}
+        for i, g in enumerate(games):
+            arr = {"offsets": np.ascontiguousarray(g["offsets"], odt),
+                   "targets": np.ascontiguousarray(g["targets"], np.int32),
+                   "owner": np.ascontiguousarray(g["owner"], np.uint8),
+                   "pri": np.ascontiguousarray(g["pri"], np.int32)}
+            keep.append(arr)
+            for k, a in arr.items():
+                ptrs[k][i] = a.ctypes.data
+        tickets = np.full(cnt, -1, np.int64)
+        status = np.zeros(cnt, np.int32)
+        _check(lib().pg_batch_submit_many(
+            self._h, cnt, _ptr(ns), _ptr(ms), ptrs["offsets"],
+            ptrs["targets"], ptrs["owner"], ptrs["pri"],
+            PG_OFFSETS_I32 if i32 else 0, _ptr(tickets), _ptr(status)))
+        out = []
+        for i in range(cnt):
+            if status[i] == PG_OK:
+                out.append(int(tickets[i]))
+            else:
+                out.append(PgError(int(status[i]),
+                                   f"game {i} refused by the batch"))
+        return out
 
     def step(self):
         """One step; returns (live, queued, finished by this step)."""

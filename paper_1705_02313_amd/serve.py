@@ -27,8 +27,9 @@ def serve(games, arrivals, max_vertices: int, max_edges: int,
     """Solves `games` arriving at `arrivals` (seconds from the start).
 
     Without `submit_thread` (default) the loop submits the games that have
-    arrived between steps, so each step sees every game that arrived before
-    it; with it submissions run on a thread of their own, overlapping the
+    arrived between steps, all in one pg_batch_submit_many call, so each
+    step sees every game that arrived before it; with it submissions run one
+    by one on a thread of their own, overlapping the
     steps (lower latency below saturation, fewer games per second near it:
     the steps then hold fewer games each).
     Returns {"results": {i: result dict}, "latency": [...], "arrival",
@@ -77,11 +78,19 @@ def serve(games, arrivals, max_vertices: int, max_edges: int,
                 if state["error"] is not None:
                     raise state["error"]
                 if th is None:
-                    # admit every request that has arrived by now
+                    # admit every request that has arrived by now, in one
+                    # call (their preprocessing runs over their union)
                     now = clock() - t0
+                    arrived = []
                     while nxt < n and arrivals[order[nxt]] <= now:
-                        submit(int(order[nxt]))
+                        arrived.append(int(order[nxt]))
                         nxt += 1
+                    if arrived:
+                        res = b.submit_many([games[i] for i in arrived])
+                        for i, t in zip(arrived, res):
+                            if isinstance(t, Exception):
+                                raise t
+                            ticket_of[t] = i
                 info_live, queued, _ = b.step()
                 steps += 1
                 for t in b.finished():

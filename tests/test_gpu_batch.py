@@ -168,3 +168,62 @@ def test_serve_with_and_without_a_submitter_thread(thread):
     assert (r["latency"] >= 0).all()
     for i, g in enumerate(games):
         _check(g, r["results"][i])
+
+
+def test_submit_many_matches_the_oracle_and_refuses_per_game():
+    """pg_batch_submit_many: the games queued in one call (preprocessed over
+    their union) finish with the oracle's results; bad games are refused
+    one by one without stopping the others."""
+    games = _mix(20, 7500, nmin=200, nmax=30000)
+    games.append(synth.random_game(40000, 2, 6, 7501, offsets_dtype=np.int32))
+    dup = synth.random_game(300, 2, 4, 7502)
+    dup["pri"] = dup["pri"].copy()
+    dup["pri"][5] = dup["pri"][6]                 # repeated priority
+    badt = synth.random_game(300, 2, 4, 7503)
+    badt["targets"] = badt["targets"].copy()
+    badt["targets"][7] = 300                      # target out of range
+    bado = synth.random_game(300, 2, 4, 7504)
+    bado["offsets"] = bado["offsets"].copy()
+    bado["offsets"][10] = bado["offsets"][9]      # an empty row
+    over = synth.random_game(300, 2, 5, 7505)
+    over["pri"] = over["pri"].copy()
+    over["pri"][0] = 2**31 - 2                    # overflows after the shift
+    huge = synth.random_game(600000, 2, 3, 7506)  # beyond the arena
+    order = [0, 1, "dup", 2, "badt", 3, "bado", 4, "over", "huge"] + \
+        list(range(5, len(games)))
+    extra = {"dup": dup, "badt": badt, "bado": bado, "over": over,
+             "huge": huge}
+    sub = [extra[k] if isinstance(k, str) else games[k] for k in order]
+    with Batch(500_000, 3_000_000) as b:
+        res = b.submit_many(sub)
+        expect = {"dup": PG_EINVAL, "badt": PG_EINVAL, "bado": PG_EINVAL,
+                  "over": PG_EINVAL, "huge": PG_ENOMEM}
+        tickets = {}
+        for k, r in zip(order, res):
+            if isinstance(k, str):
+                assert isinstance(r, PgError) and r.status == expect[k], k
+            else:
+                assert isinstance(r, int) and r > 0, k
+                tickets[r] = games[k]
+        # tickets in submission order
+        assert list(tickets) == sorted(tickets)
+        out = _drain(b, list(tickets))
+        # a second call on the same batch, then single submissions beside it
+        more = _mix(6, 7600, nmin=500, nmax=5000)
+        t2 = b.submit_many(more[:4]) + [b.submit(g) for g in more[4:]]
+        out2 = _drain(b, list(t2))
+    for t, g in tickets.items():
+        _check(g, out[t])
+    for t, g in zip(t2, more):
+        _check(g, out2[t])
+
+
+def test_submit_many_int64_offsets_and_empty_call():
+    games = [synth.random_game(n, 2, 5, 7700 + n) for n in (3, 50, 999, 4000)]
+    games.append(synth.chain_game(5000, 7701))
+    with Batch(1_000_000, 6_000_000) as b:
+        assert b.submit_many([]) == []
+        ts = b.submit_many(games)
+        out = _drain(b, list(ts))
+    for t, g in zip(ts, games):
+        _check(g, out[t])
