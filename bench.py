@@ -86,15 +86,20 @@ WORKLOADS = {
 TRAFFIC_FILES = {"c2": "traffic_random10M.json"}
 
 
+# the sources of everything a single rank-valuation game's load and solve
+# launch (batches, count valuations and PG_ODD_REGION live in other files)
+SINGLE_GAME_SOURCES = ["pg_api.hip", "pg_common.h", "pg_prims.hip",
+                       "pg_switch.hip", "pg_tune.hip", "pg_val.hip"]
+
+
 def sources_sha256() -> str:
-    """Hash of the library's kernel sources and header (file names and
-    contents), to tie stored counter readings to the code they measured."""
-    import glob
+    """Hash of the kernel sources a single rank-valuation game runs and of
+    the header (file names and contents), to tie stored counter readings to
+    the code they measured."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1705_02313_amd", "csrc")
-    files = sorted(glob.glob(os.path.join(csrc, "*.hip")) +
-                   glob.glob(os.path.join(csrc, "*.h")))
+    files = [os.path.join(csrc, f) for f in SINGLE_GAME_SOURCES]
     files.append(os.path.join(ROOT, "include", "pg.h"))
     for f in files:
         h.update(os.path.basename(f).encode())
@@ -143,6 +148,110 @@ def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 5) -> float:
     del src, dst
     torch.cuda.empty_cache()
     return 2 * nbytes / statistics.median(ts) / 1e9
+
+
+def random_gather_rate(n_words: int = 1 << 28, n_idx: int = 1 << 26,
+                       reps: int = 5) -> dict:
+    """Random 4-byte gathers per second from a 1 GiB array (each index
+    almost surely on a line of its own), with the index reads and output
+    writes (12 B per gather, coalesced) that the gather also pays: the rate
+    at which a pass that touches one random line per step can run."""
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(12345)
+    src = torch.arange(n_words, dtype=torch.int32, device="cuda")
+    idx = torch.randint(0, n_words, (n_idx,), device="cuda", generator=g)
+    out = src[idx]
+    ts = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        torch.index_select(src, 0, idx, out=out)
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b) / 1e3)
+    del src, idx, out
+    torch.cuda.empty_cache()
+    t = statistics.median(ts)
+    return {"gathers_per_s": n_idx / t, "array_bytes": 4 * n_words,
+            "gathers": n_idx, "seconds": t}
+
+
+def traffic_summary(pmc_dir: str, workload: str = "c2") -> dict:
+    """Reads four rocprofv3 --pmc runs under pmc_dir (<workload>_FETCH_SIZE,
+    <workload>_WRITE_SIZE, copy_FETCH_SIZE, copy_WRITE_SIZE, each holding a
+    *counter_collection.csv) and returns the counter bytes per launch by the
+    library's kernel kind, each counter scaled by its reading on the plain
+    copy (--copy-calibration 1024: 1 GiB read and 1 GiB written)."""
+    import csv
+    import glob
+
+    def per_kernel(sub):
+        files = glob.glob(os.path.join(pmc_dir, sub, "**",
+                                       "*counter_collection.csv"),
+                          recursive=True)
+        if not files:
+            raise FileNotFoundError(f"no counter CSV under {sub}")
+        acc = {}
+        for f in files:
+            with open(f) as fh:
+                for row in csv.DictReader(fh):
+                    name = row["Kernel_Name"].split("(")[0]
+                    name = name.replace("void ", "").strip()
+                    name = name.split("<")[0].split("::")[-1]
+                    a = acc.setdefault(name, [0.0, 0])
+                    a[0] += float(row["Counter_Value"])
+                    a[1] += 1
+        return acc
+
+    copy_f = per_kernel("copy_FETCH_SIZE")
+    copy_w = per_kernel("copy_WRITE_SIZE")
+    ck = max(copy_f, key=lambda k: copy_f[k][0])
+    gib = float(1 << 30)
+    f_scale = gib / (copy_f[ck][0] / copy_f[ck][1] * 1024.0)
+    w_scale = gib / (copy_w[ck][0] / copy_w[ck][1] * 1024.0)
+    fetch = per_kernel(f"{workload}_FETCH_SIZE")
+    write = per_kernel(f"{workload}_WRITE_SIZE")
+    by_kind = {}
+    for name, (kib, calls) in fetch.items():
+        kind = KERNEL_KINDS.get(name, "other")
+        wk = write.get(name, [0.0, calls])[0]
+        b = by_kind.setdefault(kind, [0.0, 0, 0.0, 0.0])
+        b[0] += 1024.0 * (kib * f_scale + wk * w_scale)
+        b[1] += calls
+        b[2] += 1024.0 * kib * f_scale
+        b[3] += 1024.0 * wk * w_scale
+    return {"workload": workload, "sources_sha256": sources_sha256(),
+            "scale": {"FETCH_SIZE": round(f_scale, 4),
+                      "WRITE_SIZE": round(w_scale, 4)},
+            "bytes_per_launch": {k: round(v[0] / v[1]) for k, v in
+                                 sorted(by_kind.items(),
+                                        key=lambda kv: -kv[1][0])},
+            "fetched_per_launch": {k: round(v[2] / v[1]) for k, v in
+                                   by_kind.items()},
+            "written_per_launch": {k: round(v[3] / v[1]) for k, v in
+                                   by_kind.items()},
+            "launches": {k: v[1] for k, v in by_kind.items()}}
+
+
+# the library's kernel kinds (pg_profile_read names) of each kernel a
+# rank-valuation solve launches
+KERNEL_KINDS = {
+    "k_ng_full": "ng_walk", "k_ng_round": "ng_round",
+    "k_root_full": "root_walk", "k_root_round": "root_round",
+    "k_ps_split": "sort_split", "k_1s_hist": "sort_hist",
+    "k_1s_pass": "sort_pass", "k_scan_reduce": "scan", "k_scan_down": "scan",
+    "k_scan_top": "scan", "k_link_info": "link_info",
+    "k_link_build": "link_build", "k_lr_sum1": "lr_sum1",
+    "k_lr_sumk": "lr_sumk", "k_lr_top": "lr_top", "k_lr_distk": "lr_distk",
+    "k_lr_emit1": "lr_emit1", "k_tsw_stage": "odd_stage",
+    "k_tsw_min": "odd_switch", "k_odd_switch": "odd_switch",
+    "k_even_switch": "even_switch", "k_fill_i32": "fill",
+    "k_fill_u8": "fill", "k_zero3": "fill", "k_1s_base": "scan",
+    "k_sum_dist": "other", "k_rs_upsweep": "sort_hist",
+    "k_rs_downsweep": "sort_pass",
+}
 
 
 def method_min_bytes(n_aug: int, m_aug: int, offset_bytes: int) -> int:
@@ -503,10 +612,22 @@ def main():
                          "instead of inserting dummies (PG_ODD_REGION)")
     ap.add_argument("--mix-games", type=int, default=1024,
                     help="games in the batched/served workload")
+    ap.add_argument("--traffic-summary", metavar="PMC_DIR",
+                    help="only write profiles/traffic_random10M.json from "
+                         "four rocprofv3 --pmc runs under PMC_DIR (c2 and "
+                         "copy runs of FETCH_SIZE and WRITE_SIZE)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device 3 times (a plain "
                          "copy kernel of known size, to scale HBM counters)")
     args = ap.parse_args()
+    if args.traffic_summary:
+        t = traffic_summary(args.traffic_summary, "c2")
+        path = os.path.join(ROOT, "profiles", TRAFFIC_FILES["c2"])
+        with open(path, "w") as f:
+            json.dump(t, f, indent=1)
+            f.write("\n")
+        print(json.dumps(t))
+        return
     if args.copy_calibration:
         import torch
         nbytes = args.copy_calibration << 20
@@ -678,6 +799,19 @@ def main():
             "counter_GBps": (round(it_traffic / it_ev_s / 1e9, 1)
                              if it_traffic and it_ev_s else None),
             "copy_GBps": round(copy_bandwidth(), 1)}
+        # the random-line view: counter bytes are whole 128-byte lines (or
+        # 64-byte halves), so lines per iteration over the rate of random
+        # gathers measured here is the time a pass touching each of those
+        # lines at random would take
+        rg = random_gather_rate()
+        iteration_bytes["random_gather_G_per_s"] = round(
+            rg["gathers_per_s"] / 1e9, 2)
+        if it_traffic and it_ev_s:
+            lines = it_traffic / 128.0
+            floor_s = lines / rg["gathers_per_s"]
+            iteration_bytes["counter_lines_per_iteration"] = round(lines)
+            iteration_bytes["line_floor_us"] = round(floor_s * 1e6, 1)
+            iteration_bytes["line_floor_frac"] = round(floor_s / it_ev_s, 3)
 
     line = {
         "metric": "edges/s per best-response iteration",
