@@ -32,77 +32,149 @@ namespace pgk {
 
 namespace {
 
+// raises *flag when pred holds in a lane of the wave: one atomic per wave
+// at most, and none once the flag reads raised (a million waves' atomics on
+// one address would serialise)
+__device__ __forceinline__ void raise_flag(int32_t *flag, bool pred) {
+  if (__ballot(pred) && (threadIdx.x & (kWave - 1)) == 0 &&
+      __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+    atomicOr(flag, 1);
+}
+
 __device__ __forceinline__ uint64_t color_key(int32_t pri, int32_t v) {
   return ((uint64_t)(uint32_t)pri << 32) | (uint32_t)v;
 }
 
-__global__ void k_or_color_init(const uint8_t *alive, const int32_t *pri,
-                                unsigned long long *col, int64_t n) {
+// Lists of vertices are kept in increasing id order (neighbouring entries
+// then share lines of every per-vertex array): a pass writes one keep flag
+// per entry, an exclusive scan gives each kept entry its place, and
+// k_or_scatter moves it there.
+
+// keep flags for the vertices with a[v] (mode 0), a[v] && !b[v] (mode 1) or
+// !a[v] (mode 2)
+__global__ void k_or_select(int64_t n, const uint8_t *a, const uint8_t *b,
+                            int mode, uint32_t *flag) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < n) col[v] = alive[v] ? color_key(pri[v], (int32_t)v) : 0ull;
+  if (v < n)
+    flag[v] = (mode == 0 ? a[v] != 0 : mode == 1 ? (a[v] && !b[v]) : !a[v])
+                  ? 1u : 0u;
 }
 
-// col[w] = max over live v -> w of col[v]: one relaxation sweep
-__global__ void k_or_color_sweep(const int64_t *off, const int32_t *tgt,
+// keep flags for the entries of lst not yet decided (done[v] == 0)
+__global__ void k_or_undecided(const int32_t *lst, int32_t cnt,
+                               const uint8_t *done, uint32_t *flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cnt) flag[i] = done[lst[i]] ? 0u : 1u;
+}
+
+// out[pos[i]] = the i-th entry (lst[i], or i itself when lst is null) for
+// the entries kept; *total = the number kept
+__global__ void k_or_scatter(const int32_t *lst, int64_t cnt,
+                             const uint32_t *flag, const uint32_t *pos,
+                             int32_t *out, int32_t *total) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cnt) return;
+  if (flag[i]) out[pos[i]] = lst ? lst[i] : (int32_t)i;
+  if (i == cnt - 1) *total = (int32_t)(pos[i] + flag[i]);
+}
+
+// The colouring rounds work on the list of live vertices of X (lst, cnt).
+__global__ void k_or_color_init(const int32_t *lst, int32_t cnt,
+                                const int32_t *pri, unsigned long long *col,
+                                uint8_t *reach, uint8_t *nontriv) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cnt) return;
+  const int32_t v = lst[i];
+  col[v] = color_key(pri[v], v);
+  reach[v] = 0;
+  nontriv[v] = 0;
+}
+
+// col[w] = max over live v -> w of col[v]: one relaxation sweep.  A thread
+// that raises a successor's colour goes on pushing from the first one it
+// raised, up to kChase steps, so a colour runs down a chain of live
+// vertices within one sweep instead of one link per sweep.
+constexpr int kChase = 64;
+
+__global__ void k_or_color_sweep(const int32_t *lst, int32_t cnt,
+                                 const int64_t *off, const int32_t *tgt,
                                  const uint8_t *alive,
-                                 unsigned long long *col, int64_t n,
-                                 int32_t *changed) {
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                                 unsigned long long *col, int32_t *changed) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool ch = false;
-  if (v < n && alive[v]) {
-    const unsigned long long c = col[v];
-    for (int64_t e = off[v]; e < off[v + 1]; ++e) {
-      const int32_t w = tgt[e];
-      if (alive[w] && col[w] < c) {
-        atomicMax(&col[w], c);
-        ch = true;
+  if (i < cnt) {
+    int32_t u = lst[i];
+    unsigned long long c = col[u];
+    for (int step = 0; step < kChase; ++step) {
+      int32_t nx = -1;
+      unsigned long long cn = 0;
+      for (int64_t e = off[u]; e < off[u + 1]; ++e) {
+        const int32_t w = tgt[e];
+        if (alive[w] && col[w] < c) {
+          const unsigned long long old = atomicMax(&col[w], c);
+          if (old < c) {
+            ch = true;
+            if (nx < 0) {
+              nx = w;
+              cn = c;
+            }
+          }
+        }
       }
+      if (nx < 0) break;
+      u = nx;
+      c = cn;
     }
   }
-  if (__ballot(ch) && (threadIdx.x & (kWave - 1)) == 0) atomicOr(changed, 1);
+  raise_flag(changed, ch);
 }
 
-// a colour's root reaches itself; reset of the root flags
-__global__ void k_or_reach_init(const uint8_t *alive,
-                                const unsigned long long *col, uint8_t *reach,
-                                uint8_t *nontriv, int64_t n) {
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n) return;
-  reach[v] = alive[v] && (int64_t)(uint32_t)col[v] == v;
-  nontriv[v] = 0;
+// a colour's root reaches itself
+__global__ void k_or_reach_init(const int32_t *lst, int32_t cnt,
+                                const unsigned long long *col,
+                                uint8_t *reach) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cnt) return;
+  const int32_t v = lst[i];
+  if ((int32_t)(uint32_t)col[v] == v) reach[v] = 1;
 }
 
 // v reaches its colour's root inside its colour when a successor of the
 // same colour does: one sweep
-__global__ void k_or_reach_sweep(const int64_t *off, const int32_t *tgt,
+__global__ void k_or_reach_sweep(const int32_t *lst, int32_t cnt,
+                                 const int64_t *off, const int32_t *tgt,
                                  const uint8_t *alive,
                                  const unsigned long long *col, uint8_t *reach,
-                                 int64_t n, int32_t *changed) {
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                                 int32_t *changed) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool ch = false;
-  if (v < n && alive[v] && !reach[v]) {
-    const unsigned long long c = col[v];
-    for (int64_t e = off[v]; e < off[v + 1]; ++e) {
-      const int32_t w = tgt[e];
-      if (alive[w] && col[w] == c && reach[w]) {
-        reach[v] = 1;
-        ch = true;
-        break;
+  if (i < cnt) {
+    const int32_t v = lst[i];
+    if (!reach[v]) {
+      const unsigned long long c = col[v];
+      for (int64_t e = off[v]; e < off[v + 1]; ++e) {
+        const int32_t w = tgt[e];
+        if (alive[w] && col[w] == c && reach[w]) {
+          reach[v] = 1;
+          ch = true;
+          break;
+        }
       }
     }
   }
-  if (__ballot(ch) && (threadIdx.x & (kWave - 1)) == 0) atomicOr(changed, 1);
+  raise_flag(changed, ch);
 }
 
 // a root's component has an edge when another vertex is in it or the root
 // has a loop
-__global__ void k_or_nontrivial(const int64_t *off, const int32_t *tgt,
-                                const uint8_t *alive,
+__global__ void k_or_nontrivial(const int32_t *lst, int32_t cnt,
+                                const int64_t *off, const int32_t *tgt,
                                 const unsigned long long *col,
-                                const uint8_t *reach, uint8_t *nontriv,
-                                int64_t n) {
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n || !alive[v] || !reach[v]) return;
+                                const uint8_t *reach, uint8_t *nontriv) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cnt) return;
+  const int32_t v = lst[i];
+  if (!reach[v]) return;
   const int32_t r = (int32_t)(uint32_t)col[v];
   if (r != v) {
     nontriv[r] = 1;
@@ -115,14 +187,16 @@ __global__ void k_or_nontrivial(const int64_t *off, const int32_t *tgt,
     }
 }
 
-// components with an odd root join the seed; roots of the others leave
-__global__ void k_or_peel(uint8_t *alive, const unsigned long long *col,
-                          const uint8_t *reach, const uint8_t *nontriv,
-                          uint8_t *seed, int64_t n, int32_t *left) {
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool live = false;
-  if (v < n && alive[v]) {
-    live = true;
+// components with an odd root join the seed; roots of the others leave;
+// the vertices still live form the next round's list
+__global__ void k_or_peel(const int32_t *lst, int32_t cnt, uint8_t *alive,
+                          const unsigned long long *col, const uint8_t *reach,
+                          const uint8_t *nontriv, uint8_t *seed,
+                          uint32_t *flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cnt) {
+    const int32_t v = lst[i];
+    bool live = true;
     if (reach[v]) {
       const unsigned long long c = col[v];
       const int32_t r = (int32_t)(uint32_t)c;
@@ -136,51 +210,57 @@ __global__ void k_or_peel(uint8_t *alive, const unsigned long long *col,
         live = false;
       }
     }
+    flag[i] = live ? 1u : 0u;
   }
-  if (__ballot(live) && (threadIdx.x & (kWave - 1)) == 0) atomicOr(left, 1);
 }
 
-// R: v in X with a successor in R (inside X)
-__global__ void k_or_back(const int64_t *off, const int32_t *tgt,
-                          const uint8_t *inx, uint8_t *R, int64_t n,
+// R: v in X with a successor in R (inside X); lst holds X minus R
+__global__ void k_or_back(const int32_t *lst, int32_t cnt, const int64_t *off,
+                          const int32_t *tgt, const uint8_t *inx, uint8_t *R,
                           int32_t *changed) {
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool ch = false;
-  if (v < n && inx[v] && !R[v]) {
-    for (int64_t e = off[v]; e < off[v + 1]; ++e) {
-      const int32_t w = tgt[e];
-      if (inx[w] && R[w]) {
-        R[v] = 1;
-        ch = true;
-        break;
+  if (i < cnt) {
+    const int32_t v = lst[i];
+    if (!R[v]) {
+      for (int64_t e = off[v]; e < off[v + 1]; ++e) {
+        const int32_t w = tgt[e];
+        if (inx[w] && R[w]) {
+          R[v] = 1;
+          ch = true;
+          break;
+        }
       }
     }
   }
-  if (__ballot(ch) && (threadIdx.x & (kWave - 1)) == 0) atomicOr(changed, 1);
+  raise_flag(changed, ch);
 }
 
 // Odd's attractor: an Odd vertex with a successor in A, an Even vertex with
-// every successor in A
-__global__ void k_or_attr(const int64_t *off, const int32_t *tgt,
-                          const uint8_t *owner, uint8_t *A, int64_t n,
-                          int32_t *changed) {
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// every successor in A; lst holds vertices outside A
+__global__ void k_or_attr(const int32_t *lst, int32_t cnt, const int64_t *off,
+                          const int32_t *tgt, const uint8_t *owner,
+                          uint8_t *A, int32_t *changed) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool ch = false;
-  if (v < n && !A[v]) {
-    const bool odd = owner[v] == 1;
-    bool any = false, all = true;
-    for (int64_t e = off[v]; e < off[v + 1]; ++e) {
-      const bool in = A[tgt[e]];
-      any |= in;
-      all &= in;
-      if (odd ? any : !all) break;
-    }
-    if (odd ? any : all) {
-      A[v] = 1;
-      ch = true;
+  if (i < cnt) {
+    const int32_t v = lst[i];
+    if (!A[v]) {
+      const bool odd = owner[v] == 1;
+      bool any = false, all = true;
+      for (int64_t e = off[v]; e < off[v + 1]; ++e) {
+        const bool in = A[tgt[e]];
+        any |= in;
+        all &= in;
+        if (odd ? any : !all) break;
+      }
+      if (odd ? any : all) {
+        A[v] = 1;
+        ch = true;
+      }
     }
   }
-  if (__ballot(ch) && (threadIdx.x & (kWave - 1)) == 0) atomicOr(changed, 1);
+  raise_flag(changed, ch);
 }
 
 __global__ void k_or_keep(const uint8_t *A, uint32_t *keep, int64_t n) {
@@ -224,18 +304,54 @@ __global__ void k_or_newmap(const uint8_t *A, const uint32_t *newid,
   if (v < n) newmap[v] = A[v] ? -1 : (int32_t)newid[v];
 }
 
-// Repeats `sweep` (groups of four, one synchronisation each) until a group
-// changes nothing; fails after `bound` groups.
+// Runs `sweep` over the list (*lst, cnt entries) in groups of four, one
+// synchronisation each, until a group changes nothing or the list is empty.
+// With `done`, the entries decided (done[v] != 0) leave the list after each
+// group (compacted into *spare, then the two swap).  Fails after `bound`
+// groups.
+struct ListBufs {
+  int32_t *a, *b;      // the list and its spare
+  uint32_t *flag, *pos;
+  int32_t *dcnt;
+  void *stmp;          // scan scratch
+};
+
+// keeps the flagged entries of l->a (cnt of them; all ids 0..cnt-1 when
+// `ids`) in order in l->b, swaps the two and queues the new count into
+// *host (valid after the next synchronisation)
+void list_keep(ListBufs *l, int64_t cnt, bool ids, hipStream_t s,
+               int32_t *host) {
+  scan_excl_u32(l->flag, l->pos, cnt, l->stmp, s);
+  hipLaunchKernelGGL(k_or_scatter, dim3(grid_for(cnt)), dim3(kBlock), 0, s,
+                     ids ? nullptr : l->a, cnt, l->flag, l->pos, l->b,
+                     l->dcnt);
+  (void)hipMemcpyAsync(host, l->dcnt, sizeof(int32_t), hipMemcpyDeviceToHost,
+                       s);
+  std::swap(l->a, l->b);
+}
+
 template <class F>
-pg_status fixpoint(pg_game *g, hipStream_t s, int64_t bound, F sweep) {
-  for (int64_t round = 0;; ++round) {
+pg_status fixpoint_list(pg_game *g, hipStream_t s, int64_t bound,
+                        ListBufs *l, int32_t *cnt, const uint8_t *done,
+                        F sweep) {
+  for (int64_t round = 0; *cnt > 0; ++round) {
     if (round > bound)
       return pg_fail(PG_EINTERNAL, "odd-region fixpoint did not converge");
     fill_i32(g->ctr + C_MISC, 0, 1, s);
-    for (int k = 0; k < 4; ++k) sweep(g->ctr + C_MISC);
-    PG_TRY(sync_ctr(g, s));
-    if (g->hctr[C_MISC] == 0) return PG_OK;
+    for (int k = 0; k < 4; ++k) sweep(l->a, *cnt, g->ctr + C_MISC);
+    int32_t h[2] = {0, *cnt};
+    if (done) {
+      hipLaunchKernelGGL(k_or_undecided, dim3(grid_for(*cnt)), dim3(kBlock),
+                         0, s, l->a, *cnt, done, l->flag);
+      list_keep(l, *cnt, false, s, &h[1]);
+    }
+    PG_HIP(hipMemcpyAsync(&h[0], g->ctr + C_MISC, sizeof(int32_t),
+                          hipMemcpyDeviceToHost, s));
+    PG_HIP(hipStreamSynchronize(s));
+    *cnt = h[1];
+    if (h[0] == 0) break;
   }
+  return PG_OK;
 }
 
 }  // namespace
@@ -266,41 +382,78 @@ pg_status odd_region_reduce(pg_game *g, hipStream_t s, int64_t n, int64_t m,
   tmp.p.push_back(seed);
   PG_TRY(dev_alloc(&col, n));
   tmp.p.push_back(col);
+  ListBufs L{};
+  PG_TRY(dev_alloc(&L.a, n));
+  tmp.p.push_back(L.a);
+  PG_TRY(dev_alloc(&L.b, n));
+  tmp.p.push_back(L.b);
+  PG_TRY(dev_alloc(&L.flag, n));
+  tmp.p.push_back(L.flag);
+  PG_TRY(dev_alloc(&L.pos, n));
+  tmp.p.push_back(L.pos);
+  PG_TRY(dev_alloc(&L.dcnt, 1));
+  tmp.p.push_back(L.dcnt);
+  {
+    const size_t need = scan_excl_u32(nullptr, nullptr, n, nullptr, s);
+    PG_TRY(dev_alloc((uint8_t **)&L.stmp, (int64_t)need + 16));
+    tmp.p.push_back(L.stmp);
+  }
+  // the list of the vertices selected from all n (see k_or_select)
+  auto select = [&](const uint8_t *a, const uint8_t *b, int mode,
+                    int32_t *cnt) -> pg_status {
+    hipLaunchKernelGGL(k_or_select, dim3(gn), dim3(kBlock), 0, s, n, a, b,
+                       mode, L.flag);
+    list_keep(&L, n, true, s, cnt);
+    PG_HIP(hipStreamSynchronize(s));
+    return PG_OK;
+  };
   PG_HIP(hipMemcpyAsync(alive, inx, n, hipMemcpyDeviceToDevice, s));
   fill_u8(seed, 0, n, s);
   const int64_t bound = n + 64;
-  // peeling rounds: every round drops at least every colour's root
-  for (int64_t round = 0;; ++round) {
+  // peeling rounds over the live vertices of X: every round drops at least
+  // every colour's root
+  int32_t cnt = 0;
+  PG_TRY(select(inx, nullptr, 0, &cnt));
+  for (int64_t round = 0; cnt > 0; ++round) {
     if (round > n + 1)
       return pg_fail(PG_EINTERNAL, "odd-region peeling did not converge");
-    hipLaunchKernelGGL(k_or_color_init, dim3(gn), dim3(kBlock), 0, s, alive,
-                       pri, col, n);
-    PG_TRY(fixpoint(g, s, bound, [&](int32_t *ch) {
-      hipLaunchKernelGGL(k_or_color_sweep, dim3(gn), dim3(kBlock), 0, s, off,
-                         tgt, alive, col, n, ch);
+    const unsigned gc = grid_for(cnt);
+    hipLaunchKernelGGL(k_or_color_init, dim3(gc), dim3(kBlock), 0, s, L.a,
+                       cnt, pri, col, reach, nontriv);
+    PG_TRY(fixpoint_list(g, s, bound, &L, &cnt, nullptr,
+                         [&](const int32_t *l, int32_t c, int32_t *ch) {
+      hipLaunchKernelGGL(k_or_color_sweep, dim3(grid_for(c)), dim3(kBlock), 0,
+                         s, l, c, off, tgt, alive, col, ch);
     }));
-    hipLaunchKernelGGL(k_or_reach_init, dim3(gn), dim3(kBlock), 0, s, alive,
-                       col, reach, nontriv, n);
-    PG_TRY(fixpoint(g, s, bound, [&](int32_t *ch) {
-      hipLaunchKernelGGL(k_or_reach_sweep, dim3(gn), dim3(kBlock), 0, s, off,
-                         tgt, alive, col, reach, n, ch);
+    hipLaunchKernelGGL(k_or_reach_init, dim3(gc), dim3(kBlock), 0, s, L.a,
+                       cnt, col, reach);
+    PG_TRY(fixpoint_list(g, s, bound, &L, &cnt, nullptr,
+                         [&](const int32_t *l, int32_t c, int32_t *ch) {
+      hipLaunchKernelGGL(k_or_reach_sweep, dim3(grid_for(c)), dim3(kBlock), 0,
+                         s, l, c, off, tgt, alive, col, reach, ch);
     }));
-    hipLaunchKernelGGL(k_or_nontrivial, dim3(gn), dim3(kBlock), 0, s, off,
-                       tgt, alive, col, reach, nontriv, n);
-    fill_i32(g->ctr + C_MISC, 0, 1, s);
-    hipLaunchKernelGGL(k_or_peel, dim3(gn), dim3(kBlock), 0, s, alive, col,
-                       reach, nontriv, seed, n, g->ctr + C_MISC);
-    PG_TRY(sync_ctr(g, s));
-    if (g->hctr[C_MISC] == 0) break;
+    hipLaunchKernelGGL(k_or_nontrivial, dim3(gc), dim3(kBlock), 0, s, L.a,
+                       cnt, off, tgt, col, reach, nontriv);
+    hipLaunchKernelGGL(k_or_peel, dim3(gc), dim3(kBlock), 0, s, L.a, cnt,
+                       alive, col, reach, nontriv, seed, L.flag);
+    int32_t next = 0;
+    list_keep(&L, cnt, false, s, &next);
+    PG_HIP(hipStreamSynchronize(s));
+    cnt = next;
   }
-  // R = what reaches the seed inside X; A = Odd's attractor of R (in place)
-  PG_TRY(fixpoint(g, s, bound, [&](int32_t *ch) {
-    hipLaunchKernelGGL(k_or_back, dim3(gn), dim3(kBlock), 0, s, off, tgt, inx,
-                       seed, n, ch);
+  // R = what reaches the seed inside X (over X minus R); A = Odd's attractor
+  // of R (over the vertices outside A), both in place
+  PG_TRY(select(inx, seed, 1, &cnt));
+  PG_TRY(fixpoint_list(g, s, bound, &L, &cnt, seed,
+                       [&](const int32_t *l, int32_t c, int32_t *ch) {
+    hipLaunchKernelGGL(k_or_back, dim3(grid_for(c)), dim3(kBlock), 0, s, l, c,
+                       off, tgt, inx, seed, ch);
   }));
-  PG_TRY(fixpoint(g, s, bound, [&](int32_t *ch) {
-    hipLaunchKernelGGL(k_or_attr, dim3(gn), dim3(kBlock), 0, s, off, tgt,
-                       owner, seed, n, ch);
+  PG_TRY(select(seed, nullptr, 2, &cnt));
+  PG_TRY(fixpoint_list(g, s, bound, &L, &cnt, seed,
+                       [&](const int32_t *l, int32_t c, int32_t *ch) {
+    hipLaunchKernelGGL(k_or_attr, dim3(grid_for(c)), dim3(kBlock), 0, s, l, c,
+                       off, tgt, owner, seed, ch);
   }));
   uint8_t *A = seed;
   // the game on the vertices kept, rows in their order
