@@ -217,11 +217,12 @@ def tuning_table() -> list:
 
 def solve_noalloc(g: dict, device: bool = False, max_major: int = 0,
                   max_inner: int = 0, best_response: int = PG_BR_SI,
-                  keep_dummies: bool = False) -> dict:
+                  keep_dummies: bool = False, odd_region: bool = False) -> dict:
     """pg_solve_noalloc: load, solve and release in one call that allocates
     no device memory (the library's static scratch), for games of at most
     PG_NOALLOC_MAX_VERTICES vertices and PG_NOALLOC_MAX_EDGES edges.  The
-    caller's outputs are sized 2 n (n_aug <= 2 n) and cut to n_aug."""
+    caller's outputs are sized 2 n (n_aug <= 2 n) and cut to n_aug (to n
+    with ``odd_region``, PG_ODD_REGION)."""
     n = int(g["n"])
     if device:
         import torch
@@ -246,7 +247,8 @@ def solve_noalloc(g: dict, device: bool = False, max_major: int = 0,
         dt = {"u8": np.uint8, "i32": np.int32}
     m = int(arr["targets"].numel() if device else arr["targets"].size)
     flags = (PG_PTR_DEVICE if device else 0) | \
-        (PG_OFFSETS_I32 if off_i32 else 0)
+        (PG_OFFSETS_I32 if off_i32 else 0) | \
+        (PG_ODD_REGION if odd_region else 0)
     oflags = (PG_PTR_DEVICE if device else 0) | \
         (PG_KEEP_DUMMIES if keep_dummies else 0)
     opts = SolveOpts(max_major, max_inner, oflags, best_response, None, None,
@@ -259,7 +261,7 @@ def solve_noalloc(g: dict, device: bool = False, max_major: int = 0,
         n, m, _ptr(arr["offsets"]), _ptr(arr["targets"]), _ptr(arr["owner"]),
         _ptr(arr["pri"]), flags, ctypes.byref(opts), _ptr(winner),
         _ptr(sigma), _ptr(tau), ctypes.byref(st), _stream(device)))
-    na = int(st.n_aug)
+    na = n if odd_region else int(st.n_aug)
     return {"winner": winner, "sigma": sigma[:na], "tau": tau[:na],
             "stats": st.as_dict()}
 

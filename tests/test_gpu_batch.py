@@ -227,3 +227,27 @@ def test_submit_many_int64_offsets_and_empty_call():
         out = _drain(b, list(ts))
     for t, g in zip(ts, games):
         _check(g, out[t])
+
+
+def test_submit_many_tiny_and_degenerate_games():
+    """One-vertex games, self-loops and repeated edges, one player only:
+    submitted together, each finishes with the oracle's result."""
+    games = []
+    for seed in range(12):
+        rng = np.random.Generator(np.random.PCG64(7800 + seed))
+        n = [1, 1, 2, 2, 3, 5, 8, 13, 40, 100, 300, 1000][seed]
+        deg = rng.integers(1, 4, size=n)
+        rows = [np.sort(rng.integers(0, n, size=d)) for d in deg]
+        off = np.zeros(n + 1, np.int64)
+        off[1:] = np.cumsum(deg)
+        p_odd = [0.0, 1.0, 0.5, 1.0, 0.0, 0.5, 0.5, 0.9, 0.5, 0.1, 0.5, 0.5]
+        games.append({"n": n, "m": int(off[-1]), "offsets": off,
+                      "targets": np.concatenate(rows).astype(np.int32),
+                      "owner": (rng.random(n) < p_odd[seed]).astype(np.uint8),
+                      "pri": rng.permutation(n).astype(np.int32)})
+    with Batch(100_000, 600_000) as b:
+        ts = b.submit_many(games)
+        assert all(isinstance(t, int) for t in ts)
+        out = _drain(b, list(ts))
+    for t, g in zip(ts, games):
+        _check(g, out[t])

@@ -169,3 +169,47 @@ def test_flag_conflicts():
         Game.from_dict(g, odd_region=True, preprocess=False)
     assert e.value.status == PG_EINVAL
     assert lib() is not None
+
+
+@pytest.mark.parametrize("case", ["cycles", "random", "all_odd"])
+def test_without_allocation(case):
+    """pg_solve_noalloc with PG_ODD_REGION: the same outputs as a loaded
+    game, n entries in the original ids."""
+    from paper_1705_02313_amd.pg import solve_noalloc
+    if case == "cycles":
+        g = synth.odd_cycles_game(3000, 8120)
+    elif case == "random":
+        g = synth.random_game(20000, 2, 6, 8121, np.int32)
+    else:
+        n = 5
+        g = {"n": n, "m": n, "offsets": np.arange(n + 1, dtype=np.int64),
+             "targets": ((np.arange(n) + 1) % n).astype(np.int32),
+             "owner": np.ones(n, np.uint8),
+             "pri": np.array([0, 2, 7, 4, 6], np.int32)}
+    ref = odd_region.solve(g)
+    out = solve_noalloc(g, odd_region=True)
+    _check(g, out, ref)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_small_and_degenerate_games(seed):
+    """Self-loops, repeated edges, one-vertex games and games whose every
+    vertex is one player's, against the oracle."""
+    rng = np.random.Generator(np.random.PCG64(8200 + seed))
+    n = [1, 2, 3, 7, 40, 300][seed]
+    deg = rng.integers(1, 4, size=n)
+    rows = [np.sort(rng.integers(0, n, size=d)) for d in deg]   # loops, repeats
+    off = np.zeros(n + 1, np.int64)
+    off[1:] = np.cumsum(deg)
+    own = (rng.random(n) < [0.5, 1.0, 0.0, 0.7, 0.9, 0.6][seed]).astype(
+        np.uint8)
+    g = {"n": n, "m": int(off[-1]), "offsets": off,
+         "targets": np.concatenate(rows).astype(np.int32), "owner": own,
+         "pri": rng.permutation(n).astype(np.int32)}
+    ref = odd_region.solve(g)
+    game = Game.from_dict(g, odd_region=True)
+    try:
+        out = game.solve()
+    finally:
+        game.free()
+    _check(g, out, ref)
