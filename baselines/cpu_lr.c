@@ -12,11 +12,14 @@
  * a vertex whose play reaches a cycle gets KEY_TOP.  Steps:
  *   1. ng(v), the nearest vertex after v on its play with a larger
  *      priority (the sink, or TOP when the play closes a cycle first),
- *      for vertices in increasing priority order: a walk jumps over a
- *      smaller vertex u straight to ng(u), which is already known;
- *   2. fates (finite or top) in decreasing priority order;
- *   3. children grouped by parent (a counting sort over the vertices taken
- *      in signed-priority order, so siblings come in that order);
+ *      all vertices in parallel, handed out in increasing priority order:
+ *      a walk jumps over a smaller vertex u straight to ng(u) when that is
+ *      known already, and steps to u's successor otherwise;
+ *   2. fates (finite or top) in parallel, in decreasing priority order;
+ *   3. children grouped by parent, siblings in signed-priority order
+ *      (group sizes counted in parallel; the sink's children compacted from
+ *      the signed order; the other groups filled by atomic slots and sorted
+ *      by signed position);
  *   4. the Euler list of the tree (section 5, "Formal reduction"), built in
  *      parallel: enter and leave elements per vertex, each vertex's
  *      in-order point marked on one element;
@@ -35,6 +38,11 @@
 #define STRIDE 64
 
 enum { CL_OK = 0, CL_ENOMEM = 1, CL_EINADMISSIBLE = 2, CL_EINTERNAL = 3 };
+
+static int cmp_u64(const void *a, const void *b) {
+  const uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+  return x < y ? -1 : x > y;
+}
 
 /*
  * succ[v]: successor of v (-1: the sink); pri: distinct priorities;
@@ -59,45 +67,143 @@ int cl_valuation(int64_t n, const int32_t *succ, const int32_t *pri,
     st = CL_ENOMEM;
     goto out0;
   }
-  /* 1. ng in increasing priority order */
+  /* 1. ng, every vertex in parallel, taken in increasing priority order:
+     a walk jumps over a smaller vertex u straight to ng(u) when ng(u) is
+     already known (everything between u and ng(u) is smaller than u), and
+     steps to u's successor otherwise.  More than n steps mean the walk
+     circles vertices all smaller than v: nothing larger follows (TOP). */
+#pragma omp parallel for schedule(static)
+  for (int64_t v = 0; v < n; ++v) ng[v] = -1;
+  int bad1 = 0;
+#pragma omp parallel for schedule(dynamic, 4096) reduction(| : bad1)
   for (int64_t k = 0; k < n; ++k) {
     const int32_t v = by_pri[k];
     const int32_t pv = pri[v];
     int32_t u = succ[v] < 0 ? N : succ[v];
     int32_t r;
-    for (;;) {
+    for (int64_t steps = 0;; ++steps) {
       if (u == N) { r = N; break; }
       if (u == v) {            /* v is the largest of its cycle */
-        if (pv & 1) { st = CL_EINADMISSIBLE; goto out0; }
+        if (pv & 1) bad1 = 1;
         r = TOP;
         break;
       }
       if (pri[u] > pv) { r = u; break; }
-      const int32_t j = ng[u];  /* u is smaller, so ng[u] is known */
+      if (steps > n) { r = TOP; break; }
+      const int32_t j = __atomic_load_n(&ng[u], __ATOMIC_RELAXED);
       if (j == N || j == TOP) { r = j; break; }
-      u = j;
+      u = j >= 0 ? j : (succ[u] < 0 ? N : succ[u]);
     }
-    ng[v] = r;
+    __atomic_store_n(&ng[v], r, __ATOMIC_RELAXED);
   }
-  /* 2. fates in decreasing priority order */
+  if (bad1) { st = CL_EINADMISSIBLE; goto out0; }
+  /* 2. fates, in parallel in decreasing priority order: a vertex takes the
+     fate of its parent ng(v) (a larger vertex, so mostly known already),
+     following the ng chain while it is not */
   fin[N] = 1;
+#pragma omp parallel for schedule(static)
+  for (int64_t v = 0; v < n; ++v) fin[v] = 2;   /* unknown */
+#pragma omp parallel for schedule(dynamic, 4096)
   for (int64_t k = n - 1; k >= 0; --k) {
     const int32_t v = by_pri[k];
-    const int32_t p = ng[v];
-    fin[v] = p == N ? 1 : (p == TOP ? 0 : fin[p]);
+    int32_t p = ng[v];
+    uint8_t f;
+    for (;;) {
+      if (p == N) { f = 1; break; }
+      if (p == TOP) { f = 0; break; }
+      const uint8_t q = __atomic_load_n(&fin[p], __ATOMIC_RELAXED);
+      if (q != 2) { f = q; break; }
+      p = ng[p];
+    }
+    __atomic_store_n(&fin[v], f, __ATOMIC_RELAXED);
   }
-  /* 3. children by parent, siblings in signed order */
+  /* 3. children by parent, siblings in signed order.  Counts per parent
+     (atomic), their scan; the sink's children (the largest group) taken
+     from the signed order by a per-thread-chunk compaction; every other
+     vertex placed by an atomic slot in its parent's group, each group then
+     sorted by signed position (groups are small) */
   int64_t nf = 0;
-  for (int64_t v = 0; v < n; ++v)
-    if (fin[v]) { ++cnt[ng[v] + 1]; ++nf; }
-  for (int64_t p = 0; p <= n; ++p) cnt[p + 1] += cnt[p];  /* starts */
-  memcpy(fill, cnt, sizeof(int64_t) * (size_t)(n + 1));
-  for (int64_t k = 0; k < n; ++k) {
-    const int32_t v = by_signed[k];
-    if (!fin[v]) continue;
-    const int64_t i = fill[ng[v]]++;
-    kids[i] = v;
-    pos[v] = (int32_t)i;
+  {
+    uint64_t *tmp = malloc(sizeof(uint64_t) * (size_t)(n + 1));
+    int32_t *sr = malloc(sizeof(int32_t) * (size_t)(n + 1));
+    const int T = omp_get_max_threads();
+    int64_t *chunk = calloc((size_t)T + 1, sizeof(int64_t));
+    if (!tmp || !sr || !chunk) {
+      free(tmp);
+      free(sr);
+      free(chunk);
+      st = CL_ENOMEM;
+      goto out0;
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < n; ++k) sr[by_signed[k]] = (int32_t)k;
+    int64_t sink_kids = 0;   /* counted apart: one shared counter would
+                                serialise most of the increments */
+#pragma omp parallel for schedule(static) reduction(+ : sink_kids)
+    for (int64_t v = 0; v < n; ++v) {
+      if (!fin[v]) continue;
+      if (ng[v] == N) ++sink_kids;
+      else __atomic_fetch_add(&cnt[ng[v] + 1], 1, __ATOMIC_RELAXED);
+    }
+    cnt[N + 1] = sink_kids;
+    for (int64_t q = 0; q <= n; ++q) cnt[q + 1] += cnt[q];
+    nf = cnt[n + 1];
+    /* the sink's children in signed order */
+#pragma omp parallel
+    {
+      const int nt = omp_get_num_threads();
+      for (int t = omp_get_thread_num(); t < T; t += nt) {
+        int64_t c = 0;
+        for (int64_t k = n * t / T; k < n * (t + 1) / T; ++k) {
+          const int32_t v = by_signed[k];
+          c += fin[v] && ng[v] == N;
+        }
+        chunk[t + 1] = c;
+      }
+    }
+    for (int t = 0; t < T; ++t) chunk[t + 1] += chunk[t];
+#pragma omp parallel
+    {
+      const int nt = omp_get_num_threads();
+      for (int t = omp_get_thread_num(); t < T; t += nt) {
+        int64_t i = cnt[N] + chunk[t];
+        for (int64_t k = n * t / T; k < n * (t + 1) / T; ++k) {
+          const int32_t v = by_signed[k];
+          if (fin[v] && ng[v] == N) tmp[i++] = ((uint64_t)k << 32) | (uint32_t)v;
+        }
+      }
+    }
+    /* the other groups: a slot each, then each group sorted */
+    memcpy(fill, cnt, sizeof(int64_t) * (size_t)(n + 1));
+#pragma omp parallel for schedule(static)
+    for (int64_t v = 0; v < n; ++v) {
+      if (!fin[v] || ng[v] == N) continue;
+      const int64_t i = __atomic_fetch_add(&fill[ng[v]], 1, __ATOMIC_RELAXED);
+      tmp[i] = ((uint64_t)(uint32_t)sr[v] << 32) | (uint32_t)v;
+    }
+#pragma omp parallel for schedule(dynamic, 1024)
+    for (int64_t q = 0; q < n; ++q) {
+      const int64_t a = cnt[q], b = cnt[q + 1];
+      if (b - a > 32) {
+        qsort(tmp + a, (size_t)(b - a), sizeof(uint64_t), cmp_u64);
+      } else {
+        for (int64_t i = a + 1; i < b; ++i) {   /* insertion sort */
+          const uint64_t x = tmp[i];
+          int64_t j = i - 1;
+          while (j >= a && tmp[j] > x) { tmp[j + 1] = tmp[j]; --j; }
+          tmp[j + 1] = x;
+        }
+      }
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < nf; ++i) {
+      const int32_t v = (int32_t)(uint32_t)tmp[i];
+      kids[i] = v;
+      pos[v] = (int32_t)i;
+    }
+    free(tmp);
+    free(sr);
+    free(chunk);
   }
   /* 4. the Euler list: 0/1 enter/leave the sink, 2i+2/2i+3 enter/leave
      kids[i]; y = node | (weight << 31) */
