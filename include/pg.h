@@ -447,8 +447,14 @@ pg_status pg_profile_read(const pg_game *game, int32_t kind, const char **name,
  *                  step.
  * pg_batch_poll    done = 1 once the game has finished; then writes its
  *                  winner (n), sigma and tau (n_aug, as pg_solve) and
- *                  stats, and releases the ticket.  flags: PG_PTR_DEVICE for
- *                  device output buffers.
+ *                  stats, and releases the ticket.  With winner, sigma and
+ *                  tau all NULL it only reports done and stats and keeps the
+ *                  ticket (a query, to size the outputs).  flags:
+ *                  PG_PTR_DEVICE for device output buffers.
+ * pg_batch_poll_many  the same for count tickets at once (arrays of
+ *                  output pointers, each array and each entry nullable):
+ *                  one wait for all the copies.  PG_EINVAL for an unknown
+ *                  ticket, before anything is written.
  * pg_batch_finished  tickets of finished games not yet polled (up to
  *                  capacity of them; *count = how many there are).
  * pg_batch_info    games running and queued, current arena size.
@@ -476,6 +482,11 @@ pg_status pg_batch_step(pg_batch *batch, int32_t *n_live, int32_t *n_queued,
 pg_status pg_batch_poll(pg_batch *batch, int64_t ticket, int32_t *done,
                         uint8_t *winner, int32_t *sigma, int32_t *tau,
                         pg_stats *stats, uint32_t flags);
+pg_status pg_batch_poll_many(pg_batch *batch, int32_t count,
+                             const int64_t *tickets, int32_t *done,
+                             uint8_t *const *winner, int32_t *const *sigma,
+                             int32_t *const *tau, pg_stats *stats,
+                             uint32_t flags);
 pg_status pg_batch_finished(const pg_batch *batch, int64_t *tickets,
                             int32_t capacity, int32_t *count);
 pg_status pg_batch_info(const pg_batch *batch, int32_t *n_live,

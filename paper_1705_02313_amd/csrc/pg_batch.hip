@@ -28,6 +28,7 @@
 // freed at the next rebuild, once the step that used them has finished, so a
 // rebuild never waits for the device.
 #include <chrono>
+#include <cstring>
 #include <deque>
 #include <map>
 #include <vector>
@@ -1669,32 +1670,66 @@ pg_status pg_batch_step(pg_batch *b, int32_t *n_live, int32_t *n_queued,
   return PG_OK;
 }
 
+pg_status pg_batch_poll_many(pg_batch *b, int32_t count,
+                             const int64_t *tickets, int32_t *done,
+                             uint8_t *const *winner, int32_t *const *sigma,
+                             int32_t *const *tau, pg_stats *stats,
+                             uint32_t flags) {
+  if (!b || count < 0 || (count > 0 && (!tickets || !done)))
+    return pg_fail(PG_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lock(b->mu);
+  std::vector<BGame *> gs((size_t)count);
+  for (int32_t i = 0; i < count; ++i) {
+    auto it = b->games.find(tickets[i]);
+    if (it == b->games.end()) return pg_fail(PG_EINVAL, "unknown ticket");
+    gs[i] = it->second;
+  }
+  hipStream_t s = b->stream;
+  const bool dev = flags & PG_PTR_DEVICE;
+  // what each finished game hands out (nothing: a query that keeps it)
+  auto sizes = [&](int32_t i, size_t *wb, size_t *sb, size_t *tb) {
+    const BGame *g = gs[i];
+    *wb = winner && winner[i] ? (size_t)g->g->n : 0;
+    *sb = sigma && sigma[i] ? sizeof(int32_t) * (size_t)g->g->n_aug : 0;
+    *tb = tau && tau[i] ? sizeof(int32_t) * (size_t)g->g->n_aug : 0;
+  };
+  for (int32_t i = 0; i < count; ++i) {
+    done[i] = gs[i]->state == B_DONE;
+    if (stats) stats[i] = gs[i]->st;
+  }
+  // every copy on the batch's stream, then one wait
+  for (int32_t i = 0; i < count; ++i) {
+    if (!done[i]) continue;
+    const BGame *g = gs[i];
+    size_t wb, sb, tb;
+    sizes(i, &wb, &sb, &tb);
+    if (wb) PG_TRY(copy_out(winner[i], g->res_winner, wb, dev, s));
+    if (sb) PG_TRY(copy_out(sigma[i], g->res_sigma, sb, dev, s));
+    if (tb) PG_TRY(copy_out(tau[i], g->res_tau, tb, dev, s));
+  }
+  PG_HIP(hipStreamSynchronize(s));
+  for (int32_t i = 0; i < count; ++i) {
+    if (!done[i]) continue;
+    BGame *g = gs[i];
+    size_t wb, sb, tb;
+    sizes(i, &wb, &sb, &tb);
+    if (wb + sb + tb == 0) continue;   // a query: the ticket stays
+    g->polled = true;
+    if (!g->in_arena) {
+      b->games.erase(g->ticket);
+      PoolScope ps(&b->pool);
+      free_bgame(g);
+    }  // else: still laid out in the arena; released at the next rebuild
+  }
+  return PG_OK;
+}
+
 pg_status pg_batch_poll(pg_batch *b, int64_t ticket, int32_t *done,
                         uint8_t *winner, int32_t *sigma, int32_t *tau,
                         pg_stats *stats, uint32_t flags) {
   if (!b || !done) return pg_fail(PG_EINVAL, "NULL argument");
-  std::lock_guard<std::mutex> lock(b->mu);
-  auto it = b->games.find(ticket);
-  if (it == b->games.end()) return pg_fail(PG_EINVAL, "unknown ticket");
-  BGame *g = it->second;
-  *done = g->state == B_DONE;
-  if (stats) *stats = g->st;
-  if (!*done) return PG_OK;
-  hipStream_t s = b->stream;
-  const bool dev = flags & PG_PTR_DEVICE;
-  if (winner) PG_TRY(copy_out(winner, g->res_winner, g->g->n, dev, s));
-  if (sigma)
-    PG_TRY(copy_out(sigma, g->res_sigma, sizeof(int32_t) * g->g->n_aug, dev, s));
-  if (tau)
-    PG_TRY(copy_out(tau, g->res_tau, sizeof(int32_t) * g->g->n_aug, dev, s));
-  PG_HIP(hipStreamSynchronize(s));
-  g->polled = true;
-  if (!g->in_arena) {
-    b->games.erase(it);
-    PoolScope ps(&b->pool);
-    free_bgame(g);
-  }  // else: still laid out in the arena; released at the next rebuild
-  return PG_OK;
+  return pg_batch_poll_many(b, 1, &ticket, done, &winner, &sigma, &tau,
+                            stats, flags);
 }
 
 pg_status pg_batch_finished(const pg_batch *b, int64_t *tickets,

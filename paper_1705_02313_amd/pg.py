@@ -37,7 +37,7 @@ EXPORTS = ["pg_load_csr", "pg_game_info", "pg_count_info", "pg_export_game",
            "pg_best_response",
            "pg_solve", "pg_profile_enable", "pg_profile_kinds",
            "pg_profile_read", "pg_batch_create", "pg_batch_submit",
-           "pg_batch_submit_many",
+           "pg_batch_submit_many", "pg_batch_poll_many",
            "pg_batch_step", "pg_batch_poll", "pg_batch_finished",
            "pg_batch_info", "pg_batch_free",
            "pg_free", "pg_release_cache", "pg_solve_noalloc",
@@ -146,6 +146,7 @@ def lib() -> ctypes.CDLL:
                                       ctypes.POINTER(I64)]
         L.pg_batch_submit_many.argtypes = [P, I32, P, P, P, P, P, P, U32, P,
                                            P]
+        L.pg_batch_poll_many.argtypes = [P, I32, P, P, P, P, P, P, U32]
         L.pg_batch_step.argtypes = [P] + [ctypes.POINTER(I32)] * 3
         L.pg_batch_poll.argtypes = [P, I64, ctypes.POINTER(I32), P, P, P,
                                     ctypes.POINTER(Stats), U32]
@@ -186,6 +187,17 @@ def _ptr(x):
     if _is_torch(x):
         return ctypes.c_void_p(x.data_ptr())
     return x.ctypes.data_as(ctypes.c_void_p)
+
+
+def _pinned_bytes(nbytes: int) -> np.ndarray:
+    """A uint8 array of nbytes in pinned host memory (torch's caching host
+    allocator), or in ordinary memory when that is not available."""
+    try:
+        import torch
+        return torch.empty(max(nbytes, 1), dtype=torch.uint8,
+                           pin_memory=True).numpy()[:nbytes]
+    except (ImportError, RuntimeError):
+        return np.empty(nbytes, np.uint8)
 
 
 def _stream(device: bool):
@@ -630,6 +642,45 @@ class Batch:
                                    ctypes.byref(st), 0))
         return {"winner": winner, "sigma": sigma, "tau": tau,
                 "stats": st.as_dict()}
+
+    def poll_many(self, tickets) -> list:
+        """poll() for several tickets with one wait for all the copies
+        (pg_batch_poll_many): a result dict per finished ticket, None for
+        the others."""
+        tickets = np.ascontiguousarray(tickets, np.int64)
+        cnt = int(tickets.size)
+        if cnt == 0:
+            return []
+        done = np.zeros(cnt, np.int32)
+        st = (Stats * cnt)()
+        _check(lib().pg_batch_poll_many(self._h, cnt, _ptr(tickets),
+                                        _ptr(done), None, None, None, st, 0))
+        outs = [None] * cnt
+        pw = (ctypes.c_void_p * cnt)()
+        ps = (ctypes.c_void_p * cnt)()
+        pt = (ctypes.c_void_p * cnt)()
+        # every output in one pinned host block (the copies then go to it
+        # directly instead of through the runtime's bounce buffers); the
+        # result arrays are views that keep the block alive
+        lay, total = [], 0
+        for i in range(cnt):
+            if done[i]:
+                n, na = int(st[i].n), int(st[i].n_aug)
+                lay.append((i, total, n, na))
+                total += (n + 15) // 16 * 16 + 8 * na
+        buf = _pinned_bytes(total)
+        for i, at, n, na in lay:
+            w = buf[at:at + n]
+            sg = buf[at + (n + 15) // 16 * 16:][:4 * na].view(np.int32)
+            ta = buf[at + (n + 15) // 16 * 16 + 4 * na:][:4 * na].view(
+                np.int32)
+            outs[i] = (w, sg, ta)
+            pw[i], ps[i], pt[i] = (a.ctypes.data for a in outs[i])
+        _check(lib().pg_batch_poll_many(self._h, cnt, _ptr(tickets),
+                                        _ptr(done), pw, ps, pt, st, 0))
+        return [None if o is None else
+                {"winner": o[0], "sigma": o[1], "tau": o[2],
+                 "stats": st[i].as_dict()} for i, o in enumerate(outs)]
 
     def finished(self) -> list:
         """Tickets of finished games not yet polled."""

@@ -93,15 +93,17 @@ def serve(games, arrivals, max_vertices: int, max_edges: int,
                             ticket_of[t] = i
                 info_live, queued, _ = b.step()
                 steps += 1
-                for t in b.finished():
-                    r = b.poll(t)
+                fin = b.finished()
+                rs = b.poll_many(fin) if fin else []
+                now = clock() - t0
+                for t, r in zip(fin, rs):
                     while True:
                         with lock:
                             i = ticket_of.pop(t, None)
                         if i is not None:
                             break
                         time.sleep(1e-5)   # the submitter is storing it
-                    completion[i] = clock() - t0
+                    completion[i] = now
                     if keep_results:
                         results[i] = r
                     done += 1

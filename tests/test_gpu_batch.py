@@ -251,3 +251,37 @@ def test_submit_many_tiny_and_degenerate_games():
         out = _drain(b, list(ts))
     for t, g in zip(ts, games):
         _check(g, out[t])
+
+
+def test_poll_many_and_queries_keep_the_ticket():
+    """pg_batch_poll_many hands out every finished game at once; a poll
+    with no outputs (a query) keeps the ticket, also after the game has
+    left the arena at a rebuild."""
+    games = _mix(10, 7900, nmin=300, nmax=5000)
+    biggest = max(orc.preprocess(g)["n"] for g in games)
+    edges = max(orc.preprocess(g)["m"] for g in games)
+    with Batch(3 * biggest, 3 * edges) as b:
+        ts = b.submit_many(games)
+        # step until everything finished, polling nothing (rebuilds move
+        # finished games out of the arena meanwhile)
+        for _ in range(100000):
+            live, queued, _ = b.step()
+            if live == 0 and queued == 0:
+                break
+        # queries: done, and the tickets stay
+        from paper_1705_02313_amd.pg import Stats, lib
+        import ctypes
+        for t in ts:
+            d = ctypes.c_int32()
+            st = Stats()
+            assert lib().pg_batch_poll(b._h, t, ctypes.byref(d), None, None,
+                                       None, ctypes.byref(st), 0) == 0
+            assert d.value == 1
+        assert sorted(b.finished()) == sorted(ts)
+        res = b.poll_many(ts)
+        assert b.finished() == []
+        with pytest.raises(PgError) as e:
+            b.poll_many(ts[:1])
+        assert e.value.status == PG_EINVAL
+    for g, r in zip(games, res):
+        _check(g, r)
