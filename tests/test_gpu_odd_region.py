@@ -213,3 +213,18 @@ def test_small_and_degenerate_games(seed):
     finally:
         game.free()
     _check(g, out, ref)
+
+
+@pytest.mark.parametrize("config", [1, 6])
+def test_full_size(config):
+    """The 1M-vertex workloads (distinct priorities; 4 repeated priorities,
+    count valuations) with PG_ODD_REGION against the oracle, and the same
+    winners as the dummy path."""
+    g = synth.config_game(config)
+    print(f"odd-region full size config {config} n={g['n']}", flush=True)
+    ref = odd_region.solve(g)
+    with Game.from_dict(g, odd_region=True) as game:
+        out = game.solve()
+    _check(g, out, ref)
+    with Game.from_dict(g) as game:
+        np.testing.assert_array_equal(game.solve()["winner"], ref["winner"])
