@@ -482,7 +482,9 @@ pg_status odd_region_reduce(pg_game *g, hipStream_t s, int64_t n, int64_t m,
   PG_TRY(dev_alloc(&g->or_new, n));
   hipLaunchKernelGGL(k_or_newmap, dim3(gn), dim3(kBlock), 0, s, A, newid,
                      g->or_new, n);
-  if (n2 == 0) {   // Odd wins everything on its own
+  if (n2 == 0) {   // Odd wins everything on its own: an empty game
+    PG_TRY(dev_alloc(&g->off, 1));
+    fill_i32((int32_t *)g->off, 0, 2, s);
     g->n_aug = 0;
     g->m_aug = 0;
     return PG_OK;

@@ -86,6 +86,8 @@ def test_odd_wins_everything():
     game = Game.from_dict(g, odd_region=True)
     try:
         assert game.n_aug == 0 and game.m_aug == 0
+        empty = game.export()
+        assert empty["n"] == 0 and list(empty["offsets"]) == [0]
         out = game.solve()
         with pytest.raises(PgError) as e:
             game.set_tuning(stride0=16)
