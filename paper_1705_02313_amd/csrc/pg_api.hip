@@ -1207,6 +1207,7 @@ pg_status load_game(int64_t n, int64_t m, const void *offsets,
   g->use_graph = !(flags & PG_NO_GRAPH);
   g->host_rl = (flags & PG_HOST_REDUCED_LIST) && !g->dense;
   if (st == PG_OK && !g->dense) apply_tuning(g, tuning_for(g->n_aug));
+  g->mark_top = !g->dense;
   return st;
 }
 
@@ -1323,6 +1324,8 @@ pg_status solve_game(pg_game *g, const pg_solve_opts *opts, uint8_t *winner,
       n_val += rounds;
     } else {
       st = inner_loop(g, o.max_inner, s, &n_val, &n_odd, &tr, &iter_ms);
+      // a best response: its top vertices stay top from here on
+      if (st == PG_OK) mark_top(g, s);
     }
     if (st != PG_OK) break;
     int32_t c = 0;

@@ -15,6 +15,9 @@
 namespace pgk {
 
 constexpr int kBlock = 256;            // threads per block for flat kernels
+// sp[v].y (the priority of v's successor) of a vertex known to stay top for
+// the rest of a solve: its play, and every play through it, is infinite
+constexpr int32_t kTopMark = INT32_MIN;
 constexpr int kWave = 64;              // CDNA wavefront width
 constexpr int kMaxVertices = (1 << 30) - 2;
 
@@ -151,6 +154,9 @@ struct pg_game {
   int64_t n_odd = 0, m_odd = 0;  // Odd vertices and the edges of their rows
   int sort_bits = 0;             // bits of a parent id key (ids 0..n_aug+1)
   bool careful = false;          // PG_CAREFUL_WALKS: host-driven walk rounds
+  // a solve marks, after each best response, the vertices whose valuation
+  // is top (kTopMark); rank valuations of single games
+  bool mark_top = false;
   // PG_HOST_REDUCED_LIST: the host ranks the level-1 reduced list (pinned
   // next, sum and base arrays in h_rl)
   bool host_rl = false;
@@ -405,6 +411,9 @@ pg_status redo_valuation(pg_game *g, hipStream_t s);
 pg_status valuation_status(pg_game *g);
 // One All_Odd (odd = true) or All_Even step on g->sp from g->key.
 pg_status switch_device(pg_game *g, bool odd, hipStream_t s, int32_t *count);
+// marks the vertices whose valuation (the best response's) is top, for
+// later walks to stop at (g->mark_top games; see k_mark_top)
+void mark_top(pg_game *g, hipStream_t s);
 // One best-response iteration (valuation, then All_Odd) with a single
 // host synchronisation; returns the number of Odd switches and (nullable)
 // the finite vertices, the sink included.  g->last_ms receives the

@@ -66,7 +66,13 @@ __device__ __forceinline__ int32_t ng_walk(int32_t N, const int2 *sp,
       continue;
     }
     const int32_t c = ld_relaxed(&cand[u]);
-    u = (c >= 0) ? c : sp[u].x;
+    if (c >= 0) {
+      u = c;
+    } else {
+      const int2 su = sp[u];
+      if (su.y == kTopMark) return N + 1;   // on into a known top part
+      u = su.x;
+    }
   }
   *u_io = u;
   return -1;
@@ -101,6 +107,9 @@ __global__ __launch_bounds__(kBlock) void k_ng_full(
     int lam = 1, power = 1;
     for (int st = 0; st < steps; ++st) {
       if (u == N) { res = N; break; }
+      // the successor is known to stay top (a solve marks those after each
+      // best response, Theorem 1): so is every play through it
+      if (pu == kTopMark) { res = N + 1; break; }
       if (u == v) {
         // back at v: v has the largest priority of its cycle, which must be
         // even for an admissible sigma (section 3)
@@ -597,6 +606,20 @@ __global__ __launch_bounds__(kBlock) void k_lr_emit1(
 // ---------------------------------------------------------------------------
 // Each thread takes one vertex of the player from a compacted list and reads
 // its row four targets at a time, so that four key gathers are in flight.
+// After a best response (Algorithm 1, the inner loop ended with no Odd
+// switch) a vertex whose valuation is top stays top for the rest of the
+// solve: Even's switches only raise valuations (Theorem 1, second item) and
+// every later valuation is at least the best response's (section 3, "Best
+// responses").  Its successor is then top too (for an Odd vertex every
+// successor is, or Odd would have a better one; an Even vertex never
+// switches away from top), so marking sp[v].y lets a later walk stop as
+// soon as it reaches such a vertex.
+__global__ void k_mark_top(int32_t N, const uint8_t *__restrict__ rs,
+                           int2 *sp) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < N && rs[v] == 2) sp[v].y = kTopMark;
+}
+
 constexpr int kRowBatch = 4;
 
 // All_Odd (section 4): the first successor of least key, if strictly below
@@ -610,10 +633,12 @@ __global__ __launch_bounds__(kBlock) void k_odd_switch(
   if (ctr[C_ABORT]) return;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool sw = false;
-  if (t < count) {
+  const int2 me = t < count ? sp[ids[t]] : make_int2(0, kTopMark);
+  // a vertex known to stay top has only top successors: no switch
+  if (me.y != kTopMark) {
     const int32_t v = ids[t];
     const int64_t e0 = off[v], e1 = off[v + 1];
-    const int32_t cur = sp[v].x;
+    const int32_t cur = me.x;
     // the current choice is normally in the row: its key comes with the
     // row's gathers (a strategy given at the C ABI may name another vertex)
     int32_t kc = 0;
@@ -651,10 +676,12 @@ __global__ __launch_bounds__(kBlock) void k_even_switch(
     int32_t *ctr) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool sw = false;
-  if (t < count) {
+  const int2 me = t < count ? sp[ids[t]] : make_int2(0, kTopMark);
+  // a vertex known to stay top keeps its choice (nothing is above top)
+  if (me.y != kTopMark) {
     const int32_t v = ids[t];
     const int64_t e0 = off[v], e1 = off[v + 1];
-    const int32_t cur = sp[v].x;
+    const int32_t cur = me.x;
     // the current choice is the sink or normally in the row (see All_Odd)
     int32_t best = N;
     int32_t kb = key[N];
@@ -1117,6 +1144,13 @@ pg_status valuation_device(pg_game *g, hipStream_t s, int64_t *n_finite_out) {
 pg_status iteration_device(pg_game *g, hipStream_t s, int32_t *count,
                            int64_t *n_finite) {
   return run_valuation(g, s, true, count, n_finite);
+}
+
+void mark_top(pg_game *g, hipStream_t s) {
+  const int32_t N = (int32_t)g->n_aug;
+  if (!g->mark_top || N == 0) return;
+  PG_LAUNCH(&g->prof, K_OTHER, 9.0 * N, k_mark_top, dim3(grid_for(N)),
+            dim3(kBlock), 0, s, N, g->rs, g->sp);
 }
 
 pg_status switch_device(pg_game *g, bool odd, hipStream_t s, int32_t *count) {
