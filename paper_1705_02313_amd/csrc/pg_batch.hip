@@ -228,11 +228,13 @@ __global__ __launch_bounds__(kBlock) void k_batch_odd(
   if (t < count) {
     const int32_t v = ids[t];
     s = gid[v];
-    if (run[s]) {
+    const int2 me = sp[v];
+    // a vertex known to stay top has only top successors: no switch
+    if (run[s] && me.y != kTopMark) {
       const int64_t e0 = off[v], e1 = off[v + 1];
       // the current choice's key comes with the row's gathers when it is in
       // the row (it always is in a batch: strategies start from the rows)
-      const int32_t cur = sp[v].x;
+      const int32_t cur = me.x;
       int32_t kc = 0;
       bool have_kc = false;
       int32_t best = -1, kb = 0;
@@ -272,10 +274,12 @@ __global__ __launch_bounds__(kBlock) void k_batch_even(
   if (t < count) {
     const int32_t v = ids[t];
     s = gid[v];
-    if (pending[s]) {
+    const int2 me = sp[v];
+    // a vertex known to stay top keeps its choice
+    if (pending[s] && me.y != kTopMark) {
       const int64_t e0 = off[v], e1 = off[v + 1];
       // the current choice is the sink or in the row (see k_batch_odd)
-      const int32_t cur = sp[v].x;
+      const int32_t cur = me.x;
       int32_t best = N, kb = key[N];
       int32_t kc = kb;
       bool have_kc = cur == N;
@@ -317,6 +321,18 @@ __global__ void k_batch_ctl1(int G, const uint8_t *run, const int32_t *cnt_odd,
     pending[s] = 1;
     n_major[s] += 1;
   }
+}
+
+// The games whose inner loop ended this step (a best response) mark their
+// top vertices, as a single solve does (see k_mark_top): later walks stop
+// at them.  A rebuild writes the successor records afresh (no marks).
+__global__ void k_batch_mark(int32_t N, const int32_t *__restrict__ gid,
+                             const uint8_t *__restrict__ pending,
+                             const uint8_t *__restrict__ rs, int2 *sp,
+                             const int32_t *ctr) {
+  if (ctr[C_ABORT]) return;
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < N && rs[v] == 2 && pending[gid[v]]) sp[v].y = kTopMark;
 }
 
 // Per game, after All_Even: no Even switch finishes the game.
@@ -948,6 +964,9 @@ void enqueue_step_rest(pg_batch *b, hipStream_t s) {
   hipLaunchKernelGGL(k_batch_ctl1, dim3(grid_for(G)), dim3(kBlock), 0, s, G,
                      b->d_run, b->d_cnt_odd, b->d_pending, b->d_nval,
                      b->d_nmaj, a->ctr);
+  if (N > 0)
+    hipLaunchKernelGGL(k_batch_mark, dim3(grid_for(N)), dim3(kBlock), 0, s, N,
+                       b->d_gid, b->d_pending, a->rs, a->sp, a->ctr);
   const int64_t ne = N - a->n_odd;
   if (ne > 0)
     hipLaunchKernelGGL(k_batch_even, dim3(grid_for(ne)), dim3(kBlock), 0, s,
