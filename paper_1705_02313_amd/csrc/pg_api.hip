@@ -1207,7 +1207,7 @@ pg_status load_game(int64_t n, int64_t m, const void *offsets,
   g->use_graph = !(flags & PG_NO_GRAPH);
   g->host_rl = (flags & PG_HOST_REDUCED_LIST) && !g->dense;
   if (st == PG_OK && !g->dense) apply_tuning(g, tuning_for(g->n_aug));
-  g->mark_top = !g->dense;
+  g->mark_top = true;
   return st;
 }
 

@@ -155,7 +155,7 @@ struct pg_game {
   int sort_bits = 0;             // bits of a parent id key (ids 0..n_aug+1)
   bool careful = false;          // PG_CAREFUL_WALKS: host-driven walk rounds
   // a solve marks, after each best response, the vertices whose valuation
-  // is top (kTopMark); rank valuations of single games
+  // is top (kTopMark); single games (a batch marks in its own step)
   bool mark_top = false;
   // PG_HOST_REDUCED_LIST: the host ranks the level-1 reduced list (pinned
   // next, sum and base arrays in h_rl)

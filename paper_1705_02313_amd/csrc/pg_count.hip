@@ -430,12 +430,14 @@ __global__ __launch_bounds__(kBlock) void k_cnt_odd_switch(
   if (ctr[C_ABORT]) return;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool sw = false;
-  if (t < count) {
+  const int2 me = t < count ? sp[ids[t]] : make_int2(0, kTopMark);
+  // a vertex known to stay top has only top successors: no switch
+  if (me.y != kTopMark) {
     const int32_t v = ids[t];
     const int64_t e0 = off[v], e1 = off[v + 1];
     // the current choice is normally in the row: its valuation comes with
     // the row's loads (a strategy given at the C ABI may name another vertex)
-    const int32_t cur = sp[v].x;
+    const int32_t cur = me.x;
     int32_t cv[D];
     bool ct = false, have_c = false;
     int32_t best = tgt[e0];
@@ -484,12 +486,14 @@ __global__ __launch_bounds__(kBlock) void k_cnt_even_switch(
     int32_t *ctr) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool sw = false;
-  if (t < count) {
+  const int2 me = t < count ? sp[ids[t]] : make_int2(0, kTopMark);
+  // a vertex known to stay top keeps its choice
+  if (me.y != kTopMark) {
     const int32_t v = ids[t];
     const int64_t e0 = off[v], e1 = off[v + 1];
     // the current choice is the sink (the zero vector) or normally in the
     // row (see All_Odd)
-    const int32_t cur = sp[v].x;
+    const int32_t cur = me.x;
     int32_t cv[D] = {};
     bool ct = false, have_c = cur == N;
     int32_t best = N;
