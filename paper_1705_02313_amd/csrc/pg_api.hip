@@ -1333,6 +1333,8 @@ pg_status solve_game(pg_game *g, const pg_solve_opts *opts, uint8_t *winner,
     if (st != PG_OK) break;
     n_even += c;
     if (c == 0) break;
+    // a new inner loop: Even's switches may make finite vertices top
+    fates_reset(g, s);
   }
   if (tr.dhash && tr.n > 0) {
     // the trace is the caller's even when the run stopped early

@@ -328,11 +328,15 @@ __global__ void k_batch_ctl1(int G, const uint8_t *run, const int32_t *cnt_odd,
 // at them.  A rebuild writes the successor records afresh (no marks).
 __global__ void k_batch_mark(int32_t N, const int32_t *__restrict__ gid,
                              const uint8_t *__restrict__ pending,
-                             const uint8_t *__restrict__ rs, int2 *sp,
-                             const int32_t *ctr) {
+                             uint8_t *rs, int2 *sp, const int32_t *ctr) {
   if (ctr[C_ABORT]) return;
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < N && rs[v] == 2 && pending[gid[v]]) sp[v].y = kTopMark;
+  if (v >= N || !pending[gid[v]]) return;
+  if (rs[v] == 2) sp[v].y = kTopMark;
+  // the game's next inner loop starts after its Even switches: its
+  // fates are found afresh (a valuation keeps only the finite fates of
+  // the previous one of the same inner loop)
+  rs[v] = 0;
 }
 
 // Per game, after All_Even: no Even switch finishes the game.

@@ -414,6 +414,10 @@ pg_status switch_device(pg_game *g, bool odd, hipStream_t s, int32_t *count);
 // marks the vertices whose valuation (the best response's) is top, for
 // later walks to stop at (g->mark_top games; see k_mark_top)
 void mark_top(pg_game *g, hipStream_t s);
+// forgets every vertex's fate: at the start of a solve and after each Even
+// switch step (a valuation keeps the finite fates of the previous one of
+// the same inner loop; valuation_reset includes this)
+void fates_reset(pg_game *g, hipStream_t s);
 // One best-response iteration (valuation, then All_Odd) with a single
 // host synchronisation; returns the number of Odd switches and (nullable)
 // the finite vertices, the sink included.  g->last_ms receives the

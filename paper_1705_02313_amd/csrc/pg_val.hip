@@ -91,7 +91,10 @@ __global__ __launch_bounds__(kBlock) void k_ng_full(
   bool pending = false;
   if (i < N) {
     const int32_t v = (int32_t)i;
-    rs[v] = 0;
+    // a vertex finite in the previous valuation of the same inner loop is
+    // finite now (Odd's switches only lower valuations, section 4): its
+    // fate stays; every other fate is found again
+    if (rs[v] != 1) rs[v] = 0;
     rcand[v] = -1;
     // sp[x] = {successor of x, priority of that successor}: the first
     // comparison needs no gather, each further step one
@@ -218,6 +221,8 @@ __global__ __launch_bounds__(kBlock) void k_root_full(
     int32_t r = p;
     if (r < 0) {
       r = -2;                       // ng(v) itself is not resolved yet
+    } else if (rs[v] == 1 && r <= N) {
+      r = N;                        // known finite: no walk to the root
     } else {
       for (int st = 0; st < steps; ++st) {
         if (r >= N) break;
@@ -761,10 +766,15 @@ static int plan_levels(int64_t N, int s0) {
   return k;
 }
 
+void fates_reset(pg_game *g, hipStream_t s) {
+  fill_u8(g->rs, 0, g->n_aug + 1, s, &g->prof);
+}
+
 void valuation_reset(pg_game *g, hipStream_t s) {
   const int64_t N = g->n_aug;
   fill_i32(g->ngp[g->par], -1, N, s, &g->prof);
   fill_i32(g->candp[g->par], -1, N, s, &g->prof);
+  fates_reset(g, s);
 }
 
 // ng and root phases with a fixed number of rounds; nothing is read back.
