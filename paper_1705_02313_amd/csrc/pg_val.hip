@@ -38,6 +38,15 @@ namespace pgk {
 // ---------------------------------------------------------------------------
 // ng: nearest greater vertex along the play
 // ---------------------------------------------------------------------------
+// "Greater" orders vertices by priority, then by id.  With pairwise distinct
+// priorities (rank valuations) the id never decides.  Count valuations use
+// the ng chains only for the fates and for the parity of each cycle's
+// largest priority (the largest vertex of a cycle in this order carries the
+// cycle's largest priority), and for those the order need only be total:
+// with a handful of repeated priorities a strict priority comparison would
+// send every vertex of the largest priority on a walk to the sink or round
+// its cycle, while the id breaks ties about at random on a random game and
+// keeps the chains short.
 // N = n_aug (the sink's id), TOP id = N + 1.  cand[v] of an unresolved v is
 // the next vertex of v's play not yet compared with v; every vertex strictly
 // between v and cand[v] has a smaller priority than v.  Returns ng(v), or -1
@@ -58,7 +67,8 @@ __device__ __forceinline__ int32_t ng_walk(int32_t N, const int2 *sp,
       if (pv & 1) atomicOr(&ctr[C_ERR], ERR_INADMISSIBLE);
       return N + 1;
     }
-    if (pri[u] > pv) return u;
+    const int pu = pri[u];
+    if (pu > pv || (pu == pv && u > v)) return u;   // ties: by id
     const int32_t r = ld_relaxed(&ng[u]);
     if (r >= 0) {
       if (r >= N) return r;  // nothing larger than u (hence v) after u
@@ -104,7 +114,7 @@ __global__ __launch_bounds__(kBlock) void k_ng_full(
     int pu = me.y;
     int32_t res = -1;
     // Brent's cycle detection: a walk that meets its checkpoint again
-    // circles a cycle without v whose priorities are all below v's, so
+    // circles a cycle without v whose vertices are all below v, so
     // nothing after v is larger (ng = TOP)
     int32_t mark = v;
     int lam = 1, power = 1;
@@ -120,7 +130,7 @@ __global__ __launch_bounds__(kBlock) void k_ng_full(
         res = N + 1;
         break;
       }
-      if (pu > pv) { res = u; break; }
+      if (pu > pv || (pu == pv && u > v)) { res = u; break; }   // ties: by id
       if (u == mark) { res = N + 1; break; }
       if (lam == power) {
         mark = u;
@@ -721,21 +731,18 @@ __global__ __launch_bounds__(kBlock) void k_even_switch(
 namespace pgk {
 
 // A wave lasts as long as its longest walk, so the full passes stop early and
-// leave long walks to dense rounds (which also take shortcuts).  The budgets
-// differ by valuation: with distinct priorities most ng values are a few
-// steps away; with a handful of repeated ones the vertices of the largest
-// priority walk to the sink or a cycle, which cheaper, more frequent rounds
-// (more shortcuts published between them) serve better.  Measured on the
-// 10M-vertex games: distinct 2.25 -> 2.22 ms per iteration, 4 priorities
-// 4.47 -> 4.00 ms.
+// leave long walks to dense rounds (which also take shortcuts).  Rank games
+// take their budgets from the game's tuning (per size class, measured).
+// Count games keep fixed ones: with ties broken by id their chains are about
+// as short as with distinct priorities (on the 10M-vertex game with 4
+// priorities the walks went from 773 to 369 us per valuation; before the
+// tie rule, many cheap rounds served best: {4, 32, 4}).
 struct WalkBudget {
   int full;    // plain-walk steps of the full passes
   int walk;    // shortcut-walk steps of one round
   int rounds;  // rounds enqueued without looking back
 };
-// Rank games take theirs from the game's tuning (pg_tune.hip: per size
-// class, measured); count games keep these.
-constexpr WalkBudget kCountWalks = {4, 32, 4};
+constexpr WalkBudget kCountWalks = {32, 32, 2};
 static WalkBudget walk_budget(const pg_game *g) {
   if (g->dense) return kCountWalks;
   return {g->tune.walk_full, g->tune.walk_round, g->tune.walk_rounds};
