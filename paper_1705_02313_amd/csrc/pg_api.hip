@@ -645,8 +645,8 @@ void free_game(pg_game *g) {
   if (!g) return;
   void *ptrs[] = {g->off,      g->tgt,      g->owner,    g->pri,
                   g->perm,     g->rvpos,    g->odd_ids,  g->even_ids,
-                  g->sp,       g->key,      g->ngp[0],   g->ngp[1],
-                  g->candp[0], g->candp[1], g->rcand,    g->wl0,
+                  g->sp,       g->key,      g->ng,       g->cand,
+                  g->rcand,    g->wl0,
                   g->wl1,      g->rs,       g->sk0,      g->sv0,
                   g->sk1,      g->sv1,      g->tile_cnt, g->scan_tmp,
                   g->kids,     g->fh,       g->pos,      g->elem,
@@ -665,8 +665,7 @@ void free_game(pg_game *g) {
   }
   host_free(g->hctr);
   host_free(g->h_rl);
-  for (hipGraphExec_t &ex : g->iter_exec)
-    if (ex) (void)hipGraphExecDestroy(ex);
+  if (g->iter_exec) (void)hipGraphExecDestroy(g->iter_exec);
   if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
   if (g->ev_a) (void)hipEventDestroy(g->ev_a);
   if (g->ev_b) (void)hipEventDestroy(g->ev_b);
@@ -685,10 +684,8 @@ pg_status alloc_state(pg_game *g, int64_t cap) {
   PG_TRY(dev_alloc(&g->rvpos, N));
   PG_TRY(dev_alloc(&g->sp, N + 1));
   PG_TRY(dev_alloc(&g->key, N + 1));
-  for (int k = 0; k < 2; ++k) {
-    PG_TRY(dev_alloc(&g->ngp[k], N));
-    PG_TRY(dev_alloc(&g->candp[k], N));
-  }
+  PG_TRY(dev_alloc(&g->ng, N));
+  PG_TRY(dev_alloc(&g->cand, N));
   PG_TRY(dev_alloc(&g->rcand, N));
   PG_TRY(dev_alloc(&g->wl0, N));
   PG_TRY(dev_alloc(&g->wl1, N));

@@ -686,8 +686,8 @@ struct pg_batch {
   int64_t *d_sw_odd = nullptr, *d_sw_even = nullptr;
   int32_t *d_i32 = nullptr;        // scratch
   // a step (walks, valuation, switches, control, export, the results to
-  // h_res) captured per arena layout and ng/cand pair; dropped at rebuild
-  hipGraphExec_t step_exec[2] = {nullptr, nullptr};
+  // h_res) captured per arena layout; dropped at rebuild
+  hipGraphExec_t step_exec = nullptr;
   bool use_graph = true;
   // steps since the last rebuild: a layout is captured only once it has
   // served kEagerSteps steps (admissions under a steady stream rebuild
@@ -716,11 +716,10 @@ size_t res_off_sweven(int G) { return res_off_swodd(G) + 8 * (size_t)G; }
 size_t res_bytes(int G) { return res_off_sweven(G) + 8 * (size_t)G; }
 
 void drop_step_graphs(pg_batch *b) {
-  for (hipGraphExec_t &ex : b->step_exec)
-    if (ex) {
-      (void)hipGraphExecDestroy(ex);
-      ex = nullptr;
-    }
+  if (b->step_exec) {
+    (void)hipGraphExecDestroy(b->step_exec);
+    b->step_exec = nullptr;
+  }
 }
 
 pg_status batch_alloc(pg_batch *b) {
@@ -997,7 +996,7 @@ void enqueue_step_rest(pg_batch *b, hipStream_t s) {
 }
 
 // One step of every live game: replayed from the graph of the current
-// layout and ng/cand pair (captured at first use after each rebuild), else
+// layout (captured at first use after each rebuild), else
 // launched one kernel at a time; one host synchronisation.  When the bounded
 // walks left vertices open, the careful walks, the valuation and the rest
 // of the step run again (the gated kernels did nothing).
@@ -1007,7 +1006,7 @@ pg_status step_device(pg_batch *b, hipStream_t s) {
   pg_game *a = b->arena;
   bool ran = false;
   if (b->use_graph && b->steps_in_layout++ >= kEagerSteps) {
-    hipGraphExec_t &ex = b->step_exec[a->par];
+    hipGraphExec_t &ex = b->step_exec;
     if (!ex) {
       if (!a->cap_stream &&
           hipStreamCreateWithFlags(&a->cap_stream, hipStreamNonBlocking) !=
@@ -1049,7 +1048,6 @@ pg_status step_device(pg_batch *b, hipStream_t s) {
     enqueue_step_rest(b, s);
     PG_HIP(hipStreamSynchronize(s));
   }
-  a->par ^= 1;
   return valuation_status(a);
 }
 

@@ -162,10 +162,10 @@ struct pg_game {
   bool host_rl = false;
   int32_t *h_rl = nullptr;
   // one best-response iteration (walks, valuation, All_Odd) captured as a
-  // HIP graph per ng/cand pair and replayed (unless PG_NO_GRAPH)
+  // HIP graph and replayed (unless PG_NO_GRAPH)
   bool use_graph = false;
   hipStream_t cap_stream = nullptr;
-  hipGraphExec_t iter_exec[2] = {nullptr, nullptr};
+  hipGraphExec_t iter_exec = nullptr;
   // All_Odd over the bucketed edge layout (pg_switch.hip): the Odd rows'
   // edges in target order (tsw_t) with each edge's slot in its chunk
   // (tsw_slot) and that slot's place in bucket order (tsw_g); per place the
@@ -201,9 +201,8 @@ struct pg_game {
   // [n_aug+1] {successor (the sink is n_aug), priority of that successor}
   int2 *sp = nullptr;
   int32_t *key = nullptr;   // [n_aug+1] valuation keys; n_aug is the sink
-  int32_t *ngp[2] = {nullptr, nullptr};    // [n_aug] nearest greater vertex
-  int32_t *candp[2] = {nullptr, nullptr};  // [n_aug] walk candidates
-  int par = 0;              // which ng/cand pair the next valuation uses
+  int32_t *ng = nullptr;    // [n_aug] nearest greater vertex (-1: open)
+  int32_t *cand = nullptr;  // [n_aug] walk candidates of open vertices
   int32_t *rcand = nullptr; // [n_aug]   root-walk candidates
   int32_t *wl0 = nullptr;   // [n_aug]   staging of host strategies
   int32_t *wl1 = nullptr;   // [n_aug]

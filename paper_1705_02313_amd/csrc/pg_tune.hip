@@ -52,11 +52,10 @@ pg_tuning tuning_for(int64_t n_aug) {
 void apply_tuning(pg_game *g, const pg_tuning &t) {
   g->tune = t;
   // captured iterations carry the old launch shapes: capture again
-  for (hipGraphExec_t &ex : g->iter_exec)
-    if (ex) {
-      (void)hipGraphExecDestroy(ex);
-      ex = nullptr;
-    }
+  if (g->iter_exec) {
+    (void)hipGraphExecDestroy(g->iter_exec);
+    g->iter_exec = nullptr;
+  }
 }
 
 }  // namespace pgk

@@ -142,8 +142,10 @@ __global__ __launch_bounds__(kBlock) void k_ng_full(
       u = su.x;
       pu = su.y;
     }
-    if (res >= 0) ng[v] = res;
-    else cand[v] = u;
+    // every ng entry is written (-1: open), so no valuation clears them;
+    // a candidate is read only while its vertex's ng is open
+    ng[v] = res;
+    if (res < 0) cand[v] = u;
     pending = res < 0;
   }
   if (dist) count_block(dist, pending);
@@ -209,14 +211,13 @@ __device__ __forceinline__ int root_walk(int32_t N, const int32_t *ng,
 // Full pass: a plain walk along the ng chain (one load per step).  Writes
 // the vertex's sort key at its signed-priority position rvpos[v], or at v
 // when rvpos is null (a relabeled game): its parent when finite, N + 1 when
-// top.  Also clears the other ng/cand pair (used by the
-// next valuation) and this valuation's Euler-list per-vertex state.  An
+// top.  Also clears this valuation's Euler-list per-vertex state.  An
 // undecided vertex keeps rs = 0 and records where its walk stopped in rcand
 // (-2: its own ng is still open).  With `dist`, undecided vertices are
 // counted there.
 __global__ __launch_bounds__(kBlock) void k_root_full(
     int32_t N, const int32_t *ng, uint8_t *rs, int32_t *rcand, int32_t *key,
-    int32_t *ctr, int steps, int32_t *ng_next, int32_t *cand_next,
+    int32_t *ctr, int steps,
     uint2 *fh, const int32_t *__restrict__ rvpos, uint32_t *sk,
     int32_t *dist) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -224,8 +225,6 @@ __global__ __launch_bounds__(kBlock) void k_root_full(
   int fate = 0;
   if (i < N) {
     const int32_t v = (int32_t)i;
-    ng_next[v] = -1;
-    cand_next[v] = -1;
     fh[v] = make_uint2(0u, 0u);
     const int32_t p = ng[v];
     int32_t r = p;
@@ -779,8 +778,8 @@ void fates_reset(pg_game *g, hipStream_t s) {
 
 void valuation_reset(pg_game *g, hipStream_t s) {
   const int64_t N = g->n_aug;
-  fill_i32(g->ngp[g->par], -1, N, s, &g->prof);
-  fill_i32(g->candp[g->par], -1, N, s, &g->prof);
+  fill_i32(g->ng, -1, N, s, &g->prof);
+  fill_i32(g->cand, -1, N, s, &g->prof);
   fates_reset(g, s);
 }
 
@@ -788,8 +787,7 @@ void valuation_reset(pg_game *g, hipStream_t s) {
 static void enqueue_walks(pg_game *g, hipStream_t s) {
   const int32_t N = (int32_t)g->n_aug;
   Prof *pf = &g->prof;
-  int32_t *ng = g->ngp[g->par], *cand = g->candp[g->par];
-  int32_t *ngn = g->ngp[g->par ^ 1], *candn = g->candp[g->par ^ 1];
+  int32_t *ng = g->ng, *cand = g->cand;
   const WalkBudget wb = walk_budget(g);
   fill_i32(g->ctr, 0, C_TOTAL, s, pf);
   // own record 8, first successor record 8, result 4; state resets 5
@@ -806,7 +804,7 @@ static void enqueue_walks(pg_game *g, hipStream_t s) {
   const int32_t *rvpos = kernel_rvpos(g);
   PG_LAUNCH(pf, K_ROOT_WALK, (rvpos ? 29.0 : 25.0) * N, k_root_full,
             dim3(grid_for(N, wblk)), dim3(wblk), 0, s, N, ng, g->rs,
-            g->rcand, g->key, g->ctr, wb.full, ngn, candn, g->fh, rvpos,
+            g->rcand, g->key, g->ctr, wb.full, g->fh, rvpos,
             g->sk0, (int32_t *)nullptr);
   for (int r = 1; r <= wb.rounds; ++r)
     PG_LAUNCH(pf, K_ROOT_ROUND, 1.0 * N, k_root_round, dim3(grid_for(N)),
@@ -835,8 +833,7 @@ static pg_status careful_walks(pg_game *g, hipStream_t s) {
   const int32_t N = (int32_t)g->n_aug;
   Prof *pf = &g->prof;
   const WalkBudget wb = walk_budget(g);
-  int32_t *ng = g->ngp[g->par], *cand = g->candp[g->par];
-  int32_t *ngn = g->ngp[g->par ^ 1], *candn = g->candp[g->par ^ 1];
+  int32_t *ng = g->ng, *cand = g->cand;
   fill_i32(ng, -1, N, s, pf);
   fill_i32(cand, -1, N, s, pf);
   fill_i32(g->ctr, 0, C_TOTAL, s, pf);
@@ -862,7 +859,7 @@ static pg_status careful_walks(pg_game *g, hipStream_t s) {
   PG_TRY(counted(g, s, [&](int32_t *dist) {
     PG_LAUNCH(pf, K_ROOT_WALK, (rvpos ? 29.0 : 25.0) * N, k_root_full,
               dim3(grid_for(N, wblk)), dim3(wblk), 0, s, N, ng, g->rs,
-              g->rcand, g->key, g->ctr, wb.full, ngn, candn, g->fh, rvpos,
+              g->rcand, g->key, g->ctr, wb.full, g->fh, rvpos,
               g->sk0, dist);
   }, &open));
   for (int r = 0; open > 0; ++r) {
@@ -1060,8 +1057,7 @@ static pg_status check_ctr(pg_game *g) {
 // One valuation (and, with odd_switch, the All_Odd step after it) with one
 // host synchronisation on the common path.
 // Captures one best-response iteration (fixed sizes and buffers: every size
-// a kernel needs is read on the device) on a private stream, as a graph for
-// the current ng/cand pair.
+// a kernel needs is read on the device) on a private stream, as a graph.
 static pg_status capture_iteration(pg_game *g, hipGraphExec_t *ex) {
   if (!g->cap_stream)
     PG_HIP(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
@@ -1094,7 +1090,7 @@ static pg_status run_valuation(pg_game *g, hipStream_t s, bool odd_switch,
   bool replayed = false;
   if (odd_switch && g->use_graph && !g->careful && !g->prof.on &&
       !g->host_rl) {
-    hipGraphExec_t &ex = g->iter_exec[g->par];
+    hipGraphExec_t &ex = g->iter_exec;
     if (!ex && capture_iteration(g, &ex) != PG_OK) {
       g->use_graph = false;  // capture refused: stay eager from now on
       (void)hipGetLastError();
@@ -1132,7 +1128,6 @@ static pg_status run_valuation(pg_game *g, hipStream_t s, bool odd_switch,
   if (!g->timed ||
       hipEventElapsedTime(&g->last_ms, g->ev_a, g->ev_b) != hipSuccess)
     g->last_ms = 0.0f;
-  g->par ^= 1;
   st = check_ctr(g);
   if (st != PG_OK) return st;
   if (count) *count = g->hctr[C_SWITCH];
