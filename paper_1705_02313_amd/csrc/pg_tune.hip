@@ -20,13 +20,13 @@ struct TuneEntry {
 
 // BEGIN TABLE (tune.py)
 const TuneEntry kTuneTable[] = {
-    {0, {8, 1, 8, 64, 2, 64}},
-    {4096, {8, 1, 12, 128, 2, 256}},
-    {32768, {8, 1, 12, 64, 2, 256}},
-    {262144, {8, 1, 12, 64, 2, 128}},
-    {1048576, {16, 1, 16, 128, 2, 64}},
-    {4194304, {8, 4, 24, 32, 2, 64}},
-    {8388608, {16, 8, 32, 32, 2, 256}},
+    {0, {8, 1, 16, 128, 2, 64}},
+    {4096, {8, 1, 16, 128, 2, 256}},
+    {32768, {8, 1, 8, 128, 2, 256}},
+    {262144, {8, 1, 12, 128, 2, 128}},
+    {1048576, {16, 1, 8, 128, 2, 256}},
+    {4194304, {8, 4, 12, 32, 2, 256}},
+    {8388608, {16, 8, 24, 128, 2, 64}},
 };
 // END TABLE
 constexpr int kTuneEntries = (int)(sizeof(kTuneTable) / sizeof(kTuneTable[0]));
