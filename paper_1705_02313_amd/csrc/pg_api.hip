@@ -646,7 +646,7 @@ void free_game(pg_game *g) {
   void *ptrs[] = {g->off,      g->tgt,      g->owner,    g->pri,
                   g->perm,     g->rvpos,    g->odd_ids,  g->even_ids,
                   g->sp,       g->key,      g->ng,       g->cand,
-                  g->rcand,    g->wl0,
+                  g->rcand,    g->wl0,      g->wl_ng,    g->wl_rt,
                   g->wl1,      g->rs,       g->sk0,      g->sv0,
                   g->sk1,      g->sv1,      g->tile_cnt, g->scan_tmp,
                   g->kids,     g->fh,       g->pos,      g->elem,
@@ -687,6 +687,9 @@ pg_status alloc_state(pg_game *g, int64_t cap) {
   PG_TRY(dev_alloc(&g->ng, N));
   PG_TRY(dev_alloc(&g->cand, N));
   PG_TRY(dev_alloc(&g->rcand, N));
+  g->wl_cap = (N + kDistSlots - 1) / kDistSlots + 2 * kBlock;
+  PG_TRY(dev_alloc(&g->wl_ng, kDistSlots * g->wl_cap));
+  PG_TRY(dev_alloc(&g->wl_rt, kDistSlots * g->wl_cap));
   PG_TRY(dev_alloc(&g->wl0, N));
   PG_TRY(dev_alloc(&g->wl1, N));
   PG_TRY(dev_alloc(&g->rs, N + 1));

@@ -38,7 +38,10 @@ enum Counter : int {
   C_DIST_NF = 32,
   C_DIST_SW = 32 + 1024,
   C_DIST_MISC = 32 + 2048,
-  C_TOTAL = 32 + 3072
+  // lengths of the open-walk lists (one list per slot, see append_block)
+  C_DIST_WLNG = 32 + 3072,
+  C_DIST_WLRT = 32 + 4096,
+  C_TOTAL = 32 + 5120
 };
 constexpr int kDistSlots = 64;
 constexpr int kDistStride = 16;
@@ -204,6 +207,10 @@ struct pg_game {
   int32_t *ng = nullptr;    // [n_aug] nearest greater vertex (-1: open)
   int32_t *cand = nullptr;  // [n_aug] walk candidates of open vertices
   int32_t *rcand = nullptr; // [n_aug]   root-walk candidates
+  // vertices whose ng (wl_ng) or fate (wl_rt) the full pass left open, in
+  // kDistSlots lists of wl_cap entries (see append_block)
+  int32_t *wl_ng = nullptr, *wl_rt = nullptr;
+  int64_t wl_cap = 0;
   int32_t *wl0 = nullptr;   // [n_aug]   staging of host strategies
   int32_t *wl1 = nullptr;   // [n_aug]
   uint8_t *rs = nullptr;    // [n_aug+1] 0 unknown, 1 finite, 2 top
@@ -309,6 +316,47 @@ __device__ __forceinline__ void count_block(int32_t *dist, bool pred) {
   __syncthreads();
   if (threadIdx.x == 0 && blk)
     atomicAdd(&dist[(blockIdx.x % kDistSlots) * kDistStride], blk);
+}
+
+// Adds n (per thread) to the distributed counter at `dist`.  Every thread of
+// the block must call it.
+__device__ __forceinline__ void add_block(int32_t *dist, int32_t n) {
+  __shared__ int32_t blk;
+  if (threadIdx.x == 0) blk = 0;
+  __syncthreads();
+  if (n) atomicAdd(&blk, n);
+  __syncthreads();
+  if (threadIdx.x == 0 && blk)
+    atomicAdd(&dist[(blockIdx.x % kDistSlots) * kDistStride], blk);
+}
+
+// Appends v (where pred holds) to the list of slot blockIdx % kDistSlots,
+// whose length counts at cnt[slot * kDistStride]: one LDS atomic per wave
+// and one device atomic per block, spread over the slots' counters.  A slot
+// receives at most ceil(blocks / kDistSlots) blocks' vertices, so cap =
+// ceil(n / kDistSlots) + 2 * kBlock entries per slot suffice for blocks of
+// up to kBlock threads.  Every thread of the block must call it.
+__device__ __forceinline__ void append_block(int32_t *cnt, int32_t *list,
+                                             int64_t cap, bool pred,
+                                             int32_t v) {
+  __shared__ int32_t s_n, s_base;
+  if (threadIdx.x == 0) s_n = 0;
+  __syncthreads();
+  const uint64_t b = __ballot(pred);
+  const int lane = threadIdx.x & (kWave - 1);
+  int32_t off = 0;
+  if (b) {
+    int32_t wbase = 0;
+    if (lane == 0) wbase = atomicAdd(&s_n, (int32_t)__popcll(b));
+    wbase = __shfl(wbase, 0);
+    off = wbase + (int32_t)__popcll(b & ((1ull << lane) - 1ull));
+  }
+  __syncthreads();
+  const int slot = blockIdx.x % kDistSlots;
+  if (threadIdx.x == 0 && s_n)
+    s_base = atomicAdd(&cnt[slot * kDistStride], s_n);
+  __syncthreads();
+  if (pred) list[(int64_t)slot * cap + s_base + off] = v;
 }
 
 __device__ __forceinline__ int ld_relaxed(const int32_t *p) {

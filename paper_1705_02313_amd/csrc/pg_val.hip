@@ -92,11 +92,12 @@ __device__ __forceinline__ int32_t ng_walk(int32_t N, const int2 *sp,
 // reads of other threads' results).  A vertex that runs out of steps keeps
 // ng = -1 and records where its walk stopped in cand; the rounds pick it up.
 // Also clears this valuation's root-walk state.  With `dist`, the unresolved
-// vertices are counted there (every thread of the block takes part).
+// vertices are counted there; with `wl`, they are listed there for the
+// rounds (every thread of the block takes part in either).
 __global__ __launch_bounds__(kBlock) void k_ng_full(
     int32_t N, const int2 *__restrict__ sp, const int32_t *__restrict__ pri,
     int32_t *ng, int32_t *cand, int32_t *ctr, int steps, uint8_t *rs,
-    int32_t *rcand, int32_t *dist) {
+    int32_t *rcand, int32_t *dist, int32_t *wl, int64_t wl_cap) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool pending = false;
   if (i < N) {
@@ -149,13 +150,15 @@ __global__ __launch_bounds__(kBlock) void k_ng_full(
     pending = res < 0;
   }
   if (dist) count_block(dist, pending);
+  if (wl) append_block(&ctr[C_DIST_WLNG], wl, wl_cap, pending, (int32_t)i);
 }
 
 // A round over every vertex whose ng is still open: its walk continues from
 // its candidate and jumps over other vertices' results and candidates
-// (pointer jumping).  A dense pass (one coalesced read of ng per vertex)
-// instead of a compacted worklist: appending to a shared list serialises on
-// its length counter.  `last`: a vertex still open raises C_ABORT.
+// (pointer jumping).  A dense pass (one coalesced read of ng per vertex),
+// for the host-driven rounds that count the open vertices; the bounded
+// rounds walk the full pass's lists (k_ng_round_list).  `last`: a vertex
+// still open raises C_ABORT.
 __global__ __launch_bounds__(kBlock) void k_ng_round(
     int32_t N, const int2 *__restrict__ sp, const int32_t *__restrict__ pri,
     int32_t *ng, int32_t *cand, int32_t *ctr, int last, int steps,
@@ -175,6 +178,43 @@ __global__ __launch_bounds__(kBlock) void k_ng_round(
   if (last && __ballot(pending) && (threadIdx.x & (kWave - 1)) == 0)
     atomicOr(&ctr[C_ABORT], 1);
   if (dist) count_block(dist, pending);
+}
+
+// The same round over the vertices the full pass listed: on most
+// valuations a few thousand of 10^7 vertices are open after the full pass,
+// and a dense round would read every ng.  The grid holds the same number of
+// blocks for each of the first min(grid, kDistSlots) lists (list_grid);
+// each block takes every parts-th stretch of blockDim entries of its list.
+constexpr int kListBlocks = 32;   // blocks per list at most
+struct ListPart {
+  int slot, part, parts;
+};
+__device__ __forceinline__ ListPart list_part() {
+  const int nslots = gridDim.x < kDistSlots ? (int)gridDim.x : kDistSlots;
+  return {(int)(blockIdx.x % nslots), (int)(blockIdx.x / nslots),
+          (int)(gridDim.x / nslots)};
+}
+
+__global__ __launch_bounds__(kBlock) void k_ng_round_list(
+    int32_t N, const int2 *__restrict__ sp, const int32_t *__restrict__ pri,
+    int32_t *ng, int32_t *cand, int32_t *ctr, int last, int steps,
+    const int32_t *__restrict__ wl, int64_t wl_cap) {
+  const ListPart lp = list_part();
+  const int32_t len = ctr[C_DIST_WLNG + lp.slot * kDistStride];
+  const int32_t *lst = wl + (int64_t)lp.slot * wl_cap;
+  bool open = false;
+  for (int64_t k = (int64_t)lp.part * blockDim.x + threadIdx.x; k < len;
+       k += (int64_t)lp.parts * blockDim.x) {
+    const int32_t v = lst[k];
+    if (ld_relaxed(&ng[v]) < 0) {
+      int32_t u = ld_relaxed(&cand[v]);
+      const int32_t res = ng_walk(N, sp, pri, ng, cand, v, &u, steps, ctr);
+      if (res >= 0) st_relaxed(&ng[v], res);
+      else st_relaxed(&cand[v], u);
+      open |= res < 0;
+    }
+  }
+  if (last && open) atomicOr(&ctr[C_ABORT], 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -214,12 +254,12 @@ __device__ __forceinline__ int root_walk(int32_t N, const int32_t *ng,
 // top.  Also clears this valuation's Euler-list per-vertex state.  An
 // undecided vertex keeps rs = 0 and records where its walk stopped in rcand
 // (-2: its own ng is still open).  With `dist`, undecided vertices are
-// counted there.
+// counted there; with `wl`, listed there for the rounds.
 __global__ __launch_bounds__(kBlock) void k_root_full(
     int32_t N, const int32_t *ng, uint8_t *rs, int32_t *rcand, int32_t *key,
     int32_t *ctr, int steps,
     uint2 *fh, const int32_t *__restrict__ rvpos, uint32_t *sk,
-    int32_t *dist) {
+    int32_t *dist, int32_t *wl, int64_t wl_cap) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) fh[N] = make_uint2(0u, 0u);
   int fate = 0;
@@ -252,6 +292,9 @@ __global__ __launch_bounds__(kBlock) void k_root_full(
   }
   count_block(&ctr[C_DIST_NF], fate == 1);
   if (dist) count_block(dist, i < N && fate == 0);
+  if (wl)
+    append_block(&ctr[C_DIST_WLRT], wl, wl_cap, i < N && fate == 0,
+                 (int32_t)i);
 }
 
 // A round over every undecided vertex (dense, like k_ng_round).
@@ -283,6 +326,40 @@ __global__ __launch_bounds__(kBlock) void k_root_round(
     atomicOr(&ctr[C_ABORT], 1);
   count_block(&ctr[C_DIST_NF], fate == 1);
   if (dist) count_block(dist, pending);
+}
+
+// The same round over the vertices the full pass listed (as
+// k_ng_round_list).
+__global__ __launch_bounds__(kBlock) void k_root_round_list(
+    int32_t N, const int32_t *ng, uint8_t *rs, int32_t *rcand, int32_t *key,
+    int32_t *ctr, int last, int steps, const int32_t *__restrict__ rvpos,
+    uint32_t *sk, const int32_t *__restrict__ wl, int64_t wl_cap) {
+  const ListPart lp = list_part();
+  const int32_t len = ctr[C_DIST_WLRT + lp.slot * kDistStride];
+  const int32_t *lst = wl + (int64_t)lp.slot * wl_cap;
+  bool open = false;
+  int32_t nfin = 0;
+  for (int64_t k = (int64_t)lp.part * blockDim.x + threadIdx.x; k < len;
+       k += (int64_t)lp.parts * blockDim.x) {
+    const int32_t v = lst[k];
+    if (rs[v] == 0) {
+      int32_t r = ld_relaxed(&rcand[v]);
+      const int fate = root_walk(N, ng, rs, rcand, v, &r, steps);
+      if (fate) {
+        __hip_atomic_store(&rs[v], (uint8_t)fate, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        sk[rvpos ? rvpos[v] : v] =
+            fate == 1 ? (uint32_t)ng[v] : (uint32_t)(N + 1);
+        if (fate == 2) key[v] = PG_KEY_TOP;
+        nfin += fate == 1;
+      } else {
+        st_relaxed(&rcand[v], r);
+        open = true;
+      }
+    }
+  }
+  if (last && open) atomicOr(&ctr[C_ABORT], 1);
+  add_block(&ctr[C_DIST_NF], nfin);
 }
 
 // ---------------------------------------------------------------------------
@@ -730,7 +807,7 @@ __global__ __launch_bounds__(kBlock) void k_even_switch(
 namespace pgk {
 
 // A wave lasts as long as its longest walk, so the full passes stop early and
-// leave long walks to dense rounds (which also take shortcuts).  Rank games
+// leave long walks to rounds (which also take shortcuts).  Rank games
 // take their budgets from the game's tuning (per size class, measured).
 // Count games keep fixed ones: with ties broken by id their chains are about
 // as short as with distinct priorities (on the 10M-vertex game with 4
@@ -794,23 +871,33 @@ static void enqueue_walks(pg_game *g, hipStream_t s) {
   const int wblk = walk_block(g);
   PG_LAUNCH(pf, K_NG_WALK, 25.0 * N, k_ng_full, dim3(grid_for(N, wblk)),
             dim3(wblk), 0, s, N, g->sp, g->pri, ng, cand, g->ctr,
-            wb.full, g->rs, g->rcand, (int32_t *)nullptr);
+            wb.full, g->rs, g->rcand, (int32_t *)nullptr, g->wl_ng,
+            g->wl_cap);
+  // the rounds walk the listed vertices only: as many lists as the full
+  // passes fill, each with up to kListBlocks blocks
+  const int64_t fblocks = grid_for(N, wblk);
+  const dim3 lgrid((unsigned)(
+      fblocks <= kDistSlots
+          ? fblocks
+          : kDistSlots *
+                std::min<int64_t>(kListBlocks,
+                                  (fblocks + kDistSlots - 1) / kDistSlots)));
   for (int r = 1; r <= wb.rounds; ++r)
-    PG_LAUNCH(pf, K_NG_ROUND, 4.0 * N, k_ng_round, dim3(grid_for(N)),
-              dim3(kBlock), 0, s, N, g->sp, g->pri, ng, cand, g->ctr,
-              (int)(r == wb.rounds), wb.walk, (int32_t *)nullptr);
+    PG_LAUNCH(pf, K_NG_ROUND, 0.0, k_ng_round_list, lgrid, dim3(kBlock), 0,
+              s, N, g->sp, g->pri, ng, cand, g->ctr, (int)(r == wb.rounds),
+              wb.walk, g->wl_ng, g->wl_cap);
   // own ng 4, parent's ng 4, sort key 4, rs 1 (+ rvpos 4 unless
   // relabeled); resets 12
   const int32_t *rvpos = kernel_rvpos(g);
   PG_LAUNCH(pf, K_ROOT_WALK, (rvpos ? 29.0 : 25.0) * N, k_root_full,
             dim3(grid_for(N, wblk)), dim3(wblk), 0, s, N, ng, g->rs,
             g->rcand, g->key, g->ctr, wb.full, g->fh, rvpos,
-            g->sk0, (int32_t *)nullptr);
+            g->sk0, (int32_t *)nullptr, g->wl_rt, g->wl_cap);
   for (int r = 1; r <= wb.rounds; ++r)
-    PG_LAUNCH(pf, K_ROOT_ROUND, 1.0 * N, k_root_round, dim3(grid_for(N)),
+    PG_LAUNCH(pf, K_ROOT_ROUND, 0.0, k_root_round_list, lgrid,
               dim3(kBlock), 0, s, N, ng, g->rs, g->rcand, g->key, g->ctr,
-              (int)(r == wb.rounds), wb.walk, rvpos, g->sk0,
-              (int32_t *)nullptr);
+              (int)(r == wb.rounds), wb.walk, rvpos, g->sk0, g->wl_rt,
+              g->wl_cap);
   sum_dist(g->ctr, C_DIST_NF, C_NFIN, s, pf);
 }
 
@@ -842,7 +929,8 @@ static pg_status careful_walks(pg_game *g, hipStream_t s) {
   PG_TRY(counted(g, s, [&](int32_t *dist) {
     PG_LAUNCH(pf, K_NG_WALK, 25.0 * N, k_ng_full, dim3(grid_for(N, wblk)),
               dim3(wblk), 0, s, N, g->sp, g->pri, ng, cand, g->ctr,
-              wb.full, g->rs, g->rcand, dist);
+              wb.full, g->rs, g->rcand, dist, (int32_t *)nullptr,
+              (int64_t)0);
   }, &open));
   for (int r = 0; open > 0; ++r) {
     if (r >= kMaxRounds)
@@ -860,7 +948,7 @@ static pg_status careful_walks(pg_game *g, hipStream_t s) {
     PG_LAUNCH(pf, K_ROOT_WALK, (rvpos ? 29.0 : 25.0) * N, k_root_full,
               dim3(grid_for(N, wblk)), dim3(wblk), 0, s, N, ng, g->rs,
               g->rcand, g->key, g->ctr, wb.full, g->fh, rvpos,
-              g->sk0, dist);
+              g->sk0, dist, (int32_t *)nullptr, (int64_t)0);
   }, &open));
   for (int r = 0; open > 0; ++r) {
     if (r >= kMaxRounds)
