@@ -91,13 +91,13 @@ __device__ __forceinline__ int32_t ng_walk(int32_t N, const int2 *sp,
 // Full pass: a plain walk along the play (one 8-byte load per step, no
 // reads of other threads' results).  A vertex that runs out of steps keeps
 // ng = -1 and records where its walk stopped in cand; the rounds pick it up.
-// Also clears this valuation's root-walk state.  With `dist`, the unresolved
+// Also resets the fates it does not keep.  With `dist`, the unresolved
 // vertices are counted there; with `wl`, they are listed there for the
 // rounds (every thread of the block takes part in either).
 __global__ __launch_bounds__(kBlock) void k_ng_full(
     int32_t N, const int2 *__restrict__ sp, const int32_t *__restrict__ pri,
     int32_t *ng, int32_t *cand, int32_t *ctr, int steps, uint8_t *rs,
-    int32_t *rcand, int32_t *dist, int32_t *wl, int64_t wl_cap) {
+    int32_t *dist, int32_t *wl, int64_t wl_cap) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool pending = false;
   if (i < N) {
@@ -105,8 +105,9 @@ __global__ __launch_bounds__(kBlock) void k_ng_full(
     // a vertex finite in the previous valuation of the same inner loop is
     // finite now (Odd's switches only lower valuations, section 4): its
     // fate stays; every other fate is found again
+    // (rcand needs no clearing: the root pass writes it for every vertex
+    // it leaves undecided, and the rounds read it for those only)
     if (rs[v] != 1) rs[v] = 0;
-    rcand[v] = -1;
     // sp[x] = {successor of x, priority of that successor}: the first
     // comparison needs no gather, each further step one
     const int pv = pri[v];
@@ -871,7 +872,7 @@ static void enqueue_walks(pg_game *g, hipStream_t s) {
   const int wblk = walk_block(g);
   PG_LAUNCH(pf, K_NG_WALK, 25.0 * N, k_ng_full, dim3(grid_for(N, wblk)),
             dim3(wblk), 0, s, N, g->sp, g->pri, ng, cand, g->ctr,
-            wb.full, g->rs, g->rcand, (int32_t *)nullptr, g->wl_ng,
+            wb.full, g->rs, (int32_t *)nullptr, g->wl_ng,
             g->wl_cap);
   // the rounds walk the listed vertices only: as many lists as the full
   // passes fill, each with up to kListBlocks blocks
@@ -929,7 +930,7 @@ static pg_status careful_walks(pg_game *g, hipStream_t s) {
   PG_TRY(counted(g, s, [&](int32_t *dist) {
     PG_LAUNCH(pf, K_NG_WALK, 25.0 * N, k_ng_full, dim3(grid_for(N, wblk)),
               dim3(wblk), 0, s, N, g->sp, g->pri, ng, cand, g->ctr,
-              wb.full, g->rs, g->rcand, dist, (int32_t *)nullptr,
+              wb.full, g->rs, dist, (int32_t *)nullptr,
               (int64_t)0);
   }, &open));
   for (int r = 0; open > 0; ++r) {
