@@ -637,6 +637,7 @@ pg_status sync_ctr(pg_game *g, hipStream_t s) {
   PG_HIP(hipMemcpyAsync(g->hctr, g->ctr, sizeof(int32_t) * C_COUNT,
                         hipMemcpyDeviceToHost, s));
   PG_HIP(hipStreamSynchronize(s));
+  fold_switches(g->hctr);
   if (g->prof.on) g->prof.flush();
   return PG_OK;
 }
@@ -1396,7 +1397,7 @@ pg_status solve_game(pg_game *g, const pg_solve_opts *opts, uint8_t *winner,
 constexpr size_t kScratchBytes = size_t(PG_NOALLOC_SCRATCH_MIB) << 20;
 static __device__ __align__(256) uint8_t scratch[kScratchBytes];
 constexpr int kScratchDevices = 64;
-constexpr size_t kScratchHostBytes = 4096;
+constexpr size_t kScratchHostBytes = 16384;   // the counter mirror
 static std::mutex g_scratch_mu;
 static uint8_t *g_scratch_dev[kScratchDevices];
 alignas(256) static uint8_t g_scratch_host[kScratchDevices][kScratchHostBytes];

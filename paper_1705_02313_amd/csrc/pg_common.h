@@ -31,20 +31,31 @@ enum Counter : int {
   C_MISC = 4,         // scratch counter (preprocessing changes, odd count,
                       // open vertices of host-driven walk rounds)
   C_NINNER = 5,       // finite vertices whose parent is not the sink
-  C_COUNT = 32,       // the part copied back to the host
   // Hot counts are spread over kDistSlots slots kDistStride ints apart (one
-  // atomic per block into slot blockIdx % kDistSlots) and summed by one
-  // small kernel: a single address hit by every block serialises.
-  C_DIST_NF = 32,
-  C_DIST_SW = 32 + 1024,
-  C_DIST_MISC = 32 + 2048,
+  // atomic per block into slot blockIdx % kDistSlots) and summed afterwards:
+  // a single address hit by every block serialises.  The switch slots are
+  // summed by the host (fold_switches), the others by a small kernel (a
+  // last-block-done sum inside the producing kernel would need a release
+  // fence per block, which writes back the L2 each time: 10x slower).
+  C_DIST_SW = 32,
+  C_COUNT = 32 + 1024,   // the part copied back to the host
+  C_DIST_NF = C_COUNT,
+  C_DIST_MISC = C_COUNT + 1024,
   // lengths of the open-walk lists (one list per slot, see append_block)
-  C_DIST_WLNG = 32 + 3072,
-  C_DIST_WLRT = 32 + 4096,
-  C_TOTAL = 32 + 5120
+  C_DIST_WLNG = C_COUNT + 2048,
+  C_DIST_WLRT = C_COUNT + 3072,
+  C_TOTAL = C_COUNT + 4096
 };
 constexpr int kDistSlots = 64;
 constexpr int kDistStride = 16;
+
+// After a copy of the first C_COUNT counters to the host: the switch count
+// is the sum of its slots.
+inline void fold_switches(int32_t *hctr) {
+  int32_t s = 0;
+  for (int k = 0; k < kDistSlots; ++k) s += hctr[C_DIST_SW + k * kDistStride];
+  hctr[C_SWITCH] = s;
+}
 
 enum ErrBit : int {
   ERR_INADMISSIBLE = 1,  // a cycle whose largest priority is odd

@@ -776,10 +776,7 @@ static void enqueue_count_switch_t(pg_game *g, bool odd, hipStream_t s,
                                    bool fresh) {
   const int32_t N = (int32_t)g->n_aug;
   Prof *pf = &g->prof;
-  if (!fresh) {
-    fill_i32(g->ctr + C_DIST_SW, 0, kDistSlots * kDistStride, s, pf);
-    fill_i32(g->ctr + C_SWITCH, 0, 1, s, pf);
-  }
+  if (!fresh) fill_i32(g->ctr + C_DIST_SW, 0, kDistSlots * kDistStride, s, pf);
   // per vertex: id 4, two offsets 16, current choice 8 (its row is one of
   // the row's); per edge: target 4, its top flag 1 and its count row 4 D
   if (odd) {
@@ -800,7 +797,7 @@ static void enqueue_count_switch_t(pg_game *g, bool odd, hipStream_t s,
                 N, cnt, g->even_ids, g->off, g->tgt, g->cnt,
                 g->odd_cols, g->pri, g->sp, g->ctr);
   }
-  sum_dist(g->ctr, C_DIST_SW, C_SWITCH, s, pf);
+  // the host sums the switch count's slots when it reads the counters
 }
 
 void enqueue_count_switch(pg_game *g, bool odd, hipStream_t s, bool fresh) {
@@ -824,17 +821,16 @@ static pg_status bf_best_response_t(pg_game *g, hipStream_t s,
     if (r > (int64_t)N + 2)
       return pg_fail(PG_EINTERNAL, "Bellman-Ford did not reach a fixpoint");
     fill_i32(g->ctr + C_DIST_SW, 0, kDistSlots * kDistStride, s, pf);
-    fill_i32(g->ctr + C_SWITCH, 0, 1, s, pf);
     // every vertex: its label and its row's labels; Odd rows dominate
     PG_LAUNCH(pf, K_ODD_SWITCH, (16.0 + 8.0 * D) * N + (4.0 + 4.0 * D) *
                                     g->m_aug,
               k_bf_round<D>, dim3(grid_for(N)), dim3(kBlock), 0, s, N, g->off,
               g->tgt, g->owner, g->pidx, g->sp, g->cnt, g->cnt2, g->odd_cols,
               g->ctr);
-    sum_dist(g->ctr, C_DIST_SW, C_SWITCH, s, pf);
     PG_HIP(hipMemcpyAsync(g->hctr, g->ctr, sizeof(int32_t) * C_COUNT,
                           hipMemcpyDeviceToHost, s));
     PG_HIP(hipStreamSynchronize(s));
+    fold_switches(g->hctr);
     if (g->prof.on) g->prof.flush();
     std::swap(g->cnt, g->cnt2);
     ++r;

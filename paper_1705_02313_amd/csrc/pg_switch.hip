@@ -31,18 +31,6 @@ namespace pgk {
 constexpr int kTswChunk = 32768;   // edges per stage block (128 KiB of LDS)
 constexpr int kTswBucket = 2048;   // Odd vertices per min block
 
-// Adds n (per thread) to the distributed counter at `dist`.  Every thread of
-// the block must call it.
-__device__ __forceinline__ void count_block_n(int32_t *dist, int n) {
-  __shared__ int32_t blk;
-  if (threadIdx.x == 0) blk = 0;
-  __syncthreads();
-  if (n) atomicAdd(&blk, n);
-  __syncthreads();
-  if (threadIdx.x == 0 && blk)
-    atomicAdd(&dist[(blockIdx.x % kDistSlots) * kDistStride], blk);
-}
-
 // ---- layout (load time) ----------------------------------------------------
 
 // row lengths of the Odd vertices, in list order
@@ -204,7 +192,7 @@ __global__ __launch_bounds__(kTswMinBlock) void k_tsw_min(
       ++sw;
     }
   }
-  count_block_n(&ctr[C_DIST_SW], sw);
+  add_block(&ctr[C_DIST_SW], sw);
 }
 
 // ---- host side -------------------------------------------------------------

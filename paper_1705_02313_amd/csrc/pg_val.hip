@@ -834,6 +834,7 @@ static pg_status read_ctr(pg_game *g, hipStream_t s) {
   PG_HIP(hipMemcpyAsync(g->hctr, g->ctr, sizeof(int32_t) * C_COUNT,
                         hipMemcpyDeviceToHost, s));
   PG_HIP(hipStreamSynchronize(s));
+  fold_switches(g->hctr);
   if (g->prof.on) {
     g->prof.nf = (double)g->hctr[C_NFIN];
     g->prof.ni = (double)g->hctr[C_NINNER];
@@ -1045,10 +1046,7 @@ static void enqueue_rank_emit(pg_game *g, hipStream_t s, bool device_reduced) {
 static void enqueue_switch(pg_game *g, bool odd, hipStream_t s, bool fresh) {
   const int32_t N = (int32_t)g->n_aug;
   Prof *pf = &g->prof;
-  if (!fresh) {
-    fill_i32(g->ctr + C_DIST_SW, 0, kDistSlots * kDistStride, s, pf);
-    fill_i32(g->ctr + C_SWITCH, 0, 1, s, pf);
-  }
+  if (!fresh) fill_i32(g->ctr + C_DIST_SW, 0, kDistSlots * kDistStride, s, pf);
   // per vertex: id 4, two offsets 16, current choice 8 (read and write
   // counted once; its key is one of the row's) -> 28; per edge: target 4
   // and its key 4
@@ -1067,7 +1065,7 @@ static void enqueue_switch(pg_game *g, bool odd, hipStream_t s, bool fresh) {
                 k_even_switch, dim3(grid_for(cnt)), dim3(kBlock), 0, s, N, cnt,
                 g->even_ids, g->off, g->tgt, g->key, g->pri, g->sp, g->ctr);
   }
-  sum_dist(g->ctr, C_DIST_SW, C_SWITCH, s, pf);
+  // the host sums the switch count's slots when it reads the counters
 }
 
 // The valuation after the walks: rank keys (distinct priorities) or count
