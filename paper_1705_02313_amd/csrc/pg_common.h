@@ -438,13 +438,19 @@ size_t radix_scan_tmp_bytes(int64_t n);
 // also in ctr[C_NINNER]) holds parent skS[i] and position svS[i]; a position
 // n_inner <= i < nF = ctr[C_NFIN] holds a child of the sink, at
 // svS[n_inner + nF - 1 - i].  Returns which pair holds skS/svS (1: k1/v1).
-// `work` holds onesweep_words(n) words; a look-back that waits too long sets
-// ERR_SORT, a finite count that disagrees with the keys ERR_RANKCOUNT.
+// `work` holds onesweep_words(n) words, cleared by clear_valuation since
+// the last sort; a look-back that waits too long sets ERR_SORT, a finite
+// count that disagrees with the keys ERR_RANKCOUNT.
 int64_t onesweep_words(int64_t n);
 int parent_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
                 int64_t n, uint32_t npar, int bits, uint32_t *work,
                 int32_t *ctr, hipStream_t s, Prof *prof,
                 const uint32_t **n_inner);
+// Clears the counters (C_TOTAL words) and, unless `work` is null, the parts
+// of the parent sort's work buffer for n keys that the sort needs cleared,
+// in one launch.
+void clear_valuation(int32_t *ctr, uint32_t *work, int64_t n, hipStream_t s,
+                     Prof *prof);
 
 }  // namespace pgk
 

@@ -65,7 +65,8 @@ __global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
   for (; i < n; i += stride) p[i] = v;
 }
 
-// zeroes three ranges in one launch (the parent sort's work buffer)
+// zeroes three ranges in one launch (the counters and the parent sort's
+// work buffer)
 __global__ void k_zero3(int32_t *a, int64_t na, int32_t *b, int64_t nb,
                         int32_t *c, int64_t nc) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -687,6 +688,23 @@ __global__ __launch_bounds__(kBlock) void k_ps_split(
   }
 }
 
+void clear_valuation(int32_t *ctr, uint32_t *work, int64_t n, hipStream_t s,
+                     Prof *prof) {
+  if (!work) {
+    fill_i32(ctr, 0, C_TOTAL, s, prof);
+    return;
+  }
+  // [counters | histograms] and [status | split status] (the bases are
+  // written before they are read)
+  const int64_t tiles = onesweep_tiles(n);
+  const int64_t na = k1sCounters + k1sHistWords;
+  const int64_t nb = (int64_t)k1sMaxPasses * tiles * 256 + 2 * tiles;
+  uint32_t *status = work + na + k1sMaxPasses * 256;
+  PG_LAUNCH(prof, K_FILL, 4.0 * (C_TOTAL + na + nb), k_zero3,
+            dim3(capped_grid(C_TOTAL + na + nb)), dim3(kBlock), 0, s, ctr,
+            (int64_t)C_TOTAL, (int32_t *)work, na, (int32_t *)status, nb);
+}
+
 int parent_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
                 int64_t n, uint32_t npar, int bits, uint32_t *work,
                 int32_t *ctr, hipStream_t s, Prof *prof,
@@ -700,14 +718,8 @@ int parent_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
   uint32_t *ni = wctr + 5;
   const int32_t *gate = ctr + C_ABORT;
   *n_inner = ni;
-  {
-    const int64_t na = k1sCounters + k1sHistWords;
-    const int64_t nb = (int64_t)passes * tiles * 256, nc = 2 * tiles;
-    PG_LAUNCH(prof, K_FILL, 4.0 * (na + nb + nc), k_zero3,
-              dim3(capped_grid(na + nb + nc)), dim3(kBlock), 0, s,
-              (int32_t *)wctr, na, (int32_t *)status, nb, (int32_t *)sstat,
-              nc);
-  }
+  // the tile counters, histograms and status words are zero
+  // (clear_valuation, at the start of the valuation)
   // the digit passes alternate between the pairs and end in pair 0 after
   // an odd number of passes: the sink's children go straight to that pair
   const int fin = (passes & 1) ? 0 : 1;

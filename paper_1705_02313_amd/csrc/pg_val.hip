@@ -868,7 +868,8 @@ static void enqueue_walks(pg_game *g, hipStream_t s) {
   Prof *pf = &g->prof;
   int32_t *ng = g->ng, *cand = g->cand;
   const WalkBudget wb = walk_budget(g);
-  fill_i32(g->ctr, 0, C_TOTAL, s, pf);
+  // the counters, and the parent sort's work buffer of a rank valuation
+  clear_valuation(g->ctr, g->dense ? nullptr : g->rs1, N, s, pf);
   // own record 8, first successor record 8, result 4; state resets 5
   const int wblk = walk_block(g);
   PG_LAUNCH(pf, K_NG_WALK, 25.0 * N, k_ng_full, dim3(grid_for(N, wblk)),
@@ -925,7 +926,7 @@ static pg_status careful_walks(pg_game *g, hipStream_t s) {
   int32_t *ng = g->ng, *cand = g->cand;
   fill_i32(ng, -1, N, s, pf);
   fill_i32(cand, -1, N, s, pf);
-  fill_i32(g->ctr, 0, C_TOTAL, s, pf);
+  clear_valuation(g->ctr, g->dense ? nullptr : g->rs1, N, s, pf);
   int32_t open = 0;
   const int wblk = walk_block(g);
   PG_TRY(counted(g, s, [&](int32_t *dist) {
