@@ -239,7 +239,9 @@ def traffic_summary(pmc_dir: str, workload: str = "c2") -> dict:
 # rank-valuation solve launches
 KERNEL_KINDS = {
     "k_ng_full": "ng_walk", "k_ng_round": "ng_round",
+    "k_ng_round_list": "ng_round",
     "k_root_full": "root_walk", "k_root_round": "root_round",
+    "k_root_round_list": "root_round",
     "k_ps_split": "sort_split", "k_1s_hist": "sort_hist",
     "k_1s_pass": "sort_pass", "k_scan_reduce": "scan", "k_scan_down": "scan",
     "k_scan_top": "scan", "k_link_info": "link_info",
