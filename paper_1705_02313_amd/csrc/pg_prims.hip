@@ -355,15 +355,24 @@ int radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
 // in order) and compacts the other finite vertices; one kernel builds the
 // digit histograms of every pass over that prefix; then each pass is one
 // kernel in which a tile
-// (taken in launch order from a counter) ranks its 4096 keys in LDS, learns
+// (taken in launch order from a counter) ranks its keys in LDS, learns
 // its global offset per digit by decoupled look-back over the tiles before
 // it, and writes each digit's run out contiguously.  A tile waits only on
 // tiles that took their number earlier and never wait on later ones, so the
 // look-back always ends; a bounded spin turns a broken protocol into an
 // error instead of a hang.
 // ---------------------------------------------------------------------------
-constexpr int k1sItems = 16;
-constexpr int k1sTile = kBlock * k1sItems;   // 4096 keys per tile
+// Keys per thread of a tile (ITEMS, a template argument of the kernels):
+// 4096-key tiles below kLargeTileFrom keys, 8192-key tiles (2 of them fit
+// the LDS of a CU) from there on.  Fewer, larger tiles shorten the
+// look-back chains of a large sort, smaller ones keep a small sort's grid
+// wide: per digit pass 53 -> 48 us on the 10M-vertex game (57-62 us at
+// 12288-16384 keys), 19 -> 23 us on the 1M-vertex game.
+constexpr int k1sItemsSmall = 16, k1sItemsLarge = 32;
+constexpr int64_t kLargeTileFrom = 4194304;
+inline int sort_items(int64_t n) {
+  return n >= kLargeTileFrom ? k1sItemsLarge : k1sItemsSmall;
+}
 constexpr uint32_t kStAgg = 1u << 30;        // tile count published
 constexpr uint32_t kStPre = 1u << 31;        // inclusive prefix published
 constexpr uint32_t kStVal = (1u << 30) - 1;
@@ -371,7 +380,10 @@ constexpr int kSpinMax = 1 << 22;
 constexpr int k1sMaxPasses = 4;
 constexpr int k1sCopies = 64;   // histogram copies (blocks spread over them)
 
-int64_t onesweep_tiles(int64_t n) { return (n + k1sTile - 1) / k1sTile; }
+int64_t onesweep_tiles(int64_t n, int items) {
+  const int64_t t = (int64_t)kBlock * items;
+  return (n + t - 1) / t;
+}
 
 // work buffer: [counters 8 | histograms 64 copies x 4 x 256 | bases 4 x 256
 //               | status 4 x tiles x 256 | split status 2 x tiles]
@@ -381,8 +393,9 @@ constexpr int k1sCounters = 8;
 constexpr int64_t k1sHistWords = (int64_t)k1sCopies * k1sMaxPasses * 256;
 
 int64_t onesweep_words(int64_t n) {
+  const int64_t tiles = onesweep_tiles(n, k1sItemsSmall);   // the most
   return k1sCounters + k1sHistWords + k1sMaxPasses * 256 +
-         k1sMaxPasses * onesweep_tiles(n) * 256 + 2 * onesweep_tiles(n);
+         k1sMaxPasses * tiles * 256 + 2 * tiles;
 }
 
 // lanes of the wave (among `valid` ones) whose 8-bit digit equals mine
@@ -397,28 +410,30 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
   return peers;
 }
 
-// Counts every digit of every pass, one block per 4096-key tile.  Each lane
-// loads its 16 keys at once (all in flight); then each wave adds its keys to
+// Counts every digit of every pass, one block per tile.  Each lane loads
+// its ITEMS keys at once (all in flight); then each wave adds its keys to
 // its own LDS counters with atomics.  Lanes of a wave that hit one counter
 // are serialised by the LDS, which costs less than finding the groups of
 // equal digits with ballots (eight per digit): on the 10M-vertex random game
 // 47 -> 13 us per valuation.
+template <int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_1s_hist(const uint32_t *keys,
                                                     const uint32_t *n_dev,
                                                     int passes,
                                                     uint32_t *glob,
                                                     const int32_t *gate) {
+  constexpr int kT = kBlock * ITEMS;   // keys per tile
   if (gate && *gate) return;
   const int64_t n = *n_dev;
-  if ((int64_t)blockIdx.x * k1sTile >= n) return;   // grid sized for the most
-  constexpr int kWaveItems = k1sTile / kRsWaves / kWave;   // 16
+  if ((int64_t)blockIdx.x * kT >= n) return;   // grid sized for the most
+  constexpr int kWaveItems = kT / kRsWaves / kWave;   // ITEMS
   __shared__ uint32_t h[kRsWaves][k1sMaxPasses][256];
   const int lane = threadIdx.x & (kWave - 1);
   const int w = threadIdx.x / kWave;
   for (int p = 0; p < k1sMaxPasses; ++p)
     for (int j = lane; j < 256; j += kWave) h[w][p][j] = 0;
   const int64_t base =
-      (int64_t)blockIdx.x * k1sTile + w * (k1sTile / kRsWaves);
+      (int64_t)blockIdx.x * kT + w * (kT / kRsWaves);
   uint32_t k[kWaveItems];
 #pragma unroll
   for (int r = 0; r < kWaveItems; ++r) {
@@ -470,24 +485,26 @@ __device__ __forceinline__ void st_status(uint32_t *p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Wave w of a tile owns the tile's keys [1024 w, 1024 w + 1024), 64 at a
-// time in order, so wave order then round order then lane order is input
-// order: ranks come out stable without barriers inside the loop.
+// Wave w of a tile owns a quarter of the tile's keys, 64 at a time in
+// order, so wave order then round order then lane order is input order:
+// ranks come out stable without barriers inside the loop.
+template <int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_1s_pass(
     const uint32_t *kin, const uint32_t *__restrict__ vin, uint32_t *kout,
     uint32_t *vout, const uint32_t *n_dev, int shift,
     const uint32_t *__restrict__ dbase, uint32_t *status, uint32_t *tile_ctr,
     int32_t *err, const int32_t *gate) {
+  constexpr int kT = kBlock * ITEMS;   // keys per tile
   if (gate && *gate) return;
   const int64_t n = *n_dev;
   // the grid is sized for the most keys: blocks past the tiles needed leave
   // before taking a tile number, so the ones that stay take exactly the
   // numbers of the tiles there are
-  if ((int64_t)blockIdx.x * k1sTile >= n) return;
-  constexpr int kWaveItems = k1sTile / kRsWaves / kWave;   // 16
+  if ((int64_t)blockIdx.x * kT >= n) return;
+  constexpr int kWaveItems = kT / kRsWaves / kWave;   // ITEMS
   __shared__ uint32_t s_tile;
-  __shared__ uint32_t lk[k1sTile];
-  __shared__ uint32_t lv[k1sTile];
+  __shared__ uint32_t lk[kT];
+  __shared__ uint32_t lv[kT];
   __shared__ uint32_t wc[kRsWaves][256];   // per wave: digit counts, then
                                            // the wave's first slot per digit
   __shared__ uint32_t start[256], goff[256];
@@ -499,21 +516,21 @@ __global__ __launch_bounds__(kBlock) void k_1s_pass(
   for (int j = lane; j < 256; j += kWave) wc[w][j] = 0;
   __syncthreads();
   const uint32_t tile = s_tile;
-  const int64_t base = (int64_t)tile * k1sTile;
+  const int64_t base = (int64_t)tile * kT;
   const int64_t rem = n - base;
-  const int tn = rem < k1sTile ? (int)rem : k1sTile;   // keys of this tile
+  const int tn = rem < kT ? (int)rem : kT;   // keys of this tile
   uint32_t k[kWaveItems], v[kWaveItems], rk[kWaveItems];
   // every load in flight before the first ballot waits on one
 #pragma unroll
   for (int r = 0; r < kWaveItems; ++r) {
-    const int j = w * (k1sTile / kRsWaves) + r * kWave + lane;
+    const int j = w * (kT / kRsWaves) + r * kWave + lane;
     const bool valid = j < tn;
     k[r] = valid ? kin[base + j] : 0u;
     v[r] = valid ? vin[base + j] : 0u;
   }
 #pragma unroll
   for (int r = 0; r < kWaveItems; ++r) {
-    const int j = w * (k1sTile / kRsWaves) + r * kWave + lane;
+    const int j = w * (kT / kRsWaves) + r * kWave + lane;
     const bool valid = j < tn;
     const uint32_t d = (k[r] >> shift) & 255u;
     const uint64_t peers = digit_peers(d, valid);
@@ -545,7 +562,7 @@ __global__ __launch_bounds__(kBlock) void k_1s_pass(
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kWaveItems; ++r) {
-    const int j = w * (k1sTile / kRsWaves) + r * kWave + lane;
+    const int j = w * (kT / kRsWaves) + r * kWave + lane;
     if (j < tn) {
       const uint32_t slot = wc[w][(k[r] >> shift) & 255u] + rk[r];
       lk[slot] = k[r];
@@ -576,7 +593,7 @@ __global__ __launch_bounds__(kBlock) void k_1s_pass(
   __syncthreads();
   // each digit's run goes out contiguously
 #pragma unroll 4
-  for (int r = 0; r < k1sItems; ++r) {
+  for (int r = 0; r < ITEMS; ++r) {
     const int sl = r * kBlock + tid;
     if (sl < tn) {
       const uint32_t key = lk[sl];
@@ -596,12 +613,14 @@ __global__ __launch_bounds__(kBlock) void k_1s_pass(
 // their offsets for the two classes by decoupled look-back (two status
 // words per tile); the last tile publishes the prefix length and checks that
 // the two classes add up to the finite count.
+template <int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_ps_split(
     const uint32_t *kin, int64_t n, uint32_t npar, uint32_t *kout,
     uint32_t *vout, uint32_t *cout, uint32_t *status, uint32_t *tile_ctr,
     uint32_t *n_inner, int32_t *ctr) {
+  constexpr int kT = kBlock * ITEMS;   // keys per tile
   if (ctr[C_ABORT]) return;
-  constexpr int kWaveItems = k1sTile / kRsWaves / kWave;   // 16
+  constexpr int kWaveItems = kT / kRsWaves / kWave;   // ITEMS
   __shared__ uint32_t s_tile;
   __shared__ uint32_t wcnt[2][kRsWaves];
   __shared__ uint32_t s_excl[2], s_total[2];
@@ -612,7 +631,7 @@ __global__ __launch_bounds__(kBlock) void k_ps_split(
   if (tid == 0) s_tile = atomicAdd(tile_ctr, 1u);
   __syncthreads();
   const uint32_t tile = s_tile;
-  const int64_t base = (int64_t)tile * k1sTile + w * (k1sTile / kRsWaves);
+  const int64_t base = (int64_t)tile * kT + w * (kT / kRsWaves);
   uint32_t k[kWaveItems], r0[kWaveItems], r1[kWaveItems];
   uint32_t c0 = 0, c1 = 0;
 #pragma unroll
@@ -663,7 +682,7 @@ __global__ __launch_bounds__(kBlock) void k_ps_split(
   }
   __syncthreads();
   const int64_t nf = ctr[C_NFIN];
-  if (tid == 0 && (int64_t)(tile + 1) * k1sTile >= n) {
+  if (tid == 0 && (int64_t)(tile + 1) * kT >= n) {
     *n_inner = s_total[0];
     ctr[C_NINNER] = (int32_t)s_total[0];
     if ((int64_t)s_total[0] + s_total[1] != nf)
@@ -696,7 +715,7 @@ void clear_valuation(int32_t *ctr, uint32_t *work, int64_t n, hipStream_t s,
   }
   // [counters | histograms] and [status | split status] (the bases are
   // written before they are read)
-  const int64_t tiles = onesweep_tiles(n);
+  const int64_t tiles = onesweep_tiles(n, sort_items(n));
   const int64_t na = k1sCounters + k1sHistWords;
   const int64_t nb = (int64_t)k1sMaxPasses * tiles * 256 + 2 * tiles;
   uint32_t *status = work + na + k1sMaxPasses * 256;
@@ -710,7 +729,8 @@ int parent_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
                 int32_t *ctr, hipStream_t s, Prof *prof,
                 const uint32_t **n_inner) {
   const int passes = (bits + 7) / 8;
-  const int64_t tiles = onesweep_tiles(n);
+  const int items = sort_items(n);
+  const int64_t tiles = onesweep_tiles(n, items);
   uint32_t *wctr = work, *glob = work + k1sCounters;
   uint32_t *base = glob + k1sHistWords;
   uint32_t *status = base + k1sMaxPasses * 256;
@@ -724,11 +744,15 @@ int parent_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
   // an odd number of passes: the sink's children go straight to that pair
   const int fin = (passes & 1) ? 0 : 1;
   // keys read (4 B each); 8 B per inner child, 4 B per child of the sink
-  PG_LAUNCH_NI(prof, K_SORT_SPLIT, 4.0 * n, 4.0, 4.0, k_ps_split,
+  PG_LAUNCH_NI(prof, K_SORT_SPLIT, 4.0 * n, 4.0, 4.0,
+               (items == k1sItemsLarge ? k_ps_split<k1sItemsLarge>
+                                       : k_ps_split<k1sItemsSmall>),
                dim3((unsigned)tiles), dim3(kBlock), 0, s, k0, n, npar, k1,
                v1, fin ? v1 : v0, sstat, wctr + 4, ni, ctr);
   // the prefix's keys, read once for all digits
-  PG_LAUNCH_NI(prof, K_SORT_HIST, 0.0, 0.0, 4.0, k_1s_hist,
+  PG_LAUNCH_NI(prof, K_SORT_HIST, 0.0, 0.0, 4.0,
+               (items == k1sItemsLarge ? k_1s_hist<k1sItemsLarge>
+                                       : k_1s_hist<k1sItemsSmall>),
                dim3((unsigned)tiles), dim3(kBlock), 0, s, k1, ni, passes,
                glob, gate);
   PG_LAUNCH(prof, K_SCAN, 0.0, k_1s_base, dim3(1), dim3(kBlock), 0, s,
@@ -737,8 +761,10 @@ int parent_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
   for (int p = 0; p < passes; ++p) {
     uint32_t *ki = cur ? k1 : k0, *vi = cur ? v1 : v0;
     uint32_t *ko = cur ? k0 : k1, *vo = cur ? v0 : v1;
-    // keys and values read and written (16 B), 1 KiB of status per 4096
-    PG_LAUNCH_NI(prof, K_SORT_PASS, 0.0, 0.0, 16.25, k_1s_pass,
+    // keys and values read and written (16 B), 1 KiB of status per tile
+    PG_LAUNCH_NI(prof, K_SORT_PASS, 0.0, 0.0, 16.0 + 1024.0 / (kBlock * items),
+                 (items == k1sItemsLarge ? k_1s_pass<k1sItemsLarge>
+                                         : k_1s_pass<k1sItemsSmall>),
                  dim3((unsigned)tiles), dim3(kBlock), 0, s, ki, vi, ko, vo,
                  ni, 8 * p, base + p * 256, status + (int64_t)p * tiles * 256,
                  wctr + p, ctr + C_ERR, gate);
