@@ -382,16 +382,15 @@ __device__ __forceinline__ void st_relaxed(int32_t *p, int32_t v) {
 // by many threads at once and is bound by its loads; the reduced lists are
 // short, and a level's time is its longest sublist walk (sublist lengths are
 // about geometric, so the longest is near stride x ln(sublists)): there a
-// small stride wins
-constexpr int kStride = 32;        // level 0 -> 1 (count valuations; rank
-                                   // valuations take pg_tuning::stride0)
+// small stride wins.  The level-0 stride s0 is a power of two: rank
+// valuations take pg_tuning::stride0, count valuations count_stride.
 constexpr int kStrideUp = 8;       // level k -> k + 1 for k >= 1
-constexpr int kStrideMin = 8;      // least stride0 (sizes the level arrays)
+constexpr int kStrideMin = 8;      // least level-0 stride (sizes the levels)
 
 // size of level k of the sublist ranking for an Euler list of L elements
 // whose level-0 stride is s0
 __device__ __host__ __forceinline__ int64_t level_size(int64_t L, int k,
-                                                       int s0 = kStride) {
+                                                       int s0) {
   if (k >= 1) L = (L + s0 - 1) / s0;
   for (int j = 1; j < k; ++j) L = (L + kStrideUp - 1) / kStrideUp;
   return L;
@@ -498,6 +497,8 @@ constexpr int kCountMax = 32;   // most distinct priorities of a count game
 pg_status count_setup(pg_game *g, hipStream_t s);
 // walking levels of the vector list ranking for games of n_aug vertices
 int count_levels(int64_t n_aug, int dw);
+// level-0 stride of a count valuation's list ranking (8 or 16)
+int count_stride(int64_t n_aug);
 // Euler list and vector list ranking after the walks; gated by C_ABORT.
 void enqueue_count(pg_game *g, hipStream_t s);
 // All_Odd (odd) or All_Even on count valuations; counts into C_DIST_SW.
