@@ -362,14 +362,32 @@ int radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
 // look-back always ends; a bounded spin turns a broken protocol into an
 // error instead of a hang.
 // ---------------------------------------------------------------------------
-// Keys per thread of a tile (ITEMS, a template argument of the kernels):
-// 4096-key tiles below kLargeTileFrom keys, 8192-key tiles (2 of them fit
-// the LDS of a CU) from there on.  Fewer, larger tiles shorten the
-// look-back chains of a large sort, smaller ones keep a small sort's grid
-// wide: per digit pass 53 -> 48 us on the 10M-vertex game (57-62 us at
-// 12288-16384 keys), 19 -> 23 us on the 1M-vertex game.
+// Tile shapes.  The histogram kernel takes kBlock threads and ITEMS keys
+// per thread: 4096-key tiles below kLargeTileFrom keys, 8192-key tiles from
+// there on; these also lay out the status words.  The split and the digit
+// passes take 1024-thread blocks with tiles at least as large (so never
+// more tiles than there are status words for): a pass holds its keys and
+// values in LDS, 16384 keys (128 KiB) on a large sort, one block per CU at
+// 16 waves, where 8192-key tiles of 256 threads left 2 waves per SIMD
+// (205 VGPRs) with nothing to cover the look-back and the LDS ranking; the
+// split keeps nothing in LDS and takes 32768 keys.  On the 10M-vertex game
+// per valuation: digit pass 48 -> 41 us, split 63 -> 48 us; on the
+// 1M-vertex game 18.6 -> 16.6 and 20.4 -> 15.9 us (4096- and 8192-key
+// tiles there).  Fewer, larger tiles shorten the look-back chains of a
+// large sort, smaller ones keep a small sort's grid wide.
 constexpr int k1sItemsSmall = 16, k1sItemsLarge = 32;
 constexpr int64_t kLargeTileFrom = 4194304;
+constexpr int kPassBlockSmall = 1024, kPassItemsSmall = 4;
+constexpr int kPassBlockLarge = 1024, kPassItemsLarge = 16;
+constexpr int kSplitBlockSmall = 1024, kSplitItemsSmall = 8;
+constexpr int kSplitBlockLarge = 1024, kSplitItemsLarge = 32;
+static_assert(kSplitBlockSmall * kSplitItemsSmall >= kBlock * k1sItemsSmall &&
+                  kSplitBlockLarge * kSplitItemsLarge >=
+                      kBlock * k1sItemsLarge,
+              "the split has at most as many tiles as its status words");
+static_assert(kPassBlockSmall * kPassItemsSmall >= kBlock * k1sItemsSmall &&
+                  kPassBlockLarge * kPassItemsLarge >= kBlock * k1sItemsLarge,
+              "a digit pass has at most as many tiles as its status words");
 inline int sort_items(int64_t n) {
   return n >= kLargeTileFrom ? k1sItemsLarge : k1sItemsSmall;
 }
@@ -462,19 +480,28 @@ __global__ __launch_bounds__(kBlock) void k_1s_hist(const uint32_t *keys,
   }
 }
 
-// digit bases of every pass: exclusive scans of the histograms
-__global__ __launch_bounds__(kBlock) void k_1s_base(const uint32_t *glob,
-                                                    int passes,
-                                                    uint32_t *base,
-                                                    const int32_t *gate) {
+// digit bases of every pass: exclusive scans of the histograms, summed
+// over their copies; thread group p (256 threads) takes pass p, so that the
+// passes' copies are read and scanned together
+constexpr int kBaseThreads = k1sMaxPasses * 256;
+__global__ __launch_bounds__(kBaseThreads) void k_1s_base(
+    const uint32_t *glob, int passes, uint32_t *base, const int32_t *gate) {
   if (gate && *gate) return;
-  for (int p = 0; p < passes; ++p) {
-    uint32_t c = 0;
+  __shared__ uint32_t wsum[kBaseThreads / kWave];
+  const int p = threadIdx.x / 256, d = threadIdx.x & 255;
+  const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  uint32_t c = 0;
+  if (p < passes) {
+#pragma unroll 16
     for (int j = 0; j < k1sCopies; ++j)
-      c += glob[(int64_t)j * (k1sMaxPasses * 256) + p * 256 + threadIdx.x];
-    uint32_t tot;
-    base[p * 256 + threadIdx.x] = block_excl_scan<uint32_t>(c, &tot);
+      c += glob[(int64_t)j * (k1sMaxPasses * 256) + p * 256 + d];
   }
+  const uint32_t inc = wave_incl_scan(c);
+  if (lane == kWave - 1) wsum[w] = inc;
+  __syncthreads();
+  uint32_t before = 0;
+  for (int i = p * (256 / kWave); i < w; ++i) before += wsum[i];
+  if (p < passes) base[p * 256 + d] = before + inc - c;
 }
 
 __device__ __forceinline__ uint32_t ld_status(const uint32_t *p) {
@@ -485,32 +512,57 @@ __device__ __forceinline__ void st_status(uint32_t *p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Wave w of a tile owns a quarter of the tile's keys, 64 at a time in
-// order, so wave order then round order then lane order is input order:
-// ranks come out stable without barriers inside the loop.
-template <int ITEMS>
-__global__ __launch_bounds__(kBlock) void k_1s_pass(
+// Exclusive scan of one value per thread over a block of BS threads.
+template <typename T, int BS>
+__device__ T block_excl_scan_bs(T x, T *total) {
+  __shared__ T wsum[BS / kWave];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+  T inc = wave_incl_scan(x);
+  if (lane == kWave - 1) wsum[w] = inc;
+  __syncthreads();
+  T before = 0, all = 0;
+#pragma unroll
+  for (int i = 0; i < BS / kWave; ++i) {
+    T s = wsum[i];
+    if (i < w) before += s;
+    all += s;
+  }
+  __syncthreads();
+  *total = all;
+  return before + inc - x;
+}
+
+// BS threads take a tile of BS * ITEMS keys.  Wave w of a tile owns the
+// w-th of BS / 64 equal stretches of the tile's keys, 64 at a time in order,
+// so wave order then round order then lane order is input order: ranks come
+// out stable without barriers inside the loop.  The first 256 threads then
+// take one digit each.
+template <int BS, int ITEMS>
+__global__ __launch_bounds__(BS) void k_1s_pass(
     const uint32_t *kin, const uint32_t *__restrict__ vin, uint32_t *kout,
     uint32_t *vout, const uint32_t *n_dev, int shift,
     const uint32_t *__restrict__ dbase, uint32_t *status, uint32_t *tile_ctr,
     int32_t *err, const int32_t *gate) {
-  constexpr int kT = kBlock * ITEMS;   // keys per tile
+  constexpr int kT = BS * ITEMS;   // keys per tile
+  constexpr int kW = BS / kWave;   // waves per tile
+  static_assert(BS >= 256 && BS % 256 == 0, "one thread per digit");
   if (gate && *gate) return;
   const int64_t n = *n_dev;
   // the grid is sized for the most keys: blocks past the tiles needed leave
   // before taking a tile number, so the ones that stay take exactly the
   // numbers of the tiles there are
   if ((int64_t)blockIdx.x * kT >= n) return;
-  constexpr int kWaveItems = kT / kRsWaves / kWave;   // ITEMS
   __shared__ uint32_t s_tile;
   __shared__ uint32_t lk[kT];
   __shared__ uint32_t lv[kT];
-  __shared__ uint32_t wc[kRsWaves][256];   // per wave: digit counts, then
-                                           // the wave's first slot per digit
+  __shared__ uint32_t wc[kW][256];   // per wave: digit counts, then the
+                                     // wave's first slot per digit
   __shared__ uint32_t start[256], goff[256];
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int w = tid / kWave;
+  const bool dig = tid < 256;        // thread tid owns digit tid
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
   if (tid == 0) s_tile = atomicAdd(tile_ctr, 1u);
   for (int j = lane; j < 256; j += kWave) wc[w][j] = 0;
@@ -519,18 +571,18 @@ __global__ __launch_bounds__(kBlock) void k_1s_pass(
   const int64_t base = (int64_t)tile * kT;
   const int64_t rem = n - base;
   const int tn = rem < kT ? (int)rem : kT;   // keys of this tile
-  uint32_t k[kWaveItems], v[kWaveItems], rk[kWaveItems];
+  uint32_t k[ITEMS], v[ITEMS], rk[ITEMS];
   // every load in flight before the first ballot waits on one
 #pragma unroll
-  for (int r = 0; r < kWaveItems; ++r) {
-    const int j = w * (kT / kRsWaves) + r * kWave + lane;
+  for (int r = 0; r < ITEMS; ++r) {
+    const int j = w * (kT / kW) + r * kWave + lane;
     const bool valid = j < tn;
     k[r] = valid ? kin[base + j] : 0u;
     v[r] = valid ? vin[base + j] : 0u;
   }
 #pragma unroll
-  for (int r = 0; r < kWaveItems; ++r) {
-    const int j = w * (kT / kRsWaves) + r * kWave + lane;
+  for (int r = 0; r < ITEMS; ++r) {
+    const int j = w * (kT / kW) + r * kWave + lane;
     const bool valid = j < tn;
     const uint32_t d = (k[r] >> shift) & 255u;
     const uint64_t peers = digit_peers(d, valid);
@@ -540,29 +592,32 @@ __global__ __launch_bounds__(kBlock) void k_1s_pass(
     if (valid && before == 0) wc[w][d] = cur + (uint32_t)__popcll(peers);
   }
   __syncthreads();
-  // thread t: digit t of the tile
-  uint32_t c[kRsWaves], cnt = 0;
+  uint32_t c[kW], cnt = 0;
+  if (dig) {
 #pragma unroll
-  for (int j = 0; j < kRsWaves; ++j) {
-    c[j] = wc[j][tid];
-    cnt += c[j];
+    for (int j = 0; j < kW; ++j) {
+      c[j] = wc[j][tid];
+      cnt += c[j];
+    }
+    // publish this tile's count at once (its prefix, for the first tile)
+    st_status(&status[(int64_t)tile * 256 + tid],
+              (tile == 0 ? kStPre : kStAgg) | cnt);
   }
-  // publish this tile's count at once (its prefix, for the first tile)
-  st_status(&status[(int64_t)tile * 256 + tid],
-            (tile == 0 ? kStPre : kStAgg) | cnt);
   uint32_t tot;
-  const uint32_t st0 = block_excl_scan<uint32_t>(cnt, &tot);
-  start[tid] = st0;
-  uint32_t o = st0;
+  const uint32_t st0 = block_excl_scan_bs<uint32_t, BS>(cnt, &tot);
+  if (dig) {
+    start[tid] = st0;
+    uint32_t o = st0;
 #pragma unroll
-  for (int j = 0; j < kRsWaves; ++j) {
-    wc[j][tid] = o;
-    o += c[j];
+    for (int j = 0; j < kW; ++j) {
+      wc[j][tid] = o;
+      o += c[j];
+    }
   }
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < kWaveItems; ++r) {
-    const int j = w * (kT / kRsWaves) + r * kWave + lane;
+  for (int r = 0; r < ITEMS; ++r) {
+    const int j = w * (kT / kW) + r * kWave + lane;
     if (j < tn) {
       const uint32_t slot = wc[w][(k[r] >> shift) & 255u] + rk[r];
       lk[slot] = k[r];
@@ -570,31 +625,33 @@ __global__ __launch_bounds__(kBlock) void k_1s_pass(
     }
   }
   // decoupled look-back for digit tid
-  uint32_t excl = 0;
-  if (tile > 0) {
-    int64_t t = (int64_t)tile - 1;
-    int spins = 0;
-    for (;;) {
-      const uint32_t sv = ld_status(&status[t * 256 + tid]);
-      if (!(sv & (kStAgg | kStPre))) {
-        if (++spins > kSpinMax) {
-          atomicOr(err, ERR_SORT);
-          break;
+  if (dig) {
+    uint32_t excl = 0;
+    if (tile > 0) {
+      int64_t t = (int64_t)tile - 1;
+      int spins = 0;
+      for (;;) {
+        const uint32_t sv = ld_status(&status[t * 256 + tid]);
+        if (!(sv & (kStAgg | kStPre))) {
+          if (++spins > kSpinMax) {
+            atomicOr(err, ERR_SORT);
+            break;
+          }
+          continue;
         }
-        continue;
+        excl += sv & kStVal;
+        if ((sv & kStPre) || t == 0) break;
+        --t;
       }
-      excl += sv & kStVal;
-      if ((sv & kStPre) || t == 0) break;
-      --t;
+      st_status(&status[(int64_t)tile * 256 + tid], kStPre | (excl + cnt));
     }
-    st_status(&status[(int64_t)tile * 256 + tid], kStPre | (excl + cnt));
+    goff[tid] = dbase[tid] + excl;
   }
-  goff[tid] = dbase[tid] + excl;
   __syncthreads();
   // each digit's run goes out contiguously
 #pragma unroll 4
   for (int r = 0; r < ITEMS; ++r) {
-    const int sl = r * kBlock + tid;
+    const int sl = r * BS + tid;
     if (sl < tn) {
       const uint32_t key = lk[sl];
       const uint32_t d = (key >> shift) & 255u;
@@ -613,16 +670,16 @@ __global__ __launch_bounds__(kBlock) void k_1s_pass(
 // their offsets for the two classes by decoupled look-back (two status
 // words per tile); the last tile publishes the prefix length and checks that
 // the two classes add up to the finite count.
-template <int ITEMS>
-__global__ __launch_bounds__(kBlock) void k_ps_split(
+template <int BS, int ITEMS>
+__global__ __launch_bounds__(BS) void k_ps_split(
     const uint32_t *kin, int64_t n, uint32_t npar, uint32_t *kout,
     uint32_t *vout, uint32_t *cout, uint32_t *status, uint32_t *tile_ctr,
     uint32_t *n_inner, int32_t *ctr) {
-  constexpr int kT = kBlock * ITEMS;   // keys per tile
+  constexpr int kT = BS * ITEMS;   // keys per tile
+  constexpr int kW = BS / kWave;   // waves per tile
   if (ctr[C_ABORT]) return;
-  constexpr int kWaveItems = kT / kRsWaves / kWave;   // ITEMS
   __shared__ uint32_t s_tile;
-  __shared__ uint32_t wcnt[2][kRsWaves];
+  __shared__ uint32_t wcnt[2][kW];
   __shared__ uint32_t s_excl[2], s_total[2];
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
@@ -631,16 +688,16 @@ __global__ __launch_bounds__(kBlock) void k_ps_split(
   if (tid == 0) s_tile = atomicAdd(tile_ctr, 1u);
   __syncthreads();
   const uint32_t tile = s_tile;
-  const int64_t base = (int64_t)tile * kT + w * (kT / kRsWaves);
-  uint32_t k[kWaveItems], r0[kWaveItems], r1[kWaveItems];
+  const int64_t base = (int64_t)tile * kT + w * (kT / kW);
+  uint32_t k[ITEMS], r0[ITEMS], r1[ITEMS];
   uint32_t c0 = 0, c1 = 0;
 #pragma unroll
-  for (int r = 0; r < kWaveItems; ++r) {
+  for (int r = 0; r < ITEMS; ++r) {
     const int64_t i = base + r * kWave + lane;
     k[r] = i < n ? kin[i] : 0xffffffffu;
   }
 #pragma unroll
-  for (int r = 0; r < kWaveItems; ++r) {
+  for (int r = 0; r < ITEMS; ++r) {
     const uint64_t b0 = __ballot(k[r] < npar);
     const uint64_t b1 = __ballot(k[r] == npar);
     r0[r] = c0 + (uint32_t)__popcll(b0 & lt);
@@ -655,7 +712,7 @@ __global__ __launch_bounds__(kBlock) void k_ps_split(
   __syncthreads();
   if (tid < 2) {
     uint32_t cnt = 0;
-    for (int j = 0; j < kRsWaves; ++j) cnt += wcnt[tid][j];
+    for (int j = 0; j < kW; ++j) cnt += wcnt[tid][j];
     st_status(&status[(int64_t)tile * 2 + tid],
               (tile == 0 ? kStPre : kStAgg) | cnt);
     uint32_t excl = 0;
@@ -694,7 +751,7 @@ __global__ __launch_bounds__(kBlock) void k_ps_split(
     o1 += wcnt[1][j];
   }
 #pragma unroll
-  for (int r = 0; r < kWaveItems; ++r) {
+  for (int r = 0; r < ITEMS; ++r) {
     const int64_t i = base + r * kWave + lane;
     if (k[r] < npar) {
       const uint32_t q = o0 + r0[r];
@@ -743,29 +800,45 @@ int parent_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
   // the digit passes alternate between the pairs and end in pair 0 after
   // an odd number of passes: the sink's children go straight to that pair
   const int fin = (passes & 1) ? 0 : 1;
-  // keys read (4 B each); 8 B per inner child, 4 B per child of the sink
-  PG_LAUNCH_NI(prof, K_SORT_SPLIT, 4.0 * n, 4.0, 4.0,
-               (items == k1sItemsLarge ? k_ps_split<k1sItemsLarge>
-                                       : k_ps_split<k1sItemsSmall>),
-               dim3((unsigned)tiles), dim3(kBlock), 0, s, k0, n, npar, k1,
-               v1, fin ? v1 : v0, sstat, wctr + 4, ni, ctr);
+  {
+    // the split takes its own tiles too (no more of them than `tiles`, for
+    // which its status words are laid out)
+    const bool large = items == k1sItemsLarge;
+    const int sbs = large ? kSplitBlockLarge : kSplitBlockSmall;
+    const int sitems = large ? kSplitItemsLarge : kSplitItemsSmall;
+    const int64_t stiles =
+        (n + (int64_t)sbs * sitems - 1) / ((int64_t)sbs * sitems);
+    // keys read (4 B each); 8 B per inner child, 4 B per child of the sink
+    PG_LAUNCH_NI(prof, K_SORT_SPLIT, 4.0 * n, 4.0, 4.0,
+                 (large ? k_ps_split<kSplitBlockLarge, kSplitItemsLarge>
+                        : k_ps_split<kSplitBlockSmall, kSplitItemsSmall>),
+                 dim3((unsigned)stiles), dim3(sbs), 0, s, k0, n, npar, k1,
+                 v1, fin ? v1 : v0, sstat, wctr + 4, ni, ctr);
+  }
   // the prefix's keys, read once for all digits
   PG_LAUNCH_NI(prof, K_SORT_HIST, 0.0, 0.0, 4.0,
                (items == k1sItemsLarge ? k_1s_hist<k1sItemsLarge>
                                        : k_1s_hist<k1sItemsSmall>),
                dim3((unsigned)tiles), dim3(kBlock), 0, s, k1, ni, passes,
                glob, gate);
-  PG_LAUNCH(prof, K_SCAN, 0.0, k_1s_base, dim3(1), dim3(kBlock), 0, s,
+  PG_LAUNCH(prof, K_SCAN, 0.0, k_1s_base, dim3(1), dim3(kBaseThreads), 0, s,
             glob, passes, base, gate);
+  // the digit passes take their own tiles (no more of them than `tiles`,
+  // for which the status words of a pass are laid out)
+  const bool large = items == k1sItemsLarge;
+  const int pbs = large ? kPassBlockLarge : kPassBlockSmall;
+  const int pitems = large ? kPassItemsLarge : kPassItemsSmall;
+  const int64_t ptiles =
+      (n + (int64_t)pbs * pitems - 1) / ((int64_t)pbs * pitems);
   int cur = 1;
   for (int p = 0; p < passes; ++p) {
     uint32_t *ki = cur ? k1 : k0, *vi = cur ? v1 : v0;
     uint32_t *ko = cur ? k0 : k1, *vo = cur ? v0 : v1;
     // keys and values read and written (16 B), 1 KiB of status per tile
-    PG_LAUNCH_NI(prof, K_SORT_PASS, 0.0, 0.0, 16.0 + 1024.0 / (kBlock * items),
-                 (items == k1sItemsLarge ? k_1s_pass<k1sItemsLarge>
-                                         : k_1s_pass<k1sItemsSmall>),
-                 dim3((unsigned)tiles), dim3(kBlock), 0, s, ki, vi, ko, vo,
+    PG_LAUNCH_NI(prof, K_SORT_PASS, 0.0, 0.0, 16.0 + 1024.0 / (pbs * pitems),
+                 (large ? k_1s_pass<kPassBlockLarge, kPassItemsLarge>
+                        : k_1s_pass<kPassBlockSmall, kPassItemsSmall>),
+                 dim3((unsigned)ptiles), dim3(pbs), 0, s, ki, vi, ko, vo,
                  ni, 8 * p, base + p * 256, status + (int64_t)p * tiles * 256,
                  wctr + p, ctr + C_ERR, gate);
     cur ^= 1;
