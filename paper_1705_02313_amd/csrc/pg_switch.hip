@@ -28,8 +28,15 @@
 
 namespace pgk {
 
-constexpr int kTswChunk = 32768;   // edges per stage block (128 KiB of LDS)
-constexpr int kTswBucket = 2048;   // Odd vertices per min block
+// Sizes: a 16384-edge chunk (64 KiB of LDS, two stage blocks per CU) and
+// 4096-vertex buckets, each taken by a 1024-thread min block.  Larger
+// buckets give longer runs per chunk in the stage's writes; on the
+// 10M-vertex random game stage + min went 91 + 72 -> 82 + 63 us per step
+// against 32768-edge chunks and 2048-vertex buckets of 256 threads (1M
+// vertices: 16 + 21 -> 12 + 15 us).  8192- and 6144-vertex buckets, or 512
+// threads per min block, were slower.
+constexpr int kTswChunk = 16384;   // edges per stage block
+constexpr int kTswBucket = 4096;   // Odd vertices per min block
 
 // ---- layout (load time) ----------------------------------------------------
 
@@ -101,7 +108,7 @@ __global__ void k_tsw_slots(const uint32_t *w, const uint32_t *z,
 // ---- the step (every valuation) --------------------------------------------
 
 constexpr int kTswStageBlock = 1024;
-constexpr int kTswMinBlock = 256;
+constexpr int kTswMinBlock = 1024;
 constexpr int kTswUnroll = 8;
 
 __global__ __launch_bounds__(kTswStageBlock) void k_tsw_stage(
