@@ -28,8 +28,12 @@
 //      in increasing memory order); the last of them ends the tour;
 //   3. list ranking by sublists (section 5, "List ranking") with count
 //      vectors of dw ints as weights: level-1 sums, recursive levels, the top
-//      level by pointer jumping in LDS, bases handed back down, and a last
-//      walk that writes every finite vertex's counts.
+//      level by pointer jumping in LDS, bases handed back down.  The level-1
+//      walk leaves at the edge leaving v the prefix within its sublist in
+//      v's count row, with the sublist's number in the row's last column
+//      when the priorities leave it free (else in the element's spare
+//      word), so that one coalesced pass over the positions adds each
+//      sublist's base instead of a second walk.
 // Switching compares count rows by Maxdiff (the largest column that differs
 // decides by the parity of its priority); top is above every count vector.
 #include <algorithm>
@@ -207,11 +211,15 @@ __device__ __forceinline__ void store_vec(int32_t *p, const int32_t (&a)[D]) {
 
 // Level 1: each splitter (element index a multiple of the stride s0, a
 // power of two; element 0, the head, is one) sums the weights of its
-// sublist.
+// sublist.  At the edge leaving v it writes the sum so far (v's prefix
+// within the sublist) to v's count row, and the sublist's number to the
+// row's last column when `spare` (fewer distinct priorities than columns:
+// that column is zero in every count vector), else to the element's fourth
+// word (only this walk touches the element).
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_vlr_sum1(
-    int32_t N, const int4 *__restrict__ elem, int per_thread, int s0,
-    int32_t *vsum, int32_t *next, int32_t *ctr) {
+    int32_t N, int4 *elem, int per_thread, int s0, int spare, int32_t *vsum,
+    int32_t *next, int32_t *cnt, int32_t *ctr) {
   if (ctr[C_ABORT]) return;
   const int64_t L = 2 * (int64_t)ctr[C_NFIN] + 1;
   const int64_t nsplit = level_size(L, 1, s0);
@@ -226,7 +234,17 @@ __global__ __launch_bounds__(kBlock) void k_vlr_sum1(
     for (;;) {
       const int4 el = elem[e];
       const int32_t x = el.y & 0x7fffffff;
-      if (x < N) add_unit<D>(acc, el.z, el.y < 0 ? -1 : 1);
+      if (x < N) {
+        if (el.y < 0) {
+          int32_t r[D];
+#pragma unroll
+          for (int i = 0; i < D; ++i) r[i] = acc[i];
+          if (spare) r[D - 1] = (int32_t)j;
+          else reinterpret_cast<int32_t *>(elem)[4 * e + 3] = (int32_t)j;
+          store_vec<D>(cnt + (int64_t)x * D, r);
+        }
+        add_unit<D>(acc, el.z, el.y < 0 ? -1 : 1);
+      }
       e = el.x;
       if (e < 0 || (e & (s0 - 1)) == 0) break;
       if (++steps > L) {
@@ -354,39 +372,37 @@ __global__ __launch_bounds__(kBlock) void k_vlr_distk(
   }
 }
 
-// Last walk of every level-1 sublist: the edge leaving v emits Val(v), the
-// exclusive prefix at that element.
+// Val(v) for the finite vertex v = fvert[f] at position f: the exclusive
+// prefix at the edge leaving v, i.e. the base of its level-1 sublist plus
+// the prefix within the sublist that the level-1 walk left in v's row.
+// Positions follow vertex order, so the rows are read and written in order.
+// (A list the set-up flagged as inconsistent is not read: its elements need
+// not all have been written.)
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_vlr_emit1(
-    int32_t N, const int4 *__restrict__ elem, int per_thread, int s0,
-    const int32_t *__restrict__ sbase, int32_t *cnt, const int32_t *ctr) {
-  if (ctr[C_ABORT]) return;
-  const int64_t L = 2 * (int64_t)ctr[C_NFIN] + 1;
-  const int64_t nsplit = level_size(L, 1, s0);
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
-  for (int k = 0; k < per_thread; ++k) {
-    const int64_t j = t + (int64_t)k * nthreads;
-    if (j >= nsplit) break;
-    int64_t e = j * s0;
-    int32_t b[D];
-    load_vec<D>(sbase + j * D, b);
-    for (int64_t steps = 0; steps <= L; ++steps) {
-      const int4 el = elem[e];
-      const int32_t x = el.y & 0x7fffffff;
-      if (x < N) {
-        const int col = el.z;
-        if (el.y < 0) {
-          store_vec<D>(cnt + (int64_t)x * D, b);
-          add_unit<D>(b, col, -1);
-        } else {
-          add_unit<D>(b, col, 1);
-        }
-      }
-      e = el.x;
-      if (e < 0 || (e & (s0 - 1)) == 0) break;
-    }
+    int32_t N, const int32_t *__restrict__ fvert, const int4 *__restrict__ elem,
+    int spare, const int32_t *__restrict__ sbase, int64_t nbase, int32_t *cnt,
+    const int32_t *ctr) {
+  if (ctr[C_ABORT] || (ctr[C_ERR] & ERR_RANKCOUNT)) return;
+  const int64_t nF = ctr[C_NFIN];
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nF) return;
+  const int32_t x = fvert[f];
+  if ((uint32_t)x >= (uint32_t)N) return;
+  int32_t a[D], b[D];
+  load_vec<D>(cnt + (int64_t)x * D, a);
+  int32_t sj;
+  if (spare) {
+    sj = a[D - 1];
+    a[D - 1] = 0;
+  } else {
+    sj = elem[2 * f + 2].w;
   }
+  if ((uint32_t)sj >= (uint64_t)nbase) return;
+  load_vec<D>(sbase + (int64_t)sj * D, b);
+#pragma unroll
+  for (int i = 0; i < D; ++i) a[i] += b[i];
+  store_vec<D>(cnt + (int64_t)x * D, a);
 }
 
 // ---------------------------------------------------------------------------
@@ -739,10 +755,13 @@ static void enqueue_count_t(pg_game *g, hipStream_t s) {
   const int64_t Lmax = 2 * (int64_t)N + 1;
   const int64_t ns1 = level_size(Lmax, 1, s0);
   const int64_t thr1 = (ns1 + kVPerThread1 - 1) / kVPerThread1;
-  // two elements (16 B each) per finite vertex
-  PG_LAUNCH_NF(pf, K_LR_SUM1, 32.0, k_vlr_sum1<D>, dim3(grid_for(thr1)),
-               dim3(kBlock), 0, s, N, g->elem4, kVPerThread1, s0,
-               g->vsum[0], g->lv[0].next, g->ctr);
+  // a free last column of the count rows carries the sublist's number
+  const int spare = g->d < D;
+  // two elements (16 B each) and a count row per finite vertex
+  PG_LAUNCH_NF(pf, K_LR_SUM1, 32.0 + 4.0 * D, k_vlr_sum1<D>,
+               dim3(grid_for(thr1)), dim3(kBlock), 0, s, N, g->elem4,
+               kVPerThread1, s0, spare, g->vsum[0], g->lv[0].next, g->cnt,
+               g->ctr);
   for (int k = 1; k < nl; ++k) {
     const int64_t nsk = level_size(Lmax, k + 1, s0);
     PG_LAUNCH_NF(pf, K_LR_SUMK,
@@ -765,10 +784,10 @@ static void enqueue_count_t(pg_game *g, hipStream_t s) {
                  g->lv[k - 1].next, g->vsum[k - 1], k, s0, g->vbase[k],
                  g->vbase[k - 1], g->ctr);
   }
-  // two elements (16 B each) and one count row per finite vertex
-  PG_LAUNCH_NF(pf, K_LR_EMIT1, 32.0 + 4.0 * D, k_vlr_emit1<D>,
-               dim3(grid_for(thr1)), dim3(kBlock), 0, s, N, g->elem4,
-               kVPerThread1, s0, g->vbase[0], g->cnt, g->ctr);
+  // a position's vertex, its row read and written and a base row read
+  PG_LAUNCH_NF(pf, K_LR_EMIT1, 4.0 + 12.0 * D, k_vlr_emit1<D>,
+               dim3(grid_for(N)), dim3(kBlock), 0, s, N, g->kids, g->elem4,
+               spare, g->vbase[0], ns1, g->cnt, g->ctr);
 }
 
 void enqueue_count(pg_game *g, hipStream_t s) {
