@@ -657,7 +657,7 @@ void free_game(pg_game *g) {
                   g->tsw_t,    g->tsw_slot, g->tsw_g,    g->tsw_tz,
                   g->tsw_sz,   g->tsw_bs,   g->tsw_r};
   for (void *p : ptrs) dev_free(p);
-  for (int k = 0; k < 8; ++k) {
+  for (int k = 0; k < pgk::kMaxLevels; ++k) {
     dev_free(g->lv[k].sum);
     dev_free(g->lv[k].next);
     dev_free(g->lv[k].base);
@@ -711,8 +711,9 @@ pg_status alloc_state(pg_game *g, int64_t cap) {
   fill_i32(g->pos, 0, N + 1, 0);
   PG_TRY(dev_alloc(&g->elem, 2 * N + 2));
   PG_TRY(dev_alloc(&g->aux, 2 * N + 2));
-  // sublist levels for the longest possible Euler list
-  for (int k = 0; k < 8; ++k) {
+  // sublist levels for the longest possible Euler list (down to one
+  // splitter, which every plan stops before)
+  for (int k = 0; k < kMaxLevels; ++k) {
     const int64_t ns = level_size(2 * N + 2, k + 1, kStrideMin);
     PG_TRY(dev_alloc(&g->lv[k].sum, ns));
     PG_TRY(dev_alloc(&g->lv[k].next, ns));

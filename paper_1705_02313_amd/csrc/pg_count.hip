@@ -709,7 +709,7 @@ pg_status count_setup(pg_game *g, hipStream_t s) {
   fill_i32(g->cnt, 0, (N + 1) * g->dw, s);
   PG_TRY(dev_alloc(&g->cnt2, (N + 1) * g->dw));
   fill_i32(g->cnt2, 0, (N + 1) * g->dw, s);
-  for (int k = 0; k < 8; ++k) {
+  for (int k = 0; k < kMaxLevels; ++k) {
     const int64_t ns = level_size(2 * N + 1, k + 1, count_stride(N));
     PG_TRY(dev_alloc(&g->vsum[k], ns * g->dw));
     PG_TRY(dev_alloc(&g->vbase[k], ns * g->dw));
