@@ -242,7 +242,7 @@ KERNEL_KINDS = {
     "k_ng_round_list": "ng_round",
     "k_root_full": "root_walk", "k_root_round": "root_round",
     "k_root_round_list": "root_round",
-    "k_ps_split": "sort_split", "k_1s_hist": "sort_hist",
+    "k_ps_split": "sort_split",
     "k_1s_pass": "sort_pass", "k_scan_reduce": "scan", "k_scan_down": "scan",
     "k_scan_top": "scan", "k_link_info": "link_info",
     "k_link_build": "link_build", "k_lr_sum1": "lr_sum1",

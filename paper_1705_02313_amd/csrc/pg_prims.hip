@@ -352,9 +352,8 @@ int radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
 // ---------------------------------------------------------------------------
 // one-sweep stable LSD radix sort, 8-bit digits (the parent sort of a
 // valuation): a split pass sets the sink's children aside (they are already
-// in order) and compacts the other finite vertices; one kernel builds the
-// digit histograms of every pass over that prefix; then each pass is one
-// kernel in which a tile
+// in order), compacts the other finite vertices and counts their digits of
+// every pass; then each pass is one kernel in which a tile
 // (taken in launch order from a counter) ranks its keys in LDS, learns
 // its global offset per digit by decoupled look-back over the tiles before
 // it, and writes each digit's run out contiguously.  A tile waits only on
@@ -362,9 +361,9 @@ int radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
 // look-back always ends; a bounded spin turns a broken protocol into an
 // error instead of a hang.
 // ---------------------------------------------------------------------------
-// Tile shapes.  The histogram kernel takes kBlock threads and ITEMS keys
-// per thread: 4096-key tiles below kLargeTileFrom keys, 8192-key tiles from
-// there on; these also lay out the status words.  The split and the digit
+// Tile shapes.  kBlock threads with ITEMS keys each, 4096-key tiles below
+// kLargeTileFrom keys and 8192-key tiles from there on, lay out the status
+// words.  The split and the digit
 // passes take 1024-thread blocks with tiles at least as large (so never
 // more tiles than there are status words for): a pass holds its keys and
 // values in LDS, 16384 keys (128 KiB) on a large sort, one block per CU at
@@ -426,58 +425,6 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
     peers &= bit ? bb : ~bb;
   }
   return peers;
-}
-
-// Counts every digit of every pass, one block per tile.  Each lane loads
-// its ITEMS keys at once (all in flight); then each wave adds its keys to
-// its own LDS counters with atomics.  Lanes of a wave that hit one counter
-// are serialised by the LDS, which costs less than finding the groups of
-// equal digits with ballots (eight per digit): on the 10M-vertex random game
-// 47 -> 13 us per valuation.
-template <int ITEMS>
-__global__ __launch_bounds__(kBlock) void k_1s_hist(const uint32_t *keys,
-                                                    const uint32_t *n_dev,
-                                                    int passes,
-                                                    uint32_t *glob,
-                                                    const int32_t *gate) {
-  constexpr int kT = kBlock * ITEMS;   // keys per tile
-  if (gate && *gate) return;
-  const int64_t n = *n_dev;
-  if ((int64_t)blockIdx.x * kT >= n) return;   // grid sized for the most
-  constexpr int kWaveItems = kT / kRsWaves / kWave;   // ITEMS
-  __shared__ uint32_t h[kRsWaves][k1sMaxPasses][256];
-  const int lane = threadIdx.x & (kWave - 1);
-  const int w = threadIdx.x / kWave;
-  for (int p = 0; p < k1sMaxPasses; ++p)
-    for (int j = lane; j < 256; j += kWave) h[w][p][j] = 0;
-  const int64_t base =
-      (int64_t)blockIdx.x * kT + w * (kT / kRsWaves);
-  uint32_t k[kWaveItems];
-#pragma unroll
-  for (int r = 0; r < kWaveItems; ++r) {
-    const int64_t i = base + r * kWave + lane;
-    k[r] = i < n ? keys[i] : 0u;
-  }
-  __syncthreads();
-  for (int p = 0; p < passes; ++p) {
-#pragma unroll
-    for (int r = 0; r < kWaveItems; ++r) {
-      const bool valid = base + r * kWave + lane < n;
-      const uint32_t d = (k[r] >> (8 * p)) & 255u;
-      if (valid) atomicAdd(&h[w][p][d], 1u);
-    }
-  }
-  __syncthreads();
-  // blocks add into one of k1sCopies copies: one counter hit by every block
-  // serialises on its address
-  uint32_t *copy = glob + (int64_t)(blockIdx.x % k1sCopies) *
-                              (k1sMaxPasses * 256);
-  for (int p = 0; p < passes; ++p) {
-    uint32_t t = 0;
-#pragma unroll
-    for (int j = 0; j < kRsWaves; ++j) t += h[j][p][threadIdx.x];
-    if (t) atomicAdd(&copy[p * 256 + threadIdx.x], t);
-  }
 }
 
 // digit bases of every pass: exclusive scans of the histograms, summed
@@ -669,23 +616,33 @@ __global__ __launch_bounds__(BS) void k_1s_pass(
 // need not be known; larger keys (top vertices) are dropped.  Tiles find
 // their offsets for the two classes by decoupled look-back (two status
 // words per tile); the last tile publishes the prefix length and checks that
-// the two classes add up to the finite count.
+// the two classes add up to the finite count.  The split also builds the
+// digit histograms of every pass over the keys it keeps: each wave adds its
+// inner keys' digits to its own LDS counters with atomics (lanes of a wave
+// that hit one counter are serialised by the LDS, which costs less than
+// finding the groups of equal digits with ballots, eight per digit: 47 ->
+// 13 us per valuation on the 10M-vertex random game, then in a kernel of
+// its own that read the kept keys again; folded in here they add 9 us to
+// the split against that kernel's 15 us).
 template <int BS, int ITEMS>
 __global__ __launch_bounds__(BS) void k_ps_split(
     const uint32_t *kin, int64_t n, uint32_t npar, uint32_t *kout,
     uint32_t *vout, uint32_t *cout, uint32_t *status, uint32_t *tile_ctr,
-    uint32_t *n_inner, int32_t *ctr) {
+    uint32_t *n_inner, int passes, uint32_t *glob, int32_t *ctr) {
   constexpr int kT = BS * ITEMS;   // keys per tile
   constexpr int kW = BS / kWave;   // waves per tile
   if (ctr[C_ABORT]) return;
   __shared__ uint32_t s_tile;
   __shared__ uint32_t wcnt[2][kW];
   __shared__ uint32_t s_excl[2], s_total[2];
+  __shared__ uint32_t h[kW][k1sMaxPasses][256];   // per wave: digit counts
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int w = tid / kWave;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
   if (tid == 0) s_tile = atomicAdd(tile_ctr, 1u);
+  for (int q = lane; q < k1sMaxPasses * 256; q += kWave)
+    h[w][q / 256][q & 255] = 0;
   __syncthreads();
   const uint32_t tile = s_tile;
   const int64_t base = (int64_t)tile * kT + w * (kT / kW);
@@ -705,11 +662,29 @@ __global__ __launch_bounds__(BS) void k_ps_split(
     c0 += (uint32_t)__popcll(b0);
     c1 += (uint32_t)__popcll(b1);
   }
+  // the digit histogram of every pass over the inner keys
+  for (int p = 0; p < passes; ++p) {
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r)
+      if (k[r] < npar) atomicAdd(&h[w][p][(k[r] >> (8 * p)) & 255u], 1u);
+  }
   if (lane == 0) {
     wcnt[0][w] = c0;
     wcnt[1][w] = c1;
   }
   __syncthreads();
+  {
+    // blocks add into one of k1sCopies copies: one counter hit by every
+    // block serialises on its address
+    uint32_t *copy =
+        glob + (int64_t)(blockIdx.x % k1sCopies) * (k1sMaxPasses * 256);
+    for (int q = tid; q < passes * 256; q += BS) {
+      uint32_t t = 0;
+#pragma unroll
+      for (int j = 0; j < kW; ++j) t += h[j][q / 256][q & 255];
+      if (t) atomicAdd(&copy[q], t);
+    }
+  }
   if (tid < 2) {
     uint32_t cnt = 0;
     for (int j = 0; j < kW; ++j) cnt += wcnt[tid][j];
@@ -813,14 +788,8 @@ int parent_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
                  (large ? k_ps_split<kSplitBlockLarge, kSplitItemsLarge>
                         : k_ps_split<kSplitBlockSmall, kSplitItemsSmall>),
                  dim3((unsigned)stiles), dim3(sbs), 0, s, k0, n, npar, k1,
-                 v1, fin ? v1 : v0, sstat, wctr + 4, ni, ctr);
+                 v1, fin ? v1 : v0, sstat, wctr + 4, ni, passes, glob, ctr);
   }
-  // the prefix's keys, read once for all digits
-  PG_LAUNCH_NI(prof, K_SORT_HIST, 0.0, 0.0, 4.0,
-               (items == k1sItemsLarge ? k_1s_hist<k1sItemsLarge>
-                                       : k_1s_hist<k1sItemsSmall>),
-               dim3((unsigned)tiles), dim3(kBlock), 0, s, k1, ni, passes,
-               glob, gate);
   PG_LAUNCH(prof, K_SCAN, 0.0, k_1s_base, dim3(1), dim3(kBaseThreads), 0, s,
             glob, passes, base, gate);
   // the digit passes take their own tiles (no more of them than `tiles`,
